@@ -1,0 +1,211 @@
+/*
+ * sox.h - C ABI of the MI355X (gfx950) THC second-order-exchange library.
+ *
+ * Computes the second-order-exchange (SOX) self-energy of arXiv 2412.18829,
+ * eq:sox, through the tensor-hypercontracted step chain the paper gives in
+ * its section "THC-SOX and THC-SOSEX: algorithm and implementation details
+ * for solids and molecules" (static interactions: the U-contraction
+ * eq:U_contraction, the half projections G_Rq / G_wP, then A, B, C, D,
+ * Sigma_RP and the back-transform; dynamic interactions: eq:GG, FT,
+ * W(Omega) GG(Omega), IFT, B, C, D, Sigma).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - One spin channel per call (SOX couples only same-spin quantities).
+ * - Molecules (kmesh {1,1,1}): all tensors are real float64, row-major,
+ *   contiguous:
+ *     X      [n_orb, n_thc]           X_iP, the THC collocation matrix
+ *     V, W0  [n_thc, n_thc]           symmetric interaction in the THC basis
+ *     W_tau  [n_tau, n_thc, n_thc]    dynamic part of the screened interaction
+ *     G      [n_tau, n_orb, n_orb]    G[k,p,q] = G_pq(tau_k); treated as a
+ *                                     general (not necessarily symmetric) matrix
+ *     Sigma  [n_tau, n_orb, n_orb]    Sigma[k,t,r] = Sigma_tr(tau_k)
+ * - Every tensor pointer is a DEVICE pointer owned by the caller.  Outputs
+ *   are overwritten, never accumulated into.  `stream` is a hipStream_t
+ *   (NULL = the null stream); all device work of a call is ordered on it
+ *   and the call returns before that work finishes, except sox_energy_gm,
+ *   which synchronises the stream to return the energy.
+ * - The third propagator of eq:sox is read from node n_tau-1-k, i.e. the
+ *   stored G(beta - tau_k): the tau grid must be mirror symmetric,
+ *   tau[k] + tau[n_tau-1-k] = beta (checked at plan creation, 1e-12 beta).
+ *   eq:sox keeps its leading minus with that reading.
+ * - Sign and normalisation readings: Sigma_RP = -D_PR; molecules carry no
+ *   1/N_k factors.
+ * - Errors are status codes.  A failed argument check returns before any
+ *   device work is queued; sox_last_error() then holds a message (per
+ *   thread).  Device faults surface as SOX_ERR_HIP on a later call.
+ * - A plan is not thread safe; use one plan per host thread.
+ */
+#ifndef SOX_H
+#define SOX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SOX_OK = 0,
+  SOX_ERR_INVALID_ARG = 1, /* null pointer, bad enum value, bad scalar        */
+  SOX_ERR_SHAPE = 2,       /* sizes out of range or inconsistent              */
+  SOX_ERR_GRID = 3,        /* tau grid not ascending / not mirror symmetric   */
+  SOX_ERR_WORKSPACE = 4,   /* workspace missing, misaligned or too small      */
+  SOX_ERR_OOM = 5,         /* device allocation at plan creation failed       */
+  SOX_ERR_HIP = 6,         /* a HIP runtime call or kernel launch failed      */
+  SOX_ERR_UNSUPPORTED = 7  /* valid request this build does not implement     */
+} sox_status;
+
+/* Arithmetic of the contraction kernels (the A step and the fused B.C -> D
+ * step).  G(tau) synthesis, the U-contraction, the half projections, the
+ * back-transform to orbitals, the Matsubara transforms and the energy are
+ * always float64.
+ *   SOX_FP64    float64 MFMA (v_mfma_f64_16x16x4f64)
+ *   SOX_FP32    float32 MFMA (v_mfma_f32_16x16x4f32), float32 accumulation
+ *   SOX_BF16X3  each float32 operand split as hi + lo bfloat16; the products
+ *               hi*hi + hi*lo + lo*hi run on bf16 MFMA with float32
+ *               accumulation                                                */
+typedef enum { SOX_FP64 = 0, SOX_FP32 = 1, SOX_BF16X3 = 2 } sox_precision;
+
+/* Entry kinds, for sox_workspace_size and sox_sigma_vjp. */
+typedef enum {
+  SOX_ENTRY_BARE = 0,    /* SOX(V, V)                                        */
+  SOX_ENTRY_STATIC = 1,  /* SOX(W0, V), W0 = W(Omega = 0)                    */
+  SOX_ENTRY_DYNAMIC = 2  /* SOX(W_d(tau), V)                                 */
+} sox_entry;
+
+typedef struct sox_plan sox_plan;
+
+typedef struct {
+  int32_t n_orb;          /* n, orbitals (>= 1)                                */
+  int32_t n_thc;          /* N, THC interpolation points (>= 1)                */
+  int32_t n_tau;          /* imaginary-time nodes (>= 1)                       */
+  int32_t kmesh[3];       /* {1,1,1}: molecule.  Other meshes: UNSUPPORTED.    */
+  double beta;            /* inverse temperature (> 0)                         */
+  const double* tau;      /* HOST [n_tau], ascending in [0, beta], mirror
+                             symmetric; copied at plan creation                */
+  const double* weights;  /* HOST [n_tau], quadrature weights on [0, beta]
+                             (used by sox_energy_gm); copied                   */
+  int32_t n_omega;        /* dynamic entry only: number of non-negative bosonic
+                             Matsubara samples Omega_m; 0 disables the dynamic
+                             entry                                             */
+  const double* t_fwd;    /* HOST complex128 interleaved [n_omega, n_tau]:
+                             f(i Omega_m) = sum_j t_fwd[m,j] f(tau_j); copied  */
+  const double* t_bwd;    /* HOST complex128 interleaved [n_tau, n_omega]:
+                             f(tau_i) = Re sum_m t_bwd[i,m] f(i Omega_m) for a
+                             function real in imaginary time; copied           */
+} sox_problem;
+
+/* Create a plan: validates the problem, copies the grid, uploads the
+ * quadrature weights and transform pair to the current HIP device and picks
+ * the tile shapes and the tau-slab width.  The environment variable
+ * SOX_WS_BUDGET_MB (default 8192) caps the workspace the plan asks for.
+ * precision is a sox_precision value.  On success *out owns device memory
+ * until sox_plan_destroy. */
+sox_status sox_plan_create(const sox_problem* problem, int32_t precision, sox_plan** out);
+
+/* Free a plan and its device memory.  NULL is accepted. */
+sox_status sox_plan_destroy(sox_plan* plan);
+
+/* Bytes of device workspace the entry `entry` (a sox_entry) needs for this
+ * plan; sox_sigma_vjp uses the same value.  The workspace must be 256-byte
+ * aligned. */
+sox_status sox_workspace_size(const sox_plan* plan, int32_t entry, size_t* bytes);
+
+/* Sigma = SOX(U1 = V, U2 = V): eq:sox with the bare interaction on both
+ * lines and the static time relations (tau_wp = tau_uq = tau, the third line
+ * at beta - tau).  X [n,N], V [N,N] symmetric, G [n_tau,n,n] -> Sigma
+ * [n_tau,n,n]. */
+sox_status sox_sigma_bare(sox_plan* plan, const double* X, const double* V, const double* G,
+                          double* Sigma, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Sigma = SOX(U1 = W0, U2 = V): the statically screened interaction W0 =
+ * W(Omega = 0) (bare part included) on line 1 of eq:sox, the bare V on line
+ * 2.  Shapes as sox_sigma_bare; W0 [N,N] symmetric. */
+sox_status sox_sigma_static(sox_plan* plan, const double* X, const double* W0, const double* V,
+                            const double* G, double* Sigma, void* workspace,
+                            size_t workspace_bytes, void* stream);
+
+/* Sigma = SOX(U1 = W_d(tau), U2 = V): line 1 carries the dynamic part of the
+ * screened interaction W_tau [n_tau,N,N] (each slice symmetric), evaluated
+ * with the paper's eq:GG scheme: GG -> FT -> W(Omega) GG(Omega) -> IFT ->
+ * B, C, D -> Sigma, using the plan's transform pair.  The plan must have
+ * n_omega > 0. */
+sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_tau, const double* V,
+                             const double* G, double* Sigma, void* workspace,
+                             size_t workspace_bytes, void* stream);
+
+/* Vector-Jacobian product of L = sum(Sigma * R) for the entry `entry`:
+ *   R [n_tau,n,n] cotangent;  dG [n_tau,n,n], dX [n,N], dU1, dU2 outputs.
+ * For SOX_ENTRY_BARE, U1 = U2 = V is passed as U1 (U2 ignored) and dU1
+ * receives the total dL/dV; dU2 must be NULL.  For SOX_ENTRY_STATIC dU1 =
+ * dL/dW0, dU2 = dL/dV.  For SOX_ENTRY_DYNAMIC U1 = W_tau, dU1 = dL/dW_tau
+ * [n_tau,N,N], dU2 = dL/dV.  Any output may be NULL (not computed).
+ * Gradients are with respect to every entry of the (general) matrices, not
+ * symmetrised. */
+sox_status sox_sigma_vjp(sox_plan* plan, int32_t entry, const double* X, const double* U1,
+                         const double* U2, const double* G, const double* R, double* dG,
+                         double* dX, double* dU1, double* dU2, void* workspace,
+                         size_t workspace_bytes, void* stream);
+
+/* G(tau_k) = -Q diag(n(eps, tau_k)) Q^T on the plan's grid (eq:G_def for a
+ * one-body Hamiltonian F = Q diag(eps) Q^T, chemical potential mu), with
+ * n(e,tau) = e^{-(e-mu)tau} / (1 + e^{-beta(e-mu)}) for e >= mu and the
+ * equal form e^{(beta-tau)(e-mu)} / (1 + e^{beta(e-mu)}) for e < mu, so no
+ * exponential overflows.  Q [n,n] device (eigenvectors in columns), eps [n]
+ * device, G [n_tau,n,n] device output.  float64 throughout. */
+sox_status sox_build_g_tau(sox_plan* plan, const double* Q, const double* eps, double mu,
+                           double* G, void* stream);
+
+/* Galitskii-Migdal energy of a SOX self-energy (eq:E2b in imaginary time):
+ * E = -1/2 sum_k w_k sum_tr Sigma_tr(tau_k) G_rt(beta - tau_k), float64.
+ * Sigma, G device [n_tau,n,n]; *E_host written after the stream is
+ * synchronised. */
+sox_status sox_energy_gm(sox_plan* plan, const double* Sigma, const double* G, double* E_host,
+                         void* stream);
+
+/* Per-stage device-time accounting.  While enabled, every kernel launch of
+ * the plan's entry points is bracketed by HIP events recorded on the call's
+ * stream; sox_profile_read synchronises those events and returns, per
+ * stage, the summed elapsed milliseconds and the number of launches since
+ * the last reset.  Used by the benchmark to time the dominant kernel on the
+ * stream it runs on.  At most 65536 launches are recorded between resets;
+ * later ones are counted in `dropped`. */
+typedef enum {
+  SOX_STAGE_GBUILD = 0,   /* G(tau) synthesis                               */
+  SOX_STAGE_UTENSOR = 1,  /* U-contraction (eq:U_contraction)               */
+  SOX_STAGE_PROJECT = 2,  /* half projections G_Rq, G_wP                    */
+  SOX_STAGE_ASTEP = 3,    /* A step                                         */
+  SOX_STAGE_FUSED = 4,    /* fused B, C -> D contraction                    */
+  SOX_STAGE_BACK = 5,     /* back-transform to orbitals                     */
+  SOX_STAGE_ENERGY = 6,   /* Galitskii-Migdal energy                        */
+  SOX_STAGE_GG_FT = 7,    /* dynamic: GG formation + forward transform      */
+  SOX_STAGE_WGEMM = 8,    /* dynamic: W(Omega) GG(Omega)                    */
+  SOX_STAGE_IFT = 9,      /* dynamic: inverse transform                     */
+  SOX_STAGE_SPLIT = 10,   /* bf16 hi/lo split                               */
+  SOX_STAGE_VJP = 11,     /* adjoint kernels                                */
+  SOX_N_STAGES = 12
+} sox_stage;
+
+sox_status sox_profile_enable(sox_plan* plan, int32_t on);
+
+/* ms[SOX_N_STAGES], launches[SOX_N_STAGES]; `dropped` may be NULL.  reset != 0
+ * clears the accounting afterwards. */
+sox_status sox_profile_read(sox_plan* plan, double* ms, int64_t* launches, int64_t* dropped,
+                            int32_t reset);
+
+/* Synchronise `stream` and report any pending device error. */
+sox_status sox_sync(void* stream);
+
+/* Message for the last non-OK status on this host thread ("" if none). */
+const char* sox_last_error(void);
+
+/* ABI version of this library (increments on incompatible changes). */
+int32_t sox_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SOX_H */

@@ -96,15 +96,17 @@ def sigma_static_thc(X: np.ndarray, U1: np.ndarray, U2: np.ndarray, G: np.ndarra
     nt, n, _ = G.shape
     U1t = u_tensor(X, U1)                      # [P, q, s]
     U2t = u_tensor(X, U2)                      # [R, v, w]
+    U2v = np.ascontiguousarray(U2t.transpose(1, 0, 2))   # U2t stored per v: [v][R, w]
     out = np.empty((nt, n, n))
     for k in range(nt):
         GRq = X.T @ G[k]                       # [R, q]
         GwP = G[k] @ X                         # [w, P]
-        A = np.einsum("Pqs,sv->Pqv", U1t, Gb[k])
+        A = np.tensordot(U1t, Gb[k], axes=(2, 0))         # A_Pqv = sum_s U_Pqs G_sv(beta-tau)
+        Av = np.ascontiguousarray(A.transpose(2, 0, 1))   # stored per v: [v][P, q]
         D = np.zeros((X.shape[1], X.shape[1]))
         for v in range(n):
-            B_v = A[:, :, v] @ GRq.T           # B_PRv  [P, R]
-            C_v = U2t[:, v, :] @ GwP           # C_RvP  [R, P]
+            B_v = Av[v] @ GRq.T                # B_PRv  [P, R]
+            C_v = U2v[v] @ GwP                 # C_RvP  [R, P]
             D += C_v.T * B_v
         SigRP = -D.T                           # Sigma_RP = -D_PR
         out[k] = X @ SigRP @ X.T               # sum_PR X_tR Sigma_RP X_rP

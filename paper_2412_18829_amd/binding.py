@@ -1,0 +1,282 @@
+"""ctypes binding of libsox.so with the C ABI's names (include/sox.h).
+
+Argument marshalling only: tensors are torch CUDA (HIP) tensors on the
+current device, passed by data pointer with the current torch stream.  No
+arithmetic of the method runs here.  If the library has not been built the
+first call raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsox.so")
+
+SOX_OK = 0
+STATUS_NAMES = {
+    0: "SOX_OK", 1: "SOX_ERR_INVALID_ARG", 2: "SOX_ERR_SHAPE", 3: "SOX_ERR_GRID",
+    4: "SOX_ERR_WORKSPACE", 5: "SOX_ERR_OOM", 6: "SOX_ERR_HIP", 7: "SOX_ERR_UNSUPPORTED",
+}
+SOX_FP64, SOX_FP32, SOX_BF16X3 = 0, 1, 2
+PRECISIONS = {"fp64": SOX_FP64, "fp32": SOX_FP32, "bf16x3": SOX_BF16X3}
+SOX_ENTRY_BARE, SOX_ENTRY_STATIC, SOX_ENTRY_DYNAMIC = 0, 1, 2
+ENTRIES = {"bare": SOX_ENTRY_BARE, "static": SOX_ENTRY_STATIC, "dynamic": SOX_ENTRY_DYNAMIC}
+
+EXPORTED = (
+    "sox_plan_create", "sox_plan_destroy", "sox_workspace_size", "sox_sigma_bare",
+    "sox_sigma_static", "sox_sigma_dynamic", "sox_sigma_vjp", "sox_build_g_tau",
+    "sox_energy_gm", "sox_sync", "sox_last_error", "sox_abi_version", "sox_profile_enable",
+    "sox_profile_read",
+)
+STAGES = ("gbuild", "utensor", "project", "astep", "fused", "back", "energy", "gg_ft", "wgemm",
+          "ift", "split", "vjp")
+
+
+class SoxError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        self.status = status
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {message}")
+
+
+class sox_problem(ctypes.Structure):
+    _fields_ = [
+        ("n_orb", ctypes.c_int32), ("n_thc", ctypes.c_int32), ("n_tau", ctypes.c_int32),
+        ("kmesh", ctypes.c_int32 * 3), ("beta", ctypes.c_double),
+        ("tau", ctypes.POINTER(ctypes.c_double)), ("weights", ctypes.POINTER(ctypes.c_double)),
+        ("n_omega", ctypes.c_int32),
+        ("t_fwd", ctypes.POINTER(ctypes.c_double)), ("t_bwd", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libsox.so once and declare the C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
+                           "`python -m paper_2412_18829_amd.build_lib` (no CPU fallback exists)")
+    L = ctypes.CDLL(path)
+    vp, sz, i32, dp = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32, ctypes.c_double
+    L.sox_plan_create.argtypes = [ctypes.POINTER(sox_problem), i32, ctypes.POINTER(vp)]
+    L.sox_plan_destroy.argtypes = [vp]
+    L.sox_workspace_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
+    L.sox_sigma_bare.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+    L.sox_sigma_static.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.sox_sigma_dynamic.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.sox_sigma_vjp.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.sox_build_g_tau.argtypes = [vp, vp, vp, dp, vp, vp]
+    L.sox_energy_gm.argtypes = [vp, vp, vp, ctypes.POINTER(dp), vp]
+    L.sox_sync.argtypes = [vp]
+    L.sox_last_error.argtypes = []
+    L.sox_last_error.restype = ctypes.c_char_p
+    L.sox_abi_version.argtypes = []
+    L.sox_profile_enable.argtypes = [vp, i32]
+    L.sox_profile_read.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int64),
+                                   ctypes.POINTER(ctypes.c_int64), i32]
+    for name in EXPORTED:
+        if name not in ("sox_last_error",):
+            getattr(L, name).restype = ctypes.c_int32
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str) -> None:
+    if status != SOX_OK:
+        msg = load().sox_last_error().decode(errors="replace")
+        raise SoxError(status, where, msg)
+
+
+def _ptr(t) -> int | None:
+    if t is None:
+        return None
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError("tensors must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensors must be contiguous")
+    return t.data_ptr()
+
+
+def _f64(t, shape, name):
+    import torch
+    if t is None:
+        return None
+    if t.dtype != torch.float64:
+        raise TypeError(f"{name} must be float64")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return _ptr(t)
+
+
+def _stream(stream):
+    if stream is not None:
+        return stream
+    import torch
+    return torch.cuda.current_stream().cuda_stream
+
+
+# ---------------------------------------------------------------------------
+class Plan:
+    """Owns a sox_plan* and host copies of the grid it was built from."""
+
+    def __init__(self, n_orb: int, n_thc: int, tau, weights, beta: float,
+                 precision: str | int = "fp32", kmesh=(1, 1, 1), t_fwd=None, t_bwd=None):
+        self.n, self.N = int(n_orb), int(n_thc)
+        self.tau = np.ascontiguousarray(tau, dtype=np.float64)
+        self.weights = np.ascontiguousarray(weights, dtype=np.float64)
+        self.n_tau = int(self.tau.shape[0])
+        self.beta = float(beta)
+        self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        pr = sox_problem()
+        pr.n_orb, pr.n_thc, pr.n_tau = self.n, self.N, self.n_tau
+        pr.kmesh[:] = list(kmesh)
+        pr.beta = self.beta
+        pr.tau = self.tau.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        pr.weights = self.weights.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        self._keep = []
+        if t_fwd is not None:
+            tf = np.ascontiguousarray(t_fwd, dtype=np.complex128)
+            tb = np.ascontiguousarray(t_bwd, dtype=np.complex128)
+            self._keep += [tf, tb]
+            pr.n_omega = int(tf.shape[0])
+            pr.t_fwd = tf.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+            pr.t_bwd = tb.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        else:
+            pr.n_omega = 0
+        self.n_omega = int(pr.n_omega)
+        h = ctypes.c_void_p()
+        _check(load().sox_plan_create(ctypes.byref(pr), self.precision, ctypes.byref(h)),
+               "sox_plan_create")
+        self.handle = h
+        self._ws = {}
+
+    def workspace_size(self, entry: str | int) -> int:
+        e = ENTRIES[entry] if isinstance(entry, str) else int(entry)
+        out = ctypes.c_size_t()
+        _check(load().sox_workspace_size(self.handle, e, ctypes.byref(out)), "sox_workspace_size")
+        return int(out.value)
+
+    def workspace(self, entry: str | int):
+        """A cached device workspace (torch uint8 tensor) for `entry`."""
+        import torch
+        nbytes = self.workspace_size(entry)
+        ws = self._ws.get(entry)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+            self._ws[entry] = ws
+        return ws
+
+    def close(self):
+        if getattr(self, "handle", None) is not None and self.handle.value:
+            load().sox_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _ws_args(plan: Plan, entry, ws):
+    if ws is None:
+        ws = plan.workspace(entry)
+    p = ws.data_ptr()
+    aligned = (p + 255) & ~255
+    return aligned, ws.numel() - (aligned - p)
+
+
+# ---------------------------------------------------------------------------
+# entry points, same names as the C ABI
+def sox_sigma_bare(plan: Plan, X, V, G, Sigma, ws=None, stream=None):
+    n, N, nt = plan.n, plan.N, plan.n_tau
+    w, wb = _ws_args(plan, "bare", ws)
+    _check(load().sox_sigma_bare(plan.handle, _f64(X, (n, N), "X"), _f64(V, (N, N), "V"),
+                                 _f64(G, (nt, n, n), "G"), _f64(Sigma, (nt, n, n), "Sigma"),
+                                 w, wb, _stream(stream)), "sox_sigma_bare")
+    return Sigma
+
+
+def sox_sigma_static(plan: Plan, X, W0, V, G, Sigma, ws=None, stream=None):
+    n, N, nt = plan.n, plan.N, plan.n_tau
+    w, wb = _ws_args(plan, "static", ws)
+    _check(load().sox_sigma_static(plan.handle, _f64(X, (n, N), "X"), _f64(W0, (N, N), "W0"),
+                                   _f64(V, (N, N), "V"), _f64(G, (nt, n, n), "G"),
+                                   _f64(Sigma, (nt, n, n), "Sigma"), w, wb, _stream(stream)),
+           "sox_sigma_static")
+    return Sigma
+
+
+def sox_sigma_dynamic(plan: Plan, X, W_tau, V, G, Sigma, ws=None, stream=None):
+    n, N, nt = plan.n, plan.N, plan.n_tau
+    w, wb = _ws_args(plan, "dynamic", ws)
+    _check(load().sox_sigma_dynamic(plan.handle, _f64(X, (n, N), "X"),
+                                    _f64(W_tau, (nt, N, N), "W_tau"), _f64(V, (N, N), "V"),
+                                    _f64(G, (nt, n, n), "G"), _f64(Sigma, (nt, n, n), "Sigma"),
+                                    w, wb, _stream(stream)), "sox_sigma_dynamic")
+    return Sigma
+
+
+def sox_sigma_vjp(plan: Plan, entry, X, U1, U2, G, R, dG=None, dX=None, dU1=None, dU2=None,
+                  ws=None, stream=None):
+    n, N, nt = plan.n, plan.N, plan.n_tau
+    e = ENTRIES[entry] if isinstance(entry, str) else int(entry)
+    u1_shape = (nt, N, N) if e == SOX_ENTRY_DYNAMIC else (N, N)
+    w, wb = _ws_args(plan, e, ws)
+    _check(load().sox_sigma_vjp(
+        plan.handle, e, _f64(X, (n, N), "X"), _f64(U1, u1_shape, "U1"),
+        _f64(U2, (N, N), "U2") if U2 is not None else None, _f64(G, (nt, n, n), "G"),
+        _f64(R, (nt, n, n), "R"), _f64(dG, (nt, n, n), "dG"), _f64(dX, (n, N), "dX"),
+        _f64(dU1, u1_shape, "dU1"), _f64(dU2, (N, N), "dU2"), w, wb, _stream(stream)),
+        "sox_sigma_vjp")
+
+
+def sox_build_g_tau(plan: Plan, Q, eps, mu: float, G, stream=None):
+    n, nt = plan.n, plan.n_tau
+    _check(load().sox_build_g_tau(plan.handle, _f64(Q, (n, n), "Q"), _f64(eps, (n,), "eps"),
+                                  float(mu), _f64(G, (nt, n, n), "G"), _stream(stream)),
+           "sox_build_g_tau")
+    return G
+
+
+def sox_energy_gm(plan: Plan, Sigma, G, stream=None) -> float:
+    n, nt = plan.n, plan.n_tau
+    e = ctypes.c_double()
+    _check(load().sox_energy_gm(plan.handle, _f64(Sigma, (nt, n, n), "Sigma"),
+                                _f64(G, (nt, n, n), "G"), ctypes.byref(e), _stream(stream)),
+           "sox_energy_gm")
+    return float(e.value)
+
+
+def sox_sync(stream=None):
+    _check(load().sox_sync(_stream(stream)), "sox_sync")
+
+
+def sox_abi_version() -> int:
+    return int(load().sox_abi_version())
+
+
+def sox_profile_enable(plan: Plan, on: bool = True):
+    _check(load().sox_profile_enable(plan.handle, 1 if on else 0), "sox_profile_enable")
+
+
+def sox_profile_read(plan: Plan, reset: bool = True) -> dict:
+    """{stage: (milliseconds, launches)} summed since the last reset, plus 'dropped'."""
+    n = len(STAGES)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int64 * n)()
+    dropped = ctypes.c_int64()
+    _check(load().sox_profile_read(plan.handle, ms, cnt, ctypes.byref(dropped), 1 if reset else 0),
+           "sox_profile_read")
+    out = {STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
+    out["dropped"] = int(dropped.value)
+    return out

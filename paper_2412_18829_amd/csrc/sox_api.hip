@@ -1,0 +1,510 @@
+// C ABI of the SOX library: plan, validation, workspace carving and the
+// launch sequence of each entry point.  Declarations and argument contracts
+// are in include/sox.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/sox.h"
+#include "sox_common.hpp"
+#include "sox_fused.hpp"
+#include "sox_gemm.hpp"
+#include "sox_steps.hpp"
+
+using namespace sox;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+sox_status fail(sox_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define SOX_HIP(call)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(SOX_ERR_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),   \
+                  __FILE__, __LINE__);                                                  \
+  } while (0)
+
+inline long round_up(long x, long m) { return (x + m - 1) / m * m; }
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct sox_plan {
+  int n, N, n_tau;
+  int nP, NP;
+  int precision;
+  int wg_tile;     // fused workgroup tile edge (2 * wave tile)
+  int slab;        // tau nodes per slab
+  double beta;
+  std::vector<double> tau, weights;
+  int n_omega;
+  std::vector<double> t_fwd, t_bwd;  // complex interleaved (host copies)
+  // device copies
+  double* d_tau = nullptr;
+  double* d_w = nullptr;
+  double* d_scratch = nullptr;  // occupations / traces / energy: n_tau*(n+1)+1
+  int device = 0;
+  // per-stage event timing (sox_profile_enable / sox_profile_read)
+  struct Ev {
+    hipEvent_t a, b;
+    int stage;
+  };
+  bool prof_on = false;
+  std::vector<Ev> ev_pool;
+  size_t ev_used = 0;
+  int64_t ev_dropped = 0;
+  static constexpr size_t kMaxEvents = 65536;
+
+  int prof_begin(int stage, hipStream_t s) {
+    if (!prof_on) return -1;
+    if (ev_used >= kMaxEvents) {
+      ++ev_dropped;
+      return -1;
+    }
+    if (ev_used == ev_pool.size()) {
+      Ev e{};
+      if (hipEventCreate(&e.a) != hipSuccess) return -1;
+      if (hipEventCreate(&e.b) != hipSuccess) {
+        (void)hipEventDestroy(e.a);
+        return -1;
+      }
+      ev_pool.push_back(e);
+    }
+    Ev& e = ev_pool[ev_used];
+    e.stage = stage;
+    if (hipEventRecord(e.a, s) != hipSuccess) return -1;
+    return (int)ev_used++;
+  }
+  void prof_end(int idx, hipStream_t s) {
+    if (idx >= 0) (void)hipEventRecord(ev_pool[idx].b, s);
+  }
+};
+
+namespace {
+// Brackets the launches of one stage with events when profiling is on.
+struct ProfScope {
+  sox_plan& p;
+  hipStream_t s;
+  int idx;
+  ProfScope(sox_plan& plan, int stage, hipStream_t stream) : p(plan), s(stream) {
+    idx = p.prof_begin(stage, s);
+  }
+  ~ProfScope() { p.prof_end(idx, s); }
+};
+}  // namespace
+
+namespace {
+
+// -- workspace layout --------------------------------------------------------
+struct Layout {
+  size_t u1, u2, a, p1, p2t, d, e, total;
+};
+
+size_t elem_size(int precision) { return precision == SOX_FP64 ? 8 : 4; }
+
+Layout layout_for(const sox_plan& p, int entry, int slab) {
+  Layout L{};
+  const size_t es = elem_size(p.precision);
+  const size_t nP = p.nP, NP = p.NP, n = p.n;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L.u1 = take(NP * nP * nP * es);
+  L.u2 = (entry == SOX_ENTRY_BARE) ? L.u1 : take(NP * nP * nP * es);
+  L.a = take((size_t)slab * n * NP * nP * es);
+  L.p1 = take((size_t)slab * NP * nP * es);
+  L.p2t = take((size_t)slab * NP * nP * es);
+  L.d = take((size_t)slab * NP * NP * es);
+  L.e = take((size_t)slab * n * NP * 8);
+  L.total = off;
+  return L;
+}
+
+int pick_slab(const sox_plan& p, int entry) {
+  double budget_mb = 8192.0;
+  if (const char* s = getenv("SOX_WS_BUDGET_MB")) {
+    double v = atof(s);
+    if (v > 0) budget_mb = v;
+  }
+  const size_t budget = (size_t)(budget_mb * 1048576.0);
+  int slab = p.n_tau;
+  while (slab > 1 && layout_for(p, entry, slab).total > budget) slab = (slab + 1) / 2;
+  return slab;
+}
+
+sox_status check_plan(const sox_plan* plan) {
+  if (!plan) return fail(SOX_ERR_INVALID_ARG, "plan is NULL");
+  return SOX_OK;
+}
+
+sox_status check_ws(const sox_plan* plan, int entry, const void* ws, size_t ws_bytes) {
+  const size_t need = layout_for(*plan, entry, plan->slab).total;
+  if (!ws) return fail(SOX_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", need);
+  if (((uintptr_t)ws & 255) != 0) return fail(SOX_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes < need)
+    return fail(SOX_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  return SOX_OK;
+}
+
+// -- launch sequences ----------------------------------------------------------
+template <typename T>
+sox_status launch_utensor(const sox_plan& p, const double* U, const double* X, T* out,
+                          hipStream_t s) {
+  UTensorProb<T> pr{U, X, out, p.n, p.N, p.nP, p.NP, p.nP * p.nP, p.N};
+  SOX_HIP((launch_gemm<UTensorProb<T>, double, 2, 2, 2, 2>(pr, 1, s)));
+  return SOX_OK;
+}
+
+template <typename T>
+sox_status launch_fused_cfg(const sox_plan& p, const FusedArgs<T>& fa, hipStream_t s);
+
+template <>
+sox_status launch_fused_cfg<float>(const sox_plan& p, const FusedArgs<float>& fa, hipStream_t s) {
+  if (p.wg_tile == 128) SOX_HIP((launch_fused<float, 64, 64>(fa, s)));
+  else SOX_HIP((launch_fused<float, 32, 32>(fa, s)));
+  return SOX_OK;
+}
+
+template <>
+sox_status launch_fused_cfg<double>(const sox_plan& p, const FusedArgs<double>& fa,
+                                    hipStream_t s) {
+  (void)p;
+  SOX_HIP((launch_fused<double, 32, 32>(fa, s)));
+  return SOX_OK;
+}
+
+template <typename T>
+sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1, const double* U2,
+                      const double* G, double* Sigma, void* ws, hipStream_t s) {
+  const Layout L = layout_for(p, entry, p.slab);
+  char* base = (char*)ws;
+  T* u1t = (T*)(base + L.u1);
+  T* u2t = (T*)(base + L.u2);
+  T* A = (T*)(base + L.a);
+  T* P1 = (T*)(base + L.p1);
+  T* P2T = (T*)(base + L.p2t);
+  T* D = (T*)(base + L.d);
+  double* E = (double*)(base + L.e);
+  const int n = p.n, N = p.N, nP = p.nP, NP = p.NP;
+
+  if (NP % p.wg_tile != 0) return fail(SOX_ERR_SHAPE, "internal: padded extent not a tile multiple");
+  sox_status st;
+  {
+    ProfScope ps(p, SOX_STAGE_UTENSOR, s);
+    st = launch_utensor<T>(p, U1, X, u1t, s);
+    if (st) return st;
+    if (entry != SOX_ENTRY_BARE) {
+      st = launch_utensor<T>(p, U2, X, u2t, s);
+      if (st) return st;
+    }
+  }
+  const int tiles = NP / p.wg_tile;
+  for (int t0 = 0; t0 < p.n_tau; t0 += p.slab) {
+    const int cnt = std::min(p.slab, p.n_tau - t0);
+    {
+      ProfScope ps(p, SOX_STAGE_PROJECT, s);
+      ProjP1Prob<T> pr1{X, G, P1, n, N, nP, NP, t0, NP, nP, n};
+      SOX_HIP((launch_gemm<ProjP1Prob<T>, double, 2, 2, 2, 2>(pr1, cnt, s)));
+      ProjP2TProb<T> pr2{X, G, P2T, n, N, nP, NP, t0, NP, nP, n};
+      SOX_HIP((launch_gemm<ProjP2TProb<T>, double, 2, 2, 2, 2>(pr2, cnt, s)));
+    }
+    {
+      ProfScope ps(p, SOX_STAGE_ASTEP, s);
+      AStepProb<T> pa{G, u1t, A, n, nP, NP, p.n_tau, t0, n, NP * nP, nP};
+      SOX_HIP((launch_gemm<AStepProb<T>, T, 1, 4, 4, 2>(pa, cnt, s)));
+    }
+    FusedArgs<T> fa;
+    fa.A = A;
+    fa.Y = P1;
+    fa.P2T = P2T;
+    fa.U2 = u2t;
+    fa.D = D;
+    fa.a_tstride = (long)n * NP * nP;
+    fa.a_vstride = (long)NP * nP;
+    fa.y_tstride = (long)NP * nP;
+    fa.p_tstride = (long)NP * nP;
+    fa.u_rstride = (long)nP * nP;
+    fa.u_vstride = nP;
+    fa.d_tstride = (long)NP * NP;
+    fa.n = n;
+    fa.nP = nP;
+    fa.NP = NP;
+    fa.tiles_p = tiles;
+    fa.tiles_r = tiles;
+    fa.n_tau = cnt;
+    {
+      ProfScope ps(p, SOX_STAGE_FUSED, s);
+      st = launch_fused_cfg<T>(p, fa, s);
+      if (st) return st;
+    }
+    {
+      ProfScope ps(p, SOX_STAGE_BACK, s);
+      BackEProb<T> pe{X, D, E, n, N, NP, n, N, N};
+      SOX_HIP((launch_gemm<BackEProb<T>, double, 2, 2, 2, 2>(pe, cnt, s)));
+      BackSigmaProb pb{X, E, Sigma, n, N, NP, t0, -1.0, n, n, N};
+      SOX_HIP((launch_gemm<BackSigmaProb, double, 2, 2, 2, 2>(pb, cnt, s)));
+    }
+  }
+  return SOX_OK;
+}
+
+sox_status dispatch_static(sox_plan* plan, int entry, const double* X, const double* U1,
+                           const double* U2, const double* G, double* Sigma, void* ws,
+                           size_t ws_bytes, void* stream) {
+  sox_status st = check_plan(plan);
+  if (st) return st;
+  if (!X || !U1 || !G || !Sigma || (entry == SOX_ENTRY_STATIC && !U2))
+    return fail(SOX_ERR_INVALID_ARG, "NULL tensor pointer");
+  st = check_ws(plan, entry, ws, ws_bytes);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  switch (plan->precision) {
+    case SOX_FP64: return run_static<double>(*plan, entry, X, U1, U2, G, Sigma, ws, s);
+    case SOX_FP32: return run_static<float>(*plan, entry, X, U1, U2, G, Sigma, ws, s);
+    default: return fail(SOX_ERR_UNSUPPORTED, "precision %d not implemented", plan->precision);
+  }
+}
+
+}  // namespace
+
+// =============================================================================
+extern "C" {
+
+int32_t sox_abi_version(void) { return 1; }
+
+const char* sox_last_error(void) { return g_last_error.c_str(); }
+
+sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** out) {
+  if (!out) return fail(SOX_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (!pr) return fail(SOX_ERR_INVALID_ARG, "problem is NULL");
+  if (precision < SOX_FP64 || precision > SOX_BF16X3)
+    return fail(SOX_ERR_INVALID_ARG, "unknown precision %d", precision);
+  if (pr->n_orb < 1 || pr->n_thc < 1 || pr->n_tau < 1)
+    return fail(SOX_ERR_SHAPE, "n_orb, n_thc, n_tau must be >= 1 (got %d, %d, %d)", pr->n_orb,
+                pr->n_thc, pr->n_tau);
+  if (pr->n_orb > 4096 || pr->n_thc > 32768 || pr->n_tau > 4096)
+    return fail(SOX_ERR_SHAPE, "sizes beyond the supported range");
+  if (pr->kmesh[0] != 1 || pr->kmesh[1] != 1 || pr->kmesh[2] != 1) {
+    if (pr->kmesh[0] < 1 || pr->kmesh[1] < 1 || pr->kmesh[2] < 1)
+      return fail(SOX_ERR_SHAPE, "kmesh entries must be >= 1");
+    return fail(SOX_ERR_UNSUPPORTED, "k-point meshes are not implemented in this build");
+  }
+  if (!(pr->beta > 0.0) || !std::isfinite(pr->beta))
+    return fail(SOX_ERR_INVALID_ARG, "beta must be positive and finite");
+  if (!pr->tau || !pr->weights) return fail(SOX_ERR_INVALID_ARG, "tau / weights are NULL");
+  const int nt = pr->n_tau;
+  const double tol = 1e-12 * pr->beta;
+  for (int k = 0; k < nt; ++k) {
+    const double t = pr->tau[k];
+    if (!std::isfinite(t) || t < -tol || t > pr->beta + tol)
+      return fail(SOX_ERR_GRID, "tau[%d] = %g outside [0, beta]", k, t);
+    if (k > 0 && !(t > pr->tau[k - 1])) return fail(SOX_ERR_GRID, "tau not strictly ascending");
+    if (std::fabs(t + pr->tau[nt - 1 - k] - pr->beta) > tol)
+      return fail(SOX_ERR_GRID, "tau grid not mirror symmetric at node %d", k);
+    if (!std::isfinite(pr->weights[k])) return fail(SOX_ERR_GRID, "weight %d not finite", k);
+  }
+  if (pr->n_omega < 0) return fail(SOX_ERR_SHAPE, "n_omega < 0");
+  if (pr->n_omega > 0 && (!pr->t_fwd || !pr->t_bwd))
+    return fail(SOX_ERR_INVALID_ARG, "n_omega > 0 but transform matrices are NULL");
+
+  sox_plan* p = new (std::nothrow) sox_plan();
+  if (!p) return fail(SOX_ERR_OOM, "host allocation failed");
+  p->n = pr->n_orb;
+  p->N = pr->n_thc;
+  p->n_tau = nt;
+  p->precision = precision;
+  p->beta = pr->beta;
+  p->tau.assign(pr->tau, pr->tau + nt);
+  p->weights.assign(pr->weights, pr->weights + nt);
+  p->n_omega = pr->n_omega;
+  if (pr->n_omega > 0) {
+    p->t_fwd.assign(pr->t_fwd, pr->t_fwd + 2 * (size_t)pr->n_omega * nt);
+    p->t_bwd.assign(pr->t_bwd, pr->t_bwd + 2 * (size_t)pr->n_omega * nt);
+  }
+  p->nP = (int)round_up(p->n, 16);
+  // fused workgroup tile: 128 x 128 when that wastes little padding, else 64
+  const long np128 = round_up(p->N, 128), np64 = round_up(p->N, 64);
+  p->wg_tile = 64;
+  (void)np128;
+  if (const char* s = getenv("SOX_WG_TILE")) {
+    int v = atoi(s);
+    if (v == 64 || v == 128) p->wg_tile = (precision == SOX_FP64) ? 64 : v;
+  }
+  p->NP = (int)round_up(p->N, p->wg_tile);
+  (void)np64;
+  p->slab = pick_slab(*p, SOX_ENTRY_STATIC);
+
+  hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) e = hipMalloc(&p->d_tau, sizeof(double) * nt);
+  if (e == hipSuccess) e = hipMalloc(&p->d_w, sizeof(double) * nt);
+  if (e == hipSuccess)
+    e = hipMalloc(&p->d_scratch, sizeof(double) * ((size_t)nt * (p->n + 1) + 1));
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_tau, p->tau.data(), sizeof(double) * nt, hipMemcpyHostToDevice);
+  if (e == hipSuccess)
+    e = hipMemcpy(p->d_w, p->weights.data(), sizeof(double) * nt, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    sox_status st = fail(e == hipErrorOutOfMemory ? SOX_ERR_OOM : SOX_ERR_HIP,
+                         "plan device setup failed: %s", hipGetErrorString(e));
+    sox_plan_destroy(p);
+    return st;
+  }
+  *out = p;
+  return SOX_OK;
+}
+
+sox_status sox_plan_destroy(sox_plan* p) {
+  if (!p) return SOX_OK;
+  for (auto& e : p->ev_pool) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  if (p->d_tau) (void)hipFree(p->d_tau);
+  if (p->d_w) (void)hipFree(p->d_w);
+  if (p->d_scratch) (void)hipFree(p->d_scratch);
+  delete p;
+  return SOX_OK;
+}
+
+sox_status sox_workspace_size(const sox_plan* plan, int32_t entry, size_t* bytes) {
+  if (!plan) return fail(SOX_ERR_INVALID_ARG, "plan is NULL");
+  if (!bytes) return fail(SOX_ERR_INVALID_ARG, "bytes is NULL");
+  if (entry < SOX_ENTRY_BARE || entry > SOX_ENTRY_DYNAMIC)
+    return fail(SOX_ERR_INVALID_ARG, "unknown entry %d", entry);
+  *bytes = layout_for(*plan, entry, plan->slab).total;
+  return SOX_OK;
+}
+
+sox_status sox_sigma_bare(sox_plan* plan, const double* X, const double* V, const double* G,
+                          double* Sigma, void* ws, size_t ws_bytes, void* stream) {
+  return dispatch_static(plan, SOX_ENTRY_BARE, X, V, V, G, Sigma, ws, ws_bytes, stream);
+}
+
+sox_status sox_sigma_static(sox_plan* plan, const double* X, const double* W0, const double* V,
+                            const double* G, double* Sigma, void* ws, size_t ws_bytes,
+                            void* stream) {
+  return dispatch_static(plan, SOX_ENTRY_STATIC, X, W0, V, G, Sigma, ws, ws_bytes, stream);
+}
+
+sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_tau,
+                             const double* V, const double* G, double* Sigma, void* ws,
+                             size_t ws_bytes, void* stream) {
+  (void)X; (void)W_tau; (void)V; (void)G; (void)Sigma; (void)ws; (void)ws_bytes; (void)stream;
+  sox_status st = check_plan(plan);
+  if (st) return st;
+  return fail(SOX_ERR_UNSUPPORTED, "dynamic entry not implemented yet");
+}
+
+sox_status sox_sigma_vjp(sox_plan* plan, int32_t entry, const double* X, const double* U1,
+                         const double* U2, const double* G, const double* R, double* dG,
+                         double* dX, double* dU1, double* dU2, void* ws, size_t ws_bytes,
+                         void* stream) {
+  (void)entry; (void)X; (void)U1; (void)U2; (void)G; (void)R; (void)dG; (void)dX; (void)dU1;
+  (void)dU2; (void)ws; (void)ws_bytes; (void)stream;
+  sox_status st = check_plan(plan);
+  if (st) return st;
+  return fail(SOX_ERR_UNSUPPORTED, "vjp not implemented yet");
+}
+
+sox_status sox_build_g_tau(sox_plan* plan, const double* Q, const double* eps, double mu,
+                           double* G, void* stream) {
+  sox_status st = check_plan(plan);
+  if (st) return st;
+  if (!Q || !eps || !G) return fail(SOX_ERR_INVALID_ARG, "NULL tensor pointer");
+  if (!std::isfinite(mu)) return fail(SOX_ERR_INVALID_ARG, "mu not finite");
+  hipStream_t s = (hipStream_t)stream;
+  const int n = plan->n, nt = plan->n_tau;
+  double* occ = plan->d_scratch;  // [n_tau][n]
+  const int tot = n * nt;
+  ProfScope ps(*plan, SOX_STAGE_GBUILD, s);
+  hipLaunchKernelGGL(occupation_kernel, dim3((tot + 255) / 256), dim3(256), 0, s, eps,
+                     plan->d_tau, mu, plan->beta, n, nt, occ);
+  SOX_HIP(hipGetLastError());
+  GBuildProb pg{Q, occ, G, n, n, n, n};
+  SOX_HIP((launch_gemm<GBuildProb, double, 2, 2, 2, 2>(pg, nt, s)));
+  return SOX_OK;
+}
+
+sox_status sox_energy_gm(sox_plan* plan, const double* Sigma, const double* G, double* E_host,
+                         void* stream) {
+  sox_status st = check_plan(plan);
+  if (st) return st;
+  if (!Sigma || !G || !E_host) return fail(SOX_ERR_INVALID_ARG, "NULL pointer");
+  hipStream_t s = (hipStream_t)stream;
+  const int n = plan->n, nt = plan->n_tau;
+  double* tr = plan->d_scratch + (size_t)nt * n;
+  double* e = tr + nt;
+  {
+  ProfScope ps(*plan, SOX_STAGE_ENERGY, s);
+  hipLaunchKernelGGL(energy_trace_kernel, dim3(nt), dim3(256), 0, s, Sigma, G, n, nt, tr);
+  SOX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(energy_reduce_kernel, dim3(1), dim3(256), 0, s, tr, plan->d_w, nt, e);
+  SOX_HIP(hipGetLastError());
+  }
+  SOX_HIP(hipMemcpyAsync(E_host, e, sizeof(double), hipMemcpyDeviceToHost, s));
+  SOX_HIP(hipStreamSynchronize(s));
+  return SOX_OK;
+}
+
+sox_status sox_profile_enable(sox_plan* plan, int32_t on) {
+  sox_status st = check_plan(plan);
+  if (st) return st;
+  plan->prof_on = on != 0;
+  return SOX_OK;
+}
+
+sox_status sox_profile_read(sox_plan* plan, double* ms, int64_t* launches, int64_t* dropped,
+                            int32_t reset) {
+  sox_status st = check_plan(plan);
+  if (st) return st;
+  if (!ms || !launches) return fail(SOX_ERR_INVALID_ARG, "NULL output");
+  for (int i = 0; i < SOX_N_STAGES; ++i) {
+    ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  for (size_t i = 0; i < plan->ev_used; ++i) {
+    auto& e = plan->ev_pool[i];
+    SOX_HIP(hipEventSynchronize(e.b));
+    float t = 0.f;
+    SOX_HIP(hipEventElapsedTime(&t, e.a, e.b));
+    ms[e.stage] += t;
+    launches[e.stage] += 1;
+  }
+  if (dropped) *dropped = plan->ev_dropped;
+  if (reset) {
+    plan->ev_used = 0;
+    plan->ev_dropped = 0;
+  }
+  return SOX_OK;
+}
+
+sox_status sox_sync(void* stream) {
+  SOX_HIP(hipStreamSynchronize((hipStream_t)stream));
+  SOX_HIP(hipGetLastError());
+  return SOX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,54 @@
+// Shared device helpers for the gfx950 SOX kernels: vector types, the
+// 16x16x4 MFMA wrappers used by every contraction, and the XCD-aware
+// block-to-tile remap.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sox {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct vec4;
+template <> struct vec4<float> { typedef f32x4 type; };
+template <> struct vec4<double> { typedef f64x4 type; };
+template <typename T> using vec4_t = typename vec4<T>::type;
+
+// D = A*B + C on one 16x16 tile with a K-depth of 4.  Operand layout (both
+// precisions): lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16].  The
+// accumulator element r of lane l holds C[acc_row<T>(l / 16, r)][l % 16]:
+// row 4 (l/16) + r for float32 and row (l/16) + 4 r for float64 (measured
+// on gfx950 with a row/column-tagging probe).
+__device__ __forceinline__ f32x4 mfma16x16x4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f64x4 mfma16x16x4(double a, double b, f64x4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+template <typename T> __device__ __forceinline__ int acc_row(int g, int r);
+template <> __device__ __forceinline__ int acc_row<float>(int g, int r) { return 4 * g + r; }
+template <> __device__ __forceinline__ int acc_row<double>(int g, int r) { return g + 4 * r; }
+
+template <typename T> __device__ __forceinline__ vec4_t<T> zero4() {
+  vec4_t<T> z;
+  z[0] = T(0); z[1] = T(0); z[2] = T(0); z[3] = T(0);
+  return z;
+}
+
+// Consecutive workgroup ids are dispatched round-robin over the 8 XCDs of
+// the chip, each with its own L2.  Give every XCD a contiguous range of
+// logical tiles so that tiles that share operands (same tau, same P panel)
+// run behind the same L2.  Bijective on [0, nblocks).
+__device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
+  constexpr int NX = 8;
+  const int per = nblocks / NX;
+  const int rem = nblocks % NX;
+  const int xcd = bid % NX;
+  const int local = bid / NX;
+  return xcd * per + (xcd < rem ? xcd : rem) + local;
+}
+
+}  // namespace sox

@@ -1,0 +1,168 @@
+// Fused B, C -> D contraction over the auxiliary indices (the paper's B, C
+// and D steps, the N^2 n^2 n_tau regime that dominates the SOX cost):
+//
+//   B^v[P,R] = sum_q A[P,q,v] Y[q,R]            (static: Y = G_Rq^T,
+//                                                dynamic: Y = X, B_PRv = sum_u X_uR A_Puv)
+//   C^v[R,P] = sum_w U2[R,v,w] G_wP
+//   D[P,R]   = sum_v B^v[P,R] C^v[R,P]
+//
+// Both products of one v are MFMA tiles over the same [P, R] output block,
+// so D is accumulated in registers by a Hadamard epilogue and B, C never
+// reach memory.  Operands (all zero padded, K contiguous, 16-byte aligned):
+//
+//   A   [tau][v][P][q]   row stride nP   (the A step output)
+//   Y   [tau][R][q]      row stride nP   (y_tstride = 0 shares one Y)
+//   P2T [tau][P][w]      row stride nP   (G_wP transposed)
+//   U2  R stride u_rstride, v stride u_vstride, w contiguous
+//   D   [tau][P][R]      row stride NP
+//
+// One workgroup = 4 wavefronts (2 x 2) owns a (2 WP) x (2 WR) block of D for
+// one tau.  The loop runs over (v, 16-deep k chunk) with the next chunk's
+// operands loaded before the current chunk's MFMAs are issued.
+#pragma once
+
+#include "sox_common.hpp"
+
+namespace sox {
+
+template <typename T> struct FusedArgs {
+  const T* A;
+  const T* Y;
+  const T* P2T;
+  const T* U2;
+  T* D;
+  long a_tstride, a_vstride;
+  long y_tstride;
+  long p_tstride;
+  long u_rstride, u_vstride;
+  long d_tstride;
+  int n;      // orbitals: the v range
+  int nP;     // padded k depth (multiple of 16)
+  int NP;     // padded THC extent (multiple of the tile)
+  int tiles_p, tiles_r, n_tau;
+};
+
+template <typename T, int WP, int WR>
+__global__ __launch_bounds__(256) void fused_bcd_kernel(const FusedArgs<T> p) {
+  using V4 = vec4_t<T>;
+  constexpr int PB = WP / 16;
+  constexpr int RB = WR / 16;
+  const int nblocks = gridDim.x;
+  const int bid = xcd_remap(blockIdx.x, nblocks);
+  const int rt = bid % p.tiles_r;
+  const int tmp = bid / p.tiles_r;
+  const int pt = tmp % p.tiles_p;
+  const int t = tmp / p.tiles_p;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int li = lane & 15;
+  const int g = lane >> 4;
+  const int P0 = pt * (2 * WP) + (wave >> 1) * WP;
+  const int R0 = rt * (2 * WR) + (wave & 1) * WR;
+
+  const long ld = p.nP;
+  const T* Ab = p.A + t * p.a_tstride + (long)(P0 + li) * ld + 4 * g;
+  const T* Yb = p.Y + t * p.y_tstride + (long)(R0 + li) * ld + 4 * g;
+  const T* Pb = p.P2T + t * p.p_tstride + (long)(P0 + li) * ld + 4 * g;
+  const T* Ub = p.U2 + (long)(R0 + li) * p.u_rstride + 4 * g;
+
+  V4 accB[PB][RB], accC[PB][RB], dacc[PB][RB];
+#pragma unroll
+  for (int i = 0; i < PB; ++i)
+#pragma unroll
+    for (int j = 0; j < RB; ++j) {
+      accB[i][j] = zero4<T>();
+      accC[i][j] = zero4<T>();
+      dacc[i][j] = zero4<T>();
+    }
+
+  const int KC = p.nP >> 4;
+  const int total = p.n * KC;
+
+  V4 a[PB], y[RB], pp[PB], u[RB];
+  // first chunk: v = 0, k0 = 0
+#pragma unroll
+  for (int i = 0; i < PB; ++i) {
+    a[i] = *(const V4*)(Ab + (long)(16 * i) * ld);
+    pp[i] = *(const V4*)(Pb + (long)(16 * i) * ld);
+  }
+#pragma unroll
+  for (int j = 0; j < RB; ++j) {
+    y[j] = *(const V4*)(Yb + (long)(16 * j) * ld);
+    u[j] = *(const V4*)(Ub + (long)(16 * j) * p.u_rstride);
+  }
+
+  int v = 0, kc = 0;
+  for (int it = 0; it < total; ++it) {
+    // coordinates of the next chunk
+    int vn = v, kn = kc + 1;
+    if (kn == KC) { kn = 0; ++vn; }
+    const bool more = (it + 1) < total;
+    V4 an[PB], yn[RB], pn[PB], un[RB];
+    if (more) {
+      const long ko = (long)kn * 16;
+      const T* Av = Ab + (long)vn * p.a_vstride + ko;
+      const T* Uv = Ub + (long)vn * p.u_vstride + ko;
+#pragma unroll
+      for (int i = 0; i < PB; ++i) {
+        an[i] = *(const V4*)(Av + (long)(16 * i) * ld);
+        pn[i] = *(const V4*)(Pb + ko + (long)(16 * i) * ld);
+      }
+#pragma unroll
+      for (int j = 0; j < RB; ++j) {
+        yn[j] = *(const V4*)(Yb + ko + (long)(16 * j) * ld);
+        un[j] = *(const V4*)(Uv + (long)(16 * j) * p.u_rstride);
+      }
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int i = 0; i < PB; ++i)
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+          accB[i][j] = mfma16x16x4(a[i][m], y[j][m], accB[i][j]);
+          accC[i][j] = mfma16x16x4(pp[i][m], u[j][m], accC[i][j]);
+        }
+    if (kc == KC - 1) {
+#pragma unroll
+      for (int i = 0; i < PB; ++i)
+#pragma unroll
+        for (int j = 0; j < RB; ++j) {
+          dacc[i][j] += accB[i][j] * accC[i][j];
+          accB[i][j] = zero4<T>();
+          accC[i][j] = zero4<T>();
+        }
+    }
+    if (more) {
+#pragma unroll
+      for (int i = 0; i < PB; ++i) { a[i] = an[i]; pp[i] = pn[i]; }
+#pragma unroll
+      for (int j = 0; j < RB; ++j) { y[j] = yn[j]; u[j] = un[j]; }
+    }
+    v = vn;
+    kc = kn;
+  }
+
+  T* Db = p.D + t * p.d_tstride;
+#pragma unroll
+  for (int i = 0; i < PB; ++i)
+#pragma unroll
+    for (int j = 0; j < RB; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int P = P0 + 16 * i + acc_row<T>(g, r);
+        const int R = R0 + 16 * j + li;
+        Db[(long)P * p.NP + R] = dacc[i][j][r];
+      }
+}
+
+template <typename T, int WP, int WR>
+inline hipError_t launch_fused(const FusedArgs<T>& a, hipStream_t s) {
+  const int nb = a.tiles_p * a.tiles_r * a.n_tau;
+  if (nb <= 0) return hipSuccess;
+  hipLaunchKernelGGL((fused_bcd_kernel<T, WP, WR>), dim3(nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace sox

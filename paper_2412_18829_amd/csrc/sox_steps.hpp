@@ -1,0 +1,219 @@
+// Operand-access structs that map each step of the SOX chain onto the
+// generic MFMA GEMM (sox_gemm.hpp), plus the elementwise kernels.
+//
+// Padded extents: nP = n rounded up to 16 (the MFMA k chunk), NP = N rounded
+// up to the fused kernel's workgroup tile.  Every intermediate the fused
+// kernel reads is stored with these extents and zeros in the padding, which
+// the producers below write by masking their loads to the true extents.
+#pragma once
+
+#include "sox_common.hpp"
+#include "sox_gemm.hpp"
+
+namespace sox {
+
+// ---------------------------------------------------------------------------
+// U-contraction (eq:U_contraction, molecule):
+//   Ut[P][q][s] = sum_Q U[P][Q] X[q][Q] X[s][Q]       (float64 MFMA)
+// GEMM rows P, columns (q, s) flattened over nP x nP, depth Q.
+template <typename Tout> struct UTensorProb {
+  const double* U;  // [N][N]
+  const double* X;  // [n][N]
+  Tout* out;        // [NP][nP][nP]
+  int n, Nthc, nP;
+  int M, N, K;      // M = NP, N = nP*nP, K = Nthc
+  __device__ f64x4 loadA4(int, int P, int Q) const {
+    if (P >= Nthc) return zero4<double>();
+    return load4_strided<double>(U + (long)P * Nthc, 1, Q, Nthc);
+  }
+  __device__ f64x4 loadB4(int, int j, int Q) const {
+    const int q = j / nP, s = j - (j / nP) * nP;
+    if (q >= n || s >= n) return zero4<double>();
+    f64x4 a = load4_strided<double>(X + (long)q * Nthc, 1, Q, Nthc);
+    f64x4 b = load4_strided<double>(X + (long)s * Nthc, 1, Q, Nthc);
+    return a * b;
+  }
+  __device__ void store(int, int P, int j, double v) const { out[(long)P * nP * nP + j] = Tout(v); }
+};
+
+// ---------------------------------------------------------------------------
+// Half projections onto the THC grid (float64 MFMA, stored in Tout):
+//   P1[t][R][q]  = sum_u X[u][R] G[tau][u][q]        (the paper's G_Rq)
+//   P2T[t][P][w] = sum_p X[p][P] G[tau][w][p]        (G_wP, transposed)
+template <typename Tout> struct ProjP1Prob {
+  const double* X;  // [n][N]
+  const double* G;  // [n_tau][n][n]
+  Tout* out;        // [slab][NP][nP]
+  int n, Nthc, nP, NP, t0;
+  int M, N, K;      // M = NP, N = nP, K = n
+  __device__ f64x4 loadA4(int, int R, int u) const {
+    if (R >= Nthc) return zero4<double>();
+    return load4_strided<double>(X + R, Nthc, u, n);
+  }
+  __device__ f64x4 loadB4(int b, int q, int u) const {
+    if (q >= n) return zero4<double>();
+    return load4_strided<double>(G + (long)(t0 + b) * n * n + q, n, u, n);
+  }
+  __device__ void store(int b, int R, int q, double v) const {
+    out[(long)b * NP * nP + (long)R * nP + q] = Tout(v);
+  }
+};
+
+template <typename Tout> struct ProjP2TProb {
+  const double* X;
+  const double* G;
+  Tout* out;        // [slab][NP][nP]
+  int n, Nthc, nP, NP, t0;
+  int M, N, K;      // M = NP, N = nP, K = n
+  __device__ f64x4 loadA4(int, int P, int p) const {
+    if (P >= Nthc) return zero4<double>();
+    return load4_strided<double>(X + P, Nthc, p, n);
+  }
+  __device__ f64x4 loadB4(int b, int w, int p) const {
+    if (w >= n) return zero4<double>();
+    return load4_strided<double>(G + (long)(t0 + b) * n * n + (long)w * n, 1, p, n);
+  }
+  __device__ void store(int b, int P, int w, double v) const {
+    out[(long)b * NP * nP + (long)P * nP + w] = Tout(v);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// A step:  A[t][v][P][q] = sum_s U1t[P][q][s] G_sv(beta - tau)
+// GEMM rows v, columns (P, q) flattened over NP x nP, depth s; G(beta-tau)
+// is node n_tau - 1 - tau.  Runs in the contraction precision T.
+template <typename T> struct AStepProb {
+  const double* G;  // [n_tau][n][n]
+  const T* U1t;     // [NP][nP][nP]
+  T* out;           // [slab][n][NP][nP]
+  int n, nP, NP, n_tau, t0;
+  int M, N, K;      // M = n, N = NP*nP, K = nP
+  __device__ vec4_t<T> loadA4(int b, int v, int s) const {
+    if (v >= n) return zero4<T>();
+    const double* Gb = G + (long)(n_tau - 1 - (t0 + b)) * n * n + v;
+    return load4_strided<T>(Gb, n, s, n);
+  }
+  __device__ vec4_t<T> loadB4(int, int j, int s) const {
+    if (j >= N) return zero4<T>();
+    return *(const vec4_t<T>*)(U1t + (long)j * nP + s);
+  }
+  __device__ void store(int b, int v, int j, T val) const {
+    out[((long)b * n + v) * ((long)NP * nP) + j] = val;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Back-transform (float64):  E[t][tt][P] = sum_R X[tt][R] D[t][P][R]
+//                            Sigma[tau][tt][r] = -sum_P E[t][tt][P] X[r][P]
+template <typename Td> struct BackEProb {
+  const double* X;  // [n][N]
+  const Td* D;      // [slab][NP][NP]
+  double* E;        // [slab][n][NP]
+  int n, Nthc, NP;
+  int M, N, K;      // M = n, N = Nthc, K = Nthc
+  __device__ f64x4 loadA4(int, int tt, int R) const {
+    if (tt >= n) return zero4<double>();
+    return load4_strided<double>(X + (long)tt * Nthc, 1, R, Nthc);
+  }
+  __device__ f64x4 loadB4(int b, int P, int R) const {
+    if (P >= Nthc) return zero4<double>();
+    return load4_strided<double>(D + (long)b * NP * NP + (long)P * NP, 1, R, Nthc);
+  }
+  __device__ void store(int b, int tt, int P, double v) const {
+    E[(long)b * n * NP + (long)tt * NP + P] = v;
+  }
+};
+
+struct BackSigmaProb {
+  const double* X;
+  const double* E;  // [slab][n][NP]
+  double* Sigma;    // [n_tau][n][n]
+  int n, Nthc, NP, t0;
+  double scale;     // -1 for Sigma_RP = -D_PR
+  int M, N, K;      // M = n, N = n, K = Nthc
+  __device__ f64x4 loadA4(int b, int tt, int P) const {
+    if (tt >= n) return zero4<double>();
+    return load4_strided<double>(E + (long)b * n * NP + (long)tt * NP, 1, P, Nthc);
+  }
+  __device__ f64x4 loadB4(int, int r, int P) const {
+    if (r >= n) return zero4<double>();
+    return load4_strided<double>(X + (long)r * Nthc, 1, P, Nthc);
+  }
+  __device__ void store(int b, int tt, int r, double v) const {
+    Sigma[(long)(t0 + b) * n * n + (long)tt * n + r] = scale * v;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// G(tau) synthesis (eq:G_def, one-body Hamiltonian), float64:
+//   occ[k][a] = n(eps_a, tau_k);  G[k][p][q] = -sum_a Q[p][a] occ[k][a] Q[q][a]
+__global__ void occupation_kernel(const double* eps, const double* tau, double mu, double beta,
+                                  int n, int n_tau, double* occ) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * n_tau) return;
+  const int k = idx / n, a = idx - (idx / n) * n;
+  const double x = eps[a] - mu;
+  const double t = tau[k];
+  double v;
+  if (x >= 0.0) v = exp(-x * t) / (1.0 + exp(-beta * x));
+  else v = exp((beta - t) * x) / (1.0 + exp(beta * x));
+  occ[idx] = v;
+}
+
+struct GBuildProb {
+  const double* Q;    // [n][n]
+  const double* occ;  // [n_tau][n]
+  double* G;          // [n_tau][n][n]
+  int n;
+  int M, N, K;        // n, n, n
+  __device__ f64x4 loadA4(int b, int p, int a) const {
+    if (p >= n) return zero4<double>();
+    f64x4 q = load4_strided<double>(Q + (long)p * n, 1, a, n);
+    f64x4 o = load4_strided<double>(occ + (long)b * n, 1, a, n);
+    return q * o;
+  }
+  __device__ f64x4 loadB4(int, int qq, int a) const {
+    if (qq >= n) return zero4<double>();
+    return load4_strided<double>(Q + (long)qq * n, 1, a, n);
+  }
+  __device__ void store(int b, int p, int qq, double v) const { G[((long)b * n + p) * n + qq] = -v; }
+};
+
+// ---------------------------------------------------------------------------
+// Galitskii-Migdal energy (eq:E2b in imaginary time), float64:
+//   tr[k] = sum_tr Sigma[k][t][r] G[n_tau-1-k][r][t]; E = -1/2 sum_k w_k tr[k]
+__global__ __launch_bounds__(256) void energy_trace_kernel(const double* Sigma, const double* G,
+                                                           int n, int n_tau, double* tr) {
+  const int k = blockIdx.x;
+  const double* S = Sigma + (long)k * n * n;
+  const double* Gb = G + (long)(n_tau - 1 - k) * n * n;
+  double acc = 0.0;
+  for (int idx = threadIdx.x; idx < n * n; idx += blockDim.x) {
+    const int t = idx / n, r = idx - (idx / n) * n;
+    acc += S[idx] * Gb[(long)r * n + t];
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) tr[k] = red[0];
+}
+
+__global__ __launch_bounds__(256) void energy_reduce_kernel(const double* tr, const double* w,
+                                                            int n_tau, double* E) {
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < n_tau; k += blockDim.x) acc += w[k] * tr[k];
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) E[0] = -0.5 * red[0];
+}
+
+}  // namespace sox
