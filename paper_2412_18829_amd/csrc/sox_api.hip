@@ -48,11 +48,28 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
+// Wave-tile shapes of the fused B, C -> D kernel (P rows x R columns per
+// wavefront; a workgroup is 2 x 2 wavefronts).
+struct FusedCfg {
+  int wp, wr;
+  bool fp32, fp64;
+};
+static const FusedCfg kFusedCfgs[] = {
+    {32, 32, true, true},   // 0
+    {64, 32, true, false},  // 1
+    {32, 64, true, false},  // 2
+    {64, 64, true, false},  // 3
+    {32, 16, true, true},   // 4
+    {16, 32, false, true},  // 5
+};
+static const int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
+
 struct sox_plan {
   int n, N, n_tau;
   int nP, NP;
   int precision;
-  int wg_tile;     // fused workgroup tile edge (2 * wave tile)
+  int fused_cfg;   // index into kFusedCfgs
+  int wg_tile;     // NP granule: 2 * max(wave tile edges)
   int slab;        // tau nodes per slab
   double beta;
   std::vector<double> tau, weights;
@@ -154,6 +171,21 @@ int pick_slab(const sox_plan& p, int entry) {
   return slab;
 }
 
+int default_fused_cfg(int precision, int N) {
+  if (precision == SOX_FP64) return 0;
+  // float32: the 64 x 64 wave tile halves the operand traffic per flop of
+  // the 32 x 32 one and measured fastest at N = 384 and N = 1200 even with
+  // the padding to a multiple of 128; tiny N keeps the small tile
+  return N >= 256 ? 3 : 0;
+}
+
+void set_fused_cfg(sox_plan& p, int cfg) {
+  p.fused_cfg = cfg;
+  const FusedCfg& fc = kFusedCfgs[cfg];
+  p.wg_tile = 2 * std::max(fc.wp, fc.wr);
+  p.NP = (int)round_up(p.N, p.wg_tile);
+}
+
 sox_status check_plan(const sox_plan* plan) {
   if (!plan) return fail(SOX_ERR_INVALID_ARG, "plan is NULL");
   return SOX_OK;
@@ -182,16 +214,26 @@ sox_status launch_fused_cfg(const sox_plan& p, const FusedArgs<T>& fa, hipStream
 
 template <>
 sox_status launch_fused_cfg<float>(const sox_plan& p, const FusedArgs<float>& fa, hipStream_t s) {
-  if (p.wg_tile == 128) SOX_HIP((launch_fused<float, 64, 64>(fa, s)));
-  else SOX_HIP((launch_fused<float, 32, 32>(fa, s)));
+  switch (p.fused_cfg) {
+    case 0: SOX_HIP((launch_fused<float, 32, 32>(fa, s))); break;
+    case 1: SOX_HIP((launch_fused<float, 64, 32>(fa, s))); break;
+    case 2: SOX_HIP((launch_fused<float, 32, 64>(fa, s))); break;
+    case 3: SOX_HIP((launch_fused<float, 64, 64>(fa, s))); break;
+    case 4: SOX_HIP((launch_fused<float, 32, 16>(fa, s))); break;
+    default: return fail(SOX_ERR_UNSUPPORTED, "fused config %d has no float32 kernel", p.fused_cfg);
+  }
   return SOX_OK;
 }
 
 template <>
 sox_status launch_fused_cfg<double>(const sox_plan& p, const FusedArgs<double>& fa,
                                     hipStream_t s) {
-  (void)p;
-  SOX_HIP((launch_fused<double, 32, 32>(fa, s)));
+  switch (p.fused_cfg) {
+    case 0: SOX_HIP((launch_fused<double, 32, 32>(fa, s))); break;
+    case 4: SOX_HIP((launch_fused<double, 32, 16>(fa, s))); break;
+    case 5: SOX_HIP((launch_fused<double, 16, 32>(fa, s))); break;
+    default: return fail(SOX_ERR_UNSUPPORTED, "fused config %d has no float64 kernel", p.fused_cfg);
+  }
   return SOX_OK;
 }
 
@@ -220,7 +262,10 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
       if (st) return st;
     }
   }
-  const int tiles = NP / p.wg_tile;
+  const FusedCfg& fc = kFusedCfgs[p.fused_cfg];
+  if (NP % (2 * fc.wp) != 0 || NP % (2 * fc.wr) != 0)
+    return fail(SOX_ERR_SHAPE, "internal: padded extent does not fit the fused tile");
+  const int tiles_p = NP / (2 * fc.wp), tiles_r = NP / (2 * fc.wr);
   for (int t0 = 0; t0 < p.n_tau; t0 += p.slab) {
     const int cnt = std::min(p.slab, p.n_tau - t0);
     {
@@ -251,8 +296,8 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
     fa.n = n;
     fa.nP = nP;
     fa.NP = NP;
-    fa.tiles_p = tiles;
-    fa.tiles_r = tiles;
+    fa.tiles_p = tiles_p;
+    fa.tiles_r = tiles_r;
     fa.n_tau = cnt;
     {
       ProfScope ps(p, SOX_STAGE_FUSED, s);
@@ -345,16 +390,14 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
     p->t_bwd.assign(pr->t_bwd, pr->t_bwd + 2 * (size_t)pr->n_omega * nt);
   }
   p->nP = (int)round_up(p->n, 16);
-  // fused workgroup tile: 128 x 128 when that wastes little padding, else 64
-  const long np128 = round_up(p->N, 128), np64 = round_up(p->N, 64);
-  p->wg_tile = 64;
-  (void)np128;
-  if (const char* s = getenv("SOX_WG_TILE")) {
+  p->fused_cfg = default_fused_cfg(precision, p->N);
+  if (const char* s = getenv("SOX_FUSED_CFG")) {
     int v = atoi(s);
-    if (v == 64 || v == 128) p->wg_tile = (precision == SOX_FP64) ? 64 : v;
+    if (v >= 0 && v < kNumFusedCfgs &&
+        (precision == SOX_FP64 ? kFusedCfgs[v].fp64 : kFusedCfgs[v].fp32))
+      p->fused_cfg = v;
   }
-  p->NP = (int)round_up(p->N, p->wg_tile);
-  (void)np64;
+  set_fused_cfg(*p, p->fused_cfg);
   p->slab = pick_slab(*p, SOX_ENTRY_STATIC);
 
   hipError_t e = hipGetDevice(&p->device);

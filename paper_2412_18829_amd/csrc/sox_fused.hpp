@@ -17,8 +17,9 @@
 //   D   [tau][P][R]      row stride NP
 //
 // One workgroup = 4 wavefronts (2 x 2) owns a (2 WP) x (2 WR) block of D for
-// one tau.  The loop runs over (v, 16-deep k chunk) with the next chunk's
-// operands loaded before the current chunk's MFMAs are issued.
+// one tau.  The loops run over v and 16-deep k chunks with the next chunk's
+// operands loaded before the current chunk's MFMAs are issued; the Hadamard
+// epilogue closes each v.
 #pragma once
 
 #include "sox_common.hpp"
@@ -78,10 +79,13 @@ __global__ __launch_bounds__(256) void fused_bcd_kernel(const FusedArgs<T> p) {
     }
 
   const int KC = p.nP >> 4;
-  const int total = p.n * KC;
+  const int nv = p.n;
 
+  // Operands of the current chunk.  The next chunk is always loaded (the
+  // last iteration re-loads chunk (n-1, KC-1), which stays in bounds) so the
+  // loop body has no control flow around the loads and the wait for them
+  // lands after this chunk's MFMAs have been issued.
   V4 a[PB], y[RB], pp[PB], u[RB];
-  // first chunk: v = 0, k0 = 0
 #pragma unroll
   for (int i = 0; i < PB; ++i) {
     a[i] = *(const V4*)(Ab + (long)(16 * i) * ld);
@@ -93,17 +97,18 @@ __global__ __launch_bounds__(256) void fused_bcd_kernel(const FusedArgs<T> p) {
     u[j] = *(const V4*)(Ub + (long)(16 * j) * p.u_rstride);
   }
 
-  int v = 0, kc = 0;
-  for (int it = 0; it < total; ++it) {
-    // coordinates of the next chunk
-    int vn = v, kn = kc + 1;
-    if (kn == KC) { kn = 0; ++vn; }
-    const bool more = (it + 1) < total;
-    V4 an[PB], yn[RB], pn[PB], un[RB];
-    if (more) {
+  for (int v = 0; v < nv; ++v) {
+    for (int kc = 0; kc < KC; ++kc) {
+      const bool wrap = (kc + 1 == KC);
+      int vn = wrap ? v + 1 : v;
+      int kn = wrap ? 0 : kc + 1;
+      const bool last = vn >= nv;
+      vn = last ? nv - 1 : vn;
+      kn = last ? KC - 1 : kn;
       const long ko = (long)kn * 16;
       const T* Av = Ab + (long)vn * p.a_vstride + ko;
       const T* Uv = Ub + (long)vn * p.u_vstride + ko;
+      V4 an[PB], yn[RB], pn[PB], un[RB];
 #pragma unroll
       for (int i = 0; i < PB; ++i) {
         an[i] = *(const V4*)(Av + (long)(16 * i) * ld);
@@ -114,34 +119,31 @@ __global__ __launch_bounds__(256) void fused_bcd_kernel(const FusedArgs<T> p) {
         yn[j] = *(const V4*)(Yb + ko + (long)(16 * j) * ld);
         un[j] = *(const V4*)(Uv + (long)(16 * j) * p.u_rstride);
       }
-    }
+      // keep the prefetch ahead of the MFMA block (and in its own registers)
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int m = 0; m < 4; ++m)
+      for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int i = 0; i < PB; ++i)
+        for (int i = 0; i < PB; ++i)
 #pragma unroll
-        for (int j = 0; j < RB; ++j) {
-          accB[i][j] = mfma16x16x4(a[i][m], y[j][m], accB[i][j]);
-          accC[i][j] = mfma16x16x4(pp[i][m], u[j][m], accC[i][j]);
-        }
-    if (kc == KC - 1) {
-#pragma unroll
-      for (int i = 0; i < PB; ++i)
-#pragma unroll
-        for (int j = 0; j < RB; ++j) {
-          dacc[i][j] += accB[i][j] * accC[i][j];
-          accB[i][j] = zero4<T>();
-          accC[i][j] = zero4<T>();
-        }
-    }
-    if (more) {
+          for (int j = 0; j < RB; ++j) {
+            accB[i][j] = mfma16x16x4(a[i][m], y[j][m], accB[i][j]);
+            accC[i][j] = mfma16x16x4(pp[i][m], u[j][m], accC[i][j]);
+          }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int i = 0; i < PB; ++i) { a[i] = an[i]; pp[i] = pn[i]; }
 #pragma unroll
       for (int j = 0; j < RB; ++j) { y[j] = yn[j]; u[j] = un[j]; }
     }
-    v = vn;
-    kc = kn;
+#pragma unroll
+    for (int i = 0; i < PB; ++i)
+#pragma unroll
+      for (int j = 0; j < RB; ++j) {
+        dacc[i][j] += accB[i][j] * accC[i][j];
+        accB[i][j] = zero4<T>();
+        accC[i][j] = zero4<T>();
+      }
   }
 
   T* Db = p.D + t * p.d_tstride;
