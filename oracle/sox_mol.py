@@ -141,7 +141,7 @@ def matsubara(T_fwd: np.ndarray, f: np.ndarray) -> np.ndarray:
 
 def imag_time(T_bwd: np.ndarray, fw: np.ndarray) -> np.ndarray:
     """IFT along axis 0 for a real function: f(tau_i) = Re sum_m T_bwd[i, m] f_m."""
-    return np.tensordot(T_bwd, fw, axes=(1, 0)).real
+    return np.ascontiguousarray(np.tensordot(T_bwd, fw, axes=(1, 0)).real)
 
 
 def sigma_dynamic_eri(X: np.ndarray, W_tau: np.ndarray, V: np.ndarray, G: np.ndarray,
@@ -185,19 +185,20 @@ def sigma_dynamic_thc(X: np.ndarray, W_tau: np.ndarray, V: np.ndarray, G: np.nda
     N = X.shape[1]
     Wm = matsubara(T_fwd, W_tau)                     # [n_omega, P, Q]
     U2t = u_tensor(X, V)                             # [R, v, w]
+    U2v = np.ascontiguousarray(U2t.transpose(1, 0, 2))   # stored per v: [v][R, w]
     GuQ = np.einsum("juq,qQ->juQ", G, X)             # G_uQ(tau) = sum_q G_uq X_qQ
     GQv = np.einsum("sQ,jsv->jQv", X, Gb)            # G_Qv(-tau) read as sum_s X_sQ G_sv(beta-tau)
     GwP = GuQ                                        # G_wP(tau) = sum_p G_wp X_pP
+    GQu = np.ascontiguousarray(GuQ.transpose(0, 2, 1))
     D = np.zeros((nt, N, N))
     for v in range(n):
-        GG = GuQ.transpose(0, 2, 1) * GQv[:, :, v][:, :, None]     # [nt, Q, u]
+        GG = GQu * GQv[:, :, v][:, :, None]                         # GG_Quv(tau) [nt, Q, u]
         GGm = matsubara(T_fwd, GG)                                  # [n_omega, Q, u]
-        Am = np.einsum("mPQ,mQu->mPu", Wm, GGm)
-        A = imag_time(T_bwd, Am)                                    # [nt, P, u]
-        for j in range(nt):
-            B_v = A[j] @ X                                          # B_PRv [P, R]
-            C_v = U2t[:, v, :] @ GwP[j]                             # C_RvP [R, P]
-            D[j] += C_v.T * B_v
+        Am = np.matmul(Wm, GGm)                                     # A_Puv(Omega)
+        A = imag_time(T_bwd, Am)                                    # A_Puv(tau) [nt, P, u]
+        B_v = np.matmul(A, X)                                       # B_PRv(tau) [nt, P, R]
+        C_v = np.matmul(U2v[v], GwP)                                # C_RvP(tau) [nt, R, P]
+        D += C_v.transpose(0, 2, 1) * B_v
     out = np.empty((nt, n, n))
     for j in range(nt):
         out[j] = X @ (-D[j].T) @ X.T

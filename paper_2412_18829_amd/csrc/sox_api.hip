@@ -15,6 +15,7 @@
 
 #include "../../include/sox.h"
 #include "sox_common.hpp"
+#include "sox_dense.hpp"
 #include "sox_fused.hpp"
 #include "sox_gemm.hpp"
 #include "sox_steps.hpp"
@@ -75,7 +76,11 @@ struct sox_plan {
   std::vector<double> tau, weights;
   int n_omega;
   std::vector<double> t_fwd, t_bwd;  // complex interleaved (host copies)
+  int vc = 0;       // dynamic entry: v-slab width
+  int eslab = 0;    // dynamic entry: tau nodes per back-transform slab
   // device copies
+  double* d_tf2 = nullptr;  // [2 n_omega][n_tau]  Re / Im of t_fwd
+  double* d_tb2 = nullptr;  // [n_tau][2 n_omega]  [Re t_bwd | -Im t_bwd]
   double* d_tau = nullptr;
   double* d_w = nullptr;
   double* d_scratch = nullptr;  // occupations / traces / energy: n_tau*(n+1)+1
@@ -133,42 +138,83 @@ namespace {
 
 // -- workspace layout --------------------------------------------------------
 struct Layout {
-  size_t u1, u2, a, p1, p2t, d, e, total;
+  size_t u1, u2, a, p1, p2t, d, e, gbt, total;
+};
+
+struct DynLayout {
+  size_t p1d, p2td, p2t, xt, u2, w2, gg2, aw, adyn, d, e, total;
 };
 
 size_t elem_size(int precision) { return precision == SOX_FP64 ? 8 : 4; }
+
+struct Carver {
+  size_t off = 0;
+  size_t take(size_t bytes) {
+    size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  }
+};
 
 Layout layout_for(const sox_plan& p, int entry, int slab) {
   Layout L{};
   const size_t es = elem_size(p.precision);
   const size_t nP = p.nP, NP = p.NP, n = p.n;
-  size_t off = 0;
-  auto take = [&](size_t bytes) {
-    size_t o = off;
-    off = align256(off + bytes);
-    return o;
-  };
-  L.u1 = take(NP * nP * nP * es);
-  L.u2 = (entry == SOX_ENTRY_BARE) ? L.u1 : take(NP * nP * nP * es);
-  L.a = take((size_t)slab * n * NP * nP * es);
-  L.p1 = take((size_t)slab * NP * nP * es);
-  L.p2t = take((size_t)slab * NP * nP * es);
-  L.d = take((size_t)slab * NP * NP * es);
-  L.e = take((size_t)slab * n * NP * 8);
-  L.total = off;
+  Carver c;
+  L.u1 = c.take(NP * nP * nP * es);
+  L.u2 = (entry == SOX_ENTRY_BARE) ? L.u1 : c.take(NP * nP * nP * es);
+  L.a = c.take((size_t)slab * n * NP * nP * es);
+  L.p1 = c.take((size_t)slab * NP * nP * es);
+  L.p2t = c.take((size_t)slab * NP * nP * es);
+  L.d = c.take((size_t)slab * NP * NP * es);
+  L.e = c.take((size_t)slab * n * NP * 8);
+  L.gbt = c.take((size_t)slab * nP * nP * es);
+  L.total = c.off;
   return L;
 }
 
-int pick_slab(const sox_plan& p, int entry) {
-  double budget_mb = 8192.0;
+DynLayout dyn_layout_for(const sox_plan& p, int vc, int eslab) {
+  DynLayout L{};
+  const size_t es = elem_size(p.precision);
+  const size_t nP = p.nP, NP = p.NP, n = p.n, nt = p.n_tau, nw = p.n_omega;
+  Carver c;
+  L.p1d = c.take(nt * NP * nP * 8);
+  L.p2td = c.take(nt * NP * nP * 8);
+  L.p2t = c.take(nt * NP * nP * es);
+  L.xt = c.take(NP * nP * es);
+  L.u2 = c.take(NP * nP * nP * es);
+  L.w2 = c.take(nw * 4 * NP * NP * es);
+  L.gg2 = c.take(nw * (size_t)vc * n * 2 * NP * es);
+  L.aw = c.take(nw * 2 * NP * (size_t)vc * n * es);
+  L.adyn = c.take(nt * (size_t)vc * NP * nP * es);
+  L.d = c.take(nt * NP * NP * es);
+  L.e = c.take((size_t)eslab * n * NP * 8);
+  L.total = c.off;
+  return L;
+}
+
+size_t ws_budget() {
+  double budget_mb = 32768.0;
   if (const char* s = getenv("SOX_WS_BUDGET_MB")) {
     double v = atof(s);
     if (v > 0) budget_mb = v;
   }
-  const size_t budget = (size_t)(budget_mb * 1048576.0);
+  return (size_t)(budget_mb * 1048576.0);
+}
+
+int pick_slab(const sox_plan& p, int entry) {
+  const size_t budget = ws_budget();
   int slab = p.n_tau;
   while (slab > 1 && layout_for(p, entry, slab).total > budget) slab = (slab + 1) / 2;
   return slab;
+}
+
+void pick_dyn(sox_plan& p) {
+  const size_t budget = ws_budget();
+  p.eslab = std::min(p.n_tau, 16);
+  int vc = p.n;
+  while (vc > 1 && dyn_layout_for(p, vc, p.eslab).total > budget) vc = (vc + 1) / 2;
+  p.vc = vc;
 }
 
 int default_fused_cfg(int precision, int N) {
@@ -191,8 +237,13 @@ sox_status check_plan(const sox_plan* plan) {
   return SOX_OK;
 }
 
+size_t workspace_bytes(const sox_plan& p, int entry) {
+  if (entry == SOX_ENTRY_DYNAMIC) return p.n_omega > 0 ? dyn_layout_for(p, p.vc, p.eslab).total : 0;
+  return layout_for(p, entry, p.slab).total;
+}
+
 sox_status check_ws(const sox_plan* plan, int entry, const void* ws, size_t ws_bytes) {
-  const size_t need = layout_for(*plan, entry, plan->slab).total;
+  const size_t need = workspace_bytes(*plan, entry);
   if (!ws) return fail(SOX_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", need);
   if (((uintptr_t)ws & 255) != 0) return fail(SOX_ERR_WORKSPACE, "workspace not 256-byte aligned");
   if (ws_bytes < need)
@@ -206,6 +257,47 @@ sox_status launch_utensor(const sox_plan& p, const double* U, const double* X, T
                           hipStream_t s) {
   UTensorProb<T> pr{U, X, out, p.n, p.N, p.nP, p.NP, p.nP * p.nP, p.N};
   SOX_HIP((launch_gemm<UTensorProb<T>, double, 2, 2, 2, 2>(pr, 1, s)));
+  return SOX_OK;
+}
+
+// A step on the dense kernel: A[b][v][(P,q)] = sum_s GbT[b][v][s] U1t[(P,q)][s]
+// (rows v, columns (P,q), stored row-major so stores are contiguous in q).
+template <typename T>
+sox_status launch_astep(const sox_plan& p, const T* u1t, const T* gbt, T* A, int cnt,
+                        hipStream_t s) {
+  DenseArgs<T, T> d{};
+  d.A = gbt;
+  d.B = u1t;
+  d.C = A;
+  d.lda = p.nP;
+  d.ldb = p.nP;
+  d.ldc = (long)p.NP * p.nP;
+  d.sA = (long)p.nP * p.nP;
+  d.sB = 0;
+  d.sC = (long)p.n * p.NP * p.nP;
+  d.M = p.n;
+  d.N = p.NP * p.nP;
+  d.K = p.nP;
+  d.alpha = T(1);
+  d.transposed = 0;
+  d.accumulate = 0;
+  if (sizeof(T) == 8) {
+    SOX_HIP((launch_dense<T, T, 1, 4, 2, 2>(d, cnt, s)));
+  } else if ((round_up(p.n, 64) - p.n) * 10 <= p.n) {
+    SOX_HIP((launch_dense<T, T, 1, 4, 4, 4>(d, cnt, s)));
+  } else {
+    SOX_HIP((launch_dense<T, T, 1, 4, 2, 4>(d, cnt, s)));
+  }
+  return SOX_OK;
+}
+
+template <typename T>
+sox_status launch_gbar_t(const sox_plan& p, const double* G, T* gbt, int t0, int cnt,
+                         hipStream_t s) {
+  const long tot = (long)cnt * p.nP * p.nP;
+  hipLaunchKernelGGL(gbar_t_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, G,
+                     gbt, p.n, p.nP, p.n_tau, t0, cnt);
+  SOX_HIP(hipGetLastError());
   return SOX_OK;
 }
 
@@ -249,6 +341,7 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
   T* P2T = (T*)(base + L.p2t);
   T* D = (T*)(base + L.d);
   double* E = (double*)(base + L.e);
+  T* gbt = (T*)(base + L.gbt);
   const int n = p.n, N = p.N, nP = p.nP, NP = p.NP;
 
   if (NP % p.wg_tile != 0) return fail(SOX_ERR_SHAPE, "internal: padded extent not a tile multiple");
@@ -277,8 +370,10 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
     }
     {
       ProfScope ps(p, SOX_STAGE_ASTEP, s);
-      AStepProb<T> pa{G, u1t, A, n, nP, NP, p.n_tau, t0, n, NP * nP, nP};
-      SOX_HIP((launch_gemm<AStepProb<T>, T, 1, 4, 4, 2>(pa, cnt, s)));
+      st = launch_gbar_t<T>(p, G, gbt, t0, cnt, s);
+      if (st) return st;
+      st = launch_astep<T>(p, u1t, gbt, A, cnt, s);
+      if (st) return st;
     }
     FusedArgs<T> fa;
     fa.A = A;
@@ -299,6 +394,7 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
     fa.tiles_p = tiles_p;
     fa.tiles_r = tiles_r;
     fa.n_tau = cnt;
+    fa.accumulate = 0;
     {
       ProfScope ps(p, SOX_STAGE_FUSED, s);
       st = launch_fused_cfg<T>(p, fa, s);
@@ -311,6 +407,123 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
       BackSigmaProb pb{X, E, Sigma, n, N, NP, t0, -1.0, n, n, N};
       SOX_HIP((launch_gemm<BackSigmaProb, double, 2, 2, 2, 2>(pb, cnt, s)));
     }
+  }
+  return SOX_OK;
+}
+
+template <typename T>
+sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const double* V,
+                       const double* G, double* Sigma, void* ws, hipStream_t s) {
+  const DynLayout L = dyn_layout_for(p, p.vc, p.eslab);
+  char* base = (char*)ws;
+  double* P1d = (double*)(base + L.p1d);
+  double* P2Td = (double*)(base + L.p2td);
+  T* P2T = (T*)(base + L.p2t);
+  T* XT = (T*)(base + L.xt);
+  T* U2 = (T*)(base + L.u2);
+  T* W2 = (T*)(base + L.w2);
+  T* GG2 = (T*)(base + L.gg2);
+  T* AW = (T*)(base + L.aw);
+  T* Adyn = (T*)(base + L.adyn);
+  T* D = (T*)(base + L.d);
+  double* E = (double*)(base + L.e);
+  const int n = p.n, N = p.N, nP = p.nP, NP = p.NP, nt = p.n_tau, nw = p.n_omega;
+  const FusedCfg& fc = kFusedCfgs[p.fused_cfg];
+  if (NP % (2 * fc.wp) != 0 || NP % (2 * fc.wr) != 0)
+    return fail(SOX_ERR_SHAPE, "internal: padded extent does not fit the fused tile");
+  sox_status st;
+  {
+    ProfScope ps(p, SOX_STAGE_UTENSOR, s);
+    st = launch_utensor<T>(p, V, X, U2, s);
+    if (st) return st;
+  }
+  {
+    ProfScope ps(p, SOX_STAGE_PROJECT, s);
+    ProjP1Prob<double> pr1{X, G, P1d, n, N, nP, NP, 0, NP, nP, n};
+    SOX_HIP((launch_gemm<ProjP1Prob<double>, double, 2, 2, 2, 2>(pr1, nt, s)));
+    ProjP2TProb<double> pr2{X, G, P2Td, n, N, nP, NP, 0, NP, nP, n};
+    SOX_HIP((launch_gemm<ProjP2TProb<double>, double, 2, 2, 2, 2>(pr2, nt, s)));
+    const long cnt = (long)nt * NP * nP;
+    hipLaunchKernelGGL(cast_kernel<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, P2Td,
+                       P2T, cnt);
+    SOX_HIP(hipGetLastError());
+    const long cx = (long)NP * nP;
+    hipLaunchKernelGGL(xt_kernel<T>, dim3((unsigned)((cx + 255) / 256)), dim3(256), 0, s, X, XT,
+                       n, N, nP, NP);
+    SOX_HIP(hipGetLastError());
+  }
+  {
+    ProfScope ps(p, SOX_STAGE_GG_FT, s);
+    WOmegaProb<T> wp{p.d_tf2, Wtau, W2, nw, nt, N, NP, 2 * nw, NP * NP, nt};
+    SOX_HIP((launch_gemm<WOmegaProb<T>, double, 2, 2, 2, 2>(wp, 1, s)));
+  }
+  const int tiles_p = NP / (2 * fc.wp), tiles_r = NP / (2 * fc.wr);
+  for (int v0 = 0; v0 < n; v0 += p.vc) {
+    const int vc = std::min(p.vc, n - v0);
+    {
+      ProfScope ps(p, SOX_STAGE_GG_FT, s);
+      FTProb<T> ft{p.d_tf2, P1d, P2Td, GG2, n, nP, NP, N, nw, nt, v0, vc, 2 * nw, vc * n * NP, nt};
+      SOX_HIP((launch_gemm<FTProb<T>, double, 2, 2, 2, 2>(ft, 1, s)));
+    }
+    {
+      ProfScope ps(p, SOX_STAGE_WGEMM, s);
+      DenseArgs<T, T> d{};
+      d.A = W2;
+      d.B = GG2;
+      d.C = AW;
+      d.lda = 2L * NP;
+      d.ldb = 2L * NP;
+      d.ldc = (long)vc * n;
+      d.sA = 4L * NP * NP;
+      d.sB = (long)vc * n * 2 * NP;
+      d.sC = 2L * NP * vc * n;
+      d.M = 2 * NP;
+      d.N = vc * n;
+      d.K = 2 * NP;
+      d.alpha = T(1);
+      d.transposed = 0;
+      d.accumulate = 0;
+      if (sizeof(T) == 8) SOX_HIP((launch_dense<T, T, 2, 2, 2, 2>(d, nw, s)));
+      else SOX_HIP((launch_dense<T, T, 2, 2, 4, 4>(d, nw, s)));
+    }
+    {
+      ProfScope ps(p, SOX_STAGE_IFT, s);
+      IFTProb<T> ift{p.d_tb2, AW, Adyn, n, nP, NP, nw, nt, vc, nt, NP * vc * nP, 2 * nw};
+      SOX_HIP((launch_gemm<IFTProb<T>, double, 2, 2, 2, 2>(ift, 1, s)));
+    }
+    FusedArgs<T> fa;
+    fa.A = Adyn;
+    fa.Y = XT;
+    fa.P2T = P2T;
+    fa.U2 = U2 + (long)v0 * nP;
+    fa.D = D;
+    fa.a_tstride = (long)vc * NP * nP;
+    fa.a_vstride = (long)NP * nP;
+    fa.y_tstride = 0;
+    fa.p_tstride = (long)NP * nP;
+    fa.u_rstride = (long)nP * nP;
+    fa.u_vstride = nP;
+    fa.d_tstride = (long)NP * NP;
+    fa.accumulate = v0 > 0;
+    fa.n = vc;
+    fa.nP = nP;
+    fa.NP = NP;
+    fa.tiles_p = tiles_p;
+    fa.tiles_r = tiles_r;
+    fa.n_tau = nt;
+    {
+      ProfScope ps(p, SOX_STAGE_FUSED, s);
+      st = launch_fused_cfg<T>(p, fa, s);
+      if (st) return st;
+    }
+  }
+  for (int t0 = 0; t0 < nt; t0 += p.eslab) {
+    const int cnt = std::min(p.eslab, nt - t0);
+    ProfScope ps(p, SOX_STAGE_BACK, s);
+    BackEProb<T> pe{X, D + (long)t0 * NP * NP, E, n, N, NP, n, N, N};
+    SOX_HIP((launch_gemm<BackEProb<T>, double, 2, 2, 2, 2>(pe, cnt, s)));
+    BackSigmaProb pb{X, E, Sigma, n, N, NP, t0, -1.0, n, n, N};
+    SOX_HIP((launch_gemm<BackSigmaProb, double, 2, 2, 2, 2>(pb, cnt, s)));
   }
   return SOX_OK;
 }
@@ -374,6 +587,10 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
   if (pr->n_omega < 0) return fail(SOX_ERR_SHAPE, "n_omega < 0");
   if (pr->n_omega > 0 && (!pr->t_fwd || !pr->t_bwd))
     return fail(SOX_ERR_INVALID_ARG, "n_omega > 0 but transform matrices are NULL");
+  if (pr->n_omega > 4096) return fail(SOX_ERR_SHAPE, "n_omega beyond the supported range");
+  for (size_t i = 0; pr->n_omega > 0 && i < 2 * (size_t)pr->n_omega * nt; ++i)
+    if (!std::isfinite(pr->t_fwd[i]) || !std::isfinite(pr->t_bwd[i]))
+      return fail(SOX_ERR_GRID, "transform matrices hold non-finite values");
 
   sox_plan* p = new (std::nothrow) sox_plan();
   if (!p) return fail(SOX_ERR_OOM, "host allocation failed");
@@ -399,8 +616,29 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
   }
   set_fused_cfg(*p, p->fused_cfg);
   p->slab = pick_slab(*p, SOX_ENTRY_STATIC);
+  if (p->n_omega > 0) pick_dyn(*p);
 
   hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess && p->n_omega > 0) {
+    const int nw = p->n_omega;
+    std::vector<double> tf2(2 * (size_t)nw * nt), tb2((size_t)nt * 2 * nw);
+    for (int m = 0; m < nw; ++m)
+      for (int j = 0; j < nt; ++j) {
+        tf2[(size_t)m * nt + j] = p->t_fwd[2 * ((size_t)m * nt + j)];
+        tf2[(size_t)(nw + m) * nt + j] = p->t_fwd[2 * ((size_t)m * nt + j) + 1];
+      }
+    for (int i = 0; i < nt; ++i)
+      for (int m = 0; m < nw; ++m) {
+        tb2[(size_t)i * 2 * nw + m] = p->t_bwd[2 * ((size_t)i * nw + m)];
+        tb2[(size_t)i * 2 * nw + nw + m] = -p->t_bwd[2 * ((size_t)i * nw + m) + 1];
+      }
+    e = hipMalloc(&p->d_tf2, sizeof(double) * tf2.size());
+    if (e == hipSuccess) e = hipMalloc(&p->d_tb2, sizeof(double) * tb2.size());
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_tf2, tf2.data(), sizeof(double) * tf2.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_tb2, tb2.data(), sizeof(double) * tb2.size(), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess) e = hipMalloc(&p->d_tau, sizeof(double) * nt);
   if (e == hipSuccess) e = hipMalloc(&p->d_w, sizeof(double) * nt);
   if (e == hipSuccess)
@@ -426,6 +664,8 @@ sox_status sox_plan_destroy(sox_plan* p) {
     (void)hipEventDestroy(e.b);
   }
   if (p->d_tau) (void)hipFree(p->d_tau);
+  if (p->d_tf2) (void)hipFree(p->d_tf2);
+  if (p->d_tb2) (void)hipFree(p->d_tb2);
   if (p->d_w) (void)hipFree(p->d_w);
   if (p->d_scratch) (void)hipFree(p->d_scratch);
   delete p;
@@ -437,7 +677,7 @@ sox_status sox_workspace_size(const sox_plan* plan, int32_t entry, size_t* bytes
   if (!bytes) return fail(SOX_ERR_INVALID_ARG, "bytes is NULL");
   if (entry < SOX_ENTRY_BARE || entry > SOX_ENTRY_DYNAMIC)
     return fail(SOX_ERR_INVALID_ARG, "unknown entry %d", entry);
-  *bytes = layout_for(*plan, entry, plan->slab).total;
+  *bytes = workspace_bytes(*plan, entry);
   return SOX_OK;
 }
 
@@ -455,10 +695,19 @@ sox_status sox_sigma_static(sox_plan* plan, const double* X, const double* W0, c
 sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_tau,
                              const double* V, const double* G, double* Sigma, void* ws,
                              size_t ws_bytes, void* stream) {
-  (void)X; (void)W_tau; (void)V; (void)G; (void)Sigma; (void)ws; (void)ws_bytes; (void)stream;
   sox_status st = check_plan(plan);
   if (st) return st;
-  return fail(SOX_ERR_UNSUPPORTED, "dynamic entry not implemented yet");
+  if (plan->n_omega <= 0)
+    return fail(SOX_ERR_INVALID_ARG, "plan has no transform pair (n_omega = 0)");
+  if (!X || !W_tau || !V || !G || !Sigma) return fail(SOX_ERR_INVALID_ARG, "NULL tensor pointer");
+  st = check_ws(plan, SOX_ENTRY_DYNAMIC, ws, ws_bytes);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  switch (plan->precision) {
+    case SOX_FP64: return run_dynamic<double>(*plan, X, W_tau, V, G, Sigma, ws, s);
+    case SOX_FP32: return run_dynamic<float>(*plan, X, W_tau, V, G, Sigma, ws, s);
+    default: return fail(SOX_ERR_UNSUPPORTED, "precision %d not implemented", plan->precision);
+  }
 }
 
 sox_status sox_sigma_vjp(sox_plan* plan, int32_t entry, const double* X, const double* U1,

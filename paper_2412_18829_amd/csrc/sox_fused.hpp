@@ -37,6 +37,7 @@ template <typename T> struct FusedArgs {
   long p_tstride;
   long u_rstride, u_vstride;
   long d_tstride;
+  int accumulate;  // D += result (v processed in slabs)
   int n;      // orbitals: the v range
   int nP;     // padded k depth (multiple of 16)
   int NP;     // padded THC extent (multiple of the tile)
@@ -155,7 +156,8 @@ __global__ __launch_bounds__(256) void fused_bcd_kernel(const FusedArgs<T> p) {
       for (int r = 0; r < 4; ++r) {
         const int P = P0 + 16 * i + acc_row<T>(g, r);
         const int R = R0 + 16 * j + li;
-        Db[(long)P * p.NP + R] = dacc[i][j][r];
+        const long off = (long)P * p.NP + R;
+        Db[off] = p.accumulate ? Db[off] + dacc[i][j][r] : dacc[i][j][r];
       }
 }
 

@@ -103,6 +103,160 @@ template <typename T> struct AStepProb {
 };
 
 // ---------------------------------------------------------------------------
+// Elementwise layout kernels.
+//   GbT[b][v][s] = G[n_tau-1-(t0+b)][s][v]  (A step operand, zero padded to nP)
+//   XT[R][u]     = X[u][R]                  (zero padded to NP x nP)
+//   dst = src converted (float64 -> contraction precision)
+template <typename T>
+__global__ void gbar_t_kernel(const double* G, T* out, int n, int nP, int n_tau, int t0, int cnt) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long per = (long)nP * nP;
+  if (idx >= per * cnt) return;
+  const int b = (int)(idx / per);
+  const int rem = (int)(idx - (long)b * per);
+  const int v = rem / nP, s = rem - (rem / nP) * nP;
+  T val = T(0);
+  if (v < n && s < n) val = T(G[(long)(n_tau - 1 - (t0 + b)) * n * n + (long)s * n + v]);
+  out[idx] = val;
+}
+
+template <typename T>
+__global__ void xt_kernel(const double* X, T* out, int n, int Nthc, int nP, int NP) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)NP * nP) return;
+  const int R = (int)(idx / nP), u = (int)(idx - (idx / nP) * nP);
+  out[idx] = (R < Nthc && u < n) ? T(X[(long)u * Nthc + R]) : T(0);
+}
+
+template <typename T>
+__global__ void cast_kernel(const double* src, T* dst, long count) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < count) dst[idx] = T(src[idx]);
+}
+
+// ---------------------------------------------------------------------------
+// Dynamic interaction (eq:GG scheme), transforms in float64.
+//
+// Tf2 [2 n_omega][n_tau]: rows 0..n_omega-1 = Re T_fwd, then Im T_fwd.
+// Tb2 [n_tau][2 n_omega]: [Re T_bwd | -Im T_bwd], so that
+//   Re sum_m T_bwd[i,m] f_m = sum_k Tb2[i,k] (Re f | Im f)_k.
+//
+// W(Omega_m) = sum_j T_fwd[m,j] W_tau[j] is stored as the real block matrix
+//   W2[m] = [[Re W, -Im W], [Im W, Re W]]   (2 NP x 2 NP)
+// so that one real GEMM W2[m] (Re GG; Im GG) gives (Re A; Im A).
+template <typename T> struct WOmegaProb {
+  const double* Tf2;   // [2 n_omega][n_tau]
+  const double* Wtau;  // [n_tau][N][N]
+  T* W2;               // [n_omega][2NP][2NP]
+  int n_omega, n_tau, Nthc, NP;
+  int M, N, K;         // M = 2 n_omega, N = NP*NP, K = n_tau
+  __device__ f64x4 loadA4(int, int row, int j) const {
+    if (row >= M) return zero4<double>();
+    return load4_strided<double>(Tf2 + (long)row * n_tau, 1, j, n_tau);
+  }
+  __device__ f64x4 loadB4(int, int col, int j) const {
+    if (col >= N) return zero4<double>();
+    const int P = col / NP, Q = col - (col / NP) * NP;
+    if (P >= Nthc || Q >= Nthc) return zero4<double>();
+    return load4_strided<double>(Wtau + (long)P * Nthc + Q, (long)Nthc * Nthc, j, n_tau);
+  }
+  __device__ void store(int, int row, int col, double v) const {
+    const int c = row / n_omega, m = row - (row / n_omega) * n_omega;
+    const int P = col / NP, Q = col - (col / NP) * NP;
+    const long ld = 2L * NP;
+    T* W = W2 + (long)m * ld * ld;
+    if (c == 0) {
+      W[(long)P * ld + Q] = T(v);
+      W[(long)(NP + P) * ld + NP + Q] = T(v);
+    } else {
+      W[(long)(NP + P) * ld + Q] = T(v);
+      W[(long)P * ld + NP + Q] = T(-v);
+    }
+  }
+};
+
+// GG formation fused into the forward transform, for the v-slab [v0, v0+vc):
+//   GG2[m][(vl,u)][c NP + Q] = sum_j Tf_c[m,j] G_uQ(tau_j) G_Qv(beta - tau_j)
+// with G_uQ(tau_j) = P2T[j][Q][u] and G_Qv(beta - tau_j) = P1[n_tau-1-j][Q][v]
+// (eq:GG; the third line read at beta - tau).
+template <typename T> struct FTProb {
+  const double* Tf2;   // [2 n_omega][n_tau]
+  const double* P1;    // [n_tau][NP][nP]  float64
+  const double* P2T;   // [n_tau][NP][nP]  float64
+  T* GG2;              // [n_omega][vc*n][2NP]
+  int n, nP, NP, Nthc, n_omega, n_tau, v0, vc;
+  int M, N, K;         // M = 2 n_omega, N = vc*n*NP, K = n_tau
+  __device__ f64x4 loadA4(int, int row, int j) const {
+    if (row >= M) return zero4<double>();
+    return load4_strided<double>(Tf2 + (long)row * n_tau, 1, j, n_tau);
+  }
+  __device__ f64x4 loadB4(int, int col, int j) const {
+    if (col >= N) return zero4<double>();
+    const int Q = col % NP;
+    const int vu = col / NP;
+    const int vl = vu / n, u = vu - (vu / n) * n;
+    const int v = v0 + vl;
+    if (Q >= Nthc || v >= n) return zero4<double>();
+    const long st = (long)NP * nP;
+    f64x4 r;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int jj = j + m;
+      r[m] = (jj < n_tau)
+                 ? P2T[jj * st + (long)Q * nP + u] * P1[(long)(n_tau - 1 - jj) * st + (long)Q * nP + v]
+                 : 0.0;
+    }
+    return r;
+  }
+  __device__ void store(int, int row, int col, double v) const {
+    const int c = row / n_omega, m = row - (row / n_omega) * n_omega;
+    const int Q = col % NP, vu = col / NP;
+    GG2[((long)m * vc * n + vu) * (2L * NP) + (long)c * NP + Q] = T(v);
+  }
+};
+
+// Inverse transform into the fused kernel's A layout for the v-slab:
+//   Adyn[tau][vl][P][u] = sum_k Tb2[tau][k] AW[m][c NP + P][vl n + u],  k = c n_omega + m
+// (u >= n is padding and written as zero).
+template <typename T> struct IFTProb {
+  const double* Tb2;   // [n_tau][2 n_omega]
+  const T* AW;         // [n_omega][2NP][vc*n]
+  T* Adyn;             // [n_tau][vc][NP][nP]
+  int n, nP, NP, n_omega, n_tau, vc;
+  int M, N, K;         // M = n_tau, N = NP*vc*nP, K = 2 n_omega
+  __device__ f64x4 loadA4(int, int t, int k) const {
+    if (t >= M) return zero4<double>();
+    return load4_strided<double>(Tb2 + (long)t * 2 * n_omega, 1, k, 2 * n_omega);
+  }
+  __device__ f64x4 loadB4(int, int col, int k) const {
+    if (col >= N) return zero4<double>();
+    const int u = col % nP;
+    const int pv = col / nP;
+    const int vl = pv % vc, P = pv / vc;
+    if (u >= n) return zero4<double>();
+    const long vcn = (long)vc * n;
+    f64x4 r;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int kk = k + m;
+      if (kk < 2 * n_omega) {
+        const int c = kk / n_omega, mm = kk - (kk / n_omega) * n_omega;
+        r[m] = double(AW[((long)mm * 2 * NP + (long)c * NP + P) * vcn + (long)vl * n + u]);
+      } else {
+        r[m] = 0.0;
+      }
+    }
+    return r;
+  }
+  __device__ void store(int, int t, int col, double v) const {
+    const int u = col % nP;
+    const int pv = col / nP;
+    const int vl = pv % vc, P = pv / vc;
+    Adyn[(((long)t * vc + vl) * NP + P) * nP + u] = T(v);
+  }
+};
+
+// ---------------------------------------------------------------------------
 // Back-transform (float64):  E[t][tt][P] = sum_R X[tt][R] D[t][P][R]
 //                            Sigma[tau][tt][r] = -sum_P E[t][tt][P] X[r][P]
 template <typename Td> struct BackEProb {
