@@ -19,6 +19,8 @@
 #include "sox_fused.hpp"
 #include "sox_gemm.hpp"
 #include "sox_steps.hpp"
+#include "sox_adjoint.hpp"
+#include "sox_vjp_steps.hpp"
 
 using namespace sox;
 
@@ -76,6 +78,7 @@ struct sox_plan {
   std::vector<double> tau, weights;
   int n_omega;
   std::vector<double> t_fwd, t_bwd;  // complex interleaved (host copies)
+  int vjp_slab = 1; // tau nodes per slab of the adjoint chain
   int vc = 0;       // dynamic entry: v-slab width
   int eslab = 0;    // dynamic entry: tau nodes per back-transform slab
   // device copies
@@ -237,9 +240,55 @@ sox_status check_plan(const sox_plan* plan) {
   return SOX_OK;
 }
 
+struct VjpLayout {
+  size_t u1t, u2t, u2tT, du1t, du2t, mbuf, dgs, dxs;
+  size_t p1, p1t, p2t, p2, gbt, a, at, e2, e3, dd, ddt, da, dp1, dp2t, d, total;
+};
+
+VjpLayout vjp_layout_for(const sox_plan& p, int entry, int slab) {
+  VjpLayout L{};
+  const size_t es = elem_size(p.precision);
+  const size_t nP = p.nP, NP = p.NP, n = p.n, N = p.N, nt = p.n_tau, c = slab;
+  Carver k;
+  L.u1t = k.take(NP * nP * nP * es);
+  L.u2t = (entry == SOX_ENTRY_BARE) ? L.u1t : k.take(NP * nP * nP * es);
+  L.u2tT = k.take(nP * nP * NP * es);
+  L.du1t = k.take(NP * nP * nP * 8);
+  L.du2t = k.take(nP * NP * nP * 8);
+  L.mbuf = k.take(NP * nP * nP * 8);
+  L.dgs = k.take(nt * n * n * 8);
+  L.dxs = k.take(n * N * 8);
+  L.p1 = k.take(c * NP * nP * es);
+  L.p1t = k.take(c * nP * NP * es);
+  L.p2t = k.take(c * NP * nP * es);
+  L.p2 = k.take(c * nP * NP * es);
+  L.gbt = k.take(c * nP * nP * es);
+  L.a = k.take(c * n * NP * nP * es);
+  L.at = k.take(c * n * nP * NP * es);
+  L.e2 = k.take(c * n * NP * 8);
+  L.e3 = k.take(c * n * NP * 8);
+  L.dd = k.take(c * NP * NP * es);
+  L.ddt = k.take(c * NP * NP * es);
+  L.da = k.take(c * n * NP * nP * 8);
+  L.dp1 = k.take(c * NP * nP * 8);
+  L.dp2t = k.take(c * NP * nP * 8);
+  L.d = k.take(c * NP * NP * es);
+  L.total = k.off;
+  return L;
+}
+
+int pick_vjp_slab(const sox_plan& p, int entry) {
+  const size_t budget = ws_budget();
+  int slab = p.n_tau;
+  while (slab > 1 && vjp_layout_for(p, entry, slab).total > budget) slab = (slab + 1) / 2;
+  return slab;
+}
+
 size_t workspace_bytes(const sox_plan& p, int entry) {
   if (entry == SOX_ENTRY_DYNAMIC) return p.n_omega > 0 ? dyn_layout_for(p, p.vc, p.eslab).total : 0;
-  return layout_for(p, entry, p.slab).total;
+  const size_t fwd = layout_for(p, entry, p.slab).total;
+  const size_t vjp = vjp_layout_for(p, entry, p.vjp_slab).total;
+  return std::max(fwd, vjp);
 }
 
 sox_status check_ws(const sox_plan* plan, int entry, const void* ws, size_t ws_bytes) {
@@ -255,7 +304,7 @@ sox_status check_ws(const sox_plan* plan, int entry, const void* ws, size_t ws_b
 template <typename T>
 sox_status launch_utensor(const sox_plan& p, const double* U, const double* X, T* out,
                           hipStream_t s) {
-  UTensorProb<T> pr{U, X, out, p.n, p.N, p.nP, p.NP, p.nP * p.nP, p.N};
+  UTensorProb<T> pr{U, X, out, p.n, p.N, p.nP, p.NP, p.nP * p.nP, p.N, 0, p.NP};
   SOX_HIP((launch_gemm<UTensorProb<T>, double, 2, 2, 2, 2>(pr, 1, s)));
   return SOX_OK;
 }
@@ -528,6 +577,198 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
   return SOX_OK;
 }
 
+template <typename T>
+sox_status launch_transpose(const T* in, T* out, int rows, int cols, long batch, hipStream_t s) {
+  if (batch <= 0) return SOX_OK;
+  if (batch > 65535) return fail(SOX_ERR_SHAPE, "internal: transpose batch too large");
+  dim3 grid((cols + 31) / 32, (rows + 31) / 32, (unsigned)batch);
+  hipLaunchKernelGGL(transpose_kernel<T>, grid, dim3(256), 0, s, in, out, rows, cols, batch);
+  SOX_HIP(hipGetLastError());
+  return SOX_OK;
+}
+
+template <typename T>
+sox_status launch_fill(T* ptr, long count, hipStream_t s) {
+  if (count <= 0) return SOX_OK;
+  hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, ptr,
+                     count, T(0));
+  SOX_HIP(hipGetLastError());
+  return SOX_OK;
+}
+
+template <typename T>
+sox_status launch_hc_cfg(const sox_plan& p, HcArgs<T, double> a, int nx, hipStream_t s) {
+  const int nyb = a.ny / 16;
+  const bool wide = sizeof(T) == 4 && nx % 128 == 0;
+#define SOX_HC(XB, YB) SOX_HIP((launch_hc<T, double, XB, YB>(a, nx, s)))
+  if (nyb <= 4) { if (wide) SOX_HC(2, 4); else SOX_HC(1, 4); }
+  else if (nyb <= 8) { if (wide) SOX_HC(2, 8); else SOX_HC(1, 8); }
+  else if (nyb <= 13) { if (wide) SOX_HC(2, 13); else SOX_HC(1, 13); }
+  else if (nyb <= 20) { if (wide) SOX_HC(2, 20); else SOX_HC(1, 20); }
+  else return fail(SOX_ERR_UNSUPPORTED, "adjoint kernels support n_orb <= 320");
+#undef SOX_HC
+  (void)p;
+  return SOX_OK;
+}
+
+template <typename T>
+sox_status run_vjp_static(sox_plan& p, int entry, const double* X, const double* U1,
+                          const double* U2, const double* G, const double* R, double* dG,
+                          double* dX, double* dU1, double* dU2, void* ws, hipStream_t s) {
+  // the bare entry carries one interaction: both lines read U1 (U2 may be NULL)
+  if (entry == SOX_ENTRY_BARE) U2 = U1;
+  const VjpLayout L = vjp_layout_for(p, entry, p.vjp_slab);
+  char* base = (char*)ws;
+  T* u1t = (T*)(base + L.u1t);
+  T* u2t = (T*)(base + L.u2t);
+  T* u2tT = (T*)(base + L.u2tT);
+  double* du1t = (double*)(base + L.du1t);
+  double* du2t = (double*)(base + L.du2t);
+  double* mbuf = (double*)(base + L.mbuf);
+  double* dGs = (double*)(base + L.dgs);
+  double* dXs = (double*)(base + L.dxs);
+  T* P1 = (T*)(base + L.p1);
+  T* P1T = (T*)(base + L.p1t);
+  T* P2T = (T*)(base + L.p2t);
+  T* P2 = (T*)(base + L.p2);
+  T* gbt = (T*)(base + L.gbt);
+  T* A = (T*)(base + L.a);
+  T* AT = (T*)(base + L.at);
+  double* E2 = (double*)(base + L.e2);
+  double* E3 = (double*)(base + L.e3);
+  T* dD = (T*)(base + L.dd);
+  T* dDT = (T*)(base + L.ddt);
+  double* dA = (double*)(base + L.da);
+  double* dP1 = (double*)(base + L.dp1);
+  double* dP2T = (double*)(base + L.dp2t);
+  T* D = (T*)(base + L.d);
+  const int n = p.n, N = p.N, nP = p.nP, NP = p.NP, nt = p.n_tau;
+  const long NPnP = (long)NP * nP;
+  const FusedCfg& fc = kFusedCfgs[p.fused_cfg];
+  if (NP % (2 * fc.wp) != 0 || NP % (2 * fc.wr) != 0 || NP % 64 != 0)
+    return fail(SOX_ERR_SHAPE, "internal: padded extent does not fit the tiles");
+  const int tiles_p = NP / (2 * fc.wp), tiles_r = NP / (2 * fc.wr);
+  ProfScope ps(p, SOX_STAGE_VJP, s);
+  sox_status st;
+  if ((st = launch_fill<double>(dGs, (long)nt * n * n, s))) return st;
+  if ((st = launch_fill<double>(dXs, (long)n * N, s))) return st;
+  if ((st = launch_fill<double>(du1t, NPnP * nP, s))) return st;
+  if ((st = launch_fill<double>(du2t, NPnP * nP, s))) return st;
+  if ((st = launch_utensor<T>(p, U1, X, u1t, s))) return st;
+  if (entry != SOX_ENTRY_BARE && (st = launch_utensor<T>(p, U2, X, u2t, s))) return st;
+  {
+    UTensorProb<T> pr{U2, X, u2tT, n, N, nP, NP, nP * nP, N, 1, NP};
+    SOX_HIP((launch_gemm<UTensorProb<T>, double, 2, 2, 2, 2>(pr, 1, s)));
+  }
+  for (int t0 = 0; t0 < nt; t0 += p.vjp_slab) {
+    const int cnt = std::min(p.vjp_slab, nt - t0);
+    // forward intermediates of the slab
+    ProjP1Prob<T> pr1{X, G, P1, n, N, nP, NP, t0, NP, nP, n};
+    SOX_HIP((launch_gemm<ProjP1Prob<T>, double, 2, 2, 2, 2>(pr1, cnt, s)));
+    ProjP2TProb<T> pr2{X, G, P2T, n, N, nP, NP, t0, NP, nP, n};
+    SOX_HIP((launch_gemm<ProjP2TProb<T>, double, 2, 2, 2, 2>(pr2, cnt, s)));
+    if ((st = launch_transpose<T>(P1, P1T, NP, nP, cnt, s))) return st;
+    if ((st = launch_transpose<T>(P2T, P2, NP, nP, cnt, s))) return st;
+    if ((st = launch_gbar_t<T>(p, G, gbt, t0, cnt, s))) return st;
+    if ((st = launch_astep<T>(p, u1t, gbt, A, cnt, s))) return st;
+    if ((st = launch_transpose<T>(A, AT, NP, nP, (long)cnt * n, s))) return st;
+    // cotangent of D
+    RXProb rx{R, X, E2, n, N, NP, t0, 0, n, N, n};
+    SOX_HIP((launch_gemm<RXProb, double, 2, 2, 2, 2>(rx, cnt, s)));
+    RXProb rx3{R, X, E3, n, N, NP, t0, 1, n, N, n};
+    SOX_HIP((launch_gemm<RXProb, double, 2, 2, 2, 2>(rx3, cnt, s)));
+    DDProb<T> ddp{X, E2, dD, dDT, n, N, NP, NP, NP, n};
+    SOX_HIP((launch_gemm<DDProb<T>, double, 2, 2, 2, 2>(ddp, cnt, s)));
+    // D itself (for the back-transform's dX term)
+    FusedArgs<T> fa;
+    fa.A = A; fa.Y = P1; fa.P2T = P2T; fa.U2 = u2t; fa.D = D;
+    fa.a_tstride = (long)n * NPnP; fa.a_vstride = NPnP; fa.y_tstride = NPnP; fa.p_tstride = NPnP;
+    fa.u_rstride = (long)nP * nP; fa.u_vstride = nP; fa.d_tstride = (long)NP * NP;
+    fa.accumulate = 0; fa.n = n; fa.nP = nP; fa.NP = NP;
+    fa.tiles_p = tiles_p; fa.tiles_r = tiles_r; fa.n_tau = cnt;
+    if ((st = launch_fused_cfg<T>(p, fa, s))) return st;
+    // the four Hadamard-contract adjoints
+    HcArgs<T, double> h{};
+    h.nz = NP; h.nk = nP; h.ny = nP;
+    // dA[b][v][P][q] = sum_R dD[P,R] C[R,v,P] G_Rq[R,q]
+    h.L = u2t; h.l_ld = (long)nP * nP; h.l_ts = 0; h.l_vs = nP;
+    h.Rm = P2T; h.r_ld = nP; h.r_ts = NPnP; h.r_vs = 0;
+    h.W = dDT; h.w_ld = NP; h.w_ts = (long)NP * NP;
+    h.FT = P1T; h.f_ld = NP; h.f_ts = NPnP; h.f_vs = 0;
+    h.Out = dA; h.o_ld = nP; h.o_ts = (long)n * NPnP; h.o_vs = NPnP;
+    h.n_ot = cnt; h.n_ov = n; h.n_it = 1; h.n_iv = 1; h.accumulate = 0;
+    if ((st = launch_hc_cfg<T>(p, h, NP, s))) return st;
+    // dG_Rq[b][R][q] = sum_{P,v} dD[P,R] C[R,v,P] A[P,q,v]
+    h.L = P2T; h.l_ld = nP; h.l_ts = NPnP; h.l_vs = 0;
+    h.Rm = u2t; h.r_ld = (long)nP * nP; h.r_ts = 0; h.r_vs = nP;
+    h.W = dD;
+    h.FT = AT; h.f_ld = NP; h.f_ts = (long)n * NPnP; h.f_vs = NPnP;
+    h.Out = dP1; h.o_ld = nP; h.o_ts = NPnP; h.o_vs = 0;
+    h.n_ot = cnt; h.n_ov = 1; h.n_it = 1; h.n_iv = n; h.accumulate = 0;
+    if ((st = launch_hc_cfg<T>(p, h, NP, s))) return st;
+    // dU2[v][R][w] += sum_{tau,P} dD[P,R] B[P,R,v] G_wP[w,P]
+    h.L = A; h.l_ld = nP; h.l_ts = (long)n * NPnP; h.l_vs = NPnP;
+    h.Rm = P1; h.r_ld = nP; h.r_ts = NPnP; h.r_vs = 0;
+    h.W = dD;
+    h.FT = P2; h.f_ld = NP; h.f_ts = NPnP; h.f_vs = 0;
+    h.Out = du2t; h.o_ld = nP; h.o_ts = 0; h.o_vs = NPnP;
+    h.n_ot = 1; h.n_ov = n; h.n_it = cnt; h.n_iv = 1; h.accumulate = 1;
+    if ((st = launch_hc_cfg<T>(p, h, NP, s))) return st;
+    // dG_wP^T[b][P][w] = sum_{R,v} dD[P,R] B[P,R,v] U2[R,v,w]
+    h.L = P1; h.l_ld = nP; h.l_ts = NPnP; h.l_vs = 0;
+    h.Rm = A; h.r_ld = nP; h.r_ts = (long)n * NPnP; h.r_vs = NPnP;
+    h.W = dDT;
+    h.FT = u2tT; h.f_ld = NP; h.f_ts = 0; h.f_vs = NPnP;
+    h.Out = dP2T; h.o_ld = nP; h.o_ts = NPnP; h.o_vs = 0;
+    h.n_ot = cnt; h.n_ov = 1; h.n_it = 1; h.n_iv = n; h.accumulate = 0;
+    if ((st = launch_hc_cfg<T>(p, h, NP, s))) return st;
+    // A step adjoint: dU1t and dG(beta - tau)
+    DU1tProb du{dA, G, du1t, n, nP, NP, nt, t0, (int)NPnP, nP, cnt * n};
+    SOX_HIP((launch_gemm<DU1tProb, double, 2, 2, 2, 2>(du, 1, s)));
+    DGbProb<T> dgb{u1t, dA, dGs, n, nP, NP, nt, t0, n, n, (int)NPnP};
+    SOX_HIP((launch_gemm<DGbProb<T>, double, 2, 2, 2, 2>(dgb, cnt, s)));
+    // half-projection adjoints
+    DGProjProb g1{X, dP1, dGs, n, N, nP, NP, t0, 0, n, n, N};
+    SOX_HIP((launch_gemm<DGProjProb, double, 2, 2, 2, 2>(g1, cnt, s)));
+    DGProjProb g2{X, dP2T, dGs, n, N, nP, NP, t0, 1, n, n, N};
+    SOX_HIP((launch_gemm<DGProjProb, double, 2, 2, 2, 2>(g2, cnt, s)));
+    DXProjProb x1{G, dP1, dXs, n, N, nP, NP, t0, 0, n, N, cnt * nP};
+    SOX_HIP((launch_gemm<DXProjProb, double, 2, 2, 2, 2>(x1, 1, s)));
+    DXProjProb x2{G, dP2T, dXs, n, N, nP, NP, t0, 1, n, N, cnt * nP};
+    SOX_HIP((launch_gemm<DXProjProb, double, 2, 2, 2, 2>(x2, 1, s)));
+    // back-transform adjoint
+    DXBackProb<T> b1{E2, D, dXs, n, N, NP, 0, n, N, cnt * NP};
+    SOX_HIP((launch_gemm<DXBackProb<T>, double, 2, 2, 2, 2>(b1, 1, s)));
+    DXBackProb<T> b2{E3, D, dXs, n, N, NP, 1, n, N, cnt * NP};
+    SOX_HIP((launch_gemm<DXBackProb<T>, double, 2, 2, 2, 2>(b2, 1, s)));
+  }
+  // U-contraction adjoints
+  const bool bare = entry == SOX_ENTRY_BARE;
+  if (dU1) {
+    DUProb a1{du1t, X, dU1, n, N, nP, NP, 0, 0, N, N, nP * nP};
+    SOX_HIP((launch_gemm<DUProb, double, 2, 2, 2, 2>(a1, 1, s)));
+  }
+  double* dU2dst = bare ? dU1 : dU2;
+  if (dU2dst) {
+    DUProb a2{du2t, X, dU2dst, n, N, nP, NP, 1, bare ? 1 : 0, N, N, nP * nP};
+    SOX_HIP((launch_gemm<DUProb, double, 2, 2, 2, 2>(a2, 1, s)));
+  }
+  const long nx = (long)n * N;
+  DUMProb m1{U1, du1t, mbuf, n, N, nP, NP, 0, N, nP * nP, N};
+  SOX_HIP((launch_gemm<DUMProb, double, 2, 2, 2, 2>(m1, 1, s)));
+  hipLaunchKernelGGL(ut_adjoint_x_kernel, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, mbuf,
+                     X, dXs, n, N, nP);
+  SOX_HIP(hipGetLastError());
+  DUMProb m2{U2, du2t, mbuf, n, N, nP, NP, 1, N, nP * nP, N};
+  SOX_HIP((launch_gemm<DUMProb, double, 2, 2, 2, 2>(m2, 1, s)));
+  hipLaunchKernelGGL(ut_adjoint_x_kernel, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, mbuf,
+                     X, dXs, n, N, nP);
+  SOX_HIP(hipGetLastError());
+  if (dG) SOX_HIP(hipMemcpyAsync(dG, dGs, sizeof(double) * nt * n * n, hipMemcpyDeviceToDevice, s));
+  if (dX) SOX_HIP(hipMemcpyAsync(dX, dXs, sizeof(double) * nx, hipMemcpyDeviceToDevice, s));
+  return SOX_OK;
+}
+
 sox_status dispatch_static(sox_plan* plan, int entry, const double* X, const double* U1,
                            const double* U2, const double* G, double* Sigma, void* ws,
                            size_t ws_bytes, void* stream) {
@@ -616,6 +857,7 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
   }
   set_fused_cfg(*p, p->fused_cfg);
   p->slab = pick_slab(*p, SOX_ENTRY_STATIC);
+  p->vjp_slab = pick_vjp_slab(*p, SOX_ENTRY_STATIC);
   if (p->n_omega > 0) pick_dyn(*p);
 
   hipError_t e = hipGetDevice(&p->device);
@@ -714,11 +956,25 @@ sox_status sox_sigma_vjp(sox_plan* plan, int32_t entry, const double* X, const d
                          const double* U2, const double* G, const double* R, double* dG,
                          double* dX, double* dU1, double* dU2, void* ws, size_t ws_bytes,
                          void* stream) {
-  (void)entry; (void)X; (void)U1; (void)U2; (void)G; (void)R; (void)dG; (void)dX; (void)dU1;
-  (void)dU2; (void)ws; (void)ws_bytes; (void)stream;
   sox_status st = check_plan(plan);
   if (st) return st;
-  return fail(SOX_ERR_UNSUPPORTED, "vjp not implemented yet");
+  if (entry < SOX_ENTRY_BARE || entry > SOX_ENTRY_DYNAMIC)
+    return fail(SOX_ERR_INVALID_ARG, "unknown entry %d", entry);
+  if (!X || !U1 || !G || !R) return fail(SOX_ERR_INVALID_ARG, "NULL input pointer");
+  if (entry != SOX_ENTRY_BARE && !U2) return fail(SOX_ERR_INVALID_ARG, "U2 is NULL");
+  if (entry == SOX_ENTRY_BARE && dU2)
+    return fail(SOX_ERR_INVALID_ARG, "bare entry: dU2 must be NULL (dU1 receives dL/dV)");
+  if (entry == SOX_ENTRY_DYNAMIC) return fail(SOX_ERR_UNSUPPORTED, "dynamic vjp not implemented yet");
+  st = check_ws(plan, entry, ws, ws_bytes);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  switch (plan->precision) {
+    case SOX_FP64:
+      return run_vjp_static<double>(*plan, entry, X, U1, U2, G, R, dG, dX, dU1, dU2, ws, s);
+    case SOX_FP32:
+      return run_vjp_static<float>(*plan, entry, X, U1, U2, G, R, dG, dX, dU1, dU2, ws, s);
+    default: return fail(SOX_ERR_UNSUPPORTED, "precision %d not implemented", plan->precision);
+  }
 }
 
 sox_status sox_build_g_tau(sox_plan* plan, const double* Q, const double* eps, double mu,

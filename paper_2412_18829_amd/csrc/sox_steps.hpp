@@ -19,9 +19,11 @@ namespace sox {
 template <typename Tout> struct UTensorProb {
   const double* U;  // [N][N]
   const double* X;  // [n][N]
-  Tout* out;        // [NP][nP][nP]
+  Tout* out;        // layout 0: [NP][nP][nP];  layout 1: [nP][nP][NP] (P fastest)
   int n, Nthc, nP;
   int M, N, K;      // M = NP, N = nP*nP, K = Nthc
+  int layout;
+  int NPld;         // P extent of layout 1
   __device__ f64x4 loadA4(int, int P, int Q) const {
     if (P >= Nthc) return zero4<double>();
     return load4_strided<double>(U + (long)P * Nthc, 1, Q, Nthc);
@@ -33,7 +35,10 @@ template <typename Tout> struct UTensorProb {
     f64x4 b = load4_strided<double>(X + (long)s * Nthc, 1, Q, Nthc);
     return a * b;
   }
-  __device__ void store(int, int P, int j, double v) const { out[(long)P * nP * nP + j] = Tout(v); }
+  __device__ void store(int, int P, int j, double v) const {
+    if (layout == 0) out[(long)P * nP * nP + j] = Tout(v);
+    else out[(long)j * NPld + P] = Tout(v);
+  }
 };
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,79 @@
+#include <hip/hip_runtime.h>
+// Host bounds check of every entry point of libsox: the real sources are
+// compiled for the CPU with a HIP shim under AddressSanitizer, each carved
+// workspace buffer is followed by a poisoned guard gap, and every caller
+// buffer is allocated to its exact size.
+#include <vector>
+#include <cstdio>
+thread_local uint3e threadIdx, blockIdx, blockDim, gridDim;
+const char* g_emu_kernel = "";
+// workspace guard: every carved buffer is followed by a poisoned gap
+static char* g_ws_base = nullptr;
+static size_t g_ws_size = 0;
+struct EmuCarver {
+  size_t off = 0;
+  EmuCarver() { if (g_ws_base) ASAN_UNPOISON_MEMORY_REGION(g_ws_base, g_ws_size); }
+  size_t take(size_t bytes) {
+    size_t o = off;
+    size_t end = o + bytes;
+    off = ((end + 4096) + 255) & ~size_t(255);
+    if (g_ws_base && off <= g_ws_size) ASAN_POISON_MEMORY_REGION(g_ws_base + end, off - end);
+    return o;
+  }
+};
+#define Carver EmuCarver
+#include "../../paper_2412_18829_amd/csrc/sox_api.hip"
+#undef Carver
+
+static double* dalloc(size_t n, double fill_scale = 0.1) {
+  double* p = (double*)malloc(n * sizeof(double));
+  for (size_t i = 0; i < n; ++i) p[i] = fill_scale * (((i * 2654435761u) % 1000) / 1000.0 - 0.5);
+  return p;
+}
+
+int run_case(int n, int N, int nt, int prec, int entry, bool vjp, bool dyn) {
+  std::vector<double> tau(nt), w(nt, 1.0);
+  const double beta = 5.0;
+  for (int k = 0; k < nt; ++k) tau[k] = beta * (k + 0.5) / nt;
+  sox_problem pr{};
+  pr.n_orb = n; pr.n_thc = N; pr.n_tau = nt; pr.kmesh[0] = pr.kmesh[1] = pr.kmesh[2] = 1;
+  pr.beta = beta; pr.tau = tau.data(); pr.weights = w.data();
+  int nw = 3;
+  std::vector<double> tf(2 * nw * nt, 0.01), tb(2 * nw * nt, 0.01);
+  if (dyn) { pr.n_omega = nw; pr.t_fwd = tf.data(); pr.t_bwd = tb.data(); }
+  sox_plan* plan = nullptr;
+  if (sox_plan_create(&pr, prec, &plan)) { printf("create failed: %s\n", sox_last_error()); return 1; }
+  size_t wsb = 0;
+  sox_workspace_size(plan, entry, &wsb);
+  g_ws_size = wsb + 4096;
+  g_ws_base = (char*)aligned_alloc(256, (g_ws_size + 255) & ~size_t(255));
+  double* X = dalloc((size_t)n * N);
+  double* U1 = dalloc((size_t)N * N * (entry == 2 ? nt : 1));
+  double* U2 = dalloc((size_t)N * N);
+  double* G = dalloc((size_t)nt * n * n);
+  double* S = dalloc((size_t)nt * n * n);
+  double* R = dalloc((size_t)nt * n * n);
+  double* dG = dalloc((size_t)nt * n * n);
+  double* dX = dalloc((size_t)n * N);
+  double* dU1 = dalloc((size_t)N * N * (entry == 2 ? nt : 1));
+  double* dU2 = dalloc((size_t)N * N);
+  sox_status st;
+  if (!vjp) {
+    if (entry == 0) st = sox_sigma_bare(plan, X, U1, G, S, g_ws_base, wsb, nullptr);
+    else if (entry == 1) st = sox_sigma_static(plan, X, U1, U2, G, S, g_ws_base, wsb, nullptr);
+    else st = sox_sigma_dynamic(plan, X, U1, U2, G, S, g_ws_base, wsb, nullptr);
+  } else {
+    st = sox_sigma_vjp(plan, entry, X, U1, entry == 0 ? nullptr : U2, G, R, dG, dX, dU1,
+                       entry == 0 ? nullptr : dU2, g_ws_base, wsb, nullptr);
+  }
+  printf("case n=%d N=%d nt=%d prec=%d entry=%d vjp=%d -> status %d %s\n", n, N, nt, prec, entry, vjp, st, st ? sox_last_error() : "");
+  ASAN_UNPOISON_MEMORY_REGION(g_ws_base, g_ws_size);
+  g_ws_base = nullptr;
+  sox_plan_destroy(plan);
+  return st;
+}
+
+int main(int argc, char** argv) {
+  int n = atoi(argv[1]), N = atoi(argv[2]), nt = atoi(argv[3]), prec = atoi(argv[4]), entry = atoi(argv[5]), vjp = atoi(argv[6]);
+  return run_case(n, N, nt, prec, entry, vjp, entry == 2);
+}

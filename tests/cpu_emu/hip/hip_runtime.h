@@ -1,0 +1,60 @@
+// Minimal HIP-on-CPU shim used only by the host bounds check (tests/test_cpu_emu.py):
+// the library sources are compiled for the host under AddressSanitizer and
+// every kernel launch runs all blocks and threads one after another.  MFMA
+// results are not emulated (no address in the kernels depends on data), so
+// only the memory accesses are meaningful.
+#pragma once
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <cstdio>
+#include <cstdint>
+#include <sanitizer/asan_interface.h>
+struct dim3 { unsigned x, y, z; dim3(unsigned a = 1, unsigned b = 1, unsigned c = 1) : x(a), y(b), z(c) {} };
+struct uint3e { unsigned x, y, z; };
+extern thread_local uint3e threadIdx, blockIdx, blockDim, gridDim;
+#define __global__
+#define __device__
+#define __host__
+#define __forceinline__ inline
+#define __launch_bounds__(x)
+#define __shared__ static
+inline void __syncthreads() {}
+typedef int hipError_t;
+enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2 };
+typedef void* hipStream_t;
+typedef void* hipEvent_t;
+enum hipMemcpyKind { hipMemcpyHostToDevice, hipMemcpyDeviceToHost, hipMemcpyDeviceToDevice };
+inline const char* hipGetErrorString(hipError_t) { return "emu"; }
+inline hipError_t hipGetLastError() { return hipSuccess; }
+inline hipError_t hipGetDevice(int* d) { *d = 0; return hipSuccess; }
+inline hipError_t hipMalloc(void** p, size_t n) { *p = malloc(n); return *p ? hipSuccess : hipErrorOutOfMemory; }
+template <typename T> inline hipError_t hipMalloc(T** p, size_t n) { return hipMalloc((void**)p, n); }
+inline hipError_t hipFree(void* p) { free(p); return hipSuccess; }
+inline hipError_t hipMemcpy(void* d, const void* s, size_t n, hipMemcpyKind) { memcpy(d, s, n); return hipSuccess; }
+inline hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, hipMemcpyKind, hipStream_t) { memcpy(d, s, n); return hipSuccess; }
+inline hipError_t hipStreamSynchronize(hipStream_t) { return hipSuccess; }
+inline hipError_t hipEventCreate(hipEvent_t* e) { *e = malloc(1); return hipSuccess; }
+inline hipError_t hipEventDestroy(hipEvent_t e) { free(e); return hipSuccess; }
+inline hipError_t hipEventRecord(hipEvent_t, hipStream_t) { return hipSuccess; }
+inline hipError_t hipEventSynchronize(hipEvent_t) { return hipSuccess; }
+inline hipError_t hipEventElapsedTime(float* t, hipEvent_t, hipEvent_t) { *t = 0; return hipSuccess; }
+typedef float emu_f4 __attribute__((ext_vector_type(4)));
+typedef double emu_d4 __attribute__((ext_vector_type(4)));
+inline emu_f4 emu_mfma_f(float a, float b, emu_f4 c) { return c + a * b; }
+inline emu_d4 emu_mfma_d(double a, double b, emu_d4 c) { return c + a * b; }
+#define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) emu_mfma_f(a, b, c)
+#define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) emu_mfma_d(a, b, c)
+#define __builtin_amdgcn_sched_barrier(x) ((void)0)
+extern const char* g_emu_kernel;
+template <typename K, typename... A>
+inline void emu_launch(const char* name, K kernel, dim3 g, dim3 b, A... args) {
+  g_emu_kernel = name;
+  gridDim = {g.x, g.y, g.z}; blockDim = {b.x, b.y, b.z};
+  for (unsigned bz = 0; bz < g.z; ++bz) for (unsigned by = 0; by < g.y; ++by) for (unsigned bx = 0; bx < g.x; ++bx)
+    for (unsigned tz = 0; tz < b.z; ++tz) for (unsigned ty = 0; ty < b.y; ++ty) for (unsigned tx = 0; tx < b.x; ++tx) {
+      blockIdx = {bx, by, bz}; threadIdx = {tx, ty, tz};
+      kernel(args...);
+    }
+}
+#define hipLaunchKernelGGL(k, g, b, shm, st, ...) emu_launch(#k, k, dim3(g), dim3(b), __VA_ARGS__)

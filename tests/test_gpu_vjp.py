@@ -1,0 +1,90 @@
+"""GPU adjoint (sox_sigma_vjp, via torch.autograd) against the FP64 reference
+VJP (torch CPU autograd of the step chain, pinned by finite differences of
+the 4-index brute force in test_oracle_vjp.py).
+
+Tolerance per gradient (max |diff| / max |ref|): FP64 1e-10, FP32 1e-5.
+"""
+import numpy as np
+import pytest
+
+from oracle import sox_mol as om
+from oracle import sox_vjp as ov
+from paper_2412_18829_amd import synth
+from tests.gpu_util import dev, have_gpu, host, log, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-10, "fp32": 1e-5}
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not have_gpu():
+        pytest.skip("no GPU")
+    from paper_2412_18829_amd import binding
+    binding.load()
+    return binding
+
+
+def _inputs(n, N, nt, beta, seed):
+    wl = synth.small_molecule(n, N, nt, beta, seed=seed, static=True)
+    rng = np.random.default_rng(seed)
+    G = om.g_tau(wl["eps"], wl["Q"], 0.0, beta, wl["tau"]) + 0.05 * rng.standard_normal((nt, n, n))
+    R = rng.standard_normal((nt, n, n))
+    return wl, G, R
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("entry", ["bare", "static"])
+@pytest.mark.parametrize("shape", [(6, 20, 8), (13, 70, 5), (24, 130, 6)])
+def test_static_vjp_vs_reference(B, precision, entry, shape):
+    import torch
+    from paper_2412_18829_amd import autograd as AG
+    n, N, nt = shape
+    log(f"vjp {entry} {shape} {precision}")
+    wl, G, R = _inputs(n, N, nt, 7.0, 500 + n)
+    X, V = wl["X"], wl["V"]
+    U1 = V if entry == "bare" else wl["W0"]
+    plan = B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision=precision)
+    Xd, U1d, Gd = dev(X).requires_grad_(), dev(U1).requires_grad_(), dev(G).requires_grad_()
+    U2d = None if entry == "bare" else dev(V).requires_grad_()
+    S = AG.sox_sigma(plan, Xd, U1d, Gd, U2d)
+    S.backward(dev(R))
+    torch.cuda.synchronize()
+    dG, dX, d1, d2 = ov.vjp_static(X, U1, V, G, R, bare=(entry == "bare"))
+    errs = {"dG": rel_err(host(Gd.grad), dG), "dX": rel_err(host(Xd.grad), dX),
+            "dU1": rel_err(host(U1d.grad), d1)}
+    if entry == "static":
+        errs["dU2"] = rel_err(host(U2d.grad), d2)
+    log("  " + " ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v <= TOL[precision], k
+
+
+def test_vjp_slabs_match_single_slab(B, monkeypatch):
+    import torch
+    n, N, nt = 10, 64, 7
+    wl, G, R = _inputs(n, N, nt, 5.0, 9)
+    outs = []
+    for budget in (None, "2"):
+        if budget:
+            monkeypatch.setenv("SOX_WS_BUDGET_MB", budget)
+        plan = B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision="fp64")
+        dG = torch.empty((nt, n, n), dtype=torch.float64, device="cuda")
+        dX = torch.empty((n, N), dtype=torch.float64, device="cuda")
+        dV = torch.empty((N, N), dtype=torch.float64, device="cuda")
+        B.sox_sigma_vjp(plan, "bare", dev(wl["X"]), dev(wl["V"]), None, dev(G), dev(R), dG, dX, dV, None)
+        torch.cuda.synchronize()
+        outs.append((host(dG), host(dX), host(dV)))
+    for a, b in zip(outs[0], outs[1]):
+        assert rel_err(b, a) <= 1e-13
+
+
+def test_vjp_bare_rejects_dU2(B):
+    import torch
+    n, N, nt = 4, 16, 4
+    wl, G, R = _inputs(n, N, nt, 5.0, 3)
+    plan = B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision="fp32")
+    dV = torch.empty((N, N), dtype=torch.float64, device="cuda")
+    with pytest.raises(B.SoxError):
+        B.sox_sigma_vjp(plan, "bare", dev(wl["X"]), dev(wl["V"]), None, dev(G), dev(R), None, None, dV, dV)
