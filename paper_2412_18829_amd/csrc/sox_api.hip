@@ -80,6 +80,7 @@ struct sox_plan {
   std::vector<double> t_fwd, t_bwd;  // complex interleaved (host copies)
   int vjp_slab = 1; // tau nodes per slab of the adjoint chain
   int vc = 0;       // dynamic entry: v-slab width
+  int vc_vjp = 0;   // dynamic entry: v-slab width of the adjoint
   int eslab = 0;    // dynamic entry: tau nodes per back-transform slab
   // device copies
   double* d_tf2 = nullptr;  // [2 n_omega][n_tau]  Re / Im of t_fwd
@@ -212,12 +213,17 @@ int pick_slab(const sox_plan& p, int entry) {
   return slab;
 }
 
+size_t dyn_vjp_total(const sox_plan& p, int vc);  // defined with the adjoint layout
+
 void pick_dyn(sox_plan& p) {
   const size_t budget = ws_budget();
   p.eslab = std::min(p.n_tau, 16);
   int vc = p.n;
   while (vc > 1 && dyn_layout_for(p, vc, p.eslab).total > budget) vc = (vc + 1) / 2;
   p.vc = vc;
+  vc = p.n;
+  while (vc > 1 && dyn_vjp_total(p, vc) > budget) vc = (vc + 1) / 2;
+  p.vc_vjp = vc;
 }
 
 int default_fused_cfg(int precision, int N) {
@@ -285,7 +291,9 @@ int pick_vjp_slab(const sox_plan& p, int entry) {
 }
 
 size_t workspace_bytes(const sox_plan& p, int entry) {
-  if (entry == SOX_ENTRY_DYNAMIC) return p.n_omega > 0 ? dyn_layout_for(p, p.vc, p.eslab).total : 0;
+  if (entry == SOX_ENTRY_DYNAMIC)
+    return p.n_omega > 0 ? std::max(dyn_layout_for(p, p.vc, p.eslab).total, dyn_vjp_total(p, p.vc_vjp))
+                         : 0;
   const size_t fwd = layout_for(p, entry, p.slab).total;
   const size_t vjp = vjp_layout_for(p, entry, p.vjp_slab).total;
   return std::max(fwd, vjp);
@@ -462,8 +470,10 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
 
 template <typename T>
 sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const double* V,
-                       const double* G, double* Sigma, void* ws, hipStream_t s) {
-  const DynLayout L = dyn_layout_for(p, p.vc, p.eslab);
+                       const double* G, double* Sigma, void* ws, hipStream_t s, int vcw = 0,
+                       T* W2T = nullptr) {
+  if (vcw <= 0) vcw = p.vc;
+  const DynLayout L = dyn_layout_for(p, vcw, p.eslab);
   char* base = (char*)ws;
   double* P1d = (double*)(base + L.p1d);
   double* P2Td = (double*)(base + L.p2td);
@@ -503,15 +513,16 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
   }
   {
     ProfScope ps(p, SOX_STAGE_GG_FT, s);
-    WOmegaProb<T> wp{p.d_tf2, Wtau, W2, nw, nt, N, NP, 2 * nw, NP * NP, nt};
+    WOmegaProb<T> wp{p.d_tf2, Wtau, W2, nw, nt, N, NP, 2 * nw, NP * NP, nt, W2T};
     SOX_HIP((launch_gemm<WOmegaProb<T>, double, 2, 2, 2, 2>(wp, 1, s)));
   }
   const int tiles_p = NP / (2 * fc.wp), tiles_r = NP / (2 * fc.wr);
-  for (int v0 = 0; v0 < n; v0 += p.vc) {
-    const int vc = std::min(p.vc, n - v0);
+  for (int v0 = 0; v0 < n; v0 += vcw) {
+    const int vc = std::min(vcw, n - v0);
     {
       ProfScope ps(p, SOX_STAGE_GG_FT, s);
-      FTProb<T> ft{p.d_tf2, P1d, P2Td, GG2, n, nP, NP, N, nw, nt, v0, vc, 2 * nw, vc * n * NP, nt};
+      FTProb<T> ft{p.d_tf2, P1d, P2Td, GG2, n, nP, NP, N, nw, nt, v0, vc, 2 * nw, vc * n * NP, nt,
+                   nullptr, 0};
       SOX_HIP((launch_gemm<FTProb<T>, double, 2, 2, 2, 2>(ft, 1, s)));
     }
     {
@@ -566,7 +577,7 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
       if (st) return st;
     }
   }
-  for (int t0 = 0; t0 < nt; t0 += p.eslab) {
+  for (int t0 = 0; Sigma && t0 < nt; t0 += p.eslab) {
     const int cnt = std::min(p.eslab, nt - t0);
     ProfScope ps(p, SOX_STAGE_BACK, s);
     BackEProb<T> pe{X, D + (long)t0 * NP * NP, E, n, N, NP, n, N, N};
@@ -769,6 +780,248 @@ sox_status run_vjp_static(sox_plan& p, int entry, const double* X, const double*
   return SOX_OK;
 }
 
+struct DynVjpLayout {
+  size_t w2t, gg2t, daw, dawt, dw2, dgg2, dgg, dadyn, adynT, p2, xp, u2tT, dd, ddt, e2, e3;
+  size_t dp1d, dp2td, dxt, du2t, mbuf, dgs, dxs, total;
+  int ldk;
+};
+
+DynVjpLayout dyn_vjp_layout_for(const sox_plan& p, int vc) {
+  DynVjpLayout L{};
+  const size_t es = elem_size(p.precision);
+  const size_t nP = p.nP, NP = p.NP, n = p.n, N = p.N, nt = p.n_tau, nw = p.n_omega;
+  L.ldk = (int)round_up((long)vc * n, 16);
+  const size_t ldk = L.ldk;
+  Carver k;
+  k.off = dyn_layout_for(p, vc, p.eslab).total;
+  L.w2t = k.take(nw * 4 * NP * NP * es);
+  L.gg2t = k.take(nw * 2 * NP * ldk * es);
+  L.daw = k.take(nw * 2 * NP * ldk * es);
+  L.dawt = k.take(nw * (size_t)vc * n * 2 * NP * es);
+  L.dw2 = k.take(nw * 4 * NP * NP * 8);
+  L.dgg2 = k.take(nw * (size_t)vc * n * 2 * NP * 8);
+  L.dgg = k.take(nt * (size_t)vc * n * NP * 8);
+  L.dadyn = k.take(nt * (size_t)vc * NP * nP * 8);
+  L.adynT = k.take(nt * (size_t)vc * nP * NP * es);
+  L.p2 = k.take(nt * nP * NP * es);
+  L.xp = k.take(nP * NP * es);
+  L.u2tT = k.take(nP * nP * NP * es);
+  L.dd = k.take(nt * NP * NP * es);
+  L.ddt = k.take(nt * NP * NP * es);
+  L.e2 = k.take(nt * n * NP * 8);
+  L.e3 = k.take(nt * n * NP * 8);
+  L.dp1d = k.take(nt * NP * nP * 8);
+  L.dp2td = k.take(nt * NP * nP * 8);
+  L.dxt = k.take(nt * NP * nP * 8);
+  L.du2t = k.take(nP * NP * nP * 8);
+  L.mbuf = k.take(NP * nP * nP * 8);
+  L.dgs = k.take(nt * n * n * 8);
+  L.dxs = k.take(n * N * 8);
+  L.total = k.off;
+  return L;
+}
+
+size_t dyn_vjp_total(const sox_plan& p, int vc) { return dyn_vjp_layout_for(p, vc).total; }
+
+template <typename T>
+sox_status run_vjp_dynamic(sox_plan& p, const double* X, const double* Wtau, const double* V,
+                           const double* G, const double* R, double* dG, double* dX, double* dW,
+                           double* dV, void* ws, hipStream_t s) {
+  const int vcw = p.vc_vjp;
+  const DynLayout F = dyn_layout_for(p, vcw, p.eslab);
+  const DynVjpLayout L = dyn_vjp_layout_for(p, vcw);
+  char* base = (char*)ws;
+  double* P1d = (double*)(base + F.p1d);
+  double* P2Td = (double*)(base + F.p2td);
+  T* P2T = (T*)(base + F.p2t);
+  T* XT = (T*)(base + F.xt);
+  T* U2 = (T*)(base + F.u2);
+  T* W2 = (T*)(base + F.w2);
+  T* GG2 = (T*)(base + F.gg2);
+  T* AW = (T*)(base + F.aw);
+  T* Adyn = (T*)(base + F.adyn);
+  T* D = (T*)(base + F.d);
+  T* W2T = (T*)(base + L.w2t);
+  T* GG2T = (T*)(base + L.gg2t);
+  T* dAW = (T*)(base + L.daw);
+  T* dAWT = (T*)(base + L.dawt);
+  double* dW2 = (double*)(base + L.dw2);
+  double* dGG2 = (double*)(base + L.dgg2);
+  double* dGG = (double*)(base + L.dgg);
+  double* dAdyn = (double*)(base + L.dadyn);
+  T* AdynT = (T*)(base + L.adynT);
+  T* P2 = (T*)(base + L.p2);
+  T* XP = (T*)(base + L.xp);
+  T* u2tT = (T*)(base + L.u2tT);
+  T* dD = (T*)(base + L.dd);
+  T* dDT = (T*)(base + L.ddt);
+  double* E2 = (double*)(base + L.e2);
+  double* E3 = (double*)(base + L.e3);
+  double* dP1d = (double*)(base + L.dp1d);
+  double* dP2Td = (double*)(base + L.dp2td);
+  double* dXT = (double*)(base + L.dxt);
+  double* du2t = (double*)(base + L.du2t);
+  double* mbuf = (double*)(base + L.mbuf);
+  double* dGs = (double*)(base + L.dgs);
+  double* dXs = (double*)(base + L.dxs);
+  const int n = p.n, N = p.N, nP = p.nP, NP = p.NP, nt = p.n_tau, nw = p.n_omega;
+  const long NPnP = (long)NP * nP;
+  const int ldk = L.ldk;
+  if (NP % 64 != 0) return fail(SOX_ERR_SHAPE, "internal: padded extent does not fit the tiles");
+  sox_status st;
+  if ((st = launch_fill<double>(dGs, (long)nt * n * n, s))) return st;
+  if ((st = launch_fill<double>(dXs, (long)n * N, s))) return st;
+  if ((st = launch_fill<double>(du2t, NPnP * nP, s))) return st;
+  if ((st = launch_fill<double>(dXT, (long)nt * NPnP, s))) return st;
+  if ((st = launch_fill<double>(dW2, (long)nw * 4 * NP * NP, s))) return st;
+  if ((st = launch_fill<double>(dP1d, (long)nt * NPnP, s))) return st;
+  if ((st = launch_fill<double>(dP2Td, (long)nt * NPnP, s))) return st;
+  // forward pass: every intermediate of the plain entry, and D for all tau
+  if ((st = run_dynamic<T>(p, X, Wtau, V, G, nullptr, ws, s, vcw, W2T))) return st;
+  ProfScope ps(p, SOX_STAGE_VJP, s);
+  {
+    const long cx = (long)nP * NP;
+    hipLaunchKernelGGL(xpad_kernel<T>, dim3((unsigned)((cx + 255) / 256)), dim3(256), 0, s, X, XP,
+                       n, N, nP, NP);
+    SOX_HIP(hipGetLastError());
+    UTensorProb<T> pr{V, X, u2tT, n, N, nP, NP, nP * nP, N, 1, NP};
+    SOX_HIP((launch_gemm<UTensorProb<T>, double, 2, 2, 2, 2>(pr, 1, s)));
+    if ((st = launch_transpose<T>(P2T, P2, NP, nP, nt, s))) return st;
+  }
+  // cotangent of D for all tau, and the back-transform's dX terms
+  RXProb rx{R, X, E2, n, N, NP, 0, 0, n, N, n};
+  SOX_HIP((launch_gemm<RXProb, double, 2, 2, 2, 2>(rx, nt, s)));
+  RXProb rx3{R, X, E3, n, N, NP, 0, 1, n, N, n};
+  SOX_HIP((launch_gemm<RXProb, double, 2, 2, 2, 2>(rx3, nt, s)));
+  DDProb<T> ddp{X, E2, dD, dDT, n, N, NP, NP, NP, n};
+  SOX_HIP((launch_gemm<DDProb<T>, double, 2, 2, 2, 2>(ddp, nt, s)));
+  DXBackProb<T> b1{E2, D, dXs, n, N, NP, 0, n, N, nt * NP};
+  SOX_HIP((launch_gemm<DXBackProb<T>, double, 2, 2, 2, 2>(b1, 1, s)));
+  DXBackProb<T> b2{E3, D, dXs, n, N, NP, 1, n, N, nt * NP};
+  SOX_HIP((launch_gemm<DXBackProb<T>, double, 2, 2, 2, 2>(b2, 1, s)));
+
+  for (int v0 = 0; v0 < n; v0 += vcw) {
+    const int vc = std::min(vcw, n - v0);
+    const long vcn = (long)vc * n;
+    // recompute GG(Omega) (both layouts), A(Omega), A(tau) for the slab
+    if ((st = launch_fill<T>(GG2T, (long)nw * 2 * NP * ldk, s))) return st;
+    if ((st = launch_fill<T>(dAW, (long)nw * 2 * NP * ldk, s))) return st;
+    FTProb<T> ft{p.d_tf2, P1d, P2Td, GG2, n, nP, NP, N, nw, nt, v0, vc, 2 * nw, vc * n * NP, nt,
+                 GG2T, ldk};
+    SOX_HIP((launch_gemm<FTProb<T>, double, 2, 2, 2, 2>(ft, 1, s)));
+    {
+      DenseArgs<T, T> d{};
+      d.A = W2; d.B = GG2; d.C = AW;
+      d.lda = 2L * NP; d.ldb = 2L * NP; d.ldc = vcn;
+      d.sA = 4L * NP * NP; d.sB = vcn * 2 * NP; d.sC = 2L * NP * vcn;
+      d.M = 2 * NP; d.N = (int)vcn; d.K = 2 * NP; d.alpha = T(1);
+      if (sizeof(T) == 8) SOX_HIP((launch_dense<T, T, 2, 2, 2, 2>(d, nw, s)));
+      else SOX_HIP((launch_dense<T, T, 2, 2, 4, 4>(d, nw, s)));
+    }
+    IFTProb<T> ift{p.d_tb2, AW, Adyn, n, nP, NP, nw, nt, vc, nt, NP * vc * nP, 2 * nw};
+    SOX_HIP((launch_gemm<IFTProb<T>, double, 2, 2, 2, 2>(ift, 1, s)));
+    if ((st = launch_transpose<T>(Adyn, AdynT, NP, nP, (long)nt * vc, s))) return st;
+    // Hadamard-contract adjoints with B^v = A^v X
+    HcArgs<T, double> h{};
+    h.nz = NP; h.nk = nP; h.ny = nP;
+    // dAdyn[tau][vl][P][u] = sum_R dD[P,R] C[R,v,P] X[u,R]
+    h.L = U2 + (long)v0 * nP; h.l_ld = (long)nP * nP; h.l_ts = 0; h.l_vs = nP;
+    h.Rm = P2T; h.r_ld = nP; h.r_ts = NPnP; h.r_vs = 0;
+    h.W = dDT; h.w_ld = NP; h.w_ts = (long)NP * NP;
+    h.FT = XP; h.f_ld = NP; h.f_ts = 0; h.f_vs = 0;
+    h.Out = dAdyn; h.o_ld = nP; h.o_ts = (long)vc * NPnP; h.o_vs = NPnP;
+    h.n_ot = nt; h.n_ov = vc; h.n_it = 1; h.n_iv = 1; h.accumulate = 0;
+    if ((st = launch_hc_cfg<T>(p, h, NP, s))) return st;
+    // dX^T[tau][R][u] += sum_{P,v} dD[P,R] C[R,v,P] A[tau][v][P][u]
+    h.L = P2T; h.l_ld = nP; h.l_ts = NPnP; h.l_vs = 0;
+    h.Rm = U2 + (long)v0 * nP; h.r_ld = (long)nP * nP; h.r_ts = 0; h.r_vs = nP;
+    h.W = dD;
+    h.FT = AdynT; h.f_ld = NP; h.f_ts = (long)vc * NPnP; h.f_vs = NPnP;
+    h.Out = dXT; h.o_ld = nP; h.o_ts = NPnP; h.o_vs = 0;
+    h.n_ot = nt; h.n_ov = 1; h.n_it = 1; h.n_iv = vc; h.accumulate = 1;
+    if ((st = launch_hc_cfg<T>(p, h, NP, s))) return st;
+    // dU2[v][R][w] += sum_{tau,P} dD[P,R] B[P,R,v] G_wP[w,P]
+    h.L = Adyn; h.l_ld = nP; h.l_ts = (long)vc * NPnP; h.l_vs = NPnP;
+    h.Rm = XT; h.r_ld = nP; h.r_ts = 0; h.r_vs = 0;
+    h.W = dD;
+    h.FT = P2; h.f_ld = NP; h.f_ts = NPnP; h.f_vs = 0;
+    h.Out = du2t + (long)v0 * NPnP; h.o_ld = nP; h.o_ts = 0; h.o_vs = NPnP;
+    h.n_ot = 1; h.n_ov = vc; h.n_it = nt; h.n_iv = 1; h.accumulate = 1;
+    if ((st = launch_hc_cfg<T>(p, h, NP, s))) return st;
+    // dG_wP^T[tau][P][w] += sum_{R,v} dD[P,R] B[P,R,v] U2[R,v,w]
+    h.L = XT; h.l_ld = nP; h.l_ts = 0; h.l_vs = 0;
+    h.Rm = Adyn; h.r_ld = nP; h.r_ts = (long)vc * NPnP; h.r_vs = NPnP;
+    h.W = dDT;
+    h.FT = u2tT + (long)v0 * NPnP; h.f_ld = NP; h.f_ts = 0; h.f_vs = NPnP;
+    h.Out = dP2Td; h.o_ld = nP; h.o_ts = NPnP; h.o_vs = 0;
+    h.n_ot = nt; h.n_ov = 1; h.n_it = 1; h.n_iv = vc; h.accumulate = 1;
+    if ((st = launch_hc_cfg<T>(p, h, NP, s))) return st;
+    // IFT adjoint, then the adjoints of A(Omega) = W2 GG2
+    IFTAdjProb<T> ia{p.d_tb2, dAdyn, dAW, dAWT, n, nP, NP, nw, nt, vc, ldk, 2 * nw,
+                     NP * vc * n, nt};
+    SOX_HIP((launch_gemm<IFTAdjProb<T>, double, 2, 2, 2, 2>(ia, 1, s)));
+    {
+      DenseArgs<T, double> d{};
+      d.A = dAW; d.B = GG2T; d.C = dW2;
+      d.lda = ldk; d.ldb = ldk; d.ldc = 2L * NP;
+      d.sA = 2L * NP * ldk; d.sB = 2L * NP * ldk; d.sC = 4L * NP * NP;
+      d.M = 2 * NP; d.N = 2 * NP; d.K = ldk; d.alpha = T(1); d.accumulate = 1;
+      if (sizeof(T) == 8) SOX_HIP((launch_dense<T, double, 2, 2, 2, 2>(d, nw, s)));
+      else SOX_HIP((launch_dense<T, double, 2, 2, 4, 4>(d, nw, s)));
+    }
+    {
+      DenseArgs<T, double> d{};
+      d.A = dAWT; d.B = W2T; d.C = dGG2;
+      d.lda = 2L * NP; d.ldb = 2L * NP; d.ldc = 2L * NP;
+      d.sA = vcn * 2 * NP; d.sB = 4L * NP * NP; d.sC = vcn * 2 * NP;
+      d.M = (int)vcn; d.N = 2 * NP; d.K = 2 * NP; d.alpha = T(1); d.accumulate = 0;
+      if (sizeof(T) == 8) SOX_HIP((launch_dense<T, double, 2, 2, 2, 2>(d, nw, s)));
+      else SOX_HIP((launch_dense<T, double, 2, 2, 4, 4>(d, nw, s)));
+    }
+    FTAdjProb fa{p.d_tf2, dGG2, dGG, n, NP, nw, nt, vc, nt, vc * n * NP, 2 * nw};
+    SOX_HIP((launch_gemm<FTAdjProb, double, 2, 2, 2, 2>(fa, 1, s)));
+    {
+      const long c2 = (long)nt * N * n, c1 = (long)nt * N * vc;
+      hipLaunchKernelGGL(gg_adjoint_p2_kernel, dim3((unsigned)((c2 + 255) / 256)), dim3(256), 0, s,
+                         dGG, P1d, dP2Td, n, nP, NP, N, nt, v0, vc);
+      SOX_HIP(hipGetLastError());
+      hipLaunchKernelGGL(gg_adjoint_p1_kernel, dim3((unsigned)((c1 + 255) / 256)), dim3(256), 0, s,
+                         dGG, P2Td, dP1d, n, nP, NP, N, nt, v0, vc);
+      SOX_HIP(hipGetLastError());
+    }
+  }
+  if (dW) {
+    DWtauProb dwp{p.d_tf2, dW2, dW, N, NP, nw, nt, nt, N * N, 2 * nw};
+    SOX_HIP((launch_gemm<DWtauProb, double, 2, 2, 2, 2>(dwp, 1, s)));
+  }
+  if (dV) {
+    DUProb a2{du2t, X, dV, n, N, nP, NP, 1, 0, N, N, nP * nP};
+    SOX_HIP((launch_gemm<DUProb, double, 2, 2, 2, 2>(a2, 1, s)));
+  }
+  const long nx = (long)n * N;
+  DUMProb m2{V, du2t, mbuf, n, N, nP, NP, 1, N, nP * nP, N};
+  SOX_HIP((launch_gemm<DUMProb, double, 2, 2, 2, 2>(m2, 1, s)));
+  hipLaunchKernelGGL(ut_adjoint_x_kernel, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, mbuf,
+                     X, dXs, n, N, nP);
+  SOX_HIP(hipGetLastError());
+  for (int t = 0; t < nt; ++t) {
+    hipLaunchKernelGGL(add_transposed_kernel, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s,
+                       dXT + (long)t * NPnP, dXs, n, N, nP);
+    SOX_HIP(hipGetLastError());
+  }
+  DGProjProb g1{X, dP1d, dGs, n, N, nP, NP, 0, 0, n, n, N};
+  SOX_HIP((launch_gemm<DGProjProb, double, 2, 2, 2, 2>(g1, nt, s)));
+  DGProjProb g2{X, dP2Td, dGs, n, N, nP, NP, 0, 1, n, n, N};
+  SOX_HIP((launch_gemm<DGProjProb, double, 2, 2, 2, 2>(g2, nt, s)));
+  DXProjProb x1{G, dP1d, dXs, n, N, nP, NP, 0, 0, n, N, nt * nP};
+  SOX_HIP((launch_gemm<DXProjProb, double, 2, 2, 2, 2>(x1, 1, s)));
+  DXProjProb x2{G, dP2Td, dXs, n, N, nP, NP, 0, 1, n, N, nt * nP};
+  SOX_HIP((launch_gemm<DXProjProb, double, 2, 2, 2, 2>(x2, 1, s)));
+  if (dG) SOX_HIP(hipMemcpyAsync(dG, dGs, sizeof(double) * nt * n * n, hipMemcpyDeviceToDevice, s));
+  if (dX) SOX_HIP(hipMemcpyAsync(dX, dXs, sizeof(double) * nx, hipMemcpyDeviceToDevice, s));
+  return SOX_OK;
+}
+
 sox_status dispatch_static(sox_plan* plan, int entry, const double* X, const double* U1,
                            const double* U2, const double* G, double* Sigma, void* ws,
                            size_t ws_bytes, void* stream) {
@@ -964,10 +1217,18 @@ sox_status sox_sigma_vjp(sox_plan* plan, int32_t entry, const double* X, const d
   if (entry != SOX_ENTRY_BARE && !U2) return fail(SOX_ERR_INVALID_ARG, "U2 is NULL");
   if (entry == SOX_ENTRY_BARE && dU2)
     return fail(SOX_ERR_INVALID_ARG, "bare entry: dU2 must be NULL (dU1 receives dL/dV)");
-  if (entry == SOX_ENTRY_DYNAMIC) return fail(SOX_ERR_UNSUPPORTED, "dynamic vjp not implemented yet");
+  if (entry == SOX_ENTRY_DYNAMIC && plan->n_omega <= 0)
+    return fail(SOX_ERR_INVALID_ARG, "plan has no transform pair (n_omega = 0)");
   st = check_ws(plan, entry, ws, ws_bytes);
   if (st) return st;
   hipStream_t s = (hipStream_t)stream;
+  if (entry == SOX_ENTRY_DYNAMIC) {
+    switch (plan->precision) {
+      case SOX_FP64: return run_vjp_dynamic<double>(*plan, X, U1, U2, G, R, dG, dX, dU1, dU2, ws, s);
+      case SOX_FP32: return run_vjp_dynamic<float>(*plan, X, U1, U2, G, R, dG, dX, dU1, dU2, ws, s);
+      default: return fail(SOX_ERR_UNSUPPORTED, "precision %d not implemented", plan->precision);
+    }
+  }
   switch (plan->precision) {
     case SOX_FP64:
       return run_vjp_static<double>(*plan, entry, X, U1, U2, G, R, dG, dX, dU1, dU2, ws, s);

@@ -155,6 +155,7 @@ template <typename T> struct WOmegaProb {
   T* W2;               // [n_omega][2NP][2NP]
   int n_omega, n_tau, Nthc, NP;
   int M, N, K;         // M = 2 n_omega, N = NP*NP, K = n_tau
+  T* W2T;              // optional transposed copy (adjoint), may be null
   __device__ f64x4 loadA4(int, int row, int j) const {
     if (row >= M) return zero4<double>();
     return load4_strided<double>(Tf2 + (long)row * n_tau, 1, j, n_tau);
@@ -177,6 +178,16 @@ template <typename T> struct WOmegaProb {
       W[(long)(NP + P) * ld + Q] = T(v);
       W[(long)P * ld + NP + Q] = T(-v);
     }
+    if (W2T) {
+      T* Wt = W2T + (long)m * ld * ld;
+      if (c == 0) {
+        Wt[(long)Q * ld + P] = T(v);
+        Wt[(long)(NP + Q) * ld + NP + P] = T(v);
+      } else {
+        Wt[(long)Q * ld + NP + P] = T(v);
+        Wt[(long)(NP + Q) * ld + P] = T(-v);
+      }
+    }
   }
 };
 
@@ -191,6 +202,8 @@ template <typename T> struct FTProb {
   T* GG2;              // [n_omega][vc*n][2NP]
   int n, nP, NP, Nthc, n_omega, n_tau, v0, vc;
   int M, N, K;         // M = 2 n_omega, N = vc*n*NP, K = n_tau
+  T* GG2T;             // optional [n_omega][2NP][ldt] copy (adjoint), may be null
+  int ldt;
   __device__ f64x4 loadA4(int, int row, int j) const {
     if (row >= M) return zero4<double>();
     return load4_strided<double>(Tf2 + (long)row * n_tau, 1, j, n_tau);
@@ -217,6 +230,7 @@ template <typename T> struct FTProb {
     const int c = row / n_omega, m = row - (row / n_omega) * n_omega;
     const int Q = col % NP, vu = col / NP;
     GG2[((long)m * vc * n + vu) * (2L * NP) + (long)c * NP + Q] = T(v);
+    if (GG2T) GG2T[((long)m * 2 * NP + (long)c * NP + Q) * ldt + vu] = T(v);
   }
 };
 

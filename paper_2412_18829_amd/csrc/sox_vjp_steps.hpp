@@ -258,3 +258,151 @@ struct DUMProb {
 };
 
 }  // namespace sox
+
+namespace sox {
+
+// ---------------------------------------------------------------------------
+// Dynamic-path adjoints (transforms in float64).
+//
+// IFT adjoint for the v-slab:  dAW[m][c NP + P][vl n + u] = sum_tau Tb2[tau][k] dAdyn[tau][vl][P][u]
+// (k = c n_omega + m), stored twice: dAW (rows (c,P), ld ldk) and dAWT
+// (rows (vl,u), ld 2NP).
+template <typename T> struct IFTAdjProb {
+  const double* Tb2;    // [n_tau][2 n_omega]
+  const double* dAdyn;  // [n_tau][vc][NP][nP]
+  T* dAW;               // [n_omega][2NP][ldk]
+  T* dAWT;              // [n_omega][vc*n][2NP]
+  int n, nP, NP, n_omega, n_tau, vc, ldk;
+  int M, N, K;          // M = 2 n_omega, N = NP*vc*n, K = n_tau
+  __device__ f64x4 loadA4(int, int row, int t) const {
+    if (row >= M) return zero4<double>();
+    return load4_strided<double>(Tb2 + row, 2L * n_omega, t, n_tau);
+  }
+  __device__ f64x4 loadB4(int, int col, int t) const {
+    if (col >= N) return zero4<double>();
+    const int u = col % n, pv = col / n;
+    const int vl = pv % vc, P = pv / vc;
+    return load4_strided<double>(dAdyn + ((long)vl * NP + P) * nP + u, (long)vc * NP * nP, t, n_tau);
+  }
+  __device__ void store(int, int row, int col, double v) const {
+    const int c = row / n_omega, m = row - (row / n_omega) * n_omega;
+    const int u = col % n, pv = col / n;
+    const int vl = pv % vc, P = pv / vc;
+    const long vu = (long)vl * n + u;
+    dAW[((long)m * 2 * NP + (long)c * NP + P) * ldk + vu] = T(v);
+    dAWT[((long)m * vc * n + vu) * (2L * NP) + (long)c * NP + P] = T(v);
+  }
+};
+
+// FT adjoint:  dGG[tau][(vl,u)][Q] = sum_k Tf2[k][tau] dGG2[m][(vl,u)][c NP + Q]
+struct FTAdjProb {
+  const double* Tf2;    // [2 n_omega][n_tau]
+  const double* dGG2;   // [n_omega][vc*n][2NP]
+  double* dGG;          // [n_tau][vc*n][NP]
+  int n, NP, n_omega, n_tau, vc;
+  int M, N, K;          // M = n_tau, N = vc*n*NP, K = 2 n_omega
+  __device__ f64x4 loadA4(int, int t, int k) const {
+    if (t >= M) return zero4<double>();
+    return load4_strided<double>(Tf2 + t, n_tau, k, 2 * n_omega);
+  }
+  __device__ f64x4 loadB4(int, int col, int k) const {
+    if (col >= N) return zero4<double>();
+    const int Q = col % NP, vu = col / NP;
+    f64x4 r;
+#pragma unroll
+    for (int mm = 0; mm < 4; ++mm) {
+      const int kk = k + mm;
+      if (kk < 2 * n_omega) {
+        const int c = kk / n_omega, m = kk - (kk / n_omega) * n_omega;
+        r[mm] = dGG2[((long)m * vc * n + vu) * (2L * NP) + (long)c * NP + Q];
+      } else {
+        r[mm] = 0.0;
+      }
+    }
+    return r;
+  }
+  __device__ void store(int, int t, int col, double v) const { dGG[(long)t * N + col] = v; }
+};
+
+// dW_tau[j][P][Q] = sum_k Tf2[k][j] dWc[m](P,Q) with dWr = dW2[00] + dW2[11],
+// dWi = dW2[10] - dW2[01] (blocks of the real 2NP x 2NP form)
+struct DWtauProb {
+  const double* Tf2;   // [2 n_omega][n_tau]
+  const double* dW2;   // [n_omega][2NP][2NP]
+  double* dW;          // [n_tau][N][N]
+  int Nthc, NP, n_omega, n_tau;
+  int M, N, K;         // M = n_tau, N = Nthc*Nthc, K = 2 n_omega
+  __device__ f64x4 loadA4(int, int j, int k) const {
+    if (j >= M) return zero4<double>();
+    return load4_strided<double>(Tf2 + j, n_tau, k, 2 * n_omega);
+  }
+  __device__ f64x4 loadB4(int, int col, int k) const {
+    if (col >= N) return zero4<double>();
+    const int P = col / Nthc, Q = col - (col / Nthc) * Nthc;
+    const long ld = 2L * NP;
+    f64x4 r;
+#pragma unroll
+    for (int mm = 0; mm < 4; ++mm) {
+      const int kk = k + mm;
+      double v = 0.0;
+      if (kk < 2 * n_omega) {
+        const int c = kk / n_omega, m = kk - (kk / n_omega) * n_omega;
+        const double* W = dW2 + (long)m * ld * ld;
+        v = c == 0 ? W[(long)P * ld + Q] + W[(long)(NP + P) * ld + NP + Q]
+                   : W[(long)(NP + P) * ld + Q] - W[(long)P * ld + NP + Q];
+      }
+      r[mm] = v;
+    }
+    return r;
+  }
+  __device__ void store(int, int j, int col, double v) const { dW[(long)j * N + col] = v; }
+};
+
+// eq:GG product rule for the v-slab:
+//   dP2T[tau][Q][u]           += sum_vl dGG[tau][(vl,u)][Q] P1[n_tau-1-tau][Q][v0+vl]
+//   dP1[n_tau-1-tau][Q][v0+vl] += sum_u  dGG[tau][(vl,u)][Q] P2T[tau][Q][u]
+__global__ void gg_adjoint_p2_kernel(const double* dGG, const double* P1, double* dP2T, int n,
+                                     int nP, int NP, int Nthc, int n_tau, int v0, int vc) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)n_tau * Nthc * n) return;
+  const int t = (int)(idx / ((long)Nthc * n));
+  const int rem = (int)(idx - (long)t * Nthc * n);
+  const int Q = rem / n, u = rem - (rem / n) * n;
+  const double* p1 = P1 + ((long)(n_tau - 1 - t) * NP + Q) * nP + v0;
+  const double* g = dGG + (long)t * vc * n * NP + (long)u * NP + Q;
+  double acc = 0.0;
+  for (int vl = 0; vl < vc; ++vl) acc += g[(long)vl * n * NP] * p1[vl];
+  dP2T[((long)t * NP + Q) * nP + u] += acc;
+}
+
+__global__ void gg_adjoint_p1_kernel(const double* dGG, const double* P2T, double* dP1, int n,
+                                     int nP, int NP, int Nthc, int n_tau, int v0, int vc) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)n_tau * Nthc * vc) return;
+  const int t = (int)(idx / ((long)Nthc * vc));
+  const int rem = (int)(idx - (long)t * Nthc * vc);
+  const int Q = rem / vc, vl = rem - (rem / vc) * vc;
+  const double* p2 = P2T + ((long)t * NP + Q) * nP;
+  const double* g = dGG + ((long)t * vc * n + (long)vl * n) * NP + Q;
+  double acc = 0.0;
+  for (int u = 0; u < n; ++u) acc += g[(long)u * NP] * p2[u];
+  dP1[((long)(n_tau - 1 - t) * NP + Q) * nP + v0 + vl] += acc;
+}
+
+// XP[u][R] = X[u][R] zero padded to nP x NP;  dX[u][R] += dXT[R][u]
+template <typename T>
+__global__ void xpad_kernel(const double* X, T* out, int n, int Nthc, int nP, int NP) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)nP * NP) return;
+  const int u = (int)(idx / NP), R = (int)(idx - (idx / NP) * NP);
+  out[idx] = (u < n && R < Nthc) ? T(X[(long)u * Nthc + R]) : T(0);
+}
+
+__global__ void add_transposed_kernel(const double* dXT, double* dX, int n, int Nthc, int nP) {
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)n * Nthc) return;
+  const int u = (int)(idx / Nthc), R = (int)(idx - (idx / Nthc) * Nthc);
+  dX[idx] += dXT[(long)R * nP + u];
+}
+
+}  // namespace sox

@@ -46,6 +46,11 @@ CASES = [
     (3, 7, 1, 1, 1, 1, None),
     (16, 256, 2, 1, 1, 1, None),
     (10, 64, 7, 0, 0, 1, "2"),
+    (5, 12, 6, 1, 2, 1, None),
+    (5, 12, 6, 0, 2, 1, None),
+    (13, 70, 5, 1, 2, 1, None),
+    (16, 256, 3, 1, 2, 1, None),
+    (21, 90, 6, 1, 2, 1, "4"),
 ]
 
 

@@ -88,3 +88,55 @@ def test_vjp_bare_rejects_dU2(B):
     dV = torch.empty((N, N), dtype=torch.float64, device="cuda")
     with pytest.raises(B.SoxError):
         B.sox_sigma_vjp(plan, "bare", dev(wl["X"]), dev(wl["V"]), None, dev(G), dev(R), None, None, dV, dV)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [(5, 12, 24, 20.0), (12, 64, 32, 40.0), (20, 140, 40, 100.0)])
+def test_dynamic_vjp_vs_reference(B, precision, shape):
+    import torch
+    from paper_2412_18829_amd import autograd as AG
+    n, N, nt, beta = shape
+    log(f"dynamic vjp {shape} {precision}")
+    wl = synth.small_molecule(n, N, nt, beta, seed=700 + n, dynamic=True)
+    tp = synth.bosonic_transform_pair(wl["tau"], beta, omega_max=14.0, tol=1e-10)
+    rng = np.random.default_rng(n)
+    G = om.g_tau(wl["eps"], wl["Q"], 0.0, beta, wl["tau"]) + 0.05 * rng.standard_normal((nt, n, n))
+    R = rng.standard_normal((nt, n, n))
+    plan = B.Plan(n, N, wl["tau"], wl["weights"], beta, precision=precision,
+                  t_fwd=tp["T_fwd"], t_bwd=tp["T_bwd"])
+    Xd, Wd, Vd, Gd = (dev(a).requires_grad_() for a in (wl["X"], wl["W_tau"], wl["V"], G))
+    S = AG.sox_sigma_dynamic(plan, Xd, Wd, Vd, Gd)
+    S.backward(dev(R))
+    torch.cuda.synchronize()
+    dG, dX, dW, dV = ov.vjp_dynamic(wl["X"], wl["W_tau"], wl["V"], G, R, tp["T_fwd"], tp["T_bwd"])
+    errs = {"dG": rel_err(host(Gd.grad), dG), "dX": rel_err(host(Xd.grad), dX),
+            "dW": rel_err(host(Wd.grad), dW), "dV": rel_err(host(Vd.grad), dV)}
+    log("  " + " ".join(f"{k} {v:.2e}" for k, v in errs.items()) + f"  n_omega={len(tp['m'])}")
+    tol = {"fp64": 1e-9, "fp32": 1e-5}[precision]
+    for k, v in errs.items():
+        assert v <= tol, k
+
+
+def test_dynamic_vjp_v_slabs_match(B, monkeypatch):
+    import torch
+    n, N, nt, beta = 21, 90, 20, 40.0
+    wl = synth.small_molecule(n, N, nt, beta, seed=78, dynamic=True)
+    tp = synth.bosonic_transform_pair(wl["tau"], beta, omega_max=14.0, tol=1e-10)
+    G = om.g_tau(wl["eps"], wl["Q"], 0.0, beta, wl["tau"])
+    R = np.random.default_rng(2).standard_normal((nt, n, n))
+    outs = []
+    for budget in (None, "20"):
+        if budget:
+            monkeypatch.setenv("SOX_WS_BUDGET_MB", budget)
+        plan = B.Plan(n, N, wl["tau"], wl["weights"], beta, precision="fp64",
+                      t_fwd=tp["T_fwd"], t_bwd=tp["T_bwd"])
+        dG = torch.empty((nt, n, n), dtype=torch.float64, device="cuda")
+        dX = torch.empty((n, N), dtype=torch.float64, device="cuda")
+        dW = torch.empty((nt, N, N), dtype=torch.float64, device="cuda")
+        dV = torch.empty((N, N), dtype=torch.float64, device="cuda")
+        B.sox_sigma_vjp(plan, "dynamic", dev(wl["X"]), dev(wl["W_tau"]), dev(wl["V"]), dev(G), dev(R),
+                        dG, dX, dW, dV)
+        torch.cuda.synchronize()
+        outs.append((host(dG), host(dX), host(dW), host(dV)))
+    for a, b in zip(outs[0], outs[1]):
+        assert rel_err(b, a) <= 1e-12
