@@ -54,7 +54,7 @@ typedef enum {
   SOX_ERR_WORKSPACE = 4,   /* workspace missing, misaligned or too small      */
   SOX_ERR_OOM = 5,         /* device allocation at plan creation failed       */
   SOX_ERR_HIP = 6,         /* a HIP runtime call or kernel launch failed      */
-  SOX_ERR_UNSUPPORTED = 7  /* valid request this build does not implement     */
+  SOX_ERR_UNSUPPORTED = 7  /* valid request this library version lacks        */
 } sox_status;
 
 /* Arithmetic of the contraction kernels (the A step and the fused B.C -> D

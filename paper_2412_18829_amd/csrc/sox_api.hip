@@ -1062,7 +1062,7 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
   if (pr->kmesh[0] != 1 || pr->kmesh[1] != 1 || pr->kmesh[2] != 1) {
     if (pr->kmesh[0] < 1 || pr->kmesh[1] < 1 || pr->kmesh[2] < 1)
       return fail(SOX_ERR_SHAPE, "kmesh entries must be >= 1");
-    return fail(SOX_ERR_UNSUPPORTED, "k-point meshes are not implemented in this build");
+    return fail(SOX_ERR_UNSUPPORTED, "k-point meshes are not implemented in this library version");
   }
   if (!(pr->beta > 0.0) || !std::isfinite(pr->beta))
     return fail(SOX_ERR_INVALID_ARG, "beta must be positive and finite");

@@ -72,7 +72,7 @@ def test_plan_create_rejects_bad_problems_before_device_work():
     pr, keep = _problem(tau=np.array([1.0, 0.5, 4.0, 4.5]), beta=5.5)
     assert _create(pr)[0] == 3                      # GRID: not ascending
     pr, keep = _problem(kmesh=(3, 3, 3))
-    assert _create(pr)[0] == 7                      # UNSUPPORTED in this build
+    assert _create(pr)[0] == 7                      # UNSUPPORTED by this library version
     pr, keep = _problem()
     assert _create(pr, precision=9)[0] == 1         # unknown precision
     h = ctypes.c_void_p()
