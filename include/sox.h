@@ -100,7 +100,11 @@ typedef struct {
 /* Create a plan: validates the problem, copies the grid, uploads the
  * quadrature weights and transform pair to the current HIP device and picks
  * the tile shapes and the tau-slab width.  The environment variable
- * SOX_WS_BUDGET_MB (default 8192) caps the workspace the plan asks for.
+ * SOX_WS_BUDGET_MB (default 32768) caps the workspace the plan asks for.
+ * With SOX_AUTOTUNE=1 the plan times every wave-tile shape of the fused
+ * B, C -> D kernel on the device (zero-filled operands of the plan's shape,
+ * up to 8 tau nodes) and keeps the fastest; SOX_TUNE_CACHE=<file> stores and
+ * reuses those choices per (precision, n, N) across processes.
  * precision is a sox_precision value.  On success *out owns device memory
  * until sox_plan_destroy. */
 sox_status sox_plan_create(const sox_problem* problem, int32_t precision, sox_plan** out);
@@ -194,6 +198,21 @@ sox_status sox_profile_enable(sox_plan* plan, int32_t on);
  * clears the accounting afterwards. */
 sox_status sox_profile_read(sox_plan* plan, double* ms, int64_t* launches, int64_t* dropped,
                             int32_t reset);
+
+/* Replay whole sweeps as HIP graphs.  When enabled, the first
+ * sox_sigma_bare / sox_sigma_static / sox_sigma_dynamic call with a given set
+ * of pointers (inputs, output, workspace) captures its launch sequence on a
+ * plan-owned stream into a graph; later calls with the same pointers launch
+ * that graph on `stream` (one launch per sweep).  The graph reads the
+ * buffers' current contents, so only the pointers, not the values, must
+ * match.  Up to 16 graphs are kept per plan (the oldest is dropped).  Kernel
+ * timing (sox_profile_*) records nothing for replayed sweeps. */
+sox_status sox_plan_set_graph(sox_plan* plan, int32_t enable);
+
+/* A one-line JSON description of the plan's decisions: padded extents, the
+ * fused kernel's wave tile, tau-slab and v-slab widths, and the autotuner's
+ * timings when it ran.  Writes at most `len` bytes including the NUL. */
+sox_status sox_plan_describe(const sox_plan* plan, char* buf, size_t len);
 
 /* Synchronise `stream` and report any pending device error. */
 sox_status sox_sync(void* stream);

@@ -29,7 +29,7 @@ EXPORTED = (
     "sox_plan_create", "sox_plan_destroy", "sox_workspace_size", "sox_sigma_bare",
     "sox_sigma_static", "sox_sigma_dynamic", "sox_sigma_vjp", "sox_build_g_tau",
     "sox_energy_gm", "sox_sync", "sox_last_error", "sox_abi_version", "sox_profile_enable",
-    "sox_profile_read",
+    "sox_profile_read", "sox_plan_set_graph", "sox_plan_describe",
 )
 STAGES = ("gbuild", "utensor", "project", "astep", "fused", "back", "energy", "gg_ft", "wgemm",
           "ift", "split", "vjp")
@@ -78,6 +78,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.sox_last_error.restype = ctypes.c_char_p
     L.sox_abi_version.argtypes = []
     L.sox_profile_enable.argtypes = [vp, i32]
+    L.sox_plan_set_graph.argtypes = [vp, i32]
+    L.sox_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
     L.sox_profile_read.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int64),
                                    ctypes.POINTER(ctypes.c_int64), i32]
     for name in EXPORTED:
@@ -280,3 +282,14 @@ def sox_profile_read(plan: Plan, reset: bool = True) -> dict:
     out = {STAGES[i]: (float(ms[i]), int(cnt[i])) for i in range(n)}
     out["dropped"] = int(dropped.value)
     return out
+
+
+def sox_plan_set_graph(plan: Plan, enable: bool = True):
+    _check(load().sox_plan_set_graph(plan.handle, 1 if enable else 0), "sox_plan_set_graph")
+
+
+def sox_plan_describe(plan: Plan) -> dict:
+    import json
+    buf = ctypes.create_string_buffer(4096)
+    _check(load().sox_plan_describe(plan.handle, buf, len(buf)), "sox_plan_describe")
+    return json.loads(buf.value.decode())

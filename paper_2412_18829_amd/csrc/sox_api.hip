@@ -94,6 +94,18 @@ struct sox_plan {
     hipEvent_t a, b;
     int stage;
   };
+  // whole-sweep HIP graphs keyed by the call's pointers
+  struct GraphEntry {
+    uintptr_t key[9];
+    hipGraph_t graph;
+    hipGraphExec_t exec;
+  };
+  bool graph_on = false;
+  hipStream_t cap_stream = nullptr;
+  std::vector<GraphEntry> graphs;
+  // fused-tile autotuner results: (config, ms per tau)
+  std::vector<std::pair<int, double>> tune_ms;
+  bool tune_from_cache = false;
   bool prof_on = false;
   std::vector<Ev> ev_pool;
   size_t ev_used = 0;
@@ -1022,6 +1034,156 @@ sox_status run_vjp_dynamic(sox_plan& p, const double* X, const double* Wtau, con
   return SOX_OK;
 }
 
+// Run `body` on `s`, or capture it once into a graph keyed by `key` and
+// replay the graph on later calls with the same key.
+template <typename F>
+sox_status run_maybe_graph(sox_plan& p, const uintptr_t (&key)[9], hipStream_t s, F&& body) {
+  if (!p.graph_on) return body(s);
+  for (auto& g : p.graphs) {
+    if (std::equal(key, key + 9, g.key)) {
+      SOX_HIP(hipGraphLaunch(g.exec, s));
+      return SOX_OK;
+    }
+  }
+  if (!p.cap_stream) SOX_HIP(hipStreamCreateWithFlags(&p.cap_stream, hipStreamNonBlocking));
+  const bool prof = p.prof_on;
+  p.prof_on = false;
+  SOX_HIP(hipStreamBeginCapture(p.cap_stream, hipStreamCaptureModeThreadLocal));
+  sox_status st = body(p.cap_stream);
+  hipGraph_t graph = nullptr;
+  hipError_t e = hipStreamEndCapture(p.cap_stream, &graph);
+  p.prof_on = prof;
+  if (st != SOX_OK) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return st;
+  }
+  if (e != hipSuccess) return fail(SOX_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(graph);
+    return fail(SOX_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+  }
+  if (p.graphs.size() >= 16) {
+    (void)hipGraphExecDestroy(p.graphs.front().exec);
+    (void)hipGraphDestroy(p.graphs.front().graph);
+    p.graphs.erase(p.graphs.begin());
+  }
+  sox_plan::GraphEntry ge{};
+  std::copy(key, key + 9, ge.key);
+  ge.graph = graph;
+  ge.exec = exec;
+  p.graphs.push_back(ge);
+  SOX_HIP(hipGraphLaunch(exec, s));
+  return SOX_OK;
+}
+
+void drop_graphs(sox_plan& p) {
+  for (auto& g : p.graphs) {
+    (void)hipGraphExecDestroy(g.exec);
+    (void)hipGraphDestroy(g.graph);
+  }
+  p.graphs.clear();
+}
+
+// Autotuner of the fused kernel's wave tile: time every admissible shape on
+// zero-filled operands of the plan's shape (up to 8 tau nodes).
+template <typename T>
+sox_status time_fused_cfg(sox_plan& p, int cfg, int tt, double* ms_per_tau) {
+  set_fused_cfg(p, cfg);
+  const FusedCfg& fc = kFusedCfgs[cfg];
+  const long nP = p.nP, NP = p.NP, n = p.n;
+  const size_t es = sizeof(T);
+  const size_t szA = tt * n * NP * nP, szY = tt * NP * nP, szU = NP * nP * nP, szD = tt * NP * NP;
+  T* buf = nullptr;
+  const size_t total = szA + 2 * szY + szU + szD;
+  hipError_t e = hipMalloc(&buf, total * es);
+  if (e != hipSuccess) return fail(SOX_ERR_OOM, "autotune buffers: %s", hipGetErrorString(e));
+  hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, nullptr,
+                     buf, (long)total, T(0));
+  FusedArgs<T> fa;
+  fa.A = buf; fa.Y = buf + szA; fa.P2T = buf + szA + szY; fa.U2 = buf + szA + 2 * szY;
+  fa.D = buf + szA + 2 * szY + szU;
+  fa.a_tstride = n * NP * nP; fa.a_vstride = NP * nP; fa.y_tstride = NP * nP; fa.p_tstride = NP * nP;
+  fa.u_rstride = nP * nP; fa.u_vstride = nP; fa.d_tstride = NP * NP;
+  fa.accumulate = 0; fa.n = (int)n; fa.nP = (int)nP; fa.NP = (int)NP;
+  fa.tiles_p = (int)(NP / (2 * fc.wp)); fa.tiles_r = (int)(NP / (2 * fc.wr)); fa.n_tau = tt;
+  hipEvent_t a = nullptr, b = nullptr;
+  sox_status st = SOX_OK;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) st = SOX_ERR_HIP;
+  if (!st) st = launch_fused_cfg<T>(p, fa, nullptr);
+  if (!st && hipEventRecord(a, nullptr) != hipSuccess) st = SOX_ERR_HIP;
+  for (int r = 0; r < 3 && !st; ++r) st = launch_fused_cfg<T>(p, fa, nullptr);
+  float ms = 0.f;
+  if (!st && hipEventRecord(b, nullptr) != hipSuccess) st = SOX_ERR_HIP;
+  if (!st && hipEventSynchronize(b) != hipSuccess) st = SOX_ERR_HIP;
+  if (!st && hipEventElapsedTime(&ms, a, b) != hipSuccess) st = SOX_ERR_HIP;
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  (void)hipFree(buf);
+  if (st) return st == SOX_ERR_HIP ? fail(SOX_ERR_HIP, "autotune launch failed") : st;
+  *ms_per_tau = ms / (3.0 * tt);
+  return SOX_OK;
+}
+
+std::string tune_key(const sox_plan& p) {
+  char k[96];
+  snprintf(k, sizeof(k), "fused %d %d %d", p.precision, p.n, p.N);
+  return k;
+}
+
+sox_status autotune_fused(sox_plan& p) {
+  const char* cache = getenv("SOX_TUNE_CACHE");
+  const std::string key = tune_key(p);
+  if (cache) {
+    if (FILE* f = fopen(cache, "r")) {
+      char line[160];
+      int found = -1;
+      while (fgets(line, sizeof(line), f)) {
+        int cfg;
+        char k[96];
+        int prec, n, N;
+        if (sscanf(line, "%95s %d %d %d %d", k, &prec, &n, &N, &cfg) == 5) {
+          char full[96];
+          snprintf(full, sizeof(full), "%s %d %d %d", k, prec, n, N);
+          if (key == full && cfg >= 0 && cfg < kNumFusedCfgs) found = cfg;
+        }
+      }
+      fclose(f);
+      if (found >= 0) {
+        set_fused_cfg(p, found);
+        p.tune_from_cache = true;
+        return SOX_OK;
+      }
+    }
+  }
+  const int tt = std::min(p.n_tau, 8);
+  int best = p.fused_cfg;
+  double best_ms = 1e300;
+  p.tune_ms.clear();
+  for (int c = 0; c < kNumFusedCfgs; ++c) {
+    const bool ok = p.precision == SOX_FP64 ? kFusedCfgs[c].fp64 : kFusedCfgs[c].fp32;
+    if (!ok) continue;
+    double ms = 0;
+    sox_status st = p.precision == SOX_FP64 ? time_fused_cfg<double>(p, c, tt, &ms)
+                                            : time_fused_cfg<float>(p, c, tt, &ms);
+    if (st) return st;
+    p.tune_ms.push_back({c, ms});
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  set_fused_cfg(p, best);
+  if (cache) {
+    if (FILE* f = fopen(cache, "a")) {
+      fprintf(f, "%s %d\n", key.c_str(), best);
+      fclose(f);
+    }
+  }
+  return SOX_OK;
+}
+
 sox_status dispatch_static(sox_plan* plan, int entry, const double* X, const double* U1,
                            const double* U2, const double* G, double* Sigma, void* ws,
                            size_t ws_bytes, void* stream) {
@@ -1031,12 +1193,15 @@ sox_status dispatch_static(sox_plan* plan, int entry, const double* X, const dou
     return fail(SOX_ERR_INVALID_ARG, "NULL tensor pointer");
   st = check_ws(plan, entry, ws, ws_bytes);
   if (st) return st;
-  hipStream_t s = (hipStream_t)stream;
-  switch (plan->precision) {
-    case SOX_FP64: return run_static<double>(*plan, entry, X, U1, U2, G, Sigma, ws, s);
-    case SOX_FP32: return run_static<float>(*plan, entry, X, U1, U2, G, Sigma, ws, s);
-    default: return fail(SOX_ERR_UNSUPPORTED, "precision %d not implemented", plan->precision);
-  }
+  const uintptr_t key[9] = {(uintptr_t)entry, (uintptr_t)X, (uintptr_t)U1, (uintptr_t)U2,
+                            (uintptr_t)G, (uintptr_t)Sigma, (uintptr_t)ws, (uintptr_t)ws_bytes, 0};
+  return run_maybe_graph(*plan, key, (hipStream_t)stream, [&](hipStream_t s) -> sox_status {
+    switch (plan->precision) {
+      case SOX_FP64: return run_static<double>(*plan, entry, X, U1, U2, G, Sigma, ws, s);
+      case SOX_FP32: return run_static<float>(*plan, entry, X, U1, U2, G, Sigma, ws, s);
+      default: return fail(SOX_ERR_UNSUPPORTED, "precision %d not implemented", plan->precision);
+    }
+  });
 }
 
 }  // namespace
@@ -1109,6 +1274,15 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
       p->fused_cfg = v;
   }
   set_fused_cfg(*p, p->fused_cfg);
+  if (const char* at = getenv("SOX_AUTOTUNE")) {
+    if (atoi(at) == 1 && !getenv("SOX_FUSED_CFG")) {
+      sox_status st = autotune_fused(*p);
+      if (st) {
+        sox_plan_destroy(p);
+        return st;
+      }
+    }
+  }
   p->slab = pick_slab(*p, SOX_ENTRY_STATIC);
   p->vjp_slab = pick_vjp_slab(*p, SOX_ENTRY_STATIC);
   if (p->n_omega > 0) pick_dyn(*p);
@@ -1154,6 +1328,8 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
 
 sox_status sox_plan_destroy(sox_plan* p) {
   if (!p) return SOX_OK;
+  drop_graphs(*p);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
   for (auto& e : p->ev_pool) {
     (void)hipEventDestroy(e.a);
     (void)hipEventDestroy(e.b);
@@ -1197,12 +1373,16 @@ sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_ta
   if (!X || !W_tau || !V || !G || !Sigma) return fail(SOX_ERR_INVALID_ARG, "NULL tensor pointer");
   st = check_ws(plan, SOX_ENTRY_DYNAMIC, ws, ws_bytes);
   if (st) return st;
-  hipStream_t s = (hipStream_t)stream;
-  switch (plan->precision) {
-    case SOX_FP64: return run_dynamic<double>(*plan, X, W_tau, V, G, Sigma, ws, s);
-    case SOX_FP32: return run_dynamic<float>(*plan, X, W_tau, V, G, Sigma, ws, s);
-    default: return fail(SOX_ERR_UNSUPPORTED, "precision %d not implemented", plan->precision);
-  }
+  const uintptr_t key[9] = {(uintptr_t)SOX_ENTRY_DYNAMIC, (uintptr_t)X, (uintptr_t)W_tau,
+                            (uintptr_t)V, (uintptr_t)G, (uintptr_t)Sigma, (uintptr_t)ws,
+                            (uintptr_t)ws_bytes, 0};
+  return run_maybe_graph(*plan, key, (hipStream_t)stream, [&](hipStream_t s) -> sox_status {
+    switch (plan->precision) {
+      case SOX_FP64: return run_dynamic<double>(*plan, X, W_tau, V, G, Sigma, ws, s);
+      case SOX_FP32: return run_dynamic<float>(*plan, X, W_tau, V, G, Sigma, ws, s);
+      default: return fail(SOX_ERR_UNSUPPORTED, "precision %d not implemented", plan->precision);
+    }
+  });
 }
 
 sox_status sox_sigma_vjp(sox_plan* plan, int32_t entry, const double* X, const double* U1,
@@ -1307,6 +1487,37 @@ sox_status sox_profile_read(sox_plan* plan, double* ms, int64_t* launches, int64
     plan->ev_used = 0;
     plan->ev_dropped = 0;
   }
+  return SOX_OK;
+}
+
+sox_status sox_plan_set_graph(sox_plan* plan, int32_t enable) {
+  sox_status st = check_plan(plan);
+  if (st) return st;
+  plan->graph_on = enable != 0;
+  if (!plan->graph_on) drop_graphs(*plan);
+  return SOX_OK;
+}
+
+sox_status sox_plan_describe(const sox_plan* plan, char* buf, size_t len) {
+  if (!plan) return fail(SOX_ERR_INVALID_ARG, "plan is NULL");
+  if (!buf || len == 0) return fail(SOX_ERR_INVALID_ARG, "buffer is NULL or empty");
+  std::string tune = "[";
+  for (size_t i = 0; i < plan->tune_ms.size(); ++i) {
+    char t[64];
+    snprintf(t, sizeof(t), "%s[%d,%.6g]", i ? "," : "", plan->tune_ms[i].first,
+             plan->tune_ms[i].second);
+    tune += t;
+  }
+  tune += "]";
+  const FusedCfg& fc = kFusedCfgs[plan->fused_cfg];
+  snprintf(buf, len,
+           "{\"n\":%d,\"N\":%d,\"n_tau\":%d,\"nP\":%d,\"NP\":%d,\"precision\":%d,"
+           "\"fused_cfg\":%d,\"fused_wave_tile\":[%d,%d],\"tau_slab\":%d,\"vjp_tau_slab\":%d,"
+           "\"v_slab\":%d,\"vjp_v_slab\":%d,\"graph\":%d,\"tune_ms_per_tau\":%s,"
+           "\"tune_from_cache\":%d}",
+           plan->n, plan->N, plan->n_tau, plan->nP, plan->NP, plan->precision, plan->fused_cfg,
+           fc.wp, fc.wr, plan->slab, plan->vjp_slab, plan->vc, plan->vc_vjp, plan->graph_on ? 1 : 0,
+           tune.c_str(), plan->tune_from_cache ? 1 : 0);
   return SOX_OK;
 }
 

@@ -1,0 +1,97 @@
+"""Whole-sweep HIP graph replay and the fused-tile autotuner.
+
+Graph replays are checked one by one against an eager plan of the same
+configuration (bitwise: same kernels, same launch shapes), with eager torch
+work, synchronisations and new input values between the replays.
+"""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import sox_mol as om
+from paper_2412_18829_amd import synth
+from tests.gpu_util import dev, have_gpu, host, log, rel_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not have_gpu():
+        pytest.skip("no GPU")
+    from paper_2412_18829_amd import binding
+    binding.load()
+    return binding
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_static_graph_replays_match_eager(B, precision):
+    import torch
+    wl = synth.small_molecule(24, 200, 10, 8.0, seed=41, static=True)
+    n, N, nt = wl["n"], wl["N"], wl["n_tau"]
+    pg = B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision=precision)
+    pe = B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision=precision)
+    B.sox_plan_set_graph(pg, True)
+    X, W0, V = dev(wl["X"]), dev(wl["W0"]), dev(wl["V"])
+    G = torch.empty((nt, n, n), dtype=torch.float64, device="cuda")
+    Sg = torch.empty_like(G)
+    Se = torch.empty_like(G)
+    wsg = pg.workspace("static")
+    wse = pe.workspace("static")
+    rng = np.random.default_rng(0)
+    G0 = om.g_tau(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    for rep in range(4):
+        G.copy_(dev(G0 + 0.01 * rep * rng.standard_normal(G0.shape)))
+        junk = torch.randn(1 << 20, device="cuda") * 2.0  # unrelated eager work between replays
+        B.sox_sigma_static(pg, X, W0, V, G, Sg, ws=wsg)
+        B.sox_sigma_static(pe, X, W0, V, G, Se, ws=wse)
+        torch.cuda.synchronize()
+        assert torch.equal(Sg, Se), f"replay {rep}"
+        del junk
+    assert B.sox_plan_describe(pg)["graph"] == 1
+
+
+def test_dynamic_graph_replays_match_eager(B):
+    import torch
+    wl = synth.small_molecule(13, 70, 24, 30.0, seed=42, dynamic=True)
+    tp = synth.bosonic_transform_pair(wl["tau"], wl["beta"], omega_max=14.0, tol=1e-10)
+    n, N, nt = wl["n"], wl["N"], wl["n_tau"]
+    mk = lambda: B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision="fp32",
+                        t_fwd=tp["T_fwd"], t_bwd=tp["T_bwd"])
+    pg, pe = mk(), mk()
+    B.sox_plan_set_graph(pg, True)
+    X, W, V = dev(wl["X"]), dev(wl["W_tau"]), dev(wl["V"])
+    G = dev(om.g_tau(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"]))
+    Sg, Se = torch.empty_like(G), torch.empty_like(G)
+    wsg, wse = pg.workspace("dynamic"), pe.workspace("dynamic")
+    for rep in range(3):
+        G.mul_(1.0 + 0.01 * rep)
+        B.sox_sigma_dynamic(pg, X, W, V, G, Sg, ws=wsg)
+        B.sox_sigma_dynamic(pe, X, W, V, G, Se, ws=wse)
+        torch.cuda.synchronize()
+        assert torch.equal(Sg, Se), f"replay {rep}"
+
+
+def test_autotuner_and_cache(B, tmp_path, monkeypatch):
+    import torch
+    wl = synth.small_molecule(32, 260, 6, 8.0, seed=43)
+    cache = tmp_path / "tune.txt"
+    monkeypatch.setenv("SOX_AUTOTUNE", "1")
+    monkeypatch.setenv("SOX_TUNE_CACHE", str(cache))
+    p1 = B.Plan(wl["n"], wl["N"], wl["tau"], wl["weights"], wl["beta"], precision="fp32")
+    d1 = B.sox_plan_describe(p1)
+    log(f"autotune {d1}")
+    assert len(d1["tune_ms_per_tau"]) >= 2 and d1["tune_from_cache"] == 0
+    best = min(d1["tune_ms_per_tau"], key=lambda t: t[1])[0]
+    assert d1["fused_cfg"] == best
+    p2 = B.Plan(wl["n"], wl["N"], wl["tau"], wl["weights"], wl["beta"], precision="fp32")
+    d2 = B.sox_plan_describe(p2)
+    assert d2["tune_from_cache"] == 1 and d2["fused_cfg"] == best
+    G = dev(om.g_tau(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"]))
+    S = torch.empty_like(G)
+    B.sox_sigma_bare(p2, dev(wl["X"]), dev(wl["V"]), G, S)
+    torch.cuda.synchronize()
+    Gr = host(G)
+    ref = om.sigma_static_thc(wl["X"], wl["V"], wl["V"], Gr, Gr[::-1])
+    assert rel_err(host(S), ref) <= 1e-6
