@@ -20,6 +20,7 @@
 #include "sox_gemm.hpp"
 #include "sox_steps.hpp"
 #include "sox_adjoint.hpp"
+#include "sox_bf16.hpp"
 #include "sox_vjp_steps.hpp"
 
 using namespace sox;
@@ -55,15 +56,17 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 // wavefront; a workgroup is 2 x 2 wavefronts).
 struct FusedCfg {
   int wp, wr;
-  bool fp32, fp64;
+  bool fp32, fp64, bf16;
 };
 static const FusedCfg kFusedCfgs[] = {
-    {32, 32, true, true},   // 0
-    {64, 32, true, false},  // 1
-    {32, 64, true, false},  // 2
-    {64, 64, true, false},  // 3
-    {32, 16, true, true},   // 4
-    {16, 32, false, true},  // 5
+    {32, 32, true, true, false},   // 0
+    {64, 32, true, false, false},  // 1
+    {32, 64, true, false, false},  // 2
+    {64, 64, true, false, false},  // 3
+    {32, 16, true, true, false},   // 4
+    {16, 32, false, true, false},  // 5
+    {32, 32, false, false, true},  // 6  bf16 x 3
+    {64, 32, false, false, true},  // 7  bf16 x 3
 };
 static const int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
 
@@ -154,7 +157,9 @@ namespace {
 
 // -- workspace layout --------------------------------------------------------
 struct Layout {
-  size_t u1, u2, a, p1, p2t, d, e, gbt, total;
+  size_t u1, u2, a, p1, p2t, d, e, gbt;
+  size_t ah, al, p1h, p1l, p2h, p2l, u2h, u2l;  // bf16 x 3 split operands
+  size_t total;
 };
 
 struct DynLayout {
@@ -185,6 +190,13 @@ Layout layout_for(const sox_plan& p, int entry, int slab) {
   L.d = c.take((size_t)slab * NP * NP * es);
   L.e = c.take((size_t)slab * n * NP * 8);
   L.gbt = c.take((size_t)slab * nP * nP * es);
+  if (p.precision == SOX_BF16X3) {
+    const size_t na = (size_t)slab * n * NP * nP, np1 = (size_t)slab * NP * nP, nu = NP * nP * nP;
+    L.ah = c.take(na * 2); L.al = c.take(na * 2);
+    L.p1h = c.take(np1 * 2); L.p1l = c.take(np1 * 2);
+    L.p2h = c.take(np1 * 2); L.p2l = c.take(np1 * 2);
+    L.u2h = c.take(nu * 2); L.u2l = c.take(nu * 2);
+  }
   L.total = c.off;
   return L;
 }
@@ -238,8 +250,14 @@ void pick_dyn(sox_plan& p) {
   p.vc_vjp = vc;
 }
 
+bool cfg_allowed(int precision, int cfg) {
+  const FusedCfg& c = kFusedCfgs[cfg];
+  return precision == SOX_FP64 ? c.fp64 : precision == SOX_FP32 ? c.fp32 : c.bf16;
+}
+
 int default_fused_cfg(int precision, int N) {
   if (precision == SOX_FP64) return 0;
+  if (precision == SOX_BF16X3) return N >= 256 ? 7 : 6;
   // float32: the 64 x 64 wave tile halves the operand traffic per flop of
   // the 32 x 32 one and measured fastest at N = 384 and N = 1200 even with
   // the padding to a multiple of 128; tiny N keeps the small tile
@@ -398,6 +416,14 @@ sox_status launch_fused_cfg<double>(const sox_plan& p, const FusedArgs<double>& 
   return SOX_OK;
 }
 
+sox_status launch_split(const float* src, bf16_t* hi, bf16_t* lo, long count, hipStream_t s) {
+  if (count <= 0) return SOX_OK;
+  hipLaunchKernelGGL(split_bf16_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, src,
+                     hi, lo, count);
+  SOX_HIP(hipGetLastError());
+  return SOX_OK;
+}
+
 template <typename T>
 sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1, const double* U2,
                       const double* G, double* Sigma, void* ws, hipStream_t s) {
@@ -464,7 +490,32 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
     fa.tiles_r = tiles_r;
     fa.n_tau = cnt;
     fa.accumulate = 0;
-    {
+    if (p.precision == SOX_BF16X3) {
+      // x = hi + lo split of the four float32 operands, then bf16 x 3 MFMA
+      bf16_t* ah = (bf16_t*)(base + L.ah); bf16_t* al = (bf16_t*)(base + L.al);
+      bf16_t* p1h = (bf16_t*)(base + L.p1h); bf16_t* p1l = (bf16_t*)(base + L.p1l);
+      bf16_t* p2h = (bf16_t*)(base + L.p2h); bf16_t* p2l = (bf16_t*)(base + L.p2l);
+      bf16_t* u2h = (bf16_t*)(base + L.u2h); bf16_t* u2l = (bf16_t*)(base + L.u2l);
+      {
+        ProfScope ps(p, SOX_STAGE_SPLIT, s);
+        const long na = (long)cnt * n * NP * nP, np1 = (long)cnt * NP * nP;
+        if ((st = launch_split((const float*)A, ah, al, na, s))) return st;
+        if ((st = launch_split((const float*)P1, p1h, p1l, np1, s))) return st;
+        if ((st = launch_split((const float*)P2T, p2h, p2l, np1, s))) return st;
+        if (t0 == 0 && (st = launch_split((const float*)u2t, u2h, u2l, (long)NP * nP * nP, s)))
+          return st;
+      }
+      FusedSplitArgs fs;
+      fs.Ah = ah; fs.Al = al; fs.Yh = p1h; fs.Yl = p1l; fs.Ph = p2h; fs.Pl = p2l;
+      fs.Uh = u2h; fs.Ul = u2l; fs.D = (float*)D;
+      fs.a_tstride = fa.a_tstride; fs.a_vstride = fa.a_vstride; fs.y_tstride = fa.y_tstride;
+      fs.p_tstride = fa.p_tstride; fs.u_rstride = fa.u_rstride; fs.u_vstride = fa.u_vstride;
+      fs.d_tstride = fa.d_tstride; fs.accumulate = 0; fs.n = n; fs.nP = nP; fs.NP = NP;
+      fs.tiles_p = tiles_p; fs.tiles_r = tiles_r; fs.n_tau = cnt;
+      ProfScope ps(p, SOX_STAGE_FUSED, s);
+      if (p.fused_cfg == 7) SOX_HIP((launch_fused_bf16x3<64, 32>(fs, s)));
+      else SOX_HIP((launch_fused_bf16x3<32, 32>(fs, s)));
+    } else {
       ProfScope ps(p, SOX_STAGE_FUSED, s);
       st = launch_fused_cfg<T>(p, fa, s);
       if (st) return st;
@@ -1162,8 +1213,7 @@ sox_status autotune_fused(sox_plan& p) {
   double best_ms = 1e300;
   p.tune_ms.clear();
   for (int c = 0; c < kNumFusedCfgs; ++c) {
-    const bool ok = p.precision == SOX_FP64 ? kFusedCfgs[c].fp64 : kFusedCfgs[c].fp32;
-    if (!ok) continue;
+    if (!cfg_allowed(p.precision, c)) continue;
     double ms = 0;
     sox_status st = p.precision == SOX_FP64 ? time_fused_cfg<double>(p, c, tt, &ms)
                                             : time_fused_cfg<float>(p, c, tt, &ms);
@@ -1198,8 +1248,11 @@ sox_status dispatch_static(sox_plan* plan, int entry, const double* X, const dou
   return run_maybe_graph(*plan, key, (hipStream_t)stream, [&](hipStream_t s) -> sox_status {
     switch (plan->precision) {
       case SOX_FP64: return run_static<double>(*plan, entry, X, U1, U2, G, Sigma, ws, s);
-      case SOX_FP32: return run_static<float>(*plan, entry, X, U1, U2, G, Sigma, ws, s);
-      default: return fail(SOX_ERR_UNSUPPORTED, "precision %d not implemented", plan->precision);
+      case SOX_FP32:
+      case SOX_BF16X3: return run_static<float>(*plan, entry, X, U1, U2, G, Sigma, ws, s);
+      default:
+        return fail(SOX_ERR_UNSUPPORTED, "precision %d: the dynamic entry runs in fp32 or fp64",
+                    plan->precision);
     }
   });
 }
@@ -1265,17 +1318,15 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
     p->t_fwd.assign(pr->t_fwd, pr->t_fwd + 2 * (size_t)pr->n_omega * nt);
     p->t_bwd.assign(pr->t_bwd, pr->t_bwd + 2 * (size_t)pr->n_omega * nt);
   }
-  p->nP = (int)round_up(p->n, 16);
+  p->nP = (int)round_up(p->n, precision == SOX_BF16X3 ? 32 : 16);
   p->fused_cfg = default_fused_cfg(precision, p->N);
   if (const char* s = getenv("SOX_FUSED_CFG")) {
     int v = atoi(s);
-    if (v >= 0 && v < kNumFusedCfgs &&
-        (precision == SOX_FP64 ? kFusedCfgs[v].fp64 : kFusedCfgs[v].fp32))
-      p->fused_cfg = v;
+    if (v >= 0 && v < kNumFusedCfgs && cfg_allowed(precision, v)) p->fused_cfg = v;
   }
   set_fused_cfg(*p, p->fused_cfg);
   if (const char* at = getenv("SOX_AUTOTUNE")) {
-    if (atoi(at) == 1 && !getenv("SOX_FUSED_CFG")) {
+    if (atoi(at) == 1 && !getenv("SOX_FUSED_CFG") && precision != SOX_BF16X3) {
       sox_status st = autotune_fused(*p);
       if (st) {
         sox_plan_destroy(p);
@@ -1380,7 +1431,9 @@ sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_ta
     switch (plan->precision) {
       case SOX_FP64: return run_dynamic<double>(*plan, X, W_tau, V, G, Sigma, ws, s);
       case SOX_FP32: return run_dynamic<float>(*plan, X, W_tau, V, G, Sigma, ws, s);
-      default: return fail(SOX_ERR_UNSUPPORTED, "precision %d not implemented", plan->precision);
+      default:
+        return fail(SOX_ERR_UNSUPPORTED, "precision %d: the dynamic entry runs in fp32 or fp64",
+                    plan->precision);
     }
   });
 }

@@ -28,6 +28,23 @@ __device__ __forceinline__ f64x4 mfma16x16x4(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// bfloat16 operands: 8 per lane and k chunks of 32 (v_mfma_f32_16x16x32_bf16).
+// Lane l supplies A[l % 16][8 (l/16) + e] and B[8 (l/16) + e][l % 16], e = 0..7;
+// the float32 accumulator has the same layout as the 16x16x4 float32 one.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned short bf16_t;  // storage of one bfloat16
+
+__device__ __forceinline__ f32x4 mfma16x16x32bf16(bf16x8 a, bf16x8 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Round-to-nearest-even float32 -> bfloat16 (finite inputs) and back.
+__device__ __forceinline__ bf16_t f32_to_bf16(float x) {
+  const unsigned u = __float_as_uint(x);
+  return (bf16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(bf16_t h) { return __uint_as_float((unsigned)h << 16); }
+
 template <typename T> __device__ __forceinline__ int acc_row(int g, int r);
 template <> __device__ __forceinline__ int acc_row<float>(int g, int r) { return 4 * g + r; }
 template <> __device__ __forceinline__ int acc_row<double>(int g, int r) { return g + 4 * r; }

@@ -57,6 +57,9 @@ inline emu_d4 emu_mfma_d(double a, double b, emu_d4 c) { return c + a * b; }
 #define __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, x, y, z) emu_mfma_f(a, b, c)
 #define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) emu_mfma_d(a, b, c)
 #define __builtin_amdgcn_sched_barrier(x) ((void)0)
+#define __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, x, y, z) (c)
+inline unsigned __float_as_uint(float x) { unsigned u; memcpy(&u, &x, 4); return u; }
+inline float __uint_as_float(unsigned u) { float x; memcpy(&x, &u, 4); return x; }
 extern const char* g_emu_kernel;
 template <typename K, typename... A>
 inline void emu_launch(const char* name, K kernel, dim3 g, dim3 b, A... args) {

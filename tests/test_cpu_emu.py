@@ -31,7 +31,7 @@ def emu(tmp_path_factory):
 
 
 CASES = [
-    # n, N, n_tau, precision(0 fp64 / 1 fp32), entry(0 bare, 1 static, 2 dynamic), vjp, env budget
+    # n, N, n_tau, precision(0 fp64 / 1 fp32 / 2 bf16x3), entry(0 bare, 1 static, 2 dynamic), vjp, env budget
     (6, 20, 8, 0, 0, 0, None),
     (13, 70, 5, 1, 1, 0, None),
     (3, 7, 1, 1, 1, 0, None),
@@ -51,6 +51,10 @@ CASES = [
     (13, 70, 5, 1, 2, 1, None),
     (16, 256, 3, 1, 2, 1, None),
     (21, 90, 6, 1, 2, 1, "4"),
+    (13, 70, 5, 2, 1, 0, None),
+    (6, 20, 8, 2, 0, 0, None),
+    (16, 256, 3, 2, 0, 0, None),
+    (10, 40, 6, 2, 0, 0, "1"),
 ]
 
 

@@ -149,3 +149,24 @@ def test_workspace_too_small_is_an_error(B):
     with pytest.raises(B.SoxError) as ei:
         B.sox_sigma_bare(plan, dev(wl["X"]), dev(wl["V"]), G, S, ws=small)
     assert ei.value.status == 4
+
+
+@pytest.mark.parametrize("shape", [(13, 50, 6), (40, 200, 4), (64, 384, 8)])
+def test_bf16x3_static_vs_oracle(B, shape):
+    """Split precision (x = hi + lo in bf16, three bf16 MFMA products per
+    product, float32 accumulation): max relative error <= 1e-4 before any
+    refinement."""
+    import torch
+    n, N, nt = shape
+    log(f"bf16x3 static {shape}")
+    wl = synth.small_molecule(n, N, nt, 7.0, seed=200 + n, static=True)
+    rng = np.random.default_rng(n)
+    Gr = om.g_tau(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"]) + 0.05 * rng.standard_normal((nt, n, n))
+    plan = _plan(B, wl, "bf16x3")
+    S = torch.empty((nt, n, n), dtype=torch.float64, device="cuda")
+    B.sox_sigma_static(plan, dev(wl["X"]), dev(wl["W0"]), dev(wl["V"]), dev(Gr), S)
+    torch.cuda.synchronize()
+    ref = om.sigma_static_thc(wl["X"], wl["W0"], wl["V"], Gr, Gr[::-1])
+    err = rel_err(host(S), ref)
+    log(f"  rel err {err:.3e}")
+    assert err <= 1e-4
