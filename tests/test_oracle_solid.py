@@ -1,0 +1,101 @@
+"""Pins of the k-point (solid) oracle (PN8 and a supercell unfolding).
+
+  * the paper's k-point step chain equals the k-space 4-index brute force;
+  * a Gamma-only mesh with real inputs equals the molecular oracle;
+  * momentum-independent inputs give the molecular self-energy (fixes the
+    1/N_k^2 normalisation);
+  * Sigma^k is Hermitian for U1 = U2 and Hermitian G^k;
+  * supercell unfolding: a ring of L cells with translation-invariant real
+    X, U, G, run through the MOLECULAR oracle, Bloch-transformed, equals the
+    k-space oracle on the Bloch-transformed inputs, with scale factor 1 (fixes
+    every momentum label and both 1/N_k factors; a flipped label, a missing
+    conjugate or a dropped 1/N_k each fail it), and the GM energy per cell
+    equals the supercell energy divided by L.
+"""
+import numpy as np
+import pytest
+
+from oracle import sox_mol as om
+from oracle import sox_solid as osd
+from paper_2412_18829_amd import synth
+
+
+def _tables(wl):
+    return (wl["kvecs"], wl["kdiff"], wl["ksum"], wl["kneg"])
+
+
+@pytest.mark.parametrize("mesh", [(2, 1, 1), (3, 1, 1), (2, 2, 1)])
+def test_chain_equals_bruteforce(mesh):
+    wl = synth.solid(mesh, 3, 7, 4, 5.0, seed=5)
+    rng = np.random.default_rng(1)
+    G = osd.g_tau_k(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    G = G + 0.05 * (rng.standard_normal(G.shape) + 1j * rng.standard_normal(G.shape))
+    U2 = synth.paired_hermitian(rng, wl["kneg"], 7, 1 / 7)
+    a = osd.sigma_solid_eri(wl["X"], wl["V"], U2, G, _tables(wl))
+    b = osd.sigma_solid_thc(wl["X"], wl["V"], U2, G, _tables(wl))
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
+
+
+def test_gamma_only_equals_molecule():
+    wl = synth.small_molecule(5, 12, 6, 5.0, seed=3, static=True)
+    G = om.g_tau(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    tb = synth.kmesh_index((1, 1, 1))
+    S = osd.sigma_solid_thc(wl["X"][None].astype(complex), wl["W0"][None].astype(complex),
+                            wl["V"][None].astype(complex), G[None].astype(complex), tb)
+    ref = om.sigma_static_thc(wl["X"], wl["W0"], wl["V"], G, G[::-1])
+    assert np.abs(S[0] - ref).max() <= 1e-14 * np.abs(ref).max()
+
+
+def test_k_independent_inputs_give_molecule():
+    wl = synth.small_molecule(4, 9, 5, 5.0, seed=4)
+    G = om.g_tau(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    mesh = (3, 2, 1)
+    tb = synth.kmesh_index(mesh)
+    nk = len(tb[0])
+    rep = lambda a: np.repeat(a[None], nk, axis=0).astype(complex)
+    S = osd.sigma_solid_thc(rep(wl["X"]), rep(wl["V"]), rep(wl["V"]), rep(G), tb)
+    ref = om.sigma_static_thc(wl["X"], wl["V"], wl["V"], G, G[::-1])
+    for k in range(nk):
+        assert np.abs(S[k] - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_hermitian_for_equal_interactions():
+    wl = synth.solid((3, 1, 1), 4, 8, 5, 5.0, seed=6)
+    G = osd.g_tau_k(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    S = osd.sigma_solid_thc(wl["X"], wl["V"], wl["V"], G, _tables(wl))
+    assert np.abs(S - S.conj().transpose(0, 1, 3, 2)).max() <= 1e-13 * np.abs(S).max()
+
+
+def _supercell(m, L):
+    a, b = m.shape[-2:]
+    out = np.zeros(m.shape[:-3] + (L * a, L * b))
+    for R1 in range(L):
+        for R2 in range(L):
+            out[..., R1 * a:(R1 + 1) * a, R2 * b:(R2 + 1) * b] = m[..., (R1 - R2) % L, :, :]
+    return out
+
+
+@pytest.mark.parametrize("L", [2, 3, 4])
+def test_supercell_unfolding(L):
+    n, N, nt, beta = 2, 4, 5, 4.0
+    rng = np.random.default_rng(10 + L)
+    x = rng.standard_normal((L, n, N)) * 0.5
+    u = rng.standard_normal((L, N, N)) * 0.3
+    u = 0.5 * (u + np.transpose(u[(-np.arange(L)) % L], (0, 2, 1)))    # supercell U symmetric
+    g = rng.standard_normal((nt, L, n, n)) * 0.3
+    tau, w = synth.chebyshev_tau_grid(nt, beta)
+    Xs, Us, Gs = _supercell(x, L), _supercell(u, L), _supercell(g, L)
+    Ss = om.sigma_static_thc(Xs, Us, Us, Gs, Gs[::-1])
+    sig = np.stack([Ss[:, R * n:(R + 1) * n, 0:n] for R in range(L)], axis=1)   # sigma(R)
+    tb = synth.kmesh_index((L, 1, 1))
+    ph = lambda s: np.exp(s * 2j * np.pi * np.outer(np.arange(L), np.arange(L)) / L)
+    Xk = np.einsum("kR,Rab->kab", ph(-1), x)
+    Uk = np.einsum("kR,Rab->kab", ph(1), u)
+    Gk = np.einsum("kR,tRab->ktab", ph(1), g)
+    pred = np.einsum("kR,tRab->ktab", ph(1), sig)
+    Sk = osd.sigma_solid_thc(Xk, Uk, Uk, Gk, tb)
+    assert np.abs(Sk - pred).max() <= 1e-13 * np.abs(pred).max()
+    # energy per cell = supercell energy / L
+    e_sc = om.energy_gm(Ss, Gs[::-1], w)
+    e_k = osd.energy_gm_k(Sk, Gk, w)
+    assert abs(e_k - e_sc / L) <= 1e-12 * abs(e_sc)
