@@ -20,6 +20,21 @@
  *     G      [n_tau, n_orb, n_orb]    G[k,p,q] = G_pq(tau_k); treated as a
  *                                     general (not necessarily symmetric) matrix
  *     Sigma  [n_tau, n_orb, n_orb]    Sigma[k,t,r] = Sigma_tr(tau_k)
+ * - Solids (kmesh {m0,m1,m2} with more than one point): n_k = m0 m1 m2
+ *   momenta of a Gamma-centred mesh, index (a m1 + b) m2 + c for the integer
+ *   vector (a, b, c); q = k_i - k_j is taken modulo the mesh.  Every tensor
+ *   is complex128 (interleaved re, im doubles), row-major, contiguous:
+ *     X      [n_k, n_orb, n_thc]      X^k_iP
+ *     V, W0  [n_k, n_thc, n_thc]      U^q_PQ of the THC integrals
+ *            (i k_i, j k_j | s k_s, r k_r) = sum_PQ conj(X^{k_i}_iP) X^{k_j}_jP
+ *                                         U^q_PQ conj(X^{k_s}_sQ) X^{k_r}_rQ
+ *     G      [n_k, n_tau, n_orb, n_orb]
+ *     Sigma  [n_k, n_tau, n_orb, n_orb]
+ *   The k-point form of eq:sox carries 1/N_k per momentum sum (1/N_k^2 in
+ *   all), k_s = k_p + k_q - k_t, and follows the momentum-resolved chain of
+ *   the paper's solids section (Sigma_RP = -D_PR / N_k).  The bare and
+ *   static entries, sox_build_g_tau and sox_energy_gm accept solids in fp64
+ *   and fp32; the dynamic entry and the adjoint return SOX_ERR_UNSUPPORTED.
  * - Every tensor pointer is a DEVICE pointer owned by the caller.  Outputs
  *   are overwritten, never accumulated into.  `stream` is a hipStream_t
  *   (NULL = the null stream); all device work of a call is ordered on it
@@ -81,7 +96,8 @@ typedef struct {
   int32_t n_orb;          /* n, orbitals (>= 1)                                */
   int32_t n_thc;          /* N, THC interpolation points (>= 1)                */
   int32_t n_tau;          /* imaginary-time nodes (>= 1)                       */
-  int32_t kmesh[3];       /* {1,1,1}: molecule.  Other meshes: UNSUPPORTED.    */
+  int32_t kmesh[3];       /* {1,1,1}: molecule; else a k-point mesh, each entry
+                             1..16, at most 256 points (fp64 / fp32 only)      */
   double beta;            /* inverse temperature (> 0)                         */
   const double* tau;      /* HOST [n_tau], ascending in [0, beta], mirror
                              symmetric; copied at plan creation                */
@@ -158,14 +174,18 @@ sox_status sox_sigma_vjp(sox_plan* plan, int32_t entry, const double* X, const d
  * n(e,tau) = e^{-(e-mu)tau} / (1 + e^{-beta(e-mu)}) for e >= mu and the
  * equal form e^{(beta-tau)(e-mu)} / (1 + e^{beta(e-mu)}) for e < mu, so no
  * exponential overflows.  Q [n,n] device (eigenvectors in columns), eps [n]
- * device, G [n_tau,n,n] device output.  float64 throughout. */
+ * device, G [n_tau,n,n] device output.  float64 throughout.
+ * Solids: G^k(tau) = -Q_k diag(n(eps_k, tau)) Q_k^dagger with Q complex128
+ * [n_k,n,n], eps float64 [n_k,n], G complex128 [n_k,n_tau,n,n]. */
 sox_status sox_build_g_tau(sox_plan* plan, const double* Q, const double* eps, double mu,
                            double* G, void* stream);
 
 /* Galitskii-Migdal energy of a SOX self-energy (eq:E2b in imaginary time):
  * E = -1/2 sum_k w_k sum_tr Sigma_tr(tau_k) G_rt(beta - tau_k), float64.
  * Sigma, G device [n_tau,n,n]; *E_host written after the stream is
- * synchronised. */
+ * synchronised.  Solids: E = -1/2 (1/N_k) sum_k sum_j w_j
+ * Re Tr[Sigma^k(tau_j) G^k(beta - tau_j)], Sigma and G complex128
+ * [n_k,n_tau,n,n]. */
 sox_status sox_energy_gm(sox_plan* plan, const double* Sigma, const double* G, double* E_host,
                          void* stream);
 
@@ -189,7 +209,9 @@ typedef enum {
   SOX_STAGE_IFT = 9,      /* dynamic: inverse transform                     */
   SOX_STAGE_SPLIT = 10,   /* bf16 hi/lo split                               */
   SOX_STAGE_VJP = 11,     /* adjoint kernels                                */
-  SOX_N_STAGES = 12
+  SOX_STAGE_KBC = 12,     /* solids: B and C products of every momentum pair */
+  SOX_STAGE_KD = 13,      /* solids: the n_k^3 D step                        */
+  SOX_N_STAGES = 14
 } sox_stage;
 
 sox_status sox_profile_enable(sox_plan* plan, int32_t on);

@@ -32,7 +32,7 @@ EXPORTED = (
     "sox_profile_read", "sox_plan_set_graph", "sox_plan_describe",
 )
 STAGES = ("gbuild", "utensor", "project", "astep", "fused", "back", "energy", "gg_ft", "wgemm",
-          "ift", "split", "vjp")
+          "ift", "split", "vjp", "kbc", "kd")
 
 
 class SoxError(RuntimeError):
@@ -119,6 +119,17 @@ def _f64(t, shape, name):
     return _ptr(t)
 
 
+def _c128(t, shape, name):
+    import torch
+    if t is None:
+        return None
+    if t.dtype != torch.complex128:
+        raise TypeError(f"{name} must be complex128 (k-point plans)")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
+    return _ptr(t)
+
+
 def _stream(stream):
     if stream is not None:
         return stream
@@ -138,6 +149,8 @@ class Plan:
         self.n_tau = int(self.tau.shape[0])
         self.beta = float(beta)
         self.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        self.kmesh = tuple(int(m) for m in kmesh)
+        self.nk = int(np.prod(self.kmesh))
         pr = sox_problem()
         pr.n_orb, pr.n_thc, pr.n_tau = self.n, self.N, self.n_tau
         pr.kmesh[:] = list(kmesh)
@@ -160,6 +173,17 @@ class Plan:
                "sox_plan_create")
         self.handle = h
         self._ws = {}
+
+    @property
+    def solid(self) -> bool:
+        return self.nk > 1
+
+    def _t(self, t, shape, name):
+        """Marshal a tensor: float64 `shape` for molecules, complex128
+        [n_k, *shape] for k-point plans."""
+        if self.solid:
+            return _c128(t, (self.nk, *shape), name)
+        return _f64(t, shape, name)
 
     def workspace_size(self, entry: str | int) -> int:
         e = ENTRIES[entry] if isinstance(entry, str) else int(entry)
@@ -202,8 +226,9 @@ def _ws_args(plan: Plan, entry, ws):
 def sox_sigma_bare(plan: Plan, X, V, G, Sigma, ws=None, stream=None):
     n, N, nt = plan.n, plan.N, plan.n_tau
     w, wb = _ws_args(plan, "bare", ws)
-    _check(load().sox_sigma_bare(plan.handle, _f64(X, (n, N), "X"), _f64(V, (N, N), "V"),
-                                 _f64(G, (nt, n, n), "G"), _f64(Sigma, (nt, n, n), "Sigma"),
+    t = plan._t
+    _check(load().sox_sigma_bare(plan.handle, t(X, (n, N), "X"), t(V, (N, N), "V"),
+                                 t(G, (nt, n, n), "G"), t(Sigma, (nt, n, n), "Sigma"),
                                  w, wb, _stream(stream)), "sox_sigma_bare")
     return Sigma
 
@@ -211,9 +236,10 @@ def sox_sigma_bare(plan: Plan, X, V, G, Sigma, ws=None, stream=None):
 def sox_sigma_static(plan: Plan, X, W0, V, G, Sigma, ws=None, stream=None):
     n, N, nt = plan.n, plan.N, plan.n_tau
     w, wb = _ws_args(plan, "static", ws)
-    _check(load().sox_sigma_static(plan.handle, _f64(X, (n, N), "X"), _f64(W0, (N, N), "W0"),
-                                   _f64(V, (N, N), "V"), _f64(G, (nt, n, n), "G"),
-                                   _f64(Sigma, (nt, n, n), "Sigma"), w, wb, _stream(stream)),
+    t = plan._t
+    _check(load().sox_sigma_static(plan.handle, t(X, (n, N), "X"), t(W0, (N, N), "W0"),
+                                   t(V, (N, N), "V"), t(G, (nt, n, n), "G"),
+                                   t(Sigma, (nt, n, n), "Sigma"), w, wb, _stream(stream)),
            "sox_sigma_static")
     return Sigma
 
@@ -244,17 +270,20 @@ def sox_sigma_vjp(plan: Plan, entry, X, U1, U2, G, R, dG=None, dX=None, dU1=None
 
 def sox_build_g_tau(plan: Plan, Q, eps, mu: float, G, stream=None):
     n, nt = plan.n, plan.n_tau
-    _check(load().sox_build_g_tau(plan.handle, _f64(Q, (n, n), "Q"), _f64(eps, (n,), "eps"),
-                                  float(mu), _f64(G, (nt, n, n), "G"), _stream(stream)),
-           "sox_build_g_tau")
+    if plan.solid:
+        q, e = _c128(Q, (plan.nk, n, n), "Q"), _f64(eps, (plan.nk, n), "eps")
+    else:
+        q, e = _f64(Q, (n, n), "Q"), _f64(eps, (n,), "eps")
+    _check(load().sox_build_g_tau(plan.handle, q, e, float(mu), plan._t(G, (nt, n, n), "G"),
+                                  _stream(stream)), "sox_build_g_tau")
     return G
 
 
 def sox_energy_gm(plan: Plan, Sigma, G, stream=None) -> float:
     n, nt = plan.n, plan.n_tau
     e = ctypes.c_double()
-    _check(load().sox_energy_gm(plan.handle, _f64(Sigma, (nt, n, n), "Sigma"),
-                                _f64(G, (nt, n, n), "G"), ctypes.byref(e), _stream(stream)),
+    _check(load().sox_energy_gm(plan.handle, plan._t(Sigma, (nt, n, n), "Sigma"),
+                                plan._t(G, (nt, n, n), "G"), ctypes.byref(e), _stream(stream)),
            "sox_energy_gm")
     return float(e.value)
 

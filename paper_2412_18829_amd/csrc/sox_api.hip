@@ -22,6 +22,7 @@
 #include "sox_adjoint.hpp"
 #include "sox_bf16.hpp"
 #include "sox_vjp_steps.hpp"
+#include "sox_complex.hpp"
 
 using namespace sox;
 
@@ -85,6 +86,13 @@ struct sox_plan {
   int vc = 0;       // dynamic entry: v-slab width
   int vc_vjp = 0;   // dynamic entry: v-slab width of the adjoint
   int eslab = 0;    // dynamic entry: tau nodes per back-transform slab
+  // k-point meshes (nk > 1): mesh with unit dimensions moved last, v-slab
+  // width of the solid chain and the device momentum tables
+  int kmesh[3] = {1, 1, 1};
+  int mesh_canon[3] = {1, 1, 1};
+  int nk = 1;
+  int vcs = 0;
+  int* d_ktab = nullptr;
   // device copies
   double* d_tf2 = nullptr;  // [2 n_omega][n_tau]  Re / Im of t_fwd
   double* d_tb2 = nullptr;  // [n_tau][2 n_omega]  [Re t_bwd | -Im t_bwd]
@@ -320,7 +328,10 @@ int pick_vjp_slab(const sox_plan& p, int entry) {
   return slab;
 }
 
+size_t solid_workspace_bytes(const sox_plan& p, int entry);  // with the solid launch sequence
+
 size_t workspace_bytes(const sox_plan& p, int entry) {
+  if (p.nk > 1) return solid_workspace_bytes(p, entry);
   if (entry == SOX_ENTRY_DYNAMIC)
     return p.n_omega > 0 ? std::max(dyn_layout_for(p, p.vc, p.eslab).total, dyn_vjp_total(p, p.vc_vjp))
                          : 0;
@@ -1234,6 +1245,8 @@ sox_status autotune_fused(sox_plan& p) {
   return SOX_OK;
 }
 
+#include "sox_solid_run.hpp"
+
 sox_status dispatch_static(sox_plan* plan, int entry, const double* X, const double* U1,
                            const double* U2, const double* G, double* Sigma, void* ws,
                            size_t ws_bytes, void* stream) {
@@ -1245,7 +1258,14 @@ sox_status dispatch_static(sox_plan* plan, int entry, const double* X, const dou
   if (st) return st;
   const uintptr_t key[9] = {(uintptr_t)entry, (uintptr_t)X, (uintptr_t)U1, (uintptr_t)U2,
                             (uintptr_t)G, (uintptr_t)Sigma, (uintptr_t)ws, (uintptr_t)ws_bytes, 0};
+  if (plan->nk > 1 && plan->precision == SOX_BF16X3)
+    return fail(SOX_ERR_UNSUPPORTED, "k-point meshes run in fp64 or fp32");
   return run_maybe_graph(*plan, key, (hipStream_t)stream, [&](hipStream_t s) -> sox_status {
+    if (plan->nk > 1) {
+      if (plan->precision == SOX_FP64)
+        return run_solid<double>(*plan, entry, X, U1, U2, G, Sigma, ws, s);
+      return run_solid<float>(*plan, entry, X, U1, U2, G, Sigma, ws, s);
+    }
     switch (plan->precision) {
       case SOX_FP64: return run_static<double>(*plan, entry, X, U1, U2, G, Sigma, ws, s);
       case SOX_FP32:
@@ -1262,7 +1282,7 @@ sox_status dispatch_static(sox_plan* plan, int entry, const double* X, const dou
 // =============================================================================
 extern "C" {
 
-int32_t sox_abi_version(void) { return 1; }
+int32_t sox_abi_version(void) { return 2; }
 
 const char* sox_last_error(void) { return g_last_error.c_str(); }
 
@@ -1277,11 +1297,18 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
                 pr->n_thc, pr->n_tau);
   if (pr->n_orb > 4096 || pr->n_thc > 32768 || pr->n_tau > 4096)
     return fail(SOX_ERR_SHAPE, "sizes beyond the supported range");
-  if (pr->kmesh[0] != 1 || pr->kmesh[1] != 1 || pr->kmesh[2] != 1) {
-    if (pr->kmesh[0] < 1 || pr->kmesh[1] < 1 || pr->kmesh[2] < 1)
-      return fail(SOX_ERR_SHAPE, "kmesh entries must be >= 1");
-    return fail(SOX_ERR_UNSUPPORTED, "k-point meshes are not implemented in this library version");
-  }
+  if (pr->kmesh[0] < 1 || pr->kmesh[1] < 1 || pr->kmesh[2] < 1)
+    return fail(SOX_ERR_SHAPE, "kmesh entries must be >= 1");
+  if (pr->kmesh[0] > 16 || pr->kmesh[1] > 16 || pr->kmesh[2] > 16 ||
+      pr->kmesh[0] * pr->kmesh[1] * pr->kmesh[2] > 256)
+    return fail(SOX_ERR_SHAPE, "k-point mesh beyond the supported range (<= 16 per axis, <= 256 points)");
+  const int nk_req = pr->kmesh[0] * pr->kmesh[1] * pr->kmesh[2];
+  if (nk_req > 1 && ((long)pr->n_tau * nk_req * pr->n_orb > 0x7fffffffL ||
+                     (long)nk_req * nk_req * pr->n_orb > 0x7fffffffL ||
+                     (long)pr->n_thc * pr->n_orb > 0x7fffffffL))
+    return fail(SOX_ERR_SHAPE, "k-point problem beyond the supported range");
+  if (nk_req > 1 && precision == SOX_BF16X3)
+    return fail(SOX_ERR_UNSUPPORTED, "k-point meshes run in fp64 or fp32");
   if (!(pr->beta > 0.0) || !std::isfinite(pr->beta))
     return fail(SOX_ERR_INVALID_ARG, "beta must be positive and finite");
   if (!pr->tau || !pr->weights) return fail(SOX_ERR_INVALID_ARG, "tau / weights are NULL");
@@ -1319,6 +1346,14 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
     p->t_bwd.assign(pr->t_bwd, pr->t_bwd + 2 * (size_t)pr->n_omega * nt);
   }
   p->nP = (int)round_up(p->n, precision == SOX_BF16X3 ? 32 : 16);
+  for (int i = 0; i < 3; ++i) p->kmesh[i] = pr->kmesh[i];
+  p->nk = nk_req;
+  if (p->nk > 1) {
+    int j = 0;
+    for (int i = 0; i < 3; ++i)
+      if (p->kmesh[i] > 1) p->mesh_canon[j++] = p->kmesh[i];
+    for (; j < 3; ++j) p->mesh_canon[j] = 1;
+  }
   p->fused_cfg = default_fused_cfg(precision, p->N);
   if (const char* s = getenv("SOX_FUSED_CFG")) {
     int v = atoi(s);
@@ -1326,7 +1361,7 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
   }
   set_fused_cfg(*p, p->fused_cfg);
   if (const char* at = getenv("SOX_AUTOTUNE")) {
-    if (atoi(at) == 1 && !getenv("SOX_FUSED_CFG") && precision != SOX_BF16X3) {
+    if (atoi(at) == 1 && !getenv("SOX_FUSED_CFG") && precision != SOX_BF16X3 && p->nk == 1) {
       sox_status st = autotune_fused(*p);
       if (st) {
         sox_plan_destroy(p);
@@ -1334,9 +1369,14 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
       }
     }
   }
-  p->slab = pick_slab(*p, SOX_ENTRY_STATIC);
-  p->vjp_slab = pick_vjp_slab(*p, SOX_ENTRY_STATIC);
-  if (p->n_omega > 0) pick_dyn(*p);
+  if (p->nk > 1) {
+    p->slab = p->vjp_slab = 1;
+    p->vcs = pick_solid_vc(*p);
+  } else {
+    p->slab = pick_slab(*p, SOX_ENTRY_STATIC);
+    p->vjp_slab = pick_vjp_slab(*p, SOX_ENTRY_STATIC);
+    if (p->n_omega > 0) pick_dyn(*p);
+  }
 
   hipError_t e = hipGetDevice(&p->device);
   if (e == hipSuccess && p->n_omega > 0) {
@@ -1361,8 +1401,19 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
   }
   if (e == hipSuccess) e = hipMalloc(&p->d_tau, sizeof(double) * nt);
   if (e == hipSuccess) e = hipMalloc(&p->d_w, sizeof(double) * nt);
-  if (e == hipSuccess)
-    e = hipMalloc(&p->d_scratch, sizeof(double) * ((size_t)nt * (p->n + 1) + 1));
+  if (e == hipSuccess) {
+    // molecules: occupations [n_tau][n], traces [n_tau], energy; k-points:
+    // occupations, their complex copy [n_tau][n_k n], traces [n_k][n_tau], energy
+    const size_t nsc = p->nk > 1 ? 3 * (size_t)nt * p->nk * p->n + (size_t)nt * p->nk + 1
+                                 : (size_t)nt * (p->n + 1) + 1;
+    e = hipMalloc(&p->d_scratch, sizeof(double) * nsc);
+  }
+  if (e == hipSuccess && p->nk > 1) {
+    const std::vector<int> tab = solid_tables(p->mesh_canon);
+    e = hipMalloc(&p->d_ktab, sizeof(int) * tab.size());
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_ktab, tab.data(), sizeof(int) * tab.size(), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess)
     e = hipMemcpy(p->d_tau, p->tau.data(), sizeof(double) * nt, hipMemcpyHostToDevice);
   if (e == hipSuccess)
@@ -1390,6 +1441,7 @@ sox_status sox_plan_destroy(sox_plan* p) {
   if (p->d_tb2) (void)hipFree(p->d_tb2);
   if (p->d_w) (void)hipFree(p->d_w);
   if (p->d_scratch) (void)hipFree(p->d_scratch);
+  if (p->d_ktab) (void)hipFree(p->d_ktab);
   delete p;
   return SOX_OK;
 }
@@ -1419,6 +1471,8 @@ sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_ta
                              size_t ws_bytes, void* stream) {
   sox_status st = check_plan(plan);
   if (st) return st;
+  if (plan->nk > 1)
+    return fail(SOX_ERR_UNSUPPORTED, "the dynamic entry is not implemented for k-point meshes");
   if (plan->n_omega <= 0)
     return fail(SOX_ERR_INVALID_ARG, "plan has no transform pair (n_omega = 0)");
   if (!X || !W_tau || !V || !G || !Sigma) return fail(SOX_ERR_INVALID_ARG, "NULL tensor pointer");
@@ -1446,6 +1500,8 @@ sox_status sox_sigma_vjp(sox_plan* plan, int32_t entry, const double* X, const d
   if (st) return st;
   if (entry < SOX_ENTRY_BARE || entry > SOX_ENTRY_DYNAMIC)
     return fail(SOX_ERR_INVALID_ARG, "unknown entry %d", entry);
+  if (plan->nk > 1)
+    return fail(SOX_ERR_UNSUPPORTED, "the adjoint is not implemented for k-point meshes");
   if (!X || !U1 || !G || !R) return fail(SOX_ERR_INVALID_ARG, "NULL input pointer");
   if (entry != SOX_ENTRY_BARE && !U2) return fail(SOX_ERR_INVALID_ARG, "U2 is NULL");
   if (entry == SOX_ENTRY_BARE && dU2)
@@ -1478,6 +1534,7 @@ sox_status sox_build_g_tau(sox_plan* plan, const double* Q, const double* eps, d
   if (!Q || !eps || !G) return fail(SOX_ERR_INVALID_ARG, "NULL tensor pointer");
   if (!std::isfinite(mu)) return fail(SOX_ERR_INVALID_ARG, "mu not finite");
   hipStream_t s = (hipStream_t)stream;
+  if (plan->nk > 1) return solid_build_g(*plan, Q, eps, mu, G, s);
   const int n = plan->n, nt = plan->n_tau;
   double* occ = plan->d_scratch;  // [n_tau][n]
   const int tot = n * nt;
@@ -1496,6 +1553,7 @@ sox_status sox_energy_gm(sox_plan* plan, const double* Sigma, const double* G, d
   if (st) return st;
   if (!Sigma || !G || !E_host) return fail(SOX_ERR_INVALID_ARG, "NULL pointer");
   hipStream_t s = (hipStream_t)stream;
+  if (plan->nk > 1) return solid_energy(*plan, Sigma, G, E_host, s);
   const int n = plan->n, nt = plan->n_tau;
   double* tr = plan->d_scratch + (size_t)nt * n;
   double* e = tr + nt;
@@ -1567,10 +1625,11 @@ sox_status sox_plan_describe(const sox_plan* plan, char* buf, size_t len) {
            "{\"n\":%d,\"N\":%d,\"n_tau\":%d,\"nP\":%d,\"NP\":%d,\"precision\":%d,"
            "\"fused_cfg\":%d,\"fused_wave_tile\":[%d,%d],\"tau_slab\":%d,\"vjp_tau_slab\":%d,"
            "\"v_slab\":%d,\"vjp_v_slab\":%d,\"graph\":%d,\"tune_ms_per_tau\":%s,"
-           "\"tune_from_cache\":%d}",
+           "\"tune_from_cache\":%d,\"kmesh\":[%d,%d,%d],\"n_k\":%d,\"solid_v_slab\":%d}",
            plan->n, plan->N, plan->n_tau, plan->nP, plan->NP, plan->precision, plan->fused_cfg,
            fc.wp, fc.wr, plan->slab, plan->vjp_slab, plan->vc, plan->vc_vjp, plan->graph_on ? 1 : 0,
-           tune.c_str(), plan->tune_from_cache ? 1 : 0);
+           tune.c_str(), plan->tune_from_cache ? 1 : 0, plan->kmesh[0], plan->kmesh[1],
+           plan->kmesh[2], plan->nk, plan->vcs);
   return SOX_OK;
 }
 

@@ -1,0 +1,304 @@
+// Launch sequence of the k-point (periodic solid) SOX path.  Included by
+// sox_api.hip inside its internal namespace (it uses the plan, the status
+// helpers and the per-stage profiling scopes defined there).
+//
+// The chain is the paper's momentum-resolved one (section "THC-SOX and
+// THC-SOSEX: algorithm and implementation details for solids and
+// molecules"), with pair = q * n_k + k for every (q, k) momentum pair:
+//
+//   Ut^{(q,k)}[a][P][b] = sum_Q U^q_PQ conj(X^{k-q}_aQ) X^k_bQ   (eq:U_contraction)
+//   GRq^k[R][q]   = sum_u X^k_uR G^k_uq          GwPt^k[P][w] = sum_p conj(X^k_pP) G^k_wp
+//   A[(q1,k_v)][v][P][q] = sum_s G^{k_v}(beta - tau)_sv Ut1^{(q1,k_v)}[q][P][s]
+//   B[(q1,k_v)][v][P][R] = sum_q A[(q1,k_v)][v][P][q] GRq^{k_v - q1}[R][q]
+//   C[(q2,k_w)][v][P][R] = sum_w GwPt^{k_w}[P][w] Ut2^{(q2,k_w)}[v][R][w]
+//   D^{k_t}[P][R] = (1/n_k) sum_{k_w, q2, v} C[(q2,k_w)][v][P][R] B[(k_w - k_t, k_w - q2)][v][P][R]
+//   Sigma^{k_t}_tr = -(1/n_k) sum_{P,R} conj(X^{k_t}_tR) D^{k_t}[P][R] X^{k_t}_rP
+//
+// v runs in slabs of width vcs so that A, B and C of one slab and one tau
+// node stay within the workspace budget; D accumulates over the slabs in
+// float64.  The U-contraction, the projections and the back-transform run in
+// float64; A, B, C and the D step in the plan's precision.
+
+struct SolidLayout {
+  size_t ut1, ut2, xtd, gtd, gtt, grq, gwp, abuf, bbuf, cbuf, dbuf, ebuf, total;
+};
+
+SolidLayout solid_layout_for(const sox_plan& p, int entry, int vc) {
+  SolidLayout L{};
+  const size_t es = 2 * elem_size(p.precision);  // complex element
+  const size_t n = p.n, N = p.N, nt = p.n_tau, nk = p.nk, np2 = nk * nk;
+  Carver c;
+  L.ut1 = c.take(np2 * n * N * n * es);
+  L.ut2 = (entry == SOX_ENTRY_BARE) ? L.ut1 : c.take(np2 * n * N * n * es);
+  L.xtd = c.take(nk * N * n * 16);
+  L.gtd = c.take(nk * nt * n * n * 16);
+  L.gtt = c.take(nk * nt * n * n * es);
+  L.grq = c.take(nt * nk * N * n * es);
+  L.gwp = c.take(nt * nk * N * n * es);
+  L.abuf = c.take(np2 * (size_t)vc * N * n * es);
+  L.bbuf = c.take(np2 * (size_t)vc * N * N * es);
+  L.cbuf = c.take(np2 * (size_t)vc * N * N * es);
+  L.dbuf = c.take(nk * N * N * 16);
+  L.ebuf = c.take(nk * n * N * 16);
+  L.total = c.off;
+  return L;
+}
+
+size_t solid_workspace_bytes(const sox_plan& p, int entry) {
+  if (entry == SOX_ENTRY_DYNAMIC) return 0;
+  return solid_layout_for(p, entry, p.vcs).total;
+}
+
+// Largest v-slab width that keeps the statically screened entry's workspace
+// within the budget, then evened out over the slabs it implies.
+int pick_solid_vc(const sox_plan& p) {
+  const size_t budget = ws_budget();
+  int vc = p.n;
+  while (vc > 1 && solid_layout_for(p, SOX_ENTRY_STATIC, vc).total > budget) --vc;
+  const int slabs = (p.n + vc - 1) / vc;
+  return (p.n + slabs - 1) / slabs;
+}
+
+// Host momentum tables, uploaded once per plan: for pair = q * n_k + k,
+// k_of = k, q_of = q, kmq_of = index of k - q; kdiff[a][b] = index of k_a - k_b.
+std::vector<int> solid_tables(const int mesh[3]) {
+  const int m0 = mesh[0], m1 = mesh[1], m2 = mesh[2], nk = m0 * m1 * m2;
+  auto kd = [&](int a, int b) {
+    const int a0 = a / (m1 * m2), a1 = (a / m2) % m1, a2 = a % m2;
+    const int b0 = b / (m1 * m2), b1 = (b / m2) % m1, b2 = b % m2;
+    return (((a0 - b0 + m0) % m0) * m1 + ((a1 - b1 + m1) % m1)) * m2 + ((a2 - b2 + m2) % m2);
+  };
+  const int np2 = nk * nk;
+  std::vector<int> t(4 * (size_t)np2);
+  for (int q = 0; q < nk; ++q)
+    for (int k = 0; k < nk; ++k) {
+      const int pr = q * nk + k;
+      t[pr] = k;
+      t[np2 + pr] = q;
+      t[2 * np2 + pr] = kd(k, q);
+    }
+  for (int a = 0; a < nk; ++a)
+    for (int b = 0; b < nk; ++b) t[3 * (size_t)np2 + a * nk + b] = kd(a, b);
+  return t;
+}
+
+// Tile shapes of the complex product: 0 = 64 x 64 workgroup tile (2 x 2
+// wavefronts of 32 x 32), 1 = 16 x 256 (one row of four 16 x 64 wavefronts,
+// for the A step whose row count is the v-slab width).
+template <typename T, typename TC>
+sox_status cg_launch(const CgArgs<T, TC>& a, int nz, int shape, hipStream_t s) {
+  if (shape == 1) SOX_HIP((launch_cgemm<T, TC, 1, 4, 1, 4>(a, nz, s)));
+  else SOX_HIP((launch_cgemm<T, TC, 2, 2, 2, 2>(a, nz, s)));
+  return SOX_OK;
+}
+
+template <typename T>
+sox_status launch_dstep(const sox_plan& p, const T* B, const T* C, double* D, int nv, bool acc,
+                        hipStream_t s) {
+  const long NN = (long)p.N * p.N;
+  const long sp = (long)p.vcs * NN;
+  const double scale = 1.0 / p.nk;
+  const dim3 grid((unsigned)((NN + 255) / 256));
+  const int* m = p.mesh_canon;
+#define SOX_DSTEP(A_, B_, C_)                                                                 \
+  if (m[0] == A_ && m[1] == B_ && m[2] == C_) {                                              \
+    hipLaunchKernelGGL((dstep_mesh_kernel<T, A_, B_, C_>), grid, dim3(256), 0, s, B, C, D, NN, \
+                       sp, nv, scale, acc ? 1 : 0);                                           \
+    SOX_HIP(hipGetLastError());                                                               \
+    return SOX_OK;                                                                            \
+  }
+  SOX_DSTEP(2, 1, 1)
+  SOX_DSTEP(3, 1, 1)
+  SOX_DSTEP(2, 2, 1)
+  SOX_DSTEP(2, 3, 1)
+  SOX_DSTEP(3, 2, 1)
+  SOX_DSTEP(3, 3, 1)
+  SOX_DSTEP(2, 2, 2)
+  SOX_DSTEP(3, 3, 3)
+#undef SOX_DSTEP
+  const long tot = NN * p.nk;
+  hipLaunchKernelGGL((dstep_any_kernel<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                     B, C, p.d_ktab + 3 * (size_t)p.nk * p.nk, D, NN, p.nk, sp, nv, scale,
+                     acc ? 1 : 0);
+  SOX_HIP(hipGetLastError());
+  return SOX_OK;
+}
+
+template <typename TI, typename TO>
+sox_status launch_ctranspose(const TI* in, TO* out, int rows, int cols, long batch,
+                             hipStream_t s) {
+  if (batch <= 0 || rows <= 0 || cols <= 0) return SOX_OK;
+  if (batch > 65535) return fail(SOX_ERR_SHAPE, "internal: transpose batch too large");
+  dim3 grid((cols + 31) / 32, (rows + 31) / 32, (unsigned)batch);
+  hipLaunchKernelGGL((ctranspose_kernel<TI, TO>), grid, dim3(256), 0, s, in, out, rows, cols);
+  SOX_HIP(hipGetLastError());
+  return SOX_OK;
+}
+
+// The solid U-contraction into ut [pair][a][P][b] (float64 arithmetic).
+template <typename T>
+sox_status launch_solid_utensor(const sox_plan& p, const double* U, const double* X, T* ut,
+                                hipStream_t s) {
+  const int n = p.n, N = p.N, np2 = p.nk * p.nk;
+  const int* kOf = p.d_ktab;
+  const int* qOf = p.d_ktab + np2;
+  const int* kmqOf = p.d_ktab + 2 * np2;
+  CgArgs<double, T> a = cg_args<double, T>();
+  a.A = U; a.idxA = qOf; a.soA = (long)N * N; a.ldA = N;
+  a.B = X; a.idxB = kOf; a.soB = (long)n * N; a.ldB = N;
+  a.S = X; a.idxS = kmqOf; a.soS = (long)n * N; a.siS = N; a.conjS = 1;
+  a.C = ut; a.soC = (long)n * N * n; a.siC = (long)N * n; a.ldc = n;
+  a.nzi = n;
+  a.M = N; a.N = n; a.K = N;
+  return cg_launch(a, np2 * n, 0, s);
+}
+
+template <typename T>
+sox_status run_solid(sox_plan& p, int entry, const double* X, const double* U1, const double* U2,
+                     const double* G, double* Sigma, void* ws, hipStream_t s) {
+  const int n = p.n, N = p.N, nt = p.n_tau, nk = p.nk, np2 = nk * nk, vcs = p.vcs;
+  const SolidLayout L = solid_layout_for(p, entry, vcs);
+  char* base = (char*)ws;
+  T* ut1 = (T*)(base + L.ut1);
+  T* ut2 = (T*)(base + L.ut2);
+  double* xtd = (double*)(base + L.xtd);
+  double* gtd = (double*)(base + L.gtd);
+  T* gtt = (T*)(base + L.gtt);
+  T* grq = (T*)(base + L.grq);
+  T* gwp = (T*)(base + L.gwp);
+  T* abuf = (T*)(base + L.abuf);
+  T* bbuf = (T*)(base + L.bbuf);
+  T* cbuf = (T*)(base + L.cbuf);
+  double* dbuf = (double*)(base + L.dbuf);
+  double* ebuf = (double*)(base + L.ebuf);
+  const int* kOf = p.d_ktab;
+  const int* kqOf = p.d_ktab + 2 * np2;  // index of k_v - q1 for pair (q1, k_v)
+  sox_status st;
+  {
+    ProfScope ps(p, SOX_STAGE_UTENSOR, s);
+    if ((st = launch_solid_utensor<T>(p, U1, X, ut1, s))) return st;
+    if (entry != SOX_ENTRY_BARE && (st = launch_solid_utensor<T>(p, U2, X, ut2, s))) return st;
+  }
+  {
+    ProfScope ps(p, SOX_STAGE_PROJECT, s);
+    if ((st = launch_ctranspose<double, double>(X, xtd, n, N, nk, s))) return st;
+    for (long b0 = 0; b0 < (long)nk * nt; b0 += 65535) {
+      const long cnt = std::min(65535L, (long)nk * nt - b0);
+      if ((st = launch_ctranspose<double, double>(G + 2 * b0 * n * n, gtd + 2 * b0 * n * n, n, n,
+                                                  cnt, s)))
+        return st;
+    }
+    const long cnt = 2L * nk * nt * n * n;
+    hipLaunchKernelGGL((cast_kernel<T>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
+                       gtd, gtt, cnt);
+    SOX_HIP(hipGetLastError());
+    // GRq[tau][k][R][q] and GwPt[tau][k][P][w] for every node
+    CgArgs<double, T> a = cg_args<double, T>();
+    a.A = xtd; a.soA = (long)N * n; a.ldA = n;
+    a.B = gtd; a.soB = (long)nt * n * n; a.siB = (long)n * n; a.ldB = n;
+    a.C = grq; a.soC = (long)N * n; a.siC = (long)nk * N * n; a.ldc = n;
+    a.nzi = nt;
+    a.M = N; a.N = n; a.K = n;
+    if ((st = cg_launch(a, nk * nt, 0, s))) return st;
+    a.conjA = 1;
+    a.B = G;
+    a.C = gwp;
+    if ((st = cg_launch(a, nk * nt, 0, s))) return st;
+  }
+  for (int t = 0; t < nt; ++t) {
+    const int tm = nt - 1 - t;
+    for (int v0 = 0; v0 < n; v0 += vcs) {
+      const int cnt = std::min(vcs, n - v0);
+      {
+        ProfScope ps(p, SOX_STAGE_ASTEP, s);
+        CgArgs<T, T> a = cg_args<T, T>();
+        a.A = gtt + 2 * ((long)tm * n * n + (long)v0 * n);
+        a.idxA = kOf; a.soA = (long)nt * n * n; a.ldA = n;
+        a.B = ut1; a.soB = (long)n * N * n; a.splitB = n; a.hiB = n; a.ldB = (long)N * n;
+        a.C = abuf; a.soC = (long)vcs * N * n; a.ldc = (long)N * n;
+        a.M = cnt; a.N = N * n; a.K = n;
+        if ((st = cg_launch(a, np2, 1, s))) return st;
+      }
+      {
+        ProfScope ps(p, SOX_STAGE_KBC, s);
+        CgArgs<T, T> b = cg_args<T, T>();
+        b.A = abuf; b.soA = (long)vcs * N * n; b.siA = (long)N * n; b.ldA = n;
+        b.B = grq + 2 * (long)t * nk * N * n; b.idxB = kqOf; b.soB = (long)N * n; b.ldB = n;
+        b.C = bbuf; b.soC = (long)vcs * N * N; b.siC = (long)N * N; b.ldc = N;
+        b.nzi = cnt;
+        b.M = N; b.N = N; b.K = n;
+        if ((st = cg_launch(b, np2 * cnt, 0, s))) return st;
+        CgArgs<T, T> c = cg_args<T, T>();
+        c.A = gwp + 2 * (long)t * nk * N * n; c.idxA = kOf; c.soA = (long)N * n; c.ldA = n;
+        c.B = ut2 + 2 * (long)v0 * N * n; c.soB = (long)n * N * n; c.siB = (long)N * n; c.ldB = n;
+        c.C = cbuf; c.soC = (long)vcs * N * N; c.siC = (long)N * N; c.ldc = N;
+        c.nzi = cnt;
+        c.M = N; c.N = N; c.K = n;
+        if ((st = cg_launch(c, np2 * cnt, 0, s))) return st;
+      }
+      {
+        ProfScope ps(p, SOX_STAGE_KD, s);
+        if ((st = launch_dstep<T>(p, bbuf, cbuf, dbuf, cnt, v0 > 0, s))) return st;
+      }
+    }
+    {
+      ProfScope ps(p, SOX_STAGE_BACK, s);
+      CgArgs<double, double> e = cg_args<double, double>();
+      e.A = X; e.soA = (long)n * N; e.ldA = N; e.conjA = 1;
+      e.B = dbuf; e.soB = (long)N * N; e.ldB = N;
+      e.C = ebuf; e.soC = (long)n * N; e.ldc = N;
+      e.M = n; e.N = N; e.K = N;
+      if ((st = cg_launch(e, nk, 0, s))) return st;
+      CgArgs<double, double> f = cg_args<double, double>();
+      f.A = ebuf; f.soA = (long)n * N; f.ldA = N;
+      f.B = X; f.soB = (long)n * N; f.ldB = N;
+      f.C = Sigma + 2 * (long)t * n * n; f.soC = (long)nt * n * n; f.ldc = n;
+      f.alpha = -1.0 / nk;
+      f.M = n; f.N = n; f.K = N;
+      if ((st = cg_launch(f, nk, 0, s))) return st;
+    }
+  }
+  return SOX_OK;
+}
+
+// G^k(tau) = -Q_k diag(n(eps_k, tau)) Q_k^dagger for every k and node.
+sox_status solid_build_g(sox_plan& p, const double* Q, const double* eps, double mu, double* G,
+                         hipStream_t s) {
+  const int n = p.n, nt = p.n_tau, nk = p.nk;
+  double* occ = p.d_scratch;                    // [n_tau][n_k n]
+  double* occc = occ + (size_t)nt * nk * n;     // complex copy
+  const long tot = (long)nt * nk * n;
+  ProfScope ps(p, SOX_STAGE_GBUILD, s);
+  hipLaunchKernelGGL(occupation_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, eps,
+                     p.d_tau, mu, p.beta, nk * n, nt, occ);
+  SOX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(real_to_complex_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                     occ, occc, tot);
+  SOX_HIP(hipGetLastError());
+  CgArgs<double, double> a = cg_args<double, double>();
+  a.A = Q; a.soA = (long)n * n; a.ldA = n;
+  a.B = Q; a.soB = (long)n * n; a.ldB = n; a.conjB = 1;
+  a.S = occc; a.soS = n; a.siS = (long)nk * n;
+  a.C = G; a.soC = (long)nt * n * n; a.siC = (long)n * n; a.ldc = n;
+  a.nzi = nt;
+  a.alpha = -1.0;
+  a.M = n; a.N = n; a.K = n;
+  return cg_launch(a, nk * nt, 0, s);
+}
+
+sox_status solid_energy(sox_plan& p, const double* Sigma, const double* G, double* E_host,
+                        hipStream_t s) {
+  const int n = p.n, nt = p.n_tau, nk = p.nk;
+  double* tr = p.d_scratch + 3 * (size_t)nt * nk * n;
+  double* e = tr + (size_t)nt * nk;
+  {
+    ProfScope ps(p, SOX_STAGE_ENERGY, s);
+    hipLaunchKernelGGL(energy_trace_c_kernel, dim3(nt, nk), dim3(256), 0, s, Sigma, G, n, nt, tr);
+    SOX_HIP(hipGetLastError());
+    hipLaunchKernelGGL(energy_reduce_c_kernel, dim3(1), dim3(256), 0, s, tr, p.d_w, nt, nk, e);
+    SOX_HIP(hipGetLastError());
+  }
+  SOX_HIP(hipMemcpyAsync(E_host, e, sizeof(double), hipMemcpyDeviceToHost, s));
+  SOX_HIP(hipStreamSynchronize(s));
+  return SOX_OK;
+}

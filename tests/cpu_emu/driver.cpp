@@ -73,7 +73,50 @@ int run_case(int n, int N, int nt, int prec, int entry, bool vjp, bool dyn) {
   return st;
 }
 
+// k-point plans: complex128 buffers of their exact sizes; G is built on the
+// mesh, then the bare or static entry and the energy run.
+int run_solid_case(int n, int N, int nt, int prec, int entry, const int mesh[3]) {
+  const int nk = mesh[0] * mesh[1] * mesh[2];
+  std::vector<double> tau(nt), w(nt, 1.0);
+  const double beta = 5.0;
+  for (int k = 0; k < nt; ++k) tau[k] = beta * (k + 0.5) / nt;
+  sox_problem pr{};
+  pr.n_orb = n; pr.n_thc = N; pr.n_tau = nt;
+  for (int i = 0; i < 3; ++i) pr.kmesh[i] = mesh[i];
+  pr.beta = beta; pr.tau = tau.data(); pr.weights = w.data();
+  sox_plan* plan = nullptr;
+  if (sox_plan_create(&pr, prec, &plan)) { printf("create failed: %s\n", sox_last_error()); return 1; }
+  size_t wsb = 0;
+  sox_workspace_size(plan, entry, &wsb);
+  g_ws_size = wsb + 4096;
+  g_ws_base = (char*)aligned_alloc(256, (g_ws_size + 255) & ~size_t(255));
+  double* X = dalloc(2 * (size_t)nk * n * N);
+  double* U1 = dalloc(2 * (size_t)nk * N * N);
+  double* U2 = dalloc(2 * (size_t)nk * N * N);
+  double* Q = dalloc(2 * (size_t)nk * n * n);
+  double* eps = dalloc((size_t)nk * n, 3.0);
+  double* G = dalloc(2 * (size_t)nk * nt * n * n);
+  double* S = dalloc(2 * (size_t)nk * nt * n * n);
+  sox_status st = sox_build_g_tau(plan, Q, eps, 0.0, G, nullptr);
+  if (!st) {
+    if (entry == 0) st = sox_sigma_bare(plan, X, U1, G, S, g_ws_base, wsb, nullptr);
+    else st = sox_sigma_static(plan, X, U1, U2, G, S, g_ws_base, wsb, nullptr);
+  }
+  double E = 0.0;
+  if (!st) st = sox_energy_gm(plan, S, G, &E, nullptr);
+  printf("case n=%d N=%d nt=%d prec=%d entry=%d mesh=%dx%dx%d -> status %d %s\n", n, N, nt, prec,
+         entry, mesh[0], mesh[1], mesh[2], st, st ? sox_last_error() : "");
+  ASAN_UNPOISON_MEMORY_REGION(g_ws_base, g_ws_size);
+  g_ws_base = nullptr;
+  sox_plan_destroy(plan);
+  return st;
+}
+
 int main(int argc, char** argv) {
   int n = atoi(argv[1]), N = atoi(argv[2]), nt = atoi(argv[3]), prec = atoi(argv[4]), entry = atoi(argv[5]), vjp = atoi(argv[6]);
+  if (argc >= 10) {
+    const int mesh[3] = {atoi(argv[7]), atoi(argv[8]), atoi(argv[9])};
+    return run_solid_case(n, N, nt, prec, entry, mesh);
+  }
   return run_case(n, N, nt, prec, entry, vjp, entry == 2);
 }

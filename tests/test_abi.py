@@ -35,7 +35,7 @@ def test_library_exports_every_declared_symbol():
     for name in declared_functions():
         assert hasattr(lib, name), name
     assert set(binding.EXPORTED) == set(declared_functions())
-    assert binding.sox_abi_version() == 1
+    assert binding.sox_abi_version() == 2
 
 
 def _problem(n=4, N=8, tau=None, beta=5.0, kmesh=(1, 1, 1)):
@@ -71,8 +71,12 @@ def test_plan_create_rejects_bad_problems_before_device_work():
     assert b"mirror" in lib.sox_last_error()
     pr, keep = _problem(tau=np.array([1.0, 0.5, 4.0, 4.5]), beta=5.5)
     assert _create(pr)[0] == 3                      # GRID: not ascending
+    pr, keep = _problem(kmesh=(3, 0, 3))
+    assert _create(pr)[0] == 2                      # SHAPE: mesh entry < 1
+    pr, keep = _problem(kmesh=(17, 1, 1))
+    assert _create(pr)[0] == 2                      # SHAPE: mesh beyond the supported range
     pr, keep = _problem(kmesh=(3, 3, 3))
-    assert _create(pr)[0] == 7                      # UNSUPPORTED by this library version
+    assert _create(pr, precision=2)[0] == 7         # UNSUPPORTED: bf16x3 on a k-point mesh
     pr, keep = _problem()
     assert _create(pr, precision=9)[0] == 1         # unknown precision
     h = ctypes.c_void_p()

@@ -58,6 +58,32 @@ CASES = [
 ]
 
 
+# k-point meshes: n, N, n_tau, precision, entry, mesh, env budget (the
+# templated D step for 2x1x1, 1x3x1 (canonicalised), 2x2x2, 3x3x3; the any-mesh
+# D step for 4x1x1; several v slabs under a small budget)
+SOLID_CASES = [
+    (5, 20, 3, 0, 0, (2, 1, 1), None),
+    (7, 33, 2, 1, 1, (1, 3, 1), None),
+    (6, 18, 2, 1, 0, (2, 2, 2), None),
+    (3, 10, 2, 1, 0, (3, 3, 3), None),
+    (5, 17, 2, 0, 1, (4, 1, 1), None),
+    (9, 40, 2, 1, 1, (3, 1, 1), "1"),
+]
+
+
+@pytest.mark.parametrize("case", SOLID_CASES, ids=lambda c: "-".join(str(x) for x in c))
+def test_solid_entry_in_bounds(emu, case):
+    n, N, nt, prec, entry, mesh, budget = case
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    if budget:
+        env["SOX_WS_BUDGET_MB"] = budget
+    r = subprocess.run([emu, str(n), str(N), str(nt), str(prec), str(entry), "0",
+                        *[str(m) for m in mesh]],
+                       capture_output=True, text=True, env=env, timeout=600)
+    out = r.stdout + r.stderr
+    assert r.returncode == 0 and "status 0" in out and "AddressSanitizer" not in out, out[-4000:]
+
+
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "-".join(str(x) for x in c))
 def test_entry_point_in_bounds(emu, case):
     n, N, nt, prec, entry, vjp, budget = case

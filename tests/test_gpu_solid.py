@@ -1,0 +1,212 @@
+"""GPU parity of the k-point (solid) SOX path against the complex128 oracle,
+through the C ABI.
+
+Small meshes (every momentum table exercised, including the full 3x3x3 mesh
+and the any-mesh D step on 4x1x1) are compared element by element with the
+oracle's step chain; ragged n and N span several tiles.  At the full
+3x3x3, n = 52, N = 400, 100-node shape the oracle cannot run in seconds, so
+the launch configuration of the benchmark is checked by properties that hold
+at any size: momentum-independent real inputs must reproduce the molecular
+oracle (at sampled tau nodes), and with U1 = U2 and Hermitian G^k every
+Sigma^k(tau) must be Hermitian.
+
+Tolerances (max |diff| / max |oracle|): fp64 1e-12, fp32 1e-6.
+"""
+import numpy as np
+import pytest
+
+from oracle import sox_mol as om
+from oracle import sox_solid as osd
+from paper_2412_18829_amd import synth
+from tests.gpu_util import have_gpu, log, rel_err
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp64": 1e-12, "fp32": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not have_gpu():
+        pytest.skip("no GPU")
+    from paper_2412_18829_amd import binding
+    binding.load()
+    return binding
+
+
+def cdev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.complex128, device="cuda")
+
+
+def rdev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda")
+
+
+def chost(t):
+    return t.detach().cpu().numpy()
+
+
+def _plan(B, wl, precision):
+    return B.Plan(wl["n"], wl["N"], wl["tau"], wl["weights"], wl["beta"], precision=precision,
+                  kmesh=wl["mesh"])
+
+
+def _tables(wl):
+    return (wl["kvecs"], wl["kdiff"], wl["ksum"], wl["kneg"])
+
+
+def _general_G(wl, seed):
+    rng = np.random.default_rng(seed)
+    G = osd.g_tau_k(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    return G + 0.05 * (rng.standard_normal(G.shape) + 1j * rng.standard_normal(G.shape))
+
+
+def test_g_build_matches_oracle(B):
+    import torch
+    wl = synth.solid((2, 2, 1), 7, 20, 6, 20.0, seed=11)
+    log("solid g build 2x2x1")
+    plan = _plan(B, wl, "fp64")
+    G = torch.empty((wl["nk"], wl["n_tau"], wl["n"], wl["n"]), dtype=torch.complex128, device="cuda")
+    B.sox_build_g_tau(plan, cdev(wl["Q"]), rdev(wl["eps"]), 0.0, G)
+    ref = osd.g_tau_k(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    assert np.abs(chost(G) - ref).max() <= 1e-14
+
+
+SHAPES = [
+    ((2, 1, 1), 5, 20, 4),
+    ((3, 1, 1), 13, 50, 3),
+    ((2, 2, 1), 17, 70, 2),
+    ((1, 3, 3), 4, 18, 2),
+    ((2, 2, 2), 6, 33, 2),
+    ((3, 3, 3), 6, 24, 2),
+    ((4, 1, 1), 5, 30, 2),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s[0])) + f"-{s[1]}-{s[2]}")
+def test_bare_vs_oracle(B, precision, shape):
+    import torch
+    mesh, n, N, nt = shape
+    log(f"solid bare {shape} {precision}")
+    wl = synth.solid(mesh, n, N, nt, 10.0, seed=n + N)
+    G = _general_G(wl, n)
+    plan = _plan(B, wl, precision)
+    S = torch.empty(G.shape, dtype=torch.complex128, device="cuda")
+    B.sox_sigma_bare(plan, cdev(wl["X"]), cdev(wl["V"]), cdev(G), S)
+    torch.cuda.synchronize()
+    ref = osd.sigma_solid_thc(wl["X"], wl["V"], wl["V"], G, _tables(wl))
+    err = rel_err(chost(S), ref)
+    log(f"  rel err {err:.3e}")
+    assert err <= TOL[precision]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", [((3, 1, 1), 9, 41, 3), ((3, 3, 3), 5, 20, 2)],
+                         ids=lambda s: "x".join(map(str, s[0])))
+def test_static_vs_oracle(B, precision, shape):
+    """U1 != U2 (a second momentum-paired interaction on line 1)."""
+    import torch
+    mesh, n, N, nt = shape
+    log(f"solid static {shape} {precision}")
+    wl = synth.solid(mesh, n, N, nt, 10.0, seed=3 * n)
+    rng = np.random.default_rng(n)
+    W0 = synth.paired_hermitian(rng, wl["kneg"], N, 1.0 / N)
+    G = _general_G(wl, n + 1)
+    plan = _plan(B, wl, precision)
+    S = torch.empty(G.shape, dtype=torch.complex128, device="cuda")
+    B.sox_sigma_static(plan, cdev(wl["X"]), cdev(W0), cdev(wl["V"]), cdev(G), S)
+    torch.cuda.synchronize()
+    ref = osd.sigma_solid_thc(wl["X"], W0, wl["V"], G, _tables(wl))
+    err = rel_err(chost(S), ref)
+    log(f"  rel err {err:.3e}")
+    assert err <= TOL[precision]
+
+
+def test_energy_and_v_slabs(B, monkeypatch):
+    """GM energy per cell against the oracle; a workspace budget that forces
+    several v slabs gives the same Sigma."""
+    import torch
+    wl = synth.solid((3, 1, 1), 11, 48, 4, 10.0, seed=21)
+    log("solid energy + v slabs")
+    plan1 = _plan(B, wl, "fp64")
+    monkeypatch.setenv("SOX_WS_BUDGET_MB", "2")
+    plan2 = _plan(B, wl, "fp64")
+    monkeypatch.delenv("SOX_WS_BUDGET_MB")
+    d1, d2 = B.sox_plan_describe(plan1), B.sox_plan_describe(plan2)
+    assert d2["solid_v_slab"] < d1["solid_v_slab"] == wl["n"]
+    G = torch.empty((wl["nk"], wl["n_tau"], wl["n"], wl["n"]), dtype=torch.complex128, device="cuda")
+    B.sox_build_g_tau(plan1, cdev(wl["Q"]), rdev(wl["eps"]), 0.0, G)
+    X, V = cdev(wl["X"]), cdev(wl["V"])
+    S1 = torch.empty_like(G)
+    S2 = torch.empty_like(G)
+    B.sox_sigma_bare(plan1, X, V, G, S1)
+    B.sox_sigma_bare(plan2, X, V, G, S2)
+    torch.cuda.synchronize()
+    assert rel_err(chost(S2), chost(S1)) <= 1e-14
+    Gr = osd.g_tau_k(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    ref = osd.sigma_solid_thc(wl["X"], wl["V"], wl["V"], Gr, _tables(wl))
+    assert rel_err(chost(S1), ref) <= 1e-12
+    e = B.sox_energy_gm(plan1, S1, G)
+    e_ref = osd.energy_gm_k(ref, Gr, wl["weights"])
+    assert abs(e - e_ref) <= 1e-11 * abs(e_ref)
+
+
+def test_unsupported_requests(B):
+    wl = synth.solid((2, 1, 1), 4, 10, 2, 5.0, seed=1)
+    with pytest.raises(B.SoxError) as ei:
+        _plan(B, wl, "bf16x3")
+    assert ei.value.status == 7
+
+
+# ---------------------------------------------------------------------------
+# the full 3x3x3, n = 52, N = 400, 100-node shape (the benchmarked launch
+# configuration), checked by properties
+C5 = dict(mesh=(3, 3, 3), n=52, N=400, n_tau=100, beta=100.0)
+
+
+def test_full_size_k_independent_reduces_to_molecule(B):
+    """X^k = X, U^q = V, G^k = G (real) for every momentum: Sigma^k must equal
+    the molecular SOX self-energy; the molecular oracle is evaluated at
+    sampled tau nodes (Sigma(tau_j) needs only G(tau_j) and G(beta - tau_j))."""
+    import torch
+    n, N, nt, mesh = C5["n"], C5["N"], C5["n_tau"], C5["mesh"]
+    nk = int(np.prod(mesh))
+    log("solid full size k-independent fp32")
+    mol = synth.molecule(n, N, nt, C5["beta"], rng=synth.rng_for(55))
+    Gm = om.g_tau(mol["eps"], mol["Q"], mol["mu"], mol["beta"], mol["tau"])
+    rep = lambda a: np.repeat(a[None], nk, axis=0)
+    plan = B.Plan(n, N, mol["tau"], mol["weights"], mol["beta"], precision="fp32", kmesh=mesh)
+    S = torch.empty((nk, nt, n, n), dtype=torch.complex128, device="cuda")
+    B.sox_sigma_bare(plan, cdev(rep(mol["X"])), cdev(rep(mol["V"])), cdev(rep(Gm)), S)
+    torch.cuda.synchronize()
+    Sh = chost(S)
+    assert np.abs(Sh.imag).max() <= 1e-6 * np.abs(Sh.real).max()
+    for j in (0, 1, 37, 50, 99):
+        ref = om.sigma_static_thc(mol["X"], mol["V"], mol["V"], Gm[[j]], Gm[[nt - 1 - j]])[0]
+        err = np.abs(Sh[:, j] - ref[None]).max() / np.abs(ref).max()
+        log(f"  tau node {j}: rel err {err:.3e}")
+        assert err <= TOL["fp32"]
+
+
+def test_full_size_hermitian(B):
+    """The 3x3x3 solid recipe itself (U1 = U2 paired Hermitian, Hermitian
+    G^k from a Hermitian Fock matrix): Sigma^k(tau) is Hermitian and the GM
+    energy is finite."""
+    import torch
+    wl = synth.workload(5)
+    n, N, nt, nk = wl["n"], wl["N"], wl["n_tau"], wl["nk"]
+    log("solid full size hermiticity fp32")
+    plan = _plan(B, wl, "fp32")
+    G = torch.empty((nk, nt, n, n), dtype=torch.complex128, device="cuda")
+    B.sox_build_g_tau(plan, cdev(wl["Q"]), rdev(wl["eps"]), wl["mu"], G)
+    S = torch.empty_like(G)
+    B.sox_sigma_bare(plan, cdev(wl["X"]), cdev(wl["V"]), G, S)
+    e = B.sox_energy_gm(plan, S, G)
+    Sh = chost(S)
+    herm = np.abs(Sh - np.conj(np.swapaxes(Sh, 2, 3))).max() / np.abs(Sh).max()
+    log(f"  hermiticity defect {herm:.3e}, energy {e:.6e}")
+    assert herm <= TOL["fp32"]
+    assert np.isfinite(e)
