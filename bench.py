@@ -3,16 +3,20 @@
 
 One step = one pass of the whole path over the workload: G(tau) synthesis
 from the Fock eigenbasis, the U-contraction, the half projections, the A
-step, the fused B, C -> D contraction, the back-transform to orbitals (all
-tau nodes: one "sweep") and the Galitskii-Migdal energy.  Inputs are seeded
-and synthetic (bare interaction, molecule n=64, N=384, 64 tau nodes,
-beta=50) and resident in HBM before the timed region.
+step (or, for the dynamic interaction, GG -> FT -> W(Omega) GG(Omega) -> IFT),
+the B, C -> D contraction, the back-transform to orbitals (all tau nodes and
+momenta: one "sweep") and the Galitskii-Migdal energy.  Inputs are seeded and
+synthetic and resident in HBM before the timed region.  The default workload
+is the bare molecule n=64, N=384, 64 tau nodes, beta=50; --workload selects
+the others (3: static screening n=200 N=1200; 4: dynamic screening n=300
+N=1800; 5: 3x3x3 k-point solid n=52 N=400).
 
 Prints ONE JSON line.  `value` is sweeps/s of the chosen precision path
 (float32 MFMA contractions by default); the float64 path is timed on the
 same inputs for the mixed-vs-FP64 comparison, the FP64 CPU oracle is timed
-on the host as a baseline, and the dominant kernel's roofline fraction is
-measured with HIP events on the stream it runs on.
+on the host as a baseline where a bounded sample of it fits, and the
+dominant kernel's roofline fraction is measured with HIP events on the
+stream it runs on.
 """
 from __future__ import annotations
 
@@ -31,22 +35,54 @@ PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2516.6}
 DTYPE_NAME = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
 METRIC = "SOX Sigma(all tau) sweeps/sec + TFLOP/s vs MFMA peak; mixed vs FP64 path at stated err"
 WORKLOADS = {
-    1: "molecule bare SOX n=8 N=24 n_tau=16 beta=10",
-    2: "molecule bare SOX n=64 N=384 n_tau=64 beta=50",
+    1: ("molecule bare SOX n=8 N=24 n_tau=16 beta=10", "bare"),
+    2: ("molecule bare SOX n=64 N=384 n_tau=64 beta=50", "bare"),
+    3: ("molecule static SOX n=200 N=1200 n_tau=100 beta=100, W0 = V + V Pi V", "static"),
+    4: ("molecule dynamic SOX n=300 N=1800 n_tau=120 beta=100, 8-pole W(tau)", "dynamic"),
+    5: ("solid bare SOX 3x3x3 k-mesh n=52 N=400 n_tau=100 beta=100", "solid"),
 }
+ENTRY = {"bare": "sox_sigma_bare", "static": "sox_sigma_static", "dynamic": "sox_sigma_dynamic",
+         "solid": "sox_sigma_bare"}
+# dominant kernel per kind: (profiling stage, kernel name)
+DOMINANT = {"bare": ("fused", "fused_bcd_kernel"), "static": ("fused", "fused_bcd_kernel"),
+            "dynamic": ("fused", "fused_bcd_kernel"), "solid": ("kbc", "cgemm_nt_kernel")}
 
 
-def flops_per_sweep(n: int, N: int, nt: int) -> dict:
-    """Algorithmic FLOPs of one bare sweep, by stage (the paper's step costs)."""
-    return {
+def flops_per_sweep(n: int, N: int, nt: int, kind: str = "bare", n_omega: int = 0,
+                    nk: int = 1) -> dict:
+    """Algorithmic FLOPs of one sweep, by stage (the paper's step costs).
+
+    Complex products count 8 real FLOPs per multiply-add.  The U-contraction
+    is reported but excluded from the sweep total by the caller (it is set up
+    once per X and U)."""
+    if kind == "solid":
+        np2 = nk * nk
+        return {
+            "gbuild": nk * nt * 8.0 * n ** 3,
+            "utensor": np2 * 8.0 * N * N * n * n,
+            "project": nt * nk * 2 * 8.0 * N * n * n,
+            "astep": nt * np2 * 8.0 * N * n ** 3,
+            "kbc": nt * np2 * 2 * 8.0 * N * N * n * n,
+            "kd": nt * nk ** 3 * 8.0 * N * N * n,
+            "back": nt * nk * 8.0 * (N * N * n + N * n * n),
+            "energy": nk * nt * 8.0 * n * n,
+        }
+    f = {
         "gbuild": nt * 2.0 * n ** 3,
-        "utensor": 2.0 * N * N * n * n,
+        "utensor": (2 if kind == "static" else 1) * 2.0 * N * N * n * n,
         "project": nt * 4.0 * N * n * n,
-        "astep": nt * 2.0 * N * n ** 3,
         "fused": nt * (4.0 * N * N * n * n + 2.0 * N * N * n),
         "back": nt * (2.0 * N * N * n + 2.0 * N * n * n),
         "energy": nt * 2.0 * n * n,
     }
+    if kind == "dynamic":
+        f["utensor"] = 2.0 * N * N * n * n
+        f["gg_ft"] = nt * N * n * n + 4.0 * n_omega * nt * N * n * n
+        f["wgemm"] = n_omega * 8.0 * N * N * n * n
+        f["ift"] = 4.0 * n_omega * nt * N * n * n
+    else:
+        f["astep"] = nt * 2.0 * N * n ** 3
+    return f
 
 
 def kernel_source_hash() -> str:
@@ -85,12 +121,52 @@ def blas_threads() -> int:
         return len(os.sched_getaffinity(0))
 
 
+def cpu_oracle_baseline(wl: dict, kind: str, budget_s: float):
+    """Time the FP64 oracle on the host.  Bare molecules: whole sweeps (G(tau)
+    synthesis + THC chain) until the budget is spent.  Static molecules:
+    single tau nodes (Sigma(tau_j) needs only G(tau_j) and G(beta - tau_j);
+    every call redoes the U-contraction), scaled to sweeps/s.  Dynamic
+    molecules and solids: not run (one oracle sweep needs the whole GG(tau)
+    array on the host, or minutes per tau node)."""
+    from oracle import sox_mol as om
+    nt = wl["n_tau"]
+    if kind == "bare":
+        sweeps = 0
+        c0 = time.perf_counter()
+        while True:
+            Gr = om.g_tau(wl["eps"], wl["Q"], wl["mu"], wl["beta"], wl["tau"])
+            om.sigma_static_thc(wl["X"], wl["V"], wl["V"], Gr, om.g_mirror(Gr))
+            sweeps += 1
+            if time.perf_counter() - c0 >= budget_s:
+                break
+        sec = time.perf_counter() - c0
+        return {"value": sweeps / sec, "unit": "sweeps/s", "cores": blas_threads(), "kind": "oracle",
+                "sample": f"{sweeps} full sweep(s) ({nt} tau nodes) of the FP64 numpy THC route "
+                          "(G(tau) synthesis + static SOX chain), same workload and seed"}
+    if kind == "static":
+        Gr = om.g_tau(wl["eps"], wl["Q"], wl["mu"], wl["beta"], wl["tau"])
+        nodes = 0
+        c0 = time.perf_counter()
+        while nodes < nt:
+            j = nodes
+            om.sigma_static_thc(wl["X"], wl["W0"], wl["V"], Gr[[j]], Gr[[nt - 1 - j]])
+            nodes += 1
+            if time.perf_counter() - c0 >= budget_s:
+                break
+        sec = time.perf_counter() - c0
+        return {"value": nodes / nt / sec, "unit": "sweeps/s", "cores": blas_threads(),
+                "kind": "oracle",
+                "sample": f"{nodes} of {nt} tau nodes of the FP64 numpy THC route (U-contraction "
+                          "redone per node), scaled to whole sweeps; same workload and seed"}
+    return None
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--workload", type=int, default=2, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
@@ -105,6 +181,10 @@ def main() -> int:
               "(the multi-GPU sharding is described in the design notes, not built)",
               file=sys.stderr)
         return 2
+    desc, kind = WORKLOADS[args.workload]
+    if args.precision == "bf16x3" and kind not in ("bare", "static"):
+        print(f"bench.py: bf16x3 runs the bare and static molecular entries only", file=sys.stderr)
+        return 2
 
     import numpy as np
     import torch
@@ -116,8 +196,18 @@ def main() -> int:
     torch.cuda.set_device(dev)
     wl = synth.workload(args.workload)
     n, N, nt = wl["n"], wl["N"], wl["n_tau"]
-    t = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
-    X, V, Q, eps = t(wl["X"]), t(wl["V"]), t(wl["Q"]), t(wl["eps"])
+    solid = kind == "solid"
+    nk = wl.get("nk", 1)
+    cdt = torch.complex128 if solid else torch.float64
+    t = lambda a, dt=cdt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
+    X, V, Q = t(wl["X"]), t(wl["V"]), t(wl["Q"])
+    eps = t(wl["eps"], torch.float64)
+    U1 = t(wl["W0"]) if kind == "static" else (t(wl["W_tau"]) if kind == "dynamic" else V)
+    tp = None
+    if kind == "dynamic":
+        tp = synth.bosonic_transform_pair(wl["tau"], wl["beta"], omega_max=14.0, tol=1e-10)
+    n_omega = len(tp["m"]) if tp is not None else 0
+    gshape = (nk, nt, n, n) if solid else (nt, n, n)
 
     if args.copy_probe_mib > 0:
         nbytes = args.copy_probe_mib * 1048576
@@ -128,15 +218,25 @@ def main() -> int:
         del a, b
 
     def run(precision: str, steps: int, warmup: int, profile: bool):
-        plan = B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision=precision)
-        G = torch.empty((nt, n, n), dtype=torch.float64, device=dev)
+        extra = {}
+        if tp is not None:
+            extra = dict(t_fwd=tp["T_fwd"], t_bwd=tp["T_bwd"])
+        plan = B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision=precision,
+                      kmesh=wl.get("mesh", (1, 1, 1)), **extra)
+        G = torch.empty(gshape, dtype=cdt, device=dev)
         S = torch.empty_like(G)
-        ws = plan.workspace("bare")
+        entry = "static" if kind == "static" else ("dynamic" if kind == "dynamic" else "bare")
+        ws = plan.workspace(entry)
         energies = []
 
         def step():
             B.sox_build_g_tau(plan, Q, eps, wl["mu"], G)
-            B.sox_sigma_bare(plan, X, V, G, S, ws=ws)
+            if kind == "static":
+                B.sox_sigma_static(plan, X, U1, V, G, S, ws=ws)
+            elif kind == "dynamic":
+                B.sox_sigma_dynamic(plan, X, U1, V, G, S, ws=ws)
+            else:
+                B.sox_sigma_bare(plan, X, V, G, S, ws=ws)
             energies.append(B.sox_energy_gm(plan, S, G))
 
         for _ in range(warmup):
@@ -153,46 +253,42 @@ def main() -> int:
         prof = B.sox_profile_read(plan, reset=True) if profile else None
         if profile:
             B.sox_profile_enable(plan, False)
-        return dict(seconds=t1 - t0, Sigma=S.cpu().numpy(), G=G.cpu().numpy(), prof=prof,
-                    energy=energies[-1], plan_slab=None)
+        return dict(seconds=t1 - t0, Sigma=S.cpu().numpy(), prof=prof, energy=energies[-1],
+                    plan=B.sox_plan_describe(plan))
 
     main_run = run(args.precision, args.steps, args.warmup, profile=True)
     sec = main_run["seconds"]
     ms_per_step = 1e3 * sec / args.steps
     value = args.steps / sec
 
-    fl = flops_per_sweep(n, N, nt)
-    total_flops = sum(fl.values())
+    fl = flops_per_sweep(n, N, nt, kind, n_omega, nk)
+    sweep_flops = sum(v for k, v in fl.items() if k != "utensor")
     prof = main_run["prof"]
-    fused_ms, fused_launches = prof["fused"]
-    fused_avg_ms = fused_ms / max(fused_launches, 1)
-    fused_flops_per_launch = fl["fused"] * args.steps / max(fused_launches, 1)
-    achieved = fused_flops_per_launch / (fused_avg_ms * 1e-3) / 1e12
+    stage, kname = DOMINANT[kind]
+    if args.precision == "bf16x3":
+        kname = "fused_bcd_bf16x3_kernel"
+    dom_ms, dom_launches = prof[stage]
+    dom_avg_ms = dom_ms / max(dom_launches, 1)
+    dom_flops_per_launch = fl[stage] * args.steps / max(dom_launches, 1)
+    achieved = dom_flops_per_launch / (dom_avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     stage_ms = {k: round(v[0] / args.steps, 4) for k, v in prof.items()
                 if k != "dropped" and v[1] > 0}
 
-    # FP64 oracle on the host: the error reference and the CPU baseline
+    # FP64 oracle on the host: the error reference (bare molecules) and the CPU baseline
     from oracle import sox_mol as om
     out = {}
     ref = None
-    if not args.no_cpu_baseline:
+    if kind == "bare" and not solid and args.workload <= 2:
         Gr = om.g_tau(wl["eps"], wl["Q"], wl["mu"], wl["beta"], wl["tau"])
-        sweeps = 0
-        c0 = time.perf_counter()
-        while True:
-            Gr = om.g_tau(wl["eps"], wl["Q"], wl["mu"], wl["beta"], wl["tau"])
-            ref = om.sigma_static_thc(wl["X"], wl["V"], wl["V"], Gr, om.g_mirror(Gr))
-            sweeps += 1
-            if time.perf_counter() - c0 >= args.cpu_seconds:
-                break
-        c1 = time.perf_counter()
-        out["cpu_baseline"] = {
-            "value": sweeps / (c1 - c0), "unit": "sweeps/s", "cores": blas_threads(),
-            "kind": "oracle",
-            "sample": f"{sweeps} full sweep(s) ({nt} tau nodes) of the FP64 numpy THC route "
-                      "(G(tau) synthesis + static SOX chain), same workload and seed",
-        }
+        ref = om.sigma_static_thc(wl["X"], wl["V"], wl["V"], Gr, om.g_mirror(Gr))
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_oracle_baseline(wl, kind, args.cpu_seconds)
+    out["cpu_baseline"] = cpu
+    if cpu is None:
+        out["cpu_baseline_note"] = ("not run: " + ("disabled by flag" if args.no_cpu_baseline else
+                                    "no bounded oracle sample fits this workload on the host"))
 
     def err_of(S):
         if ref is None:
@@ -201,13 +297,16 @@ def main() -> int:
 
     main_err = err_of(main_run["Sigma"])
     if not args.no_fp64_compare and args.precision != "fp64":
-        r64 = run("fp64", max(3, args.steps // 2), 2, profile=False)
-        s64 = r64["seconds"] / max(3, args.steps // 2)
+        k64 = max(1, args.steps // 2)
+        r64 = run("fp64", k64, 1, profile=False)
+        s64 = r64["seconds"] / k64
+        d = np.abs(main_run["Sigma"] - r64["Sigma"]).max() / np.abs(r64["Sigma"]).max()
         out["fp64_path"] = {"sweeps_per_s": 1.0 / s64, "ms_per_step": 1e3 * s64,
-                            "max_rel_err": err_of(r64["Sigma"])}
-        tol = 1e-6
-        out["mixed_beats_fp64"] = bool(value > 1.0 / s64 and main_err is not None
-                                       and main_err <= tol)
+                            "max_rel_err": err_of(r64["Sigma"]),
+                            "max_rel_diff_to_main": float(d)}
+        tol = 1e-6 if args.precision == "fp32" else 1e-4
+        acc = main_err if main_err is not None else float(d)
+        out["mixed_beats_fp64"] = bool(value > 1.0 / s64 and acc <= tol)
 
     rec = {
         "metric": METRIC,
@@ -220,24 +319,24 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": DTYPE_NAME[args.precision],
+        "dtype": DTYPE_NAME[args.precision] if not solid else "c" + DTYPE_NAME[args.precision],
         "data": "synthetic",
-        "config": {"workload": WORKLOADS[args.workload], "entry": "sox_sigma_bare",
-                   "n_orb": n, "n_thc": N, "n_tau": nt, "beta": wl["beta"],
-                   "precision": args.precision, "step": "G(tau) + Sigma(all tau) + E_GM"},
-        "tflops_alg": total_flops / (ms_per_step * 1e-3) / 1e12,
+        "config": {"workload": desc, "entry": ENTRY[kind], "n_orb": n, "n_thc": N, "n_tau": nt,
+                   "beta": wl["beta"], "kmesh": list(wl.get("mesh", (1, 1, 1))),
+                   "n_omega": n_omega, "precision": args.precision,
+                   "step": "G(tau) + Sigma(all tau" + (", all k" if solid else "") + ") + E_GM"},
+        "tflops_alg": sweep_flops / (ms_per_step * 1e-3) / 1e12,
         "max_rel_err": main_err,
         "roofline": {
-            "kernel": "fused_bcd_kernel", "bound": "mfma", "achieved": achieved, "peak": peak,
+            "kernel": kname, "bound": "mfma", "achieved": achieved, "peak": peak,
             "unit": "TFLOP/s", "frac": achieved / peak,
             "traffic": read_traffic(args.workload, args.precision),
-            "avg_launch_ms": fused_avg_ms, "flops_per_launch": fused_flops_per_launch,
+            "avg_launch_ms": dom_avg_ms, "flops_per_launch": dom_flops_per_launch,
         },
         "stage_ms_per_step": stage_ms,
+        "plan": main_run["plan"],
     }
     rec.update(out)
-    if "cpu_baseline" not in rec:
-        rec["cpu_baseline"] = None
     print(json.dumps(rec), flush=True)
     return 0
 

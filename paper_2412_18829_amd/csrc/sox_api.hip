@@ -91,7 +91,8 @@ struct sox_plan {
   int kmesh[3] = {1, 1, 1};
   int mesh_canon[3] = {1, 1, 1};
   int nk = 1;
-  int vcs = 0;
+  int vcs = 0;       // statically screened entry
+  int vcs_bare = 0;  // bare entry (one U-tensor: wider slabs fit)
   int* d_ktab = nullptr;
   // device copies
   double* d_tf2 = nullptr;  // [2 n_omega][n_tau]  Re / Im of t_fwd
@@ -1371,7 +1372,8 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
   }
   if (p->nk > 1) {
     p->slab = p->vjp_slab = 1;
-    p->vcs = pick_solid_vc(*p);
+    p->vcs = pick_solid_vc(*p, SOX_ENTRY_STATIC);
+    p->vcs_bare = pick_solid_vc(*p, SOX_ENTRY_BARE);
   } else {
     p->slab = pick_slab(*p, SOX_ENTRY_STATIC);
     p->vjp_slab = pick_vjp_slab(*p, SOX_ENTRY_STATIC);
@@ -1404,7 +1406,8 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
   if (e == hipSuccess) {
     // molecules: occupations [n_tau][n], traces [n_tau], energy; k-points:
     // occupations, their complex copy [n_tau][n_k n], traces [n_k][n_tau], energy
-    const size_t nsc = p->nk > 1 ? 3 * (size_t)nt * p->nk * p->n + (size_t)nt * p->nk + 1
+    const size_t nocc = (size_t)nt * p->nk * p->n;
+    const size_t nsc = p->nk > 1 ? round_up(nocc, 2) + 2 * nocc + (size_t)nt * p->nk + 1
                                  : (size_t)nt * (p->n + 1) + 1;
     e = hipMalloc(&p->d_scratch, sizeof(double) * nsc);
   }
@@ -1625,11 +1628,12 @@ sox_status sox_plan_describe(const sox_plan* plan, char* buf, size_t len) {
            "{\"n\":%d,\"N\":%d,\"n_tau\":%d,\"nP\":%d,\"NP\":%d,\"precision\":%d,"
            "\"fused_cfg\":%d,\"fused_wave_tile\":[%d,%d],\"tau_slab\":%d,\"vjp_tau_slab\":%d,"
            "\"v_slab\":%d,\"vjp_v_slab\":%d,\"graph\":%d,\"tune_ms_per_tau\":%s,"
-           "\"tune_from_cache\":%d,\"kmesh\":[%d,%d,%d],\"n_k\":%d,\"solid_v_slab\":%d}",
+           "\"tune_from_cache\":%d,\"kmesh\":[%d,%d,%d],\"n_k\":%d,\"solid_v_slab\":%d,"
+           "\"solid_v_slab_bare\":%d}",
            plan->n, plan->N, plan->n_tau, plan->nP, plan->NP, plan->precision, plan->fused_cfg,
            fc.wp, fc.wr, plan->slab, plan->vjp_slab, plan->vc, plan->vc_vjp, plan->graph_on ? 1 : 0,
            tune.c_str(), plan->tune_from_cache ? 1 : 0, plan->kmesh[0], plan->kmesh[1],
-           plan->kmesh[2], plan->nk, plan->vcs);
+           plan->kmesh[2], plan->nk, plan->vcs, plan->vcs_bare);
   return SOX_OK;
 }
 

@@ -3,7 +3,7 @@
 // Storage is interleaved complex (re, im) in the compute type T.  Every
 // complex contraction of the chain is one batched NT product
 //
-//   C[z][i][j] (+)= alpha * sum_k opA(A[z])[i][k] * opB(B[z])[j][k]
+//   C[z][v][i][j] (+)= alpha * sum_k opA(A[z][v])[i][k] * opB(B[z][v])[j][k]
 //
 // run on the real 16x16x4 MFMA: each complex product is four real products
 // into a real and an imaginary accumulator (re += ar br - ai bi,
@@ -15,13 +15,17 @@
 // (idx ? idx[zo] : zo) * so + zi * si, so momentum-indexed gathers (k_v - q1,
 // k_w, q) come from small device tables.  Row r of A or B sits at
 // (r / split) * hi + (r % split) * ld, which lets one kernel read the
-// U-tensor [a][P][b] as rows (P, a).
+// U-tensor [a][P][b] as rows (P, a).  Inside a workgroup, v = 0 .. nv-1
+// offsets A, B and C by v * vsA, v * vsB, v * vsC: one operand of the B and
+// C steps is the same for every v (vs = 0) and stays in cache, and the
+// software pipeline runs on across the v boundary.
 //
-// K runs in 16-deep chunks (lane group g holds k = 4g + m, m = 0..3, four
-// consecutive complex values) with the next chunk's loads issued ahead of
-// the current chunk's MFMAs; a K tail below 16 runs in 4-deep steps (lane
-// group g holds k = 4m + g).  Rows past M or N read the last valid row and
-// are zeroed; k past K is zeroed; nothing is read out of range.
+// K runs in 16-deep chunks: in MFMA step m of a chunk, lane group g holds
+// k = 16 kc + 4 m + g, so a final partial chunk costs only ceil(rest / 4)
+// steps.  The loads of the next chunk (of this v or the next) are issued
+// before the current chunk's MFMAs.  Rows past M or N read the last valid
+// row and are zeroed; k past K reads the last valid k and is zeroed; nothing
+// is read out of range.
 #pragma once
 
 #include "sox_common.hpp"
@@ -46,7 +50,8 @@ template <typename T, typename TC> struct CgArgs {
   const int* idxC;
   long soA, soB, soS, soC;
   long siA, siB, siS, siC;
-  int nzi, nz;
+  long vsA, vsB, vsC;
+  int nzi, nz, nv;
   int splitA, splitB;
   long ldA, hiA, ldB, hiB, ldc;
   int M, N, K;
@@ -56,16 +61,15 @@ template <typename T, typename TC> struct CgArgs {
   int accumulate;
 };
 
-template <typename T>
 __device__ __forceinline__ long cg_off(const int* idx, long so, long si, int zo, int zi) {
   return (long)(idx ? idx[zo] : zo) * so + (long)zi * si;
 }
 
 template <typename T, typename TC, int WGR, int WGC, int RB, int CB>
-__global__ __launch_bounds__(256) void cgemm_nt_kernel(const CgArgs<T, TC> p) {
-  static_assert(WGR * WGC == 4, "four wavefronts per workgroup");
+__global__ __launch_bounds__(64 * WGR * WGC) void cgemm_nt_kernel(const CgArgs<T, TC> p) {
   using V2 = vec2_t<T>;
   using V4 = vec4_t<T>;
+  using C2 = vec2_t<TC>;
   const int z = blockIdx.y + blockIdx.z * gridDim.y;
   if (z >= p.nz) return;
   const int zo = z / p.nzi;
@@ -80,67 +84,119 @@ __global__ __launch_bounds__(256) void cgemm_nt_kernel(const CgArgs<T, TC> p) {
   const int row0 = tm * (WGR * RB * 16) + (wave / WGC) * (RB * 16);
   const int col0 = tn * (WGC * CB * 16) + (wave % WGC) * (CB * 16);
 
-  const V2* Ab = (const V2*)p.A + cg_off<T>(p.idxA, p.soA, p.siA, zo, zi);
-  const V2* Bb = (const V2*)p.B + cg_off<T>(p.idxB, p.soB, p.siB, zo, zi);
-  const V2* Sb = p.S ? (const V2*)p.S + cg_off<T>(p.idxS, p.soS, p.siS, zo, zi) : nullptr;
-  const V2* arow[RB];
-  const V2* brow[CB];
+  const V2* Ab = (const V2*)p.A + cg_off(p.idxA, p.soA, p.siA, zo, zi);
+  const V2* Bb = (const V2*)p.B + cg_off(p.idxB, p.soB, p.siB, zo, zi);
+  const V2* Sb = p.S ? (const V2*)p.S + cg_off(p.idxS, p.soS, p.siS, zo, zi) : nullptr;
+  TC* Cb = p.C + 2 * cg_off(p.idxC, p.soC, p.siC, zo, zi);
+  long aoff[RB], boff[CB];
   bool aok[RB], bok[CB];
 #pragma unroll
   for (int i = 0; i < RB; ++i) {
     const int r0 = row0 + 16 * i + li;
     aok[i] = r0 < p.M;
     const int r = aok[i] ? r0 : p.M - 1;
-    arow[i] = Ab + (long)(r / p.splitA) * p.hiA + (long)(r % p.splitA) * p.ldA;
+    aoff[i] = (long)(r / p.splitA) * p.hiA + (long)(r % p.splitA) * p.ldA;
   }
 #pragma unroll
   for (int j = 0; j < CB; ++j) {
     const int c0 = col0 + 16 * j + li;
     bok[j] = c0 < p.N;
     const int c = bok[j] ? c0 : p.N - 1;
-    brow[j] = Bb + (long)(c / p.splitB) * p.hiB + (long)(c % p.splitB) * p.ldB;
+    boff[j] = (long)(c / p.splitB) * p.hiB + (long)(c % p.splitB) * p.ldB;
   }
   const T sa = p.conjA ? T(-1) : T(1);
   const T sb = p.conjB ? T(-1) : T(1);
   const T ss = p.conjS ? T(-1) : T(1);
 
   V4 accr[RB][CB], acci[RB][CB];
-#pragma unroll
-  for (int i = 0; i < RB; ++i)
-#pragma unroll
-    for (int j = 0; j < CB; ++j) {
-      accr[i][j] = zero4<T>();
-      acci[i][j] = zero4<T>();
-    }
-
-  // operand registers of the current chunk: A as (re, im), B as (re, im, -im)
-  T ar[RB][4], ai[RB][4], br[CB][4], bi[CB][4], nbi[CB][4];
-  V2 ra[RB][4], rb[CB][4], rs[4];
-
-  auto prep = [&](const V2 (&xa)[RB][4], const V2 (&xb)[CB][4], const V2 (&xs)[4]) {
+  auto zero_acc = [&]() {
 #pragma unroll
     for (int i = 0; i < RB; ++i)
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        ar[i][m] = aok[i] ? xa[i][m].x : T(0);
-        ai[i][m] = aok[i] ? sa * xa[i][m].y : T(0);
+      for (int j = 0; j < CB; ++j) {
+        accr[i][j] = zero4<T>();
+        acci[i][j] = zero4<T>();
+      }
+  };
+  auto store = [&](int v) {
+    TC* Cv = Cb + 2 * (long)v * p.vsC;
+#pragma unroll
+    for (int i = 0; i < RB; ++i)
+#pragma unroll
+      for (int j = 0; j < CB; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = row0 + 16 * i + acc_row<T>(g, r);
+          const int col = col0 + 16 * j + li;
+          if (row < p.M && col < p.N) {
+            C2* o = (C2*)(Cv + 2 * ((long)row * p.ldc + col));
+            C2 val;
+            val.x = TC(p.alpha * accr[i][j][r]);
+            val.y = TC(p.alpha * acci[i][j][r]);
+            if (p.accumulate) val += *o;
+            *o = val;
+          }
+        }
+  };
+  zero_acc();
+  const int KC = (p.K + 15) >> 4;
+  if (KC == 0) {
+    for (int v = 0; v < p.nv; ++v) store(v);
+    return;
+  }
+  const int T_ = p.nv * KC;
+
+  // operand registers of the current step: (re, im) of both, plus the
+  // negated imaginary part of the operand with fewer blocks
+  constexpr bool NEG_A = RB <= CB;
+  constexpr int NA = NEG_A ? RB : 1, NB = NEG_A ? 1 : CB;
+  T ar[RB][4], ai[RB][4], br[CB][4], bi[CB][4], nai[NA][4], nbi[NB][4];
+  V2 ra[RB][4], rb[CB][4], rs[4];
+
+  auto load = [&](int t) {
+    const int v = t / KC;
+    const int kc = t - v * KC;
+    const V2* Av = Ab + (long)v * p.vsA;
+    const V2* Bv = Bb + (long)v * p.vsB;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      int k = kc * 16 + 4 * m + g;
+      k = k < p.K ? k : p.K - 1;
+#pragma unroll
+      for (int i = 0; i < RB; ++i) ra[i][m] = Av[aoff[i] + k];
+#pragma unroll
+      for (int j = 0; j < CB; ++j) rb[j][m] = Bv[boff[j] + k];
+      rs[m] = Sb ? Sb[k] : V2{T(0), T(0)};
+    }
+  };
+  auto prep = [&](int t) {
+    const int kc = t % KC;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const bool kin = kc * 16 + 4 * m + g < p.K;
+#pragma unroll
+      for (int i = 0; i < RB; ++i) {
+        const bool ok = aok[i] && kin;
+        ar[i][m] = ok ? ra[i][m].x : T(0);
+        ai[i][m] = ok ? sa * ra[i][m].y : T(0);
+        if constexpr (NEG_A) nai[i][m] = -ai[i][m];
       }
 #pragma unroll
-    for (int j = 0; j < CB; ++j)
-#pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        T re = bok[j] ? xb[j][m].x : T(0);
-        T im = bok[j] ? sb * xb[j][m].y : T(0);
+      for (int j = 0; j < CB; ++j) {
+        const bool ok = bok[j] && kin;
+        T re = ok ? rb[j][m].x : T(0);
+        T im = ok ? sb * rb[j][m].y : T(0);
         if (Sb) {
-          const T sr = xs[m].x, si = ss * xs[m].y;
+          const T sr = rs[m].x, si = ss * rs[m].y;
           const T r2 = re * sr - im * si;
           im = re * si + im * sr;
           re = r2;
         }
         br[j][m] = re;
         bi[j][m] = im;
-        nbi[j][m] = -im;
+        if constexpr (!NEG_A) nbi[j][m] = -im;
       }
+    }
   };
   auto mma = [&](int m) {
 #pragma unroll
@@ -148,95 +204,38 @@ __global__ __launch_bounds__(256) void cgemm_nt_kernel(const CgArgs<T, TC> p) {
 #pragma unroll
       for (int j = 0; j < CB; ++j) {
         accr[i][j] = mfma16x16x4(ar[i][m], br[j][m], accr[i][j]);
-        accr[i][j] = mfma16x16x4(ai[i][m], nbi[j][m], accr[i][j]);
+        if constexpr (NEG_A) accr[i][j] = mfma16x16x4(nai[i][m], bi[j][m], accr[i][j]);
+        else accr[i][j] = mfma16x16x4(ai[i][m], nbi[j][m], accr[i][j]);
         acci[i][j] = mfma16x16x4(ar[i][m], bi[j][m], acci[i][j]);
         acci[i][j] = mfma16x16x4(ai[i][m], br[j][m], acci[i][j]);
       }
   };
 
-  const int KC = p.K >> 4;
-  if (KC > 0) {
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-#pragma unroll
-      for (int i = 0; i < RB; ++i) ra[i][m] = arow[i][4 * g + m];
-#pragma unroll
-      for (int j = 0; j < CB; ++j) rb[j][m] = brow[j][4 * g + m];
-      rs[m] = Sb ? Sb[4 * g + m] : V2{T(0), T(0)};
-    }
-    prep(ra, rb, rs);
-  }
-  for (int kc = 0; kc < KC; ++kc) {
-    const int kn = (kc + 1 < KC) ? kc + 1 : kc;
-    const int ko = kn * 16 + 4 * g;
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-#pragma unroll
-      for (int i = 0; i < RB; ++i) ra[i][m] = arow[i][ko + m];
-#pragma unroll
-      for (int j = 0; j < CB; ++j) rb[j][m] = brow[j][ko + m];
-      rs[m] = Sb ? Sb[ko + m] : V2{T(0), T(0)};
-    }
+  const int last_steps = (p.K - (KC - 1) * 16 + 3) >> 2;  // MFMA steps of the final chunk
+  load(0);
+  prep(0);
+  for (int t = 0; t < T_; ++t) {
+    load(t + 1 < T_ ? t + 1 : t);
     __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int m = 0; m < 4; ++m) mma(m);
-    __builtin_amdgcn_sched_barrier(0);
-    prep(ra, rb, rs);
-  }
-  // K tail: 4-deep steps, lane group g holds k = base + 4m + g
-  const int base = KC * 16;
-  const int kr = p.K - base;
-  for (int m = 0; 4 * m < kr; ++m) {
-    const int k = base + 4 * m + g;
-    const bool kin = k < p.K;
-    const int kk = kin ? k : base;
-    V2 xa[RB][4], xb[CB][4], xs[4];
-#pragma unroll
-    for (int i = 0; i < RB; ++i) {
-      V2 v = arow[i][kk];
-      if (!kin) v = V2{T(0), T(0)};
-      xa[i][0] = v;
-      xa[i][1] = xa[i][2] = xa[i][3] = v;
-    }
-#pragma unroll
-    for (int j = 0; j < CB; ++j) {
-      V2 v = brow[j][kk];
-      if (!kin) v = V2{T(0), T(0)};
-      xb[j][0] = v;
-      xb[j][1] = xb[j][2] = xb[j][3] = v;
-    }
-    V2 s = Sb ? Sb[kk] : V2{T(0), T(0)};
-    xs[0] = xs[1] = xs[2] = xs[3] = s;
-    prep(xa, xb, xs);
+    const int kc = t % KC;
+    const int steps = kc == KC - 1 ? last_steps : 4;
     mma(0);
+    if (steps > 1) mma(1);
+    if (steps > 2) mma(2);
+    if (steps > 3) mma(3);
+    __builtin_amdgcn_sched_barrier(0);
+    if (kc == KC - 1) {
+      store(t / KC);
+      zero_acc();
+    }
+    prep(t + 1 < T_ ? t + 1 : t);
   }
-
-  TC* Cb = p.C + 2 * cg_off<T>(p.idxC, p.soC, p.siC, zo, zi);
-#pragma unroll
-  for (int i = 0; i < RB; ++i)
-#pragma unroll
-    for (int j = 0; j < CB; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = row0 + 16 * i + acc_row<T>(g, r);
-        const int col = col0 + 16 * j + li;
-        if (row < p.M && col < p.N) {
-          const long off = 2 * ((long)row * p.ldc + col);
-          TC re = TC(p.alpha * accr[i][j][r]);
-          TC im = TC(p.alpha * acci[i][j][r]);
-          if (p.accumulate) {
-            re += Cb[off];
-            im += Cb[off + 1];
-          }
-          Cb[off] = re;
-          Cb[off + 1] = im;
-        }
-      }
 }
 
 template <typename T, typename TC> inline CgArgs<T, TC> cg_args() {
   CgArgs<T, TC> a{};
   a.nzi = 1;
+  a.nv = 1;
   a.splitA = a.splitB = 1 << 30;
   a.alpha = T(1);
   return a;
@@ -246,7 +245,7 @@ template <typename T, typename TC, int WGR, int WGC, int RB, int CB>
 inline hipError_t launch_cgemm(CgArgs<T, TC> a, int nz, hipStream_t s) {
   constexpr int TM = WGR * RB * 16;
   constexpr int TN = WGC * CB * 16;
-  if (a.M <= 0 || a.N <= 0 || nz <= 0) return hipSuccess;
+  if (a.M <= 0 || a.N <= 0 || nz <= 0 || a.nv <= 0) return hipSuccess;
   if (a.K < 0 || a.nzi <= 0 || a.splitA <= 0 || a.splitB <= 0) return hipErrorInvalidValue;
   a.nz = nz;
   a.tiles_m = (a.M + TM - 1) / TM;
@@ -254,7 +253,8 @@ inline hipError_t launch_cgemm(CgArgs<T, TC> a, int nz, hipStream_t s) {
   const int gy = nz < 65535 ? nz : 65535;
   const int gz = (nz + gy - 1) / gy;
   dim3 grid(a.tiles_m * a.tiles_n, gy, gz);
-  hipLaunchKernelGGL((cgemm_nt_kernel<T, TC, WGR, WGC, RB, CB>), grid, dim3(256), 0, s, a);
+  hipLaunchKernelGGL((cgemm_nt_kernel<T, TC, WGR, WGC, RB, CB>), grid, dim3(64 * WGR * WGC), 0, s,
+                     a);
   return hipGetLastError();
 }
 
@@ -270,7 +270,9 @@ inline hipError_t launch_cgemm(CgArgs<T, TC> a, int nz, hipStream_t s) {
 // One thread per element: for each (k_v, v) it loads the n_k values
 // B[(., k_v)][v][e] and the n_k values C[(k_w - k_v, k_w)][v][e] once and
 // forms all n_k^2 products in registers.  Pairs are sp elements apart, v
-// slices NN apart; nv slices are summed.  The mesh is a template parameter so
+// slices NN apart; nv slices are summed.  The k_v range is split over the
+// rows of the grid (gk momenta each) so that the launch fills the chip; each
+// row writes its own partial D, summed by dsum_kernel.  The mesh is a template parameter so
 // that every momentum difference is a compile-time register index.
 // D is float64 (the cross-slab accumulation).
 template <int M1, int M2, int M3>
@@ -283,18 +285,22 @@ __host__ __device__ constexpr int kdiff_of(int a, int b) {
 template <typename T, int M1, int M2, int M3>
 __global__ __launch_bounds__(256) void dstep_mesh_kernel(const T* __restrict__ B,
                                                          const T* __restrict__ C, double* D,
-                                                         long NN, long sp, int nv, double scale,
-                                                         int accumulate) {
+                                                         long NN, long sp, int nv, int gk,
+                                                         double scale, int accumulate) {
   constexpr int NK = M1 * M2 * M3;
   using V2 = vec2_t<T>;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= NN) return;
+  // workgroup row y sums k_v in [y gk, y gk + gk) into its own partial D
+  const int kv0 = blockIdx.y * gk;
+  const int kv1 = kv0 + gk < NK ? kv0 + gk : NK;
+  D += 2 * (long)blockIdx.y * NK * NN;
   const V2* Bp = (const V2*)B + e;
   const V2* Cp = (const V2*)C + e;
   double dr[NK], di[NK];
 #pragma unroll
   for (int k = 0; k < NK; ++k) dr[k] = di[k] = 0.0;
-  for (int kv = 0; kv < NK; ++kv) {
+  for (int kv = kv0; kv < kv1; ++kv) {
     for (int v = 0; v < nv; ++v) {
       const long ov = (long)v * NN;
       V2 b[NK], c[NK];
@@ -331,6 +337,17 @@ __global__ __launch_bounds__(256) void dstep_mesh_kernel(const T* __restrict__ B
     o[0] = re;
     o[1] = im;
   }
+}
+
+// D[i] (+)= sum_g Dp[g][i], i < count (float64 values): the partial D sums of
+// the k_v groups.
+__global__ __launch_bounds__(256) void dsum_kernel(const double* Dp, int ng, long count, double* D,
+                                                   int accumulate) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  double acc = accumulate ? D[i] : 0.0;
+  for (int g = 0; g < ng; ++g) acc += Dp[(long)g * count + i];
+  D[i] = acc;
 }
 
 // Any mesh (runtime momentum-difference table kdiff[n_k][n_k]): one thread

@@ -14,14 +14,24 @@
 //   D^{k_t}[P][R] = (1/n_k) sum_{k_w, q2, v} C[(q2,k_w)][v][P][R] B[(k_w - k_t, k_w - q2)][v][P][R]
 //   Sigma^{k_t}_tr = -(1/n_k) sum_{P,R} conj(X^{k_t}_tR) D^{k_t}[P][R] X^{k_t}_rP
 //
-// v runs in slabs of width vcs so that A, B and C of one slab and one tau
-// node stay within the workspace budget; D accumulates over the slabs in
-// float64.  The U-contraction, the projections and the back-transform run in
-// float64; A, B, C and the D step in the plan's precision.
+// Per tau node the A step runs once for every v (the U-tensor is streamed
+// once per node); B, C and D then run over v slabs whose width keeps B and C
+// within the workspace budget, and D accumulates over the slabs in float64.
+// The U-contraction, the projections and the back-transform run in float64;
+// A, B, C and the D step in the plan's precision.
 
 struct SolidLayout {
-  size_t ut1, ut2, xtd, gtd, gtt, grq, gwp, abuf, bbuf, cbuf, dbuf, ebuf, total;
+  size_t ut1, ut2, xtd, gtd, gtt, grq, gwp, abuf, bbuf, cbuf, dbuf, dpart, ebuf, total;
 };
+
+// Number of k_v groups of the D step: enough workgroup rows that the launch
+// holds at least 16384 wavefronts.
+int solid_dgroups(const sox_plan& p) {
+  const long NN = (long)p.N * p.N;
+  const long want = (16384L * 64 + NN - 1) / NN;
+  const int gk = (int)((p.nk + std::min<long>(want, p.nk) - 1) / std::min<long>(want, p.nk));
+  return (p.nk + gk - 1) / gk;
+}
 
 SolidLayout solid_layout_for(const sox_plan& p, int entry, int vc) {
   SolidLayout L{};
@@ -35,26 +45,30 @@ SolidLayout solid_layout_for(const sox_plan& p, int entry, int vc) {
   L.gtt = c.take(nk * nt * n * n * es);
   L.grq = c.take(nt * nk * N * n * es);
   L.gwp = c.take(nt * nk * N * n * es);
-  L.abuf = c.take(np2 * (size_t)vc * N * n * es);
+  L.abuf = c.take(np2 * n * N * n * es);
   L.bbuf = c.take(np2 * (size_t)vc * N * N * es);
   L.cbuf = c.take(np2 * (size_t)vc * N * N * es);
   L.dbuf = c.take(nk * N * N * 16);
+  const int ng = solid_dgroups(p);
+  L.dpart = ng > 1 ? c.take((size_t)ng * nk * N * N * 16) : L.dbuf;
   L.ebuf = c.take(nk * n * N * 16);
   L.total = c.off;
   return L;
 }
 
+int solid_vc(const sox_plan& p, int entry) { return entry == SOX_ENTRY_BARE ? p.vcs_bare : p.vcs; }
+
 size_t solid_workspace_bytes(const sox_plan& p, int entry) {
   if (entry == SOX_ENTRY_DYNAMIC) return 0;
-  return solid_layout_for(p, entry, p.vcs).total;
+  return solid_layout_for(p, entry, solid_vc(p, entry)).total;
 }
 
-// Largest v-slab width that keeps the statically screened entry's workspace
-// within the budget, then evened out over the slabs it implies.
-int pick_solid_vc(const sox_plan& p) {
+// Largest v-slab width that keeps the entry's workspace within the budget,
+// then evened out over the slabs it implies.
+int pick_solid_vc(const sox_plan& p, int entry) {
   const size_t budget = ws_budget();
   int vc = p.n;
-  while (vc > 1 && solid_layout_for(p, SOX_ENTRY_STATIC, vc).total > budget) --vc;
+  while (vc > 1 && solid_layout_for(p, entry, vc).total > budget) --vc;
   const int slabs = (p.n + vc - 1) / vc;
   return (p.n + slabs - 1) / slabs;
 }
@@ -82,30 +96,52 @@ std::vector<int> solid_tables(const int mesh[3]) {
   return t;
 }
 
-// Tile shapes of the complex product: 0 = 64 x 64 workgroup tile (2 x 2
-// wavefronts of 32 x 32), 1 = 16 x 256 (one row of four 16 x 64 wavefronts,
-// for the A step whose row count is the v-slab width).
+// Tile shapes of the complex product.  0: 64 x 64 workgroup tile (2 x 2
+// wavefronts of 32 x 32).  1: 64 x 64 as four 64 x 16 wavefronts, for the A
+// step, whose 64 rows hold every v so that each U-tensor row is read once.
+// 2: the B and C steps, five wavefronts stacked along the rows, each 16 x 80
+// (float32) or 16 x 16 (float64): an 80 x 80 or 80 x 16 tile, which divides
+// N = 400 exactly.
 template <typename T, typename TC>
 sox_status cg_launch(const CgArgs<T, TC>& a, int nz, int shape, hipStream_t s) {
-  if (shape == 1) SOX_HIP((launch_cgemm<T, TC, 1, 4, 1, 4>(a, nz, s)));
-  else SOX_HIP((launch_cgemm<T, TC, 2, 2, 2, 2>(a, nz, s)));
+  if (shape == 1) {
+    SOX_HIP((launch_cgemm<T, TC, 1, 4, 4, 1>(a, nz, s)));
+  } else if (shape == 2) {
+    if constexpr (sizeof(T) == 4) SOX_HIP((launch_cgemm<T, TC, 5, 1, 1, 5>(a, nz, s)));
+    else SOX_HIP((launch_cgemm<T, TC, 5, 1, 1, 1>(a, nz, s)));
+  } else {
+    SOX_HIP((launch_cgemm<T, TC, 2, 2, 2, 2>(a, nz, s)));
+  }
   return SOX_OK;
 }
 
+// Tile of the B and C steps for this N: the 80-row tiles when they pad less
+// than the 64 x 64 ones.
+int bc_shape(int N) {
+  const long w80 = ((N + 79) / 80) * 80L, w64 = ((N + 63) / 64) * 64L;
+  return w80 < w64 ? 2 : 0;
+}
+
+// D (+)= the D step of one v slab.  The templated kernels write per-group
+// partial sums into Dp (accumulated over the slabs of a node); the caller
+// sums the groups into D once per node (solid_dsum).  The any-mesh kernel
+// writes D directly.
 template <typename T>
-sox_status launch_dstep(const sox_plan& p, const T* B, const T* C, double* D, int nv, bool acc,
-                        hipStream_t s) {
+sox_status launch_dstep(const sox_plan& p, const T* B, const T* C, double* D, double* Dp, int vcs,
+                        int nv, bool acc, hipStream_t s) {
   const long NN = (long)p.N * p.N;
-  const long sp = (long)p.vcs * NN;
+  const long sp = (long)vcs * NN;
   const double scale = 1.0 / p.nk;
-  const dim3 grid((unsigned)((NN + 255) / 256));
+  const int ng = solid_dgroups(p);
+  const int gk = (p.nk + ng - 1) / ng;
+  const dim3 grid((unsigned)((NN + 255) / 256), (unsigned)ng);
   const int* m = p.mesh_canon;
-#define SOX_DSTEP(A_, B_, C_)                                                                 \
-  if (m[0] == A_ && m[1] == B_ && m[2] == C_) {                                              \
-    hipLaunchKernelGGL((dstep_mesh_kernel<T, A_, B_, C_>), grid, dim3(256), 0, s, B, C, D, NN, \
-                       sp, nv, scale, acc ? 1 : 0);                                           \
-    SOX_HIP(hipGetLastError());                                                               \
-    return SOX_OK;                                                                            \
+#define SOX_DSTEP(A_, B_, C_)                                                                  \
+  if (m[0] == A_ && m[1] == B_ && m[2] == C_) {                                               \
+    hipLaunchKernelGGL((dstep_mesh_kernel<T, A_, B_, C_>), grid, dim3(256), 0, s, B, C, Dp, NN, \
+                       sp, nv, gk, scale, acc ? 1 : 0);                                        \
+    SOX_HIP(hipGetLastError());                                                                \
+    return SOX_OK;                                                                             \
   }
   SOX_DSTEP(2, 1, 1)
   SOX_DSTEP(3, 1, 1)
@@ -120,6 +156,25 @@ sox_status launch_dstep(const sox_plan& p, const T* B, const T* C, double* D, in
   hipLaunchKernelGGL((dstep_any_kernel<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
                      B, C, p.d_ktab + 3 * (size_t)p.nk * p.nk, D, NN, p.nk, sp, nv, scale,
                      acc ? 1 : 0);
+  SOX_HIP(hipGetLastError());
+  return SOX_OK;
+}
+
+bool dstep_templated(const sox_plan& p) {
+  static const int meshes[8][3] = {{2, 1, 1}, {3, 1, 1}, {2, 2, 1}, {2, 3, 1},
+                                   {3, 2, 1}, {3, 3, 1}, {2, 2, 2}, {3, 3, 3}};
+  for (auto& m : meshes)
+    if (p.mesh_canon[0] == m[0] && p.mesh_canon[1] == m[1] && p.mesh_canon[2] == m[2]) return true;
+  return false;
+}
+
+// D = sum of the per-group partial sums (templated D step with several groups).
+sox_status solid_dsum(const sox_plan& p, const double* Dp, double* D, hipStream_t s) {
+  const int ng = solid_dgroups(p);
+  if (!dstep_templated(p) || Dp == D) return SOX_OK;
+  const long count = 2L * p.nk * p.N * p.N;
+  hipLaunchKernelGGL(dsum_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, Dp, ng,
+                     count, D, 0);
   SOX_HIP(hipGetLastError());
   return SOX_OK;
 }
@@ -156,7 +211,7 @@ sox_status launch_solid_utensor(const sox_plan& p, const double* U, const double
 template <typename T>
 sox_status run_solid(sox_plan& p, int entry, const double* X, const double* U1, const double* U2,
                      const double* G, double* Sigma, void* ws, hipStream_t s) {
-  const int n = p.n, N = p.N, nt = p.n_tau, nk = p.nk, np2 = nk * nk, vcs = p.vcs;
+  const int n = p.n, N = p.N, nt = p.n_tau, nk = p.nk, np2 = nk * nk, vcs = solid_vc(p, entry);
   const SolidLayout L = solid_layout_for(p, entry, vcs);
   char* base = (char*)ws;
   T* ut1 = (T*)(base + L.ut1);
@@ -170,6 +225,8 @@ sox_status run_solid(sox_plan& p, int entry, const double* X, const double* U1, 
   T* bbuf = (T*)(base + L.bbuf);
   T* cbuf = (T*)(base + L.cbuf);
   double* dbuf = (double*)(base + L.dbuf);
+  double* dpart = (double*)(base + L.dpart);
+  const int bcs = bc_shape(N);
   double* ebuf = (double*)(base + L.ebuf);
   const int* kOf = p.d_ktab;
   const int* kqOf = p.d_ktab + 2 * np2;  // index of k_v - q1 for pair (q1, k_v)
@@ -207,39 +264,49 @@ sox_status run_solid(sox_plan& p, int entry, const double* X, const double* U1, 
   }
   for (int t = 0; t < nt; ++t) {
     const int tm = nt - 1 - t;
+    {
+      // A[pair][v][(P, q)] for every v: rows v of G^{k_v}(beta - tau)^T
+      ProfScope ps(p, SOX_STAGE_ASTEP, s);
+      CgArgs<T, T> a = cg_args<T, T>();
+      a.A = gtt + 2 * (long)tm * n * n;
+      a.idxA = kOf; a.soA = (long)nt * n * n; a.ldA = n;
+      a.B = ut1; a.soB = (long)n * N * n; a.splitB = n; a.hiB = n; a.ldB = (long)N * n;
+      a.C = abuf; a.soC = (long)n * N * n; a.ldc = (long)N * n;
+      a.M = n; a.N = N * n; a.K = n;
+      if ((st = cg_launch(a, np2, 1, s))) return st;
+    }
     for (int v0 = 0; v0 < n; v0 += vcs) {
       const int cnt = std::min(vcs, n - v0);
       {
-        ProfScope ps(p, SOX_STAGE_ASTEP, s);
-        CgArgs<T, T> a = cg_args<T, T>();
-        a.A = gtt + 2 * ((long)tm * n * n + (long)v0 * n);
-        a.idxA = kOf; a.soA = (long)nt * n * n; a.ldA = n;
-        a.B = ut1; a.soB = (long)n * N * n; a.splitB = n; a.hiB = n; a.ldB = (long)N * n;
-        a.C = abuf; a.soC = (long)vcs * N * n; a.ldc = (long)N * n;
-        a.M = cnt; a.N = N * n; a.K = n;
-        if ((st = cg_launch(a, np2, 1, s))) return st;
-      }
-      {
+        // B[pair][v] = A[pair][v0 + v] GRq^{k_v - q1}^T, the GRq panel shared by every v
         ProfScope ps(p, SOX_STAGE_KBC, s);
         CgArgs<T, T> b = cg_args<T, T>();
-        b.A = abuf; b.soA = (long)vcs * N * n; b.siA = (long)N * n; b.ldA = n;
+        b.A = abuf + 2 * (long)v0 * N * n; b.soA = (long)n * N * n; b.vsA = (long)N * n; b.ldA = n;
         b.B = grq + 2 * (long)t * nk * N * n; b.idxB = kqOf; b.soB = (long)N * n; b.ldB = n;
-        b.C = bbuf; b.soC = (long)vcs * N * N; b.siC = (long)N * N; b.ldc = N;
-        b.nzi = cnt;
+        b.C = bbuf; b.soC = (long)vcs * N * N; b.vsC = (long)N * N; b.ldc = N;
+        b.nv = cnt;
         b.M = N; b.N = N; b.K = n;
-        if ((st = cg_launch(b, np2 * cnt, 0, s))) return st;
+        if ((st = cg_launch(b, np2, bcs, s))) return st;
+      }
+      {
+        // C[pair][v] = GwPt^{k_w} Ut2[pair][v0 + v]^T, the GwPt panel shared by every v
+        ProfScope ps(p, SOX_STAGE_KBC, s);
         CgArgs<T, T> c = cg_args<T, T>();
         c.A = gwp + 2 * (long)t * nk * N * n; c.idxA = kOf; c.soA = (long)N * n; c.ldA = n;
-        c.B = ut2 + 2 * (long)v0 * N * n; c.soB = (long)n * N * n; c.siB = (long)N * n; c.ldB = n;
-        c.C = cbuf; c.soC = (long)vcs * N * N; c.siC = (long)N * N; c.ldc = N;
-        c.nzi = cnt;
+        c.B = ut2 + 2 * (long)v0 * N * n; c.soB = (long)n * N * n; c.vsB = (long)N * n; c.ldB = n;
+        c.C = cbuf; c.soC = (long)vcs * N * N; c.vsC = (long)N * N; c.ldc = N;
+        c.nv = cnt;
         c.M = N; c.N = N; c.K = n;
-        if ((st = cg_launch(c, np2 * cnt, 0, s))) return st;
+        if ((st = cg_launch(c, np2, bcs, s))) return st;
       }
       {
         ProfScope ps(p, SOX_STAGE_KD, s);
-        if ((st = launch_dstep<T>(p, bbuf, cbuf, dbuf, cnt, v0 > 0, s))) return st;
+        if ((st = launch_dstep<T>(p, bbuf, cbuf, dbuf, dpart, vcs, cnt, v0 > 0, s))) return st;
       }
+    }
+    {
+      ProfScope ps(p, SOX_STAGE_KD, s);
+      if ((st = solid_dsum(p, dpart, dbuf, s))) return st;
     }
     {
       ProfScope ps(p, SOX_STAGE_BACK, s);
@@ -265,8 +332,8 @@ sox_status run_solid(sox_plan& p, int entry, const double* X, const double* U1, 
 sox_status solid_build_g(sox_plan& p, const double* Q, const double* eps, double mu, double* G,
                          hipStream_t s) {
   const int n = p.n, nt = p.n_tau, nk = p.nk;
-  double* occ = p.d_scratch;                    // [n_tau][n_k n]
-  double* occc = occ + (size_t)nt * nk * n;     // complex copy
+  double* occ = p.d_scratch;                                  // [n_tau][n_k n]
+  double* occc = occ + round_up((long)nt * nk * n, 2);        // complex copy, 16-byte aligned
   const long tot = (long)nt * nk * n;
   ProfScope ps(p, SOX_STAGE_GBUILD, s);
   hipLaunchKernelGGL(occupation_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, eps,
@@ -289,7 +356,7 @@ sox_status solid_build_g(sox_plan& p, const double* Q, const double* eps, double
 sox_status solid_energy(sox_plan& p, const double* Sigma, const double* G, double* E_host,
                         hipStream_t s) {
   const int n = p.n, nt = p.n_tau, nk = p.nk;
-  double* tr = p.d_scratch + 3 * (size_t)nt * nk * n;
+  double* tr = p.d_scratch + round_up((long)nt * nk * n, 2) + 2L * nt * nk * n;
   double* e = tr + (size_t)nt * nk;
   {
     ProfScope ps(p, SOX_STAGE_ENERGY, s);

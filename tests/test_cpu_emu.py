@@ -68,6 +68,8 @@ SOLID_CASES = [
     (3, 10, 2, 1, 0, (3, 3, 3), None),
     (5, 17, 2, 0, 1, (4, 1, 1), None),
     (9, 40, 2, 1, 1, (3, 1, 1), "1"),
+    (5, 160, 1, 1, 0, (3, 1, 1), None),   # 80 x 80 B / C tiles (float32)
+    (4, 80, 1, 0, 1, (2, 1, 1), None),    # 80 x 16 B / C tiles (float64)
 ]
 
 
