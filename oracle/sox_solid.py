@@ -114,3 +114,102 @@ def energy_gm_k(Sigma, G, weights) -> float:
     nk = Sigma.shape[0]
     tr = np.einsum("ktab,ktba->t", Sigma, G[:, ::-1])
     return float(-0.5 * np.dot(weights, tr.real) / nk)
+
+
+# ---------------------------------------------------------------------------
+# dynamic interaction on line 1 (eq:GG scheme for solids)
+# ---------------------------------------------------------------------------
+# The plan's transform pair acts on functions that are real in imaginary
+# time: f(i Omega_m) = sum_j T_fwd[m, j] f(tau_j) for m >= 0 and
+# f(tau_i) = Re sum_m T_bwd[i, m] f(i Omega_m).  Momentum-resolved functions
+# are complex; their transforms are taken at +Omega_m with T_fwd and at
+# -Omega_m with conj(T_fwd), and the inverse transform is
+# f(tau_i) = 1/2 sum_m [T_bwd[i, m] f(i Omega_m) + conj(T_bwd[i, m]) f(-i Omega_m)],
+# which is the bilinear extension of the real-function pair (it returns
+# Re T_bwd T_fwd f for real f), so a periodic convolution becomes a product
+# at every signed frequency.
+
+def matsubara_pm(T_fwd: np.ndarray, f: np.ndarray):
+    """(f(+i Omega), f(-i Omega)) along axis 0."""
+    return np.tensordot(T_fwd, f, axes=(1, 0)), np.tensordot(T_fwd.conj(), f, axes=(1, 0))
+
+
+def imag_time_pm(T_bwd: np.ndarray, fp: np.ndarray, fm: np.ndarray) -> np.ndarray:
+    """f(tau) from its transforms at +Omega and -Omega (axis 0)."""
+    return 0.5 * (np.tensordot(T_bwd, fp, axes=(1, 0)) + np.tensordot(T_bwd.conj(), fm, axes=(1, 0)))
+
+
+def sigma_solid_dynamic_eri(X, W, V, G, T_fwd, T_bwd, tables) -> np.ndarray:
+    """4-index brute force of eq:sox with U(1) = W^q(tau) and U(2) = V^q.
+
+    W [n_k, n_tau, N, N] (W^q(tau_j)).  As for molecules, the U(1) line
+    couples G_uq(s) G_sv(beta - s) to the external time through the periodic
+    convolution K(tau) = int_0^beta (pr|qs)_W(tau - s) G_uq(s) G_sv(beta - s) ds,
+    here evaluated with the signed-frequency pair above."""
+    ks_list, kdiff, ksum, kneg = tables
+    nk, nt, n, _ = G.shape
+    Gb = G[:, ::-1]
+    out = np.zeros((nk, nt, n, n), dtype=complex)
+    for kt in range(nk):
+        for kp in range(nk):
+            for kq in range(nk):
+                kss = kdiff[ksum[kp, kq], kt]
+                E2 = eri_k(X, V, kt, kq, kss, kp, kdiff)                     # (t kt, u kq | v ks, w kp)
+                E1w = np.stack([eri_k(X, W[:, j], kp, kt, kq, kss, kdiff) for j in range(nt)])
+                f = np.einsum("juq,jsv->juqsv", G[kq], Gb[kss])
+                Ep, Em = matsubara_pm(T_fwd, E1w)
+                fp, fm = matsubara_pm(T_fwd, f)
+                K = imag_time_pm(T_bwd, np.einsum("mprqs,muqsv->mpruv", Ep, fp),
+                                 np.einsum("mprqs,muqsv->mpruv", Em, fm))
+                for i in range(nt):
+                    out[kt, i] -= np.einsum("tuvw,wp,pruv->tr", E2, G[kp, i], K[i], optimize=True)
+    return out / nk ** 2
+
+
+def sigma_solid_dynamic_thc(X, W, V, G, T_fwd, T_bwd, tables) -> np.ndarray:
+    """The paper's momentum-resolved eq:GG chain with v outermost.
+
+    GG^{q1,k_v}_Quv(tau) = G^{k_v-q1}_uQ(tau) G^{k_v}_Qv(-tau) with
+    G^k_uQ = sum_q G^k_uq conj(X^k_qQ) and G^k_Qv(-tau) read as
+    sum_s X^k_sQ G^k_sv(beta - tau); A = W^{q1} * GG (periodic convolution as
+    a product at +-Omega); B^{q1,k_v}_PRv = sum_u X^{k_v-q1}_uR A_Puv;
+    C, D and Sigma as for static interactions."""
+    ks_list, kdiff, ksum, kneg = tables
+    nk, nt, n, _ = G.shape
+    N = X.shape[2]
+    Gb = G[:, ::-1]
+    Wp = [np.tensordot(T_fwd, W[q], axes=(1, 0)) for q in range(nk)]
+    Wm = [np.tensordot(T_fwd.conj(), W[q], axes=(1, 0)) for q in range(nk)]
+    GwP = [np.einsum("jwp,pP->jwP", G[k], X[k].conj()) for k in range(nk)]        # [nt, w, P]
+    GQv = [np.einsum("sQ,jsv->jQv", X[k], Gb[k]) for k in range(nk)]              # [nt, Q, v]
+
+    def utensor(U, q, kv):
+        kq = kdiff[kv, q]
+        return np.einsum("PQ,qQ,sQ->Pqs", U[q], X[kq].conj(), X[kv], optimize=True)
+
+    U2t = {(q, k): utensor(V, q, k) for q in range(nk) for k in range(nk)}
+    D = np.zeros((nk, nt, N, N), dtype=complex)
+    for v in range(n):
+        B = {}
+        for q1 in range(nk):
+            for kv in range(nk):
+                kq = kdiff[kv, q1]
+                GG = GwP[kq].transpose(0, 2, 1) * GQv[kv][:, :, v][:, :, None]   # [nt, Q, u]
+                GGp, GGm = matsubara_pm(T_fwd, GG)
+                A = imag_time_pm(T_bwd, np.matmul(Wp[q1], GGp), np.matmul(Wm[q1], GGm))   # [nt, P, u]
+                B[(q1, kv)] = np.matmul(A, X[kq])                                  # [nt, P, R]
+        C = {}
+        for q2 in range(nk):
+            for kw in range(nk):
+                C[(q2, kw)] = np.matmul(U2t[(q2, kw)][:, v, :], GwP[kw])          # [nt, R, P]
+        for kt in range(nk):
+            for kw in range(nk):
+                q1 = kdiff[kw, kt]
+                for q2 in range(nk):
+                    kv = kdiff[kw, q2]
+                    D[kt] += C[(q2, kw)].transpose(0, 2, 1) * B[(q1, kv)] / nk
+    out = np.empty((nk, nt, n, n), dtype=complex)
+    for kt in range(nk):
+        for j in range(nt):
+            out[kt, j] = X[kt].conj() @ (-D[kt, j].T / nk) @ X[kt].T
+    return out

@@ -294,6 +294,24 @@ def solid(mesh, n: int, N: int, n_tau: int, beta: float, *, eps_window=(-1.5, 1.
                 kdiff=kdiff, ksum=ksum, kneg=kneg, rng=rng)
 
 
+def add_dynamic_screening_solid(wl: dict, n_poles: int = 8, amp=(0.01, 0.1),
+                                log10_w=(-1.0, 1.0)) -> dict:
+    """W^q(tau) = sum_k a_k pole_{w_k}(tau) S_k^q on a k-point workload, with
+    each S_k^q momentum-paired Hermitian (S^{-q} = conj(S^q)); the pole
+    parameters are drawn as for molecules.  Stored q-major: [n_k, n_tau, N, N]."""
+    rng = wl["rng"]
+    N, tau, beta = wl["N"], wl["tau"], wl["beta"]
+    W = np.zeros((wl["nk"], len(tau), N, N), dtype=complex)
+    for _ in range(n_poles):
+        w = 10.0 ** rng.uniform(*log10_w)
+        a = rng.uniform(*amp)
+        S = paired_hermitian(rng, wl["kneg"], N, 1.0 / N)
+        pole = periodic_bosonic_pole(tau, beta, w)
+        W += a * pole[None, :, None, None] * S[:, None]
+    wl.update(W_tau=W)
+    return wl
+
+
 def paired_hermitian(rng: np.random.Generator, kneg, N: int, scale: float) -> np.ndarray:
     """Hermitian positive matrices U^q with U^{-q} = conj(U^q)."""
     nk = len(kneg)

@@ -1,4 +1,5 @@
-"""Pins of the k-point (solid) oracle (PN8 and a supercell unfolding).
+"""Pins of the k-point (solid) oracle (PN8 and a supercell unfolding), for
+static and dynamic interactions.
 
   * the paper's k-point step chain equals the k-space 4-index brute force;
   * a Gamma-only mesh with real inputs equals the molecular oracle;
@@ -11,6 +12,12 @@
     every momentum label and both 1/N_k factors; a flipped label, a missing
     conjugate or a dropped 1/N_k each fail it), and the GM energy per cell
     equals the supercell energy divided by L.
+  * dynamic interaction (signed-frequency transforms of complex functions of
+    imaginary time): the eq:GG chain equals the brute force; a Gamma-only
+    real mesh and momentum-independent inputs equal the molecular dynamic
+    oracle; supercell unfolding of a translation-invariant W(tau) equals the
+    molecular dynamic oracle on the supercell (a wrong negative-frequency
+    transform, a real part taken too early or a lost 1/2 each fail it).
 """
 import numpy as np
 import pytest
@@ -99,3 +106,84 @@ def test_supercell_unfolding(L):
     e_sc = om.energy_gm(Ss, Gs[::-1], w)
     e_k = osd.energy_gm_k(Sk, Gk, w)
     assert abs(e_k - e_sc / L) <= 1e-12 * abs(e_sc)
+
+
+# ---------------------------------------------------------------------------
+# dynamic interaction
+def _pair(tau, beta, omega_max=10.0):
+    return synth.bosonic_transform_pair(tau, beta, omega_max=omega_max, tol=1e-10)
+
+
+def _dyn_solid(mesh, n, N, nt, beta, seed, n_poles=3):
+    wl = synth.solid(mesh, n, N, nt, beta, seed=seed)
+    return synth.add_dynamic_screening_solid(wl, n_poles=n_poles)
+
+
+@pytest.mark.parametrize("mesh", [(2, 1, 1), (3, 1, 1)])
+def test_dynamic_chain_equals_bruteforce(mesh):
+    wl = _dyn_solid(mesh, 3, 6, 12, 10.0, seed=4)
+    tp = _pair(wl["tau"], wl["beta"])
+    rng = np.random.default_rng(5)
+    G = osd.g_tau_k(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    G = G + 0.05 * (rng.standard_normal(G.shape) + 1j * rng.standard_normal(G.shape))
+    a = osd.sigma_solid_dynamic_eri(wl["X"], wl["W_tau"], wl["V"], G, tp["T_fwd"], tp["T_bwd"],
+                                    _tables(wl))
+    b = osd.sigma_solid_dynamic_thc(wl["X"], wl["W_tau"], wl["V"], G, tp["T_fwd"], tp["T_bwd"],
+                                    _tables(wl))
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(a).max()
+
+
+def test_dynamic_gamma_and_k_independent_equal_molecule():
+    wl = synth.small_molecule(5, 12, 16, 10.0, seed=11, dynamic=True)
+    tp = _pair(wl["tau"], wl["beta"], omega_max=14.0)
+    G = om.g_tau(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    ref = om.sigma_dynamic_thc(wl["X"], wl["W_tau"], wl["V"], G, G[::-1], tp["T_fwd"], tp["T_bwd"])
+    for mesh in [(1, 1, 1), (3, 1, 1)]:
+        tb = synth.kmesh_index(mesh)
+        nk = len(tb[0])
+        rep = lambda a: np.repeat(a[None], nk, axis=0).astype(complex)
+        S = osd.sigma_solid_dynamic_thc(rep(wl["X"]), rep(wl["W_tau"]), rep(wl["V"]), rep(G),
+                                        tp["T_fwd"], tp["T_bwd"], tb)
+        for k in range(nk):
+            assert np.abs(S[k] - ref).max() <= 1e-13 * np.abs(ref).max()
+
+
+def test_signed_frequency_transform_of_real_function_is_the_real_pair():
+    tau, _ = synth.chebyshev_tau_grid(24, 10.0)
+    tp = _pair(tau, 10.0)
+    f = synth.periodic_bosonic_pole(tau, 10.0, 0.8)[:, None] * np.array([1.0, -0.5])[None]
+    fp, fm = osd.matsubara_pm(tp["T_fwd"], f)
+    back = osd.imag_time_pm(tp["T_bwd"], fp, fm)
+    assert np.abs(back - om.imag_time(tp["T_bwd"], om.matsubara(tp["T_fwd"], f))).max() <= 1e-14
+    # a complex function is carried by its real and imaginary parts separately
+    g = f + 1j * synth.periodic_bosonic_pole(tau, 10.0, 2.1)[:, None]
+    gp, gm = osd.matsubara_pm(tp["T_fwd"], g)
+    back = osd.imag_time_pm(tp["T_bwd"], gp, gm)
+    assert np.abs(back - g).max() <= 1e-6 * np.abs(g).max()
+
+
+@pytest.mark.parametrize("L", [2, 3])
+def test_dynamic_supercell_unfolding(L):
+    n, N, nt, beta = 2, 3, 12, 6.0
+    rng = np.random.default_rng(20 + L)
+    tau, _ = synth.chebyshev_tau_grid(nt, beta)
+    tp = _pair(tau, beta)
+    x = rng.standard_normal((L, n, N)) * 0.5
+    u = rng.standard_normal((L, N, N)) * 0.3
+    u = 0.5 * (u + np.transpose(u[(-np.arange(L)) % L], (0, 2, 1)))
+    sm = rng.standard_normal((L, N, N)) * 0.3
+    sm = 0.5 * (sm + np.transpose(sm[(-np.arange(L)) % L], (0, 2, 1)))
+    wt = 0.05 * synth.periodic_bosonic_pole(tau, beta, 1.3)[:, None, None, None] * sm[None]
+    g = rng.standard_normal((nt, L, n, n)) * 0.3
+    Ss = om.sigma_dynamic_thc(_supercell(x, L), _supercell(wt, L), _supercell(u, L),
+                              _supercell(g, L), _supercell(g, L)[::-1], tp["T_fwd"], tp["T_bwd"])
+    sig = np.stack([Ss[:, R * n:(R + 1) * n, 0:n] for R in range(L)], axis=1)
+    tb = synth.kmesh_index((L, 1, 1))
+    ph = lambda s: np.exp(s * 2j * np.pi * np.outer(np.arange(L), np.arange(L)) / L)
+    Sk = osd.sigma_solid_dynamic_thc(np.einsum("kR,Rab->kab", ph(-1), x),
+                                     np.einsum("kR,tRab->ktab", ph(1), wt),
+                                     np.einsum("kR,Rab->kab", ph(1), u),
+                                     np.einsum("kR,tRab->ktab", ph(1), g),
+                                     tp["T_fwd"], tp["T_bwd"], tb)
+    pred = np.einsum("kR,tRab->ktab", ph(1), sig)
+    assert np.abs(Sk - pred).max() <= 1e-13 * np.abs(pred).max()
