@@ -28,13 +28,18 @@
  *     V, W0  [n_k, n_thc, n_thc]      U^q_PQ of the THC integrals
  *            (i k_i, j k_j | s k_s, r k_r) = sum_PQ conj(X^{k_i}_iP) X^{k_j}_jP
  *                                         U^q_PQ conj(X^{k_s}_sQ) X^{k_r}_rQ
+ *     W_tau  [n_k, n_tau, n_thc, n_thc] W^q(tau_j) (dynamic entry)
  *     G      [n_k, n_tau, n_orb, n_orb]
  *     Sigma  [n_k, n_tau, n_orb, n_orb]
  *   The k-point form of eq:sox carries 1/N_k per momentum sum (1/N_k^2 in
  *   all), k_s = k_p + k_q - k_t, and follows the momentum-resolved chain of
- *   the paper's solids section (Sigma_RP = -D_PR / N_k).  The bare and
- *   static entries, sox_build_g_tau and sox_energy_gm accept solids in fp64
- *   and fp32; the dynamic entry and the adjoint return SOX_ERR_UNSUPPORTED.
+ *   the paper's solids section (Sigma_RP = -D_PR / N_k).  The bare, static
+ *   and dynamic entries, sox_build_g_tau and sox_energy_gm accept solids in
+ *   fp64 and fp32; the adjoint returns SOX_ERR_UNSUPPORTED.  The dynamic
+ *   entry transforms complex functions of imaginary time at +Omega_m with
+ *   t_fwd and at -Omega_m with conj(t_fwd), and inverts with
+ *   f(tau) = 1/2 sum_m [t_bwd f(i Omega_m) + conj(t_bwd) f(-i Omega_m)]
+ *   (the same pair, extended from real to complex functions).
  * - Every tensor pointer is a DEVICE pointer owned by the caller.  Outputs
  *   are overwritten, never accumulated into.  `stream` is a hipStream_t
  *   (NULL = the null stream); all device work of a call is ordered on it
@@ -116,7 +121,8 @@ typedef struct {
 /* Create a plan: validates the problem, copies the grid, uploads the
  * quadrature weights and transform pair to the current HIP device and picks
  * the tile shapes and the tau-slab width.  The environment variable
- * SOX_WS_BUDGET_MB (default 32768) caps the workspace the plan asks for.
+ * SOX_WS_BUDGET_MB (default 65536) caps the workspace the plan asks for
+ * (when even the smallest slabs exceed it, the plan asks for those).
  * With SOX_AUTOTUNE=1 the plan times every wave-tile shape of the fused
  * B, C -> D kernel on the device (zero-filled operands of the plan's shape,
  * up to 8 tau nodes) and keeps the fastest; SOX_TUNE_CACHE=<file> stores and
@@ -151,7 +157,7 @@ sox_status sox_sigma_static(sox_plan* plan, const double* X, const double* W0, c
  * screened interaction W_tau [n_tau,N,N] (each slice symmetric), evaluated
  * with the paper's eq:GG scheme: GG -> FT -> W(Omega) GG(Omega) -> IFT ->
  * B, C, D -> Sigma, using the plan's transform pair.  The plan must have
- * n_omega > 0. */
+ * n_omega > 0.  Solids: W_tau, V, X, G, Sigma complex128 as listed above. */
 sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_tau, const double* V,
                              const double* G, double* Sigma, void* workspace,
                              size_t workspace_bytes, void* stream);

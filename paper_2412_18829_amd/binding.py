@@ -247,9 +247,10 @@ def sox_sigma_static(plan: Plan, X, W0, V, G, Sigma, ws=None, stream=None):
 def sox_sigma_dynamic(plan: Plan, X, W_tau, V, G, Sigma, ws=None, stream=None):
     n, N, nt = plan.n, plan.N, plan.n_tau
     w, wb = _ws_args(plan, "dynamic", ws)
-    _check(load().sox_sigma_dynamic(plan.handle, _f64(X, (n, N), "X"),
-                                    _f64(W_tau, (nt, N, N), "W_tau"), _f64(V, (N, N), "V"),
-                                    _f64(G, (nt, n, n), "G"), _f64(Sigma, (nt, n, n), "Sigma"),
+    t = plan._t
+    _check(load().sox_sigma_dynamic(plan.handle, t(X, (n, N), "X"),
+                                    t(W_tau, (nt, N, N), "W_tau"), t(V, (N, N), "V"),
+                                    t(G, (nt, n, n), "G"), t(Sigma, (nt, n, n), "Sigma"),
                                     w, wb, _stream(stream)), "sox_sigma_dynamic")
     return Sigma
 

@@ -93,7 +93,11 @@ struct sox_plan {
   int nk = 1;
   int vcs = 0;       // statically screened entry
   int vcs_bare = 0;  // bare entry (one U-tensor: wider slabs fit)
+  int dyn_ps = 0;    // dynamic entry: momentum pairs per slab
+  int dyn_ts = 0;    // dynamic entry: tau nodes per B, C, D slab
   int* d_ktab = nullptr;
+  double* d_tfc = nullptr;  // [n_omega][n_tau] complex T_fwd
+  double* d_tbc = nullptr;  // [n_tau][2 n_omega] complex [T_bwd / 2 | conj(T_bwd) / 2]
   // device copies
   double* d_tf2 = nullptr;  // [2 n_omega][n_tau]  Re / Im of t_fwd
   double* d_tb2 = nullptr;  // [n_tau][2 n_omega]  [Re t_bwd | -Im t_bwd]
@@ -231,7 +235,7 @@ DynLayout dyn_layout_for(const sox_plan& p, int vc, int eslab) {
 }
 
 size_t ws_budget() {
-  double budget_mb = 32768.0;
+  double budget_mb = 65536.0;
   if (const char* s = getenv("SOX_WS_BUDGET_MB")) {
     double v = atof(s);
     if (v > 0) budget_mb = v;
@@ -1374,6 +1378,7 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
     p->slab = p->vjp_slab = 1;
     p->vcs = pick_solid_vc(*p, SOX_ENTRY_STATIC);
     p->vcs_bare = pick_solid_vc(*p, SOX_ENTRY_BARE);
+    if (p->n_omega > 0) pick_solid_dyn(*p);
   } else {
     p->slab = pick_slab(*p, SOX_ENTRY_STATIC);
     p->vjp_slab = pick_vjp_slab(*p, SOX_ENTRY_STATIC);
@@ -1411,6 +1416,25 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
                                  : (size_t)nt * (p->n + 1) + 1;
     e = hipMalloc(&p->d_scratch, sizeof(double) * nsc);
   }
+  if (e == hipSuccess && p->nk > 1 && p->n_omega > 0) {
+    const int nw = p->n_omega;
+    std::vector<double> tbc((size_t)nt * 4 * nw);
+    for (int i = 0; i < nt; ++i)
+      for (int m = 0; m < nw; ++m) {
+        const double re = p->t_bwd[2 * ((size_t)i * nw + m)], im = p->t_bwd[2 * ((size_t)i * nw + m) + 1];
+        double* row = tbc.data() + (size_t)i * 4 * nw;
+        row[2 * m] = 0.5 * re;
+        row[2 * m + 1] = 0.5 * im;
+        row[2 * (nw + m)] = 0.5 * re;
+        row[2 * (nw + m) + 1] = -0.5 * im;
+      }
+    e = hipMalloc(&p->d_tfc, sizeof(double) * p->t_fwd.size());
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_tfc, p->t_fwd.data(), sizeof(double) * p->t_fwd.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMalloc(&p->d_tbc, sizeof(double) * tbc.size());
+    if (e == hipSuccess)
+      e = hipMemcpy(p->d_tbc, tbc.data(), sizeof(double) * tbc.size(), hipMemcpyHostToDevice);
+  }
   if (e == hipSuccess && p->nk > 1) {
     const std::vector<int> tab = solid_tables(p->mesh_canon);
     e = hipMalloc(&p->d_ktab, sizeof(int) * tab.size());
@@ -1445,6 +1469,8 @@ sox_status sox_plan_destroy(sox_plan* p) {
   if (p->d_w) (void)hipFree(p->d_w);
   if (p->d_scratch) (void)hipFree(p->d_scratch);
   if (p->d_ktab) (void)hipFree(p->d_ktab);
+  if (p->d_tfc) (void)hipFree(p->d_tfc);
+  if (p->d_tbc) (void)hipFree(p->d_tbc);
   delete p;
   return SOX_OK;
 }
@@ -1474,8 +1500,6 @@ sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_ta
                              size_t ws_bytes, void* stream) {
   sox_status st = check_plan(plan);
   if (st) return st;
-  if (plan->nk > 1)
-    return fail(SOX_ERR_UNSUPPORTED, "the dynamic entry is not implemented for k-point meshes");
   if (plan->n_omega <= 0)
     return fail(SOX_ERR_INVALID_ARG, "plan has no transform pair (n_omega = 0)");
   if (!X || !W_tau || !V || !G || !Sigma) return fail(SOX_ERR_INVALID_ARG, "NULL tensor pointer");
@@ -1485,6 +1509,11 @@ sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_ta
                             (uintptr_t)V, (uintptr_t)G, (uintptr_t)Sigma, (uintptr_t)ws,
                             (uintptr_t)ws_bytes, 0};
   return run_maybe_graph(*plan, key, (hipStream_t)stream, [&](hipStream_t s) -> sox_status {
+    if (plan->nk > 1) {
+      if (plan->precision == SOX_FP64)
+        return run_solid_dynamic<double>(*plan, X, W_tau, V, G, Sigma, ws, s);
+      return run_solid_dynamic<float>(*plan, X, W_tau, V, G, Sigma, ws, s);
+    }
     switch (plan->precision) {
       case SOX_FP64: return run_dynamic<double>(*plan, X, W_tau, V, G, Sigma, ws, s);
       case SOX_FP32: return run_dynamic<float>(*plan, X, W_tau, V, G, Sigma, ws, s);
@@ -1629,11 +1658,11 @@ sox_status sox_plan_describe(const sox_plan* plan, char* buf, size_t len) {
            "\"fused_cfg\":%d,\"fused_wave_tile\":[%d,%d],\"tau_slab\":%d,\"vjp_tau_slab\":%d,"
            "\"v_slab\":%d,\"vjp_v_slab\":%d,\"graph\":%d,\"tune_ms_per_tau\":%s,"
            "\"tune_from_cache\":%d,\"kmesh\":[%d,%d,%d],\"n_k\":%d,\"solid_v_slab\":%d,"
-           "\"solid_v_slab_bare\":%d}",
+           "\"solid_v_slab_bare\":%d,\"solid_dyn_pair_slab\":%d,\"solid_dyn_tau_slab\":%d}",
            plan->n, plan->N, plan->n_tau, plan->nP, plan->NP, plan->precision, plan->fused_cfg,
            fc.wp, fc.wr, plan->slab, plan->vjp_slab, plan->vc, plan->vc_vjp, plan->graph_on ? 1 : 0,
            tune.c_str(), plan->tune_from_cache ? 1 : 0, plan->kmesh[0], plan->kmesh[1],
-           plan->kmesh[2], plan->nk, plan->vcs, plan->vcs_bare);
+           plan->kmesh[2], plan->nk, plan->vcs, plan->vcs_bare, plan->dyn_ps, plan->dyn_ts);
   return SOX_OK;
 }
 

@@ -15,7 +15,9 @@
 // (idx ? idx[zo] : zo) * so + zi * si, so momentum-indexed gathers (k_v - q1,
 // k_w, q) come from small device tables.  Row r of A or B sits at
 // (r / split) * hi + (r % split) * ld, which lets one kernel read the
-// U-tensor [a][P][b] as rows (P, a).  Inside a workgroup, v = 0 .. nv-1
+// U-tensor [a][P][b] as rows (P, a); element k of a row is ks elements past
+// element k - 1 (ks = 1 for K-contiguous rows, the row count of a K-major
+// operand otherwise).  Inside a workgroup, v = 0 .. nv-1
 // offsets A, B and C by v * vsA, v * vsB, v * vsC: one operand of the B and
 // C steps is the same for every v (vs = 0) and stays in cache, and the
 // software pipeline runs on across the v boundary.
@@ -51,6 +53,7 @@ template <typename T, typename TC> struct CgArgs {
   long soA, soB, soS, soC;
   long siA, siB, siS, siC;
   long vsA, vsB, vsC;
+  long ksA, ksB;  // k strides of A and B (1: K-contiguous rows)
   int nzi, nz, nv;
   int splitA, splitB;
   long ldA, hiA, ldB, hiB, ldc;
@@ -162,10 +165,11 @@ __global__ __launch_bounds__(64 * WGR * WGC) void cgemm_nt_kernel(const CgArgs<T
     for (int m = 0; m < 4; ++m) {
       int k = kc * 16 + 4 * m + g;
       k = k < p.K ? k : p.K - 1;
+      const long ka = (long)k * p.ksA, kb = (long)k * p.ksB;
 #pragma unroll
-      for (int i = 0; i < RB; ++i) ra[i][m] = Av[aoff[i] + k];
+      for (int i = 0; i < RB; ++i) ra[i][m] = Av[aoff[i] + ka];
 #pragma unroll
-      for (int j = 0; j < CB; ++j) rb[j][m] = Bv[boff[j] + k];
+      for (int j = 0; j < CB; ++j) rb[j][m] = Bv[boff[j] + kb];
       rs[m] = Sb ? Sb[k] : V2{T(0), T(0)};
     }
   };
@@ -236,6 +240,7 @@ template <typename T, typename TC> inline CgArgs<T, TC> cg_args() {
   CgArgs<T, TC> a{};
   a.nzi = 1;
   a.nv = 1;
+  a.ksA = a.ksB = 1;
   a.splitA = a.splitB = 1 << 30;
   a.alpha = T(1);
   return a;
@@ -286,15 +291,19 @@ template <typename T, int M1, int M2, int M3>
 __global__ __launch_bounds__(256) void dstep_mesh_kernel(const T* __restrict__ B,
                                                          const T* __restrict__ C, double* D,
                                                          long NN, long sp, int nv, int gk,
-                                                         double scale, int accumulate) {
+                                                         long sbt, long sdt, double scale,
+                                                         int accumulate) {
   constexpr int NK = M1 * M2 * M3;
   using V2 = vec2_t<T>;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= NN) return;
-  // workgroup row y sums k_v in [y gk, y gk + gk) into its own partial D
+  // workgroup row y sums k_v in [y gk, y gk + gk) into its own partial D;
+  // grid layer z is the z-th tau node of a slab (B, C sbt and D sdt apart)
   const int kv0 = blockIdx.y * gk;
   const int kv1 = kv0 + gk < NK ? kv0 + gk : NK;
-  D += 2 * (long)blockIdx.y * NK * NN;
+  D += 2 * ((long)blockIdx.y * NK * NN + (long)blockIdx.z * sdt);
+  B += 2 * (long)blockIdx.z * sbt;
+  C += 2 * (long)blockIdx.z * sbt;
   const V2* Bp = (const V2*)B + e;
   const V2* Cp = (const V2*)C + e;
   double dr[NK], di[NK];
@@ -356,11 +365,14 @@ template <typename T>
 __global__ __launch_bounds__(256) void dstep_any_kernel(const T* __restrict__ B,
                                                         const T* __restrict__ C,
                                                         const int* __restrict__ kdiff, double* D,
-                                                        long NN, int nk, long sp, int nv,
-                                                        double scale, int accumulate) {
+                                                        long NN, int nk, long sp, int nv, long sbt,
+                                                        long sdt, double scale, int accumulate) {
   using V2 = vec2_t<T>;
   const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= NN * nk) return;
+  D += 2 * (long)blockIdx.y * sdt;
+  B += 2 * (long)blockIdx.y * sbt;
+  C += 2 * (long)blockIdx.y * sbt;
   const int kt = (int)(idx / NN);
   const long e = idx - (long)kt * NN;
   const V2* Bp = (const V2*)B + e;
@@ -387,6 +399,33 @@ __global__ __launch_bounds__(256) void dstep_any_kernel(const T* __restrict__ B,
   }
   o[0] = re;
   o[1] = im;
+}
+
+// ---------------------------------------------------------------------------
+// eq:GG for a slab of momentum pairs and one orbital v (float64):
+//   GG[tau][l][u][Q] = GwP^{k_v - q1}(tau)[u][Q] * GRqT^{k_v}(beta - tau)[v][Q]
+// for pair = p0 + l = q1 n_k + k_v; GwP and GRqT are stored [tau][k][n][N].
+__global__ __launch_bounds__(256) void gg_solid_kernel(const double* __restrict__ gwp,
+                                                       const double* __restrict__ grqt,
+                                                       const int* __restrict__ k_of,
+                                                       const int* __restrict__ kmq_of, double* gg,
+                                                       int nt, int nk, int n, int N, int p0, int cnt,
+                                                       int ps, int v) {
+  const long per = (long)n * N;
+  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long)nt * cnt * per) return;
+  const long tl = idx / per;
+  const long uq = idx - tl * per;
+  const int t = (int)(tl / cnt);
+  const int l = (int)(tl - (long)t * cnt);
+  const int Q = (int)(uq % N);
+  const int pair = p0 + l;
+  const int kv = k_of[pair], kq = kmq_of[pair];
+  const double* a = gwp + 2 * (((long)t * nk + kq) * per + uq);
+  const double* b = grqt + 2 * (((long)(nt - 1 - t) * nk + kv) * per + (long)v * N + Q);
+  double* o = gg + 2 * (((long)t * ps + l) * per + uq);
+  o[0] = a[0] * b[0] - a[1] * b[1];
+  o[1] = a[0] * b[1] + a[1] * b[0];
 }
 
 // ---------------------------------------------------------------------------

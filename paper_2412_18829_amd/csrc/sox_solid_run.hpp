@@ -58,8 +58,10 @@ SolidLayout solid_layout_for(const sox_plan& p, int entry, int vc) {
 
 int solid_vc(const sox_plan& p, int entry) { return entry == SOX_ENTRY_BARE ? p.vcs_bare : p.vcs; }
 
+size_t solid_dyn_total(const sox_plan& p);  // with the dynamic launch sequence
+
 size_t solid_workspace_bytes(const sox_plan& p, int entry) {
-  if (entry == SOX_ENTRY_DYNAMIC) return 0;
+  if (entry == SOX_ENTRY_DYNAMIC) return p.n_omega > 0 ? solid_dyn_total(p) : 0;
   return solid_layout_for(p, entry, solid_vc(p, entry)).total;
 }
 
@@ -101,11 +103,18 @@ std::vector<int> solid_tables(const int mesh[3]) {
 // step, whose 64 rows hold every v so that each U-tensor row is read once.
 // 2: the B and C steps, five wavefronts stacked along the rows, each 16 x 80
 // (float32) or 16 x 16 (float64): an 80 x 80 or 80 x 16 tile, which divides
-// N = 400 exactly.
+// N = 400 exactly.  3: 128 x 64 (eight 64 x 16 wavefronts), for the inverse
+// transform over up to 128 tau nodes.  4: 80 x 64 (float32) or 80 x 32
+// (float64) for W(Omega) GG(Omega), whose columns are the n orbitals u.
 template <typename T, typename TC>
 sox_status cg_launch(const CgArgs<T, TC>& a, int nz, int shape, hipStream_t s) {
   if (shape == 1) {
     SOX_HIP((launch_cgemm<T, TC, 1, 4, 4, 1>(a, nz, s)));
+  } else if (shape == 3) {
+    SOX_HIP((launch_cgemm<T, TC, 2, 4, 4, 1>(a, nz, s)));
+  } else if (shape == 4) {
+    if constexpr (sizeof(T) == 4) SOX_HIP((launch_cgemm<T, TC, 5, 1, 1, 4>(a, nz, s)));
+    else SOX_HIP((launch_cgemm<T, TC, 5, 1, 1, 2>(a, nz, s)));
   } else if (shape == 2) {
     if constexpr (sizeof(T) == 4) SOX_HIP((launch_cgemm<T, TC, 5, 1, 1, 5>(a, nz, s)));
     else SOX_HIP((launch_cgemm<T, TC, 5, 1, 1, 1>(a, nz, s)));
@@ -122,26 +131,28 @@ int bc_shape(int N) {
   return w80 < w64 ? 2 : 0;
 }
 
-// D (+)= the D step of one v slab.  The templated kernels write per-group
-// partial sums into Dp (accumulated over the slabs of a node); the caller
-// sums the groups into D once per node (solid_dsum).  The any-mesh kernel
-// writes D directly.
+// D (+)= the D step of nv orbitals v for ntl tau nodes (B and C sbt apart
+// per node, pairs sp apart; D sdt apart).  grouped: the templated kernels
+// split k_v over solid_dgroups(p) workgroup rows that write per-group partial
+// sums into Dp (summed by solid_dsum); otherwise, and for the any-mesh
+// kernel, D is written directly.
 template <typename T>
-sox_status launch_dstep(const sox_plan& p, const T* B, const T* C, double* D, double* Dp, int vcs,
-                        int nv, bool acc, hipStream_t s) {
+sox_status launch_dstep(const sox_plan& p, const T* B, const T* C, double* D, double* Dp, long sp,
+                        int nv, int ntl, long sbt, long sdt, bool grouped, bool acc,
+                        hipStream_t s) {
   const long NN = (long)p.N * p.N;
-  const long sp = (long)vcs * NN;
   const double scale = 1.0 / p.nk;
-  const int ng = solid_dgroups(p);
+  const int ng = grouped ? solid_dgroups(p) : 1;
   const int gk = (p.nk + ng - 1) / ng;
-  const dim3 grid((unsigned)((NN + 255) / 256), (unsigned)ng);
+  double* out = grouped ? Dp : D;
+  const dim3 grid((unsigned)((NN + 255) / 256), (unsigned)ng, (unsigned)ntl);
   const int* m = p.mesh_canon;
-#define SOX_DSTEP(A_, B_, C_)                                                                  \
-  if (m[0] == A_ && m[1] == B_ && m[2] == C_) {                                               \
-    hipLaunchKernelGGL((dstep_mesh_kernel<T, A_, B_, C_>), grid, dim3(256), 0, s, B, C, Dp, NN, \
-                       sp, nv, gk, scale, acc ? 1 : 0);                                        \
-    SOX_HIP(hipGetLastError());                                                                \
-    return SOX_OK;                                                                             \
+#define SOX_DSTEP(A_, B_, C_)                                                                 \
+  if (m[0] == A_ && m[1] == B_ && m[2] == C_) {                                              \
+    hipLaunchKernelGGL((dstep_mesh_kernel<T, A_, B_, C_>), grid, dim3(256), 0, s, B, C, out,   \
+                       NN, sp, nv, gk, sbt, sdt, scale, acc ? 1 : 0);                         \
+    SOX_HIP(hipGetLastError());                                                               \
+    return SOX_OK;                                                                            \
   }
   SOX_DSTEP(2, 1, 1)
   SOX_DSTEP(3, 1, 1)
@@ -153,9 +164,9 @@ sox_status launch_dstep(const sox_plan& p, const T* B, const T* C, double* D, do
   SOX_DSTEP(3, 3, 3)
 #undef SOX_DSTEP
   const long tot = NN * p.nk;
-  hipLaunchKernelGGL((dstep_any_kernel<T>), dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
-                     B, C, p.d_ktab + 3 * (size_t)p.nk * p.nk, D, NN, p.nk, sp, nv, scale,
-                     acc ? 1 : 0);
+  hipLaunchKernelGGL((dstep_any_kernel<T>), dim3((unsigned)((tot + 255) / 256), (unsigned)ntl),
+                     dim3(256), 0, s, B, C, p.d_ktab + 3 * (size_t)p.nk * p.nk, D, NN, p.nk, sp,
+                     nv, sbt, sdt, scale, acc ? 1 : 0);
   SOX_HIP(hipGetLastError());
   return SOX_OK;
 }
@@ -301,7 +312,9 @@ sox_status run_solid(sox_plan& p, int entry, const double* X, const double* U1, 
       }
       {
         ProfScope ps(p, SOX_STAGE_KD, s);
-        if ((st = launch_dstep<T>(p, bbuf, cbuf, dbuf, dpart, vcs, cnt, v0 > 0, s))) return st;
+        if ((st = launch_dstep<T>(p, bbuf, cbuf, dbuf, dpart, (long)vcs * N * N, cnt, 1, 0, 0,
+                                  true, v0 > 0, s)))
+          return st;
       }
     }
     {
@@ -367,5 +380,242 @@ sox_status solid_energy(sox_plan& p, const double* Sigma, const double* G, doubl
   }
   SOX_HIP(hipMemcpyAsync(E_host, e, sizeof(double), hipMemcpyDeviceToHost, s));
   SOX_HIP(hipStreamSynchronize(s));
+  return SOX_OK;
+}
+
+// -----------------------------------------------------------------------------
+// Dynamic interaction on a k-point mesh (eq:GG for solids).
+//
+// Functions of imaginary time are complex here, so the plan's transform pair
+// (made for real functions) is applied at +Omega_m with T_fwd and at -Omega_m
+// with conj(T_fwd); the inverse transform is
+// f(tau) = 1/2 sum_m [T_bwd f(+i Omega_m) + conj(T_bwd) f(-i Omega_m)], one
+// product with the [n_tau][2 n_omega] matrix d_tbc.  The periodic convolution
+// W^{q1} * GG becomes one W(Omega) GG(Omega) product per signed frequency.
+//
+// v runs outermost (the paper moves v to an outer loop for memory).  For
+// each v: per slab of momentum pairs, GG(tau) -> FT -> W GG -> IFT gives
+// A^{pair}(tau)[P][u] for every node; then per slab of tau nodes, B = A X,
+// C = GwPt Ut2^v and the D step accumulate into D(tau) of every node.  The
+// projections, GG and both transforms run in float64, W GG, B, C and D in the
+// plan's precision; D and the back-transform in float64.
+struct SolidDynLayout {
+  size_t ut2, xtd, gtd, xtt, gwpd, grqtd, gwpt, wm, gg, ggw, aw, atau, bbuf, cbuf, dtau, ebuf, total;
+};
+
+SolidDynLayout solid_dyn_layout_for(const sox_plan& p, int ps, int ts) {
+  SolidDynLayout L{};
+  const size_t es = 2 * elem_size(p.precision);
+  const size_t n = p.n, N = p.N, nt = p.n_tau, nk = p.nk, np2 = nk * nk, nw = p.n_omega;
+  Carver c;
+  L.ut2 = c.take(np2 * n * N * n * es);
+  L.xtd = c.take(nk * N * n * 16);
+  L.gtd = c.take(nk * nt * n * n * 16);
+  L.xtt = c.take(nk * N * n * es);
+  L.gwpd = c.take(nt * nk * n * N * 16);
+  L.grqtd = c.take(nt * nk * n * N * 16);
+  L.gwpt = c.take(nt * nk * N * n * es);
+  L.wm = c.take(nk * 2 * nw * N * N * es);
+  L.gg = c.take(nt * (size_t)ps * n * N * 16);
+  L.ggw = c.take(2 * nw * (size_t)ps * n * N * es);
+  L.aw = c.take(2 * nw * (size_t)ps * N * n * 16);
+  L.atau = c.take(nt * np2 * N * n * es);
+  L.bbuf = c.take((size_t)ts * np2 * N * N * es);
+  L.cbuf = c.take((size_t)ts * np2 * N * N * es);
+  L.dtau = c.take(nt * nk * N * N * 16);
+  L.ebuf = c.take(nt * nk * n * N * 16);
+  L.total = c.off;
+  return L;
+}
+
+// Pair slab ps and tau slab ts within the budget: halve the pair slab first
+// (down to one momentum transfer, n_k pairs), then the tau slab, then the
+// pair slab further.
+void pick_solid_dyn(sox_plan& p) {
+  const size_t budget = ws_budget();
+  const int np2 = p.nk * p.nk;
+  int ps = np2, ts = std::min(p.n_tau, 8);
+  while (ps > p.nk && solid_dyn_layout_for(p, ps, ts).total > budget) ps = (ps + 1) / 2;
+  while (ts > 1 && solid_dyn_layout_for(p, ps, ts).total > budget) ts = (ts + 1) / 2;
+  while (ps > 1 && solid_dyn_layout_for(p, ps, ts).total > budget) ps = (ps + 1) / 2;
+  p.dyn_ps = ps;
+  p.dyn_ts = ts;
+}
+
+size_t solid_dyn_total(const sox_plan& p) { return solid_dyn_layout_for(p, p.dyn_ps, p.dyn_ts).total; }
+
+template <typename T>
+sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, const double* V,
+                             const double* G, double* Sigma, void* ws, hipStream_t s) {
+  const int n = p.n, N = p.N, nt = p.n_tau, nk = p.nk, np2 = nk * nk, nw = p.n_omega;
+  const int ps = p.dyn_ps, ts = p.dyn_ts;
+  const SolidDynLayout L = solid_dyn_layout_for(p, ps, ts);
+  char* base = (char*)ws;
+  T* ut2 = (T*)(base + L.ut2);
+  double* xtd = (double*)(base + L.xtd);
+  double* gtd = (double*)(base + L.gtd);
+  T* xtt = (T*)(base + L.xtt);
+  double* gwpd = (double*)(base + L.gwpd);
+  double* grqtd = (double*)(base + L.grqtd);
+  T* gwpt = (T*)(base + L.gwpt);
+  T* wm = (T*)(base + L.wm);
+  double* gg = (double*)(base + L.gg);
+  T* ggw = (T*)(base + L.ggw);
+  double* aw = (double*)(base + L.aw);
+  T* atau = (T*)(base + L.atau);
+  T* bbuf = (T*)(base + L.bbuf);
+  T* cbuf = (T*)(base + L.cbuf);
+  double* dtau = (double*)(base + L.dtau);
+  double* ebuf = (double*)(base + L.ebuf);
+  const int* kOf = p.d_ktab;
+  const int* qOf = p.d_ktab + np2;
+  const int* kmqOf = p.d_ktab + 2 * np2;
+  const long nN = (long)n * N, NN = (long)N * N;
+  sox_status st;
+  {
+    ProfScope ps_(p, SOX_STAGE_UTENSOR, s);
+    if ((st = launch_solid_utensor<T>(p, V, X, ut2, s))) return st;
+  }
+  {
+    ProfScope ps_(p, SOX_STAGE_PROJECT, s);
+    if ((st = launch_ctranspose<double, double>(X, xtd, n, N, nk, s))) return st;
+    for (long b0 = 0; b0 < (long)nk * nt; b0 += 65535) {
+      const long cnt = std::min(65535L, (long)nk * nt - b0);
+      if ((st = launch_ctranspose<double, double>(G + 2 * b0 * n * n, gtd + 2 * b0 * n * n, n, n,
+                                                  cnt, s)))
+        return st;
+    }
+    const long cx = 2L * nk * N * n;
+    hipLaunchKernelGGL((cast_kernel<T>), dim3((unsigned)((cx + 255) / 256)), dim3(256), 0, s, xtd,
+                       xtt, cx);
+    SOX_HIP(hipGetLastError());
+    // GwP^k(tau)[w][P] = sum_p G^k_wp conj(X^k_pP)        (float64, for GG)
+    CgArgs<double, double> a = cg_args<double, double>();
+    a.A = G; a.soA = (long)nt * n * n; a.siA = (long)n * n; a.ldA = n;
+    a.B = xtd; a.soB = nN; a.ldB = n; a.conjB = 1;
+    a.C = gwpd; a.soC = nN; a.siC = (long)nk * nN; a.ldc = N;
+    a.nzi = nt;
+    a.M = n; a.N = N; a.K = n;
+    if ((st = cg_launch(a, nk * nt, 0, s))) return st;
+    // GRqT^k(tau)[v][Q] = sum_s G^k_sv X^k_sQ                (float64, for GG)
+    a = cg_args<double, double>();
+    a.A = gtd; a.soA = (long)nt * n * n; a.siA = (long)n * n; a.ldA = n;
+    a.B = xtd; a.soB = nN; a.ldB = n;
+    a.C = grqtd; a.soC = nN; a.siC = (long)nk * nN; a.ldc = N;
+    a.nzi = nt;
+    a.M = n; a.N = N; a.K = n;
+    if ((st = cg_launch(a, nk * nt, 0, s))) return st;
+    // GwPt^k(tau)[P][w] in the plan's precision (the C step)
+    CgArgs<double, T> b = cg_args<double, T>();
+    b.A = xtd; b.soA = nN; b.ldA = n; b.conjA = 1;
+    b.B = G; b.soB = (long)nt * n * n; b.siB = (long)n * n; b.ldB = n;
+    b.C = gwpt; b.soC = nN; b.siC = (long)nk * nN; b.ldc = n;
+    b.nzi = nt;
+    b.M = N; b.N = n; b.K = n;
+    if ((st = cg_launch(b, nk * nt, 0, s))) return st;
+  }
+  {
+    // W^q(+-Omega)[P][Q] = sum_j T_fwd(*)[m][j] W^q(tau_j)[P][Q]
+    ProfScope ps_(p, SOX_STAGE_GG_FT, s);
+    for (int sg = 0; sg < 2; ++sg) {
+      CgArgs<double, T> a = cg_args<double, T>();
+      a.A = p.d_tfc; a.ldA = nt; a.soA = 0; a.conjA = sg;
+      a.B = W; a.soB = (long)nt * NN; a.ldB = 1; a.ksB = NN;
+      a.C = wm + 2 * (long)sg * nw * NN; a.soC = 2L * nw * NN; a.ldc = NN;
+      a.M = nw; a.N = (int)NN; a.K = nt;
+      if ((st = cg_launch(a, nk, 1, s))) return st;
+    }
+  }
+  for (int v = 0; v < n; ++v) {
+    for (int p0 = 0; p0 < np2; p0 += ps) {
+      const int cp = std::min(ps, np2 - p0);
+      {
+        ProfScope ps_(p, SOX_STAGE_GG_FT, s);
+        const long tot = (long)nt * cp * nN;
+        hipLaunchKernelGGL(gg_solid_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                           gwpd, grqtd, kOf, kmqOf, gg, nt, nk, n, N, p0, cp, ps, v);
+        SOX_HIP(hipGetLastError());
+        for (int sg = 0; sg < 2; ++sg) {
+          CgArgs<double, T> a = cg_args<double, T>();
+          a.A = p.d_tfc; a.ldA = nt; a.conjA = sg;
+          a.B = gg; a.ldB = 1; a.ksB = (long)ps * nN;
+          a.C = ggw + 2 * (long)sg * nw * ps * nN; a.ldc = (long)ps * nN;
+          a.M = nw; a.N = (int)(cp * nN); a.K = nt;
+          if ((st = cg_launch(a, 1, 1, s))) return st;
+        }
+      }
+      {
+        // A(+-Omega)[l][P][u] = sum_Q W^{q1}(+-Omega)[P][Q] GG(+-Omega)[l][u][Q]
+        ProfScope ps_(p, SOX_STAGE_WGEMM, s);
+        CgArgs<T, double> a = cg_args<T, double>();
+        a.A = wm; a.idxA = qOf + p0; a.soA = 2L * nw * NN; a.siA = NN; a.ldA = N;
+        a.B = ggw; a.soB = nN; a.siB = (long)ps * nN; a.ldB = N;
+        a.C = aw; a.soC = nN; a.siC = (long)ps * nN; a.ldc = n;
+        a.nzi = 2 * nw;
+        a.M = N; a.N = n; a.K = N;
+        if ((st = cg_launch(a, cp * 2 * nw, 4, s))) return st;
+      }
+      {
+        // A(tau)[pair][P][u] = sum_{+-m} Tb[tau][+-m] A(+-Omega_m)[l][P][u]
+        ProfScope ps_(p, SOX_STAGE_IFT, s);
+        CgArgs<double, T> a = cg_args<double, T>();
+        a.A = p.d_tbc; a.ldA = 2 * nw;
+        a.B = aw; a.ldB = 1; a.ksB = (long)ps * nN;
+        a.C = atau + 2 * (long)p0 * nN; a.ldc = (long)np2 * nN;
+        a.M = nt; a.N = (int)(cp * nN); a.K = 2 * nw;
+        if ((st = cg_launch(a, 1, 3, s))) return st;
+      }
+    }
+    for (int t0 = 0; t0 < nt; t0 += ts) {
+      const int ct = std::min(ts, nt - t0);
+      {
+        ProfScope ps_(p, SOX_STAGE_KBC, s);
+        // B[l][pair][P][R] = sum_u A(tau)[pair][P][u] X^{k_v - q1}[u][R]
+        CgArgs<T, T> b = cg_args<T, T>();
+        b.A = atau + 2 * (long)t0 * np2 * nN; b.soA = nN; b.siA = (long)np2 * nN; b.ldA = n;
+        b.B = xtt; b.idxB = kmqOf; b.soB = nN; b.ldB = n;
+        b.C = bbuf; b.soC = NN; b.siC = (long)np2 * NN; b.ldc = N;
+        b.nzi = ct;
+        b.M = N; b.N = N; b.K = n;
+        if ((st = cg_launch(b, np2 * ct, bc_shape(N), s))) return st;
+      }
+      {
+        ProfScope ps_(p, SOX_STAGE_KBC, s);
+        // C[l][pair][P][R] = sum_w GwPt^{k_w}(tau)[P][w] Ut2[pair][v][R][w]
+        CgArgs<T, T> c = cg_args<T, T>();
+        c.A = gwpt + 2 * (long)t0 * nk * nN; c.idxA = kOf; c.soA = nN; c.siA = (long)nk * nN;
+        c.ldA = n;
+        c.B = ut2 + 2 * (long)v * nN; c.soB = (long)n * nN; c.ldB = n;
+        c.C = cbuf; c.soC = NN; c.siC = (long)np2 * NN; c.ldc = N;
+        c.nzi = ct;
+        c.M = N; c.N = N; c.K = n;
+        if ((st = cg_launch(c, np2 * ct, bc_shape(N), s))) return st;
+      }
+      {
+        ProfScope ps_(p, SOX_STAGE_KD, s);
+        if ((st = launch_dstep<T>(p, bbuf, cbuf, dtau + 2 * (long)t0 * nk * NN, nullptr, NN, 1,
+                                  ct, (long)np2 * NN, (long)nk * NN, false, v > 0, s)))
+          return st;
+      }
+    }
+  }
+  {
+    ProfScope ps_(p, SOX_STAGE_BACK, s);
+    CgArgs<double, double> e = cg_args<double, double>();
+    e.A = X; e.soA = nN; e.ldA = N; e.conjA = 1;
+    e.B = dtau; e.soB = NN; e.siB = (long)nk * NN; e.ldB = N;
+    e.C = ebuf; e.soC = nN; e.siC = (long)nk * nN; e.ldc = N;
+    e.nzi = nt;
+    e.M = n; e.N = N; e.K = N;
+    if ((st = cg_launch(e, nk * nt, 0, s))) return st;
+    CgArgs<double, double> f = cg_args<double, double>();
+    f.A = ebuf; f.soA = nN; f.siA = (long)nk * nN; f.ldA = N;
+    f.B = X; f.soB = nN; f.ldB = N;
+    f.C = Sigma; f.soC = (long)nt * n * n; f.siC = (long)n * n; f.ldc = n;
+    f.nzi = nt;
+    f.alpha = -1.0 / nk;
+    f.M = n; f.N = n; f.K = N;
+    if ((st = cg_launch(f, nk * nt, 0, s))) return st;
+  }
   return SOX_OK;
 }

@@ -84,6 +84,9 @@ int run_solid_case(int n, int N, int nt, int prec, int entry, const int mesh[3])
   pr.n_orb = n; pr.n_thc = N; pr.n_tau = nt;
   for (int i = 0; i < 3; ++i) pr.kmesh[i] = mesh[i];
   pr.beta = beta; pr.tau = tau.data(); pr.weights = w.data();
+  const int nw = 3;
+  std::vector<double> tf(2 * nw * nt, 0.01), tb(2 * nw * nt, 0.01);
+  if (entry == 2) { pr.n_omega = nw; pr.t_fwd = tf.data(); pr.t_bwd = tb.data(); }
   sox_plan* plan = nullptr;
   if (sox_plan_create(&pr, prec, &plan)) { printf("create failed: %s\n", sox_last_error()); return 1; }
   size_t wsb = 0;
@@ -91,7 +94,7 @@ int run_solid_case(int n, int N, int nt, int prec, int entry, const int mesh[3])
   g_ws_size = wsb + 4096;
   g_ws_base = (char*)aligned_alloc(256, (g_ws_size + 255) & ~size_t(255));
   double* X = dalloc(2 * (size_t)nk * n * N);
-  double* U1 = dalloc(2 * (size_t)nk * N * N);
+  double* U1 = dalloc(2 * (size_t)nk * N * N * (entry == 2 ? nt : 1));
   double* U2 = dalloc(2 * (size_t)nk * N * N);
   double* Q = dalloc(2 * (size_t)nk * n * n);
   double* eps = dalloc((size_t)nk * n, 3.0);
@@ -100,10 +103,14 @@ int run_solid_case(int n, int N, int nt, int prec, int entry, const int mesh[3])
   sox_status st = sox_build_g_tau(plan, Q, eps, 0.0, G, nullptr);
   if (!st) {
     if (entry == 0) st = sox_sigma_bare(plan, X, U1, G, S, g_ws_base, wsb, nullptr);
-    else st = sox_sigma_static(plan, X, U1, U2, G, S, g_ws_base, wsb, nullptr);
+    else if (entry == 1) st = sox_sigma_static(plan, X, U1, U2, G, S, g_ws_base, wsb, nullptr);
+    else st = sox_sigma_dynamic(plan, X, U1, U2, G, S, g_ws_base, wsb, nullptr);
   }
   double E = 0.0;
   if (!st) st = sox_energy_gm(plan, S, G, &E, nullptr);
+  char desc[1024];
+  sox_plan_describe(plan, desc, sizeof(desc));
+  printf("plan %s\n", desc);
   printf("case n=%d N=%d nt=%d prec=%d entry=%d mesh=%dx%dx%d -> status %d %s\n", n, N, nt, prec,
          entry, mesh[0], mesh[1], mesh[2], st, st ? sox_last_error() : "");
   ASAN_UNPOISON_MEMORY_REGION(g_ws_base, g_ws_size);

@@ -70,6 +70,9 @@ SOLID_CASES = [
     (9, 40, 2, 1, 1, (3, 1, 1), "1"),
     (5, 160, 1, 1, 0, (3, 1, 1), None),   # 80 x 80 B / C tiles (float32)
     (4, 80, 1, 0, 1, (2, 1, 1), None),    # 80 x 16 B / C tiles (float64)
+    (3, 10, 4, 1, 2, (3, 1, 1), None),    # dynamic entry, templated D step
+    (4, 17, 3, 0, 2, (4, 1, 1), None),    # dynamic entry, any-mesh D step
+    (5, 80, 3, 1, 2, (2, 2, 1), "1"),     # dynamic entry, pair and tau slabs
 ]
 
 

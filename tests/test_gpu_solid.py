@@ -7,8 +7,9 @@ oracle's step chain; ragged n and N span several tiles.  At the full
 3x3x3, n = 52, N = 400, 100-node shape the oracle cannot run in seconds, so
 the launch configuration of the benchmark is checked by properties that hold
 at any size: momentum-independent real inputs must reproduce the molecular
-oracle (at sampled tau nodes), and with U1 = U2 and Hermitian G^k every
-Sigma^k(tau) must be Hermitian.
+oracle (static: at sampled tau nodes; dynamic: every node), and with U1 = U2
+and Hermitian G^k every Sigma^k(tau) must be Hermitian.  The dynamic entry
+is compared with the oracle's eq:GG chain for solids on small meshes.
 
 Tolerances (max |diff| / max |oracle|): fp64 1e-12, fp32 1e-6.
 """
@@ -210,3 +211,109 @@ def test_full_size_hermitian(B):
     log(f"  hermiticity defect {herm:.3e}, energy {e:.6e}")
     assert herm <= TOL["fp32"]
     assert np.isfinite(e)
+
+
+# ---------------------------------------------------------------------------
+# dynamic interaction (eq:GG for solids)
+def _tp(wl, omega_max=10.0):
+    return synth.bosonic_transform_pair(wl["tau"], wl["beta"], omega_max=omega_max, tol=1e-10)
+
+
+def _dyn_plan(B, wl, tp, precision):
+    return B.Plan(wl["n"], wl["N"], wl["tau"], wl["weights"], wl["beta"], precision=precision,
+                  kmesh=wl["mesh"], t_fwd=tp["T_fwd"], t_bwd=tp["T_bwd"])
+
+
+DYN_SHAPES = [
+    ((2, 1, 1), 5, 20, 12),
+    ((3, 1, 1), 7, 33, 10),
+    ((2, 2, 1), 4, 18, 8),
+    ((3, 3, 3), 3, 12, 6),
+    ((4, 1, 1), 3, 10, 8),
+]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("shape", DYN_SHAPES, ids=lambda s: "x".join(map(str, s[0])) + f"-{s[1]}-{s[2]}")
+def test_dynamic_vs_oracle(B, precision, shape):
+    """fp64 bound: ten times the oracle's own chain-vs-brute-force spread (the
+    transform pair is ill-conditioned), at least 1e-11, and 1e-10 on the
+    3x3x3 mesh, whose brute force takes minutes; fp32: 1e-6."""
+    import torch
+    mesh, n, N, nt = shape
+    log(f"solid dynamic {shape} {precision}")
+    wl = synth.add_dynamic_screening_solid(synth.solid(mesh, n, N, nt, 10.0, seed=7 * n + N),
+                                           n_poles=3)
+    tp = _tp(wl)
+    G = _general_G(wl, n + 2)
+    plan = _dyn_plan(B, wl, tp, precision)
+    S = torch.empty(G.shape, dtype=torch.complex128, device="cuda")
+    B.sox_sigma_dynamic(plan, cdev(wl["X"]), cdev(wl["W_tau"]), cdev(wl["V"]), cdev(G), S)
+    torch.cuda.synchronize()
+    ref = osd.sigma_solid_dynamic_thc(wl["X"], wl["W_tau"], wl["V"], G, tp["T_fwd"], tp["T_bwd"],
+                                      _tables(wl))
+    tol = TOL[precision]
+    if precision == "fp64":
+        if wl["nk"] <= 8:
+            bf = osd.sigma_solid_dynamic_eri(wl["X"], wl["W_tau"], wl["V"], G, tp["T_fwd"],
+                                             tp["T_bwd"], _tables(wl))
+            tol = max(1e-11, 10 * rel_err(bf, ref))
+        else:
+            tol = 1e-10
+    err = rel_err(chost(S), ref)
+    log(f"  rel err {err:.3e} (tol {tol:.1e}), n_omega={len(tp['m'])}, plan {B.sox_plan_describe(plan)['solid_dyn_pair_slab']}")
+    assert err <= tol
+
+
+def test_dynamic_slabs_match(B, monkeypatch):
+    """A budget that forces pair and tau slabs gives the same Sigma."""
+    import torch
+    wl = synth.add_dynamic_screening_solid(synth.solid((2, 2, 1), 5, 26, 9, 10.0, seed=31),
+                                           n_poles=2)
+    tp = _tp(wl)
+    log("solid dynamic slabs")
+    plan1 = _dyn_plan(B, wl, tp, "fp64")
+    monkeypatch.setenv("SOX_WS_BUDGET_MB", "3")
+    plan2 = _dyn_plan(B, wl, tp, "fp64")
+    monkeypatch.delenv("SOX_WS_BUDGET_MB")
+    d1, d2 = B.sox_plan_describe(plan1), B.sox_plan_describe(plan2)
+    log(f"  slabs {d1['solid_dyn_pair_slab']},{d1['solid_dyn_tau_slab']} vs "
+        f"{d2['solid_dyn_pair_slab']},{d2['solid_dyn_tau_slab']}")
+    assert d2["solid_dyn_pair_slab"] < d1["solid_dyn_pair_slab"]
+    G = cdev(_general_G(wl, 3))
+    args = (cdev(wl["X"]), cdev(wl["W_tau"]), cdev(wl["V"]), G)
+    S1 = torch.empty(G.shape, dtype=torch.complex128, device="cuda")
+    S2 = torch.empty_like(S1)
+    B.sox_sigma_dynamic(plan1, *args, S1)
+    B.sox_sigma_dynamic(plan2, *args, S2)
+    torch.cuda.synchronize()
+    assert rel_err(chost(S2), chost(S1)) <= 1e-13
+
+
+def test_dynamic_full_size_k_independent_reduces_to_molecule(B):
+    """3x3x3 mesh, n = 52, N = 400, 100 nodes, 8-pole W(tau): with X^k = X,
+    V^q = V, W^q(tau) = W(tau), G^k = G (real) for every momentum, Sigma^k
+    equals the molecular dynamic SOX self-energy of the FP64 oracle."""
+    import torch
+    n, N, nt, mesh = C5["n"], C5["N"], C5["n_tau"], C5["mesh"]
+    nk = int(np.prod(mesh))
+    mol = synth.add_dynamic_screening(synth.molecule(n, N, nt, C5["beta"], rng=synth.rng_for(56)))
+    tp = synth.bosonic_transform_pair(mol["tau"], mol["beta"], omega_max=14.0, tol=1e-10)
+    log(f"solid dynamic full size k-independent fp32, n_omega={len(tp['m'])}")
+    Gm = om.g_tau(mol["eps"], mol["Q"], mol["mu"], mol["beta"], mol["tau"])
+    plan = B.Plan(n, N, mol["tau"], mol["weights"], mol["beta"], precision="fp32", kmesh=mesh,
+                  t_fwd=tp["T_fwd"], t_bwd=tp["T_bwd"])
+    log(f"  plan {B.sox_plan_describe(plan)}")
+    W = torch.as_tensor(mol["W_tau"], dtype=torch.complex128, device="cuda")[None].expand(
+        nk, -1, -1, -1).contiguous()
+    rep = lambda a: np.repeat(a[None], nk, axis=0)
+    S = torch.empty((nk, nt, n, n), dtype=torch.complex128, device="cuda")
+    B.sox_sigma_dynamic(plan, cdev(rep(mol["X"])), W, cdev(rep(mol["V"])), cdev(rep(Gm)), S)
+    torch.cuda.synchronize()
+    del W
+    Sh = chost(S)
+    ref = om.sigma_dynamic_thc(mol["X"], mol["W_tau"], mol["V"], Gm, Gm[::-1], tp["T_fwd"],
+                               tp["T_bwd"])
+    err = np.abs(Sh - ref[None]).max() / np.abs(ref).max()
+    log(f"  rel err {err:.3e}")
+    assert err <= TOL["fp32"]
