@@ -39,10 +39,11 @@ WORKLOADS = {
     2: ("molecule bare SOX n=64 N=384 n_tau=64 beta=50", "bare"),
     3: ("molecule static SOX n=200 N=1200 n_tau=100 beta=100, W0 = V + V Pi V", "static"),
     4: ("molecule dynamic SOX n=300 N=1800 n_tau=120 beta=100, 8-pole W(tau)", "dynamic"),
-    5: ("solid bare SOX 3x3x3 k-mesh n=52 N=400 n_tau=100 beta=100", "solid"),
+    5: ("solid bare + dynamic SOX 3x3x3 k-mesh n=52 N=400 n_tau=100 beta=100, 8-pole W^q(tau)",
+        "solid"),
 }
 ENTRY = {"bare": "sox_sigma_bare", "static": "sox_sigma_static", "dynamic": "sox_sigma_dynamic",
-         "solid": "sox_sigma_bare"}
+         "solid": "sox_sigma_bare + sox_sigma_dynamic"}
 # dominant kernel per kind: (profiling stage, kernel name)
 DOMINANT = {"bare": ("fused", "fused_bcd_kernel"), "static": ("fused", "fused_bcd_kernel"),
             "dynamic": ("fused", "fused_bcd_kernel"), "solid": ("kbc", "cgemm_nt_kernel")}
@@ -56,16 +57,22 @@ def flops_per_sweep(n: int, N: int, nt: int, kind: str = "bare", n_omega: int = 
     is reported but excluded from the sweep total by the caller (it is set up
     once per X and U)."""
     if kind == "solid":
+        # bare and dynamic entries on the same mesh (one step runs both)
         np2 = nk * nk
+        nw = n_omega
         return {
             "gbuild": nk * nt * 8.0 * n ** 3,
-            "utensor": np2 * 8.0 * N * N * n * n,
-            "project": nt * nk * 2 * 8.0 * N * n * n,
+            "utensor": 2 * np2 * 8.0 * N * N * n * n,
+            "project": nt * nk * 5 * 8.0 * N * n * n,
             "astep": nt * np2 * 8.0 * N * n ** 3,
-            "kbc": nt * np2 * 2 * 8.0 * N * N * n * n,
-            "kd": nt * nk ** 3 * 8.0 * N * N * n,
-            "back": nt * nk * 8.0 * (N * N * n + N * n * n),
-            "energy": nk * nt * 8.0 * n * n,
+            "gg_ft": 2 * 8.0 * nw * nt * nk * N * N + nt * np2 * N * n * n * 6.0
+                     + 2 * 8.0 * nw * nt * np2 * N * n * n,
+            "wgemm": 2 * nw * np2 * 8.0 * N * N * n * n,
+            "ift": 8.0 * nt * 2 * nw * np2 * N * n * n,
+            "kbc": 2 * nt * np2 * 2 * 8.0 * N * N * n * n,
+            "kd": 2 * nt * nk ** 3 * 8.0 * N * N * n,
+            "back": 2 * nt * nk * 8.0 * (N * N * n + N * n * n),
+            "energy": 2 * nk * nt * 8.0 * n * n,
         }
     f = {
         "gbuild": nt * 2.0 * n ** 3,
@@ -202,9 +209,13 @@ def main() -> int:
     t = lambda a, dt=cdt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
     X, V, Q = t(wl["X"]), t(wl["V"]), t(wl["Q"])
     eps = t(wl["eps"], torch.float64)
-    U1 = t(wl["W0"]) if kind == "static" else (t(wl["W_tau"]) if kind == "dynamic" else V)
+    if solid:
+        synth.add_dynamic_screening_solid(wl)
+    U1 = t(wl["W0"]) if kind == "static" else (t(wl["W_tau"]) if kind in ("dynamic", "solid") else V)
+    if solid:
+        wl.pop("W_tau")
     tp = None
-    if kind == "dynamic":
+    if kind in ("dynamic", "solid"):
         tp = synth.bosonic_transform_pair(wl["tau"], wl["beta"], omega_max=14.0, tol=1e-10)
     n_omega = len(tp["m"]) if tp is not None else 0
     gshape = (nk, nt, n, n) if solid else (nt, n, n)
@@ -227,6 +238,9 @@ def main() -> int:
         S = torch.empty_like(G)
         entry = "static" if kind == "static" else ("dynamic" if kind == "dynamic" else "bare")
         ws = plan.workspace(entry)
+        if solid:  # one buffer serves both entries
+            ws = torch.empty(max(plan.workspace_size("bare"), plan.workspace_size("dynamic")) + 256,
+                             dtype=torch.uint8, device=dev)
         energies = []
 
         def step():
@@ -234,6 +248,10 @@ def main() -> int:
             if kind == "static":
                 B.sox_sigma_static(plan, X, U1, V, G, S, ws=ws)
             elif kind == "dynamic":
+                B.sox_sigma_dynamic(plan, X, U1, V, G, S, ws=ws)
+            elif solid:
+                B.sox_sigma_bare(plan, X, V, G, S, ws=ws)
+                energies.append(B.sox_energy_gm(plan, S, G))
                 B.sox_sigma_dynamic(plan, X, U1, V, G, S, ws=ws)
             else:
                 B.sox_sigma_bare(plan, X, V, G, S, ws=ws)
@@ -324,7 +342,8 @@ def main() -> int:
         "config": {"workload": desc, "entry": ENTRY[kind], "n_orb": n, "n_thc": N, "n_tau": nt,
                    "beta": wl["beta"], "kmesh": list(wl.get("mesh", (1, 1, 1))),
                    "n_omega": n_omega, "precision": args.precision,
-                   "step": "G(tau) + Sigma(all tau" + (", all k" if solid else "") + ") + E_GM"},
+                   "step": ("G(tau) + Sigma(all tau" + (", all k; bare and dynamic" if solid else "")
+                            + ") + E_GM")},
         "tflops_alg": sweep_flops / (ms_per_step * 1e-3) / 1e12,
         "max_rel_err": main_err,
         "roofline": {

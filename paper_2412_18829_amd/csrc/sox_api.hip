@@ -76,6 +76,8 @@ struct sox_plan {
   int nP, NP;
   int precision;
   int fused_cfg;   // index into kFusedCfgs
+  int fused_vsplit = 1;  // workgroups sharing one D tile's v sum (static entries)
+  int n_cu = 256;        // compute units of the device
   int wg_tile;     // NP granule: 2 * max(wave tile edges)
   int slab;        // tau nodes per slab
   double beta;
@@ -200,7 +202,7 @@ Layout layout_for(const sox_plan& p, int entry, int slab) {
   L.a = c.take((size_t)slab * n * NP * nP * es);
   L.p1 = c.take((size_t)slab * NP * nP * es);
   L.p2t = c.take((size_t)slab * NP * nP * es);
-  L.d = c.take((size_t)slab * NP * NP * es);
+  L.d = c.take((size_t)slab * NP * NP * es * std::max(1, p.fused_vsplit));
   L.e = c.take((size_t)slab * n * NP * 8);
   L.gbt = c.take((size_t)slab * nP * nP * es);
   if (p.precision == SOX_BF16X3) {
@@ -407,6 +409,55 @@ sox_status launch_gbar_t(const sox_plan& p, const double* G, T* gbt, int t0, int
 template <typename T>
 sox_status launch_fused_cfg(const sox_plan& p, const FusedArgs<T>& fa, hipStream_t s);
 
+// Resident workgroups per CU of the plan's fused kernel (register-limited).
+int fused_blocks_per_cu(const sox_plan& p) {
+  int nb = 0;
+  hipError_t e = hipErrorInvalidValue;
+  if (p.precision == SOX_FP32) {
+    switch (p.fused_cfg) {
+      case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<float, 32, 32>, 256, 0); break;
+      case 1: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<float, 64, 32>, 256, 0); break;
+      case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<float, 32, 64>, 256, 0); break;
+      case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<float, 64, 64>, 256, 0); break;
+      case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<float, 32, 16>, 256, 0); break;
+      default: break;
+    }
+  } else if (p.precision == SOX_FP64) {
+    switch (p.fused_cfg) {
+      case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<double, 32, 32>, 256, 0); break;
+      case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<double, 32, 16>, 256, 0); break;
+      case 5: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<double, 16, 32>, 256, 0); break;
+      default: break;
+    }
+  }
+  return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+// Split of the fused kernel's v sum: the smallest split (chunks of at least
+// 8 orbitals) whose launch over one tau slab fills the most complete rounds
+// of resident workgroups; 1 when the launch already holds many rounds.
+void pick_vsplit(sox_plan& p) {
+  p.fused_vsplit = 1;
+  if (p.precision == SOX_BF16X3 || p.nk > 1) return;
+  const FusedCfg& fc = kFusedCfgs[p.fused_cfg];
+  const long tiles = (long)(p.NP / (2 * fc.wp)) * (p.NP / (2 * fc.wr)) * p.slab;
+  const long resident = (long)fused_blocks_per_cu(p) * p.n_cu;
+  double best = -1.0;
+  for (int s : {1, 2, 3, 4, 6, 8}) {
+    const int chunk = (p.n + s - 1) / s;
+    if (s > 1 && chunk < 8) break;
+    const int se = (p.n + chunk - 1) / chunk;
+    const long wgs = tiles * se;
+    const long rounds = (wgs + resident - 1) / resident;
+    const double eff = (double)wgs / (double)(rounds * resident);
+    if (eff > best + 0.02) {
+      best = eff;
+      p.fused_vsplit = se;
+    }
+  }
+  if (layout_for(p, SOX_ENTRY_STATIC, p.slab).total > ws_budget()) p.fused_vsplit = 1;
+}
+
 template <>
 sox_status launch_fused_cfg<float>(const sox_plan& p, const FusedArgs<float>& fa, hipStream_t s) {
   switch (p.fused_cfg) {
@@ -506,6 +557,9 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
     fa.tiles_r = tiles_r;
     fa.n_tau = cnt;
     fa.accumulate = 0;
+    fa.vsplit = p.fused_vsplit;
+    fa.vchunk = (n + p.fused_vsplit - 1) / p.fused_vsplit;
+    fa.d_sstride = (long)p.slab * NP * NP;
     if (p.precision == SOX_BF16X3) {
       // x = hi + lo split of the four float32 operands, then bf16 x 3 MFMA
       bf16_t* ah = (bf16_t*)(base + L.ah); bf16_t* al = (bf16_t*)(base + L.al);
@@ -535,6 +589,14 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
       ProfScope ps(p, SOX_STAGE_FUSED, s);
       st = launch_fused_cfg<T>(p, fa, s);
       if (st) return st;
+    }
+    if (p.fused_vsplit > 1 && p.precision != SOX_BF16X3) {
+      // the v splits' partial D blocks, summed ahead of the back-transform
+      ProfScope ps(p, SOX_STAGE_BACK, s);
+      const long count = (long)cnt * NP * NP;
+      hipLaunchKernelGGL(dsplit_sum_kernel<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+                         s, D, count, fa.d_sstride, p.fused_vsplit);
+      SOX_HIP(hipGetLastError());
     }
     {
       ProfScope ps(p, SOX_STAGE_BACK, s);
@@ -1386,6 +1448,13 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
   }
 
   hipError_t e = hipGetDevice(&p->device);
+  if (e == hipSuccess) {
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, p->device) == hipSuccess &&
+        ncu > 0)
+      p->n_cu = ncu;
+    if (p->nk == 1) pick_vsplit(*p);
+  }
   if (e == hipSuccess && p->n_omega > 0) {
     const int nw = p->n_omega;
     std::vector<double> tf2(2 * (size_t)nw * nt), tb2((size_t)nt * 2 * nw);
@@ -1656,12 +1725,13 @@ sox_status sox_plan_describe(const sox_plan* plan, char* buf, size_t len) {
   snprintf(buf, len,
            "{\"n\":%d,\"N\":%d,\"n_tau\":%d,\"nP\":%d,\"NP\":%d,\"precision\":%d,"
            "\"fused_cfg\":%d,\"fused_wave_tile\":[%d,%d],\"tau_slab\":%d,\"vjp_tau_slab\":%d,"
-           "\"v_slab\":%d,\"vjp_v_slab\":%d,\"graph\":%d,\"tune_ms_per_tau\":%s,"
+           "\"v_slab\":%d,\"vjp_v_slab\":%d,\"graph\":%d,\"fused_vsplit\":%d,\"n_cu\":%d,"
+           "\"tune_ms_per_tau\":%s,"
            "\"tune_from_cache\":%d,\"kmesh\":[%d,%d,%d],\"n_k\":%d,\"solid_v_slab\":%d,"
            "\"solid_v_slab_bare\":%d,\"solid_dyn_pair_slab\":%d,\"solid_dyn_tau_slab\":%d}",
            plan->n, plan->N, plan->n_tau, plan->nP, plan->NP, plan->precision, plan->fused_cfg,
            fc.wp, fc.wr, plan->slab, plan->vjp_slab, plan->vc, plan->vc_vjp, plan->graph_on ? 1 : 0,
-           tune.c_str(), plan->tune_from_cache ? 1 : 0, plan->kmesh[0], plan->kmesh[1],
+           plan->fused_vsplit, plan->n_cu, tune.c_str(), plan->tune_from_cache ? 1 : 0, plan->kmesh[0], plan->kmesh[1],
            plan->kmesh[2], plan->nk, plan->vcs, plan->vcs_bare, plan->dyn_ps, plan->dyn_ts);
   return SOX_OK;
 }

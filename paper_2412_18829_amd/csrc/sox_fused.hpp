@@ -17,9 +17,11 @@
 //   D   [tau][P][R]      row stride NP
 //
 // One workgroup = 4 wavefronts (2 x 2) owns a (2 WP) x (2 WR) block of D for
-// one tau.  The loops run over v and 16-deep k chunks with the next chunk's
-// operands loaded before the current chunk's MFMAs are issued; the Hadamard
-// epilogue closes each v.
+// one tau and one range of v (the v sum may be split over several
+// workgroups so that a launch fills whole rounds of the chip; the partial D
+// blocks are then added by dsplit_sum_kernel).  The loops run over v and
+// 16-deep k chunks with the next chunk's operands loaded before the current
+// chunk's MFMAs are issued; the Hadamard epilogue closes each v.
 #pragma once
 
 #include "sox_common.hpp"
@@ -42,6 +44,11 @@ template <typename T> struct FusedArgs {
   int nP;     // padded k depth (multiple of 16)
   int NP;     // padded THC extent (multiple of the tile)
   int tiles_p, tiles_r, n_tau;
+  // the v sum split over vsplit workgroups per tile (vchunk orbitals each,
+  // every split non-empty); split s writes its partial D at D + s d_sstride
+  int vsplit = 1;
+  int vchunk = 0;
+  long d_sstride = 0;
 };
 
 template <typename T, int WP, int WR>
@@ -50,11 +57,16 @@ __global__ __launch_bounds__(256) void fused_bcd_kernel(const FusedArgs<T> p) {
   constexpr int PB = WP / 16;
   constexpr int RB = WR / 16;
   const int nblocks = gridDim.x;
-  const int bid = xcd_remap(blockIdx.x, nblocks);
+  const int bid0 = xcd_remap(blockIdx.x, nblocks);
+  const int per_split = p.tiles_r * p.tiles_p * p.n_tau;
+  const int sidx = bid0 / per_split;
+  const int bid = bid0 - sidx * per_split;
   const int rt = bid % p.tiles_r;
   const int tmp = bid / p.tiles_r;
   const int pt = tmp % p.tiles_p;
   const int t = tmp / p.tiles_p;
+  const int vbeg = p.vsplit > 1 ? sidx * p.vchunk : 0;
+  const int vend = p.vsplit > 1 ? (vbeg + p.vchunk < p.n ? vbeg + p.vchunk : p.n) : p.n;
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -64,10 +76,10 @@ __global__ __launch_bounds__(256) void fused_bcd_kernel(const FusedArgs<T> p) {
   const int R0 = rt * (2 * WR) + (wave & 1) * WR;
 
   const long ld = p.nP;
-  const T* Ab = p.A + t * p.a_tstride + (long)(P0 + li) * ld + 4 * g;
+  const T* Ab = p.A + t * p.a_tstride + (long)vbeg * p.a_vstride + (long)(P0 + li) * ld + 4 * g;
   const T* Yb = p.Y + t * p.y_tstride + (long)(R0 + li) * ld + 4 * g;
   const T* Pb = p.P2T + t * p.p_tstride + (long)(P0 + li) * ld + 4 * g;
-  const T* Ub = p.U2 + (long)(R0 + li) * p.u_rstride + 4 * g;
+  const T* Ub = p.U2 + (long)vbeg * p.u_vstride + (long)(R0 + li) * p.u_rstride + 4 * g;
 
   V4 accB[PB][RB], accC[PB][RB], dacc[PB][RB];
 #pragma unroll
@@ -80,7 +92,7 @@ __global__ __launch_bounds__(256) void fused_bcd_kernel(const FusedArgs<T> p) {
     }
 
   const int KC = p.nP >> 4;
-  const int nv = p.n;
+  const int nv = vend - vbeg;
 
   // Operands of the current chunk.  The next chunk is always loaded (the
   // last iteration re-loads chunk (n-1, KC-1), which stays in bounds) so the
@@ -147,7 +159,7 @@ __global__ __launch_bounds__(256) void fused_bcd_kernel(const FusedArgs<T> p) {
       }
   }
 
-  T* Db = p.D + t * p.d_tstride;
+  T* Db = p.D + t * p.d_tstride + (long)sidx * p.d_sstride;
 #pragma unroll
   for (int i = 0; i < PB; ++i)
 #pragma unroll
@@ -163,10 +175,21 @@ __global__ __launch_bounds__(256) void fused_bcd_kernel(const FusedArgs<T> p) {
 
 template <typename T, int WP, int WR>
 inline hipError_t launch_fused(const FusedArgs<T>& a, hipStream_t s) {
-  const int nb = a.tiles_p * a.tiles_r * a.n_tau;
+  const int nb = a.tiles_p * a.tiles_r * a.n_tau * (a.vsplit > 1 ? a.vsplit : 1);
   if (nb <= 0) return hipSuccess;
   hipLaunchKernelGGL((fused_bcd_kernel<T, WP, WR>), dim3(nb), dim3(256), 0, s, a);
   return hipGetLastError();
+}
+
+// D[i] (+)= sum_{s=1}^{ns-1} D[s stride + i]: adds the partial D blocks of
+// the v splits into the first one.
+template <typename T>
+__global__ __launch_bounds__(256) void dsplit_sum_kernel(T* D, long count, long stride, int ns) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  T acc = D[i];
+  for (int s = 1; s < ns; ++s) acc += D[(long)s * stride + i];
+  D[i] = acc;
 }
 
 }  // namespace sox

@@ -122,7 +122,9 @@ def test_bare_equals_static_with_same_interaction(B):
 
 
 def test_tau_slabs_match_single_slab(B, monkeypatch):
-    """A workspace budget that forces several tau slabs gives the same Sigma."""
+    """A workspace budget that forces several tau slabs gives the same Sigma
+    (to the float32 bound: the split of the v sum over workgroups follows the
+    slab's tile count, so the summation order may differ)."""
     import torch
     wl = synth.small_molecule(24, 120, 9, 9.0, seed=6)
     plan1 = _plan(B, wl, "fp32")
@@ -136,7 +138,7 @@ def test_tau_slabs_match_single_slab(B, monkeypatch):
     B.sox_sigma_bare(plan2, X, V, G, S2)
     torch.cuda.synchronize()
     assert plan2.workspace_size("bare") < plan1.workspace_size("bare")
-    assert np.array_equal(host(S1), host(S2))
+    assert rel_err(host(S2), host(S1)) <= 1e-6
 
 
 def test_workspace_too_small_is_an_error(B):
