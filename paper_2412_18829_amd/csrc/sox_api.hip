@@ -433,9 +433,10 @@ int fused_blocks_per_cu(const sox_plan& p) {
   return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
-// Split of the fused kernel's v sum: the smallest split (chunks of at least
-// 8 orbitals) whose launch over one tau slab fills the most complete rounds
-// of resident workgroups; 1 when the launch already holds many rounds.
+// Split of the fused kernel's v sum (chunks of at least 8 orbitals): the
+// split whose launch over one tau slab fills complete rounds of resident
+// workgroups best, each extra split charged 2% for its extra epilogue and
+// partial-D traffic; 1 when the launch already holds many rounds.
 void pick_vsplit(sox_plan& p) {
   p.fused_vsplit = 1;
   if (p.precision == SOX_BF16X3 || p.nk > 1) return;
@@ -449,9 +450,9 @@ void pick_vsplit(sox_plan& p) {
     const int se = (p.n + chunk - 1) / chunk;
     const long wgs = tiles * se;
     const long rounds = (wgs + resident - 1) / resident;
-    const double eff = (double)wgs / (double)(rounds * resident);
-    if (eff > best + 0.02) {
-      best = eff;
+    const double score = (double)wgs / (double)(rounds * resident) - 0.02 * (se - 1);
+    if (score > best) {
+      best = score;
       p.fused_vsplit = se;
     }
   }
