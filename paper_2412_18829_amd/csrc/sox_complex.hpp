@@ -264,22 +264,198 @@ inline hipError_t launch_cgemm(CgArgs<T, TC> a, int nz, hipStream_t s) {
 }
 
 // ---------------------------------------------------------------------------
-// The n_k^3 D step of a solid (section on solids: for every (P, R) pair,
-// D^{k_t}_PR accumulates C^{q2,k_w}_RvP B^{q1,k_w-q2}_PRv over k_w, q2 and
-// v with q1 = k_w - k_t).  B and C are stored [pair][v][P][R] with pair =
-// q * n_k + k; with k_v = k_w - q2 the sum reads, per element e = (P, R),
-//
-//   D[k_t][e] += scale * sum_{k_v, v} sum_{k_w} C[(k_w - k_v, k_w)][v][e]
-//                                              * B[(k_w - k_t, k_v)][v][e].
-//
-// One thread per element: for each (k_v, v) it loads the n_k values
-// B[(., k_v)][v][e] and the n_k values C[(k_w - k_v, k_w)][v][e] once and
-// forms all n_k^2 products in registers.  Pairs are sp elements apart, v
-// slices NN apart; nv slices are summed.  The k_v range is split over the
-// rows of the grid (gk momenta each) so that the launch fills the chip; each
-// row writes its own partial D, summed by dsum_kernel.  The mesh is a template parameter so
-// that every momentum difference is a compile-time register index.
-// D is float64 (the cross-slab accumulation).
+// The B and C steps of a solid: the same complex NT product as above, for
+// nv orbitals v per workgroup, where one operand does not depend on v (the
+// G_Rq panel of the B step, the G_wP^T panel of the C step).  A workgroup
+// of NW wavefronts owns an (16 NW) x 80 output tile:
+//   FIXA = false (B step): A varies with v; wavefront w owns rows
+//     [16 w, 16 w + 16) and keeps them in registers; B (80 rows) is staged
+//     once in LDS for every v.
+//   FIXA = true (C step): B varies with v; wavefront w owns columns
+//     [16 w, 16 w + 16); A (80 rows) is staged once in LDS.
+// Four wavefronts let two workgroups share a CU (about 200 registers per
+// lane), which keeps all four SIMDs busy; five would divide N = 400 exactly
+// but leave one SIMD with twice the work.
+// A wavefront's own rows for v + 1 are loaded while the MFMAs of v run
+// (one lane holds k = 4 s + g for s < SM, the instantiated step count
+// >= ceil(K / 4); steps past K multiply zeros), so the loads have a whole v
+// of MFMAs to arrive.  K <= 64, no conjugation, no S factor,
+// K-contiguous rows, float32 (the launcher checks and otherwise uses the
+// kernel above).  The LDS row stride is K rounded up to 4, then to 4 mod 32
+// complex, so the 16 rows a load instruction touches spread over the banks.
+constexpr int kPanelRows = 80;
+constexpr int kPanelSmax = 16;
+
+__host__ __device__ constexpr int panel_ls(int K) {
+  return ((K + 3) & ~3) + ((4 - ((K + 3) & ~3) % 32) + 32) % 32;
+}
+constexpr int kPanelLSMax = panel_ls(4 * kPanelSmax);  // 68 complex
+
+template <typename T, bool FIXA, int SM, int NW>
+__global__ __launch_bounds__(64 * NW) void cgemm_panel_kernel(const CgArgs<T, T> p) {
+  static_assert(SM <= kPanelSmax, "panel holds at most 64 k");
+  using V2 = vec2_t<T>;
+  using V4 = vec4_t<T>;
+  __shared__ V2 panel[kPanelRows * kPanelLSMax];
+  const int z = blockIdx.y + blockIdx.z * gridDim.y;
+  if (z >= p.nz) return;
+  const int zo = z / p.nzi;
+  const int zi = z - zo * p.nzi;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int tn = bid % p.tiles_n;
+  const int tm = bid / p.tiles_n;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int li = lane & 15;
+  const int g = lane >> 4;
+  const int row0 = tm * (FIXA ? kPanelRows : 16 * NW);
+  const int col0 = tn * (FIXA ? 16 * NW : kPanelRows);
+  const int LS = panel_ls(p.K);
+
+  const V2* Ab = (const V2*)p.A + cg_off(p.idxA, p.soA, p.siA, zo, zi);
+  const V2* Bb = (const V2*)p.B + cg_off(p.idxB, p.soB, p.siB, zo, zi);
+  T* Cb = p.C + 2 * cg_off(p.idxC, p.soC, p.siC, zo, zi);
+
+  // stage the fixed panel: 80 rows x LS complex, zero past K and past M / N
+  {
+    const V2* F = FIXA ? Ab : Bb;
+    const long ldf = FIXA ? p.ldA : p.ldB;
+    const int f0 = FIXA ? row0 : col0;
+    const int fext = FIXA ? p.M : p.N;
+    for (int idx = threadIdx.x; idx < kPanelRows * LS; idx += blockDim.x) {
+      const int r = idx / LS, k = idx - (idx / LS) * LS;
+      V2 v = V2{T(0), T(0)};
+      if (f0 + r < fext && k < p.K) v = F[(long)(f0 + r) * ldf + k];
+      panel[idx] = v;
+    }
+  }
+  __syncthreads();
+
+  // this wavefront's varying rows
+  const int vr0 = (FIXA ? col0 : row0) + 16 * wave;
+  const int vext = FIXA ? p.N : p.M;
+  const bool vok = vr0 + li < vext;
+  const V2* Vb = (FIXA ? Bb : Ab) + (long)(vok ? vr0 + li : vext - 1) * (FIXA ? p.ldB : p.ldA);
+  const long vsv = FIXA ? p.vsB : p.vsA;
+  V2 cur[SM], nxt[SM];
+  auto load = [&](int v, V2 (&dst)[SM]) {
+    const V2* src = Vb + (long)v * vsv;
+#pragma unroll
+    for (int s = 0; s < SM; ++s) {
+      int k = 4 * s + g;
+      k = k < p.K ? k : p.K - 1;
+      dst[s] = src[k];
+    }
+  };
+  auto mask = [&](V2 (&x)[SM]) {
+#pragma unroll
+    for (int s = 0; s < SM; ++s) {
+      const bool ok = vok && 4 * s + g < p.K;
+      x[s].x = ok ? x[s].x : T(0);
+      x[s].y = ok ? x[s].y : T(0);
+    }
+  };
+
+  const V2* P = panel + li * LS + g;  // row 16 b + li, column 4 s + g
+  load(0, cur);
+  mask(cur);
+  for (int v = 0; v < p.nv; ++v) {
+    load(v + 1 < p.nv ? v + 1 : v, nxt);
+    V4 accr[5], acci[5];
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      accr[b] = zero4<T>();
+      acci[b] = zero4<T>();
+    }
+    // panel operands one step ahead of the MFMAs that use them
+    V2 fc[5], fn[5];
+#pragma unroll
+    for (int b = 0; b < 5; ++b) fc[b] = P[16 * b * LS];
+#pragma unroll
+    for (int s = 0; s < SM; ++s) {
+      {
+        if (s + 1 < SM) {
+#pragma unroll
+          for (int b = 0; b < 5; ++b) fn[b] = P[16 * b * LS + 4 * (s + 1)];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        const T xr = cur[s].x, xi = cur[s].y, nxi = -cur[s].y;
+#pragma unroll
+        for (int b = 0; b < 5; ++b) {
+          const V2 f = fc[b];
+          if (FIXA) {  // A = panel (f), B = own rows (x)
+            accr[b] = mfma16x16x4(f.x, xr, accr[b]);
+            accr[b] = mfma16x16x4(f.y, nxi, accr[b]);
+            acci[b] = mfma16x16x4(f.x, xi, acci[b]);
+            acci[b] = mfma16x16x4(f.y, xr, acci[b]);
+          } else {     // A = own rows (x), B = panel (f)
+            accr[b] = mfma16x16x4(xr, f.x, accr[b]);
+            accr[b] = mfma16x16x4(nxi, f.y, accr[b]);
+            acci[b] = mfma16x16x4(xr, f.y, acci[b]);
+            acci[b] = mfma16x16x4(xi, f.x, acci[b]);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int b = 0; b < 5; ++b) fc[b] = fn[b];
+      }
+    }
+    T* Cv = Cb + 2 * (long)v * p.vsC;
+#pragma unroll
+    for (int b = 0; b < 5; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = FIXA ? row0 + 16 * b + acc_row<T>(g, r) : vr0 + acc_row<T>(g, r);
+        const int col = FIXA ? vr0 + li : col0 + 16 * b + li;
+        if (row < p.M && col < p.N) {
+          V2 o;
+          o.x = p.alpha * accr[b][r];
+          o.y = p.alpha * acci[b][r];
+          *(V2*)(Cv + 2 * ((long)row * p.ldc + col)) = o;
+        }
+      }
+#pragma unroll
+    for (int s = 0; s < SM; ++s) cur[s] = nxt[s];
+    mask(cur);
+  }
+}
+
+// The panel kernel for the B and C steps when its conditions hold (K <= 64,
+// plain rows, no conjugation, no S factor, no accumulation, LDS within the
+// per-workgroup limit); returns hipErrorNotSupported otherwise.
+inline hipError_t launch_cgemm_panel(CgArgs<float, float> a, int nz, bool fixa, hipStream_t s) {
+  if (a.K < 1 || a.K > 4 * kPanelSmax || a.conjA || a.conjB || a.S || a.accumulate ||
+      a.splitA != (1 << 30) || a.splitB != (1 << 30) || a.ksA != 1 || a.ksB != 1 ||
+      (fixa ? a.vsA : a.vsB) != 0)
+    return hipErrorNotSupported;
+  if (a.M <= 0 || a.N <= 0 || nz <= 0 || a.nv <= 0) return hipSuccess;
+  constexpr int NW = 4;
+  a.nz = nz;
+  a.tiles_m = (a.M + (fixa ? kPanelRows : 16 * NW) - 1) / (fixa ? kPanelRows : 16 * NW);
+  a.tiles_n = (a.N + (fixa ? 16 * NW : kPanelRows) - 1) / (fixa ? 16 * NW : kPanelRows);
+  const int gy = nz < 65535 ? nz : 65535;
+  const int gz = (nz + gy - 1) / gy;
+  dim3 grid(a.tiles_m * a.tiles_n, gy, gz);
+  const int S = (a.K + 3) / 4;
+#define SOX_PANEL(SM_)                                                                     \
+  if (S <= SM_) {                                                                          \
+    if (fixa)                                                                              \
+      hipLaunchKernelGGL((cgemm_panel_kernel<float, true, SM_, NW>), grid, dim3(64 * NW), 0, \
+                         s, a);                                                            \
+    else                                                                                   \
+      hipLaunchKernelGGL((cgemm_panel_kernel<float, false, SM_, NW>), grid, dim3(64 * NW),  \
+                         0, s, a);                                                         \
+    return hipGetLastError();                                                              \
+  }
+  SOX_PANEL(4)
+  SOX_PANEL(8)
+  SOX_PANEL(13)
+  SOX_PANEL(16)
+#undef SOX_PANEL
+  return hipErrorNotSupported;
+}
+
+// ---------------------------------------------------------------------------
 template <int M1, int M2, int M3>
 __host__ __device__ constexpr int kdiff_of(int a, int b) {
   return ((((a / (M2 * M3)) - (b / (M2 * M3)) + M1) % M1) * M2 +
@@ -287,6 +463,69 @@ __host__ __device__ constexpr int kdiff_of(int a, int b) {
          ((a % M3 - b % M3 + M3) % M3);
 }
 
+// In-register discrete Fourier transform over the momentum mesh (axes of
+// length 1, 2 or 3): x[k] <- sum_j x[j] w^(SIGN xi.j), w_a = exp(2 pi i / m_a),
+// with k = (k0 M2 + k1) M3 + k2.  One radix-2 or radix-3 butterfly pass per
+// axis.
+template <typename R, int SIGN, int M1, int M2, int M3, int AX>
+__device__ __forceinline__ void mesh_dft_axis(R (&xr)[M1 * M2 * M3], R (&xi)[M1 * M2 * M3]) {
+  constexpr int m = AX == 0 ? M1 : (AX == 1 ? M2 : M3);
+  constexpr int stride = AX == 0 ? M2 * M3 : (AX == 1 ? M3 : 1);
+  constexpr int NK = M1 * M2 * M3;
+  if constexpr (m == 2) {
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      if ((k / stride) % 2 != 0) continue;
+      const int k1 = k + stride;
+      const R ar = xr[k], ai = xi[k], br = xr[k1], bi = xi[k1];
+      xr[k] = ar + br; xi[k] = ai + bi;
+      xr[k1] = ar - br; xi[k1] = ai - bi;
+    }
+  } else if constexpr (m == 3) {
+    const R s = R(SIGN) * R(0.86602540378443864676);  // sin(2 pi / 3) with the sign
+#pragma unroll
+    for (int k = 0; k < NK; ++k) {
+      if ((k / stride) % 3 != 0) continue;
+      const int k1 = k + stride, k2 = k + 2 * stride;
+      const R tr = xr[k1] + xr[k2], ti = xi[k1] + xi[k2];
+      const R dr = xr[k1] - xr[k2], di = xi[k1] - xi[k2];
+      const R hr = xr[k] - R(0.5) * tr, hi = xi[k] - R(0.5) * ti;
+      xr[k] += tr; xi[k] += ti;
+      // y1 = h + i s d, y2 = h - i s d
+      xr[k1] = hr - s * di; xi[k1] = hi + s * dr;
+      xr[k2] = hr + s * di; xi[k2] = hi - s * dr;
+    }
+  }
+}
+
+template <typename R, int SIGN, int M1, int M2, int M3>
+__device__ __forceinline__ void mesh_dft(R (&xr)[M1 * M2 * M3], R (&xi)[M1 * M2 * M3]) {
+  mesh_dft_axis<R, SIGN, M1, M2, M3, 0>(xr, xi);
+  mesh_dft_axis<R, SIGN, M1, M2, M3, 1>(xr, xi);
+  mesh_dft_axis<R, SIGN, M1, M2, M3, 2>(xr, xi);
+}
+
+// The n_k^3 D step of a solid (section on solids: for every (P, R) pair,
+// D^{k_t}_PR accumulates C^{q2,k_w}_RvP B^{q1,k_w-q2}_PRv over k_w, q2 and
+// v with q1 = k_w - k_t).  B and C are stored [pair][v][P][R] with pair =
+// q * n_k + k; with k_v = k_w - q2 the sum reads, per element e = (P, R),
+//
+//   D[k_t][e] += scale * sum_{k_v, v} sum_{k_w} c_{k_v}[k_w] b_{k_v}[k_w - k_t],
+//   c_{k_v}[k_w] = C[(k_w - k_v, k_w)][v][e],  b_{k_v}[j] = B[(j, k_v)][v][e].
+//
+// The inner sum is a cyclic cross-correlation over the momentum group, so
+// with F[f](xi) = sum_k f[k] w^(xi.k) it is F^-1[ F[c] * F~[b] ] where F~
+// uses the conjugate phases.  One thread per element: for each (k_v, v) it
+// loads the n_k values of b and of c, transforms both in registers (one
+// butterfly pass per mesh axis), and accumulates the n_k products of the
+// transforms in float64; the inverse transform runs once at the end.  This
+// is the same sum as the direct n_k^2 products, in n_k log n_k work.  The
+// mesh is a template parameter (every index a compile-time register).
+// Pairs are sp elements apart, v slices NN apart; nv slices are summed.  The
+// k_v range is split over the rows of the grid (gk momenta each) so that the
+// launch fills the chip; each row writes its own partial D, summed by
+// dsum_kernel; grid layer z is the z-th tau node of a slab (B, C sbt and D
+// sdt apart).
 template <typename T, int M1, int M2, int M3>
 __global__ __launch_bounds__(256) void dstep_mesh_kernel(const T* __restrict__ B,
                                                          const T* __restrict__ C, double* D,
@@ -297,8 +536,6 @@ __global__ __launch_bounds__(256) void dstep_mesh_kernel(const T* __restrict__ B
   using V2 = vec2_t<T>;
   const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= NN) return;
-  // workgroup row y sums k_v in [y gk, y gk + gk) into its own partial D;
-  // grid layer z is the z-th tau node of a slab (B, C sbt and D sdt apart)
   const int kv0 = blockIdx.y * gk;
   const int kv1 = kv0 + gk < NK ? kv0 + gk : NK;
   D += 2 * ((long)blockIdx.y * NK * NN + (long)blockIdx.z * sdt);
@@ -306,39 +543,41 @@ __global__ __launch_bounds__(256) void dstep_mesh_kernel(const T* __restrict__ B
   C += 2 * (long)blockIdx.z * sbt;
   const V2* Bp = (const V2*)B + e;
   const V2* Cp = (const V2*)C + e;
-  double dr[NK], di[NK];
+  double hr[NK], hi[NK];  // F[D] accumulated
 #pragma unroll
-  for (int k = 0; k < NK; ++k) dr[k] = di[k] = 0.0;
+  for (int k = 0; k < NK; ++k) hr[k] = hi[k] = 0.0;
   for (int kv = kv0; kv < kv1; ++kv) {
     for (int v = 0; v < nv; ++v) {
       const long ov = (long)v * NN;
-      V2 b[NK], c[NK];
+      T br[NK], bi[NK], cr[NK], ci[NK];
 #pragma unroll
-      for (int q1 = 0; q1 < NK; ++q1) b[q1] = Bp[(long)(q1 * NK + kv) * sp + ov];
+      for (int q1 = 0; q1 < NK; ++q1) {
+        const V2 x = Bp[(long)(q1 * NK + kv) * sp + ov];
+        br[q1] = x.x;
+        bi[q1] = x.y;
+      }
 #pragma unroll
       for (int kw = 0; kw < NK; ++kw) {
         const int q2 = kdiff_of<M1, M2, M3>(kw, kv);
-        c[kw] = Cp[(long)(q2 * NK + kw) * sp + ov];
+        const V2 x = Cp[(long)(q2 * NK + kw) * sp + ov];
+        cr[kw] = x.x;
+        ci[kw] = x.y;
       }
-      // n_k-term partial sums in T, accumulated across (k_v, v) in float64
+      mesh_dft<T, +1, M1, M2, M3>(cr, ci);
+      mesh_dft<T, -1, M1, M2, M3>(br, bi);
 #pragma unroll
-      for (int kt = 0; kt < NK; ++kt) {
-        T sr = T(0), si = T(0);
-#pragma unroll
-        for (int kw = 0; kw < NK; ++kw) {
-          const int q1 = kdiff_of<M1, M2, M3>(kw, kt);
-          sr += c[kw].x * b[q1].x - c[kw].y * b[q1].y;
-          si += c[kw].x * b[q1].y + c[kw].y * b[q1].x;
-        }
-        dr[kt] += (double)sr;
-        di[kt] += (double)si;
+      for (int k = 0; k < NK; ++k) {
+        hr[k] += (double)(cr[k] * br[k] - ci[k] * bi[k]);
+        hi[k] += (double)(cr[k] * bi[k] + ci[k] * br[k]);
       }
     }
   }
+  mesh_dft<double, -1, M1, M2, M3>(hr, hi);
+  const double f = scale / NK;
 #pragma unroll
   for (int kt = 0; kt < NK; ++kt) {
     double* o = D + 2 * ((long)kt * NN + e);
-    double re = scale * dr[kt], im = scale * di[kt];
+    double re = f * hr[kt], im = f * hi[kt];
     if (accumulate) {
       re += o[0];
       im += o[1];

@@ -124,6 +124,21 @@ sox_status cg_launch(const CgArgs<T, TC>& a, int nz, int shape, hipStream_t s) {
   return SOX_OK;
 }
 
+// The B (fixa = false) and C (fixa = true) steps: the LDS-panel kernel where
+// it applies (float32, K <= 64), else the generic kernel with tile `shape`.
+template <typename T>
+sox_status bc_launch(const CgArgs<T, T>& a, int nz, bool fixa, int shape, hipStream_t s) {
+  if constexpr (sizeof(T) == 4) {
+    if (getenv("SOX_NO_PANEL") == nullptr) {
+      const hipError_t e = launch_cgemm_panel(a, nz, fixa, s);
+      if (e == hipSuccess) return SOX_OK;
+      if (e != hipErrorNotSupported)
+        return fail(SOX_ERR_HIP, "panel kernel launch failed: %s", hipGetErrorString(e));
+    }
+  }
+  return cg_launch(a, nz, shape, s);
+}
+
 // Tile of the B and C steps for this N: the 80-row tiles when they pad less
 // than the 64 x 64 ones.
 int bc_shape(int N) {
@@ -297,7 +312,7 @@ sox_status run_solid(sox_plan& p, int entry, const double* X, const double* U1, 
         b.C = bbuf; b.soC = (long)vcs * N * N; b.vsC = (long)N * N; b.ldc = N;
         b.nv = cnt;
         b.M = N; b.N = N; b.K = n;
-        if ((st = cg_launch(b, np2, bcs, s))) return st;
+        if ((st = bc_launch(b, np2, false, bcs, s))) return st;
       }
       {
         // C[pair][v] = GwPt^{k_w} Ut2[pair][v0 + v]^T, the GwPt panel shared by every v
@@ -308,7 +323,7 @@ sox_status run_solid(sox_plan& p, int entry, const double* X, const double* U1, 
         c.C = cbuf; c.soC = (long)vcs * N * N; c.vsC = (long)N * N; c.ldc = N;
         c.nv = cnt;
         c.M = N; c.N = N; c.K = n;
-        if ((st = cg_launch(c, np2, bcs, s))) return st;
+        if ((st = bc_launch(c, np2, true, bcs, s))) return st;
       }
       {
         ProfScope ps(p, SOX_STAGE_KD, s);
@@ -570,26 +585,28 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
       const int ct = std::min(ts, nt - t0);
       {
         ProfScope ps_(p, SOX_STAGE_KBC, s);
-        // B[l][pair][P][R] = sum_u A(tau)[pair][P][u] X^{k_v - q1}[u][R]
+        // B[l][pair][P][R] = sum_u A(tau)[pair][P][u] X^{k_v - q1}[u][R]; the X panel is
+        // the same for every node l of the slab (the workgroup's inner loop)
         CgArgs<T, T> b = cg_args<T, T>();
-        b.A = atau + 2 * (long)t0 * np2 * nN; b.soA = nN; b.siA = (long)np2 * nN; b.ldA = n;
+        b.A = atau + 2 * (long)t0 * np2 * nN; b.soA = nN; b.vsA = (long)np2 * nN; b.ldA = n;
         b.B = xtt; b.idxB = kmqOf; b.soB = nN; b.ldB = n;
-        b.C = bbuf; b.soC = NN; b.siC = (long)np2 * NN; b.ldc = N;
-        b.nzi = ct;
+        b.C = bbuf; b.soC = NN; b.vsC = (long)np2 * NN; b.ldc = N;
+        b.nv = ct;
         b.M = N; b.N = N; b.K = n;
-        if ((st = cg_launch(b, np2 * ct, bc_shape(N), s))) return st;
+        if ((st = bc_launch(b, np2, false, bc_shape(N), s))) return st;
       }
       {
         ProfScope ps_(p, SOX_STAGE_KBC, s);
-        // C[l][pair][P][R] = sum_w GwPt^{k_w}(tau)[P][w] Ut2[pair][v][R][w]
+        // C[l][pair][P][R] = sum_w GwPt^{k_w}(tau)[P][w] Ut2[pair][v][R][w]; the Ut2^v panel
+        // is the same for every node l of the slab
         CgArgs<T, T> c = cg_args<T, T>();
-        c.A = gwpt + 2 * (long)t0 * nk * nN; c.idxA = kOf; c.soA = nN; c.siA = (long)nk * nN;
+        c.A = gwpt + 2 * (long)t0 * nk * nN; c.idxA = kOf; c.soA = nN; c.vsA = (long)nk * nN;
         c.ldA = n;
         c.B = ut2 + 2 * (long)v * nN; c.soB = (long)n * nN; c.ldB = n;
-        c.C = cbuf; c.soC = NN; c.siC = (long)np2 * NN; c.ldc = N;
-        c.nzi = ct;
+        c.C = cbuf; c.soC = NN; c.vsC = (long)np2 * NN; c.ldc = N;
+        c.nv = ct;
         c.M = N; c.N = N; c.K = n;
-        if ((st = cg_launch(c, np2 * ct, bc_shape(N), s))) return st;
+        if ((st = bc_launch(c, np2, false, bc_shape(N), s))) return st;
       }
       {
         ProfScope ps_(p, SOX_STAGE_KD, s);

@@ -21,7 +21,7 @@ extern thread_local uint3e threadIdx, blockIdx, blockDim, gridDim;
 #define __shared__ static
 inline void __syncthreads() {}
 typedef int hipError_t;
-enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2 };
+enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2, hipErrorNotSupported = 3 };
 typedef void* hipStream_t;
 typedef void* hipEvent_t;
 typedef void* hipGraph_t;
