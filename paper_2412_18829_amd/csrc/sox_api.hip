@@ -178,7 +178,7 @@ struct Layout {
 };
 
 struct DynLayout {
-  size_t p1d, p2td, p2t, xt, u2, w2, gg2, aw, adyn, d, e, total;
+  size_t p1d, p2td, p1q, p2q, p2t, xt, u2, w2, gg2, aw, adyn, d, e, total;
 };
 
 size_t elem_size(int precision) { return precision == SOX_FP64 ? 8 : 4; }
@@ -223,6 +223,8 @@ DynLayout dyn_layout_for(const sox_plan& p, int vc, int eslab) {
   Carver c;
   L.p1d = c.take(nt * NP * nP * 8);
   L.p2td = c.take(nt * NP * nP * 8);
+  L.p1q = c.take(nt * NP * nP * 8);
+  L.p2q = c.take(nt * NP * nP * 8);
   L.p2t = c.take(nt * NP * nP * es);
   L.xt = c.take(NP * nP * es);
   L.u2 = c.take(NP * nP * nP * es);
@@ -611,6 +613,9 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
 }
 
 template <typename T>
+sox_status launch_transpose(const T* in, T* out, int rows, int cols, long batch, hipStream_t s);
+
+template <typename T>
 sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const double* V,
                        const double* G, double* Sigma, void* ws, hipStream_t s, int vcw = 0,
                        T* W2T = nullptr) {
@@ -619,6 +624,8 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
   char* base = (char*)ws;
   double* P1d = (double*)(base + L.p1d);
   double* P2Td = (double*)(base + L.p2td);
+  double* P1q = (double*)(base + L.p1q);
+  double* P2q = (double*)(base + L.p2q);
   T* P2T = (T*)(base + L.p2t);
   T* XT = (T*)(base + L.xt);
   T* U2 = (T*)(base + L.u2);
@@ -652,6 +659,9 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
     hipLaunchKernelGGL(xt_kernel<T>, dim3((unsigned)((cx + 255) / 256)), dim3(256), 0, s, X, XT,
                        n, N, nP, NP);
     SOX_HIP(hipGetLastError());
+    // Q-contiguous copies for the forward transform's loads
+    if ((st = launch_transpose<double>(P1d, P1q, NP, nP, nt, s))) return st;
+    if ((st = launch_transpose<double>(P2Td, P2q, NP, nP, nt, s))) return st;
   }
   {
     ProfScope ps(p, SOX_STAGE_GG_FT, s);
@@ -663,8 +673,8 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
     const int vc = std::min(vcw, n - v0);
     {
       ProfScope ps(p, SOX_STAGE_GG_FT, s);
-      FTProb<T> ft{p.d_tf2, P1d, P2Td, GG2, n, nP, NP, N, nw, nt, v0, vc, 2 * nw, vc * n * NP, nt,
-                   nullptr, 0};
+      FTProb<T> ft{p.d_tf2, P1q, P2q, GG2, n, nP, NP, N, nw, nt, v0, vc, 2 * nw, vc * n * NP, nt,
+                   nullptr, 0, 1};
       SOX_HIP((launch_gemm<FTProb<T>, double, 2, 2, 2, 2>(ft, 1, s)));
     }
     {

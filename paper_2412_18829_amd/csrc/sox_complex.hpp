@@ -56,6 +56,8 @@ template <typename T, typename TC> struct CgArgs {
   long ksA, ksB;  // k strides of A and B (1: K-contiguous rows)
   int nzi, nz, nv;
   int splitA, splitB;
+  int splitC;     // column c of C sits at (c / splitC) * hiC + c % splitC
+  long hiC;
   long ldA, hiA, ldB, hiB, ldc;
   int M, N, K;
   int tiles_m, tiles_n;
@@ -132,7 +134,8 @@ __global__ __launch_bounds__(64 * WGR * WGC) void cgemm_nt_kernel(const CgArgs<T
           const int row = row0 + 16 * i + acc_row<T>(g, r);
           const int col = col0 + 16 * j + li;
           if (row < p.M && col < p.N) {
-            C2* o = (C2*)(Cv + 2 * ((long)row * p.ldc + col));
+            const long co = (long)(col / p.splitC) * p.hiC + (col % p.splitC);
+            C2* o = (C2*)(Cv + 2 * ((long)row * p.ldc + co));
             C2 val;
             val.x = TC(p.alpha * accr[i][j][r]);
             val.y = TC(p.alpha * acci[i][j][r]);
@@ -241,7 +244,7 @@ template <typename T, typename TC> inline CgArgs<T, TC> cg_args() {
   a.nzi = 1;
   a.nv = 1;
   a.ksA = a.ksB = 1;
-  a.splitA = a.splitB = 1 << 30;
+  a.splitA = a.splitB = a.splitC = 1 << 30;
   a.alpha = T(1);
   return a;
 }
@@ -251,7 +254,8 @@ inline hipError_t launch_cgemm(CgArgs<T, TC> a, int nz, hipStream_t s) {
   constexpr int TM = WGR * RB * 16;
   constexpr int TN = WGC * CB * 16;
   if (a.M <= 0 || a.N <= 0 || nz <= 0 || a.nv <= 0) return hipSuccess;
-  if (a.K < 0 || a.nzi <= 0 || a.splitA <= 0 || a.splitB <= 0) return hipErrorInvalidValue;
+  if (a.K < 0 || a.nzi <= 0 || a.splitA <= 0 || a.splitB <= 0 || a.splitC <= 0)
+    return hipErrorInvalidValue;
   a.nz = nz;
   a.tiles_m = (a.M + TM - 1) / TM;
   a.tiles_n = (a.N + TN - 1) / TN;
@@ -425,7 +429,8 @@ __global__ __launch_bounds__(64 * NW) void cgemm_panel_kernel(const CgArgs<T, T>
 // per-workgroup limit); returns hipErrorNotSupported otherwise.
 inline hipError_t launch_cgemm_panel(CgArgs<float, float> a, int nz, bool fixa, hipStream_t s) {
   if (a.K < 1 || a.K > 4 * kPanelSmax || a.conjA || a.conjB || a.S || a.accumulate ||
-      a.splitA != (1 << 30) || a.splitB != (1 << 30) || a.ksA != 1 || a.ksB != 1 ||
+      a.splitA != (1 << 30) || a.splitB != (1 << 30) || a.splitC != (1 << 30) || a.ksA != 1 ||
+      a.ksB != 1 ||
       (fixa ? a.vsA : a.vsB) != 0)
     return hipErrorNotSupported;
   if (a.M <= 0 || a.N <= 0 || nz <= 0 || a.nv <= 0) return hipSuccess;

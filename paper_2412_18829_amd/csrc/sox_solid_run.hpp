@@ -443,17 +443,15 @@ SolidDynLayout solid_dyn_layout_for(const sox_plan& p, int ps, int ts) {
   return L;
 }
 
-// Pair slab ps and tau slab ts within the budget: halve the pair slab first
-// (down to one momentum transfer, n_k pairs), then the tau slab, then the
-// pair slab further.
+// Pair slab ps (whole momentum transfers q1, n_k pairs each) and tau slab
+// ts within the budget: shrink the pair slab first (down to one transfer),
+// then the tau slab.
 void pick_solid_dyn(sox_plan& p) {
   const size_t budget = ws_budget();
-  const int np2 = p.nk * p.nk;
-  int ps = np2, ts = std::min(p.n_tau, 8);
-  while (ps > p.nk && solid_dyn_layout_for(p, ps, ts).total > budget) ps = (ps + 1) / 2;
-  while (ts > 1 && solid_dyn_layout_for(p, ps, ts).total > budget) ts = (ts + 1) / 2;
-  while (ps > 1 && solid_dyn_layout_for(p, ps, ts).total > budget) ps = (ps + 1) / 2;
-  p.dyn_ps = ps;
+  int nq = p.nk, ts = std::min(p.n_tau, 8);
+  while (nq > 1 && solid_dyn_layout_for(p, nq * p.nk, ts).total > budget) nq = (nq + 1) / 2;
+  while (ts > 1 && solid_dyn_layout_for(p, nq * p.nk, ts).total > budget) ts = (ts + 1) / 2;
+  p.dyn_ps = nq * p.nk;
   p.dyn_ts = ts;
 }
 
@@ -560,15 +558,17 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
         }
       }
       {
-        // A(+-Omega)[l][P][u] = sum_Q W^{q1}(+-Omega)[P][Q] GG(+-Omega)[l][u][Q]
+        // A(+-Omega)[l][P][u] = sum_Q W^{q1}(+-Omega)[P][Q] GG(+-Omega)[l][u][Q]: one
+        // product per (+-Omega, q1) over the columns (k_v, u) of that transfer's n_k pairs
         ProfScope ps_(p, SOX_STAGE_WGEMM, s);
         CgArgs<T, double> a = cg_args<T, double>();
-        a.A = wm; a.idxA = qOf + p0; a.soA = 2L * nw * NN; a.siA = NN; a.ldA = N;
-        a.B = ggw; a.soB = nN; a.siB = (long)ps * nN; a.ldB = N;
-        a.C = aw; a.soC = nN; a.siC = (long)ps * nN; a.ldc = n;
+        a.A = wm + 2 * (long)(p0 / nk) * 2 * nw * NN; a.soA = 2L * nw * NN; a.siA = NN; a.ldA = N;
+        a.B = ggw; a.soB = (long)nk * nN; a.siB = (long)ps * nN; a.ldB = N;
+        a.C = aw; a.soC = (long)nk * nN; a.siC = (long)ps * nN; a.ldc = n;
+        a.splitC = n; a.hiC = nN;
         a.nzi = 2 * nw;
-        a.M = N; a.N = n; a.K = N;
-        if ((st = cg_launch(a, cp * 2 * nw, 4, s))) return st;
+        a.M = N; a.N = nk * n; a.K = N;
+        if ((st = cg_launch(a, (cp / nk) * 2 * nw, 4, s))) return st;
       }
       {
         // A(tau)[pair][P][u] = sum_{+-m} Tb[tau][+-m] A(+-Omega_m)[l][P][u]

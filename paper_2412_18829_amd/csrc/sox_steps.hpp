@@ -204,6 +204,10 @@ template <typename T> struct FTProb {
   int M, N, K;         // M = 2 n_omega, N = vc*n*NP, K = n_tau
   T* GG2T;             // optional [n_omega][2NP][ldt] copy (adjoint), may be null
   int ldt;
+  // qmajor = 1: P1 and P2T hold the transposed copies [n_tau][nP][NP] (Q
+  // contiguous), so the lanes of a load instruction, which run over Q, read
+  // consecutive addresses
+  int qmajor = 0;
   __device__ f64x4 loadA4(int, int row, int j) const {
     if (row >= M) return zero4<double>();
     return load4_strided<double>(Tf2 + (long)row * n_tau, 1, j, n_tau);
@@ -217,12 +221,22 @@ template <typename T> struct FTProb {
     if (Q >= Nthc || v >= n) return zero4<double>();
     const long st = (long)NP * nP;
     f64x4 r;
+    if (qmajor) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int jj = j + m;
-      r[m] = (jj < n_tau)
-                 ? P2T[jj * st + (long)Q * nP + u] * P1[(long)(n_tau - 1 - jj) * st + (long)Q * nP + v]
-                 : 0.0;
+      for (int m = 0; m < 4; ++m) {
+        const int jj = j + m;
+        r[m] = (jj < n_tau) ? P2T[jj * st + (long)u * NP + Q] *
+                                  P1[(long)(n_tau - 1 - jj) * st + (long)v * NP + Q]
+                            : 0.0;
+      }
+    } else {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int jj = j + m;
+        r[m] = (jj < n_tau) ? P2T[jj * st + (long)Q * nP + u] *
+                                  P1[(long)(n_tau - 1 - jj) * st + (long)Q * nP + v]
+                            : 0.0;
+      }
     }
     return r;
   }
