@@ -189,8 +189,9 @@ def main() -> int:
               file=sys.stderr)
         return 2
     desc, kind = WORKLOADS[args.workload]
-    if args.precision == "bf16x3" and kind not in ("bare", "static"):
-        print(f"bench.py: bf16x3 runs the bare and static molecular entries only", file=sys.stderr)
+    if args.precision == "bf16x3" and kind not in ("bare", "static", "solid"):
+        print("bench.py: bf16x3 runs the bare and static molecular entries and k-point meshes "
+              "only", file=sys.stderr)
         return 2
 
     import numpy as np
@@ -284,7 +285,7 @@ def main() -> int:
     prof = main_run["prof"]
     stage, kname = DOMINANT[kind]
     if args.precision == "bf16x3":
-        kname = "fused_bcd_bf16x3_kernel"
+        kname = "cgemm_panel_bf16x3_kernel" if solid else "fused_bcd_bf16x3_kernel"
     dom_ms, dom_launches = prof[stage]
     dom_avg_ms = dom_ms / max(dom_launches, 1)
     dom_flops_per_launch = fl[stage] * args.steps / max(dom_launches, 1)

@@ -35,7 +35,8 @@
  *   all), k_s = k_p + k_q - k_t, and follows the momentum-resolved chain of
  *   the paper's solids section (Sigma_RP = -D_PR / N_k).  The bare, static
  *   and dynamic entries, sox_build_g_tau and sox_energy_gm accept solids in
- *   fp64 and fp32; the adjoint returns SOX_ERR_UNSUPPORTED.  The dynamic
+ *   fp64, fp32 and bf16x3 (bf16x3: the B and C products in split precision,
+ *   every other step as fp32); the adjoint returns SOX_ERR_UNSUPPORTED.  The dynamic
  *   entry transforms complex functions of imaginary time at +Omega_m with
  *   t_fwd and at -Omega_m with conj(t_fwd), and inverts with
  *   f(tau) = 1/2 sum_m [t_bwd f(i Omega_m) + conj(t_bwd) f(-i Omega_m)]
@@ -102,7 +103,7 @@ typedef struct {
   int32_t n_thc;          /* N, THC interpolation points (>= 1)                */
   int32_t n_tau;          /* imaginary-time nodes (>= 1)                       */
   int32_t kmesh[3];       /* {1,1,1}: molecule; else a k-point mesh, each entry
-                             1..16, at most 256 points (fp64 / fp32 only)      */
+                             1..16, at most 256 points                         */
   double beta;            /* inverse temperature (> 0)                         */
   const double* tau;      /* HOST [n_tau], ascending in [0, beta], mirror
                              symmetric; copied at plan creation                */

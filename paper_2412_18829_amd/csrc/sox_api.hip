@@ -1336,8 +1336,6 @@ sox_status dispatch_static(sox_plan* plan, int entry, const double* X, const dou
   if (st) return st;
   const uintptr_t key[9] = {(uintptr_t)entry, (uintptr_t)X, (uintptr_t)U1, (uintptr_t)U2,
                             (uintptr_t)G, (uintptr_t)Sigma, (uintptr_t)ws, (uintptr_t)ws_bytes, 0};
-  if (plan->nk > 1 && plan->precision == SOX_BF16X3)
-    return fail(SOX_ERR_UNSUPPORTED, "k-point meshes run in fp64 or fp32");
   return run_maybe_graph(*plan, key, (hipStream_t)stream, [&](hipStream_t s) -> sox_status {
     if (plan->nk > 1) {
       if (plan->precision == SOX_FP64)
@@ -1385,8 +1383,6 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
                      (long)nk_req * nk_req * pr->n_orb > 0x7fffffffL ||
                      (long)pr->n_thc * pr->n_orb > 0x7fffffffL))
     return fail(SOX_ERR_SHAPE, "k-point problem beyond the supported range");
-  if (nk_req > 1 && precision == SOX_BF16X3)
-    return fail(SOX_ERR_UNSUPPORTED, "k-point meshes run in fp64 or fp32");
   if (!(pr->beta > 0.0) || !std::isfinite(pr->beta))
     return fail(SOX_ERR_INVALID_ARG, "beta must be positive and finite");
   if (!pr->tau || !pr->weights) return fail(SOX_ERR_INVALID_ARG, "tau / weights are NULL");

@@ -461,6 +461,192 @@ inline hipError_t launch_cgemm_panel(CgArgs<float, float> a, int nz, bool fixa, 
 }
 
 // ---------------------------------------------------------------------------
+// The same B and C products in split precision: every float32 operand x is
+// written as hi + lo with hi = bf16(x), lo = bf16(x - hi) (round to nearest
+// even), and each real product is hi*hi + hi*lo + lo*hi on the bf16 MFMA
+// (v_mfma_f32_16x16x32_bf16) with float32 accumulation; a complex
+// multiply-add is four real products, twelve MFMAs per 32-deep k chunk.
+// The fixed panel is split while it is staged into LDS (four bf16 planes:
+// hi and lo of the real and imaginary parts), the wavefront's own rows are
+// split in registers, so no split copy ever reaches HBM.  Operand layout of
+// the bf16 MFMA: lane (li, g) holds row li, k = 32 kc + 8 g + e, e < 8.
+// K <= 64 (two chunks).
+constexpr int kSplitLS = 72;  // bf16 row stride of one LDS plane (K <= 64, padded)
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u16x8 x) { return __builtin_bit_cast(bf16x8, x); }
+
+template <bool FIXA, int NW>
+__global__ __launch_bounds__(64 * NW) void cgemm_panel_bf16x3_kernel(const CgArgs<float, float> p) {
+  using V2 = f32x2;
+  __shared__ __align__(16) bf16_t pl[4][kPanelRows * kSplitLS];  // hi re, hi im, lo re, lo im
+  const int z = blockIdx.y + blockIdx.z * gridDim.y;
+  if (z >= p.nz) return;
+  const int zo = z / p.nzi;
+  const int zi = z - zo * p.nzi;
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int tn = bid % p.tiles_n;
+  const int tm = bid / p.tiles_n;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int li = lane & 15;
+  const int g = lane >> 4;
+  const int row0 = tm * (FIXA ? kPanelRows : 16 * NW);
+  const int col0 = tn * (FIXA ? 16 * NW : kPanelRows);
+
+  const V2* Ab = (const V2*)p.A + cg_off(p.idxA, p.soA, p.siA, zo, zi);
+  const V2* Bb = (const V2*)p.B + cg_off(p.idxB, p.soB, p.siB, zo, zi);
+  float* Cb = p.C + 2 * cg_off(p.idxC, p.soC, p.siC, zo, zi);
+
+  {
+    const V2* F = FIXA ? Ab : Bb;
+    const long ldf = FIXA ? p.ldA : p.ldB;
+    const int f0 = FIXA ? row0 : col0;
+    const int fext = FIXA ? p.M : p.N;
+    for (int idx = threadIdx.x; idx < kPanelRows * 64; idx += blockDim.x) {
+      const int r = idx >> 6, k = idx & 63;
+      V2 v = V2{0.f, 0.f};
+      if (f0 + r < fext && k < p.K) v = F[(long)(f0 + r) * ldf + k];
+      const bf16_t hr = f32_to_bf16(v.x), hi = f32_to_bf16(v.y);
+      const int o = r * kSplitLS + k;
+      pl[0][o] = hr;
+      pl[1][o] = hi;
+      pl[2][o] = f32_to_bf16(v.x - bf16_to_f32(hr));
+      pl[3][o] = f32_to_bf16(v.y - bf16_to_f32(hi));
+    }
+  }
+  __syncthreads();
+
+  const int vr0 = (FIXA ? col0 : row0) + 16 * wave;
+  const int vext = FIXA ? p.N : p.M;
+  const bool vok = vr0 + li < vext;
+  const V2* Vb = (FIXA ? Bb : Ab) + (long)(vok ? vr0 + li : vext - 1) * (FIXA ? p.ldB : p.ldA);
+  const long vsv = FIXA ? p.vsB : p.vsA;
+  V2 raw[16];  // own row, k = 32 kc + 8 g + e at raw[8 kc + e]
+  auto load = [&](int v) {
+    const V2* src = Vb + (long)v * vsv;
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      int k = 32 * (j >> 3) + 8 * g + (j & 7);
+      k = k < p.K ? k : p.K - 1;
+      raw[j] = src[k];
+    }
+  };
+  // own operand planes: [kc][hi re, hi im, lo re, lo im, -hi im, -lo im]
+  bf16x8 own[2][6];
+  auto split = [&]() {
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc) {
+      u16x8 hr, hm, lr, lm, nhm, nlm;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const bool ok = vok && 32 * kc + 8 * g + e < p.K;
+        const float xr = ok ? raw[8 * kc + e].x : 0.f, xi = ok ? raw[8 * kc + e].y : 0.f;
+        const bf16_t a = f32_to_bf16(xr), b = f32_to_bf16(xi);
+        const bf16_t c = f32_to_bf16(xr - bf16_to_f32(a)), d = f32_to_bf16(xi - bf16_to_f32(b));
+        hr[e] = a; hm[e] = b; lr[e] = c; lm[e] = d;
+        nhm[e] = (bf16_t)(b ^ 0x8000u);
+        nlm[e] = (bf16_t)(d ^ 0x8000u);
+      }
+      own[kc][0] = as_bf16x8(hr); own[kc][1] = as_bf16x8(hm);
+      own[kc][2] = as_bf16x8(lr); own[kc][3] = as_bf16x8(lm);
+      own[kc][4] = as_bf16x8(nhm); own[kc][5] = as_bf16x8(nlm);
+    }
+  };
+  // x * y in split precision: xh yh + xh yl + xl yh
+  auto prod3 = [](bf16x8 xh, bf16x8 xl, bf16x8 yh, bf16x8 yl, f32x4 acc) {
+    acc = mfma16x16x32bf16(xh, yh, acc);
+    acc = mfma16x16x32bf16(xh, yl, acc);
+    acc = mfma16x16x32bf16(xl, yh, acc);
+    return acc;
+  };
+
+  load(0);
+  split();
+  for (int v = 0; v < p.nv; ++v) {
+    load(v + 1 < p.nv ? v + 1 : v);
+    f32x4 accr[5], acci[5];
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      accr[b] = zero4<float>();
+      acci[b] = zero4<float>();
+    }
+    // the four panel planes of step (kc, b), read one step ahead of its MFMAs
+    auto rd = [&](int kc, int b, u16x8 (&q)[4]) {
+      const int o = (16 * b + li) * kSplitLS + 32 * kc + 8 * g;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) q[c] = *(const u16x8*)&pl[c][o];
+    };
+    u16x8 qc[4], qn[4];
+    rd(0, 0, qc);
+#pragma unroll
+    for (int kc = 0; kc < 2; ++kc) {
+#pragma unroll
+      for (int b = 0; b < 5; ++b) {
+        const int st = 5 * kc + b;
+        if (st + 1 < 10) rd((st + 1) / 5, (st + 1) % 5, qn);
+        __builtin_amdgcn_sched_barrier(0);
+        const bf16x8 phr = as_bf16x8(qc[0]);
+        const bf16x8 phm = as_bf16x8(qc[1]);
+        const bf16x8 plr = as_bf16x8(qc[2]);
+        const bf16x8 plm = as_bf16x8(qc[3]);
+        const bf16x8* w = own[kc];
+        if (FIXA) {  // A = panel, B = own: re += Ar Br + Ai (-Bi); im += Ar Bi + Ai Br
+          accr[b] = prod3(phr, plr, w[0], w[2], accr[b]);
+          accr[b] = prod3(phm, plm, w[4], w[5], accr[b]);
+          acci[b] = prod3(phr, plr, w[1], w[3], acci[b]);
+          acci[b] = prod3(phm, plm, w[0], w[2], acci[b]);
+        } else {     // A = own, B = panel: re += Ar Br + (-Ai) Bi; im += Ar Bi + Ai Br
+          accr[b] = prod3(w[0], w[2], phr, plr, accr[b]);
+          accr[b] = prod3(w[4], w[5], phm, plm, accr[b]);
+          acci[b] = prod3(w[0], w[2], phm, plm, acci[b]);
+          acci[b] = prod3(w[1], w[3], phr, plr, acci[b]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) qc[c] = qn[c];
+      }
+    }
+    float* Cv = Cb + 2 * (long)v * p.vsC;
+#pragma unroll
+    for (int b = 0; b < 5; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = FIXA ? row0 + 16 * b + acc_row<float>(g, r) : vr0 + acc_row<float>(g, r);
+        const int col = FIXA ? vr0 + li : col0 + 16 * b + li;
+        if (row < p.M && col < p.N) {
+          V2 o;
+          o.x = p.alpha * accr[b][r];
+          o.y = p.alpha * acci[b][r];
+          *(V2*)(Cv + 2 * ((long)row * p.ldc + col)) = o;
+        }
+      }
+    split();
+  }
+}
+
+inline hipError_t launch_cgemm_panel_bf16x3(CgArgs<float, float> a, int nz, bool fixa,
+                                            hipStream_t s) {
+  if (a.K < 1 || a.K > 64 || a.conjA || a.conjB || a.S || a.accumulate ||
+      a.splitA != (1 << 30) || a.splitB != (1 << 30) || a.splitC != (1 << 30) || a.ksA != 1 ||
+      a.ksB != 1 || (fixa ? a.vsA : a.vsB) != 0)
+    return hipErrorNotSupported;
+  if (a.M <= 0 || a.N <= 0 || nz <= 0 || a.nv <= 0) return hipSuccess;
+  constexpr int NW = 4;
+  a.nz = nz;
+  a.tiles_m = (a.M + (fixa ? kPanelRows : 16 * NW) - 1) / (fixa ? kPanelRows : 16 * NW);
+  a.tiles_n = (a.N + (fixa ? 16 * NW : kPanelRows) - 1) / (fixa ? 16 * NW : kPanelRows);
+  const int gy = nz < 65535 ? nz : 65535;
+  const int gz = (nz + gy - 1) / gy;
+  dim3 grid(a.tiles_m * a.tiles_n, gy, gz);
+  if (fixa)
+    hipLaunchKernelGGL((cgemm_panel_bf16x3_kernel<true, NW>), grid, dim3(64 * NW), 0, s, a);
+  else
+    hipLaunchKernelGGL((cgemm_panel_bf16x3_kernel<false, NW>), grid, dim3(64 * NW), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 template <int M1, int M2, int M3>
 __host__ __device__ constexpr int kdiff_of(int a, int b) {
   return ((((a / (M2 * M3)) - (b / (M2 * M3)) + M1) % M1) * M2 +

@@ -125,10 +125,18 @@ sox_status cg_launch(const CgArgs<T, TC>& a, int nz, int shape, hipStream_t s) {
 }
 
 // The B (fixa = false) and C (fixa = true) steps: the LDS-panel kernel where
-// it applies (float32, K <= 64), else the generic kernel with tile `shape`.
+// it applies (float32, K <= 64; split bf16 x 3 products for bf16 plans), else
+// the generic kernel with tile `shape`.
 template <typename T>
-sox_status bc_launch(const CgArgs<T, T>& a, int nz, bool fixa, int shape, hipStream_t s) {
+sox_status bc_launch(const CgArgs<T, T>& a, int nz, bool fixa, int shape, hipStream_t s,
+                     bool bf16 = false) {
   if constexpr (sizeof(T) == 4) {
+    if (bf16) {
+      const hipError_t e = launch_cgemm_panel_bf16x3(a, nz, fixa, s);
+      if (e == hipSuccess) return SOX_OK;
+      if (e != hipErrorNotSupported)
+        return fail(SOX_ERR_HIP, "split panel kernel launch failed: %s", hipGetErrorString(e));
+    }
     if (getenv("SOX_NO_PANEL") == nullptr) {
       const hipError_t e = launch_cgemm_panel(a, nz, fixa, s);
       if (e == hipSuccess) return SOX_OK;
@@ -312,7 +320,7 @@ sox_status run_solid(sox_plan& p, int entry, const double* X, const double* U1, 
         b.C = bbuf; b.soC = (long)vcs * N * N; b.vsC = (long)N * N; b.ldc = N;
         b.nv = cnt;
         b.M = N; b.N = N; b.K = n;
-        if ((st = bc_launch(b, np2, false, bcs, s))) return st;
+        if ((st = bc_launch(b, np2, false, bcs, s, p.precision == SOX_BF16X3))) return st;
       }
       {
         // C[pair][v] = GwPt^{k_w} Ut2[pair][v0 + v]^T, the GwPt panel shared by every v
@@ -323,7 +331,7 @@ sox_status run_solid(sox_plan& p, int entry, const double* X, const double* U1, 
         c.C = cbuf; c.soC = (long)vcs * N * N; c.vsC = (long)N * N; c.ldc = N;
         c.nv = cnt;
         c.M = N; c.N = N; c.K = n;
-        if ((st = bc_launch(c, np2, true, bcs, s))) return st;
+        if ((st = bc_launch(c, np2, true, bcs, s, p.precision == SOX_BF16X3))) return st;
       }
       {
         ProfScope ps(p, SOX_STAGE_KD, s);
@@ -593,7 +601,7 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
         b.C = bbuf; b.soC = NN; b.vsC = (long)np2 * NN; b.ldc = N;
         b.nv = ct;
         b.M = N; b.N = N; b.K = n;
-        if ((st = bc_launch(b, np2, false, bc_shape(N), s))) return st;
+        if ((st = bc_launch(b, np2, false, bc_shape(N), s, p.precision == SOX_BF16X3))) return st;
       }
       {
         ProfScope ps_(p, SOX_STAGE_KBC, s);
@@ -606,7 +614,7 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
         c.C = cbuf; c.soC = NN; c.vsC = (long)np2 * NN; c.ldc = N;
         c.nv = ct;
         c.M = N; c.N = N; c.K = n;
-        if ((st = bc_launch(c, np2, false, bc_shape(N), s))) return st;
+        if ((st = bc_launch(c, np2, false, bc_shape(N), s, p.precision == SOX_BF16X3))) return st;
       }
       {
         ProfScope ps_(p, SOX_STAGE_KD, s);

@@ -19,6 +19,7 @@ extern thread_local uint3e threadIdx, blockIdx, blockDim, gridDim;
 #define __forceinline__ inline
 #define __launch_bounds__(x)
 #define __shared__ static
+#define __align__(x) __attribute__((aligned(x)))
 inline void __syncthreads() {}
 typedef int hipError_t;
 enum { hipSuccess = 0, hipErrorInvalidValue = 1, hipErrorOutOfMemory = 2, hipErrorNotSupported = 3 };

@@ -75,8 +75,6 @@ def test_plan_create_rejects_bad_problems_before_device_work():
     assert _create(pr)[0] == 2                      # SHAPE: mesh entry < 1
     pr, keep = _problem(kmesh=(17, 1, 1))
     assert _create(pr)[0] == 2                      # SHAPE: mesh beyond the supported range
-    pr, keep = _problem(kmesh=(3, 3, 3))
-    assert _create(pr, precision=2)[0] == 7         # UNSUPPORTED: bf16x3 on a k-point mesh
     pr, keep = _problem()
     assert _create(pr, precision=9)[0] == 1         # unknown precision
     h = ctypes.c_void_p()

@@ -73,6 +73,8 @@ SOLID_CASES = [
     (3, 10, 4, 1, 2, (3, 1, 1), None),    # dynamic entry, templated D step
     (4, 17, 3, 0, 2, (4, 1, 1), None),    # dynamic entry, any-mesh D step
     (5, 80, 3, 1, 2, (2, 2, 1), "1"),     # dynamic entry, pair and tau slabs
+    (5, 160, 1, 2, 0, (3, 1, 1), None),   # bf16 x 3 split B / C products
+    (3, 10, 4, 2, 2, (3, 1, 1), None),    # bf16 x 3, dynamic entry
 ]
 
 

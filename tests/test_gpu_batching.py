@@ -95,3 +95,44 @@ def test_autotuner_and_cache(B, tmp_path, monkeypatch):
     Gr = host(G)
     ref = om.sigma_static_thc(wl["X"], wl["V"], wl["V"], Gr, Gr[::-1])
     assert rel_err(host(S), ref) <= 1e-6
+
+
+@pytest.mark.parametrize("entry", ["bare", "dynamic"])
+def test_solid_graph_replays_match_eager(B, entry):
+    """k-point plans (3x1x1 mesh): every launch of a sweep (all tau nodes,
+    all momentum pairs) replayed as one graph equals the eager sweep."""
+    import torch
+    wl = synth.solid((3, 1, 1), 9, 40, 10, 10.0, seed=43)
+    tp = None
+    if entry == "dynamic":
+        synth.add_dynamic_screening_solid(wl, n_poles=2)
+        tp = synth.bosonic_transform_pair(wl["tau"], wl["beta"], omega_max=10.0, tol=1e-10)
+    n, N, nt, nk = wl["n"], wl["N"], wl["n_tau"], wl["nk"]
+    extra = dict(t_fwd=tp["T_fwd"], t_bwd=tp["T_bwd"]) if tp is not None else {}
+    mk = lambda: B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision="fp32",
+                        kmesh=wl["mesh"], **extra)
+    pg, pe = mk(), mk()
+    B.sox_plan_set_graph(pg, True)
+    c = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.complex128, device="cuda")
+    X, V = c(wl["X"]), c(wl["V"])
+    W = c(wl["W_tau"]) if tp is not None else None
+    G = torch.empty((nk, nt, n, n), dtype=torch.complex128, device="cuda")
+    Sg = torch.empty_like(G)
+    Se = torch.empty_like(G)
+    wsg, wse = pg.workspace(entry), pe.workspace(entry)
+    rng = np.random.default_rng(1)
+    from oracle import sox_solid as osd
+    G0 = osd.g_tau_k(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    log(f"solid graph {entry}")
+    for rep in range(3):
+        G.copy_(c(G0 + 0.01 * rep * (rng.standard_normal(G0.shape) + 0j)))
+        junk = torch.randn(1 << 20, device="cuda") * 2.0
+        if entry == "bare":
+            B.sox_sigma_bare(pg, X, V, G, Sg, ws=wsg)
+            B.sox_sigma_bare(pe, X, V, G, Se, ws=wse)
+        else:
+            B.sox_sigma_dynamic(pg, X, W, V, G, Sg, ws=wsg)
+            B.sox_sigma_dynamic(pe, X, W, V, G, Se, ws=wse)
+        torch.cuda.synchronize()
+        assert torch.equal(Sg, Se), f"replay {rep}"
+        del junk

@@ -156,10 +156,37 @@ def test_energy_and_v_slabs(B, monkeypatch):
 
 
 def test_unsupported_requests(B):
+    """The adjoint of a k-point plan is not implemented: a status, no work."""
+    import torch
     wl = synth.solid((2, 1, 1), 4, 10, 2, 5.0, seed=1)
-    with pytest.raises(B.SoxError) as ei:
-        _plan(B, wl, "bf16x3")
-    assert ei.value.status == 7
+    plan = _plan(B, wl, "fp32")
+    z = lambda *sh: torch.zeros(sh, dtype=torch.complex128, device="cuda")
+    ws = torch.empty(1 << 20, dtype=torch.uint8, device="cuda")
+    lib = B.load()
+    st = lib.sox_sigma_vjp(plan.handle, 0, z(2, 4, 10).data_ptr(), z(2, 10, 10).data_ptr(), None,
+                           z(2, 2, 4, 4).data_ptr(), z(2, 2, 4, 4).data_ptr(), None, None, None,
+                           None, ws.data_ptr(), ws.numel(), None)
+    assert st == 7
+
+
+@pytest.mark.parametrize("shape", [((3, 1, 1), 13, 50, 3), ((3, 3, 3), 6, 24, 2)],
+                         ids=lambda s: "x".join(map(str, s[0])))
+def test_bf16x3_bare_vs_oracle(B, shape):
+    """Split precision B and C products (bf16 hi + lo, three MFMA products,
+    float32 accumulation): max relative error <= 1e-4 before any refinement."""
+    import torch
+    mesh, n, N, nt = shape
+    log(f"solid bf16x3 bare {shape}")
+    wl = synth.solid(mesh, n, N, nt, 10.0, seed=n + N)
+    G = _general_G(wl, n)
+    plan = _plan(B, wl, "bf16x3")
+    S = torch.empty(G.shape, dtype=torch.complex128, device="cuda")
+    B.sox_sigma_bare(plan, cdev(wl["X"]), cdev(wl["V"]), cdev(G), S)
+    torch.cuda.synchronize()
+    ref = osd.sigma_solid_thc(wl["X"], wl["V"], wl["V"], G, _tables(wl))
+    err = rel_err(chost(S), ref)
+    log(f"  rel err {err:.3e}")
+    assert err <= 1e-4
 
 
 # ---------------------------------------------------------------------------
@@ -317,3 +344,43 @@ def test_dynamic_full_size_k_independent_reduces_to_molecule(B):
     err = np.abs(Sh - ref[None]).max() / np.abs(ref).max()
     log(f"  rel err {err:.3e}")
     assert err <= TOL["fp32"]
+
+
+def test_bf16x3_dynamic_vs_oracle(B):
+    import torch
+    wl = synth.add_dynamic_screening_solid(synth.solid((3, 1, 1), 7, 33, 10, 10.0, seed=82),
+                                           n_poles=3)
+    tp = _tp(wl)
+    log("solid bf16x3 dynamic 3x1x1")
+    G = _general_G(wl, 9)
+    plan = _dyn_plan(B, wl, tp, "bf16x3")
+    S = torch.empty(G.shape, dtype=torch.complex128, device="cuda")
+    B.sox_sigma_dynamic(plan, cdev(wl["X"]), cdev(wl["W_tau"]), cdev(wl["V"]), cdev(G), S)
+    torch.cuda.synchronize()
+    ref = osd.sigma_solid_dynamic_thc(wl["X"], wl["W_tau"], wl["V"], G, tp["T_fwd"], tp["T_bwd"],
+                                      _tables(wl))
+    err = rel_err(chost(S), ref)
+    log(f"  rel err {err:.3e}")
+    assert err <= 1e-4
+
+
+def test_bf16x3_full_size_k_independent(B):
+    """bf16 x 3 at the full 3x3x3, n = 52, N = 400, 100-node shape against
+    the molecular oracle at sampled tau nodes (momentum-independent inputs)."""
+    import torch
+    n, N, nt, mesh = C5["n"], C5["N"], C5["n_tau"], C5["mesh"]
+    nk = int(np.prod(mesh))
+    log("solid full size k-independent bf16x3")
+    mol = synth.molecule(n, N, nt, C5["beta"], rng=synth.rng_for(57))
+    Gm = om.g_tau(mol["eps"], mol["Q"], mol["mu"], mol["beta"], mol["tau"])
+    rep = lambda a: np.repeat(a[None], nk, axis=0)
+    plan = B.Plan(n, N, mol["tau"], mol["weights"], mol["beta"], precision="bf16x3", kmesh=mesh)
+    S = torch.empty((nk, nt, n, n), dtype=torch.complex128, device="cuda")
+    B.sox_sigma_bare(plan, cdev(rep(mol["X"])), cdev(rep(mol["V"])), cdev(rep(Gm)), S)
+    torch.cuda.synchronize()
+    Sh = chost(S)
+    for j in (0, 49, 99):
+        ref = om.sigma_static_thc(mol["X"], mol["V"], mol["V"], Gm[[j]], Gm[[nt - 1 - j]])[0]
+        err = np.abs(Sh[:, j] - ref[None]).max() / np.abs(ref).max()
+        log(f"  tau node {j}: rel err {err:.3e}")
+        assert err <= 1e-4
