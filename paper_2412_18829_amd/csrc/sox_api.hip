@@ -388,6 +388,7 @@ sox_status launch_astep(const sox_plan& p, const T* u1t, const T* gbt, T* A, int
   d.alpha = T(1);
   d.transposed = 0;
   d.accumulate = 0;
+  d.m_fast = 1;  // the v row tiles of one U-tensor column panel back to back
   if (sizeof(T) == 8) {
     SOX_HIP((launch_dense<T, T, 1, 4, 2, 2>(d, cnt, s)));
   } else if ((round_up(p.n, 64) - p.n) * 10 <= p.n) {

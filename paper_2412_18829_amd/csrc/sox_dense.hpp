@@ -31,6 +31,10 @@ template <typename T, typename TC> struct DenseArgs {
   T alpha;
   int transposed;   // store C[j][i]
   int accumulate;   // C += result
+  // row tiles fastest in the workgroup order: the row tiles sharing one B
+  // column panel run back to back (same XCD, same L2) when B is the large
+  // operand
+  int m_fast = 0;
 };
 
 template <typename T, typename TC, int WGR, int WGC, int RB, int CB>
@@ -39,8 +43,8 @@ __global__ __launch_bounds__(256) void dense_nt_kernel(const DenseArgs<T, TC> p)
   using V4 = vec4_t<T>;
   const int b = blockIdx.y;
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int tn = bid % p.tiles_n;
-  const int tm = bid / p.tiles_n;
+  const int tn = p.m_fast ? bid / p.tiles_m : bid % p.tiles_n;
+  const int tm = p.m_fast ? bid % p.tiles_m : bid / p.tiles_n;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int li = lane & 15;
