@@ -98,7 +98,7 @@ struct sox_plan {
   int dyn_ps = 0;    // dynamic entry: momentum pairs per slab
   int dyn_ts = 0;    // dynamic entry: tau nodes per B, C, D slab
   int* d_ktab = nullptr;
-  double* d_tfc = nullptr;  // [n_omega][n_tau] complex T_fwd
+  double* d_tfc = nullptr;  // [2 n_omega][n_tau] complex [T_fwd; conj(T_fwd)]
   double* d_tbc = nullptr;  // [n_tau][2 n_omega] complex [T_bwd / 2 | conj(T_bwd) / 2]
   // device copies
   double* d_tf2 = nullptr;  // [2 n_omega][n_tau]  Re / Im of t_fwd
@@ -1505,9 +1505,16 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
         row[2 * (nw + m)] = 0.5 * re;
         row[2 * (nw + m) + 1] = -0.5 * im;
       }
-    e = hipMalloc(&p->d_tfc, sizeof(double) * p->t_fwd.size());
+    std::vector<double> tfs(2 * p->t_fwd.size());
+    for (size_t i = 0; i < p->t_fwd.size(); i += 2) {
+      tfs[i] = p->t_fwd[i];
+      tfs[i + 1] = p->t_fwd[i + 1];
+      tfs[p->t_fwd.size() + i] = p->t_fwd[i];
+      tfs[p->t_fwd.size() + i + 1] = -p->t_fwd[i + 1];
+    }
+    e = hipMalloc(&p->d_tfc, sizeof(double) * tfs.size());
     if (e == hipSuccess)
-      e = hipMemcpy(p->d_tfc, p->t_fwd.data(), sizeof(double) * p->t_fwd.size(), hipMemcpyHostToDevice);
+      e = hipMemcpy(p->d_tfc, tfs.data(), sizeof(double) * tfs.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMalloc(&p->d_tbc, sizeof(double) * tbc.size());
     if (e == hipSuccess)
       e = hipMemcpy(p->d_tbc, tbc.data(), sizeof(double) * tbc.size(), hipMemcpyHostToDevice);

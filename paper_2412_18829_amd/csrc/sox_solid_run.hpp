@@ -105,7 +105,9 @@ std::vector<int> solid_tables(const int mesh[3]) {
 // (float32) or 16 x 16 (float64): an 80 x 80 or 80 x 16 tile, which divides
 // N = 400 exactly.  3: 128 x 64 (eight 64 x 16 wavefronts), for the inverse
 // transform over up to 128 tau nodes.  4: 80 x 64 (float32) or 80 x 32
-// (float64) for W(Omega) GG(Omega), whose columns are the n orbitals u.
+// (float64) for W(Omega) GG(Omega) and the forward transforms (2 n_Omega
+// rows).  5: 112 x 32 (seven 16 x 32 wavefronts), for the inverse transform
+// over up to 112 tau nodes.
 template <typename T, typename TC>
 sox_status cg_launch(const CgArgs<T, TC>& a, int nz, int shape, hipStream_t s) {
   if (shape == 1) {
@@ -115,6 +117,8 @@ sox_status cg_launch(const CgArgs<T, TC>& a, int nz, int shape, hipStream_t s) {
   } else if (shape == 4) {
     if constexpr (sizeof(T) == 4) SOX_HIP((launch_cgemm<T, TC, 5, 1, 1, 4>(a, nz, s)));
     else SOX_HIP((launch_cgemm<T, TC, 5, 1, 1, 2>(a, nz, s)));
+  } else if (shape == 5) {
+    SOX_HIP((launch_cgemm<T, TC, 7, 1, 1, 2>(a, nz, s)));
   } else if (shape == 2) {
     if constexpr (sizeof(T) == 4) SOX_HIP((launch_cgemm<T, TC, 5, 1, 1, 5>(a, nz, s)));
     else SOX_HIP((launch_cgemm<T, TC, 5, 1, 1, 1>(a, nz, s)));
@@ -536,16 +540,14 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
     if ((st = cg_launch(b, nk * nt, 0, s))) return st;
   }
   {
-    // W^q(+-Omega)[P][Q] = sum_j T_fwd(*)[m][j] W^q(tau_j)[P][Q]
+    // W^q(+-Omega)[P][Q] = sum_j [T_fwd; conj(T_fwd)][(+-, m)][j] W^q(tau_j)[P][Q]
     ProfScope ps_(p, SOX_STAGE_GG_FT, s);
-    for (int sg = 0; sg < 2; ++sg) {
-      CgArgs<double, T> a = cg_args<double, T>();
-      a.A = p.d_tfc; a.ldA = nt; a.soA = 0; a.conjA = sg;
-      a.B = W; a.soB = (long)nt * NN; a.ldB = 1; a.ksB = NN;
-      a.C = wm + 2 * (long)sg * nw * NN; a.soC = 2L * nw * NN; a.ldc = NN;
-      a.M = nw; a.N = (int)NN; a.K = nt;
-      if ((st = cg_launch(a, nk, 1, s))) return st;
-    }
+    CgArgs<double, T> a = cg_args<double, T>();
+    a.A = p.d_tfc; a.ldA = nt; a.soA = 0;
+    a.B = W; a.soB = (long)nt * NN; a.ldB = 1; a.ksB = NN;
+    a.C = wm; a.soC = 2L * nw * NN; a.ldc = NN;
+    a.M = 2 * nw; a.N = (int)NN; a.K = nt;
+    if ((st = cg_launch(a, nk, 4, s))) return st;
   }
   for (int v = 0; v < n; ++v) {
     for (int p0 = 0; p0 < np2; p0 += ps) {
@@ -556,14 +558,12 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
         hipLaunchKernelGGL(gg_solid_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
                            gwpd, grqtd, kOf, kmqOf, gg, nt, nk, n, N, p0, cp, ps, v);
         SOX_HIP(hipGetLastError());
-        for (int sg = 0; sg < 2; ++sg) {
-          CgArgs<double, T> a = cg_args<double, T>();
-          a.A = p.d_tfc; a.ldA = nt; a.conjA = sg;
-          a.B = gg; a.ldB = 1; a.ksB = (long)ps * nN;
-          a.C = ggw + 2 * (long)sg * nw * ps * nN; a.ldc = (long)ps * nN;
-          a.M = nw; a.N = (int)(cp * nN); a.K = nt;
-          if ((st = cg_launch(a, 1, 1, s))) return st;
-        }
+        CgArgs<double, T> a = cg_args<double, T>();
+        a.A = p.d_tfc; a.ldA = nt;
+        a.B = gg; a.ldB = 1; a.ksB = (long)ps * nN;
+        a.C = ggw; a.ldc = (long)ps * nN;
+        a.M = 2 * nw; a.N = (int)(cp * nN); a.K = nt;
+        if ((st = cg_launch(a, 1, 4, s))) return st;
       }
       {
         // A(+-Omega)[l][P][u] = sum_Q W^{q1}(+-Omega)[P][Q] GG(+-Omega)[l][u][Q]: one
@@ -586,7 +586,7 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
         a.B = aw; a.ldB = 1; a.ksB = (long)ps * nN;
         a.C = atau + 2 * (long)p0 * nN; a.ldc = (long)np2 * nN;
         a.M = nt; a.N = (int)(cp * nN); a.K = 2 * nw;
-        if ((st = cg_launch(a, 1, 3, s))) return st;
+        if ((st = cg_launch(a, 1, nt <= 112 ? 5 : 3, s))) return st;
       }
     }
     for (int t0 = 0; t0 < nt; t0 += ts) {
