@@ -182,20 +182,20 @@ __global__ __launch_bounds__(256) void transpose_kernel(const T* in, T* out, int
 
 template <typename T>
 __global__ void fill_kernel(T* p, long count, T value) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < count) p[idx] = value;
+  SOX_FOR_FLAT(idx, count) p[idx] = value;
 }
 
 // dX[q][Q] += sum_s (M[Q][q][s] + M[Q][s][q]) X[s][Q]   (U-contraction adjoint)
 __global__ void ut_adjoint_x_kernel(const double* M, const double* X, double* dX, int n, int Nthc,
                                     int nP) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)n * Nthc) return;
-  const int q = (int)(idx / Nthc), Q = (int)(idx - (idx / Nthc) * Nthc);
-  const double* MQ = M + (long)Q * nP * nP;
-  double acc = 0.0;
-  for (int s = 0; s < n; ++s) acc += (MQ[(long)q * nP + s] + MQ[(long)s * nP + q]) * X[(long)s * Nthc + Q];
-  dX[idx] += acc;
+  SOX_FOR_FLAT(idx, (long)n * Nthc) {
+    const int q = (int)(idx / Nthc), Q = (int)(idx - (idx / Nthc) * Nthc);
+    const double* MQ = M + (long)Q * nP * nP;
+    double acc = 0.0;
+    for (int s = 0; s < n; ++s)
+      acc += (MQ[(long)q * nP + s] + MQ[(long)s * nP + q]) * X[(long)s * Nthc + Q];
+    dX[idx] += acc;
+  }
 }
 
 }  // namespace sox

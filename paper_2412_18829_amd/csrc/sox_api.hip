@@ -403,7 +403,7 @@ template <typename T>
 sox_status launch_gbar_t(const sox_plan& p, const double* G, T* gbt, int t0, int cnt,
                          hipStream_t s) {
   const long tot = (long)cnt * p.nP * p.nP;
-  hipLaunchKernelGGL(gbar_t_kernel<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, G,
+  hipLaunchKernelGGL(gbar_t_kernel<T>, grid1d(tot), dim3(256), 0, s, G,
                      gbt, p.n, p.nP, p.n_tau, t0, cnt);
   SOX_HIP(hipGetLastError());
   return SOX_OK;
@@ -489,7 +489,7 @@ sox_status launch_fused_cfg<double>(const sox_plan& p, const FusedArgs<double>& 
 
 sox_status launch_split(const float* src, bf16_t* hi, bf16_t* lo, long count, hipStream_t s) {
   if (count <= 0) return SOX_OK;
-  hipLaunchKernelGGL(split_bf16_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, src,
+  hipLaunchKernelGGL(split_bf16_kernel, grid1d(count), dim3(256), 0, s, src,
                      hi, lo, count);
   SOX_HIP(hipGetLastError());
   return SOX_OK;
@@ -598,7 +598,7 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
       // the v splits' partial D blocks, summed ahead of the back-transform
       ProfScope ps(p, SOX_STAGE_BACK, s);
       const long count = (long)cnt * NP * NP;
-      hipLaunchKernelGGL(dsplit_sum_kernel<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0,
+      hipLaunchKernelGGL(dsplit_sum_kernel<T>, grid1d(count), dim3(256), 0,
                          s, D, count, fa.d_sstride, p.fused_vsplit);
       SOX_HIP(hipGetLastError());
     }
@@ -653,11 +653,11 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
     ProjP2TProb<double> pr2{X, G, P2Td, n, N, nP, NP, 0, NP, nP, n};
     SOX_HIP((launch_gemm<ProjP2TProb<double>, double, 2, 2, 2, 2>(pr2, nt, s)));
     const long cnt = (long)nt * NP * nP;
-    hipLaunchKernelGGL(cast_kernel<T>, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, P2Td,
+    hipLaunchKernelGGL(cast_kernel<T>, grid1d(cnt), dim3(256), 0, s, P2Td,
                        P2T, cnt);
     SOX_HIP(hipGetLastError());
     const long cx = (long)NP * nP;
-    hipLaunchKernelGGL(xt_kernel<T>, dim3((unsigned)((cx + 255) / 256)), dim3(256), 0, s, X, XT,
+    hipLaunchKernelGGL(xt_kernel<T>, grid1d(cx), dim3(256), 0, s, X, XT,
                        n, N, nP, NP);
     SOX_HIP(hipGetLastError());
     // Q-contiguous copies for the forward transform's loads
@@ -756,7 +756,7 @@ sox_status launch_transpose(const T* in, T* out, int rows, int cols, long batch,
 template <typename T>
 sox_status launch_fill(T* ptr, long count, hipStream_t s) {
   if (count <= 0) return SOX_OK;
-  hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, ptr,
+  hipLaunchKernelGGL(fill_kernel<T>, grid1d(count), dim3(256), 0, s, ptr,
                      count, T(0));
   SOX_HIP(hipGetLastError());
   return SOX_OK;
@@ -922,12 +922,12 @@ sox_status run_vjp_static(sox_plan& p, int entry, const double* X, const double*
   const long nx = (long)n * N;
   DUMProb m1{U1, du1t, mbuf, n, N, nP, NP, 0, N, nP * nP, N};
   SOX_HIP((launch_gemm<DUMProb, double, 2, 2, 2, 2>(m1, 1, s)));
-  hipLaunchKernelGGL(ut_adjoint_x_kernel, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, mbuf,
+  hipLaunchKernelGGL(ut_adjoint_x_kernel, grid1d(nx), dim3(256), 0, s, mbuf,
                      X, dXs, n, N, nP);
   SOX_HIP(hipGetLastError());
   DUMProb m2{U2, du2t, mbuf, n, N, nP, NP, 1, N, nP * nP, N};
   SOX_HIP((launch_gemm<DUMProb, double, 2, 2, 2, 2>(m2, 1, s)));
-  hipLaunchKernelGGL(ut_adjoint_x_kernel, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, mbuf,
+  hipLaunchKernelGGL(ut_adjoint_x_kernel, grid1d(nx), dim3(256), 0, s, mbuf,
                      X, dXs, n, N, nP);
   SOX_HIP(hipGetLastError());
   if (dG) SOX_HIP(hipMemcpyAsync(dG, dGs, sizeof(double) * nt * n * n, hipMemcpyDeviceToDevice, s));
@@ -1036,7 +1036,7 @@ sox_status run_vjp_dynamic(sox_plan& p, const double* X, const double* Wtau, con
   ProfScope ps(p, SOX_STAGE_VJP, s);
   {
     const long cx = (long)nP * NP;
-    hipLaunchKernelGGL(xpad_kernel<T>, dim3((unsigned)((cx + 255) / 256)), dim3(256), 0, s, X, XP,
+    hipLaunchKernelGGL(xpad_kernel<T>, grid1d(cx), dim3(256), 0, s, X, XP,
                        n, N, nP, NP);
     SOX_HIP(hipGetLastError());
     UTensorProb<T> pr{V, X, u2tT, n, N, nP, NP, nP * nP, N, 1, NP};
@@ -1137,10 +1137,10 @@ sox_status run_vjp_dynamic(sox_plan& p, const double* X, const double* Wtau, con
     SOX_HIP((launch_gemm<FTAdjProb, double, 2, 2, 2, 2>(fa, 1, s)));
     {
       const long c2 = (long)nt * N * n, c1 = (long)nt * N * vc;
-      hipLaunchKernelGGL(gg_adjoint_p2_kernel, dim3((unsigned)((c2 + 255) / 256)), dim3(256), 0, s,
+      hipLaunchKernelGGL(gg_adjoint_p2_kernel, grid1d(c2), dim3(256), 0, s,
                          dGG, P1d, dP2Td, n, nP, NP, N, nt, v0, vc);
       SOX_HIP(hipGetLastError());
-      hipLaunchKernelGGL(gg_adjoint_p1_kernel, dim3((unsigned)((c1 + 255) / 256)), dim3(256), 0, s,
+      hipLaunchKernelGGL(gg_adjoint_p1_kernel, grid1d(c1), dim3(256), 0, s,
                          dGG, P2Td, dP1d, n, nP, NP, N, nt, v0, vc);
       SOX_HIP(hipGetLastError());
     }
@@ -1156,11 +1156,11 @@ sox_status run_vjp_dynamic(sox_plan& p, const double* X, const double* Wtau, con
   const long nx = (long)n * N;
   DUMProb m2{V, du2t, mbuf, n, N, nP, NP, 1, N, nP * nP, N};
   SOX_HIP((launch_gemm<DUMProb, double, 2, 2, 2, 2>(m2, 1, s)));
-  hipLaunchKernelGGL(ut_adjoint_x_kernel, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s, mbuf,
+  hipLaunchKernelGGL(ut_adjoint_x_kernel, grid1d(nx), dim3(256), 0, s, mbuf,
                      X, dXs, n, N, nP);
   SOX_HIP(hipGetLastError());
   for (int t = 0; t < nt; ++t) {
-    hipLaunchKernelGGL(add_transposed_kernel, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL(add_transposed_kernel, grid1d(nx), dim3(256), 0, s,
                        dXT + (long)t * NPnP, dXs, n, N, nP);
     SOX_HIP(hipGetLastError());
   }
@@ -1242,7 +1242,7 @@ sox_status time_fused_cfg(sox_plan& p, int cfg, int tt, double* ms_per_tau) {
   const size_t total = szA + 2 * szY + szU + szD;
   hipError_t e = hipMalloc(&buf, total * es);
   if (e != hipSuccess) return fail(SOX_ERR_OOM, "autotune buffers: %s", hipGetErrorString(e));
-  hipLaunchKernelGGL(fill_kernel<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, nullptr,
+  hipLaunchKernelGGL(fill_kernel<T>, grid1d(total), dim3(256), 0, nullptr,
                      buf, (long)total, T(0));
   FusedArgs<T> fa;
   fa.A = buf; fa.Y = buf + szA; fa.P2T = buf + szA + szY; fa.U2 = buf + szA + 2 * szY;

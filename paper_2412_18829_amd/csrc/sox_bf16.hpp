@@ -15,12 +15,12 @@
 namespace sox {
 
 __global__ void split_bf16_kernel(const float* src, bf16_t* hi, bf16_t* lo, long count) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= count) return;
-  const float x = src[idx];
-  const bf16_t h = f32_to_bf16(x);
-  hi[idx] = h;
-  lo[idx] = f32_to_bf16(x - bf16_to_f32(h));
+  SOX_FOR_FLAT(idx, count) {
+    const float x = src[idx];
+    const bf16_t h = f32_to_bf16(x);
+    hi[idx] = h;
+    lo[idx] = f32_to_bf16(x - bf16_to_f32(h));
+  }
 }
 
 struct FusedSplitArgs {

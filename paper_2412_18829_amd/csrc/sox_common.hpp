@@ -68,4 +68,17 @@ __device__ __forceinline__ int xcd_remap(int bid, int nblocks) {
   return xcd * per + (xcd < rem ? xcd : rem) + local;
 }
 
+// Flat elementwise launches.  A dispatch packet carries the grid size in
+// work-items as a 32-bit value, so such a launch is capped at kGrid1dMax
+// workgroups of 256 and its kernel strides over the rest of the range.
+constexpr long kGrid1dMax = 1L << 20;
+inline dim3 grid1d(long count) {
+  long b = (count + 255) / 256;
+  if (b < 1) b = 1;
+  return dim3((unsigned)(b < kGrid1dMax ? b : kGrid1dMax));
+}
+#define SOX_FOR_FLAT(i, count)                                                   \
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)(count); \
+       i += (long)gridDim.x * blockDim.x)
+
 }  // namespace sox

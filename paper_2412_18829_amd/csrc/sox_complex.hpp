@@ -782,11 +782,11 @@ __global__ __launch_bounds__(256) void dstep_mesh_kernel(const T* __restrict__ B
 // the k_v groups.
 __global__ __launch_bounds__(256) void dsum_kernel(const double* Dp, int ng, long count, double* D,
                                                    int accumulate) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  double acc = accumulate ? D[i] : 0.0;
-  for (int g = 0; g < ng; ++g) acc += Dp[(long)g * count + i];
-  D[i] = acc;
+  SOX_FOR_FLAT(i, count) {
+    double acc = accumulate ? D[i] : 0.0;
+    for (int g = 0; g < ng; ++g) acc += Dp[(long)g * count + i];
+    D[i] = acc;
+  }
 }
 
 // Any mesh (runtime momentum-difference table kdiff[n_k][n_k]): one thread
@@ -842,20 +842,20 @@ __global__ __launch_bounds__(256) void gg_solid_kernel(const double* __restrict_
                                                        int nt, int nk, int n, int N, int p0, int cnt,
                                                        int ps, int v) {
   const long per = (long)n * N;
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)nt * cnt * per) return;
-  const long tl = idx / per;
-  const long uq = idx - tl * per;
-  const int t = (int)(tl / cnt);
-  const int l = (int)(tl - (long)t * cnt);
-  const int Q = (int)(uq % N);
-  const int pair = p0 + l;
-  const int kv = k_of[pair], kq = kmq_of[pair];
-  const double* a = gwp + 2 * (((long)t * nk + kq) * per + uq);
-  const double* b = grqt + 2 * (((long)(nt - 1 - t) * nk + kv) * per + (long)v * N + Q);
-  double* o = gg + 2 * (((long)t * ps + l) * per + uq);
-  o[0] = a[0] * b[0] - a[1] * b[1];
-  o[1] = a[0] * b[1] + a[1] * b[0];
+  SOX_FOR_FLAT(idx, (long)nt * cnt * per) {
+    const long tl = idx / per;
+    const long uq = idx - tl * per;
+    const int t = (int)(tl / cnt);
+    const int l = (int)(tl - (long)t * cnt);
+    const int Q = (int)(uq % N);
+    const int pair = p0 + l;
+    const int kv = k_of[pair], kq = kmq_of[pair];
+    const double* a = gwp + 2 * (((long)t * nk + kq) * per + uq);
+    const double* b = grqt + 2 * (((long)(nt - 1 - t) * nk + kv) * per + (long)v * N + Q);
+    double* o = gg + 2 * (((long)t * ps + l) * per + uq);
+    o[0] = a[0] * b[0] - a[1] * b[1];
+    o[1] = a[0] * b[1] + a[1] * b[0];
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -890,8 +890,7 @@ __global__ __launch_bounds__(256) void ctranspose_kernel(const TI* in, TO* out, 
 
 // occ_c[i] = (occ[i], 0): the occupation factors as complex values.
 __global__ void real_to_complex_kernel(const double* x, double* out, long count) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) {
+  SOX_FOR_FLAT(i, count) {
     out[2 * i] = x[i];
     out[2 * i + 1] = 0.0;
   }

@@ -185,11 +185,11 @@ inline hipError_t launch_fused(const FusedArgs<T>& a, hipStream_t s) {
 // the v splits into the first one.
 template <typename T>
 __global__ __launch_bounds__(256) void dsplit_sum_kernel(T* D, long count, long stride, int ns) {
-  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= count) return;
-  T acc = D[i];
-  for (int s = 1; s < ns; ++s) acc += D[(long)s * stride + i];
-  D[i] = acc;
+  SOX_FOR_FLAT(i, count) {
+    T acc = D[i];
+    for (int s = 1; s < ns; ++s) acc += D[(long)s * stride + i];
+    D[i] = acc;
+  }
 }
 
 }  // namespace sox

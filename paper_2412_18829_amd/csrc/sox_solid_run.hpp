@@ -211,7 +211,7 @@ sox_status solid_dsum(const sox_plan& p, const double* Dp, double* D, hipStream_
   const int ng = solid_dgroups(p);
   if (!dstep_templated(p) || Dp == D) return SOX_OK;
   const long count = 2L * p.nk * p.N * p.N;
-  hipLaunchKernelGGL(dsum_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, Dp, ng,
+  hipLaunchKernelGGL(dsum_kernel, grid1d(count), dim3(256), 0, s, Dp, ng,
                      count, D, 0);
   SOX_HIP(hipGetLastError());
   return SOX_OK;
@@ -284,7 +284,7 @@ sox_status run_solid(sox_plan& p, int entry, const double* X, const double* U1, 
         return st;
     }
     const long cnt = 2L * nk * nt * n * n;
-    hipLaunchKernelGGL((cast_kernel<T>), dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
+    hipLaunchKernelGGL((cast_kernel<T>), grid1d(cnt), dim3(256), 0, s,
                        gtd, gtt, cnt);
     SOX_HIP(hipGetLastError());
     // GRq[tau][k][R][q] and GwPt[tau][k][P][w] for every node
@@ -379,7 +379,7 @@ sox_status solid_build_g(sox_plan& p, const double* Q, const double* eps, double
   hipLaunchKernelGGL(occupation_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, eps,
                      p.d_tau, mu, p.beta, nk * n, nt, occ);
   SOX_HIP(hipGetLastError());
-  hipLaunchKernelGGL(real_to_complex_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+  hipLaunchKernelGGL(real_to_complex_kernel, grid1d(tot), dim3(256), 0, s,
                      occ, occc, tot);
   SOX_HIP(hipGetLastError());
   CgArgs<double, double> a = cg_args<double, double>();
@@ -511,7 +511,7 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
         return st;
     }
     const long cx = 2L * nk * N * n;
-    hipLaunchKernelGGL((cast_kernel<T>), dim3((unsigned)((cx + 255) / 256)), dim3(256), 0, s, xtd,
+    hipLaunchKernelGGL((cast_kernel<T>), grid1d(cx), dim3(256), 0, s, xtd,
                        xtt, cx);
     SOX_HIP(hipGetLastError());
     // GwP^k(tau)[w][P] = sum_p G^k_wp conj(X^k_pP)        (float64, for GG)
@@ -555,7 +555,7 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
       {
         ProfScope ps_(p, SOX_STAGE_GG_FT, s);
         const long tot = (long)nt * cp * nN;
-        hipLaunchKernelGGL(gg_solid_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+        hipLaunchKernelGGL(gg_solid_kernel, grid1d(tot), dim3(256), 0, s,
                            gwpd, grqtd, kOf, kmqOf, gg, nt, nk, n, N, p0, cp, ps, v);
         SOX_HIP(hipGetLastError());
         CgArgs<double, T> a = cg_args<double, T>();

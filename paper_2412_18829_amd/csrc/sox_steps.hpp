@@ -114,29 +114,28 @@ template <typename T> struct AStepProb {
 //   dst = src converted (float64 -> contraction precision)
 template <typename T>
 __global__ void gbar_t_kernel(const double* G, T* out, int n, int nP, int n_tau, int t0, int cnt) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
   const long per = (long)nP * nP;
-  if (idx >= per * cnt) return;
-  const int b = (int)(idx / per);
-  const int rem = (int)(idx - (long)b * per);
-  const int v = rem / nP, s = rem - (rem / nP) * nP;
-  T val = T(0);
-  if (v < n && s < n) val = T(G[(long)(n_tau - 1 - (t0 + b)) * n * n + (long)s * n + v]);
-  out[idx] = val;
+  SOX_FOR_FLAT(idx, per * cnt) {
+    const int b = (int)(idx / per);
+    const int rem = (int)(idx - (long)b * per);
+    const int v = rem / nP, s = rem - (rem / nP) * nP;
+    T val = T(0);
+    if (v < n && s < n) val = T(G[(long)(n_tau - 1 - (t0 + b)) * n * n + (long)s * n + v]);
+    out[idx] = val;
+  }
 }
 
 template <typename T>
 __global__ void xt_kernel(const double* X, T* out, int n, int Nthc, int nP, int NP) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)NP * nP) return;
-  const int R = (int)(idx / nP), u = (int)(idx - (idx / nP) * nP);
-  out[idx] = (R < Nthc && u < n) ? T(X[(long)u * Nthc + R]) : T(0);
+  SOX_FOR_FLAT(idx, (long)NP * nP) {
+    const int R = (int)(idx / nP), u = (int)(idx - (idx / nP) * nP);
+    out[idx] = (R < Nthc && u < n) ? T(X[(long)u * Nthc + R]) : T(0);
+  }
 }
 
 template <typename T>
 __global__ void cast_kernel(const double* src, T* dst, long count) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < count) dst[idx] = T(src[idx]);
+  SOX_FOR_FLAT(idx, count) dst[idx] = T(src[idx]);
 }
 
 // ---------------------------------------------------------------------------

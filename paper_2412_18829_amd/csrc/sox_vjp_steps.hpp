@@ -363,46 +363,46 @@ struct DWtauProb {
 //   dP1[n_tau-1-tau][Q][v0+vl] += sum_u  dGG[tau][(vl,u)][Q] P2T[tau][Q][u]
 __global__ void gg_adjoint_p2_kernel(const double* dGG, const double* P1, double* dP2T, int n,
                                      int nP, int NP, int Nthc, int n_tau, int v0, int vc) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)n_tau * Nthc * n) return;
-  const int t = (int)(idx / ((long)Nthc * n));
-  const int rem = (int)(idx - (long)t * Nthc * n);
-  const int Q = rem / n, u = rem - (rem / n) * n;
-  const double* p1 = P1 + ((long)(n_tau - 1 - t) * NP + Q) * nP + v0;
-  const double* g = dGG + (long)t * vc * n * NP + (long)u * NP + Q;
-  double acc = 0.0;
-  for (int vl = 0; vl < vc; ++vl) acc += g[(long)vl * n * NP] * p1[vl];
-  dP2T[((long)t * NP + Q) * nP + u] += acc;
+  SOX_FOR_FLAT(idx, (long)n_tau * Nthc * n) {
+    const int t = (int)(idx / ((long)Nthc * n));
+    const int rem = (int)(idx - (long)t * Nthc * n);
+    const int Q = rem / n, u = rem - (rem / n) * n;
+    const double* p1 = P1 + ((long)(n_tau - 1 - t) * NP + Q) * nP + v0;
+    const double* g = dGG + (long)t * vc * n * NP + (long)u * NP + Q;
+    double acc = 0.0;
+    for (int vl = 0; vl < vc; ++vl) acc += g[(long)vl * n * NP] * p1[vl];
+    dP2T[((long)t * NP + Q) * nP + u] += acc;
+  }
 }
 
 __global__ void gg_adjoint_p1_kernel(const double* dGG, const double* P2T, double* dP1, int n,
                                      int nP, int NP, int Nthc, int n_tau, int v0, int vc) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)n_tau * Nthc * vc) return;
-  const int t = (int)(idx / ((long)Nthc * vc));
-  const int rem = (int)(idx - (long)t * Nthc * vc);
-  const int Q = rem / vc, vl = rem - (rem / vc) * vc;
-  const double* p2 = P2T + ((long)t * NP + Q) * nP;
-  const double* g = dGG + ((long)t * vc * n + (long)vl * n) * NP + Q;
-  double acc = 0.0;
-  for (int u = 0; u < n; ++u) acc += g[(long)u * NP] * p2[u];
-  dP1[((long)(n_tau - 1 - t) * NP + Q) * nP + v0 + vl] += acc;
+  SOX_FOR_FLAT(idx, (long)n_tau * Nthc * vc) {
+    const int t = (int)(idx / ((long)Nthc * vc));
+    const int rem = (int)(idx - (long)t * Nthc * vc);
+    const int Q = rem / vc, vl = rem - (rem / vc) * vc;
+    const double* p2 = P2T + ((long)t * NP + Q) * nP;
+    const double* g = dGG + ((long)t * vc * n + (long)vl * n) * NP + Q;
+    double acc = 0.0;
+    for (int u = 0; u < n; ++u) acc += g[(long)u * NP] * p2[u];
+    dP1[((long)(n_tau - 1 - t) * NP + Q) * nP + v0 + vl] += acc;
+  }
 }
 
 // XP[u][R] = X[u][R] zero padded to nP x NP;  dX[u][R] += dXT[R][u]
 template <typename T>
 __global__ void xpad_kernel(const double* X, T* out, int n, int Nthc, int nP, int NP) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)nP * NP) return;
-  const int u = (int)(idx / NP), R = (int)(idx - (idx / NP) * NP);
-  out[idx] = (u < n && R < Nthc) ? T(X[(long)u * Nthc + R]) : T(0);
+  SOX_FOR_FLAT(idx, (long)nP * NP) {
+    const int u = (int)(idx / NP), R = (int)(idx - (idx / NP) * NP);
+    out[idx] = (u < n && R < Nthc) ? T(X[(long)u * Nthc + R]) : T(0);
+  }
 }
 
 __global__ void add_transposed_kernel(const double* dXT, double* dX, int n, int Nthc, int nP) {
-  const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long)n * Nthc) return;
-  const int u = (int)(idx / Nthc), R = (int)(idx - (idx / Nthc) * Nthc);
-  dX[idx] += dXT[(long)R * nP + u];
+  SOX_FOR_FLAT(idx, (long)n * Nthc) {
+    const int u = (int)(idx / Nthc), R = (int)(idx - (idx / Nthc) * Nthc);
+    dX[idx] += dXT[(long)R * nP + u];
+  }
 }
 
 }  // namespace sox

@@ -107,6 +107,32 @@ def test_bare_workload2_full_size(B, precision):
     assert abs(e - e_ref) <= 10 * TOL[precision] * abs(e_ref)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_static_workload3_full_size_sampled_tau(B, precision):
+    """n=200, N=1200, 100 tau nodes, beta=100, W(0) = V + V Pi V: the full
+    launch configuration (all tau nodes in one slab; in the split path the
+    A operand holds more than 2^32 elements, so its flat launches stride).
+    The static Sigma(tau) depends only on G(tau) and G(beta - tau), so the
+    oracle evaluates two sampled nodes on their own."""
+    import torch
+    wl = synth.workload(3)
+    log(f"static workload3 {precision}")
+    plan = _plan(B, wl, precision)
+    G = _gpu_g(B, plan, wl)
+    S = torch.empty_like(G)
+    B.sox_sigma_static(plan, dev(wl["X"]), dev(wl["W0"]), dev(wl["V"]), G, S)
+    torch.cuda.synchronize()
+    got = host(S)
+    assert np.isfinite(got).all()
+    Gr = om.g_tau(wl["eps"], wl["Q"], wl["mu"], wl["beta"], wl["tau"])
+    Gb = om.g_mirror(Gr)
+    ts = [0, wl["n_tau"] // 2 + 1]
+    ref = om.sigma_static_thc(wl["X"], wl["W0"], wl["V"], Gr[ts], Gb[ts])
+    err = rel_err(got[ts], ref)
+    log(f"  rel err {err:.3e} at tau nodes {ts}")
+    assert err <= {"fp32": 1e-6, "bf16x3": 1e-4}[precision]
+
+
 def test_bare_equals_static_with_same_interaction(B):
     import torch
     wl = synth.small_molecule(20, 96, 6, 9.0, seed=5)
