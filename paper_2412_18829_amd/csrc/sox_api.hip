@@ -68,6 +68,7 @@ static const FusedCfg kFusedCfgs[] = {
     {16, 32, false, true, false},  // 5
     {32, 32, false, false, true},  // 6  bf16 x 3
     {64, 32, false, false, true},  // 7  bf16 x 3
+    {64, 64, false, false, true},  // 8  bf16 x 3, LDS-staged 128 x 128 workgroup tile
 };
 static const int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
 
@@ -274,7 +275,10 @@ bool cfg_allowed(int precision, int cfg) {
 
 int default_fused_cfg(int precision, int N) {
   if (precision == SOX_FP64) return 0;
-  if (precision == SOX_BF16X3) return N >= 256 ? 7 : 6;
+  // split precision: the LDS-staged 128 x 128 workgroup tile (2.3x the
+  // direct-load 64 x 32 wave tile at n = 64, N = 384 and 1.7x at n = 200,
+  // N = 1200)
+  if (precision == SOX_BF16X3) return 8;
   // float32: the 64 x 64 wave tile halves the operand traffic per flop of
   // the 32 x 32 one and measured fastest at N = 384 and N = 1200 even with
   // the padding to a multiple of 128; tiny N keeps the small tile
@@ -425,6 +429,9 @@ int fused_blocks_per_cu(const sox_plan& p) {
       case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<float, 32, 16>, 256, 0); break;
       default: break;
     }
+  } else if (p.precision == SOX_BF16X3) {
+    if (p.fused_cfg == 8)
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_lds_bf16x3_kernel, 256, 0);
   } else if (p.precision == SOX_FP64) {
     switch (p.fused_cfg) {
       case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<double, 32, 32>, 256, 0); break;
@@ -442,7 +449,8 @@ int fused_blocks_per_cu(const sox_plan& p) {
 // partial-D traffic; 1 when the launch already holds many rounds.
 void pick_vsplit(sox_plan& p) {
   p.fused_vsplit = 1;
-  if (p.precision == SOX_BF16X3 || p.nk > 1) return;
+  // the split-precision kernels other than the LDS-staged one sum all v
+  if ((p.precision == SOX_BF16X3 && p.fused_cfg != 8) || p.nk > 1) return;
   const FusedCfg& fc = kFusedCfgs[p.fused_cfg];
   const long tiles = (long)(p.NP / (2 * fc.wp)) * (p.NP / (2 * fc.wr)) * p.slab;
   const long resident = (long)fused_blocks_per_cu(p) * p.n_cu;
@@ -587,14 +595,22 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
       fs.d_tstride = fa.d_tstride; fs.accumulate = 0; fs.n = n; fs.nP = nP; fs.NP = NP;
       fs.tiles_p = tiles_p; fs.tiles_r = tiles_r; fs.n_tau = cnt;
       ProfScope ps(p, SOX_STAGE_FUSED, s);
-      if (p.fused_cfg == 7) SOX_HIP((launch_fused_bf16x3<64, 32>(fs, s)));
-      else SOX_HIP((launch_fused_bf16x3<32, 32>(fs, s)));
+      if (p.fused_cfg == 8) {
+        fs.vsplit = p.fused_vsplit;
+        fs.vchunk = fa.vchunk;
+        fs.d_sstride = fa.d_sstride;
+        SOX_HIP(launch_fused_lds_bf16x3(fs, s));
+      } else if (p.fused_cfg == 7) {
+        SOX_HIP((launch_fused_bf16x3<64, 32>(fs, s)));
+      } else {
+        SOX_HIP((launch_fused_bf16x3<32, 32>(fs, s)));
+      }
     } else {
       ProfScope ps(p, SOX_STAGE_FUSED, s);
       st = launch_fused_cfg<T>(p, fa, s);
       if (st) return st;
     }
-    if (p.fused_vsplit > 1 && p.precision != SOX_BF16X3) {
+    if (p.fused_vsplit > 1) {
       // the v splits' partial D blocks, summed ahead of the back-transform
       ProfScope ps(p, SOX_STAGE_BACK, s);
       const long count = (long)cnt * NP * NP;

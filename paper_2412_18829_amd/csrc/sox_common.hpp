@@ -38,6 +38,17 @@ __device__ __forceinline__ f32x4 mfma16x16x32bf16(bf16x8 a, bf16x8 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
+// 16 bytes per lane from global memory straight into LDS (gfx950
+// global_load_lds_dwordx4): the bytes of lane l land at lds + 16 l, so lds
+// must be the same for every lane of the wavefront.  Completion is tracked
+// by the vector-memory counter (wait_vm_all), not by the LDS counter.
+__device__ __forceinline__ void global_to_lds16(const void* src, void* lds) {
+  __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void*)src,
+                                   (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+// s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima)
+__device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
 // Round-to-nearest-even float32 -> bfloat16 (finite inputs) and back.
 __device__ __forceinline__ bf16_t f32_to_bf16(float x) {
   const unsigned u = __float_as_uint(x);

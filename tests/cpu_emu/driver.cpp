@@ -43,6 +43,11 @@ int run_case(int n, int N, int nt, int prec, int entry, bool vjp, bool dyn) {
   if (dyn) { pr.n_omega = nw; pr.t_fwd = tf.data(); pr.t_bwd = tb.data(); }
   sox_plan* plan = nullptr;
   if (sox_plan_create(&pr, prec, &plan)) { printf("create failed: %s\n", sox_last_error()); return 1; }
+  {
+    char desc[2048];
+    sox_plan_describe(plan, desc, sizeof(desc));
+    printf("plan %s\n", desc);
+  }
   size_t wsb = 0;
   sox_workspace_size(plan, entry, &wsb);
   g_ws_size = wsb + 4096;

@@ -63,6 +63,13 @@ inline emu_d4 emu_mfma_d(double a, double b, emu_d4 c) { return c + a * b; }
 #define __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, x, y, z) emu_mfma_d(a, b, c)
 #define __builtin_amdgcn_sched_barrier(x) ((void)0)
 #define __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, x, y, z) (c)
+// global-to-LDS copy: lane l's bytes land at dst + size * l
+inline void emu_global_load_lds(const void* src, void* dst, unsigned size) {
+  memcpy((char*)dst + (size_t)(threadIdx.x & 63) * size, src, size);
+}
+#define __builtin_amdgcn_global_load_lds(src, dst, size, off, aux) \
+  emu_global_load_lds((const void*)(src), (void*)(dst), (size))
+#define __builtin_amdgcn_s_waitcnt(x) ((void)0)
 inline unsigned __float_as_uint(float x) { unsigned u; memcpy(&u, &x, 4); return u; }
 inline float __uint_as_float(unsigned u) { float x; memcpy(&x, &u, 4); return x; }
 extern const char* g_emu_kernel;

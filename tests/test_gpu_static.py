@@ -198,3 +198,30 @@ def test_bf16x3_static_vs_oracle(B, shape):
     err = rel_err(host(S), ref)
     log(f"  rel err {err:.3e}")
     assert err <= 1e-4
+
+
+@pytest.mark.parametrize("shape,cfg", [((13, 50, 6), 8), ((40, 200, 4), 8), ((70, 300, 5), 8),
+                                       ((64, 384, 3), 8), ((40, 200, 4), 6), ((70, 300, 5), 7)])
+def test_bf16x3_kernels_vs_oracle(B, shape, cfg, monkeypatch):
+    """The LDS-staged split-precision kernel (128 x 128 workgroup tile,
+    32-deep k stages; config 8, the default) on one, two and three k stages
+    per v, padded P/R tiles and the v-split its occupancy selects; and the
+    direct-load kernels (configs 6 and 7)."""
+    import torch
+    monkeypatch.setenv("SOX_FUSED_CFG", str(cfg))
+    n, N, nt = shape
+    log(f"bf16x3 static {shape} config {cfg}")
+    wl = synth.small_molecule(n, N, nt, 7.0, seed=300 + n, static=True)
+    rng = np.random.default_rng(n + 1)
+    Gr = om.g_tau(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"]) + 0.05 * rng.standard_normal((nt, n, n))
+    plan = _plan(B, wl, "bf16x3")
+    info = B.sox_plan_describe(plan)
+    assert info["fused_cfg"] == cfg
+    log(f"  v split {info['fused_vsplit']}")
+    S = torch.empty((nt, n, n), dtype=torch.float64, device="cuda")
+    B.sox_sigma_static(plan, dev(wl["X"]), dev(wl["W0"]), dev(wl["V"]), dev(Gr), S)
+    torch.cuda.synchronize()
+    ref = om.sigma_static_thc(wl["X"], wl["W0"], wl["V"], Gr, Gr[::-1])
+    err = rel_err(host(S), ref)
+    log(f"  rel err {err:.3e}")
+    assert err <= 1e-4
