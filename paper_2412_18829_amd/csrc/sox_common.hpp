@@ -49,6 +49,17 @@ __device__ __forceinline__ void global_to_lds16(const void* src, void* lds) {
 // s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima)
 __device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
 
+// Workgroup barrier without a memory fence.  __syncthreads() fences, and a
+// fence makes every wavefront wait for all of its global-to-LDS copies
+// still in flight; here the caller waits explicitly for the copies the
+// other wavefronts are about to read.  The empty asm statements keep the
+// compiler from moving memory accesses across the barrier.
+__device__ __forceinline__ void barrier_nofence() {
+  asm volatile("" ::: "memory");
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
 // Round-to-nearest-even float32 -> bfloat16 (finite inputs) and back.
 __device__ __forceinline__ bf16_t f32_to_bf16(float x) {
   const unsigned u = __float_as_uint(x);

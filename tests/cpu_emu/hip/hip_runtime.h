@@ -70,6 +70,9 @@ inline void emu_global_load_lds(const void* src, void* dst, unsigned size) {
 #define __builtin_amdgcn_global_load_lds(src, dst, size, off, aux) \
   emu_global_load_lds((const void*)(src), (void*)(dst), (size))
 #define __builtin_amdgcn_s_waitcnt(x) ((void)0)
+#define __builtin_amdgcn_s_barrier() ((void)0)
+#define __builtin_amdgcn_readfirstlane(x) (x)
+#define __builtin_amdgcn_sched_group_barrier(a, b, c) ((void)0)
 inline unsigned __float_as_uint(float x) { unsigned u; memcpy(&u, &x, 4); return u; }
 inline float __uint_as_float(unsigned u) { float x; memcpy(&x, &u, 4); return x; }
 extern const char* g_emu_kernel;
