@@ -200,7 +200,8 @@ Layout layout_for(const sox_plan& p, int entry, int slab) {
   Carver c;
   L.u1 = c.take(NP * nP * nP * es);
   L.u2 = (entry == SOX_ENTRY_BARE) ? L.u1 : c.take(NP * nP * nP * es);
-  L.a = c.take((size_t)slab * n * NP * nP * es);
+  // split precision keeps A only as its bf16 hi and lo planes (written by the A step)
+  L.a = c.take(p.precision == SOX_BF16X3 ? 0 : (size_t)slab * n * NP * nP * es);
   L.p1 = c.take((size_t)slab * NP * nP * es);
   L.p2t = c.take((size_t)slab * NP * nP * es);
   L.d = c.take((size_t)slab * NP * NP * es * std::max(1, p.fused_vsplit));
@@ -375,8 +376,10 @@ sox_status launch_utensor(const sox_plan& p, const double* U, const double* X, T
 // (rows v, columns (P,q), stored row-major so stores are contiguous in q).
 template <typename T>
 sox_status launch_astep(const sox_plan& p, const T* u1t, const T* gbt, T* A, int cnt,
-                        hipStream_t s) {
+                        hipStream_t s, bf16_t* a_hi = nullptr, bf16_t* a_lo = nullptr) {
   DenseArgs<T, T> d{};
+  d.Chi = a_hi;  // split-precision path: A is stored only as its hi and lo planes
+  d.Clo = a_lo;
   d.A = gbt;
   d.B = u1t;
   d.C = A;
@@ -546,7 +549,11 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
       ProfScope ps(p, SOX_STAGE_ASTEP, s);
       st = launch_gbar_t<T>(p, G, gbt, t0, cnt, s);
       if (st) return st;
-      st = launch_astep<T>(p, u1t, gbt, A, cnt, s);
+      if (p.precision == SOX_BF16X3)
+        st = launch_astep<T>(p, u1t, gbt, A, cnt, s, (bf16_t*)(base + L.ah),
+                             (bf16_t*)(base + L.al));
+      else
+        st = launch_astep<T>(p, u1t, gbt, A, cnt, s);
       if (st) return st;
     }
     FusedArgs<T> fa;
@@ -573,15 +580,15 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
     fa.vchunk = (n + p.fused_vsplit - 1) / p.fused_vsplit;
     fa.d_sstride = (long)p.slab * NP * NP;
     if (p.precision == SOX_BF16X3) {
-      // x = hi + lo split of the four float32 operands, then bf16 x 3 MFMA
+      // x = hi + lo split of the float32 operands (A arrives split from the
+      // A step), then bf16 x 3 MFMA
       bf16_t* ah = (bf16_t*)(base + L.ah); bf16_t* al = (bf16_t*)(base + L.al);
       bf16_t* p1h = (bf16_t*)(base + L.p1h); bf16_t* p1l = (bf16_t*)(base + L.p1l);
       bf16_t* p2h = (bf16_t*)(base + L.p2h); bf16_t* p2l = (bf16_t*)(base + L.p2l);
       bf16_t* u2h = (bf16_t*)(base + L.u2h); bf16_t* u2l = (bf16_t*)(base + L.u2l);
       {
         ProfScope ps(p, SOX_STAGE_SPLIT, s);
-        const long na = (long)cnt * n * NP * nP, np1 = (long)cnt * NP * nP;
-        if ((st = launch_split((const float*)A, ah, al, na, s))) return st;
+        const long np1 = (long)cnt * NP * nP;
         if ((st = launch_split((const float*)P1, p1h, p1l, np1, s))) return st;
         if ((st = launch_split((const float*)P2T, p2h, p2l, np1, s))) return st;
         if (t0 == 0 && (st = launch_split((const float*)u2t, u2h, u2l, (long)NP * nP * nP, s)))

@@ -35,6 +35,11 @@ template <typename T, typename TC> struct DenseArgs {
   // column panel run back to back (same XCD, same L2) when B is the large
   // operand
   int m_fast = 0;
+  // split-precision output (float32 results only, no accumulate): when set,
+  // C is not written; each result x goes to Chi = bf16(x) and
+  // Clo = bf16(x - Chi) at the offset C would have had
+  bf16_t* Chi = nullptr;
+  bf16_t* Clo = nullptr;
 };
 
 template <typename T, typename TC, int WGR, int WGC, int RB, int CB>
@@ -117,8 +122,15 @@ __global__ __launch_bounds__(256) void dense_nt_kernel(const DenseArgs<T, TC> p)
         if (row < p.M && col < p.N) {
           const long off = p.transposed ? (long)col * p.ldc + row : (long)row * p.ldc + col;
           TC v = TC(p.alpha * acc[i][j][r]);
-          if (p.accumulate) v += Cb[off];
-          Cb[off] = v;
+          if (p.Chi) {
+            const float x = (float)v;
+            const bf16_t h = f32_to_bf16(x);
+            p.Chi[(long)b * p.sC + off] = h;
+            p.Clo[(long)b * p.sC + off] = f32_to_bf16(x - bf16_to_f32(h));
+          } else {
+            if (p.accumulate) v += Cb[off];
+            Cb[off] = v;
+          }
         }
       }
 }
@@ -129,6 +141,7 @@ inline hipError_t launch_dense(DenseArgs<T, TC> a, int batch, hipStream_t s) {
   constexpr int TN = WGC * CB * 16;
   if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;
   if (a.K % 16 != 0) return hipErrorInvalidValue;
+  if (a.Chi && (sizeof(TC) != 4 || !a.Clo || a.accumulate)) return hipErrorInvalidValue;
   a.tiles_m = (a.M + TM - 1) / TM;
   a.tiles_n = (a.N + TN - 1) / TN;
   dim3 grid(a.tiles_m * a.tiles_n, batch);
