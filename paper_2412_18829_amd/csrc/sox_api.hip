@@ -21,6 +21,7 @@
 #include "sox_steps.hpp"
 #include "sox_adjoint.hpp"
 #include "sox_bf16.hpp"
+#include "sox_fused_lds.hpp"
 #include "sox_vjp_steps.hpp"
 #include "sox_complex.hpp"
 
@@ -69,6 +70,7 @@ static const FusedCfg kFusedCfgs[] = {
     {32, 32, false, false, true},  // 6  bf16 x 3
     {64, 32, false, false, true},  // 7  bf16 x 3
     {64, 64, false, false, true},  // 8  bf16 x 3, LDS-staged 128 x 128 workgroup tile
+    {64, 64, true, false, false},  // 9  float32, LDS-staged 128 x 128 workgroup tile
 };
 static const int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
 
@@ -280,10 +282,10 @@ int default_fused_cfg(int precision, int N) {
   // direct-load 64 x 32 wave tile at n = 64, N = 384 and 1.7x at n = 200,
   // N = 1200)
   if (precision == SOX_BF16X3) return 8;
-  // float32: the 64 x 64 wave tile halves the operand traffic per flop of
-  // the 32 x 32 one and measured fastest at N = 384 and N = 1200 even with
-  // the padding to a multiple of 128; tiny N keeps the small tile
-  return N >= 256 ? 3 : 0;
+  // float32: the LDS-staged 128 x 128 workgroup tile (64 x 64 per
+  // wavefront) measured 1.18x (N = 384) and 1.20x (N = 1200) the direct-load
+  // 64 x 64 wave tile; tiny N keeps the small direct-load tile
+  return N >= 256 ? 9 : 0;
 }
 
 void set_fused_cfg(sox_plan& p, int cfg) {
@@ -430,11 +432,12 @@ int fused_blocks_per_cu(const sox_plan& p) {
       case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<float, 32, 64>, 256, 0); break;
       case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<float, 64, 64>, 256, 0); break;
       case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<float, 32, 16>, 256, 0); break;
+      case 9: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_lds_kernel<kLdsFp32>, 256, 0); break;
       default: break;
     }
   } else if (p.precision == SOX_BF16X3) {
     if (p.fused_cfg == 8)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_lds_bf16x3_kernel, 256, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_lds_kernel<kLdsBf16x3>, 256, 0);
   } else if (p.precision == SOX_FP64) {
     switch (p.fused_cfg) {
       case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<double, 32, 32>, 256, 0); break;
@@ -473,9 +476,41 @@ void pick_vsplit(sox_plan& p) {
   if (layout_for(p, SOX_ENTRY_STATIC, p.slab).total > ws_budget()) p.fused_vsplit = 1;
 }
 
+// Arguments of the LDS-staged kernel from the direct-load kernel's (strides
+// in elements; one plane per operand in float32, hi and lo in bf16 x 3).
+template <typename E>
+LdsFusedArgs lds_args(const FusedArgs<float>& fa, const E* a[2], const E* y[2], const E* pt[2],
+                      const E* u[2]) {
+  LdsFusedArgs l{};
+  for (int q = 0; q < 2; ++q) {
+    l.bp[q] = (const char*)a[q];
+    l.br[q] = (const char*)y[q];
+    l.cp[q] = (const char*)pt[q];
+    l.cr[q] = (const char*)u[q];
+  }
+  l.a_tstride = fa.a_tstride; l.a_vstride = fa.a_vstride; l.y_tstride = fa.y_tstride;
+  l.p_tstride = fa.p_tstride; l.u_rstride = fa.u_rstride; l.u_vstride = fa.u_vstride;
+  l.d_tstride = fa.d_tstride; l.d_sstride = fa.d_sstride;
+  l.D = fa.D;
+  l.accumulate = fa.accumulate;
+  l.n = fa.n; l.nP = fa.nP; l.NP = fa.NP;
+  l.tiles_p = fa.tiles_p; l.tiles_r = fa.tiles_r; l.n_tau = fa.n_tau;
+  l.vsplit = fa.vsplit > 1 ? fa.vsplit : 1;
+  l.vchunk = fa.vsplit > 1 ? fa.vchunk : fa.n;
+  return l;
+}
+
 template <>
 sox_status launch_fused_cfg<float>(const sox_plan& p, const FusedArgs<float>& fa, hipStream_t s) {
   switch (p.fused_cfg) {
+    case 9: {
+      const float* a[2] = {fa.A, fa.A};
+      const float* y[2] = {fa.Y, fa.Y};
+      const float* pt[2] = {fa.P2T, fa.P2T};
+      const float* u[2] = {fa.U2, fa.U2};
+      SOX_HIP(launch_fused_lds<kLdsFp32>(lds_args(fa, a, y, pt, u), s));
+      break;
+    }
     case 0: SOX_HIP((launch_fused<float, 32, 32>(fa, s))); break;
     case 1: SOX_HIP((launch_fused<float, 64, 32>(fa, s))); break;
     case 2: SOX_HIP((launch_fused<float, 32, 64>(fa, s))); break;
@@ -603,10 +638,17 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
       fs.tiles_p = tiles_p; fs.tiles_r = tiles_r; fs.n_tau = cnt;
       ProfScope ps(p, SOX_STAGE_FUSED, s);
       if (p.fused_cfg == 8) {
-        fs.vsplit = p.fused_vsplit;
-        fs.vchunk = fa.vchunk;
-        fs.d_sstride = fa.d_sstride;
-        SOX_HIP(launch_fused_lds_bf16x3(fs, s));
+        FusedArgs<float> fl;
+        fl.a_tstride = fa.a_tstride; fl.a_vstride = fa.a_vstride; fl.y_tstride = fa.y_tstride;
+        fl.p_tstride = fa.p_tstride; fl.u_rstride = fa.u_rstride; fl.u_vstride = fa.u_vstride;
+        fl.d_tstride = fa.d_tstride; fl.d_sstride = fa.d_sstride; fl.D = (float*)D;
+        fl.accumulate = 0; fl.n = n; fl.nP = nP; fl.NP = NP; fl.tiles_p = tiles_p;
+        fl.tiles_r = tiles_r; fl.n_tau = cnt; fl.vsplit = p.fused_vsplit; fl.vchunk = fa.vchunk;
+        const bf16_t* a[2] = {ah, al};
+        const bf16_t* y[2] = {p1h, p1l};
+        const bf16_t* pt[2] = {p2h, p2l};
+        const bf16_t* u[2] = {u2h, u2l};
+        SOX_HIP(launch_fused_lds<kLdsBf16x3>(lds_args(fl, a, y, pt, u), s));
       } else if (p.fused_cfg == 7) {
         SOX_HIP((launch_fused_bf16x3<64, 32>(fs, s)));
       } else {

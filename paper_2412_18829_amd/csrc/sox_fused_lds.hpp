@@ -1,0 +1,313 @@
+// LDS-staged fused B, C -> D contraction (the same products as
+// fused_bcd_kernel in sox_fused.hpp), for float32 operands on the 16x16x4
+// float32 MFMA and for split-precision operands (x = hi + lo in bf16,
+// hi hi + hi lo + lo hi on the 16x16x32 bf16 MFMA, float32 accumulation).
+//
+// A workgroup of four wavefronts owns a 128 x 128 block of D for one tau and
+// one range of v; each wavefront a 64 x 64 block (4 x 4 MFMA tiles).  The v
+// sum runs in stages of one v and one 64-byte k chunk (16 float32 or 32
+// bf16 values), and each stage in two halves: the B half needs the P-row
+// panel of A^v and the R-row panel of Y, the C half the P-row panel of
+// G_wP^T and the R-row panel of U2^v, 128 rows x 64 bytes per panel and
+// plane (hi and lo are separate planes).  The halves are copied straight
+// from global memory into a ring of five LDS buffers (16-byte global-to-LDS
+// loads, no registers in between), four halves ahead of the MFMAs.  Each
+// panel row is read from LDS by the two wavefronts that share it, so the
+// operand traffic through the vector cache is that of the workgroup tile,
+// not of four wave tiles, and the fragments of half h + 1 are read into a
+// second register set while the MFMAs of half h run.
+//
+// One barrier per half h, after the wavefront has waited for its own copies
+// of half h + 2 (copies of halves h + 3 and h + 4 stay in flight; the
+// barrier carries no memory fence, which would wait for them too): the copy
+// issued in half h overwrites the buffer of half h - 1, whose fragments
+// every wavefront consumed before the barrier that ends half h - 1.  Past
+// the last stage the copy cursor repeats the last stage, so every half
+// issues the same number of copies and the wait stays exact; the kernel
+// drains them before it ends.
+//
+// LDS rows are 64 bytes (four 16-byte segments); segment c of row r sits at
+// position c ^ ((r >> 1) & 3), so the 16-byte reads of eight consecutive
+// rows at one k group cover all banks once.  Lane (li, g) reads segment g of
+// row li: k = 4g..4g+3 for float32 (MFMA step m takes k = 4g + m in both
+// operands) and k = 8g..8g+7 for bf16.  The Hadamard epilogue of v is folded
+// into the first stage of v + 1: the first MFMA of each B and C tile starts
+// from zero, and the products of the previous v are added to D just before.
+#pragma once
+
+#include <type_traits>
+
+#include "sox_common.hpp"
+
+namespace sox {
+
+enum { kLdsBf16x3 = 0, kLdsFp32 = 1 };
+
+struct LdsFusedArgs {
+  // panel planes (hi then lo in split precision; one plane in float32)
+  const char* bp[2];  // B half, P rows: A^v      [tau][v][P][k]
+  const char* br[2];  // B half, R rows: Y        [tau][R][k]
+  const char* cp[2];  // C half, P rows: G_wP^T   [tau][P][k]
+  const char* cr[2];  // C half, R rows: U2^v     R stride u_rstride, v stride u_vstride
+  long a_tstride, a_vstride, y_tstride, p_tstride, u_rstride, u_vstride;  // elements
+  long d_tstride, d_sstride;  // float32 D: tau and v-split strides
+  float* D;
+  int accumulate;
+  int n, nP, NP;      // v range, k depth (64-byte chunks), padded THC extent
+  int tiles_p, tiles_r, n_tau;
+  int vsplit, vchunk;  // split s sums v in [s vchunk, (s+1) vchunk)
+};
+
+template <int MODE> struct LdsMode;
+template <> struct LdsMode<kLdsBf16x3> {
+  static constexpr int kPlanes = 2;  // hi, lo
+  static constexpr int kEsize = 2;
+  struct Frags {
+    bf16x8 ah[4], al[4], bh[4], bl[4];
+  };
+};
+template <> struct LdsMode<kLdsFp32> {
+  static constexpr int kPlanes = 1;
+  static constexpr int kEsize = 4;
+  struct Frags {
+    f32x4 a[4], b[4];
+  };
+};
+
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int kLdsTile = 128;             // rows of each staged panel
+constexpr int kLdsPieces = kLdsTile * 4;  // 16-byte pieces per panel plane
+constexpr int kLdsBufs = 5;               // ring of half-stage buffers
+constexpr int kLdsAhead = kLdsBufs - 1;   // halves copied ahead of the MFMAs
+
+// s_waitcnt vmcnt(N) with the other counters at their maxima
+template <int N> __device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt holds six bits");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
+}
+
+template <int MODE, int NPL>
+__device__ __forceinline__ void lds_frags(const u32x4 (*buf)[kLdsPieces], const int* sa,
+                                          const int* sy, typename LdsMode<MODE>::Frags& f) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if constexpr (MODE == kLdsBf16x3) {
+      f.ah[i] = __builtin_bit_cast(bf16x8, buf[0][sa[i]]);
+      f.al[i] = __builtin_bit_cast(bf16x8, buf[1][sa[i]]);
+      f.bh[i] = __builtin_bit_cast(bf16x8, buf[NPL][sy[i]]);
+      f.bl[i] = __builtin_bit_cast(bf16x8, buf[NPL + 1][sy[i]]);
+    } else {
+      f.a[i] = __builtin_bit_cast(f32x4, buf[0][sa[i]]);
+      f.b[i] = __builtin_bit_cast(f32x4, buf[NPL][sy[i]]);
+    }
+  }
+}
+
+// acc (+)= one 64-byte k chunk of the product; FIRST starts from zero
+template <int MODE, bool FIRST>
+__device__ __forceinline__ void lds_half_mfma(const typename LdsMode<MODE>::Frags& f,
+                                              f32x4 (*acc)[4]) {
+  if constexpr (MODE == kLdsBf16x3) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        acc[i][j] = mfma16x16x32bf16(f.ah[i], f.bh[j], FIRST ? zero4<float>() : acc[i][j]);
+        acc[i][j] = mfma16x16x32bf16(f.ah[i], f.bl[j], acc[i][j]);
+        acc[i][j] = mfma16x16x32bf16(f.al[i], f.bh[j], acc[i][j]);
+      }
+  } else {
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = mfma16x16x4(f.a[i][m], f.b[j][m],
+                                  (FIRST && m == 0) ? zero4<float>() : acc[i][j]);
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void fused_bcd_lds_kernel(const LdsFusedArgs p) {
+  constexpr int NPL = LdsMode<MODE>::kPlanes;
+  constexpr int ES = LdsMode<MODE>::kEsize;
+  constexpr int kCopies = 2 * NPL * 2;  // copies per wavefront and half
+  // [buffer][plane: P rows (hi, lo), then R rows (hi, lo)][row * 4 + swizzled segment]
+  __shared__ u32x4 lds[kLdsBufs][2 * NPL][kLdsPieces];
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int rt = bid % p.tiles_r;
+  int rest = bid / p.tiles_r;
+  const int pt = rest % p.tiles_p;
+  rest /= p.tiles_p;
+  const int t = rest % p.n_tau;
+  const int sp = rest / p.n_tau;
+  const int v_begin = sp * p.vchunk;
+  const int v_end = v_begin + p.vchunk < p.n ? v_begin + p.vchunk : p.n;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15;
+  const int g = lane >> 4;
+  const int P0 = pt * kLdsTile, R0 = rt * kLdsTile;
+
+  // Copies: instruction h of wavefront w fills LDS pieces 64 c .. 64 c + 63
+  // (c = w + 4 h) of a plane, one 16-byte piece per lane at position 64 c +
+  // lane, i.e. row 16 c + lane / 4 and swizzled segment lane % 4.  Sources
+  // are a wave-uniform base (tau, v, k chunk) plus a 32-bit byte offset per
+  // lane (the launcher checks the panels' extents).
+  unsigned orow_p[2], orow_r[2], orow_u[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = wave + 4 * h;
+    const int row = 16 * c + (lane >> 2);
+    const unsigned seg = (unsigned)((lane & 3) ^ ((row >> 1) & 3));
+    orow_p[h] = (unsigned)(P0 + row) * (unsigned)(p.nP * ES) + 16u * seg;
+    orow_r[h] = (unsigned)(R0 + row) * (unsigned)(p.nP * ES) + 16u * seg;
+    orow_u[h] = (unsigned)(R0 + row) * (unsigned)(p.u_rstride * ES) + 16u * seg;
+  }
+  const long ot_a = (long)t * p.a_tstride * ES, ot_y = (long)t * p.y_tstride * ES;
+  const long ot_p = (long)t * p.p_tstride * ES;
+  // fragment positions: P rows (wave >> 1) 64 + 16 i + li, R rows (wave & 1) 64 + 16 j + li
+  int sa[4], sy[4];
+  const int sw = g ^ ((li >> 1) & 3);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    sa[i] = ((wave >> 1) * 64 + 16 * i + li) * 4 + sw;
+    sy[i] = ((wave & 1) * 64 + 16 * i + li) * 4 + sw;
+  }
+
+  f32x4 accB[4][4], accC[4][4], dacc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      accB[i][j] = zero4<float>();
+      accC[i][j] = zero4<float>();
+      dacc[i][j] = zero4<float>();
+    }
+
+  const int KC = p.nP * ES / 64;
+  const int nst = v_end > v_begin ? (v_end - v_begin) * KC : 0;
+  // copy cursor: the stage whose halves are copied next, held at the last
+  // stage once every stage is under way
+  int cv = v_begin, ckc = 0, cs = 0;
+  const int c0 = 64 * wave, c1 = 64 * (wave + 4);
+  auto copy_panels = [&](u32x4 (*buf)[kLdsPieces], const char* const* srcp, long offp,
+                         const char* const* srcr, long offr, const unsigned* orr) {
+#pragma unroll
+    for (int q = 0; q < NPL; ++q) {
+      global_to_lds16(srcp[q] + offp + orow_p[0], &buf[q][c0]);
+      global_to_lds16(srcp[q] + offp + orow_p[1], &buf[q][c1]);
+      global_to_lds16(srcr[q] + offr + orr[0], &buf[NPL + q][c0]);
+      global_to_lds16(srcr[q] + offr + orr[1], &buf[NPL + q][c1]);
+    }
+  };
+  auto copy_b = [&](int b) {
+    const long ko = (long)ckc * 64;
+    copy_panels(lds[b], p.bp, ot_a + (long)cv * p.a_vstride * ES + ko, p.br, ot_y + ko, orow_r);
+  };
+  auto copy_c = [&](int b) {
+    const long ko = (long)ckc * 64;
+    copy_panels(lds[b], p.cp, ot_p + ko, p.cr, (long)cv * p.u_vstride * ES + ko, orow_u);
+    const int adv = cs + 1 < nst ? 1 : 0;  // selects, no branch: one block per half
+    cs += adv;
+    ckc += adv;
+    const int wrap = ckc == KC ? 1 : 0;
+    ckc = wrap ? 0 : ckc;
+    cv += wrap;
+  };
+
+  if (nst > 0) {
+    typename LdsMode<MODE>::Frags f0, f1;
+    // halves 0..3 (stages 0 and 1) in flight, then halves 0 and 1 landed
+    copy_b(0);
+    copy_c(1);
+    copy_b(2);
+    copy_c(3);
+    wait_vm<kCopies * (kLdsAhead - 2)>();
+    barrier_nofence();
+    lds_frags<MODE, NPL>(lds[0], sa, sy, f0);
+    int b1 = 1;  // buffer of half 2 s + 1
+    // B half of stage s: copy half 2 s + 4 into the buffer of half 2 s - 1,
+    // read the C-half fragments, MFMAs from f0.  C half: copy half 2 s + 5
+    // into the buffer of half 2 s, read the next B-half fragments, MFMAs
+    // from f1.  Each half is one basic block (no branch between its copies,
+    // fragment reads and MFMAs), which leaves the compiler free to overlap
+    // them.
+    auto half_b = [&](auto first, int bcopy) {
+      constexpr bool F = decltype(first)::value;
+      copy_b(bcopy);
+      lds_frags<MODE, NPL>(lds[b1], sa, sy, f1);
+      if constexpr (F) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) dacc[i][j] += accB[i][j] * accC[i][j];
+      }
+      lds_half_mfma<MODE, F>(f0, accB);
+      wait_vm<kCopies * (kLdsAhead - 2)>();
+      barrier_nofence();
+    };
+    auto half_c = [&](auto first, int bcopy, int bread) {
+      constexpr bool F = decltype(first)::value;
+      copy_c(bcopy);
+      lds_frags<MODE, NPL>(lds[bread], sa, sy, f0);
+      lds_half_mfma<MODE, F>(f1, accC);
+      wait_vm<kCopies * (kLdsAhead - 2)>();
+      barrier_nofence();
+    };
+    for (int v = v_begin; v < v_end; ++v) {
+      for (int kc = 0; kc < KC; ++kc) {
+        const int b0 = b1 == 0 ? kLdsBufs - 1 : b1 - 1;  // half 2 s
+        const int b2 = b1 + 1 == kLdsBufs ? 0 : b1 + 1;  // half 2 s + 2
+        const int b3 = b2 + 1 == kLdsBufs ? 0 : b2 + 1;  // half 2 s + 3
+        const int b4 = b3 + 1 == kLdsBufs ? 0 : b3 + 1;  // half 2 s + 4
+        if (kc == 0) {
+          half_b(std::true_type{}, b4);
+          half_c(std::true_type{}, b0, b2);
+        } else {
+          half_b(std::false_type{}, b4);
+          half_c(std::false_type{}, b0, b2);
+        }
+        b1 = b3;
+      }
+    }
+    wait_vm<0>();  // the repeated copies past the end
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) dacc[i][j] += accB[i][j] * accC[i][j];
+
+  float* Db = p.D + (long)sp * p.d_sstride + (long)t * p.d_tstride;
+  const int Pw = P0 + (wave >> 1) * 64, Rw = R0 + (wave & 1) * 64;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const long off = (long)(Pw + 16 * i + 4 * g + r) * p.NP + Rw + 16 * j + li;
+        Db[off] = p.accumulate ? Db[off] + dacc[i][j][r] : dacc[i][j][r];
+      }
+}
+
+// Grid: (R tile, P tile, tau, v split), R tiles fastest.
+template <int MODE>
+inline hipError_t launch_fused_lds(const LdsFusedArgs& a, hipStream_t s) {
+  constexpr long ES = LdsMode<MODE>::kEsize;
+  if ((a.nP * ES) % 64 != 0 || a.NP % kLdsTile != 0 || a.tiles_p * kLdsTile != a.NP ||
+      a.tiles_r * kLdsTile != a.NP || a.vsplit < 1 || a.vchunk < 1)
+    return hipErrorInvalidValue;
+  // lane offsets within one (tau, v) panel set are 32-bit
+  if ((long)a.NP * a.nP * ES >= (1L << 32) || (long)a.NP * a.u_rstride * ES >= (1L << 32))
+    return hipErrorInvalidValue;
+  const long nb = (long)a.tiles_p * a.tiles_r * a.n_tau * a.vsplit;
+  if (nb <= 0) return hipSuccess;
+  if (nb > (1L << 31) - 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fused_bcd_lds_kernel<MODE>, dim3((unsigned)nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace sox

@@ -91,27 +91,32 @@ def test_solid_entry_in_bounds(emu, case):
     assert r.returncode == 0 and "status 0" in out and "AddressSanitizer" not in out, out[-4000:]
 
 
-# the LDS-staged split-precision fused kernel (config 8): one, two and three
-# k stages per v, padded tiles, several tau slabs
+# the LDS-staged fused kernel, split precision (config 8) and float32
+# (config 9): one, two and three k stages per v, padded tiles, several tau
+# slabs, the dynamic entry's v slabs
 LDS_CASES = [
-    (13, 70, 5, 2, 1, 0, None),
-    (40, 130, 3, 2, 0, 0, None),
-    (70, 300, 2, 2, 1, 0, None),
-    (10, 40, 6, 2, 0, 0, "1"),
+    (13, 70, 5, 2, 1, 0, None, 8),
+    (40, 130, 3, 2, 0, 0, None, 8),
+    (70, 300, 2, 2, 1, 0, None, 8),
+    (10, 40, 6, 2, 0, 0, "1", 8),
+    (13, 70, 5, 1, 1, 0, None, 9),
+    (40, 130, 3, 1, 0, 0, None, 9),
+    (10, 40, 6, 1, 0, 0, "1", 9),
+    (21, 90, 6, 1, 2, 0, "3", 9),
 ]
 
 
 @pytest.mark.parametrize("case", LDS_CASES, ids=lambda c: "-".join(str(x) for x in c))
-def test_lds_split_kernel_in_bounds(emu, case):
-    n, N, nt, prec, entry, vjp, budget = case
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", SOX_FUSED_CFG="8")
+def test_lds_fused_kernel_in_bounds(emu, case):
+    n, N, nt, prec, entry, vjp, budget, cfg = case
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", SOX_FUSED_CFG=str(cfg))
     if budget:
         env["SOX_WS_BUDGET_MB"] = budget
     r = subprocess.run([emu, str(n), str(N), str(nt), str(prec), str(entry), str(vjp)],
                        capture_output=True, text=True, env=env, timeout=900)
     out = r.stdout + r.stderr
     assert r.returncode == 0 and "status 0" in out and "AddressSanitizer" not in out, out[-4000:]
-    assert '"fused_cfg":8' in out, out[-2000:]
+    assert f'"fused_cfg":{cfg}' in out, out[-2000:]
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "-".join(str(x) for x in c))

@@ -225,3 +225,27 @@ def test_bf16x3_kernels_vs_oracle(B, shape, cfg, monkeypatch):
     err = rel_err(host(S), ref)
     log(f"  rel err {err:.3e}")
     assert err <= 1e-4
+
+
+@pytest.mark.parametrize("shape", [(13, 50, 6), (40, 200, 4), (70, 300, 5), (64, 384, 3)])
+def test_fp32_lds_kernel_vs_oracle(B, shape, monkeypatch):
+    """The LDS-staged float32 fused kernel (config 9, 128 x 128 workgroup
+    tile, 16-deep k stages) against the oracle at the float32 tolerance."""
+    import torch
+    monkeypatch.setenv("SOX_FUSED_CFG", "9")
+    n, N, nt = shape
+    log(f"fp32 lds static {shape}")
+    wl = synth.small_molecule(n, N, nt, 7.0, seed=400 + n, static=True)
+    rng = np.random.default_rng(n + 2)
+    Gr = om.g_tau(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"]) + 0.05 * rng.standard_normal((nt, n, n))
+    plan = _plan(B, wl, "fp32")
+    info = B.sox_plan_describe(plan)
+    assert info["fused_cfg"] == 9
+    log(f"  v split {info['fused_vsplit']}")
+    S = torch.empty((nt, n, n), dtype=torch.float64, device="cuda")
+    B.sox_sigma_static(plan, dev(wl["X"]), dev(wl["W0"]), dev(wl["V"]), dev(Gr), S)
+    torch.cuda.synchronize()
+    ref = om.sigma_static_thc(wl["X"], wl["W0"], wl["V"], Gr, Gr[::-1])
+    err = rel_err(host(S), ref)
+    log(f"  rel err {err:.3e}")
+    assert err <= TOL["fp32"]
