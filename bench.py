@@ -45,8 +45,12 @@ WORKLOADS = {
 ENTRY = {"bare": "sox_sigma_bare", "static": "sox_sigma_static", "dynamic": "sox_sigma_dynamic",
          "solid": "sox_sigma_bare + sox_sigma_dynamic"}
 # dominant kernel per kind: (profiling stage, kernel name)
+# the fused kernel each molecular configuration launches (rocprofv3 names)
+FUSED_KERNEL = {0: "fused_bcd_kernel<float|double, 32, 32>", 3: "fused_bcd_kernel<float, 64, 64>",
+                6: "fused_bcd_bf16x3_kernel<32, 32>", 7: "fused_bcd_bf16x3_kernel<64, 32>",
+                8: "fused_bcd_lds_kernel<0> (bf16 x 3)", 9: "fused_bcd_lds_kernel<1> (float32)"}
 DOMINANT = {"bare": ("fused", "fused_bcd_kernel"), "static": ("fused", "fused_bcd_kernel"),
-            "dynamic": ("fused", "fused_bcd_kernel"), "solid": ("kbc", "cgemm_nt_kernel")}
+            "dynamic": ("fused", "fused_bcd_kernel"), "solid": ("kbc", "cgemm_panel_kernel")}
 
 
 def flops_per_sweep(n: int, N: int, nt: int, kind: str = "bare", n_omega: int = 0,
@@ -94,7 +98,7 @@ def flops_per_sweep(n: int, N: int, nt: int, kind: str = "bare", n_omega: int = 
 
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in ("sox_fused.hpp", "sox_common.hpp"):
+    for f in ("sox_fused.hpp", "sox_fused_lds.hpp", "sox_common.hpp"):
         with open(os.path.join(ROOT, "paper_2412_18829_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -284,8 +288,10 @@ def main() -> int:
     sweep_flops = sum(v for k, v in fl.items() if k != "utensor")
     prof = main_run["prof"]
     stage, kname = DOMINANT[kind]
-    if args.precision == "bf16x3":
-        kname = "cgemm_panel_bf16x3_kernel" if solid else "fused_bcd_bf16x3_kernel"
+    if not solid:
+        kname = FUSED_KERNEL.get(main_run["plan"]["fused_cfg"], kname)
+    elif args.precision == "bf16x3":
+        kname = "cgemm_panel_bf16x3_kernel"
     dom_ms, dom_launches = prof[stage]
     dom_avg_ms = dom_ms / max(dom_launches, 1)
     dom_flops_per_launch = fl[stage] * args.steps / max(dom_launches, 1)
