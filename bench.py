@@ -181,6 +181,8 @@ def main() -> int:
     ap.add_argument("--workload", type=int, default=2, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
+    ap.add_argument("--no-bf16x3-compare", action="store_true",
+                    help="skip the split-precision run reported beside a float32 run")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time of the oracle sample")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -332,6 +334,26 @@ def main() -> int:
         tol = 1e-6 if args.precision == "fp32" else 1e-4
         acc = main_err if main_err is not None else float(d)
         out["mixed_beats_fp64"] = bool(value > 1.0 / s64 and acc <= tol)
+
+    if (args.precision == "fp32" and kind in ("bare", "static") and not solid
+            and not args.no_bf16x3_compare):
+        # the split-precision path on the same workload, same step
+        rb = run("bf16x3", args.steps, args.warmup, profile=True)
+        sb = rb["seconds"] / args.steps
+        fb_ms, fb_n = rb["prof"]["fused"]
+        fb_ach = fl["fused"] * args.steps / max(fb_n, 1) / (fb_ms / max(fb_n, 1) * 1e-3) / 1e12
+        d = np.abs(rb["Sigma"] - main_run["Sigma"]).max() / np.abs(main_run["Sigma"]).max()
+        out["bf16x3_path"] = {
+            "sweeps_per_s": 1.0 / sb, "ms_per_step": 1e3 * sb,
+            "max_rel_err": err_of(rb["Sigma"]), "max_rel_diff_to_fp32": float(d),
+            "fused_kernel": FUSED_KERNEL.get(rb["plan"]["fused_cfg"], "?"),
+            "fused_avg_launch_ms": fb_ms / max(fb_n, 1),
+            "fused_achieved_tflops_alg": fb_ach,
+            "fused_frac_of_bf16_peak": fb_ach / PEAK_TFLOPS["bf16x3"],
+            "fused_frac_of_bf16_peak_mfma_work": 3.0 * fb_ach / PEAK_TFLOPS["bf16x3"],
+            "stage_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in rb["prof"].items()
+                                  if k != "dropped" and v[1] > 0},
+        }
 
     rec = {
         "metric": METRIC,

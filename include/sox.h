@@ -86,7 +86,11 @@ typedef enum {
  *   SOX_FP32    float32 MFMA (v_mfma_f32_16x16x4f32), float32 accumulation
  *   SOX_BF16X3  each float32 operand split as hi + lo bfloat16; the products
  *               hi*hi + hi*lo + lo*hi run on bf16 MFMA with float32
- *               accumulation                                                */
+ *               accumulation.  Molecules: the bare and static entries (the
+ *               A step and the fused B, C -> D contraction in split
+ *               precision, the other steps in float32); the molecular
+ *               dynamic entry and the adjoint return SOX_ERR_UNSUPPORTED
+ *               for a bf16x3 plan.                                          */
 typedef enum { SOX_FP64 = 0, SOX_FP32 = 1, SOX_BF16X3 = 2 } sox_precision;
 
 /* Entry kinds, for sox_workspace_size and sox_sigma_vjp. */

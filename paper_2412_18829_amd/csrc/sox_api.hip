@@ -22,6 +22,7 @@
 #include "sox_adjoint.hpp"
 #include "sox_bf16.hpp"
 #include "sox_fused_lds.hpp"
+#include "sox_dense_lds.hpp"
 #include "sox_vjp_steps.hpp"
 #include "sox_complex.hpp"
 
@@ -379,8 +380,29 @@ sox_status launch_utensor(const sox_plan& p, const double* U, const double* X, T
 template <typename T>
 sox_status launch_astep(const sox_plan& p, const T* u1t, const T* gbt, T* A, int cnt,
                         hipStream_t s, bf16_t* a_hi = nullptr, bf16_t* a_lo = nullptr) {
+  if (sizeof(T) == 4) {
+    // LDS-staged GEMM (C3: 37.5 -> 22.4 ms per sweep against the direct-load
+    // kernel below); rows (tau, v) with v padded to nP, one launch per slab
+    DenseLdsArgs l{};
+    l.A = (const float*)gbt;
+    l.B = (const float*)u1t;
+    l.lda = p.nP;
+    l.ldb = p.nP;
+    l.M = cnt * p.nP;
+    l.N = p.NP * p.nP;
+    l.K = p.nP;
+    l.rgroup = p.nP;
+    l.rvalid = p.n;
+    l.c_gstride = (long)p.n * p.NP * p.nP;
+    l.ldc = (long)p.NP * p.nP;
+    l.C = (float*)A;
+    l.Chi = a_hi;  // split-precision path: A is stored only as its hi and lo planes
+    l.Clo = a_lo;
+    SOX_HIP(launch_dense_lds_f32(l, s));
+    return SOX_OK;
+  }
   DenseArgs<T, T> d{};
-  d.Chi = a_hi;  // split-precision path: A is stored only as its hi and lo planes
+  d.Chi = a_hi;
   d.Clo = a_lo;
   d.A = gbt;
   d.B = u1t;
