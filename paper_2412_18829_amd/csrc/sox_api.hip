@@ -398,7 +398,7 @@ sox_status launch_astep(const sox_plan& p, const T* u1t, const T* gbt, T* A, int
     l.C = (float*)A;
     l.Chi = a_hi;  // split-precision path: A is stored only as its hi and lo planes
     l.Clo = a_lo;
-    SOX_HIP(launch_dense_lds_f32(l, s));
+    SOX_HIP(launch_dense_lds_f32(l, 1, s));
     return SOX_OK;
   }
   DenseArgs<T, T> d{};
@@ -700,6 +700,40 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
   return SOX_OK;
 }
 
+// W(Omega) GG(Omega) for every Omega of a v-slab: AW[m] = W2[m] GG2[m]^T
+// (W2 [2NP][2NP], GG2 [vcn][2NP], AW [2NP][vcn]).  float32 on the LDS-staged
+// GEMM (C4: 1.28 s per sweep on the direct-load kernel), float64 on the
+// direct-load one.
+template <typename T>
+sox_status launch_wgg(const T* W2, const T* GG2, T* AW, int NP, long vcn, int nw, hipStream_t s) {
+  if (sizeof(T) == 4) {
+    DenseLdsArgs l{};
+    l.A = (const float*)W2;
+    l.B = (const float*)GG2;
+    l.C = (float*)AW;
+    l.lda = 2L * NP;
+    l.ldb = 2L * NP;
+    l.ldc = vcn;
+    l.sA = 4L * NP * NP;
+    l.sB = vcn * 2 * NP;
+    l.sC = 2L * NP * vcn;
+    l.M = 2 * NP;
+    l.N = (int)vcn;
+    l.K = 2 * NP;
+    l.rgroup = l.M;
+    l.rvalid = l.M;
+    SOX_HIP(launch_dense_lds_f32(l, nw, s));
+    return SOX_OK;
+  }
+  DenseArgs<T, T> d{};
+  d.A = W2; d.B = GG2; d.C = AW;
+  d.lda = 2L * NP; d.ldb = 2L * NP; d.ldc = vcn;
+  d.sA = 4L * NP * NP; d.sB = vcn * 2 * NP; d.sC = 2L * NP * vcn;
+  d.M = 2 * NP; d.N = (int)vcn; d.K = 2 * NP; d.alpha = T(1);
+  SOX_HIP((launch_dense<T, T, 2, 2, 2, 2>(d, nw, s)));
+  return SOX_OK;
+}
+
 template <typename T>
 sox_status launch_transpose(const T* in, T* out, int rows, int cols, long batch, hipStream_t s);
 
@@ -767,26 +801,7 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
     }
     {
       ProfScope ps(p, SOX_STAGE_WGEMM, s);
-      DenseArgs<T, T> d{};
-      d.A = W2;
-      d.B = GG2;
-      d.C = AW;
-      d.lda = 2L * NP;
-      d.ldb = 2L * NP;
-      d.ldc = (long)vc * n;
-      d.sA = 4L * NP * NP;
-      d.sB = (long)vc * n * 2 * NP;
-      d.sC = 2L * NP * vc * n;
-      d.M = 2 * NP;
-      d.N = vc * n;
-      d.K = 2 * NP;
-      d.alpha = T(1);
-      d.transposed = 0;
-      d.accumulate = 0;
-      // 64 x 32 wave tiles: measured 20% faster than 64 x 64 at n = 300, N = 1800
-      // (higher occupancy hides the operand loads of the long K loop)
-      if (sizeof(T) == 8) SOX_HIP((launch_dense<T, T, 2, 2, 2, 2>(d, nw, s)));
-      else SOX_HIP((launch_dense<T, T, 2, 2, 4, 2>(d, nw, s)));
+      if ((st = launch_wgg<T>(W2, GG2, AW, NP, (long)vc * n, nw, s))) return st;
     }
     {
       ProfScope ps(p, SOX_STAGE_IFT, s);
@@ -1151,15 +1166,7 @@ sox_status run_vjp_dynamic(sox_plan& p, const double* X, const double* Wtau, con
     FTProb<T> ft{p.d_tf2, P1d, P2Td, GG2, n, nP, NP, N, nw, nt, v0, vc, 2 * nw, vc * n * NP, nt,
                  GG2T, ldk};
     SOX_HIP((launch_gemm<FTProb<T>, double, 2, 2, 2, 2>(ft, 1, s)));
-    {
-      DenseArgs<T, T> d{};
-      d.A = W2; d.B = GG2; d.C = AW;
-      d.lda = 2L * NP; d.ldb = 2L * NP; d.ldc = vcn;
-      d.sA = 4L * NP * NP; d.sB = vcn * 2 * NP; d.sC = 2L * NP * vcn;
-      d.M = 2 * NP; d.N = (int)vcn; d.K = 2 * NP; d.alpha = T(1);
-      if (sizeof(T) == 8) SOX_HIP((launch_dense<T, T, 2, 2, 2, 2>(d, nw, s)));
-      else SOX_HIP((launch_dense<T, T, 2, 2, 4, 2>(d, nw, s)));  // as in the forward sweep
-    }
+    if ((st = launch_wgg<T>(W2, GG2, AW, NP, vcn, nw, s))) return st;
     IFTProb<T> ift{p.d_tb2, AW, Adyn, n, nP, NP, nw, nt, vc, nt, NP * vc * nP, 2 * nw};
     SOX_HIP((launch_gemm<IFTProb<T>, double, 2, 2, 2, 2>(ift, 1, s)));
     if ((st = launch_transpose<T>(Adyn, AdynT, NP, nP, (long)nt * vc, s))) return st;

@@ -12,6 +12,7 @@
 // multiple of 16; rows and columns past M and N are read from the last
 // valid row and not stored.
 //
+// blockIdx.y runs over a batch (operand and output strides sA, sB, sC).
 // Rows come in groups (the A step: group = tau, rows = v padded to nP):
 // row r is row r % rgroup of group r / rgroup, stored only when
 // r % rgroup < rvalid, at C + group c_gstride + (r % rgroup) ldc + col.
@@ -36,6 +37,7 @@ struct DenseLdsArgs {
   float* C;
   bf16_t* Chi;
   bf16_t* Clo;
+  long sA, sB, sC;      // batch strides (elements; blockIdx.y is the batch)
   int tiles_m, tiles_n;
 };
 
@@ -50,6 +52,7 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
   const int li = lane & 15;
   const int g = lane >> 4;
   const int M0 = tm * kLdsTile, N0 = tn * kLdsTile;
+  const long bat = blockIdx.y;
 
   // copies: instruction h of wavefront w fills pieces 64 c .. 64 c + 63 (c = w + 4 h)
   const char* srca[2];
@@ -61,8 +64,8 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
     const int seg = (lane & 3) ^ ((row >> 1) & 3);
     const int ra = M0 + row < p.M ? M0 + row : p.M - 1;
     const int rb = N0 + row < p.N ? N0 + row : p.N - 1;
-    srca[h] = (const char*)(p.A + (long)ra * p.lda) + 16 * seg;
-    srcb[h] = (const char*)(p.B + (long)rb * p.ldb) + 16 * seg;
+    srca[h] = (const char*)(p.A + bat * p.sA + (long)ra * p.lda) + 16 * seg;
+    srcb[h] = (const char*)(p.B + bat * p.sB + (long)rb * p.ldb) + 16 * seg;
   }
   int sa[4], sb[4];
   const int sw = g ^ ((li >> 1) & 3);
@@ -144,7 +147,7 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
       const int row = Rw + 16 * i + 4 * g + r;
       const int grp = row / p.rgroup, rin = row - grp * p.rgroup;
       if (row >= p.M || rin >= p.rvalid) continue;
-      const long base = (long)grp * p.c_gstride + (long)rin * p.ldc;
+      const long base = bat * p.sC + (long)grp * p.c_gstride + (long)rin * p.ldc;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int col = Cw + 16 * j + li;
@@ -161,15 +164,16 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
     }
 }
 
-inline hipError_t launch_dense_lds_f32(DenseLdsArgs a, hipStream_t s) {
-  if (a.M <= 0 || a.N <= 0) return hipSuccess;
+inline hipError_t launch_dense_lds_f32(DenseLdsArgs a, int batch, hipStream_t s) {
+  if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;
+  if (batch > 65535) return hipErrorInvalidValue;
   if (a.K % 16 != 0 || a.K <= 0 || a.rgroup <= 0 || (a.Chi && !a.Clo) || (!a.Chi && !a.C))
     return hipErrorInvalidValue;
   a.tiles_m = (a.M + kLdsTile - 1) / kLdsTile;
   a.tiles_n = (a.N + kLdsTile - 1) / kLdsTile;
   const long nb = (long)a.tiles_m * a.tiles_n;
   if (nb > (1L << 31) - 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(dense_lds_f32_kernel, dim3((unsigned)nb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(dense_lds_f32_kernel, dim3((unsigned)nb, (unsigned)batch), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
