@@ -176,16 +176,24 @@ namespace {
 
 // -- workspace layout --------------------------------------------------------
 struct Layout {
-  size_t u1, u2, a, p1, p2t, d, e, gbt;
+  size_t u1, u2, a, p1, p2t, d, e, gbt, ukr;
   size_t ah, al, p1h, p1l, p2h, p2l, u2h, u2l;  // bf16 x 3 split operands
   size_t total;
 };
 
 struct DynLayout {
-  size_t p1d, p2td, p1q, p2q, p2t, xt, u2, w2, gg2, aw, adyn, d, e, total;
+  size_t p1d, p2td, p1q, p2q, p2t, xt, u2, w2, gg2, aw, adyn, d, e, ukr, total;
 };
 
 size_t elem_size(int precision) { return precision == SOX_FP64 ? 8 : 4; }
+
+// float32 scratch of the U-contraction on the LDS-staged GEMM (the
+// Khatri-Rao factor and the padded interaction); none in float64 plans
+size_t utensor_scratch_bytes(const sox_plan& p) {
+  if (p.precision == SOX_FP64) return 0;
+  return ((size_t)p.nP * p.nP * p.NP + (size_t)p.NP * p.NP) * 4;
+}
+
 
 struct Carver {
   size_t off = 0;
@@ -210,6 +218,7 @@ Layout layout_for(const sox_plan& p, int entry, int slab) {
   L.d = c.take((size_t)slab * NP * NP * es * std::max(1, p.fused_vsplit));
   L.e = c.take((size_t)slab * n * NP * 8);
   L.gbt = c.take((size_t)slab * nP * nP * es);
+  L.ukr = c.take(utensor_scratch_bytes(p));
   if (p.precision == SOX_BF16X3) {
     const size_t na = (size_t)slab * n * NP * nP, np1 = (size_t)slab * NP * nP, nu = NP * nP * nP;
     L.ah = c.take(na * 2); L.al = c.take(na * 2);
@@ -239,6 +248,7 @@ DynLayout dyn_layout_for(const sox_plan& p, int vc, int eslab) {
   L.adyn = c.take(nt * (size_t)vc * NP * nP * es);
   L.d = c.take(nt * NP * NP * es);
   L.e = c.take((size_t)eslab * n * NP * 8);
+  L.ukr = c.take(utensor_scratch_bytes(p));
   L.total = c.off;
   return L;
 }
@@ -369,7 +379,34 @@ sox_status check_ws(const sox_plan* plan, int entry, const void* ws, size_t ws_b
 // -- launch sequences ----------------------------------------------------------
 template <typename T>
 sox_status launch_utensor(const sox_plan& p, const double* U, const double* X, T* out,
-                          hipStream_t s) {
+                          hipStream_t s, float* scratch = nullptr) {
+  if (sizeof(T) == 4 && scratch) {
+    // float32: U[P][(q,s)] = sum_Q V_PQ KR[(q,s)][Q] on the LDS-staged GEMM
+    // (C3: 14.6 ms for both U-tensors with the float64 loader-formed
+    // Khatri-Rao product)
+    float* KR = scratch;
+    float* V32 = scratch + (size_t)p.nP * p.nP * p.NP;
+    const long nkr = (long)p.nP * p.nP * p.NP, nv = (long)p.NP * p.NP;
+    hipLaunchKernelGGL(kr_kernel, grid1d(nkr), dim3(256), 0, s, X, KR, p.n, p.N, p.nP, p.NP);
+    SOX_HIP(hipGetLastError());
+    hipLaunchKernelGGL(pad_cast_kernel, grid1d(nv), dim3(256), 0, s, U, V32, p.N, p.N, p.NP,
+                       p.NP);
+    SOX_HIP(hipGetLastError());
+    DenseLdsArgs l{};
+    l.A = V32;
+    l.B = KR;
+    l.C = (float*)out;
+    l.lda = p.NP;
+    l.ldb = p.NP;
+    l.ldc = (long)p.nP * p.nP;
+    l.M = p.NP;
+    l.N = p.nP * p.nP;
+    l.K = p.NP;
+    l.rgroup = l.M;
+    l.rvalid = l.M;
+    SOX_HIP(launch_dense_lds_f32(l, 1, s));
+    return SOX_OK;
+  }
   UTensorProb<T> pr{U, X, out, p.n, p.N, p.nP, p.NP, p.nP * p.nP, p.N, 0, p.NP};
   SOX_HIP((launch_gemm<UTensorProb<T>, double, 2, 2, 2, 2>(pr, 1, s)));
   return SOX_OK;
@@ -582,12 +619,14 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
   sox_status st;
   {
     ProfScope ps(p, SOX_STAGE_UTENSOR, s);
-    st = launch_utensor<T>(p, U1, X, u1t, s);
+    float* ukr = (float*)(base + L.ukr);
+    st = launch_utensor<T>(p, U1, X, u1t, s, ukr);
     if (st) return st;
     if (entry != SOX_ENTRY_BARE) {
-      st = launch_utensor<T>(p, U2, X, u2t, s);
+      st = launch_utensor<T>(p, U2, X, u2t, s, ukr);
       if (st) return st;
     }
+
   }
   const FusedCfg& fc = kFusedCfgs[p.fused_cfg];
   if (NP % (2 * fc.wp) != 0 || NP % (2 * fc.wr) != 0)
@@ -764,8 +803,9 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
   sox_status st;
   {
     ProfScope ps(p, SOX_STAGE_UTENSOR, s);
-    st = launch_utensor<T>(p, V, X, U2, s);
+    st = launch_utensor<T>(p, V, X, U2, s, (float*)(base + L.ukr));
     if (st) return st;
+
   }
   {
     ProfScope ps(p, SOX_STAGE_PROJECT, s);

@@ -133,6 +133,29 @@ __global__ void xt_kernel(const double* X, T* out, int n, int Nthc, int nP, int 
   }
 }
 
+// float32 operands of the U-contraction on the LDS-staged GEMM (zero
+// padded so the GEMM runs without masks):
+//   KR[(q nP + s)][Q] = X_qQ X_sQ   ([nP*nP][NP], the Khatri-Rao factor)
+//   V32[P][Q] = U_PQ                ([NP][NP])
+__global__ void kr_kernel(const double* X, float* KR, int n, int Nthc, int nP, int NP) {
+  SOX_FOR_FLAT(idx, (long)nP * nP * NP) {
+    const long j = idx / NP;
+    const int Q = (int)(idx - j * NP);
+    const int q = (int)(j / nP), s = (int)(j - (long)q * nP);
+    float v = 0.0f;
+    if (q < n && s < n && Q < Nthc) v = (float)(X[(long)q * Nthc + Q] * X[(long)s * Nthc + Q]);
+    KR[idx] = v;
+  }
+}
+
+__global__ void pad_cast_kernel(const double* src, float* dst, int rows, int cols, int rows_pad,
+                                int cols_pad) {
+  SOX_FOR_FLAT(idx, (long)rows_pad * cols_pad) {
+    const int r = (int)(idx / cols_pad), c = (int)(idx - (long)r * cols_pad);
+    dst[idx] = (r < rows && c < cols) ? (float)src[(long)r * cols + c] : 0.0f;
+  }
+}
+
 template <typename T>
 __global__ void cast_kernel(const double* src, T* dst, long count) {
   SOX_FOR_FLAT(idx, count) dst[idx] = T(src[idx]);
