@@ -176,13 +176,13 @@ namespace {
 
 // -- workspace layout --------------------------------------------------------
 struct Layout {
-  size_t u1, u2, a, p1, p2t, d, e, gbt, ukr;
+  size_t u1, u2, a, p1, p2t, d, e, gbt, ukr, xp, d64;
   size_t ah, al, p1h, p1l, p2h, p2l, u2h, u2l;  // bf16 x 3 split operands
   size_t total;
 };
 
 struct DynLayout {
-  size_t p1d, p2td, p1q, p2q, p2t, xt, u2, w2, gg2, aw, adyn, d, e, ukr, total;
+  size_t p1d, p2td, p1q, p2q, p2t, xt, u2, w2, gg2, aw, adyn, d, e, ukr, xp, d64, total;
 };
 
 size_t elem_size(int precision) { return precision == SOX_FP64 ? 8 : 4; }
@@ -219,6 +219,8 @@ Layout layout_for(const sox_plan& p, int entry, int slab) {
   L.e = c.take((size_t)slab * n * NP * 8);
   L.gbt = c.take((size_t)slab * nP * nP * es);
   L.ukr = c.take(utensor_scratch_bytes(p));
+  L.xp = c.take((size_t)n * NP * 8);
+  L.d64 = c.take(p.precision == SOX_FP64 ? 0 : (size_t)slab * NP * NP * 8);
   if (p.precision == SOX_BF16X3) {
     const size_t na = (size_t)slab * n * NP * nP, np1 = (size_t)slab * NP * nP, nu = NP * nP * nP;
     L.ah = c.take(na * 2); L.al = c.take(na * 2);
@@ -249,6 +251,8 @@ DynLayout dyn_layout_for(const sox_plan& p, int vc, int eslab) {
   L.d = c.take(nt * NP * NP * es);
   L.e = c.take((size_t)eslab * n * NP * 8);
   L.ukr = c.take(utensor_scratch_bytes(p));
+  L.xp = c.take((size_t)n * NP * 8);
+  L.d64 = c.take(p.precision == SOX_FP64 ? 0 : (size_t)eslab * NP * NP * 8);
   L.total = c.off;
   return L;
 }
@@ -600,6 +604,44 @@ sox_status launch_split(const float* src, bf16_t* hi, bf16_t* lo, long count, hi
   return SOX_OK;
 }
 
+// Back-transform of cnt tau nodes in float64 (THC section): Sigma_RP =
+// -D_PR, E = X D^T, Sigma[t0 + b] = -E X^T, both products on the direct-load
+// float64 MFMA GEMM from the zero-padded XP [n][NP] (float32 D is widened
+// into D64 first; float64 D is read in place).
+template <typename T>
+sox_status launch_back(const sox_plan& p, const double* XP, const T* D, double* D64, double* E,
+                       double* Sigma, int t0, int cnt, hipStream_t s) {
+  const int n = p.n, NP = p.NP;
+  const double* Dd = (const double*)D;
+  if (sizeof(T) == 4) {
+    const long cd = (long)cnt * NP * NP;
+    hipLaunchKernelGGL(widen_kernel, grid1d(cd), dim3(256), 0, s, (const float*)D, D64, cd);
+    SOX_HIP(hipGetLastError());
+    Dd = D64;
+  }
+  DenseArgs<double, double> e{};
+  e.A = XP; e.B = Dd; e.C = E;
+  e.lda = NP; e.ldb = NP; e.ldc = NP;
+  e.sA = 0; e.sB = (long)NP * NP; e.sC = (long)n * NP;
+  e.M = n; e.N = NP; e.K = NP; e.alpha = 1.0;
+  SOX_HIP((launch_dense<double, double, 1, 4, 2, 2>(e, cnt, s)));
+  DenseArgs<double, double> g{};
+  g.A = E; g.B = XP; g.C = Sigma + (long)t0 * n * n;
+  g.lda = NP; g.ldb = NP; g.ldc = n;
+  g.sA = (long)n * NP; g.sB = 0; g.sC = (long)n * n;
+  g.M = n; g.N = n; g.K = NP; g.alpha = -1.0;
+  SOX_HIP((launch_dense<double, double, 1, 4, 2, 2>(g, cnt, s)));
+  return SOX_OK;
+}
+
+// XP = X zero padded to [n][NP] float64
+sox_status launch_xpad64(const sox_plan& p, const double* X, double* XP, hipStream_t s) {
+  const long cx = (long)p.n * p.NP;
+  hipLaunchKernelGGL(xpad64_kernel, grid1d(cx), dim3(256), 0, s, X, XP, p.n, p.N, p.NP);
+  SOX_HIP(hipGetLastError());
+  return SOX_OK;
+}
+
 template <typename T>
 sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1, const double* U2,
                       const double* G, double* Sigma, void* ws, hipStream_t s) {
@@ -622,6 +664,7 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
     float* ukr = (float*)(base + L.ukr);
     st = launch_utensor<T>(p, U1, X, u1t, s, ukr);
     if (st) return st;
+    if ((st = launch_xpad64(p, X, (double*)(base + L.xp), s))) return st;
     if (entry != SOX_ENTRY_BARE) {
       st = launch_utensor<T>(p, U2, X, u2t, s, ukr);
       if (st) return st;
@@ -730,10 +773,9 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
     }
     {
       ProfScope ps(p, SOX_STAGE_BACK, s);
-      BackEProb<T> pe{X, D, E, n, N, NP, n, N, N};
-      SOX_HIP((launch_gemm<BackEProb<T>, double, 2, 2, 2, 2>(pe, cnt, s)));
-      BackSigmaProb pb{X, E, Sigma, n, N, NP, t0, -1.0, n, n, N};
-      SOX_HIP((launch_gemm<BackSigmaProb, double, 2, 2, 2, 2>(pb, cnt, s)));
+      if ((st = launch_back<T>(p, (const double*)(base + L.xp), D, (double*)(base + L.d64), E,
+                               Sigma, t0, cnt, s)))
+        return st;
     }
   }
   return SOX_OK;
@@ -805,6 +847,7 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
     ProfScope ps(p, SOX_STAGE_UTENSOR, s);
     st = launch_utensor<T>(p, V, X, U2, s, (float*)(base + L.ukr));
     if (st) return st;
+    if ((st = launch_xpad64(p, X, (double*)(base + L.xp), s))) return st;
 
   }
   {
@@ -877,10 +920,9 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
   for (int t0 = 0; Sigma && t0 < nt; t0 += p.eslab) {
     const int cnt = std::min(p.eslab, nt - t0);
     ProfScope ps(p, SOX_STAGE_BACK, s);
-    BackEProb<T> pe{X, D + (long)t0 * NP * NP, E, n, N, NP, n, N, N};
-    SOX_HIP((launch_gemm<BackEProb<T>, double, 2, 2, 2, 2>(pe, cnt, s)));
-    BackSigmaProb pb{X, E, Sigma, n, N, NP, t0, -1.0, n, n, N};
-    SOX_HIP((launch_gemm<BackSigmaProb, double, 2, 2, 2, 2>(pb, cnt, s)));
+    if ((st = launch_back<T>(p, (const double*)(base + L.xp), D + (long)t0 * NP * NP,
+                             (double*)(base + L.d64), E, Sigma, t0, cnt, s)))
+      return st;
   }
   return SOX_OK;
 }

@@ -156,6 +156,18 @@ __global__ void pad_cast_kernel(const double* src, float* dst, int rows, int col
   }
 }
 
+// X zero padded to [n][NP] float64 (the back-transform operand)
+__global__ void xpad64_kernel(const double* X, double* XP, int n, int Nthc, int NP) {
+  SOX_FOR_FLAT(idx, (long)n * NP) {
+    const int u = (int)(idx / NP), R = (int)(idx - (long)u * NP);
+    XP[idx] = R < Nthc ? X[(long)u * Nthc + R] : 0.0;
+  }
+}
+
+__global__ void widen_kernel(const float* src, double* dst, long count) {
+  SOX_FOR_FLAT(idx, count) dst[idx] = (double)src[idx];
+}
+
 template <typename T>
 __global__ void cast_kernel(const double* src, T* dst, long count) {
   SOX_FOR_FLAT(idx, count) dst[idx] = T(src[idx]);
@@ -308,48 +320,6 @@ template <typename T> struct IFTProb {
     const int pv = col / nP;
     const int vl = pv % vc, P = pv / vc;
     Adyn[(((long)t * vc + vl) * NP + P) * nP + u] = T(v);
-  }
-};
-
-// ---------------------------------------------------------------------------
-// Back-transform (float64):  E[t][tt][P] = sum_R X[tt][R] D[t][P][R]
-//                            Sigma[tau][tt][r] = -sum_P E[t][tt][P] X[r][P]
-template <typename Td> struct BackEProb {
-  const double* X;  // [n][N]
-  const Td* D;      // [slab][NP][NP]
-  double* E;        // [slab][n][NP]
-  int n, Nthc, NP;
-  int M, N, K;      // M = n, N = Nthc, K = Nthc
-  __device__ f64x4 loadA4(int, int tt, int R) const {
-    if (tt >= n) return zero4<double>();
-    return load4_strided<double>(X + (long)tt * Nthc, 1, R, Nthc);
-  }
-  __device__ f64x4 loadB4(int b, int P, int R) const {
-    if (P >= Nthc) return zero4<double>();
-    return load4_strided<double>(D + (long)b * NP * NP + (long)P * NP, 1, R, Nthc);
-  }
-  __device__ void store(int b, int tt, int P, double v) const {
-    E[(long)b * n * NP + (long)tt * NP + P] = v;
-  }
-};
-
-struct BackSigmaProb {
-  const double* X;
-  const double* E;  // [slab][n][NP]
-  double* Sigma;    // [n_tau][n][n]
-  int n, Nthc, NP, t0;
-  double scale;     // -1 for Sigma_RP = -D_PR
-  int M, N, K;      // M = n, N = n, K = Nthc
-  __device__ f64x4 loadA4(int b, int tt, int P) const {
-    if (tt >= n) return zero4<double>();
-    return load4_strided<double>(E + (long)b * n * NP + (long)tt * NP, 1, P, Nthc);
-  }
-  __device__ f64x4 loadB4(int, int r, int P) const {
-    if (r >= n) return zero4<double>();
-    return load4_strided<double>(X + (long)r * Nthc, 1, P, Nthc);
-  }
-  __device__ void store(int b, int tt, int r, double v) const {
-    Sigma[(long)(t0 + b) * n * n + (long)tt * n + r] = scale * v;
   }
 };
 
