@@ -302,9 +302,20 @@ def main() -> int:
     stage_ms = {k: round(v[0] / args.steps, 4) for k, v in prof.items()
                 if k != "dropped" and v[1] > 0}
 
-    # FP64 oracle on the host: the error reference (bare molecules) and the CPU baseline
-    from oracle import sox_mol as om
+    # every GPU run first (host-side numpy work between them would perturb
+    # the launch timing), then the FP64 oracle on the host: the error
+    # reference (bare molecules) and the CPU baseline
     out = {}
+    r64 = rb = None
+    if not args.no_fp64_compare and args.precision != "fp64":
+        k64 = max(1, args.steps // 2)
+        r64 = run("fp64", k64, 1, profile=False)
+    if (args.precision == "fp32" and kind in ("bare", "static") and not solid
+            and not args.no_bf16x3_compare):
+        # the split-precision path on the same workload, same step
+        rb = run("bf16x3", args.steps, args.warmup, profile=True)
+
+    from oracle import sox_mol as om
     ref = None
     if kind == "bare" and not solid and args.workload <= 2:
         Gr = om.g_tau(wl["eps"], wl["Q"], wl["mu"], wl["beta"], wl["tau"])
@@ -323,9 +334,7 @@ def main() -> int:
         return float(np.abs(S - ref).max() / np.abs(ref).max())
 
     main_err = err_of(main_run["Sigma"])
-    if not args.no_fp64_compare and args.precision != "fp64":
-        k64 = max(1, args.steps // 2)
-        r64 = run("fp64", k64, 1, profile=False)
+    if r64 is not None:
         s64 = r64["seconds"] / k64
         d = np.abs(main_run["Sigma"] - r64["Sigma"]).max() / np.abs(r64["Sigma"]).max()
         out["fp64_path"] = {"sweeps_per_s": 1.0 / s64, "ms_per_step": 1e3 * s64,
@@ -334,11 +343,7 @@ def main() -> int:
         tol = 1e-6 if args.precision == "fp32" else 1e-4
         acc = main_err if main_err is not None else float(d)
         out["mixed_beats_fp64"] = bool(value > 1.0 / s64 and acc <= tol)
-
-    if (args.precision == "fp32" and kind in ("bare", "static") and not solid
-            and not args.no_bf16x3_compare):
-        # the split-precision path on the same workload, same step
-        rb = run("bf16x3", args.steps, args.warmup, profile=True)
+    if rb is not None:
         sb = rb["seconds"] / args.steps
         fb_ms, fb_n = rb["prof"]["fused"]
         fb_ach = fl["fused"] * args.steps / max(fb_n, 1) / (fb_ms / max(fb_n, 1) * 1e-3) / 1e12
