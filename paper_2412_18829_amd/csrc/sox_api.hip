@@ -303,6 +303,14 @@ int default_fused_cfg(int precision, int N) {
   return N >= 256 ? 9 : 0;
 }
 
+// the LDS-staged fused kernel's 32-bit byte offsets within one (tau, v)
+// panel set: NP rows of nP values, and NP rows of the U-tensor (stride nP^2)
+bool lds_offsets_fit(const sox_plan& p) {
+  const double es = p.precision == SOX_BF16X3 ? 2.0 : 4.0;
+  const double lim = 4294967296.0;
+  return (double)p.NP * p.nP * es < lim && (double)p.NP * p.nP * p.nP * es < lim;
+}
+
 void set_fused_cfg(sox_plan& p, int cfg) {
   p.fused_cfg = cfg;
   const FusedCfg& fc = kFusedCfgs[cfg];
@@ -1615,6 +1623,11 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
     if (v >= 0 && v < kNumFusedCfgs && cfg_allowed(precision, v)) p->fused_cfg = v;
   }
   set_fused_cfg(*p, p->fused_cfg);
+  if ((p->fused_cfg == 8 || p->fused_cfg == 9) && !lds_offsets_fit(*p)) {
+    // the LDS-staged kernel addresses a (tau, v) panel set with 32-bit lane
+    // offsets; past that size the direct-load kernel of the same precision
+    set_fused_cfg(*p, p->fused_cfg == 8 ? 7 : 3);
+  }
   if (const char* at = getenv("SOX_AUTOTUNE")) {
     if (atoi(at) == 1 && !getenv("SOX_FUSED_CFG") && precision != SOX_BF16X3 && p->nk == 1) {
       sox_status st = autotune_fused(*p);
