@@ -251,14 +251,15 @@ def test_fp32_lds_kernel_vs_oracle(B, shape, monkeypatch):
     assert err <= TOL["fp32"]
 
 
-@pytest.mark.parametrize("precision,expect", [("fp32", 3), ("bf16x3", 7)])
-def test_lds_kernel_offset_limit_falls_back(B, precision, expect):
-    """Past the LDS-staged kernel's 32-bit panel offsets (NP nP^2 bytes >=
-    2^32) the plan picks the direct-load kernel of the same precision."""
+@pytest.mark.parametrize("precision,n,expect", [("fp32", 512, 3), ("bf16x3", 736, 7)])
+def test_lds_kernel_offset_limit_falls_back(B, precision, n, expect):
+    """Past the LDS-staged kernel's 32-bit panel offsets (NP nP^2 element
+    bytes >= 2^32) the plan picks the direct-load kernel of the same
+    precision."""
     tau, w = synth.chebyshev_tau_grid(4, 10.0)
-    plan = B.Plan(512, 4100, tau, w, 10.0, precision=precision)
+    plan = B.Plan(n, 4100, tau, w, 10.0, precision=precision)
     info = B.sox_plan_describe(plan)
-    log(f"n=512 N=4100 {precision}: fused config {info['fused_cfg']} (nP {info['nP']}, NP {info['NP']})")
+    log(f"n={n} N=4100 {precision}: fused config {info['fused_cfg']} (nP {info['nP']}, NP {info['NP']})")
     assert info["fused_cfg"] == expect
     small = B.Plan(64, 384, tau, w, 10.0, precision=precision)
     assert B.sox_plan_describe(small)["fused_cfg"] in (8, 9)
