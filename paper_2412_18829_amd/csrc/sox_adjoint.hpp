@@ -82,25 +82,8 @@ __global__ __launch_bounds__(256) void hc_kernel(const HcArgs<T, TC> p) {
       const T* Wp = p.W + tau * p.w_ts;
       const T* Fp = p.FT + tau * p.f_ts + v * p.f_vs;
       for (int z0 = 0; z0 < p.nz; z0 += 32) {
-        V4 M[2][XB];
-#pragma unroll
-        for (int i = 0; i < 2; ++i)
-#pragma unroll
-          for (int j = 0; j < XB; ++j) M[i][j] = zero4<T>();
-        for (int k0 = 0; k0 < p.nk; k0 += 16) {
-          V4 l[2], r[XB];
-#pragma unroll
-          for (int i = 0; i < 2; ++i) l[i] = *(const V4*)(Lp + (long)(z0 + 16 * i + li) * p.l_ld + k0);
-#pragma unroll
-          for (int j = 0; j < XB; ++j) r[j] = *(const V4*)(Rp + (long)(x0 + 16 * j + li) * p.r_ld + k0);
-#pragma unroll
-          for (int m = 0; m < 4; ++m)
-#pragma unroll
-            for (int i = 0; i < 2; ++i)
-#pragma unroll
-              for (int j = 0; j < XB; ++j) M[i][j] = mfma16x16x4(l[i][m], r[j][m], M[i][j]);
-        }
-        // Hadamard with the cotangent tile
+        // cotangent weights of this z chunk, loaded ahead of stage 1
+        T wt[2][XB][4];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -108,21 +91,87 @@ __global__ __launch_bounds__(256) void hc_kernel(const HcArgs<T, TC> p) {
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
               const int z = z0 + 16 * i + acc_row<T>(g, rr);
-              M[i][j][rr] *= Wp[(long)z * p.w_ld + x0 + 16 * j + li];
+              wt[i][j][rr] = Wp[(long)z * p.w_ld + x0 + 16 * j + li];
             }
-        // contract over z: Out[x][y] += sum_z H[z][x] F[z][y]
+        V4 M[2][XB];
 #pragma unroll
-        for (int yb = 0; yb < YB; ++yb) {
-          if (yb < nyb) {
-            const T* frow = Fp + (long)(16 * yb + li) * p.f_ld;
+        for (int i = 0; i < 2; ++i)
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
-              const V4 f = load_perm4<T>(frow, z0 + 16 * i, g);
+          for (int j = 0; j < XB; ++j) M[i][j] = zero4<T>();
+        // stage 1, software-pipelined: the next k chunk's operands are
+        // loaded before the current chunk's MFMAs
+        V4 l[2], r[XB];
+#pragma unroll
+        for (int i = 0; i < 2; ++i) l[i] = *(const V4*)(Lp + (long)(z0 + 16 * i + li) * p.l_ld);
+#pragma unroll
+        for (int j = 0; j < XB; ++j) r[j] = *(const V4*)(Rp + (long)(x0 + 16 * j + li) * p.r_ld);
+        for (int k0 = 0; k0 < p.nk; k0 += 16) {
+          const int kn = k0 + 16 < p.nk ? k0 + 16 : k0;
+          V4 ln[2], rn[XB];
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+            ln[i] = *(const V4*)(Lp + (long)(z0 + 16 * i + li) * p.l_ld + kn);
+#pragma unroll
+          for (int j = 0; j < XB; ++j)
+            rn[j] = *(const V4*)(Rp + (long)(x0 + 16 * j + li) * p.r_ld + kn);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+#pragma unroll
+              for (int j = 0; j < XB; ++j) M[i][j] = mfma16x16x4(l[i][m], r[j][m], M[i][j]);
+          __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int i = 0; i < 2; ++i) l[i] = ln[i];
+#pragma unroll
+          for (int j = 0; j < XB; ++j) r[j] = rn[j];
+        }
+        // Hadamard with the cotangent tile
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < XB; ++j)
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) M[i][j][rr] *= wt[i][j][rr];
+        // contract over z: Out[x][y] += sum_z H[z][x] F[z][y], in groups of
+        // four y blocks so that eight independent accumulators sit between
+        // two MFMAs into the same one; the F rows of the next group are
+        // loaded before the current group's MFMAs
+        constexpr int YG = 4;
+        V4 f[YG][2], fn[YG][2];
+#pragma unroll
+        for (int q = 0; q < YG; ++q) {
+          const int yq = q < nyb ? q : nyb - 1;
+          const T* frow = Fp + (long)(16 * yq + li) * p.f_ld;
+#pragma unroll
+          for (int i = 0; i < 2; ++i) f[q][i] = load_perm4<T>(frow, z0 + 16 * i, g);
+        }
+#pragma unroll
+        for (int y0 = 0; y0 < YB; y0 += YG) {
+          if (y0 < nyb) {
+#pragma unroll
+            for (int q = 0; q < YG; ++q) {
+              int yq = y0 + YG + q;
+              yq = yq < nyb ? yq : nyb - 1;
+              const T* frow = Fp + (long)(16 * yq + li) * p.f_ld;
+#pragma unroll
+              for (int i = 0; i < 2; ++i) fn[q][i] = load_perm4<T>(frow, z0 + 16 * i, g);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
               for (int m = 0; m < 4; ++m)
 #pragma unroll
-                for (int j = 0; j < XB; ++j) acc[j][yb] = mfma16x16x4(M[i][j][m], f[m], acc[j][yb]);
-            }
+                for (int q = 0; q < YG; ++q)
+#pragma unroll
+                  for (int j = 0; j < XB; ++j)
+                    if (y0 + q < YB && y0 + q < nyb)
+                      acc[j][y0 + q] = mfma16x16x4(M[i][j][m], f[q][i][m], acc[j][y0 + q]);
+#pragma unroll
+            for (int q = 0; q < YG; ++q)
+#pragma unroll
+              for (int i = 0; i < 2; ++i) f[q][i] = fn[q][i];
           }
         }
       }

@@ -140,3 +140,53 @@ def test_dynamic_vjp_v_slabs_match(B, monkeypatch):
         outs.append((host(dG), host(dX), host(dW), host(dV)))
     for a, b in zip(outs[0], outs[1]):
         assert rel_err(b, a) <= 1e-12
+
+
+def test_dynamic_vjp_full_size_directional_fd(B):
+    """n=300, N=1800, 120 tau nodes, 8-pole W(tau): the float32 adjoint of
+    L = sum(Sigma * R) along one random direction in (G, X, W, V) against a
+    central finite difference of the float64 forward path at the same size
+    (L is a polynomial of degree 4 in the inputs, so the step 1e-4 leaves a
+    truncation error near 1e-8).  The bound 5e-5 is the float32 one (1e-5)
+    widened for a derivative summed over 4e8 gradient entries (measured
+    7.5e-6)."""
+    import time
+    import torch
+    wl = synth.workload(4)
+    n, N, nt = wl["n"], wl["N"], wl["n_tau"]
+    tp = synth.bosonic_transform_pair(wl["tau"], wl["beta"], omega_max=14.0, tol=1e-10)
+    rng = np.random.default_rng(44)
+    G = om.g_tau(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    R = rng.standard_normal((nt, n, n))
+    kw = dict(t_fwd=tp["T_fwd"], t_bwd=tp["T_bwd"])
+    p32 = B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision="fp32", **kw)
+    X, W, V, Gd, Rd = dev(wl["X"]), dev(wl["W_tau"]), dev(wl["V"]), dev(G), dev(R)
+    dG, dX, dW, dV = (torch.zeros_like(a) for a in (Gd, X, W, V))
+    log(f"dynamic vjp full size n={n} N={N} n_tau={nt} n_omega={len(tp['m'])}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.sox_sigma_vjp(p32, "dynamic", X, W, V, Gd, Rd, dG, dX, dW, dV)
+    torch.cuda.synchronize()
+    log(f"  fp32 vjp {time.perf_counter() - t0:.2f} s")
+    del p32
+    # one random direction, scaled to each input's size
+    dirs = []
+    for a in (Gd, X, W, V):
+        d = torch.empty_like(a).normal_(generator=torch.Generator(device="cuda").manual_seed(7))
+        dirs.append(d * (a.abs().max() / d.abs().max()))
+    ana = sum(float((g * d).sum()) for g, d in zip((dG, dX, dW, dV), dirs))
+    del dG, dX, dW, dV
+    p64 = B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision="fp64", **kw)
+    S = torch.empty_like(Gd)
+    eps = 1e-4
+
+    def loss(sign):
+        a = [x + sign * eps * d for x, d in zip((Gd, X, W, V), dirs)]
+        B.sox_sigma_dynamic(p64, a[1], a[2], a[3], a[0], S)
+        torch.cuda.synchronize()
+        return float((S * Rd).sum())
+
+    fd = (loss(1.0) - loss(-1.0)) / (2 * eps)
+    err = abs(ana - fd) / abs(fd)
+    log(f"  directional derivative: vjp {ana:.10e} fd {fd:.10e} rel diff {err:.2e}")
+    assert err <= 5e-5
