@@ -1301,23 +1301,35 @@ sox_status run_vjp_dynamic(sox_plan& p, const double* X, const double* Wtau, con
     IFTAdjProb<T> ia{p.d_tb2, dAdyn, dAW, dAWT, n, nP, NP, nw, nt, vc, ldk, 2 * nw,
                      NP * vc * n, nt};
     SOX_HIP((launch_gemm<IFTAdjProb<T>, double, 2, 2, 2, 2>(ia, 1, s)));
-    {
+    if (sizeof(T) == 4) {
+      // float32 on the LDS-staged GEMM, results stored or accumulated in float64
+      DenseLdsArgs d{};
+      d.A = (const float*)dAW; d.B = (const float*)GG2T; d.C64 = dW2;
+      d.lda = ldk; d.ldb = ldk; d.ldc = 2L * NP;
+      d.sA = 2L * NP * ldk; d.sB = 2L * NP * ldk; d.sC = 4L * NP * NP;
+      d.M = 2 * NP; d.N = 2 * NP; d.K = ldk; d.accumulate = 1;
+      d.rgroup = d.M; d.rvalid = d.M;
+      SOX_HIP(launch_dense_lds_f32(d, nw, s));
+      DenseLdsArgs e{};
+      e.A = (const float*)dAWT; e.B = (const float*)W2T; e.C64 = dGG2;
+      e.lda = 2L * NP; e.ldb = 2L * NP; e.ldc = 2L * NP;
+      e.sA = vcn * 2 * NP; e.sB = 4L * NP * NP; e.sC = vcn * 2 * NP;
+      e.M = (int)vcn; e.N = 2 * NP; e.K = 2 * NP;
+      e.rgroup = e.M; e.rvalid = e.M;
+      SOX_HIP(launch_dense_lds_f32(e, nw, s));
+    } else {
       DenseArgs<T, double> d{};
       d.A = dAW; d.B = GG2T; d.C = dW2;
       d.lda = ldk; d.ldb = ldk; d.ldc = 2L * NP;
       d.sA = 2L * NP * ldk; d.sB = 2L * NP * ldk; d.sC = 4L * NP * NP;
       d.M = 2 * NP; d.N = 2 * NP; d.K = ldk; d.alpha = T(1); d.accumulate = 1;
-      if (sizeof(T) == 8) SOX_HIP((launch_dense<T, double, 2, 2, 2, 2>(d, nw, s)));
-      else SOX_HIP((launch_dense<T, double, 2, 2, 4, 4>(d, nw, s)));
-    }
-    {
-      DenseArgs<T, double> d{};
-      d.A = dAWT; d.B = W2T; d.C = dGG2;
-      d.lda = 2L * NP; d.ldb = 2L * NP; d.ldc = 2L * NP;
-      d.sA = vcn * 2 * NP; d.sB = 4L * NP * NP; d.sC = vcn * 2 * NP;
-      d.M = (int)vcn; d.N = 2 * NP; d.K = 2 * NP; d.alpha = T(1); d.accumulate = 0;
-      if (sizeof(T) == 8) SOX_HIP((launch_dense<T, double, 2, 2, 2, 2>(d, nw, s)));
-      else SOX_HIP((launch_dense<T, double, 2, 2, 4, 4>(d, nw, s)));
+      SOX_HIP((launch_dense<T, double, 2, 2, 2, 2>(d, nw, s)));
+      DenseArgs<T, double> e{};
+      e.A = dAWT; e.B = W2T; e.C = dGG2;
+      e.lda = 2L * NP; e.ldb = 2L * NP; e.ldc = 2L * NP;
+      e.sA = vcn * 2 * NP; e.sB = 4L * NP * NP; e.sC = vcn * 2 * NP;
+      e.M = (int)vcn; e.N = 2 * NP; e.K = 2 * NP; e.alpha = T(1); e.accumulate = 0;
+      SOX_HIP((launch_dense<T, double, 2, 2, 2, 2>(e, nw, s)));
     }
     FTAdjProb fa{p.d_tf2, dGG2, dGG, n, NP, nw, nt, vc, nt, vc * n * NP, 2 * nw};
     SOX_HIP((launch_gemm<FTAdjProb, double, 2, 2, 2, 2>(fa, 1, s)));

@@ -17,7 +17,8 @@
 // row r is row r % rgroup of group r / rgroup, stored only when
 // r % rgroup < rvalid, at C + group c_gstride + (r % rgroup) ldc + col.
 // With Chi set the result x is stored as bf16 hi = bf16(x) and
-// lo = bf16(x - hi) at the same offsets of Chi and Clo instead of C.
+// lo = bf16(x - hi) at the same offsets of Chi and Clo instead of C; with
+// C64 set it is stored (or, with accumulate, added) in float64.
 #pragma once
 
 #include <type_traits>
@@ -39,6 +40,8 @@ struct DenseLdsArgs {
   bf16_t* Clo;
   long sA, sB, sC;      // batch strides (elements; blockIdx.y is the batch)
   int tiles_m, tiles_n;
+  double* C64 = nullptr;  // float64 output instead of C (same offsets)
+  int accumulate = 0;     // float64 output only: C64 += result
 };
 
 __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p) {
@@ -157,6 +160,8 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
           const bf16_t hgh = f32_to_bf16(x);
           p.Chi[base + col] = hgh;
           p.Clo[base + col] = f32_to_bf16(x - bf16_to_f32(hgh));
+        } else if (p.C64) {
+          p.C64[base + col] = p.accumulate ? p.C64[base + col] + (double)x : (double)x;
         } else {
           p.C[base + col] = x;
         }
@@ -167,7 +172,8 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
 inline hipError_t launch_dense_lds_f32(DenseLdsArgs a, int batch, hipStream_t s) {
   if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;
   if (batch > 65535) return hipErrorInvalidValue;
-  if (a.K % 16 != 0 || a.K <= 0 || a.rgroup <= 0 || (a.Chi && !a.Clo) || (!a.Chi && !a.C))
+  if (a.K % 16 != 0 || a.K <= 0 || a.rgroup <= 0 || (a.Chi && !a.Clo) ||
+      (!a.Chi && !a.C && !a.C64) || (a.accumulate && !a.C64))
     return hipErrorInvalidValue;
   a.tiles_m = (a.M + kLdsTile - 1) / kLdsTile;
   a.tiles_n = (a.N + kLdsTile - 1) / kLdsTile;
