@@ -183,6 +183,9 @@ def main() -> int:
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-bf16x3-compare", action="store_true",
                     help="skip the split-precision run reported beside a float32 run")
+    ap.add_argument("--no-vjp", action="store_true",
+                    help="skip the adjoint (vector-Jacobian product) call timed after a "
+                         "dynamic molecular run")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time of the oracle sample")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -315,6 +318,31 @@ def main() -> int:
         # the split-precision path on the same workload, same step
         rb = run("bf16x3", args.steps, args.warmup, profile=True)
 
+    vjp = None
+    if kind == "dynamic" and not args.no_vjp and args.precision != "bf16x3":
+        # one adjoint call of L = sum(Sigma * R) for a seeded R, on the same
+        # inputs: dG, dX, dW(tau), dV (the forward chain is recomputed inside)
+        plan = B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision=args.precision,
+                      t_fwd=tp["T_fwd"], t_bwd=tp["T_bwd"])
+        G = torch.empty(gshape, dtype=cdt, device=dev)
+        B.sox_build_g_tau(plan, Q, eps, wl["mu"], G)
+        Rr = torch.as_tensor(np.random.default_rng(2024).standard_normal(gshape), device=dev)
+        grads = [torch.zeros_like(a) for a in (G, X, U1, V)]
+        torch.cuda.synchronize()
+        B.sox_profile_enable(plan, True)
+        B.sox_profile_read(plan, reset=True)
+        t0 = time.perf_counter()
+        B.sox_sigma_vjp(plan, "dynamic", X, U1, V, G, Rr, *grads)
+        torch.cuda.synchronize()
+        tv = time.perf_counter() - t0
+        pv = B.sox_profile_read(plan, reset=True)
+        vjp = {"entry": "sox_sigma_vjp (dynamic)", "seconds_per_call": tv,
+               "forward_steps_equivalent": tv / (ms_per_step * 1e-3),
+               "stage_ms": {k: round(v[0], 2) for k, v in pv.items()
+                            if k != "dropped" and v[1] > 0},
+               "note": "one call after the timed forward steps, no warmup"}
+        del plan, G, Rr, grads
+
     from oracle import sox_mol as om
     ref = None
     if kind == "bare" and not solid and args.workload <= 2:
@@ -389,6 +417,8 @@ def main() -> int:
         "stage_ms_per_step": stage_ms,
         "plan": main_run["plan"],
     }
+    if vjp is not None:
+        out["vjp"] = vjp
     rec.update(out)
     print(json.dumps(rec), flush=True)
     return 0
