@@ -198,11 +198,6 @@ def main() -> int:
               file=sys.stderr)
         return 2
     desc, kind = WORKLOADS[args.workload]
-    if args.precision == "bf16x3" and kind not in ("bare", "static", "solid"):
-        print("bench.py: bf16x3 runs the bare and static molecular entries and k-point meshes "
-              "only", file=sys.stderr)
-        return 2
-
     import numpy as np
     import torch
 
@@ -313,7 +308,7 @@ def main() -> int:
     if not args.no_fp64_compare and args.precision != "fp64":
         k64 = max(1, args.steps // 2)
         r64 = run("fp64", k64, 1, profile=False)
-    if (args.precision == "fp32" and kind in ("bare", "static") and not solid
+    if (args.precision == "fp32" and kind in ("bare", "static", "dynamic") and not solid
             and not args.no_bf16x3_compare):
         # the split-precision path on the same workload, same step
         rb = run("bf16x3", args.steps, args.warmup, profile=True)

@@ -88,9 +88,11 @@ typedef enum {
  *               hi*hi + hi*lo + lo*hi run on bf16 MFMA with float32
  *               accumulation.  Molecules: the bare and static entries (the
  *               A step and the fused B, C -> D contraction in split
- *               precision, the other steps in float32); the molecular
- *               dynamic entry and the adjoint return SOX_ERR_UNSUPPORTED
- *               for a bf16x3 plan.                                          */
+ *               precision, the other steps in float32) and the dynamic
+ *               entry (the fused contraction in split precision, A(tau)
+ *               written by the inverse transform as hi + lo planes, the
+ *               other steps in float32); the adjoint returns
+ *               SOX_ERR_UNSUPPORTED for a bf16x3 plan.                      */
 typedef enum { SOX_FP64 = 0, SOX_FP32 = 1, SOX_BF16X3 = 2 } sox_precision;
 
 /* Entry kinds, for sox_workspace_size and sox_sigma_vjp. */

@@ -183,6 +183,7 @@ struct Layout {
 
 struct DynLayout {
   size_t p1d, p2td, p1q, p2q, p2t, xt, u2, w2, gg2, aw, adyn, d, e, ukr, xp, d64, total;
+  size_t xth, xtl, p2h, p2l, u2h, u2l;  // bf16 x 3 split operands of the fused contraction
 };
 
 size_t elem_size(int precision) { return precision == SOX_FP64 ? 8 : 4; }
@@ -253,6 +254,11 @@ DynLayout dyn_layout_for(const sox_plan& p, int vc, int eslab) {
   L.ukr = c.take(utensor_scratch_bytes(p));
   L.xp = c.take((size_t)n * NP * 8);
   L.d64 = c.take(p.precision == SOX_FP64 ? 0 : (size_t)eslab * NP * NP * 8);
+  if (p.precision == SOX_BF16X3) {
+    L.xth = c.take(NP * nP * 2); L.xtl = c.take(NP * nP * 2);
+    L.p2h = c.take(nt * NP * nP * 2); L.p2l = c.take(nt * NP * nP * 2);
+    L.u2h = c.take(NP * nP * nP * 2); L.u2l = c.take(NP * nP * nP * 2);
+  }
   L.total = c.off;
   return L;
 }
@@ -856,7 +862,6 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
     st = launch_utensor<T>(p, V, X, U2, s, (float*)(base + L.ukr));
     if (st) return st;
     if ((st = launch_xpad64(p, X, (double*)(base + L.xp), s))) return st;
-
   }
   {
     ProfScope ps(p, SOX_STAGE_PROJECT, s);
@@ -875,6 +880,22 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
     // Q-contiguous copies for the forward transform's loads
     if ((st = launch_transpose<double>(P1d, P1q, NP, nP, nt, s))) return st;
     if ((st = launch_transpose<double>(P2Td, P2q, NP, nP, nt, s))) return st;
+  }
+  const bool split = p.precision == SOX_BF16X3;
+  if (split) {
+    // the v-independent operands of the fused contraction as bf16 hi/lo planes
+    ProfScope ps(p, SOX_STAGE_SPLIT, s);
+    if (p.fused_cfg != 8)
+      return fail(SOX_ERR_UNSUPPORTED, "the dynamic entry in bf16x3 runs the LDS-staged kernel only");
+    if ((st = launch_split((const float*)XT, (bf16_t*)(base + L.xth), (bf16_t*)(base + L.xtl),
+                           (long)NP * nP, s)))
+      return st;
+    if ((st = launch_split((const float*)P2T, (bf16_t*)(base + L.p2h), (bf16_t*)(base + L.p2l),
+                           (long)nt * NP * nP, s)))
+      return st;
+    if ((st = launch_split((const float*)U2, (bf16_t*)(base + L.u2h), (bf16_t*)(base + L.u2l),
+                           (long)NP * nP * nP, s)))
+      return st;
   }
   {
     ProfScope ps(p, SOX_STAGE_GG_FT, s);
@@ -899,6 +920,10 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
     {
       ProfScope ps(p, SOX_STAGE_IFT, s);
       IFTProb<T> ift{p.d_tb2, AW, Adyn, n, nP, NP, nw, nt, vc, nt, NP * vc * nP, 2 * nw};
+      if (split) {  // A(tau) as hi and lo planes in the A(tau) buffer
+        ift.Ahi = (bf16_t*)Adyn;
+        ift.Alo = ift.Ahi + (long)nt * vc * NP * nP;
+      }
       SOX_HIP((launch_gemm<IFTProb<T>, double, 2, 2, 2, 2>(ift, 1, s)));
     }
     FusedArgs<T> fa;
@@ -921,7 +946,22 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
     fa.tiles_p = tiles_p;
     fa.tiles_r = tiles_r;
     fa.n_tau = nt;
-    {
+    if (split) {
+      ProfScope ps(p, SOX_STAGE_FUSED, s);
+      FusedArgs<float> fl;
+      fl.a_tstride = fa.a_tstride; fl.a_vstride = fa.a_vstride; fl.y_tstride = 0;
+      fl.p_tstride = fa.p_tstride; fl.u_rstride = fa.u_rstride; fl.u_vstride = fa.u_vstride;
+      fl.d_tstride = fa.d_tstride; fl.D = (float*)D; fl.accumulate = fa.accumulate;
+      fl.n = vc; fl.nP = nP; fl.NP = NP; fl.tiles_p = tiles_p; fl.tiles_r = tiles_r;
+      fl.n_tau = nt;
+      const bf16_t* ah = (const bf16_t*)Adyn;
+      const bf16_t* a[2] = {ah, ah + (long)nt * vc * NP * nP};
+      const bf16_t* y[2] = {(const bf16_t*)(base + L.xth), (const bf16_t*)(base + L.xtl)};
+      const bf16_t* pt[2] = {(const bf16_t*)(base + L.p2h), (const bf16_t*)(base + L.p2l)};
+      const bf16_t* u[2] = {(const bf16_t*)(base + L.u2h) + (long)v0 * nP,
+                            (const bf16_t*)(base + L.u2l) + (long)v0 * nP};
+      SOX_HIP(launch_fused_lds<kLdsBf16x3>(lds_args(fl, a, y, pt, u), s));
+    } else {
       ProfScope ps(p, SOX_STAGE_FUSED, s);
       st = launch_fused_cfg<T>(p, fa, s);
       if (st) return st;
@@ -1548,8 +1588,7 @@ sox_status dispatch_static(sox_plan* plan, int entry, const double* X, const dou
       case SOX_FP32:
       case SOX_BF16X3: return run_static<float>(*plan, entry, X, U1, U2, G, Sigma, ws, s);
       default:
-        return fail(SOX_ERR_UNSUPPORTED, "precision %d: the dynamic entry runs in fp32 or fp64",
-                    plan->precision);
+        return fail(SOX_ERR_UNSUPPORTED, "unknown precision %d", plan->precision);
     }
   });
 }
@@ -1805,10 +1844,10 @@ sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_ta
     }
     switch (plan->precision) {
       case SOX_FP64: return run_dynamic<double>(*plan, X, W_tau, V, G, Sigma, ws, s);
-      case SOX_FP32: return run_dynamic<float>(*plan, X, W_tau, V, G, Sigma, ws, s);
+      case SOX_FP32:
+      case SOX_BF16X3: return run_dynamic<float>(*plan, X, W_tau, V, G, Sigma, ws, s);
       default:
-        return fail(SOX_ERR_UNSUPPORTED, "precision %d: the dynamic entry runs in fp32 or fp64",
-                    plan->precision);
+        return fail(SOX_ERR_UNSUPPORTED, "unknown precision %d", plan->precision);
     }
   });
 }

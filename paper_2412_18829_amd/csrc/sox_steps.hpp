@@ -291,6 +291,10 @@ template <typename T> struct IFTProb {
   T* Adyn;             // [n_tau][vc][NP][nP]
   int n, nP, NP, n_omega, n_tau, vc;
   int M, N, K;         // M = n_tau, N = NP*vc*nP, K = 2 n_omega
+  // split precision: A(tau) stored as bf16 hi and lo planes (same layout)
+  // instead of Adyn
+  bf16_t* Ahi = nullptr;
+  bf16_t* Alo = nullptr;
   __device__ f64x4 loadA4(int, int t, int k) const {
     if (t >= M) return zero4<double>();
     return load4_strided<double>(Tb2 + (long)t * 2 * n_omega, 1, k, 2 * n_omega);
@@ -319,7 +323,15 @@ template <typename T> struct IFTProb {
     const int u = col % nP;
     const int pv = col / nP;
     const int vl = pv % vc, P = pv / vc;
-    Adyn[(((long)t * vc + vl) * NP + P) * nP + u] = T(v);
+    const long o = (((long)t * vc + vl) * NP + P) * nP + u;
+    if (Ahi) {
+      const float x = (float)v;
+      const bf16_t h = f32_to_bf16(x);
+      Ahi[o] = h;
+      Alo[o] = f32_to_bf16(x - bf16_to_f32(h));
+    } else {
+      Adyn[o] = T(v);
+    }
   }
 };
 

@@ -103,6 +103,8 @@ LDS_CASES = [
     (40, 130, 3, 1, 0, 0, None, 9),
     (10, 40, 6, 1, 0, 0, "1", 9),
     (21, 90, 6, 1, 2, 0, "3", 9),
+    (5, 12, 6, 2, 2, 0, None, 8),
+    (21, 90, 6, 2, 2, 0, "3", 8),
 ]
 
 

@@ -4,7 +4,7 @@ against the FP64 oracle's eq:GG chain, through the C ABI.
 The oracle's chain is pinned to the 4-index brute force and to the
 continuum single-pole result in test_oracle_dyn.py.  Both sides use the same
 transform pair (an input).  Tolerances (max |diff| / max |oracle|): FP32
-1e-6; FP64 1e-11, raised to 10x the input's own rounding floor (the
+1e-6; BF16x3 (the fused contraction in split precision) 1e-4; FP64 1e-11, raised to 10x the input's own rounding floor (the
 disagreement of two exact float64 codings of the oracle) when a coarse grid
 makes the transform pair ill-conditioned.
 
@@ -22,7 +22,7 @@ from tests.gpu_util import dev, have_gpu, host, log, rel_err
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"fp64": 1e-11, "fp32": 1e-6}
+TOL = {"fp64": 1e-11, "fp32": 1e-6, "bf16x3": 1e-4}
 
 
 @pytest.fixture(scope="module")
@@ -49,7 +49,7 @@ def _run(B, wl, tp, precision, X, W, V, G):
     return host(S), plan
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 @pytest.mark.parametrize("shape", [(5, 12, 24, 20.0), (13, 70, 30, 30.0), (24, 150, 40, 100.0)])
 def test_dynamic_small_general_G(B, precision, shape):
     n, N, nt, beta = shape
@@ -72,7 +72,7 @@ def test_dynamic_small_general_G(B, precision, shape):
     assert err <= tol
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_dynamic_v_slabs_match(B, precision, monkeypatch):
     """A small workspace budget forces several v slabs (D accumulated across
     slabs); the result must match the single-slab run and the oracle."""
@@ -87,7 +87,7 @@ def test_dynamic_v_slabs_match(B, precision, monkeypatch):
     ref = om.sigma_dynamic_thc(wl["X"], wl["W_tau"], wl["V"], G, G[::-1], tp["T_fwd"], tp["T_bwd"])
     assert rel_err(one, ref) <= TOL[precision]
     assert rel_err(many, ref) <= TOL[precision]
-    assert rel_err(many, one) <= (1e-14 if precision == "fp64" else 1e-6)
+    assert rel_err(many, one) <= {"fp64": 1e-14, "fp32": 1e-6, "bf16x3": 1e-5}[precision]
 
 
 def test_dynamic_full_size_on_column_subset(B):
