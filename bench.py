@@ -5,7 +5,8 @@ One step = one pass of the whole path over the workload: G(tau) synthesis
 from the Fock eigenbasis, the U-contraction, the half projections, the A
 step (or, for the dynamic interaction, GG -> FT -> W(Omega) GG(Omega) -> IFT),
 the B, C -> D contraction, the back-transform to orbitals (all tau nodes and
-momenta: one "sweep") and the Galitskii-Migdal energy.  Inputs are seeded and
+momenta: one "sweep") and the Galitskii-Migdal energy (queued into device
+memory each step, read after the timed region).  Inputs are seeded and
 synthetic and resident in HBM before the timed region.  The default workload
 is the bare molecule n=64, N=384, 64 tau nodes, beta=50; --workload selects
 the others (3: static screening n=200 N=1200; 4: dynamic screening n=300
@@ -175,8 +176,10 @@ def cpu_oracle_baseline(wl: dict, kind: str, budget_s: float):
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default by workload: 100, 100, 5, 3, 2)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed steps first (default by workload: 10, 10, 1, 1, 1)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
     ap.add_argument("--workload", type=int, default=2, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -198,6 +201,12 @@ def main() -> int:
               file=sys.stderr)
         return 2
     desc, kind = WORKLOADS[args.workload]
+    # defaults keep each timed region under a minute; the small workloads run
+    # long enough for the clocks to settle and the launch ramp to amortise
+    if args.steps is None:
+        args.steps = {1: 100, 2: 100, 3: 5, 4: 3, 5: 2}[args.workload]
+    if args.warmup is None:
+        args.warmup = {1: 10, 2: 10}.get(args.workload, 1)
     import numpy as np
     import torch
 
@@ -246,26 +255,34 @@ def main() -> int:
         if solid:  # one buffer serves both entries
             ws = torch.empty(max(plan.workspace_size("bare"), plan.workspace_size("dynamic")) + 256,
                              dtype=torch.uint8, device=dev)
-        energies = []
+        # the energy of every step is queued into device memory (no host
+        # synchronisation per step) and read after the timed region
+        E = torch.zeros((warmup + steps + 3, 2), dtype=torch.float64, device=dev)
+        cur = [0]
 
         def step():
             B.sox_build_g_tau(plan, Q, eps, wl["mu"], G)
+            e = E[cur[0]]
             if kind == "static":
                 B.sox_sigma_static(plan, X, U1, V, G, S, ws=ws)
             elif kind == "dynamic":
                 B.sox_sigma_dynamic(plan, X, U1, V, G, S, ws=ws)
             elif solid:
                 B.sox_sigma_bare(plan, X, V, G, S, ws=ws)
-                energies.append(B.sox_energy_gm(plan, S, G))
+                B.sox_energy_gm_device(plan, S, G, e[1])
                 B.sox_sigma_dynamic(plan, X, U1, V, G, S, ws=ws)
             else:
                 B.sox_sigma_bare(plan, X, V, G, S, ws=ws)
-            energies.append(B.sox_energy_gm(plan, S, G))
+            B.sox_energy_gm_device(plan, S, G, e[0])
+            cur[0] += 1
 
         for _ in range(warmup):
             step()
         torch.cuda.synchronize()
         if profile:
+            # inside the timed region only the dominant stage is bracketed
+            # with events (on the stream its kernels run on)
+            B.sox_profile_select(plan, [DOMINANT[kind][0]])
             B.sox_profile_enable(plan, True)
             B.sox_profile_read(plan, reset=True)
         t0 = time.perf_counter()
@@ -273,10 +290,23 @@ def main() -> int:
             step()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        prof = B.sox_profile_read(plan, reset=True) if profile else None
+        prof = stages = None
         if profile:
+            prof = B.sox_profile_read(plan, reset=True)
+            # the per-stage breakdown from a short untimed pass with every
+            # stage recorded
+            B.sox_profile_select(plan, None)
+            kb = min(steps, 3)
+            for _ in range(kb):
+                step()
+            torch.cuda.synchronize()
+            stages = {k: round(v[0] / kb, 4) for k, v in B.sox_profile_read(plan, reset=True).items()
+                      if k != "dropped" and v[1] > 0}
             B.sox_profile_enable(plan, False)
-        return dict(seconds=t1 - t0, Sigma=S.cpu().numpy(), prof=prof, energy=energies[-1],
+        energies = E.cpu().numpy()[:cur[0]]
+        return dict(seconds=t1 - t0, Sigma=S.cpu().numpy(), prof=prof, stages=stages,
+                    energy=float(energies[warmup + steps - 1, 0]),
+                    energy_spread=float(np.ptp(energies[:, 0])),
                     plan=B.sox_plan_describe(plan))
 
     main_run = run(args.precision, args.steps, args.warmup, profile=True)
@@ -297,8 +327,7 @@ def main() -> int:
     dom_flops_per_launch = fl[stage] * args.steps / max(dom_launches, 1)
     achieved = dom_flops_per_launch / (dom_avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
-    stage_ms = {k: round(v[0] / args.steps, 4) for k, v in prof.items()
-                if k != "dropped" and v[1] > 0}
+    stage_ms = main_run["stages"]
 
     # every GPU run first (host-side numpy work between them would perturb
     # the launch timing), then the FP64 oracle on the host: the error
@@ -379,8 +408,7 @@ def main() -> int:
             "fused_achieved_tflops_alg": fb_ach,
             "fused_frac_of_bf16_peak": fb_ach / PEAK_TFLOPS["bf16x3"],
             "fused_frac_of_bf16_peak_mfma_work": 3.0 * fb_ach / PEAK_TFLOPS["bf16x3"],
-            "stage_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in rb["prof"].items()
-                                  if k != "dropped" and v[1] > 0},
+            "stage_ms_per_step": rb["stages"],
         }
 
     rec = {
@@ -402,6 +430,8 @@ def main() -> int:
                    "step": ("G(tau) + Sigma(all tau" + (", all k; bare and dynamic" if solid else "")
                             + ") + E_GM")},
         "tflops_alg": sweep_flops / (ms_per_step * 1e-3) / 1e12,
+        "energy_gm": main_run["energy"],
+        "energy_gm_spread_over_steps": main_run["energy_spread"],
         "max_rel_err": main_err,
         "roofline": {
             "kernel": kname, "bound": "mfma", "achieved": achieved, "peak": peak,

@@ -45,7 +45,8 @@
  *   are overwritten, never accumulated into.  `stream` is a hipStream_t
  *   (NULL = the null stream); all device work of a call is ordered on it
  *   and the call returns before that work finishes, except sox_energy_gm,
- *   which synchronises the stream to return the energy.
+ *   which synchronises the stream to return the energy to the host
+ *   (sox_energy_gm_device leaves it in device memory instead).
  * - The third propagator of eq:sox is read from node n_tau-1-k, i.e. the
  *   stored G(beta - tau_k): the tau grid must be mirror symmetric,
  *   tau[k] + tau[n_tau-1-k] = beta (checked at plan creation, 1e-12 beta).
@@ -202,6 +203,14 @@ sox_status sox_build_g_tau(sox_plan* plan, const double* Q, const double* eps, d
 sox_status sox_energy_gm(sox_plan* plan, const double* Sigma, const double* G, double* E_host,
                          void* stream);
 
+/* The same energy (eq:E2b) stored in DEVICE memory: E_dev is one float64
+ * owned by the caller, written on `stream`; the call returns before it is
+ * written and does not synchronise, so a loop of sweeps can queue the
+ * energy of every iteration and read the values later.  Arguments and
+ * errors as for sox_energy_gm. */
+sox_status sox_energy_gm_device(sox_plan* plan, const double* Sigma, const double* G,
+                                double* E_dev, void* stream);
+
 /* Per-stage device-time accounting.  While enabled, every kernel launch of
  * the plan's entry points is bracketed by HIP events recorded on the call's
  * stream; sox_profile_read synchronises those events and returns, per
@@ -228,6 +237,12 @@ typedef enum {
 } sox_stage;
 
 sox_status sox_profile_enable(sox_plan* plan, int32_t on);
+
+/* Bit s of stage_mask selects stage s (sox_stage) for recording while
+ * profiling is enabled; the other stages launch without events.  Default:
+ * every stage.  Each recorded stage adds two event records per launch
+ * group to the stream, so timing one stage perturbs the rest least. */
+sox_status sox_profile_select(sox_plan* plan, uint32_t stage_mask);
 
 /* ms[SOX_N_STAGES], launches[SOX_N_STAGES]; `dropped` may be NULL.  reset != 0
  * clears the accounting afterwards. */

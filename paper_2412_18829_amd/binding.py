@@ -28,8 +28,8 @@ ENTRIES = {"bare": SOX_ENTRY_BARE, "static": SOX_ENTRY_STATIC, "dynamic": SOX_EN
 EXPORTED = (
     "sox_plan_create", "sox_plan_destroy", "sox_workspace_size", "sox_sigma_bare",
     "sox_sigma_static", "sox_sigma_dynamic", "sox_sigma_vjp", "sox_build_g_tau",
-    "sox_energy_gm", "sox_sync", "sox_last_error", "sox_abi_version", "sox_profile_enable",
-    "sox_profile_read", "sox_plan_set_graph", "sox_plan_describe",
+    "sox_energy_gm", "sox_energy_gm_device", "sox_sync", "sox_last_error", "sox_abi_version", "sox_profile_enable",
+    "sox_profile_read", "sox_profile_select", "sox_plan_set_graph", "sox_plan_describe",
 )
 STAGES = ("gbuild", "utensor", "project", "astep", "fused", "back", "energy", "gg_ft", "wgemm",
           "ift", "split", "vjp", "kbc", "kd")
@@ -73,11 +73,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.sox_sigma_vjp.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_build_g_tau.argtypes = [vp, vp, vp, dp, vp, vp]
     L.sox_energy_gm.argtypes = [vp, vp, vp, ctypes.POINTER(dp), vp]
+    L.sox_energy_gm_device.argtypes = [vp, vp, vp, vp, vp]
     L.sox_sync.argtypes = [vp]
     L.sox_last_error.argtypes = []
     L.sox_last_error.restype = ctypes.c_char_p
     L.sox_abi_version.argtypes = []
     L.sox_profile_enable.argtypes = [vp, i32]
+    L.sox_profile_select.argtypes = [vp, ctypes.c_uint32]
     L.sox_plan_set_graph.argtypes = [vp, i32]
     L.sox_plan_describe.argtypes = [vp, ctypes.c_char_p, sz]
     L.sox_profile_read.argtypes = [vp, ctypes.POINTER(dp), ctypes.POINTER(ctypes.c_int64),
@@ -289,6 +291,19 @@ def sox_energy_gm(plan: Plan, Sigma, G, stream=None) -> float:
     return float(e.value)
 
 
+def sox_energy_gm_device(plan: Plan, Sigma, G, E, stream=None):
+    """Queue the energy into E (a one-element float64 device tensor, e.g. a
+    row of a preallocated buffer) without synchronising."""
+    import torch
+    if E.dtype != torch.float64 or E.numel() != 1:
+        raise ValueError("E must be a one-element float64 tensor")
+    n, nt = plan.n, plan.n_tau
+    _check(load().sox_energy_gm_device(plan.handle, plan._t(Sigma, (nt, n, n), "Sigma"),
+                                       plan._t(G, (nt, n, n), "G"), _ptr(E), _stream(stream)),
+           "sox_energy_gm_device")
+    return E
+
+
 def sox_sync(stream=None):
     _check(load().sox_sync(_stream(stream)), "sox_sync")
 
@@ -299,6 +314,12 @@ def sox_abi_version() -> int:
 
 def sox_profile_enable(plan: Plan, on: bool = True):
     _check(load().sox_profile_enable(plan.handle, 1 if on else 0), "sox_profile_enable")
+
+
+def sox_profile_select(plan: Plan, stages=None):
+    """Record only `stages` (names from STAGES; None: all) while profiling."""
+    mask = 0xFFFFFFFF if stages is None else sum(1 << STAGES.index(s) for s in stages)
+    _check(load().sox_profile_select(plan.handle, ctypes.c_uint32(mask)), "sox_profile_select")
 
 
 def sox_profile_read(plan: Plan, reset: bool = True) -> dict:

@@ -129,13 +129,14 @@ struct sox_plan {
   std::vector<std::pair<int, double>> tune_ms;
   bool tune_from_cache = false;
   bool prof_on = false;
+  uint32_t prof_mask = 0xFFFFFFFFu;  // stages recorded while profiling is on
   std::vector<Ev> ev_pool;
   size_t ev_used = 0;
   int64_t ev_dropped = 0;
   static constexpr size_t kMaxEvents = 65536;
 
   int prof_begin(int stage, hipStream_t s) {
-    if (!prof_on) return -1;
+    if (!prof_on || !((prof_mask >> stage) & 1u)) return -1;
     if (ev_used >= kMaxEvents) {
       ++ev_dropped;
       return -1;
@@ -1907,32 +1908,57 @@ sox_status sox_build_g_tau(sox_plan* plan, const double* Q, const double* eps, d
   return SOX_OK;
 }
 
+namespace {
+// Queues the Galitskii-Migdal energy into e (device; null: the plan's scratch
+// slot, returned in *slot).
+sox_status queue_energy(sox_plan& p, const double* Sigma, const double* G, double* e,
+                        double** slot, hipStream_t s) {
+  if (p.nk > 1) return solid_energy(p, Sigma, G, e, slot, s);
+  const int n = p.n, nt = p.n_tau;
+  double* tr = p.d_scratch + (size_t)nt * n;
+  if (!e) e = tr + nt;
+  if (slot) *slot = e;
+  ProfScope ps(p, SOX_STAGE_ENERGY, s);
+  hipLaunchKernelGGL(energy_trace_kernel, dim3(nt), dim3(256), 0, s, Sigma, G, n, nt, tr);
+  SOX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(energy_reduce_kernel, dim3(1), dim3(256), 0, s, tr, p.d_w, nt, e);
+  SOX_HIP(hipGetLastError());
+  return SOX_OK;
+}
+}  // namespace
+
 sox_status sox_energy_gm(sox_plan* plan, const double* Sigma, const double* G, double* E_host,
                          void* stream) {
   sox_status st = check_plan(plan);
   if (st) return st;
   if (!Sigma || !G || !E_host) return fail(SOX_ERR_INVALID_ARG, "NULL pointer");
   hipStream_t s = (hipStream_t)stream;
-  if (plan->nk > 1) return solid_energy(*plan, Sigma, G, E_host, s);
-  const int n = plan->n, nt = plan->n_tau;
-  double* tr = plan->d_scratch + (size_t)nt * n;
-  double* e = tr + nt;
-  {
-  ProfScope ps(*plan, SOX_STAGE_ENERGY, s);
-  hipLaunchKernelGGL(energy_trace_kernel, dim3(nt), dim3(256), 0, s, Sigma, G, n, nt, tr);
-  SOX_HIP(hipGetLastError());
-  hipLaunchKernelGGL(energy_reduce_kernel, dim3(1), dim3(256), 0, s, tr, plan->d_w, nt, e);
-  SOX_HIP(hipGetLastError());
-  }
+  double* e = nullptr;
+  if ((st = queue_energy(*plan, Sigma, G, nullptr, &e, s))) return st;
   SOX_HIP(hipMemcpyAsync(E_host, e, sizeof(double), hipMemcpyDeviceToHost, s));
   SOX_HIP(hipStreamSynchronize(s));
   return SOX_OK;
+}
+
+sox_status sox_energy_gm_device(sox_plan* plan, const double* Sigma, const double* G,
+                                double* E_dev, void* stream) {
+  sox_status st = check_plan(plan);
+  if (st) return st;
+  if (!Sigma || !G || !E_dev) return fail(SOX_ERR_INVALID_ARG, "NULL pointer");
+  return queue_energy(*plan, Sigma, G, E_dev, nullptr, (hipStream_t)stream);
 }
 
 sox_status sox_profile_enable(sox_plan* plan, int32_t on) {
   sox_status st = check_plan(plan);
   if (st) return st;
   plan->prof_on = on != 0;
+  return SOX_OK;
+}
+
+sox_status sox_profile_select(sox_plan* plan, uint32_t stage_mask) {
+  sox_status st = check_plan(plan);
+  if (st) return st;
+  plan->prof_mask = stage_mask;
   return SOX_OK;
 }
 

@@ -393,20 +393,19 @@ sox_status solid_build_g(sox_plan& p, const double* Q, const double* eps, double
   return cg_launch(a, nk * nt, 0, s);
 }
 
-sox_status solid_energy(sox_plan& p, const double* Sigma, const double* G, double* E_host,
-                        hipStream_t s) {
+// Queues the energy into e (device; null: the plan's scratch slot, returned
+// in *slot).
+sox_status solid_energy(sox_plan& p, const double* Sigma, const double* G, double* e,
+                        double** slot, hipStream_t s) {
   const int n = p.n, nt = p.n_tau, nk = p.nk;
   double* tr = p.d_scratch + round_up((long)nt * nk * n, 2) + 2L * nt * nk * n;
-  double* e = tr + (size_t)nt * nk;
-  {
-    ProfScope ps(p, SOX_STAGE_ENERGY, s);
-    hipLaunchKernelGGL(energy_trace_c_kernel, dim3(nt, nk), dim3(256), 0, s, Sigma, G, n, nt, tr);
-    SOX_HIP(hipGetLastError());
-    hipLaunchKernelGGL(energy_reduce_c_kernel, dim3(1), dim3(256), 0, s, tr, p.d_w, nt, nk, e);
-    SOX_HIP(hipGetLastError());
-  }
-  SOX_HIP(hipMemcpyAsync(E_host, e, sizeof(double), hipMemcpyDeviceToHost, s));
-  SOX_HIP(hipStreamSynchronize(s));
+  if (!e) e = tr + (size_t)nt * nk;
+  if (slot) *slot = e;
+  ProfScope ps(p, SOX_STAGE_ENERGY, s);
+  hipLaunchKernelGGL(energy_trace_c_kernel, dim3(nt, nk), dim3(256), 0, s, Sigma, G, n, nt, tr);
+  SOX_HIP(hipGetLastError());
+  hipLaunchKernelGGL(energy_reduce_c_kernel, dim3(1), dim3(256), 0, s, tr, p.d_w, nt, nk, e);
+  SOX_HIP(hipGetLastError());
   return SOX_OK;
 }
 

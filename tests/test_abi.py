@@ -92,5 +92,7 @@ def test_entry_points_reject_null_plan():
     assert lib.sox_sigma_vjp(None, 0, *([None] * 9), None, 0, None) == 1
     e = ctypes.c_double()
     assert lib.sox_energy_gm(None, None, None, ctypes.byref(e), None) == 1
+    assert lib.sox_energy_gm_device(None, None, None, None, None) == 1
     assert lib.sox_build_g_tau(None, None, None, 0.0, None, None) == 1
+    assert lib.sox_profile_select(None, 1) == 1
     assert lib.sox_plan_destroy(None) == 0

@@ -153,6 +153,10 @@ def test_energy_and_v_slabs(B, monkeypatch):
     e = B.sox_energy_gm(plan1, S1, G)
     e_ref = osd.energy_gm_k(ref, Gr, wl["weights"])
     assert abs(e - e_ref) <= 1e-11 * abs(e_ref)
+    E = torch.full((1,), float("nan"), dtype=torch.float64, device="cuda")
+    B.sox_energy_gm_device(plan1, S1, G, E)
+    torch.cuda.synchronize()
+    assert E.cpu().numpy()[0] == e
 
 
 def test_unsupported_requests(B):

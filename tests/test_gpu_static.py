@@ -105,6 +105,12 @@ def test_bare_workload2_full_size(B, precision):
     e = B.sox_energy_gm(plan, S, G)
     e_ref = om.energy_gm(ref, om.g_mirror(Gr), wl["weights"])
     assert abs(e - e_ref) <= 10 * TOL[precision] * abs(e_ref)
+    # the device-output form: the same value, queued twice without a sync
+    E = torch.full((2,), float("nan"), dtype=torch.float64, device="cuda")
+    B.sox_energy_gm_device(plan, S, G, E[0])
+    B.sox_energy_gm_device(plan, S, G, E[1])
+    torch.cuda.synchronize()
+    assert host(E).tolist() == [e, e]
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
