@@ -191,9 +191,22 @@ size_t elem_size(int precision) { return precision == SOX_FP64 ? 8 : 4; }
 
 // float32 scratch of the U-contraction on the LDS-staged GEMM (the
 // Khatri-Rao factor and the padded interaction); none in float64 plans
+// K splits of the float32 U-contraction: doubled while the output tiles
+// alone give fewer than two workgroups per CU (small molecules), each split
+// a multiple of 16 deep
+int utensor_ksplit(const sox_plan& p) {
+  const long tiles = (long)((p.NP + kLdsTile - 1) / kLdsTile) *
+                     (((long)p.nP * p.nP + kLdsTile - 1) / kLdsTile);
+  int ks = 1;
+  while (ks < 4 && tiles * ks < 2L * p.n_cu && p.NP % (32 * ks) == 0) ks *= 2;
+  return ks;
+}
+
 size_t utensor_scratch_bytes(const sox_plan& p) {
   if (p.precision == SOX_FP64) return 0;
-  return ((size_t)p.nP * p.nP * p.NP + (size_t)p.NP * p.NP) * 4;
+  const int ks = utensor_ksplit(p);
+  return ((size_t)p.nP * p.nP * p.NP + (size_t)p.NP * p.NP +
+          (ks > 1 ? (size_t)ks * p.NP * p.nP * p.nP : 0)) * 4;
 }
 
 
@@ -411,19 +424,31 @@ sox_status launch_utensor(const sox_plan& p, const double* U, const double* X, T
     hipLaunchKernelGGL(pad_cast_kernel, grid1d(nv), dim3(256), 0, s, U, V32, p.N, p.N, p.NP,
                        p.NP);
     SOX_HIP(hipGetLastError());
+    // ks > 1: K split over the batch index into ks partial blocks, then summed
+    const int ks = utensor_ksplit(p);
+    const long blk = (long)p.NP * p.nP * p.nP;
+    float* part = V32 + nv;
     DenseLdsArgs l{};
     l.A = V32;
     l.B = KR;
-    l.C = (float*)out;
+    l.C = ks > 1 ? part : (float*)out;
     l.lda = p.NP;
     l.ldb = p.NP;
     l.ldc = (long)p.nP * p.nP;
     l.M = p.NP;
     l.N = p.nP * p.nP;
-    l.K = p.NP;
+    l.K = p.NP / ks;
     l.rgroup = l.M;
     l.rvalid = l.M;
-    SOX_HIP(launch_dense_lds_f32(l, 1, s));
+    l.sA = l.K;
+    l.sB = l.K;
+    l.sC = blk;
+    SOX_HIP(launch_dense_lds_f32(l, ks, s));
+    if (ks > 1) {
+      hipLaunchKernelGGL(sum_blocks_kernel, grid1d(blk), dim3(256), 0, s, part, (float*)out, blk,
+                         blk, ks);
+      SOX_HIP(hipGetLastError());
+    }
     return SOX_OK;
   }
   UTensorProb<T> pr{U, X, out, p.n, p.N, p.nP, p.NP, p.nP * p.nP, p.N, 0, p.NP};
@@ -625,14 +650,23 @@ sox_status launch_split(const float* src, bf16_t* hi, bf16_t* lo, long count, hi
 // into D64 first; float64 D is read in place).
 template <typename T>
 sox_status launch_back(const sox_plan& p, const double* XP, const T* D, double* D64, double* E,
-                       double* Sigma, int t0, int cnt, hipStream_t s) {
+                       double* Sigma, int t0, int cnt, hipStream_t s, int nsplit = 1,
+                       long sstride = 0) {
   const int n = p.n, NP = p.NP;
   const double* Dd = (const double*)D;
   if (sizeof(T) == 4) {
+    // float32 D (the nsplit partial blocks of a split v sum, if any) summed
+    // and widened to float64 in one pass
     const long cd = (long)cnt * NP * NP;
-    hipLaunchKernelGGL(widen_kernel, grid1d(cd), dim3(256), 0, s, (const float*)D, D64, cd);
+    if (nsplit > 1)
+      hipLaunchKernelGGL(widen_sum_kernel, grid1d(cd), dim3(256), 0, s, (const float*)D, D64, cd,
+                         sstride, nsplit);
+    else
+      hipLaunchKernelGGL(widen_kernel, grid1d(cd), dim3(256), 0, s, (const float*)D, D64, cd);
     SOX_HIP(hipGetLastError());
     Dd = D64;
+  } else if (nsplit > 1) {
+    return fail(SOX_ERR_SHAPE, "internal: split D blocks in a float64 back-transform");
   }
   DenseArgs<double, double> e{};
   e.A = XP; e.B = Dd; e.C = E;
@@ -778,8 +812,10 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
       st = launch_fused_cfg<T>(p, fa, s);
       if (st) return st;
     }
-    if (p.fused_vsplit > 1) {
-      // the v splits' partial D blocks, summed ahead of the back-transform
+    // float32: the v splits' partial D blocks are summed while widening;
+    // float64: summed here first
+    const int nsplit = sizeof(T) == 4 ? p.fused_vsplit : 1;
+    if (sizeof(T) == 8 && p.fused_vsplit > 1) {
       ProfScope ps(p, SOX_STAGE_BACK, s);
       const long count = (long)cnt * NP * NP;
       hipLaunchKernelGGL(dsplit_sum_kernel<T>, grid1d(count), dim3(256), 0,
@@ -789,7 +825,7 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
     {
       ProfScope ps(p, SOX_STAGE_BACK, s);
       if ((st = launch_back<T>(p, (const double*)(base + L.xp), D, (double*)(base + L.d64), E,
-                               Sigma, t0, cnt, s)))
+                               Sigma, t0, cnt, s, nsplit, fa.d_sstride)))
         return st;
     }
   }

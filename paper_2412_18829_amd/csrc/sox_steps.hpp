@@ -168,6 +168,25 @@ __global__ void widen_kernel(const float* src, double* dst, long count) {
   SOX_FOR_FLAT(idx, count) dst[idx] = (double)src[idx];
 }
 
+// dst = sum over ns float32 blocks src + s stride (split-K partial products)
+__global__ void sum_blocks_kernel(const float* src, float* dst, long count, long stride, int ns) {
+  SOX_FOR_FLAT(idx, count) {
+    float acc = src[idx];
+    for (int s = 1; s < ns; ++s) acc += src[idx + s * stride];
+    dst[idx] = acc;
+  }
+}
+
+// dst = sum over ns float32 blocks src + s stride, formed in float64 (the
+// partial D blocks of a split v sum, summed and widened in one pass)
+__global__ void widen_sum_kernel(const float* src, double* dst, long count, long stride, int ns) {
+  SOX_FOR_FLAT(idx, count) {
+    double acc = (double)src[idx];
+    for (int s = 1; s < ns; ++s) acc += (double)src[idx + s * stride];
+    dst[idx] = acc;
+  }
+}
+
 template <typename T>
 __global__ void cast_kernel(const double* src, T* dst, long count) {
   SOX_FOR_FLAT(idx, count) dst[idx] = T(src[idx]);
