@@ -82,6 +82,7 @@ struct sox_plan {
   int fused_cfg;   // index into kFusedCfgs
   int fused_vsplit = 1;  // workgroups sharing one D tile's v sum (static entries)
   int n_cu = 256;        // compute units of the device
+  long dense_wg = 512;   // short-K LDS-staged GEMM: workgroups in the grid at most
   int wg_tile;     // NP granule: 2 * max(wave tile edges)
   int slab;        // tau nodes per slab
   double beta;
@@ -443,7 +444,7 @@ sox_status launch_utensor(const sox_plan& p, const double* U, const double* X, T
     l.sA = l.K;
     l.sB = l.K;
     l.sC = blk;
-    SOX_HIP(launch_dense_lds_f32(l, ks, s));
+    SOX_HIP(launch_dense_lds_f32(l, ks, s, p.dense_wg));
     if (ks > 1) {
       hipLaunchKernelGGL(sum_blocks_kernel, grid1d(blk), dim3(256), 0, s, part, (float*)out, blk,
                          blk, ks);
@@ -479,7 +480,7 @@ sox_status launch_astep(const sox_plan& p, const T* u1t, const T* gbt, T* A, int
     l.C = (float*)A;
     l.Chi = a_hi;  // split-precision path: A is stored only as its hi and lo planes
     l.Clo = a_lo;
-    SOX_HIP(launch_dense_lds_f32(l, 1, s));
+    SOX_HIP(launch_dense_lds_f32(l, 1, s, p.dense_wg));
     return SOX_OK;
   }
   DenseArgs<T, T> d{};
@@ -1744,6 +1745,8 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
       p->n_cu = ncu;
     if (p->nk == 1) pick_vsplit(*p);
   }
+  p->dense_wg = 2L * p->n_cu;  // two workgroups of the LDS-staged GEMM per CU
+  if (const char* s = getenv("SOX_DENSE_WG")) p->dense_wg = atol(s);
   if (e == hipSuccess && p->n_omega > 0) {
     const int nw = p->n_omega;
     std::vector<double> tf2(2 * (size_t)nw * nt), tb2((size_t)nt * 2 * nw);

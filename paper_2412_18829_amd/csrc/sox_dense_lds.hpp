@@ -3,14 +3,19 @@
 //
 //   C[row][col] = sum_k A[row][k] * B[col][k]
 //
-// A workgroup of four wavefronts owns a 128 x 128 block of C, each
-// wavefront 64 x 64 (4 x 4 tiles of v_mfma_f32_16x16x4f32).  K runs in
-// stages of 16 values (64 bytes per row): the stage's 128-row panels of A
-// and B are copied straight into a ring of five LDS buffers four stages
-// ahead of the MFMAs, with the same swizzled 64-byte rows, fence-free
-// barriers, exact copy counting and buffer reuse rule as the fused kernel.  K must be a
-// multiple of 16; rows and columns past M and N are read from the last
-// valid row and not stored.
+// A workgroup of four wavefronts computes about tpw of the 128 x 128 blocks
+// of C (block b of the grid's w workgroups: b, b + w, b + 2 w, ...; row
+// blocks fastest), each wavefront 64 x 64 of a block (4 x 4 tiles
+// of v_mfma_f32_16x16x4f32).  K runs in stages of 16 values (64 bytes per
+// row): the stage's 128-row panels of A and B are copied straight into a
+// ring of five LDS buffers four stages ahead of the MFMAs, with the same
+// swizzled 64-byte rows, fence-free barriers, exact copy counting and
+// buffer reuse rule as the fused kernel.  The stages of a workgroup's
+// blocks run back to back through the ring, so with a short K (the A step)
+// the copies of the next block are in flight while the current block's
+// MFMAs run and its results are stored.  K must be a multiple of 16; rows
+// and columns past M and N are read from the last valid row and not
+// stored.
 //
 // blockIdx.y runs over a batch (operand and output strides sA, sB, sC).
 // Rows come in groups (the A step: group = tau, rows = v padded to nP):
@@ -40,6 +45,7 @@ struct DenseLdsArgs {
   bf16_t* Clo;
   long sA, sB, sC;      // batch strides (elements; blockIdx.y is the batch)
   int tiles_m, tiles_n;
+  int tpw;              // output tiles per workgroup (set by the launcher)
   double* C64 = nullptr;  // float64 output instead of C (same offsets)
   int accumulate = 0;     // float64 output only: C64 += result
 };
@@ -47,29 +53,39 @@ struct DenseLdsArgs {
 __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p) {
   // [buffer][plane: A rows, B rows][row * 4 + swizzled segment]
   __shared__ u32x4 lds[kLdsBufs][2][kLdsPieces];
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int tm = bid % p.tiles_m;  // row tiles fastest: they share the B panel
-  const int tn = bid / p.tiles_m;
+  // tiles wid, wid + nwg, wid + 2 nwg, ...: the workgroups resident at one
+  // time work on neighbouring tiles, as with one tile per workgroup
+  const long ntiles = (long)p.tiles_m * p.tiles_n;
+  const long nwg = gridDim.x;
+  const long wid = xcd_remap(blockIdx.x, gridDim.x);
+  const int ntl = (int)((ntiles - wid + nwg - 1) / nwg);
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15;
   const int g = lane >> 4;
-  const int M0 = tm * kLdsTile, N0 = tn * kLdsTile;
   const long bat = blockIdx.y;
+  const int KC = p.K / 16;
+  const int nst = ntl * KC;  // stages of every tile of this workgroup, back to back
 
-  // copies: instruction h of wavefront w fills pieces 64 c .. 64 c + 63 (c = w + 4 h)
+  // copies: instruction h of wavefront w fills pieces 64 c .. 64 c + 63 (c =
+  // w + 4 h) from the rows of the tile under the copy cursor
   const char* srca[2];
   const char* srcb[2];
+  auto set_src = [&](long tile) {
+    const int M0 = (int)(tile % p.tiles_m) * kLdsTile;  // row tiles fastest: they share B
+    const int N0 = (int)(tile / p.tiles_m) * kLdsTile;
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int c = wave + 4 * h;
-    const int row = 16 * c + (lane >> 2);
-    const int seg = (lane & 3) ^ ((row >> 1) & 3);
-    const int ra = M0 + row < p.M ? M0 + row : p.M - 1;
-    const int rb = N0 + row < p.N ? N0 + row : p.N - 1;
-    srca[h] = (const char*)(p.A + bat * p.sA + (long)ra * p.lda) + 16 * seg;
-    srcb[h] = (const char*)(p.B + bat * p.sB + (long)rb * p.ldb) + 16 * seg;
-  }
+    for (int h = 0; h < 2; ++h) {
+      const int c = wave + 4 * h;
+      const int row = 16 * c + (lane >> 2);
+      const int seg = (lane & 3) ^ ((row >> 1) & 3);
+      const int ra = M0 + row < p.M ? M0 + row : p.M - 1;
+      const int rb = N0 + row < p.N ? N0 + row : p.N - 1;
+      srca[h] = (const char*)(p.A + bat * p.sA + (long)ra * p.lda) + 16 * seg;
+      srcb[h] = (const char*)(p.B + bat * p.sB + (long)rb * p.ldb) + 16 * seg;
+    }
+  };
+  set_src(wid);
   int sa[4], sb[4];
   const int sw = g ^ ((li >> 1) & 3);
 #pragma unroll
@@ -77,16 +93,23 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
     sa[i] = ((wave >> 1) * 64 + 16 * i + li) * 4 + sw;
     sb[i] = ((wave & 1) * 64 + 16 * i + li) * 4 + sw;
   }
-  const int KC = p.K / 16;
   const int c0 = 64 * wave, c1 = 64 * (wave + 4);
-  int ck = 0;  // next chunk to copy, held at the last one past the end
+  // copy cursor: tile ct, chunk ck, stage cs; held at the last stage once
+  // every stage is under way
+  int ct = 0, ck = 0, cs = 0;
   auto copy_stage = [&](int b) {
     const long ko = (long)ck * 64;
     global_to_lds16(srca[0] + ko, &lds[b][0][c0]);
     global_to_lds16(srca[1] + ko, &lds[b][0][c1]);
     global_to_lds16(srcb[0] + ko, &lds[b][1][c0]);
     global_to_lds16(srcb[1] + ko, &lds[b][1][c1]);
-    ck += ck + 1 < KC ? 1 : 0;
+    if (cs + 1 < nst) {
+      ++cs;
+      if (++ck == KC) {
+        ck = 0;
+        set_src(wid + ++ct * nwg);
+      }
+    }
   };
   auto frags = [&](int b, f32x4* fa, f32x4* fb) {
 #pragma unroll
@@ -108,11 +131,47 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = mfma16x16x4(fa[i][m], fb[j][m], acc[i][j]);
   };
+  // stores local tile tl and clears the accumulators for the next tile
+  auto store_tile = [&](int tl) {
+    const long tile = wid + tl * nwg;
+    const int M0 = (int)(tile % p.tiles_m) * kLdsTile, N0 = (int)(tile / p.tiles_m) * kLdsTile;
+    const int Rw = M0 + (wave >> 1) * 64, Cw = N0 + (wave & 1) * 64;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = Rw + 16 * i + 4 * g + r;
+        const int grp = row / p.rgroup, rin = row - grp * p.rgroup;
+        if (row >= p.M || rin >= p.rvalid) continue;
+        const long base = bat * p.sC + (long)grp * p.c_gstride + (long)rin * p.ldc;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int col = Cw + 16 * j + li;
+          if (col >= p.N) continue;
+          const float x = acc[i][j][r];
+          if (p.Chi) {
+            const bf16_t hgh = f32_to_bf16(x);
+            p.Chi[base + col] = hgh;
+            p.Clo[base + col] = f32_to_bf16(x - bf16_to_f32(hgh));
+          } else if (p.C64) {
+            p.C64[base + col] = p.accumulate ? p.C64[base + col] + (double)x : (double)x;
+          } else {
+            p.C[base + col] = x;
+          }
+        }
+      }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = zero4<float>();
+  };
 
   // Stage s (buffer s % 5): copy stage s + 4 into the buffer of stage s - 1
   // (whose fragments every wavefront consumed before the barrier that ended
-  // stage s - 1), read the fragments of stage s + 1, MFMAs of stage s, wait
-  // for the own copies of stage s + 2, barrier.
+  // stage s - 1), read the fragments of stage s + 1, MFMAs of stage s (and,
+  // on a tile's last stage, its stores), wait for the own copies of stage
+  // s + 2, barrier.  The copies of the next tile run ahead of the current
+  // tile's MFMAs and stores like those of its own later stages.
   copy_stage(0);
   copy_stage(1);
   copy_stage(2);
@@ -124,52 +183,36 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
   int b1 = 1;  // buffer of stage s + 1
   auto next = [](int x) { return x + 1 == kLdsBufs ? 0 : x + 1; };
   auto back2 = [](int x) { return x >= 2 ? x - 2 : x + kLdsBufs - 2; };
-  for (int s = 0; s < KC; s += 2) {
+  int kk = 0, tl = 0;  // chunk and tile of the stage under the MFMAs
+  for (int st = 0; st < nst; st += 2) {
     copy_stage(back2(b1));
     frags(b1, fa1, fb1);
     mfma_stage(fa0, fb0);
+    if (++kk == KC) {
+      store_tile(tl++);
+      kk = 0;
+    }
     wait_vm<8>();
     barrier_nofence();
     b1 = next(b1);
-    if (s + 1 < KC) {
+    if (st + 1 < nst) {
       copy_stage(back2(b1));
       frags(b1, fa0, fb0);
       mfma_stage(fa1, fb1);
+      if (++kk == KC) {
+        store_tile(tl++);
+        kk = 0;
+      }
       wait_vm<8>();
       barrier_nofence();
       b1 = next(b1);
     }
   }
   wait_vm<0>();  // the repeated copies past the end
-
-  const int Rw = M0 + (wave >> 1) * 64, Cw = N0 + (wave & 1) * 64;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int row = Rw + 16 * i + 4 * g + r;
-      const int grp = row / p.rgroup, rin = row - grp * p.rgroup;
-      if (row >= p.M || rin >= p.rvalid) continue;
-      const long base = bat * p.sC + (long)grp * p.c_gstride + (long)rin * p.ldc;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int col = Cw + 16 * j + li;
-        if (col >= p.N) continue;
-        const float x = acc[i][j][r];
-        if (p.Chi) {
-          const bf16_t hgh = f32_to_bf16(x);
-          p.Chi[base + col] = hgh;
-          p.Clo[base + col] = f32_to_bf16(x - bf16_to_f32(hgh));
-        } else if (p.C64) {
-          p.C64[base + col] = p.accumulate ? p.C64[base + col] + (double)x : (double)x;
-        } else {
-          p.C[base + col] = x;
-        }
-      }
-    }
 }
 
-inline hipError_t launch_dense_lds_f32(DenseLdsArgs a, int batch, hipStream_t s) {
+inline hipError_t launch_dense_lds_f32(DenseLdsArgs a, int batch, hipStream_t s,
+                                      long wg_target = 0) {
   if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;
   if (batch > 65535) return hipErrorInvalidValue;
   if (a.K % 16 != 0 || a.K <= 0 || a.rgroup <= 0 || (a.Chi && !a.Clo) ||
@@ -177,7 +220,17 @@ inline hipError_t launch_dense_lds_f32(DenseLdsArgs a, int batch, hipStream_t s)
     return hipErrorInvalidValue;
   a.tiles_m = (a.M + kLdsTile - 1) / kLdsTile;
   a.tiles_n = (a.N + kLdsTile - 1) / kLdsTile;
-  const long nb = (long)a.tiles_m * a.tiles_n;
+  const long ntiles = (long)a.tiles_m * a.tiles_n;
+  // short K (at most 8 stages): several tiles per workgroup, so that the
+  // grid holds at most wg_target workgroups (all resident at once) and a
+  // workgroup's copies for its next tile overlap its current tile.  Longer
+  // K (or wg_target 0): one tile per workgroup (with 13 stages, C = 20800 x
+  // 266240, the shared workgroups measured 4% slower: each tile's stores
+  // hold up the next wait)
+  long per = 1;
+  if (wg_target > 0 && a.K <= 128) per = (ntiles * batch + wg_target - 1) / wg_target;
+  a.tpw = (int)(per < 1 ? 1 : per > ntiles ? ntiles : per);
+  const long nb = (ntiles + a.tpw - 1) / a.tpw;
   if (nb > (1L << 31) - 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(dense_lds_f32_kernel, dim3((unsigned)nb, (unsigned)batch), dim3(256), 0, s, a);
   return hipGetLastError();

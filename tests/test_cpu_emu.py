@@ -121,6 +121,30 @@ def test_lds_fused_kernel_in_bounds(emu, case):
     assert f'"fused_cfg":{cfg}' in out, out[-2000:]
 
 
+# the LDS-staged GEMM with several output tiles per workgroup (A step and
+# U-contraction): every tile in one workgroup, and three workgroups with a
+# short last one
+DENSE_WG_CASES = [
+    (13, 70, 5, 1, 1, 0, None, 1),
+    (13, 70, 5, 1, 1, 0, None, 3),
+    (13, 70, 5, 2, 1, 0, None, 3),
+    (16, 256, 3, 1, 0, 0, None, 5),
+    (10, 40, 6, 1, 0, 0, "1", 2),
+]
+
+
+@pytest.mark.parametrize("case", DENSE_WG_CASES, ids=lambda c: "-".join(str(x) for x in c))
+def test_dense_multi_tile_in_bounds(emu, case):
+    n, N, nt, prec, entry, vjp, budget, wg = case
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", SOX_DENSE_WG=str(wg))
+    if budget:
+        env["SOX_WS_BUDGET_MB"] = budget
+    r = subprocess.run([emu, str(n), str(N), str(nt), str(prec), str(entry), str(vjp)],
+                       capture_output=True, text=True, env=env, timeout=900)
+    out = r.stdout + r.stderr
+    assert r.returncode == 0 and "status 0" in out and "AddressSanitizer" not in out, out[-4000:]
+
+
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "-".join(str(x) for x in c))
 def test_entry_point_in_bounds(emu, case):
     n, N, nt, prec, entry, vjp, budget = case

@@ -257,6 +257,33 @@ def test_fp32_lds_kernel_vs_oracle(B, shape, monkeypatch):
     assert err <= TOL["fp32"]
 
 
+@pytest.mark.parametrize("precision,wg", [("fp32", 1), ("fp32", 3), ("bf16x3", 3), ("fp32", 7)])
+@pytest.mark.parametrize("shape", [(13, 50, 6), (40, 200, 4)])
+def test_dense_multi_tile_workgroups_vs_oracle(B, shape, precision, wg, monkeypatch):
+    """The A step and U-contraction GEMM with several output tiles per
+    workgroup (at most `wg` workgroups: every tile in one, or several with a
+    short last one) against the oracle; the result matches the default
+    launch to rounding."""
+    import torch
+    n, N, nt = shape
+    log(f"dense multi-tile {shape} {precision} wg={wg}")
+    wl = synth.small_molecule(n, N, nt, 7.0, seed=500 + n, static=True)
+    rng = np.random.default_rng(n + 3)
+    Gr = om.g_tau(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"]) + 0.05 * rng.standard_normal((nt, n, n))
+    args = (dev(wl["X"]), dev(wl["W0"]), dev(wl["V"]), dev(Gr))
+    S0 = torch.empty((nt, n, n), dtype=torch.float64, device="cuda")
+    B.sox_sigma_static(_plan(B, wl, precision), *args, S0)
+    monkeypatch.setenv("SOX_DENSE_WG", str(wg))
+    S = torch.empty_like(S0)
+    B.sox_sigma_static(_plan(B, wl, precision), *args, S)
+    torch.cuda.synchronize()
+    ref = om.sigma_static_thc(wl["X"], wl["W0"], wl["V"], Gr, Gr[::-1])
+    err = rel_err(host(S), ref)
+    log(f"  rel err {err:.3e}, vs default launch {rel_err(host(S), host(S0)):.3e}")
+    assert err <= {"fp32": TOL["fp32"], "bf16x3": 1e-4}[precision]
+    assert rel_err(host(S), host(S0)) <= 1e-12
+
+
 @pytest.mark.parametrize("precision,n,expect", [("fp32", 512, 3), ("bf16x3", 736, 7)])
 def test_lds_kernel_offset_limit_falls_back(B, precision, n, expect):
     """Past the LDS-staged kernel's 32-bit panel offsets (NP nP^2 element
