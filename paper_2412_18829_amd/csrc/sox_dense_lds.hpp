@@ -33,6 +33,9 @@
 
 namespace sox {
 
+typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
 struct DenseLdsArgs {
   const float* A;
   const float* B;
@@ -46,10 +49,12 @@ struct DenseLdsArgs {
   long sA, sB, sC;      // batch strides (elements; blockIdx.y is the batch)
   int tiles_m, tiles_n;
   int tpw;              // output tiles per workgroup (set by the launcher)
+  int vec;              // vector stores allowed (set by the launcher)
   double* C64 = nullptr;  // float64 output instead of C (same offsets)
   int accumulate = 0;     // float64 output only: C64 += result
 };
 
+template <bool MULTI>
 __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p) {
   // [buffer][plane: A rows, B rows][row * 4 + swizzled segment]
   __shared__ u32x4 lds[kLdsBufs][2][kLdsPieces];
@@ -58,7 +63,7 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
   const long ntiles = (long)p.tiles_m * p.tiles_n;
   const long nwg = gridDim.x;
   const long wid = xcd_remap(blockIdx.x, gridDim.x);
-  const int ntl = (int)((ntiles - wid + nwg - 1) / nwg);
+  const int ntl = MULTI ? (int)((ntiles - wid + nwg - 1) / nwg) : 1;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15;
@@ -103,12 +108,16 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
     global_to_lds16(srca[1] + ko, &lds[b][0][c1]);
     global_to_lds16(srcb[0] + ko, &lds[b][1][c0]);
     global_to_lds16(srcb[1] + ko, &lds[b][1][c1]);
-    if (cs + 1 < nst) {
-      ++cs;
-      if (++ck == KC) {
-        ck = 0;
-        set_src(wid + ++ct * nwg);
+    if constexpr (MULTI) {
+      if (cs + 1 < nst) {
+        ++cs;
+        if (++ck == KC) {
+          ck = 0;
+          set_src(wid + ++ct * nwg);
+        }
       }
+    } else {
+      ck += ck + 1 < KC ? 1 : 0;  // a select: the stage stays one basic block
     }
   };
   auto frags = [&](int b, f32x4* fa, f32x4* fb) {
@@ -129,37 +138,72 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
 #pragma unroll
       for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = mfma16x16x4(fa[i][m], fb[j][m], acc[i][j]);
+        for (int j = 0; j < 4; ++j) acc[i][j] = mfma16x16x4(fb[j][m], fa[i][m], acc[i][j]);
   };
   // stores local tile tl and clears the accumulators for the next tile
   auto store_tile = [&](int tl) {
     const long tile = wid + tl * nwg;
     const int M0 = (int)(tile % p.tiles_m) * kLdsTile, N0 = (int)(tile / p.tiles_m) * kLdsTile;
     const int Rw = M0 + (wave >> 1) * 64, Cw = N0 + (wave & 1) * 64;
+    // B rows are the MFMA's first operand, so lane (li, g) holds columns
+    // 4 g .. 4 g + 3 of row li of each 16 x 16 tile: one 16-byte (float32),
+    // two 8-byte (bf16 hi, lo) or two 16-byte (float64) stores per tile
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < 4; ++i) {
+      const int row = Rw + 16 * i + li;
+      const int grp = row / p.rgroup, rin = row - grp * p.rgroup;
+      if (row >= p.M || rin >= p.rvalid) continue;
+      const long base = bat * p.sC + (long)grp * p.c_gstride + (long)rin * p.ldc;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = Rw + 16 * i + 4 * g + r;
-        const int grp = row / p.rgroup, rin = row - grp * p.rgroup;
-        if (row >= p.M || rin >= p.rvalid) continue;
-        const long base = bat * p.sC + (long)grp * p.c_gstride + (long)rin * p.ldc;
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int col = Cw + 16 * j + li;
-          if (col >= p.N) continue;
-          const float x = acc[i][j][r];
+      for (int j = 0; j < 4; ++j) {
+        const int col = Cw + 16 * j + 4 * g;
+        if (col >= p.N) continue;
+        const f32x4 x = acc[i][j];
+        if (p.vec && col + 3 < p.N) {
           if (p.Chi) {
-            const bf16_t hgh = f32_to_bf16(x);
-            p.Chi[base + col] = hgh;
-            p.Clo[base + col] = f32_to_bf16(x - bf16_to_f32(hgh));
+            bf16_t h[4], l[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              h[r] = f32_to_bf16(x[r]);
+              l[r] = f32_to_bf16(x[r] - bf16_to_f32(h[r]));
+            }
+            u32x2 vh, vl;
+            vh[0] = h[0] | ((unsigned)h[1] << 16);
+            vh[1] = h[2] | ((unsigned)h[3] << 16);
+            vl[0] = l[0] | ((unsigned)l[1] << 16);
+            vl[1] = l[2] | ((unsigned)l[3] << 16);
+            *(u32x2*)(p.Chi + base + col) = vh;
+            *(u32x2*)(p.Clo + base + col) = vl;
           } else if (p.C64) {
-            p.C64[base + col] = p.accumulate ? p.C64[base + col] + (double)x : (double)x;
+            f64x2* d = (f64x2*)(p.C64 + base + col);
+            f64x2 lo, hi;
+            lo[0] = x[0]; lo[1] = x[1]; hi[0] = x[2]; hi[1] = x[3];
+            if (p.accumulate) {
+              lo += d[0];
+              hi += d[1];
+            }
+            d[0] = lo;
+            d[1] = hi;
           } else {
-            p.C[base + col] = x;
+            *(f32x4*)(p.C + base + col) = x;
+          }
+          continue;
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          if (col + r >= p.N) continue;
+          if (p.Chi) {
+            const bf16_t hgh = f32_to_bf16(x[r]);
+            p.Chi[base + col + r] = hgh;
+            p.Clo[base + col + r] = f32_to_bf16(x[r] - bf16_to_f32(hgh));
+          } else if (p.C64) {
+            p.C64[base + col + r] = p.accumulate ? p.C64[base + col + r] + (double)x[r] : (double)x[r];
+          } else {
+            p.C[base + col + r] = x[r];
           }
         }
       }
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -183,30 +227,34 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
   int b1 = 1;  // buffer of stage s + 1
   auto next = [](int x) { return x + 1 == kLdsBufs ? 0 : x + 1; };
   auto back2 = [](int x) { return x >= 2 ? x - 2 : x + kLdsBufs - 2; };
-  int kk = 0, tl = 0;  // chunk and tile of the stage under the MFMAs
-  for (int st = 0; st < nst; st += 2) {
+  // Stages run in pairs (fragments of the first in fa0/fb0, of the second in
+  // fa1/fb1) with no branch inside a pair, so the accumulators and fragments
+  // keep their registers around the loop; an odd K ends with one more stage
+  // (the launcher gives a workgroup several tiles only for an even number
+  // of stages, so every tile starts on fa0/fb0).
+  auto stage_a = [&]() {
     copy_stage(back2(b1));
     frags(b1, fa1, fb1);
     mfma_stage(fa0, fb0);
-    if (++kk == KC) {
-      store_tile(tl++);
-      kk = 0;
-    }
     wait_vm<8>();
     barrier_nofence();
     b1 = next(b1);
-    if (st + 1 < nst) {
-      copy_stage(back2(b1));
-      frags(b1, fa0, fb0);
-      mfma_stage(fa1, fb1);
-      if (++kk == KC) {
-        store_tile(tl++);
-        kk = 0;
-      }
-      wait_vm<8>();
-      barrier_nofence();
-      b1 = next(b1);
+  };
+  auto stage_b = [&]() {
+    copy_stage(back2(b1));
+    frags(b1, fa0, fb0);
+    mfma_stage(fa1, fb1);
+    wait_vm<8>();
+    barrier_nofence();
+    b1 = next(b1);
+  };
+  for (int tl = 0; tl < ntl; ++tl) {
+    for (int kp = 0; kp < KC / 2; ++kp) {
+      stage_a();
+      stage_b();
     }
+    if (KC & 1) stage_a();
+    store_tile(tl);
   }
   wait_vm<0>();  // the repeated copies past the end
 }
@@ -218,21 +266,35 @@ inline hipError_t launch_dense_lds_f32(DenseLdsArgs a, int batch, hipStream_t s,
   if (a.K % 16 != 0 || a.K <= 0 || a.rgroup <= 0 || (a.Chi && !a.Clo) ||
       (!a.Chi && !a.C && !a.C64) || (a.accumulate && !a.C64))
     return hipErrorInvalidValue;
+  // vector stores of four consecutive columns: every row start a multiple of
+  // four elements and the output 16-byte aligned
+  {
+    const uintptr_t out = a.Chi ? (uintptr_t)a.Chi | (uintptr_t)a.Clo
+                                : a.C64 ? (uintptr_t)a.C64 : (uintptr_t)a.C;
+    const long esz = a.Chi ? 2 : a.C64 ? 8 : 4;
+    a.vec = (a.ldc % 4 == 0 && a.c_gstride % 4 == 0 && a.sC % 4 == 0 && out % (4 * esz < 16 ? 4 * esz : 16) == 0) ? 1 : 0;
+  }
   a.tiles_m = (a.M + kLdsTile - 1) / kLdsTile;
   a.tiles_n = (a.N + kLdsTile - 1) / kLdsTile;
   const long ntiles = (long)a.tiles_m * a.tiles_n;
-  // short K (at most 8 stages): several tiles per workgroup, so that the
+  // short K (at most 8 stages, an even number): several tiles per workgroup, so that the
   // grid holds at most wg_target workgroups (all resident at once) and a
   // workgroup's copies for its next tile overlap its current tile.  Longer
   // K (or wg_target 0): one tile per workgroup (with 13 stages, C = 20800 x
   // 266240, the shared workgroups measured 4% slower: each tile's stores
   // hold up the next wait)
   long per = 1;
-  if (wg_target > 0 && a.K <= 128) per = (ntiles * batch + wg_target - 1) / wg_target;
+  if (wg_target > 0 && a.K <= 128 && a.K % 32 == 0)
+    per = (ntiles * batch + wg_target - 1) / wg_target;
   a.tpw = (int)(per < 1 ? 1 : per > ntiles ? ntiles : per);
   const long nb = (ntiles + a.tpw - 1) / a.tpw;
   if (nb > (1L << 31) - 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(dense_lds_f32_kernel, dim3((unsigned)nb, (unsigned)batch), dim3(256), 0, s, a);
+  if (a.tpw > 1)
+    hipLaunchKernelGGL(dense_lds_f32_kernel<true>, dim3((unsigned)nb, (unsigned)batch), dim3(256),
+                       0, s, a);
+  else
+    hipLaunchKernelGGL(dense_lds_f32_kernel<false>, dim3((unsigned)nb, (unsigned)batch), dim3(256),
+                       0, s, a);
   return hipGetLastError();
 }
 
