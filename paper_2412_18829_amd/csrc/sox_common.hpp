@@ -60,10 +60,10 @@ __device__ __forceinline__ void barrier_nofence() {
   asm volatile("" ::: "memory");
 }
 
-// Round-to-nearest-even float32 -> bfloat16 (finite inputs) and back.
+// Round-to-nearest-even float32 -> bfloat16 (one v_cvt_pk_bf16_f32 on
+// gfx950) and back.
 __device__ __forceinline__ bf16_t f32_to_bf16(float x) {
-  const unsigned u = __float_as_uint(x);
-  return (bf16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+  return __builtin_bit_cast(bf16_t, (__bf16)x);
 }
 __device__ __forceinline__ float bf16_to_f32(bf16_t h) { return __uint_as_float((unsigned)h << 16); }
 
