@@ -962,7 +962,7 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
         ift.Ahi = (bf16_t*)Adyn;
         ift.Alo = ift.Ahi + (long)nt * vc * NP * nP;
       }
-      SOX_HIP((launch_gemm<IFTProb<T>, double, 2, 2, 2, 2>(ift, 1, s)));
+      SOX_HIP(launch_ift<T>(ift, p.n_cu, s));
     }
     FusedArgs<T> fa;
     fa.A = Adyn;
@@ -1338,7 +1338,7 @@ sox_status run_vjp_dynamic(sox_plan& p, const double* X, const double* Wtau, con
     SOX_HIP((launch_gemm<FTProb<T>, double, 1, 4, 5, 1>(ft, 1, s)));
     if ((st = launch_wgg<T>(W2, GG2, AW, NP, vcn, nw, s))) return st;
     IFTProb<T> ift{p.d_tb2, AW, Adyn, n, nP, NP, nw, nt, vc, nt, NP * vc * nP, 2 * nw};
-    SOX_HIP((launch_gemm<IFTProb<T>, double, 2, 2, 2, 2>(ift, 1, s)));
+    SOX_HIP(launch_ift<T>(ift, p.n_cu, s));
     if ((st = launch_transpose<T>(Adyn, AdynT, NP, nP, (long)nt * vc, s))) return st;
     // Hadamard-contract adjoints with B^v = A^v X
     HcArgs<T, double> h{};

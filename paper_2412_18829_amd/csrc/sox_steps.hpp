@@ -354,6 +354,129 @@ template <typename T> struct IFTProb {
   }
 };
 
+// Inverse transform with the transform matrix held stationary: the rows
+// tau < 128 of Tb2 (K = 2 n_omega <= kIftKmax, zero padded to a multiple of
+// 16) sit in LDS for the whole launch.  Wavefront w of a workgroup takes the
+// 64-row slab w % 2 and walks column groups (32 output columns: two blocks
+// of 16 consecutive u of one (P, v)) together with the other slab's
+// wavefront, so each AW value is fetched from memory once.  float64 MFMA
+// and accumulation as in the generic product, 16 k per chunk (lane g takes
+// k = 16 s + 4 g + m in step m of both operands); the AW values of the next
+// two chunks are in flight while a chunk's MFMAs run.
+constexpr int kIftKmax = 96;
+constexpr int kIftJB = 2;  // 16-column blocks per wavefront
+
+template <typename T>
+__global__ __launch_bounds__(512) void ift_kernel(const IFTProb<T> q, long ngroups) {
+  __shared__ double tb[128][kIftKmax + 2];
+  const int K = q.K, Kp = (K + 15) & ~15;
+  for (int e = threadIdx.x; e < 128 * Kp; e += blockDim.x) {
+    const int r = e / Kp, k = e - (e / Kp) * Kp;
+    tb[r][k] = (r < q.M && k < K) ? q.Tb2[(long)r * K + k] : 0.0;
+  }
+  __syncthreads();
+  constexpr int JB = kIftJB;
+  const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  const int wave = threadIdx.x >> 6;
+  const int r0 = 64 * (wave & 1);
+  const int nP16 = q.nP / 16;
+  const long nblk = (long)q.NP * q.vc * nP16;
+  const long vcn = (long)q.vc * q.n;
+  const int nch = Kp / 16;
+  for (long grp = (long)blockIdx.x * 4 + (wave >> 1); grp < ngroups; grp += (long)gridDim.x * 4) {
+    // the lane's column in block j: u = 16 ub + li of (P, vl)
+    const T* src[JB];
+    int ok[JB], vlj[JB], Pj[JB], uj[JB];
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+      const long blk = grp * JB + j;
+      const int ub = (int)(blk % nP16);
+      const long pv = blk / nP16;
+      vlj[j] = (int)(pv % q.vc);
+      Pj[j] = (int)(pv / q.vc);
+      uj[j] = 16 * ub + li;
+      ok[j] = blk < nblk && uj[j] < q.n;
+      src[j] = q.AW + (ok[j] ? (long)Pj[j] * vcn + (long)vlj[j] * q.n + uj[j] : 0);
+    }
+    auto load_b = [&](int ch, T (*b)[4]) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int k = 16 * ch + 4 * g + m;
+        const int c = k / q.n_omega, mm = k - (k / q.n_omega) * q.n_omega;
+        const long koff = ((long)mm * 2 * q.NP + (long)c * q.NP) * vcn;
+#pragma unroll
+        for (int j = 0; j < JB; ++j)
+          b[j][m] = (ok[j] && k < K && ch < nch) ? src[j][koff] : T(0);
+      }
+    };
+    f64x4 acc[4][JB];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < JB; ++j) acc[i][j] = zero4<double>();
+    T b0[JB][4], b1[JB][4], b2[JB][4];
+    load_b(0, b0);
+    load_b(1, b1);
+    for (int ch = 0; ch < nch; ++ch) {
+      load_b(ch + 2, b2);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        double a[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) a[i] = tb[r0 + 16 * i + li][16 * ch + 4 * g + m];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < JB; ++j) acc[i][j] = mfma16x16x4(a[i], double(b0[j][m]), acc[i][j]);
+      }
+#pragma unroll
+      for (int j = 0; j < JB; ++j)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          b0[j][m] = b1[j][m];
+          b1[j][m] = b2[j][m];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+      if (grp * JB + j >= nblk) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int t = r0 + 16 * i + acc_row<double>(g, r);
+          if (t >= q.M) continue;
+          const long o = (((long)t * q.vc + vlj[j]) * q.NP + Pj[j]) * q.nP + uj[j];
+          const double v = acc[i][j][r];
+          if (q.Ahi) {
+            const float x = (float)v;
+            const bf16_t h = f32_to_bf16(x);
+            q.Ahi[o] = h;
+            q.Alo[o] = f32_to_bf16(x - bf16_to_f32(h));
+          } else {
+            q.Adyn[o] = T(v);
+          }
+        }
+    }
+  }
+}
+
+// The inverse transform: the stationary kernel above when n_tau <= 128 and
+// 2 n_omega <= kIftKmax, else the generic product.
+template <typename T>
+inline hipError_t launch_ift(const IFTProb<T>& q, int n_cu, hipStream_t s) {
+  if (q.M <= 128 && q.K <= kIftKmax && q.nP % 16 == 0) {
+    const long nblk = (long)q.NP * q.vc * (q.nP / 16);
+    const long ngroups = (nblk + kIftJB - 1) / kIftJB;
+    long nwg = (ngroups + 3) / 4;
+    if (nwg > 4L * n_cu) nwg = 4L * n_cu;
+    if (nwg < 1) return hipSuccess;
+    hipLaunchKernelGGL(ift_kernel<T>, dim3((unsigned)nwg), dim3(512), 0, s, q, ngroups);
+    return hipGetLastError();
+  }
+  return launch_gemm<IFTProb<T>, double, 2, 2, 2, 2>(q, 1, s);
+}
+
 // ---------------------------------------------------------------------------
 // G(tau) synthesis (eq:G_def, one-body Hamiltonian), float64:
 //   occ[k][a] = n(eps_a, tau_k);  G[k][p][q] = -sum_a Q[p][a] occ[k][a] Q[q][a]
