@@ -949,7 +949,7 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
                    nullptr, 0, 1};
       // 80-row tiles: all 2 n_Omega rows (72 at n_Omega = 36) in one tile, so
       // each GG column is formed once (C4: 279 -> 204 ms against 64-row tiles)
-      SOX_HIP((launch_gemm<FTProb<T>, double, 1, 4, 5, 1>(ft, 1, s)));
+      SOX_HIP(launch_ft<T>(ft, p.n_cu, s));
     }
     {
       ProfScope ps(p, SOX_STAGE_WGEMM, s);

@@ -301,6 +301,128 @@ template <typename T> struct FTProb {
   }
 };
 
+// Forward transform with the transform matrix held stationary (the
+// qmajor layout, no adjoint copy): the rows of Tf2 (2 n_omega <= 80) over
+// K = n_tau <= kFtKmax nodes (zero padded to a multiple of 16) sit in LDS
+// for the whole launch.  A wavefront owns all rows of kFtJB column blocks
+// that share u and the 16 THC points Q = 16 qb + lane % 16 and differ in v,
+// so each G_uQ(tau_j) value is loaded once for the kFtJB blocks; groups run
+// with v fastest, then qb, then u, so the wavefronts resident at one time
+// reuse the same G_uQ and G_Qv rows from the cache.  The GG column values
+// are formed in registers (two float64 loads and a product), float64 MFMA
+// and accumulation, 16 k per chunk, the next chunk's loads in flight.
+constexpr int kFtKmax = 128;
+constexpr int kFtJB = 1;
+
+template <typename T>
+__global__ __launch_bounds__(512) void ft_kernel(const FTProb<T> q, long ngroups) {
+  __shared__ double tf[80][kFtKmax + 2];
+  const int K = q.n_tau, Kp = (K + 15) & ~15;
+  for (int e = threadIdx.x; e < 80 * Kp; e += blockDim.x) {
+    const int r = e / Kp, k = e - (e / Kp) * Kp;
+    tf[r][k] = (r < q.M && k < K) ? q.Tf2[(long)r * K + k] : 0.0;
+  }
+  __syncthreads();
+  constexpr int JB = kFtJB;
+  const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  const int wave = threadIdx.x >> 6;
+  const int nqb = q.NP / 16;
+  const int nvp = (q.vc + JB - 1) / JB;
+  const long st = (long)q.NP * q.nP;
+  const int nch = Kp / 16;
+  const int nwaves = blockDim.x >> 6;
+  for (long grp = (long)blockIdx.x * nwaves + wave; grp < ngroups;
+       grp += (long)gridDim.x * nwaves) {
+    const int vp = (int)(grp % nvp);
+    const long rest = grp / nvp;
+    const int qb = (int)(rest % nqb);
+    const int u = (int)(rest / nqb);
+    const int Q = 16 * qb + li;
+    const bool qok = Q < q.Nthc;
+    int vl[JB];
+    bool vok[JB];
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+      vl[j] = JB * vp + j;
+      vok[j] = qok && vl[j] < q.vc && q.v0 + vl[j] < q.n;
+    }
+    // G_uQ(tau_k) and G_Qv(beta - tau_k) of chunk ch (zero past K or outside)
+    auto load = [&](int ch, double* gu, double (*gv)[4]) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int k = 16 * ch + 4 * g + m;
+        const bool kok = ch < nch && k < K;
+        gu[m] = (qok && kok) ? q.P2T[k * st + (long)u * q.NP + Q] : 0.0;
+#pragma unroll
+        for (int j = 0; j < JB; ++j)
+          gv[j][m] = (vok[j] && kok)
+                         ? q.P1[(long)(K - 1 - k) * st + (long)(q.v0 + vl[j]) * q.NP + Q]
+                         : 0.0;
+      }
+    };
+    f64x4 acc[5][JB];
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+      for (int j = 0; j < JB; ++j) acc[i][j] = zero4<double>();
+    double u0[4], u1[4], w0[JB][4], w1[JB][4];
+    load(0, u0, w0);
+    for (int ch = 0; ch < nch; ++ch) {
+      load(ch + 1, u1, w1);
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        double a[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) a[i] = tf[16 * i + li][16 * ch + 4 * g + m];
+#pragma unroll
+        for (int j = 0; j < JB; ++j) {
+          const double b = u0[m] * w0[j][m];
+#pragma unroll
+          for (int i = 0; i < 5; ++i) acc[i][j] = mfma16x16x4(a[i], b, acc[i][j]);
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        u0[m] = u1[m];
+#pragma unroll
+        for (int j = 0; j < JB; ++j) w0[j][m] = w1[j][m];
+      }
+    }
+    // GG2[m][vl n + u][c NP + Q], rows r = c n_omega + m (padded Q stored as 0)
+#pragma unroll
+    for (int j = 0; j < JB; ++j) {
+      if (vl[j] >= q.vc) continue;
+      const long vu = (long)vl[j] * q.n + u;
+#pragma unroll
+      for (int i = 0; i < 5; ++i)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int row = 16 * i + acc_row<double>(g, r);
+          if (row >= q.M) continue;
+          const int c = row / q.n_omega, mm = row - (row / q.n_omega) * q.n_omega;
+          q.GG2[((long)mm * q.vc * q.n + vu) * (2L * q.NP) + (long)c * q.NP + Q] =
+              T(acc[i][j][r]);
+        }
+    }
+  }
+}
+
+// The forward transform: the stationary kernel above for the qmajor layout
+// without the adjoint copy when 2 n_omega <= 80 and n_tau <= kFtKmax, else
+// the generic product with 80-row tiles.
+template <typename T>
+inline hipError_t launch_ft(const FTProb<T>& q, int n_cu, hipStream_t s) {
+  if (q.qmajor && !q.GG2T && q.M <= 80 && q.n_tau <= kFtKmax && q.NP % 16 == 0) {
+    const long ngroups = (long)q.n * (q.NP / 16) * ((q.vc + kFtJB - 1) / kFtJB);
+    long nwg = (ngroups + 7) / 8;
+    if (nwg > 4L * n_cu) nwg = 4L * n_cu;
+    if (nwg < 1) return hipSuccess;
+    hipLaunchKernelGGL(ft_kernel<T>, dim3((unsigned)nwg), dim3(512), 0, s, q, ngroups);
+    return hipGetLastError();
+  }
+  return launch_gemm<FTProb<T>, double, 1, 4, 5, 1>(q, 1, s);
+}
+
 // Inverse transform into the fused kernel's A layout for the v-slab:
 //   Adyn[tau][vl][P][u] = sum_k Tb2[tau][k] AW[m][c NP + P][vl n + u],  k = c n_omega + m
 // (u >= n is padding and written as zero).
