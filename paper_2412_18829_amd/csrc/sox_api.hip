@@ -186,6 +186,7 @@ struct Layout {
 struct DynLayout {
   size_t p1d, p2td, p1q, p2q, p2t, xt, u2, w2, gg2, aw, adyn, d, e, ukr, xp, d64, total;
   size_t xth, xtl, p2h, p2l, u2h, u2l;  // bf16 x 3 split operands of the fused contraction
+  size_t w2h, w2l;                      // bf16 x 3 split W(Omega)
 };
 
 size_t elem_size(int precision) { return precision == SOX_FP64 ? 8 : 4; }
@@ -273,6 +274,7 @@ DynLayout dyn_layout_for(const sox_plan& p, int vc, int eslab) {
     L.xth = c.take(NP * nP * 2); L.xtl = c.take(NP * nP * 2);
     L.p2h = c.take(nt * NP * nP * 2); L.p2l = c.take(nt * NP * nP * 2);
     L.u2h = c.take(NP * nP * nP * 2); L.u2l = c.take(NP * nP * nP * 2);
+    L.w2h = c.take(nw * 4 * NP * NP * 2); L.w2l = c.take(nw * 4 * NP * NP * 2);
   }
   L.total = c.off;
   return L;
@@ -939,6 +941,10 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
     ProfScope ps(p, SOX_STAGE_GG_FT, s);
     WOmegaProb<T> wp{p.d_tf2, Wtau, W2, nw, nt, N, NP, 2 * nw, NP * NP, nt, W2T};
     SOX_HIP((launch_gemm<WOmegaProb<T>, double, 2, 2, 2, 2>(wp, 1, s)));
+    // split precision: W(Omega) as bf16 hi/lo planes for the W GG product
+    if (split && (st = launch_split((const float*)W2, (bf16_t*)(base + L.w2h),
+                                    (bf16_t*)(base + L.w2l), (long)nw * 4 * NP * NP, s)))
+      return st;
   }
   const int tiles_p = NP / (2 * fc.wp), tiles_r = NP / (2 * fc.wr);
   for (int v0 = 0; v0 < n; v0 += vcw) {
@@ -947,13 +953,31 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
       ProfScope ps(p, SOX_STAGE_GG_FT, s);
       FTProb<T> ft{p.d_tf2, P1q, P2q, GG2, n, nP, NP, N, nw, nt, v0, vc, 2 * nw, vc * n * NP, nt,
                    nullptr, 0, 1};
+      if (split) {  // GG(Omega) as hi and lo planes in the GG2 buffer
+        ft.GGhi = (bf16_t*)GG2;
+        ft.GGlo = ft.GGhi + (long)nw * vc * n * 2 * NP;
+      }
       // 80-row tiles: all 2 n_Omega rows (72 at n_Omega = 36) in one tile, so
       // each GG column is formed once (C4: 279 -> 204 ms against 64-row tiles)
       SOX_HIP(launch_ft<T>(ft, p.n_cu, s));
     }
     {
       ProfScope ps(p, SOX_STAGE_WGEMM, s);
-      if ((st = launch_wgg<T>(W2, GG2, AW, NP, (long)vc * n, nw, s))) return st;
+      if (split) {
+        const long vcn = (long)vc * n;
+        DenseLdsSplitArgs l{};
+        l.Ah = (const bf16_t*)(base + L.w2h);
+        l.Al = (const bf16_t*)(base + L.w2l);
+        l.Bh = (const bf16_t*)GG2;
+        l.Bl = l.Bh + (long)nw * vcn * 2 * NP;
+        l.C = (float*)AW;
+        l.lda = 2L * NP; l.ldb = 2L * NP; l.ldc = vcn;
+        l.sA = 4L * NP * NP; l.sB = vcn * 2 * NP; l.sC = 2L * NP * vcn;
+        l.M = 2 * NP; l.N = (int)vcn; l.K = 2 * NP;
+        SOX_HIP(launch_dense_lds_bf16x3(l, nw, s));
+      } else if ((st = launch_wgg<T>(W2, GG2, AW, NP, (long)vc * n, nw, s))) {
+        return st;
+      }
     }
     {
       ProfScope ps(p, SOX_STAGE_IFT, s);

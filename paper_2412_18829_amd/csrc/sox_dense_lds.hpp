@@ -259,6 +259,155 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
   wait_vm<0>();  // the repeated copies past the end
 }
 
+// The same NT product with both operands given as bf16 hi and lo planes
+// (x = hi + lo) on the 16x16x32 bf16 MFMA, hi hi + hi lo + lo hi with
+// float32 accumulation: C[row][col] = sum_k A[row][k] B[col][k] in float32.
+// One 128 x 128 block of C per workgroup; a stage is 32 k (64 bytes per row
+// and plane), four planes per stage (B hi, B lo, A hi, A lo) in the ring of
+// five buffers (160 KB of LDS); K a multiple of 32.  W(Omega) GG(Omega) of
+// the split-precision dynamic entry.
+struct DenseLdsSplitArgs {
+  const bf16_t* Ah;
+  const bf16_t* Al;
+  const bf16_t* Bh;
+  const bf16_t* Bl;
+  long lda, ldb, ldc;  // row strides (elements)
+  long sA, sB, sC;     // batch strides (elements; blockIdx.y is the batch)
+  int M, N, K;
+  float* C;
+  int tiles_m, tiles_n;
+  int vec;  // 16-byte stores allowed (set by the launcher)
+};
+
+__global__ __launch_bounds__(256) void dense_lds_bf16x3_kernel(const DenseLdsSplitArgs p) {
+  constexpr int MODE = kLdsBf16x3;
+  // [buffer][plane: B rows hi, lo (first MFMA operand), A rows hi, lo][row * 4 + swizzled segment]
+  __shared__ u32x4 lds[kLdsBufs][4][kLdsPieces];
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int M0 = (bid % p.tiles_m) * kLdsTile;  // row blocks fastest: they share B
+  const int N0 = (bid / p.tiles_m) * kLdsTile;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15;
+  const int g = lane >> 4;
+  const long bat = blockIdx.y;
+  const char* srcb[2][2];  // [plane][copy]
+  const char* srca[2][2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int c = wave + 4 * h;
+    const int row = 16 * c + (lane >> 2);
+    const int seg = (lane & 3) ^ ((row >> 1) & 3);
+    const long ra = M0 + row < p.M ? M0 + row : p.M - 1;
+    const long rb = N0 + row < p.N ? N0 + row : p.N - 1;
+    const long oa = bat * p.sA + ra * p.lda, ob = bat * p.sB + rb * p.ldb;
+    srca[0][h] = (const char*)(p.Ah + oa) + 16 * seg;
+    srca[1][h] = (const char*)(p.Al + oa) + 16 * seg;
+    srcb[0][h] = (const char*)(p.Bh + ob) + 16 * seg;
+    srcb[1][h] = (const char*)(p.Bl + ob) + 16 * seg;
+  }
+  // fragments: first operand B rows (wave & 1) 64 + 16 i, second A rows (wave >> 1) 64 + 16 j
+  int sb[4], sa[4];
+  const int sw = g ^ ((li >> 1) & 3);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    sb[i] = ((wave & 1) * 64 + 16 * i + li) * 4 + sw;
+    sa[i] = ((wave >> 1) * 64 + 16 * i + li) * 4 + sw;
+  }
+  const int KC = p.K / 32;
+  const int c0 = 64 * wave, c1 = 64 * (wave + 4);
+  int ck = 0;  // next chunk to copy, held at the last one past the end
+  auto copy_stage = [&](int b) {
+    const long ko = (long)ck * 64;
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      global_to_lds16(srcb[q][0] + ko, &lds[b][q][c0]);
+      global_to_lds16(srcb[q][1] + ko, &lds[b][q][c1]);
+      global_to_lds16(srca[q][0] + ko, &lds[b][2 + q][c0]);
+      global_to_lds16(srca[q][1] + ko, &lds[b][2 + q][c1]);
+    }
+    ck += ck + 1 < KC ? 1 : 0;
+  };
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = zero4<float>();
+  typename LdsMode<MODE>::Frags f0, f1;
+  auto next = [](int x) { return x + 1 == kLdsBufs ? 0 : x + 1; };
+  auto back2 = [](int x) { return x >= 2 ? x - 2 : x + kLdsBufs - 2; };
+  // the schedule of the float32 kernel: copy stage s + 4 into the buffer of
+  // stage s - 1, read the fragments of stage s + 1, MFMAs of stage s, wait
+  // for the own copies of stage s + 2 (eight per stage), barrier
+  copy_stage(0);
+  copy_stage(1);
+  copy_stage(2);
+  copy_stage(3);
+  wait_vm<16>();
+  barrier_nofence();
+  lds_frags<MODE, 2>(lds[0], sb, sa, f0);
+  int b1 = 1;
+  auto stage_a = [&]() {
+    copy_stage(back2(b1));
+    lds_frags<MODE, 2>(lds[b1], sb, sa, f1);
+    lds_half_mfma<MODE, false>(f0, acc);
+    wait_vm<16>();
+    barrier_nofence();
+    b1 = next(b1);
+  };
+  auto stage_b = [&]() {
+    copy_stage(back2(b1));
+    lds_frags<MODE, 2>(lds[b1], sb, sa, f0);
+    lds_half_mfma<MODE, false>(f1, acc);
+    wait_vm<16>();
+    barrier_nofence();
+    b1 = next(b1);
+  };
+  for (int kp = 0; kp < KC / 2; ++kp) {
+    stage_a();
+    stage_b();
+  }
+  if (KC & 1) stage_a();
+  wait_vm<0>();  // the repeated copies past the end
+
+  // lane (li, g) holds C[row 16 j + li][columns 16 i + 4 g .. + 3]
+  const int Rw = M0 + (wave >> 1) * 64, Cw = N0 + (wave & 1) * 64;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int row = Rw + 16 * j + li;
+    if (row >= p.M) continue;
+    float* crow = p.C + bat * p.sC + (long)row * p.ldc;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int col = Cw + 16 * i + 4 * g;
+      if (col >= p.N) continue;
+      if (p.vec && col + 3 < p.N) {
+        *(f32x4*)(crow + col) = acc[i][j];
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (col + r < p.N) crow[col + r] = acc[i][j][r];
+      }
+    }
+  }
+}
+
+inline hipError_t launch_dense_lds_bf16x3(DenseLdsSplitArgs a, int batch, hipStream_t s) {
+  if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;
+  if (batch > 65535 || a.K % 32 != 0 || a.K <= 0 || !a.Ah || !a.Al || !a.Bh || !a.Bl || !a.C)
+    return hipErrorInvalidValue;
+  // 16-byte panel rows: row strides and batch strides multiples of 8 bf16
+  if (a.lda % 8 || a.ldb % 8 || a.sA % 8 || a.sB % 8) return hipErrorInvalidValue;
+  a.vec = (a.ldc % 4 == 0 && a.sC % 4 == 0 && (uintptr_t)a.C % 16 == 0) ? 1 : 0;
+  a.tiles_m = (a.M + kLdsTile - 1) / kLdsTile;
+  a.tiles_n = (a.N + kLdsTile - 1) / kLdsTile;
+  const long nb = (long)a.tiles_m * a.tiles_n;
+  if (nb > (1L << 31) - 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(dense_lds_bf16x3_kernel, dim3((unsigned)nb, (unsigned)batch), dim3(256), 0, s,
+                     a);
+  return hipGetLastError();
+}
+
 inline hipError_t launch_dense_lds_f32(DenseLdsArgs a, int batch, hipStream_t s,
                                       long wg_target = 0) {
   if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;

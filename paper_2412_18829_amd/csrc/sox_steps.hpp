@@ -261,6 +261,19 @@ template <typename T> struct FTProb {
   // contiguous), so the lanes of a load instruction, which run over Q, read
   // consecutive addresses
   int qmajor = 0;
+  // split precision: GG2 stored as bf16 hi and lo planes (same layout)
+  bf16_t* GGhi = nullptr;
+  bf16_t* GGlo = nullptr;
+  __device__ void put(long o, double v) const {
+    if (GGhi) {
+      const float x = (float)v;
+      const bf16_t h = f32_to_bf16(x);
+      GGhi[o] = h;
+      GGlo[o] = f32_to_bf16(x - bf16_to_f32(h));
+    } else {
+      GG2[o] = T(v);
+    }
+  }
   __device__ f64x4 loadA4(int, int row, int j) const {
     if (row >= M) return zero4<double>();
     return load4_strided<double>(Tf2 + (long)row * n_tau, 1, j, n_tau);
@@ -296,7 +309,7 @@ template <typename T> struct FTProb {
   __device__ void store(int, int row, int col, double v) const {
     const int c = row / n_omega, m = row - (row / n_omega) * n_omega;
     const int Q = col % NP, vu = col / NP;
-    GG2[((long)m * vc * n + vu) * (2L * NP) + (long)c * NP + Q] = T(v);
+    put(((long)m * vc * n + vu) * (2L * NP) + (long)c * NP + Q, v);
     if (GG2T) GG2T[((long)m * 2 * NP + (long)c * NP + Q) * ldt + vu] = T(v);
   }
 };
@@ -400,8 +413,7 @@ __global__ __launch_bounds__(512) void ft_kernel(const FTProb<T> q, long ngroups
           const int row = 16 * i + acc_row<double>(g, r);
           if (row >= q.M) continue;
           const int c = row / q.n_omega, mm = row - (row / q.n_omega) * q.n_omega;
-          q.GG2[((long)mm * q.vc * q.n + vu) * (2L * q.NP) + (long)c * q.NP + Q] =
-              T(acc[i][j][r]);
+          q.put(((long)mm * q.vc * q.n + vu) * (2L * q.NP) + (long)c * q.NP + Q, acc[i][j][r]);
         }
     }
   }
