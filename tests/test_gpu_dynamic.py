@@ -73,6 +73,27 @@ def test_dynamic_small_general_G(B, precision, shape):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_dynamic_many_tau_nodes_generic_transforms(B, precision):
+    """140 tau nodes: past the 128 rows the transform kernels hold in LDS, so
+    both transforms run on the generic float64 product; parity as above."""
+    n, N, nt, beta = 7, 30, 140, 30.0
+    log(f"dynamic {n} {N} {nt} {precision} (generic transforms)")
+    wl = synth.small_molecule(n, N, nt, beta, seed=901, dynamic=True)
+    tp = _pair(wl)
+    rng = np.random.default_rng(901)
+    G = om.g_tau(wl["eps"], wl["Q"], 0.0, beta, wl["tau"]) + 0.05 * rng.standard_normal((nt, n, n))
+    got, _ = _run(B, wl, tp, precision, wl["X"], wl["W_tau"], wl["V"], G)
+    ref = om.sigma_dynamic_thc(wl["X"], wl["W_tau"], wl["V"], G, G[::-1], tp["T_fwd"], tp["T_bwd"])
+    err = rel_err(got, ref)
+    tol = TOL[precision]
+    if precision == "fp64":
+        bf = om.sigma_dynamic_eri(wl["X"], wl["W_tau"], wl["V"], G, G[::-1], tp["T_fwd"], tp["T_bwd"])
+        tol = max(tol, 10.0 * rel_err(bf, ref))
+    log(f"  rel err {err:.3e} (tol {tol:.1e})  n_omega={len(tp['m'])}")
+    assert err <= tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_dynamic_v_slabs_match(B, precision, monkeypatch):
     """A small workspace budget forces several v slabs (D accumulated across
     slabs); the result must match the single-slab run and the oracle."""
