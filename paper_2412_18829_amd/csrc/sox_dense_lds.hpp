@@ -1,5 +1,6 @@
-// LDS-staged float32 NT GEMM for the A step (the copy machinery of the
-// LDS-staged fused kernel, sox_fused_lds.hpp, with one product):
+// LDS-staged float32 NT GEMM for the A step, the U-contraction and
+// W(Omega) GG(Omega) (the copy machinery of the LDS-staged fused kernel,
+// sox_fused_lds.hpp, with one product):
 //
 //   C[row][col] = sum_k A[row][k] * B[col][k]
 //
