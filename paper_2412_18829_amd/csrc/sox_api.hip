@@ -1357,9 +1357,11 @@ sox_status run_vjp_dynamic(sox_plan& p, const double* X, const double* Wtau, con
     // recompute GG(Omega) (both layouts), A(Omega), A(tau) for the slab
     if ((st = launch_fill<T>(GG2T, (long)nw * 2 * NP * ldk, s))) return st;
     if ((st = launch_fill<T>(dAW, (long)nw * 2 * NP * ldk, s))) return st;
-    FTProb<T> ft{p.d_tf2, P1d, P2Td, GG2, n, nP, NP, N, nw, nt, v0, vc, 2 * nw, vc * n * NP, nt,
-                 GG2T, ldk};
-    SOX_HIP((launch_gemm<FTProb<T>, double, 1, 4, 5, 1>(ft, 1, s)));
+    // the forward pass's Q-contiguous copies of P1 and P2^T are still in
+    // the workspace
+    FTProb<T> ft{p.d_tf2, (const double*)(base + F.p1q), (const double*)(base + F.p2q), GG2, n, nP,
+                 NP, N, nw, nt, v0, vc, 2 * nw, vc * n * NP, nt, GG2T, ldk, 1};
+    SOX_HIP(launch_ft<T>(ft, p.n_cu, s));
     if ((st = launch_wgg<T>(W2, GG2, AW, NP, vcn, nw, s))) return st;
     IFTProb<T> ift{p.d_tb2, AW, Adyn, n, nP, NP, nw, nt, vc, nt, NP * vc * nP, 2 * nw};
     SOX_HIP(launch_ift<T>(ift, p.n_cu, s));

@@ -315,7 +315,7 @@ template <typename T> struct FTProb {
 };
 
 // Forward transform with the transform matrix held stationary (the
-// qmajor layout, no adjoint copy): the rows of Tf2 (2 n_omega <= 80) over
+// qmajor layout; the adjoint's transposed copy GG2T too when set): the rows of Tf2 (2 n_omega <= 80) over
 // K = n_tau <= kFtKmax nodes (zero padded to a multiple of 16) sit in LDS
 // for the whole launch.  A wavefront owns all rows of kFtJB column blocks
 // that share u and the 16 THC points Q = 16 qb + lane % 16 and differ in v,
@@ -414,17 +414,19 @@ __global__ __launch_bounds__(512) void ft_kernel(const FTProb<T> q, long ngroups
           if (row >= q.M) continue;
           const int c = row / q.n_omega, mm = row - (row / q.n_omega) * q.n_omega;
           q.put(((long)mm * q.vc * q.n + vu) * (2L * q.NP) + (long)c * q.NP + Q, acc[i][j][r]);
+          if (q.GG2T)
+            q.GG2T[((long)mm * 2 * q.NP + (long)c * q.NP + Q) * q.ldt + vu] = T(acc[i][j][r]);
         }
     }
   }
 }
 
 // The forward transform: the stationary kernel above for the qmajor layout
-// without the adjoint copy when 2 n_omega <= 80 and n_tau <= kFtKmax, else
-// the generic product with 80-row tiles.
+// when 2 n_omega <= 80 and n_tau <= kFtKmax, else the generic product with
+// 80-row tiles.
 template <typename T>
 inline hipError_t launch_ft(const FTProb<T>& q, int n_cu, hipStream_t s) {
-  if (q.qmajor && !q.GG2T && q.M <= 80 && q.n_tau <= kFtKmax && q.NP % 16 == 0) {
+  if (q.qmajor && q.M <= 80 && q.n_tau <= kFtKmax && q.NP % 16 == 0) {
     const long ngroups = (long)q.n * (q.NP / 16) * ((q.vc + kFtJB - 1) / kFtJB);
     long nwg = (ngroups + 7) / 8;
     if (nwg > 4L * n_cu) nwg = 4L * n_cu;
