@@ -111,9 +111,12 @@ def test_dynamic_v_slabs_match(B, precision, monkeypatch):
     assert rel_err(many, one) <= {"fp64": 1e-14, "fp32": 1e-6, "bf16x3": 1e-5}[precision]
 
 
-def test_dynamic_full_size_on_column_subset(B):
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_dynamic_full_size_on_column_subset(B, precision):
     """n=300, N=1800, 120 tau nodes, beta=100, 8 poles: the full launch
-    configuration, checked on a collocation matrix supported on 64 columns."""
+    configuration (in bf16x3 the split W(Omega) GG(Omega) product and the
+    split fused contraction), checked on a collocation matrix supported on 64
+    columns."""
     import torch
     wl = synth.workload(4)
     n, N, nt = wl["n"], wl["N"], wl["n_tau"]
@@ -122,16 +125,16 @@ def test_dynamic_full_size_on_column_subset(B):
     cols = np.sort(rng.choice(N, size=64, replace=False))
     X = np.zeros_like(wl["X"])
     X[:, cols] = wl["X"][:, cols]
-    log(f"dynamic full size, support {len(cols)} columns, n_omega={len(tp['m'])}")
+    log(f"dynamic full size {precision}, support {len(cols)} columns, n_omega={len(tp['m'])}")
     G = om.g_tau(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
-    got, plan = _run(B, wl, tp, "fp32", X, wl["W_tau"], wl["V"], G)
+    got, plan = _run(B, wl, tp, precision, X, wl["W_tau"], wl["V"], G)
     Xs = wl["X"][:, cols]
     Ws = np.ascontiguousarray(wl["W_tau"][:, cols][:, :, cols])
     Vs = wl["V"][np.ix_(cols, cols)]
     ref = om.sigma_dynamic_thc(Xs, Ws, Vs, G, G[::-1], tp["T_fwd"], tp["T_bwd"])
     err = rel_err(got, ref)
     log(f"  rel err {err:.3e}")
-    assert err <= TOL["fp32"]
+    assert err <= TOL[precision]
 
 
 def test_dynamic_requires_transform_pair(B):
