@@ -649,8 +649,9 @@ sox_status launch_split(const float* src, bf16_t* hi, bf16_t* lo, long count, hi
 
 // Back-transform of cnt tau nodes in float64 (THC section): Sigma_RP =
 // -D_PR, E = X D^T, Sigma[t0 + b] = -E X^T, both products on the direct-load
-// float64 MFMA GEMM from the zero-padded XP [n][NP] (float32 D is widened
-// into D64 first; float64 D is read in place).
+// float64 MFMA GEMM from the zero-padded XP [n][NP] (float32 D, summed over
+// its nsplit partial blocks, is widened into D64 first; float64 D is read in
+// place).
 template <typename T>
 sox_status launch_back(const sox_plan& p, const double* XP, const T* D, double* D64, double* E,
                        double* Sigma, int t0, int cnt, hipStream_t s, int nsplit = 1,

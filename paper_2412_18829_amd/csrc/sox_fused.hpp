@@ -19,7 +19,8 @@
 // One workgroup = 4 wavefronts (2 x 2) owns a (2 WP) x (2 WR) block of D for
 // one tau and one range of v (the v sum may be split over several
 // workgroups so that a launch fills whole rounds of the chip; the partial D
-// blocks are then added by dsplit_sum_kernel).  The loops run over v and
+// blocks are summed ahead of the back-transform, by dsplit_sum_kernel in
+// float64 and while D is widened to float64 in float32).  The loops run over v and
 // 16-deep k chunks with the next chunk's operands loaded before the current
 // chunk's MFMAs are issued; the Hadamard epilogue closes each v.
 #pragma once
