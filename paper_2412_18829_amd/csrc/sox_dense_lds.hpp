@@ -36,6 +36,7 @@ namespace sox {
 
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 struct DenseLdsArgs {
   const float* A;
@@ -162,19 +163,11 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
         const f32x4 x = acc[i][j];
         if (p.vec && col + 3 < p.N) {
           if (p.Chi) {
-            bf16_t h[4], l[4];
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              h[r] = f32_to_bf16(x[r]);
-              l[r] = f32_to_bf16(x[r] - bf16_to_f32(h[r]));
-            }
-            u32x2 vh, vl;
-            vh[0] = h[0] | ((unsigned)h[1] << 16);
-            vh[1] = h[2] | ((unsigned)h[3] << 16);
-            vl[0] = l[0] | ((unsigned)l[1] << 16);
-            vl[1] = l[2] | ((unsigned)l[3] << 16);
-            *(u32x2*)(p.Chi + base + col) = vh;
-            *(u32x2*)(p.Clo + base + col) = vl;
+            // four values at once: packed round-to-nearest-even conversions
+            const bf16x4 h = __builtin_convertvector(x, bf16x4);
+            const bf16x4 l = __builtin_convertvector(x - __builtin_convertvector(h, f32x4), bf16x4);
+            *(u32x2*)(p.Chi + base + col) = __builtin_bit_cast(u32x2, h);
+            *(u32x2*)(p.Clo + base + col) = __builtin_bit_cast(u32x2, l);
           } else if (p.C64) {
             f64x2* d = (f64x2*)(p.C64 + base + col);
             f64x2 lo, hi;
