@@ -51,7 +51,7 @@ struct DenseLdsArgs {
   long sA, sB, sC;      // batch strides (elements; blockIdx.y is the batch)
   int tiles_m, tiles_n;
   int tpw;              // output tiles per workgroup (set by the launcher)
-  int vec;              // vector stores allowed (set by the launcher)
+  int vec;              // vector stores: 0 none, 1 four columns, 2 paired split planes (launcher)
   double* C64 = nullptr;  // float64 output instead of C (same offsets)
   int accumulate = 0;     // float64 output only: C64 += result
 };
@@ -166,8 +166,26 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
             // four values at once: packed round-to-nearest-even conversions
             const bf16x4 h = __builtin_convertvector(x, bf16x4);
             const bf16x4 l = __builtin_convertvector(x - __builtin_convertvector(h, f32x4), bf16x4);
-            *(u32x2*)(p.Chi + base + col) = __builtin_bit_cast(u32x2, h);
-            *(u32x2*)(p.Clo + base + col) = __builtin_bit_cast(u32x2, l);
+            const u32x2 hv = __builtin_bit_cast(u32x2, h), lv = __builtin_bit_cast(u32x2, l);
+            if (p.vec == 2) {
+              // lanes g and g ^ 1 (same row, columns 8 (g / 2) .. + 7) trade
+              // halves: the even lane stores the eight hi values, the odd
+              // lane the eight lo values, one 16-byte store each
+              const bool odd = g & 1;
+              const u32x2 send = odd ? hv : lv;
+              u32x2 recv;
+              recv[0] = __shfl_xor(send[0], 16);
+              recv[1] = __shfl_xor(send[1], 16);
+              u32x4 o;
+              o[0] = odd ? recv[0] : hv[0];
+              o[1] = odd ? recv[1] : hv[1];
+              o[2] = odd ? lv[0] : recv[0];
+              o[3] = odd ? lv[1] : recv[1];
+              *(u32x4*)(odd ? p.Clo + base + col - 4 : p.Chi + base + col) = o;
+            } else {
+              *(u32x2*)(p.Chi + base + col) = hv;
+              *(u32x2*)(p.Clo + base + col) = lv;
+            }
           } else if (p.C64) {
             f64x2* d = (f64x2*)(p.C64 + base + col);
             f64x2 lo, hi;
@@ -416,6 +434,12 @@ inline hipError_t launch_dense_lds_f32(DenseLdsArgs a, int batch, hipStream_t s,
                                 : a.C64 ? (uintptr_t)a.C64 : (uintptr_t)a.C;
     const long esz = a.Chi ? 2 : a.C64 ? 8 : 4;
     a.vec = (a.ldc % 4 == 0 && a.c_gstride % 4 == 0 && a.sC % 4 == 0 && out % (4 * esz < 16 ? 4 * esz : 16) == 0) ? 1 : 0;
+    // split planes: paired 16-byte stores of eight columns when every row
+    // start is a multiple of eight, N too (partner lanes are then both in
+    // or both out of range) and both planes 16-byte aligned
+    if (a.Chi && a.vec && a.ldc % 8 == 0 && a.c_gstride % 8 == 0 && a.sC % 8 == 0 &&
+        a.N % 8 == 0 && out % 16 == 0)
+      a.vec = 2;
   }
   a.tiles_m = (a.M + kLdsTile - 1) / kLdsTile;
   a.tiles_n = (a.N + kLdsTile - 1) / kLdsTile;

@@ -72,6 +72,9 @@ inline void emu_global_load_lds(const void* src, void* dst, unsigned size) {
 #define __builtin_amdgcn_s_waitcnt(x) ((void)0)
 #define __builtin_amdgcn_s_barrier() ((void)0)
 #define __builtin_amdgcn_readfirstlane(x) (x)
+// threads run one after another: a lane exchange returns the lane's own value
+// (the emulator checks memory accesses, not the values)
+template <typename T> inline T __shfl_xor(T v, int, int = 64) { return v; }
 #define __builtin_amdgcn_sched_group_barrier(a, b, c) ((void)0)
 inline unsigned __float_as_uint(float x) { unsigned u; memcpy(&u, &x, 4); return u; }
 inline float __uint_as_float(unsigned u) { float x; memcpy(&x, &u, 4); return x; }
