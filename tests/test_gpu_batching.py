@@ -25,7 +25,7 @@ def B():
     return binding
 
 
-@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+@pytest.mark.parametrize("precision", ["fp32", "fp64", "bf16x3"])
 def test_static_graph_replays_match_eager(B, precision):
     import torch
     wl = synth.small_molecule(24, 200, 10, 8.0, seed=41, static=True)
@@ -52,12 +52,13 @@ def test_static_graph_replays_match_eager(B, precision):
     assert B.sox_plan_describe(pg)["graph"] == 1
 
 
-def test_dynamic_graph_replays_match_eager(B):
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_dynamic_graph_replays_match_eager(B, precision):
     import torch
     wl = synth.small_molecule(13, 70, 24, 30.0, seed=42, dynamic=True)
     tp = synth.bosonic_transform_pair(wl["tau"], wl["beta"], omega_max=14.0, tol=1e-10)
     n, N, nt = wl["n"], wl["N"], wl["n_tau"]
-    mk = lambda: B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision="fp32",
+    mk = lambda: B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision=precision,
                         t_fwd=tp["T_fwd"], t_bwd=tp["T_bwd"])
     pg, pe = mk(), mk()
     B.sox_plan_set_graph(pg, True)
