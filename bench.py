@@ -49,7 +49,7 @@ ENTRY = {"bare": "sox_sigma_bare", "static": "sox_sigma_static", "dynamic": "sox
 # the fused kernel each molecular configuration launches (rocprofv3 names)
 FUSED_KERNEL = {0: "fused_bcd_kernel<float|double, 32, 32>", 3: "fused_bcd_kernel<float, 64, 64>",
                 6: "fused_bcd_bf16x3_kernel<32, 32>", 7: "fused_bcd_bf16x3_kernel<64, 32>",
-                8: "fused_bcd_lds_kernel<0> (bf16 x 3)", 9: "fused_bcd_lds_kernel<1> (float32)"}
+                8: "fused_bcd_lds_kernel<0, 2> (bf16 x 3)", 9: "fused_bcd_lds_kernel<1, 2> (float32)"}
 DOMINANT = {"bare": ("fused", "fused_bcd_kernel"), "static": ("fused", "fused_bcd_kernel"),
             "dynamic": ("fused", "fused_bcd_kernel"), "solid": ("kbc", "cgemm_panel_kernel")}
 

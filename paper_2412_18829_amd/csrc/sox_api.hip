@@ -75,6 +75,14 @@ static const FusedCfg kFusedCfgs[] = {
 };
 static const int kNumFusedCfgs = sizeof(kFusedCfgs) / sizeof(kFusedCfgs[0]);
 
+// 16-row P blocks per wavefront of the LDS-staged fused kernels (configs 8
+// and 9): 4 = four wavefronts of 64 x 64, 2 = eight of 32 x 64, two per
+// SIMD.  Eight against four, per sweep: split precision n=64 N=384 0.533
+// -> 0.508 ms, n=200 N=1200 88.4 -> 85.4 ms, dynamic n=300 N=1800 529 ->
+// 489 ms; float32 n=64 N=384 1.307 -> 1.225 ms, n=200 N=1200 207 -> 198 ms.
+constexpr int kBf16LdsPB = 2;
+constexpr int kFp32LdsPB = 2;
+
 struct sox_plan {
   int n, N, n_tau;
   int nP, NP;
@@ -538,12 +546,16 @@ int fused_blocks_per_cu(const sox_plan& p) {
       case 2: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<float, 32, 64>, 256, 0); break;
       case 3: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<float, 64, 64>, 256, 0); break;
       case 4: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<float, 32, 16>, 256, 0); break;
-      case 9: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_lds_kernel<kLdsFp32>, 256, 0); break;
+      case 9:
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &nb, fused_bcd_lds_kernel<kLdsFp32, kFp32LdsPB>, 1024 / kFp32LdsPB, 0);
+        break;
       default: break;
     }
   } else if (p.precision == SOX_BF16X3) {
     if (p.fused_cfg == 8)
-      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_lds_kernel<kLdsBf16x3>, 256, 0);
+      e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, fused_bcd_lds_kernel<kLdsBf16x3, kBf16LdsPB>, 1024 / kBf16LdsPB, 0);
   } else if (p.precision == SOX_FP64) {
     switch (p.fused_cfg) {
       case 0: e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fused_bcd_kernel<double, 32, 32>, 256, 0); break;
@@ -614,7 +626,7 @@ sox_status launch_fused_cfg<float>(const sox_plan& p, const FusedArgs<float>& fa
       const float* y[2] = {fa.Y, fa.Y};
       const float* pt[2] = {fa.P2T, fa.P2T};
       const float* u[2] = {fa.U2, fa.U2};
-      SOX_HIP(launch_fused_lds<kLdsFp32>(lds_args(fa, a, y, pt, u), s));
+      SOX_HIP((launch_fused_lds<kLdsFp32, kFp32LdsPB>(lds_args(fa, a, y, pt, u), s)));
       break;
     }
     case 0: SOX_HIP((launch_fused<float, 32, 32>(fa, s))); break;
@@ -805,7 +817,7 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
         const bf16_t* y[2] = {p1h, p1l};
         const bf16_t* pt[2] = {p2h, p2l};
         const bf16_t* u[2] = {u2h, u2l};
-        SOX_HIP(launch_fused_lds<kLdsBf16x3>(lds_args(fl, a, y, pt, u), s));
+        SOX_HIP((launch_fused_lds<kLdsBf16x3, kBf16LdsPB>(lds_args(fl, a, y, pt, u), s)));
       } else if (p.fused_cfg == 7) {
         SOX_HIP((launch_fused_bf16x3<64, 32>(fs, s)));
       } else {
@@ -1023,7 +1035,7 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
       const bf16_t* pt[2] = {(const bf16_t*)(base + L.p2h), (const bf16_t*)(base + L.p2l)};
       const bf16_t* u[2] = {(const bf16_t*)(base + L.u2h) + (long)v0 * nP,
                             (const bf16_t*)(base + L.u2l) + (long)v0 * nP};
-      SOX_HIP(launch_fused_lds<kLdsBf16x3>(lds_args(fl, a, y, pt, u), s));
+      SOX_HIP((launch_fused_lds<kLdsBf16x3, kBf16LdsPB>(lds_args(fl, a, y, pt, u), s)));
     } else {
       ProfScope ps(p, SOX_STAGE_FUSED, s);
       st = launch_fused_cfg<T>(p, fa, s);

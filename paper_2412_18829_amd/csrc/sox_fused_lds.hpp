@@ -3,8 +3,10 @@
 // float32 MFMA and for split-precision operands (x = hi + lo in bf16,
 // hi hi + hi lo + lo hi on the 16x16x32 bf16 MFMA, float32 accumulation).
 //
-// A workgroup of four wavefronts owns a 128 x 128 block of D for one tau and
-// one range of v; each wavefront a 64 x 64 block (4 x 4 MFMA tiles).  The v
+// A workgroup owns a 128 x 128 block of D for one tau and one range of v,
+// split over four wavefronts of 64 x 64 (PB = 4: 4 x 4 MFMA tiles each, one
+// wavefront per SIMD) or eight of 32 x 64 (PB = 2: 2 x 4 tiles, two per
+// SIMD, so one wavefront's MFMAs cover the other's LDS reads).  The v
 // sum runs in stages of one v and one 64-byte k chunk (16 float32 or 32
 // bf16 values), and each stage in two halves: the B half needs the P-row
 // panel of A^v and the R-row panel of Y, the C half the P-row panel of
@@ -12,9 +14,9 @@
 // plane (hi and lo are separate planes).  The halves are copied straight
 // from global memory into a ring of five LDS buffers (16-byte global-to-LDS
 // loads, no registers in between), four halves ahead of the MFMAs.  Each
-// panel row is read from LDS by the two wavefronts that share it, so the
+// panel row is read from LDS by the wavefronts that share it, so the
 // operand traffic through the vector cache is that of the workgroup tile,
-// not of four wave tiles, and the fragments of half h + 1 are read into a
+// not of the wave tiles, and the fragments of half h + 1 are read into a
 // second register set while the MFMAs of half h run.
 //
 // One barrier per half h, after the wavefront has waited for its own copies
@@ -58,20 +60,26 @@ struct LdsFusedArgs {
   int vsplit, vchunk;  // split s sums v in [s vchunk, (s+1) vchunk)
 };
 
+// Fragments of one half stage: PB 16-row blocks of the P rows (first MFMA
+// operand) and four of the R rows.
+template <int MODE, int PB> struct LdsFrags;
+template <int PB> struct LdsFrags<kLdsBf16x3, PB> {
+  bf16x8 ah[PB], al[PB], bh[4], bl[4];
+};
+template <int PB> struct LdsFrags<kLdsFp32, PB> {
+  f32x4 a[PB], b[4];
+};
+
 template <int MODE> struct LdsMode;
 template <> struct LdsMode<kLdsBf16x3> {
   static constexpr int kPlanes = 2;  // hi, lo
   static constexpr int kEsize = 2;
-  struct Frags {
-    bf16x8 ah[4], al[4], bh[4], bl[4];
-  };
+  typedef LdsFrags<kLdsBf16x3, 4> Frags;
 };
 template <> struct LdsMode<kLdsFp32> {
   static constexpr int kPlanes = 1;
   static constexpr int kEsize = 4;
-  struct Frags {
-    f32x4 a[4], b[4];
-  };
+  typedef LdsFrags<kLdsFp32, 4> Frags;
 };
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
@@ -87,30 +95,31 @@ template <int N> __device__ __forceinline__ void wait_vm() {
   __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
 }
 
-template <int MODE, int NPL>
+template <int MODE, int NPL, int PB = 4>
 __device__ __forceinline__ void lds_frags(const u32x4 (*buf)[kLdsPieces], const int* sa,
-                                          const int* sy, typename LdsMode<MODE>::Frags& f) {
+                                          const int* sy, LdsFrags<MODE, PB>& f) {
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
     if constexpr (MODE == kLdsBf16x3) {
-      f.ah[i] = __builtin_bit_cast(bf16x8, buf[0][sa[i]]);
-      f.al[i] = __builtin_bit_cast(bf16x8, buf[1][sa[i]]);
+      if (i < PB) {
+        f.ah[i] = __builtin_bit_cast(bf16x8, buf[0][sa[i]]);
+        f.al[i] = __builtin_bit_cast(bf16x8, buf[1][sa[i]]);
+      }
       f.bh[i] = __builtin_bit_cast(bf16x8, buf[NPL][sy[i]]);
       f.bl[i] = __builtin_bit_cast(bf16x8, buf[NPL + 1][sy[i]]);
     } else {
-      f.a[i] = __builtin_bit_cast(f32x4, buf[0][sa[i]]);
+      if (i < PB) f.a[i] = __builtin_bit_cast(f32x4, buf[0][sa[i]]);
       f.b[i] = __builtin_bit_cast(f32x4, buf[NPL][sy[i]]);
     }
   }
 }
 
 // acc (+)= one 64-byte k chunk of the product; FIRST starts from zero
-template <int MODE, bool FIRST>
-__device__ __forceinline__ void lds_half_mfma(const typename LdsMode<MODE>::Frags& f,
-                                              f32x4 (*acc)[4]) {
+template <int MODE, bool FIRST, int PB = 4>
+__device__ __forceinline__ void lds_half_mfma(const LdsFrags<MODE, PB>& f, f32x4 (*acc)[4]) {
   if constexpr (MODE == kLdsBf16x3) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int i = 0; i < PB; ++i)
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         acc[i][j] = mfma16x16x32bf16(f.ah[i], f.bh[j], FIRST ? zero4<float>() : acc[i][j]);
@@ -121,7 +130,7 @@ __device__ __forceinline__ void lds_half_mfma(const typename LdsMode<MODE>::Frag
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < PB; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j)
           acc[i][j] = mfma16x16x4(f.a[i][m], f.b[j][m],
@@ -129,11 +138,16 @@ __device__ __forceinline__ void lds_half_mfma(const typename LdsMode<MODE>::Frag
   }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(256) void fused_bcd_lds_kernel(const LdsFusedArgs p) {
+// PB = 4: four wavefronts of 64 x 64; PB = 2: eight wavefronts of 32 x 64
+// (the P rows of the workgroup tile split four ways), two per SIMD.
+template <int MODE, int PB = 4>
+__global__ __launch_bounds__(1024 / PB) void fused_bcd_lds_kernel(const LdsFusedArgs p) {
+  static_assert(PB == 2 || PB == 4, "32 or 64 P rows per wavefront");
   constexpr int NPL = LdsMode<MODE>::kPlanes;
   constexpr int ES = LdsMode<MODE>::kEsize;
-  constexpr int kCopies = 2 * NPL * 2;  // copies per wavefront and half
+  constexpr int NW = 16 / PB;           // wavefronts
+  constexpr int CP = PB / 2;            // copies per wavefront, panel and plane
+  constexpr int kCopies = 2 * NPL * CP;  // copies per wavefront and half
   // [buffer][plane: P rows (hi, lo), then R rows (hi, lo)][row * 4 + swizzled segment]
   __shared__ u32x4 lds[kLdsBufs][2 * NPL][kLdsPieces];
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -152,14 +166,14 @@ __global__ __launch_bounds__(256) void fused_bcd_lds_kernel(const LdsFusedArgs p
   const int P0 = pt * kLdsTile, R0 = rt * kLdsTile;
 
   // Copies: instruction h of wavefront w fills LDS pieces 64 c .. 64 c + 63
-  // (c = w + 4 h) of a plane, one 16-byte piece per lane at position 64 c +
+  // (c = w + NW h) of a plane, one 16-byte piece per lane at position 64 c +
   // lane, i.e. row 16 c + lane / 4 and swizzled segment lane % 4.  Sources
   // are a wave-uniform base (tau, v, k chunk) plus a 32-bit byte offset per
   // lane (the launcher checks the panels' extents).
-  unsigned orow_p[2], orow_r[2], orow_u[2];
+  unsigned orow_p[CP], orow_r[CP], orow_u[CP];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int c = wave + 4 * h;
+  for (int h = 0; h < CP; ++h) {
+    const int c = wave + NW * h;
     const int row = 16 * c + (lane >> 2);
     const unsigned seg = (unsigned)((lane & 3) ^ ((row >> 1) & 3));
     orow_p[h] = (unsigned)(P0 + row) * (unsigned)(p.nP * ES) + 16u * seg;
@@ -168,18 +182,18 @@ __global__ __launch_bounds__(256) void fused_bcd_lds_kernel(const LdsFusedArgs p
   }
   const long ot_a = (long)t * p.a_tstride * ES, ot_y = (long)t * p.y_tstride * ES;
   const long ot_p = (long)t * p.p_tstride * ES;
-  // fragment positions: P rows (wave >> 1) 64 + 16 i + li, R rows (wave & 1) 64 + 16 j + li
+  // fragment positions: P rows (wave >> 1) 16 PB + 16 i + li, R rows (wave & 1) 64 + 16 j + li
   int sa[4], sy[4];
   const int sw = g ^ ((li >> 1) & 3);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    sa[i] = ((wave >> 1) * 64 + 16 * i + li) * 4 + sw;
+    sa[i] = ((wave >> 1) * 16 * PB + 16 * (i < PB ? i : 0) + li) * 4 + sw;
     sy[i] = ((wave & 1) * 64 + 16 * i + li) * 4 + sw;
   }
 
-  f32x4 accB[4][4], accC[4][4], dacc[4][4];
+  f32x4 accB[PB][4], accC[PB][4], dacc[PB][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < PB; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       accB[i][j] = zero4<float>();
@@ -192,16 +206,16 @@ __global__ __launch_bounds__(256) void fused_bcd_lds_kernel(const LdsFusedArgs p
   // copy cursor: the stage whose halves are copied next, held at the last
   // stage once every stage is under way
   int cv = v_begin, ckc = 0, cs = 0;
-  const int c0 = 64 * wave, c1 = 64 * (wave + 4);
   auto copy_panels = [&](u32x4 (*buf)[kLdsPieces], const char* const* srcp, long offp,
                          const char* const* srcr, long offr, const unsigned* orr) {
 #pragma unroll
-    for (int q = 0; q < NPL; ++q) {
-      global_to_lds16(srcp[q] + offp + orow_p[0], &buf[q][c0]);
-      global_to_lds16(srcp[q] + offp + orow_p[1], &buf[q][c1]);
-      global_to_lds16(srcr[q] + offr + orr[0], &buf[NPL + q][c0]);
-      global_to_lds16(srcr[q] + offr + orr[1], &buf[NPL + q][c1]);
-    }
+    for (int q = 0; q < NPL; ++q)
+#pragma unroll
+      for (int h = 0; h < CP; ++h) {
+        const int ch = 64 * (wave + NW * h);
+        global_to_lds16(srcp[q] + offp + orow_p[h], &buf[q][ch]);
+        global_to_lds16(srcr[q] + offr + orr[h], &buf[NPL + q][ch]);
+      }
   };
   auto copy_b = [&](int b) {
     const long ko = (long)ckc * 64;
@@ -219,7 +233,7 @@ __global__ __launch_bounds__(256) void fused_bcd_lds_kernel(const LdsFusedArgs p
   };
 
   if (nst > 0) {
-    typename LdsMode<MODE>::Frags f0, f1;
+    LdsFrags<MODE, PB> f0, f1;
     // halves 0..3 (stages 0 and 1) in flight, then halves 0 and 1 landed
     copy_b(0);
     copy_c(1);
@@ -227,7 +241,7 @@ __global__ __launch_bounds__(256) void fused_bcd_lds_kernel(const LdsFusedArgs p
     copy_c(3);
     wait_vm<kCopies * (kLdsAhead - 2)>();
     barrier_nofence();
-    lds_frags<MODE, NPL>(lds[0], sa, sy, f0);
+    lds_frags<MODE, NPL, PB>(lds[0], sa, sy, f0);
     int b1 = 1;  // buffer of half 2 s + 1
     // B half of stage s: copy half 2 s + 4 into the buffer of half 2 s - 1,
     // read the C-half fragments, MFMAs from f0.  C half: copy half 2 s + 5
@@ -238,22 +252,22 @@ __global__ __launch_bounds__(256) void fused_bcd_lds_kernel(const LdsFusedArgs p
     auto half_b = [&](auto first, int bcopy) {
       constexpr bool F = decltype(first)::value;
       copy_b(bcopy);
-      lds_frags<MODE, NPL>(lds[b1], sa, sy, f1);
+      lds_frags<MODE, NPL, PB>(lds[b1], sa, sy, f1);
       if constexpr (F) {
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < PB; ++i)
 #pragma unroll
           for (int j = 0; j < 4; ++j) dacc[i][j] += accB[i][j] * accC[i][j];
       }
-      lds_half_mfma<MODE, F>(f0, accB);
+      lds_half_mfma<MODE, F, PB>(f0, accB);
       wait_vm<kCopies * (kLdsAhead - 2)>();
       barrier_nofence();
     };
     auto half_c = [&](auto first, int bcopy, int bread) {
       constexpr bool F = decltype(first)::value;
       copy_c(bcopy);
-      lds_frags<MODE, NPL>(lds[bread], sa, sy, f0);
-      lds_half_mfma<MODE, F>(f1, accC);
+      lds_frags<MODE, NPL, PB>(lds[bread], sa, sy, f0);
+      lds_half_mfma<MODE, F, PB>(f1, accC);
       wait_vm<kCopies * (kLdsAhead - 2)>();
       barrier_nofence();
     };
@@ -276,14 +290,14 @@ __global__ __launch_bounds__(256) void fused_bcd_lds_kernel(const LdsFusedArgs p
     wait_vm<0>();  // the repeated copies past the end
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < PB; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) dacc[i][j] += accB[i][j] * accC[i][j];
 
   float* Db = p.D + (long)sp * p.d_sstride + (long)t * p.d_tstride;
-  const int Pw = P0 + (wave >> 1) * 64, Rw = R0 + (wave & 1) * 64;
+  const int Pw = P0 + (wave >> 1) * 16 * PB, Rw = R0 + (wave & 1) * 64;
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < PB; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j)
 #pragma unroll
@@ -293,8 +307,8 @@ __global__ __launch_bounds__(256) void fused_bcd_lds_kernel(const LdsFusedArgs p
       }
 }
 
-// Grid: (R tile, P tile, tau, v split), R tiles fastest.
-template <int MODE>
+// Grid: (R tile, P tile, tau, v split), R tiles fastest; 1024 / PB threads.
+template <int MODE, int PB = 4>
 inline hipError_t launch_fused_lds(const LdsFusedArgs& a, hipStream_t s) {
   constexpr long ES = LdsMode<MODE>::kEsize;
   if ((a.nP * ES) % 64 != 0 || a.NP % kLdsTile != 0 || a.tiles_p * kLdsTile != a.NP ||
@@ -306,7 +320,8 @@ inline hipError_t launch_fused_lds(const LdsFusedArgs& a, hipStream_t s) {
   const long nb = (long)a.tiles_p * a.tiles_r * a.n_tau * a.vsplit;
   if (nb <= 0) return hipSuccess;
   if (nb > (1L << 31) - 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fused_bcd_lds_kernel<MODE>, dim3((unsigned)nb), dim3(256), 0, s, a);
+  hipLaunchKernelGGL((fused_bcd_lds_kernel<MODE, PB>), dim3((unsigned)nb), dim3(1024 / PB), 0, s,
+                     a);
   return hipGetLastError();
 }
 
