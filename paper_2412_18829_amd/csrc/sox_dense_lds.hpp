@@ -291,8 +291,14 @@ struct DenseLdsSplitArgs {
   int vec;  // 16-byte stores allowed (set by the launcher)
 };
 
-__global__ __launch_bounds__(256) void dense_lds_bf16x3_kernel(const DenseLdsSplitArgs p) {
+// PB = 4: four wavefronts of 64 x 64 of C; PB = 2: eight of 64 rows x 32
+// columns, two per SIMD.
+template <int PB = 4>
+__global__ __launch_bounds__(1024 / PB) void dense_lds_bf16x3_kernel(const DenseLdsSplitArgs p) {
   constexpr int MODE = kLdsBf16x3;
+  constexpr int NW = 16 / PB;    // wavefronts
+  constexpr int CP = PB / 2;     // copies per wavefront, panel and plane
+  constexpr int NBG = 8 / PB;    // wavefront groups over the B rows (C columns)
   // [buffer][plane: B rows hi, lo (first MFMA operand), A rows hi, lo][row * 4 + swizzled segment]
   __shared__ u32x4 lds[kLdsBufs][4][kLdsPieces];
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -303,11 +309,11 @@ __global__ __launch_bounds__(256) void dense_lds_bf16x3_kernel(const DenseLdsSpl
   const int li = lane & 15;
   const int g = lane >> 4;
   const long bat = blockIdx.y;
-  const char* srcb[2][2];  // [plane][copy]
-  const char* srca[2][2];
+  const char* srcb[2][CP];  // [plane][copy]
+  const char* srca[2][CP];
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    const int c = wave + 4 * h;
+  for (int h = 0; h < CP; ++h) {
+    const int c = wave + NW * h;
     const int row = 16 * c + (lane >> 2);
     const int seg = (lane & 3) ^ ((row >> 1) & 3);
     const long ra = M0 + row < p.M ? M0 + row : p.M - 1;
@@ -318,60 +324,63 @@ __global__ __launch_bounds__(256) void dense_lds_bf16x3_kernel(const DenseLdsSpl
     srcb[0][h] = (const char*)(p.Bh + ob) + 16 * seg;
     srcb[1][h] = (const char*)(p.Bl + ob) + 16 * seg;
   }
-  // fragments: first operand B rows (wave & 1) 64 + 16 i, second A rows (wave >> 1) 64 + 16 j
+  // fragments: first operand B rows wb 16 PB + 16 i (i < PB), second A rows
+  // wa 64 + 16 j
+  const int wb = wave % NBG, wa = wave / NBG;
   int sb[4], sa[4];
   const int sw = g ^ ((li >> 1) & 3);
 #pragma unroll
   for (int i = 0; i < 4; ++i) {
-    sb[i] = ((wave & 1) * 64 + 16 * i + li) * 4 + sw;
-    sa[i] = ((wave >> 1) * 64 + 16 * i + li) * 4 + sw;
+    sb[i] = (wb * 16 * PB + 16 * (i < PB ? i : 0) + li) * 4 + sw;
+    sa[i] = (wa * 64 + 16 * i + li) * 4 + sw;
   }
   const int KC = p.K / 32;
-  const int c0 = 64 * wave, c1 = 64 * (wave + 4);
   int ck = 0;  // next chunk to copy, held at the last one past the end
   auto copy_stage = [&](int b) {
     const long ko = (long)ck * 64;
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      global_to_lds16(srcb[q][0] + ko, &lds[b][q][c0]);
-      global_to_lds16(srcb[q][1] + ko, &lds[b][q][c1]);
-      global_to_lds16(srca[q][0] + ko, &lds[b][2 + q][c0]);
-      global_to_lds16(srca[q][1] + ko, &lds[b][2 + q][c1]);
-    }
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int h = 0; h < CP; ++h) {
+        const int ch = 64 * (wave + NW * h);
+        global_to_lds16(srcb[q][h] + ko, &lds[b][q][ch]);
+        global_to_lds16(srca[q][h] + ko, &lds[b][2 + q][ch]);
+      }
     ck += ck + 1 < KC ? 1 : 0;
   };
-  f32x4 acc[4][4];
+  constexpr int kStageCopies = 4 * CP;  // per wavefront
+  f32x4 acc[PB][4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < PB; ++i)
 #pragma unroll
     for (int j = 0; j < 4; ++j) acc[i][j] = zero4<float>();
-  typename LdsMode<MODE>::Frags f0, f1;
+  LdsFrags<MODE, PB> f0, f1;
   auto next = [](int x) { return x + 1 == kLdsBufs ? 0 : x + 1; };
   auto back2 = [](int x) { return x >= 2 ? x - 2 : x + kLdsBufs - 2; };
   // the schedule of the float32 kernel: copy stage s + 4 into the buffer of
   // stage s - 1, read the fragments of stage s + 1, MFMAs of stage s, wait
-  // for the own copies of stage s + 2 (eight per stage), barrier
+  // for the own copies of stage s + 2, barrier
   copy_stage(0);
   copy_stage(1);
   copy_stage(2);
   copy_stage(3);
-  wait_vm<16>();
+  wait_vm<2 * kStageCopies>();
   barrier_nofence();
-  lds_frags<MODE, 2>(lds[0], sb, sa, f0);
+  lds_frags<MODE, 2, PB>(lds[0], sb, sa, f0);
   int b1 = 1;
   auto stage_a = [&]() {
     copy_stage(back2(b1));
-    lds_frags<MODE, 2>(lds[b1], sb, sa, f1);
-    lds_half_mfma<MODE, false>(f0, acc);
-    wait_vm<16>();
+    lds_frags<MODE, 2, PB>(lds[b1], sb, sa, f1);
+    lds_half_mfma<MODE, false, PB>(f0, acc);
+    wait_vm<2 * kStageCopies>();
     barrier_nofence();
     b1 = next(b1);
   };
   auto stage_b = [&]() {
     copy_stage(back2(b1));
-    lds_frags<MODE, 2>(lds[b1], sb, sa, f0);
-    lds_half_mfma<MODE, false>(f1, acc);
-    wait_vm<16>();
+    lds_frags<MODE, 2, PB>(lds[b1], sb, sa, f0);
+    lds_half_mfma<MODE, false, PB>(f1, acc);
+    wait_vm<2 * kStageCopies>();
     barrier_nofence();
     b1 = next(b1);
   };
@@ -383,14 +392,14 @@ __global__ __launch_bounds__(256) void dense_lds_bf16x3_kernel(const DenseLdsSpl
   wait_vm<0>();  // the repeated copies past the end
 
   // lane (li, g) holds C[row 16 j + li][columns 16 i + 4 g .. + 3]
-  const int Rw = M0 + (wave >> 1) * 64, Cw = N0 + (wave & 1) * 64;
+  const int Rw = M0 + wa * 64, Cw = N0 + wb * 16 * PB;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int row = Rw + 16 * j + li;
     if (row >= p.M) continue;
     float* crow = p.C + bat * p.sC + (long)row * p.ldc;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < PB; ++i) {
       const int col = Cw + 16 * i + 4 * g;
       if (col >= p.N) continue;
       if (p.vec && col + 3 < p.N) {
@@ -404,6 +413,7 @@ __global__ __launch_bounds__(256) void dense_lds_bf16x3_kernel(const DenseLdsSpl
   }
 }
 
+template <int PB = 4>
 inline hipError_t launch_dense_lds_bf16x3(DenseLdsSplitArgs a, int batch, hipStream_t s) {
   if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;
   if (batch > 65535 || a.K % 32 != 0 || a.K <= 0 || !a.Ah || !a.Al || !a.Bh || !a.Bl || !a.C)
@@ -415,8 +425,8 @@ inline hipError_t launch_dense_lds_bf16x3(DenseLdsSplitArgs a, int batch, hipStr
   a.tiles_n = (a.N + kLdsTile - 1) / kLdsTile;
   const long nb = (long)a.tiles_m * a.tiles_n;
   if (nb > (1L << 31) - 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(dense_lds_bf16x3_kernel, dim3((unsigned)nb, (unsigned)batch), dim3(256), 0, s,
-                     a);
+  hipLaunchKernelGGL((dense_lds_bf16x3_kernel<PB>), dim3((unsigned)nb, (unsigned)batch),
+                     dim3(1024 / PB), 0, s, a);
   return hipGetLastError();
 }
 
