@@ -674,7 +674,11 @@ sox_status launch_back(const sox_plan& p, const double* XP, const T* D, double* 
     // float32 D (the nsplit partial blocks of a split v sum, if any) summed
     // and widened to float64 in one pass
     const long cd = (long)cnt * NP * NP;
-    if (nsplit > 1)
+    if (nsplit <= 8 && cd % 4 == 0 && sstride % 4 == 0 && (uintptr_t)D % 16 == 0 &&
+        (uintptr_t)D64 % 32 == 0)
+      hipLaunchKernelGGL(widen_sum4_kernel, grid1d(cd / 4), dim3(256), 0, s, (const float*)D, D64,
+                         cd / 4, sstride, nsplit);
+    else if (nsplit > 1)
       hipLaunchKernelGGL(widen_sum_kernel, grid1d(cd), dim3(256), 0, s, (const float*)D, D64, cd,
                          sstride, nsplit);
     else

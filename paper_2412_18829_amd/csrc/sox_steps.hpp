@@ -187,6 +187,24 @@ __global__ void widen_sum_kernel(const float* src, double* dst, long count, long
   }
 }
 
+// widen_sum_kernel on four consecutive elements per work-item: count and
+// stride multiples of 4, src and dst 16- and 32-byte aligned.  The ns blocks
+// (at most 8) are all loaded before the float64 sum, taken in block order as
+// in widen_sum_kernel, so both give the same bits.
+__global__ void widen_sum4_kernel(const float* src, double* dst, long count4, long stride, int ns) {
+  SOX_FOR_FLAT(i, count4) {
+    f32x4 v[8];
+#pragma unroll
+    for (int s = 0; s < 8; ++s)
+      if (s < ns) v[s] = *(const f32x4*)(src + s * stride + 4 * i);
+    f64x4 acc = __builtin_convertvector(v[0], f64x4);
+#pragma unroll
+    for (int s = 1; s < 8; ++s)
+      if (s < ns) acc += __builtin_convertvector(v[s], f64x4);
+    *(f64x4*)(dst + 4 * i) = acc;
+  }
+}
+
 template <typename T>
 __global__ void cast_kernel(const double* src, T* dst, long count) {
   SOX_FOR_FLAT(idx, count) dst[idx] = T(src[idx]);
