@@ -80,9 +80,11 @@ typedef enum {
 } sox_status;
 
 /* Arithmetic of the contraction kernels (the A step and the fused B.C -> D
- * step).  G(tau) synthesis, the U-contraction, the half projections, the
- * back-transform to orbitals, the Matsubara transforms and the energy are
- * always float64.
+ * step).  G(tau) synthesis, the half projections, the back-transform to
+ * orbitals, the Matsubara transforms and the energy are always float64.
+ * The U-contraction (eq:U_contraction) runs in float64 for SOX_FP64 plans
+ * and for every k-point plan; molecular SOX_FP32 and SOX_BF16X3 plans run it
+ * in float32 (its result is stored in float32 for the A step either way).
  *   SOX_FP64    float64 MFMA (v_mfma_f64_16x16x4f64)
  *   SOX_FP32    float32 MFMA (v_mfma_f32_16x16x4f32), float32 accumulation
  *   SOX_BF16X3  each float32 operand split as hi + lo bfloat16; the products
@@ -93,7 +95,12 @@ typedef enum {
  *               entry (the fused contraction in split precision, A(tau)
  *               written by the inverse transform as hi + lo planes, the
  *               other steps in float32); the adjoint returns
- *               SOX_ERR_UNSUPPORTED for a bf16x3 plan.                      */
+ *               SOX_ERR_UNSUPPORTED for a bf16x3 plan.  The molecular
+ *               dynamic entry needs the LDS-staged fused kernel, whose
+ *               panel offsets are 32-bit: with n_thc * n_orb^2 * 2 bytes at
+ *               or past 2^32 (after padding) it returns SOX_ERR_UNSUPPORTED
+ *               before any device work (the bare and static entries fall
+ *               back to the direct-load kernel there).                      */
 typedef enum { SOX_FP64 = 0, SOX_FP32 = 1, SOX_BF16X3 = 2 } sox_precision;
 
 /* Entry kinds, for sox_workspace_size and sox_sigma_vjp. */

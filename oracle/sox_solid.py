@@ -61,7 +61,7 @@ def sigma_solid_eri(X, U1, U2, G, tables) -> np.ndarray:
     return out / nk ** 2
 
 
-def sigma_solid_thc(X, U1, U2, G, tables) -> np.ndarray:
+def sigma_solid_thc(X, U1, U2, G, tables, v_subset=None) -> np.ndarray:
     """The paper's k-point step chain.
 
     U^{q1,k_v}_Pqs = sum_Q U1^{q1}_PQ conj(X^{k_v-q1}_qQ) X^{k_v}_sQ    (eq:U_contraction)
@@ -71,6 +71,10 @@ def sigma_solid_thc(X, U1, U2, G, tables) -> np.ndarray:
     C^{q2,k_w}_RvP = sum_w U(2)^{q2,k_w}_Rvw G^{k_w}_wP
     D^{k_t}_PR = (1/N_k) sum_{k_w, q2} sum_v C^{q2,k_w}_RvP B^{q1,k_w-q2}_PRv,  q1 = k_w - k_t
     Sigma^{k_t}_RP = -(1/N_k) D^{k_t}_PR;  Sigma^{k_t}_tr = sum_PR conj(X^{k_t}_tR) Sigma_RP X^{k_t}_rP
+
+    v_subset (optional): only the orbitals v listed contribute to D (the
+    chain's innermost orbital sum); Sigma is linear in the per-v terms, so
+    the results of disjoint subsets add up to the full Sigma.
     """
     ks_list, kdiff, ksum, kneg = tables
     nk, nt, n, _ = G.shape
@@ -83,6 +87,7 @@ def sigma_solid_thc(X, U1, U2, G, tables) -> np.ndarray:
 
     U1t = {(q, kv): utensor(U1, q, kv) for q in range(nk) for kv in range(nk)}
     U2t = {(q, kv): utensor(U2, q, kv) for q in range(nk) for kv in range(nk)}
+    vs = np.arange(n) if v_subset is None else np.asarray(v_subset, dtype=int)
     out = np.empty((nk, nt, n, n), dtype=complex)
     for k in range(nt):
         GRq = [X[kk].T @ G[kk, k] for kk in range(nk)]             # G^k_Rq
@@ -90,13 +95,13 @@ def sigma_solid_thc(X, U1, U2, G, tables) -> np.ndarray:
         B = {}
         for q1 in range(nk):
             for kv in range(nk):
-                A = np.tensordot(U1t[(q1, kv)], Gb[kv, k], axes=(2, 0))   # A_Pqv
+                A = np.tensordot(U1t[(q1, kv)], Gb[kv, k][:, vs], axes=(2, 0))   # A_Pqv
                 kq = kdiff[kv, q1]
                 B[(q1, kv)] = np.einsum("Pqv,Rq->PRv", A, GRq[kq])
         C = {}
         for q2 in range(nk):
             for kw in range(nk):
-                C[(q2, kw)] = np.einsum("Rvw,wP->RvP", U2t[(q2, kw)], GwP[kw])
+                C[(q2, kw)] = np.einsum("Rvw,wP->RvP", U2t[(q2, kw)][:, vs], GwP[kw])
         for kt in range(nk):
             D = np.zeros((N, N), dtype=complex)
             for kw in range(nk):
@@ -166,8 +171,11 @@ def sigma_solid_dynamic_eri(X, W, V, G, T_fwd, T_bwd, tables) -> np.ndarray:
     return out / nk ** 2
 
 
-def sigma_solid_dynamic_thc(X, W, V, G, T_fwd, T_bwd, tables) -> np.ndarray:
+def sigma_solid_dynamic_thc(X, W, V, G, T_fwd, T_bwd, tables, v_subset=None) -> np.ndarray:
     """The paper's momentum-resolved eq:GG chain with v outermost.
+
+    v_subset (optional): run the outer orbital loop over the listed v only
+    (Sigma is linear in the per-v contributions to D).
 
     GG^{q1,k_v}_Quv(tau) = G^{k_v-q1}_uQ(tau) G^{k_v}_Qv(-tau) with
     G^k_uQ = sum_q G^k_uq conj(X^k_qQ) and G^k_Qv(-tau) read as
@@ -189,7 +197,7 @@ def sigma_solid_dynamic_thc(X, W, V, G, T_fwd, T_bwd, tables) -> np.ndarray:
 
     U2t = {(q, k): utensor(V, q, k) for q in range(nk) for k in range(nk)}
     D = np.zeros((nk, nt, N, N), dtype=complex)
-    for v in range(n):
+    for v in (range(n) if v_subset is None else v_subset):
         B = {}
         for q1 in range(nk):
             for kv in range(nk):

@@ -202,6 +202,7 @@ inline hipError_t launch_hc(HcArgs<T, TC> a, int nx, hipStream_t s) {
   a.tiles_x = nx / (64 * XB);
   const long nb = (long)a.tiles_x * a.n_ot * a.n_ov;
   if (nb <= 0) return hipSuccess;
+  if (!grid_fits(nb, 256)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((hc_kernel<T, TC, XB, YB>), dim3((unsigned)nb), dim3(256), 0, s, a);
   return hipGetLastError();
 }

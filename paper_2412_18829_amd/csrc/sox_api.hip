@@ -336,17 +336,28 @@ int default_fused_cfg(int precision, int N) {
 
 // the LDS-staged fused kernel's 32-bit byte offsets within one (tau, v)
 // panel set: NP rows of nP values, and NP rows of the U-tensor (stride nP^2)
-bool lds_offsets_fit(const sox_plan& p) {
-  const double es = p.precision == SOX_BF16X3 ? 2.0 : 4.0;
+bool lds_offsets_fit(int precision, long NP, long nP) {
+  const double es = precision == SOX_BF16X3 ? 2.0 : 4.0;
   const double lim = 4294967296.0;
-  return (double)p.NP * p.nP * es < lim && (double)p.NP * p.nP * p.nP * es < lim;
+  return (double)NP * nP * es < lim && (double)NP * nP * nP * es < lim;
 }
+bool lds_offsets_fit(const sox_plan& p) { return lds_offsets_fit(p.precision, p.NP, p.nP); }
 
 void set_fused_cfg(sox_plan& p, int cfg) {
   p.fused_cfg = cfg;
   const FusedCfg& fc = kFusedCfgs[cfg];
   p.wg_tile = 2 * std::max(fc.wp, fc.wr);
   p.NP = (int)round_up(p.N, p.wg_tile);
+}
+
+// A fused config this plan can launch: one of its precision, and for the
+// LDS-staged configs (8, 9) panel offsets within 32 bits at that config's
+// padding.  Leaves the plan's config unchanged.
+bool cfg_usable(const sox_plan& p, int cfg) {
+  if (cfg < 0 || cfg >= kNumFusedCfgs || !cfg_allowed(p.precision, cfg)) return false;
+  if (cfg != 8 && cfg != 9) return true;
+  const FusedCfg& fc = kFusedCfgs[cfg];
+  return lds_offsets_fit(p.precision, round_up(p.N, 2 * std::max(fc.wp, fc.wr)), p.nP);
 }
 
 sox_status check_plan(const sox_plan* plan) {
@@ -1610,7 +1621,7 @@ sox_status autotune_fused(sox_plan& p) {
         if (sscanf(line, "%95s %d %d %d %d", k, &prec, &n, &N, &cfg) == 5) {
           char full[96];
           snprintf(full, sizeof(full), "%s %d %d %d", k, prec, n, N);
-          if (key == full && cfg >= 0 && cfg < kNumFusedCfgs) found = cfg;
+          if (key == full && cfg_usable(p, cfg)) found = cfg;
         }
       }
       fclose(f);
@@ -1626,7 +1637,7 @@ sox_status autotune_fused(sox_plan& p) {
   double best_ms = 1e300;
   p.tune_ms.clear();
   for (int c = 0; c < kNumFusedCfgs; ++c) {
-    if (!cfg_allowed(p.precision, c)) continue;
+    if (!cfg_usable(p, c)) continue;
     double ms = 0;
     sox_status st = p.precision == SOX_FP64 ? time_fused_cfg<double>(p, c, tt, &ms)
                                             : time_fused_cfg<float>(p, c, tt, &ms);
@@ -1918,6 +1929,10 @@ sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_ta
   if (!X || !W_tau || !V || !G || !Sigma) return fail(SOX_ERR_INVALID_ARG, "NULL tensor pointer");
   st = check_ws(plan, SOX_ENTRY_DYNAMIC, ws, ws_bytes);
   if (st) return st;
+  if (plan->nk == 1 && plan->precision == SOX_BF16X3 && plan->fused_cfg != 8)
+    return fail(SOX_ERR_UNSUPPORTED,
+                "the molecular dynamic entry in bf16x3 needs the LDS-staged fused kernel, whose "
+                "32-bit panel offsets overflow at this n_orb and n_thc");
   const uintptr_t key[9] = {(uintptr_t)SOX_ENTRY_DYNAMIC, (uintptr_t)X, (uintptr_t)W_tau,
                             (uintptr_t)V, (uintptr_t)G, (uintptr_t)Sigma, (uintptr_t)ws,
                             (uintptr_t)ws_bytes, 0};

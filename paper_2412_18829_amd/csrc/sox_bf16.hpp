@@ -148,10 +148,10 @@ __global__ __launch_bounds__(256) void fused_bcd_bf16x3_kernel(const FusedSplitA
 
 template <int WP, int WR>
 inline hipError_t launch_fused_bf16x3(const FusedSplitArgs& a, hipStream_t s) {
-  const int nb = a.tiles_p * a.tiles_r * a.n_tau;
+  const long nb = (long)a.tiles_p * a.tiles_r * a.n_tau;
   if (nb <= 0) return hipSuccess;
-  if (a.nP % 32 != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((fused_bcd_bf16x3_kernel<WP, WR>), dim3(nb), dim3(256), 0, s, a);
+  if (a.nP % 32 != 0 || !grid_fits(nb, 256)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((fused_bcd_bf16x3_kernel<WP, WR>), dim3((unsigned)nb), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

@@ -99,6 +99,16 @@ inline dim3 grid1d(long count) {
   if (b < 1) b = 1;
   return dim3((unsigned)(b < kGrid1dMax ? b : kGrid1dMax));
 }
+// A dispatch packet carries each grid extent in work-items (workgroups times
+// the workgroup size) as a 32-bit value, so an extent of 2^32 work-items or
+// more wraps.  Every tiled launcher refuses such a grid (hipErrorInvalidValue)
+// instead of launching it.
+inline bool grid_fits(long wg_x, long threads, long wg_y = 1, long wg_z = 1) {
+  constexpr long kLim = 1L << 32;
+  return wg_x >= 1 && wg_y >= 1 && wg_z >= 1 && threads >= 1 && wg_x * threads < kLim &&
+         wg_y < kLim && wg_z < kLim;
+}
+
 #define SOX_FOR_FLAT(i, count)                                                   \
   for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < (long)(count); \
        i += (long)gridDim.x * blockDim.x)

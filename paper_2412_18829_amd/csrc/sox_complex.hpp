@@ -261,7 +261,9 @@ inline hipError_t launch_cgemm(CgArgs<T, TC> a, int nz, hipStream_t s) {
   a.tiles_n = (a.N + TN - 1) / TN;
   const int gy = nz < 65535 ? nz : 65535;
   const int gz = (nz + gy - 1) / gy;
-  dim3 grid(a.tiles_m * a.tiles_n, gy, gz);
+  const long gx = (long)a.tiles_m * a.tiles_n;
+  if (!grid_fits(gx, 64 * WGR * WGC, gy, gz)) return hipErrorInvalidValue;
+  dim3 grid((unsigned)gx, gy, gz);
   hipLaunchKernelGGL((cgemm_nt_kernel<T, TC, WGR, WGC, RB, CB>), grid, dim3(64 * WGR * WGC), 0, s,
                      a);
   return hipGetLastError();
@@ -440,7 +442,9 @@ inline hipError_t launch_cgemm_panel(CgArgs<float, float> a, int nz, bool fixa, 
   a.tiles_n = (a.N + (fixa ? 16 * NW : kPanelRows) - 1) / (fixa ? 16 * NW : kPanelRows);
   const int gy = nz < 65535 ? nz : 65535;
   const int gz = (nz + gy - 1) / gy;
-  dim3 grid(a.tiles_m * a.tiles_n, gy, gz);
+  const long gx = (long)a.tiles_m * a.tiles_n;
+  if (!grid_fits(gx, 64 * NW, gy, gz)) return hipErrorInvalidValue;
+  dim3 grid((unsigned)gx, gy, gz);
   const int S = (a.K + 3) / 4;
 #define SOX_PANEL(SM_)                                                                     \
   if (S <= SM_) {                                                                          \
@@ -638,7 +642,9 @@ inline hipError_t launch_cgemm_panel_bf16x3(CgArgs<float, float> a, int nz, bool
   a.tiles_n = (a.N + (fixa ? 16 * NW : kPanelRows) - 1) / (fixa ? 16 * NW : kPanelRows);
   const int gy = nz < 65535 ? nz : 65535;
   const int gz = (nz + gy - 1) / gy;
-  dim3 grid(a.tiles_m * a.tiles_n, gy, gz);
+  const long gx = (long)a.tiles_m * a.tiles_n;
+  if (!grid_fits(gx, 64 * NW, gy, gz)) return hipErrorInvalidValue;
+  dim3 grid((unsigned)gx, gy, gz);
   if (fixa)
     hipLaunchKernelGGL((cgemm_panel_bf16x3_kernel<true, NW>), grid, dim3(64 * NW), 0, s, a);
   else

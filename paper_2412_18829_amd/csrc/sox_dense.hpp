@@ -144,7 +144,9 @@ inline hipError_t launch_dense(DenseArgs<T, TC> a, int batch, hipStream_t s) {
   if (a.Chi && (sizeof(TC) != 4 || !a.Clo || a.accumulate)) return hipErrorInvalidValue;
   a.tiles_m = (a.M + TM - 1) / TM;
   a.tiles_n = (a.N + TN - 1) / TN;
-  dim3 grid(a.tiles_m * a.tiles_n, batch);
+  const long gx = (long)a.tiles_m * a.tiles_n;
+  if (!grid_fits(gx, 256, batch)) return hipErrorInvalidValue;
+  dim3 grid((unsigned)gx, batch);
   hipLaunchKernelGGL((dense_nt_kernel<T, TC, WGR, WGC, RB, CB>), grid, dim3(256), 0, s, a);
   return hipGetLastError();
 }

@@ -424,7 +424,7 @@ inline hipError_t launch_dense_lds_bf16x3(DenseLdsSplitArgs a, int batch, hipStr
   a.tiles_m = (a.M + kLdsTile - 1) / kLdsTile;
   a.tiles_n = (a.N + kLdsTile - 1) / kLdsTile;
   const long nb = (long)a.tiles_m * a.tiles_n;
-  if (nb > (1L << 31) - 1) return hipErrorInvalidValue;
+  if (!grid_fits(nb, 1024 / PB, batch)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((dense_lds_bf16x3_kernel<PB>), dim3((unsigned)nb, (unsigned)batch),
                      dim3(1024 / PB), 0, s, a);
   return hipGetLastError();
@@ -465,7 +465,7 @@ inline hipError_t launch_dense_lds_f32(DenseLdsArgs a, int batch, hipStream_t s,
     per = (ntiles * batch + wg_target - 1) / wg_target;
   a.tpw = (int)(per < 1 ? 1 : per > ntiles ? ntiles : per);
   const long nb = (ntiles + a.tpw - 1) / a.tpw;
-  if (nb > (1L << 31) - 1) return hipErrorInvalidValue;
+  if (!grid_fits(nb, 256, batch)) return hipErrorInvalidValue;
   if (a.tpw > 1)
     hipLaunchKernelGGL(dense_lds_f32_kernel<true>, dim3((unsigned)nb, (unsigned)batch), dim3(256),
                        0, s, a);

@@ -176,9 +176,10 @@ __global__ __launch_bounds__(256) void fused_bcd_kernel(const FusedArgs<T> p) {
 
 template <typename T, int WP, int WR>
 inline hipError_t launch_fused(const FusedArgs<T>& a, hipStream_t s) {
-  const int nb = a.tiles_p * a.tiles_r * a.n_tau * (a.vsplit > 1 ? a.vsplit : 1);
+  const long nb = (long)a.tiles_p * a.tiles_r * a.n_tau * (a.vsplit > 1 ? a.vsplit : 1);
   if (nb <= 0) return hipSuccess;
-  hipLaunchKernelGGL((fused_bcd_kernel<T, WP, WR>), dim3(nb), dim3(256), 0, s, a);
+  if (!grid_fits(nb, 256)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((fused_bcd_kernel<T, WP, WR>), dim3((unsigned)nb), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

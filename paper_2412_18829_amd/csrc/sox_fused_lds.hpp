@@ -319,7 +319,7 @@ inline hipError_t launch_fused_lds(const LdsFusedArgs& a, hipStream_t s) {
     return hipErrorInvalidValue;
   const long nb = (long)a.tiles_p * a.tiles_r * a.n_tau * a.vsplit;
   if (nb <= 0) return hipSuccess;
-  if (nb > (1L << 31) - 1) return hipErrorInvalidValue;
+  if (!grid_fits(nb, 1024 / PB)) return hipErrorInvalidValue;
   hipLaunchKernelGGL((fused_bcd_lds_kernel<MODE, PB>), dim3((unsigned)nb), dim3(1024 / PB), 0, s,
                      a);
   return hipGetLastError();

@@ -72,7 +72,9 @@ inline hipError_t launch_gemm(const Prob& p, int batch, hipStream_t s) {
   constexpr int TM = WGR * RB * 16;
   constexpr int TN = WGC * CB * 16;
   if (p.M <= 0 || p.N <= 0 || batch <= 0) return hipSuccess;
-  dim3 grid((p.N + TN - 1) / TN, (p.M + TM - 1) / TM, batch);
+  const long gx = ((long)p.N + TN - 1) / TN, gy = ((long)p.M + TM - 1) / TM;
+  if (!grid_fits(gx, 256, gy, batch)) return hipErrorInvalidValue;
+  dim3 grid((unsigned)gx, (unsigned)gy, batch);
   hipLaunchKernelGGL((gemm_kernel<Prob, Tacc, WGR, WGC, RB, CB>), grid, dim3(256), 0, s, p);
   return hipGetLastError();
 }

@@ -294,19 +294,30 @@ def solid(mesh, n: int, N: int, n_tau: int, beta: float, *, eps_window=(-1.5, 1.
                 kdiff=kdiff, ksum=ksum, kneg=kneg, rng=rng)
 
 
+def solid_screening_poles(wl: dict, n_poles: int = 8, amp=(0.01, 0.1),
+                          log10_w=(-1.0, 1.0)) -> list:
+    """The draws of add_dynamic_screening_solid without forming W: a list of
+    (a_k, pole_{w_k}(tau) [n_tau], S_k [n_k, N, N]) in drawing order, so that
+    W^q(tau_j) = sum_k a_k pole_k[j] S_k[q] can be assembled on a device."""
+    rng = wl["rng"]
+    N, tau, beta = wl["N"], wl["tau"], wl["beta"]
+    out = []
+    for _ in range(n_poles):
+        w = 10.0 ** rng.uniform(*log10_w)
+        a = rng.uniform(*amp)
+        S = paired_hermitian(rng, wl["kneg"], N, 1.0 / N)
+        out.append((a, periodic_bosonic_pole(tau, beta, w), S))
+    return out
+
+
 def add_dynamic_screening_solid(wl: dict, n_poles: int = 8, amp=(0.01, 0.1),
                                 log10_w=(-1.0, 1.0)) -> dict:
     """W^q(tau) = sum_k a_k pole_{w_k}(tau) S_k^q on a k-point workload, with
     each S_k^q momentum-paired Hermitian (S^{-q} = conj(S^q)); the pole
     parameters are drawn as for molecules.  Stored q-major: [n_k, n_tau, N, N]."""
-    rng = wl["rng"]
-    N, tau, beta = wl["N"], wl["tau"], wl["beta"]
+    N, tau = wl["N"], wl["tau"]
     W = np.zeros((wl["nk"], len(tau), N, N), dtype=complex)
-    for _ in range(n_poles):
-        w = 10.0 ** rng.uniform(*log10_w)
-        a = rng.uniform(*amp)
-        S = paired_hermitian(rng, wl["kneg"], N, 1.0 / N)
-        pole = periodic_bosonic_pole(tau, beta, w)
+    for a, pole, S in solid_screening_poles(wl, n_poles, amp, log10_w):
         W += a * pole[None, :, None, None] * S[:, None]
     wl.update(W_tau=W)
     return wl

@@ -5,6 +5,7 @@
 // buffer is allocated to its exact size.
 #include <vector>
 #include <cstdio>
+#include <string>
 thread_local uint3e threadIdx, blockIdx, blockDim, gridDim;
 const char* g_emu_kernel = "";
 // workspace guard: every carved buffer is followed by a poisoned gap
@@ -124,7 +125,67 @@ int run_solid_case(int n, int N, int nt, int prec, int entry, const int mesh[3])
   return st;
 }
 
+// Every tiled launcher refuses a grid whose x extent reaches 2^32
+// work-items (the 32-bit field of a dispatch packet) with hipErrorInvalidValue
+// and launches nothing (a launch would abort in the shim above).  The
+// arguments are otherwise valid, the pointers never dereferenced.
+int run_guards() {
+  using namespace sox;
+  static float fdummy[64];
+  static double ddummy[64];
+  static bf16_t bdummy[64];
+  int bad = 0;
+  auto expect = [&](const char* what, hipError_t e) {
+    printf("guard %-28s -> %s\n", what, e == hipErrorInvalidValue ? "refused" : "LAUNCHED");
+    if (e != hipErrorInvalidValue) ++bad;
+  };
+  {
+    HcArgs<float, double> a{};
+    a.nz = 32; a.nk = 16; a.ny = 64; a.n_ot = 1 << 12; a.n_ov = 1 << 12;
+    a.L = a.Rm = a.W = a.FT = fdummy; a.Out = ddummy;
+    expect("hc_kernel", launch_hc<float, double, 1, 4>(a, 64 * 1024, nullptr));
+  }
+  {
+    LdsFusedArgs a{};
+    a.nP = 16; a.NP = 128; a.tiles_p = a.tiles_r = 1; a.n_tau = 1 << 23; a.vsplit = 1; a.vchunk = 1;
+    a.u_rstride = 256; a.D = fdummy;
+    expect("fused_bcd_lds_kernel", launch_fused_lds<kLdsFp32, kFp32LdsPB>(a, nullptr));
+  }
+  {
+    DenseLdsArgs a{};
+    a.A = a.B = fdummy; a.C = fdummy; a.M = a.N = 1 << 22; a.K = 16; a.rgroup = 1; a.rvalid = 1;
+    a.lda = a.ldb = 16; a.ldc = 1 << 22;
+    expect("dense_lds_f32_kernel", launch_dense_lds_f32(a, 1, nullptr));
+  }
+  {
+    DenseLdsSplitArgs a{};
+    a.Ah = a.Al = a.Bh = a.Bl = bdummy; a.C = fdummy; a.M = a.N = 1 << 22; a.K = 32;
+    a.lda = a.ldb = 32; a.ldc = 1 << 22;
+    expect("dense_lds_bf16x3_kernel", launch_dense_lds_bf16x3<2>(a, 1, nullptr));
+  }
+  {
+    CgArgs<float, float> a = cg_args<float, float>();
+    a.A = a.B = fdummy; a.C = fdummy; a.M = a.N = 1 << 22; a.K = 16; a.ldA = a.ldB = 16;
+    a.ldc = 1 << 22;
+    expect("cgemm_nt_kernel", launch_cgemm<float, float, 2, 2, 2, 2>(a, 1, nullptr));
+    expect("cgemm_panel_kernel", launch_cgemm_panel(a, 1, true, nullptr));
+  }
+  {
+    DenseArgs<double, double> a{};
+    a.A = a.B = ddummy; a.C = ddummy; a.M = a.N = 1 << 22; a.K = 16;
+    expect("dense_nt_kernel", launch_dense<double, double, 1, 4, 2, 2>(a, 1, nullptr));
+  }
+  {
+    FusedArgs<float> a{};
+    a.tiles_p = a.tiles_r = 1 << 12; a.n_tau = 1 << 12; a.vsplit = 1;
+    expect("fused_bcd_kernel", launch_fused<float, 32, 32>(a, nullptr));
+  }
+  printf("guards: %d launched\n", bad);
+  return bad;
+}
+
 int main(int argc, char** argv) {
+  if (argc == 2 && std::string(argv[1]) == "guards") return run_guards();
   int n = atoi(argv[1]), N = atoi(argv[2]), nt = atoi(argv[3]), prec = atoi(argv[4]), entry = atoi(argv[5]), vjp = atoi(argv[6]);
   if (argc >= 10) {
     const int mesh[3] = {atoi(argv[7]), atoi(argv[8]), atoi(argv[9])};

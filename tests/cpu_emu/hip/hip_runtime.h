@@ -82,6 +82,13 @@ extern const char* g_emu_kernel;
 template <typename K, typename... A>
 inline void emu_launch(const char* name, K kernel, dim3 g, dim3 b, A... args) {
   g_emu_kernel = name;
+  // a real dispatch packet holds each extent in work-items as 32 bits: a
+  // launch past that would wrap on the device, so it stops the run here
+  if ((unsigned long long)g.x * b.x >= (1ull << 32) || (unsigned long long)g.y * b.y >= (1ull << 32) ||
+      (unsigned long long)g.z * b.z >= (1ull << 32)) {
+    fprintf(stderr, "emu: %s launched with a grid past 2^32 work-items\n", name);
+    abort();
+  }
   gridDim = {g.x, g.y, g.z}; blockDim = {b.x, b.y, b.z};
   for (unsigned bz = 0; bz < g.z; ++bz) for (unsigned by = 0; by < g.y; ++by) for (unsigned bx = 0; bx < g.x; ++bx)
     for (unsigned tz = 0; tz < b.z; ++tz) for (unsigned ty = 0; ty < b.y; ++ty) for (unsigned tx = 0; tx < b.x; ++tx) {

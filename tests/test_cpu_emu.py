@@ -155,3 +155,14 @@ def test_entry_point_in_bounds(emu, case):
                        capture_output=True, text=True, env=env, timeout=600)
     out = r.stdout + r.stderr
     assert r.returncode == 0 and "status 0" in out and "AddressSanitizer" not in out, out[-4000:]
+
+
+def test_launchers_refuse_grids_past_32bit_work_items(emu):
+    """A dispatch packet holds each grid extent in work-items as 32 bits: every
+    tiled launcher must refuse an x extent of 2^32 work-items or more with
+    hipErrorInvalidValue instead of launching (the shim aborts on any such
+    launch, here and in every case above)."""
+    r = subprocess.run([emu, "guards"], capture_output=True, text=True,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"), timeout=120)
+    out = r.stdout + r.stderr
+    assert r.returncode == 0 and "guards: 0 launched" in out, out[-4000:]

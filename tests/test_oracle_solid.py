@@ -187,3 +187,51 @@ def test_dynamic_supercell_unfolding(L):
                                      tp["T_fwd"], tp["T_bwd"], tb)
     pred = np.einsum("kR,tRab->ktab", ph(1), sig)
     assert np.abs(Sk - pred).max() <= 1e-13 * np.abs(pred).max()
+
+
+def _column_supported(wl, cols):
+    """The workload with X^k zero outside the THC columns `cols`, and the
+    reduced problem (X^k, U^q restricted to those columns)."""
+    X = np.zeros_like(wl["X"])
+    X[:, :, cols] = wl["X"][:, :, cols]
+    return X, wl["X"][:, :, cols], wl["V"][:, cols][:, :, cols]
+
+
+def test_v_subsets_add_up_and_column_support_reduces():
+    """Sigma is linear in the per-v terms of the D sum, so the chain over
+    disjoint v subsets adds up to the full chain; and a collocation matrix
+    supported on a column subset S gives the reduced problem's Sigma (every
+    THC index carries two X factors).  Both facts are what the full-size GPU
+    checks rely on."""
+    wl = synth.solid((3, 1, 1), 5, 11, 4, 5.0, seed=12)
+    rng = np.random.default_rng(3)
+    G = osd.g_tau_k(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    G = G + 0.05 * (rng.standard_normal(G.shape) + 1j * rng.standard_normal(G.shape))
+    tb = _tables(wl)
+    full = osd.sigma_solid_thc(wl["X"], wl["V"], wl["V"], G, tb)
+    parts = sum(osd.sigma_solid_thc(wl["X"], wl["V"], wl["V"], G, tb, v_subset=vs)
+                for vs in ([0, 3], [1], [2, 4]))
+    assert np.abs(parts - full).max() <= 1e-14 * np.abs(full).max()
+    cols = np.array([1, 4, 5, 9])
+    Xc, Xs, Vs = _column_supported(wl, cols)
+    a = osd.sigma_solid_thc(Xc, wl["V"], wl["V"], G, tb)
+    b = osd.sigma_solid_thc(Xs, Vs, Vs, G, tb)
+    assert np.abs(a - b).max() <= 1e-14 * np.abs(b).max()
+
+
+def test_dynamic_v_subsets_add_up_and_column_support_reduces():
+    wl = _dyn_solid((2, 1, 1), 4, 9, 10, 8.0, seed=13)
+    tp = _pair(wl["tau"], wl["beta"])
+    G = osd.g_tau_k(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    tb = _tables(wl)
+    args = (tp["T_fwd"], tp["T_bwd"], tb)
+    full = osd.sigma_solid_dynamic_thc(wl["X"], wl["W_tau"], wl["V"], G, *args)
+    parts = sum(osd.sigma_solid_dynamic_thc(wl["X"], wl["W_tau"], wl["V"], G, *args, v_subset=vs)
+                for vs in ([0, 2], [1, 3]))
+    assert np.abs(parts - full).max() <= 1e-13 * np.abs(full).max()
+    cols = np.array([0, 3, 7])
+    Xc, Xs, Vs = _column_supported(wl, cols)
+    Ws = np.ascontiguousarray(wl["W_tau"][:, :, cols][:, :, :, cols])
+    a = osd.sigma_solid_dynamic_thc(Xc, wl["W_tau"], wl["V"], G, *args)
+    b = osd.sigma_solid_dynamic_thc(Xs, Ws, Vs, G, *args)
+    assert np.abs(a - b).max() <= 1e-13 * np.abs(b).max()
