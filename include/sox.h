@@ -161,6 +161,25 @@ sox_status sox_workspace_size(const sox_plan* plan, int32_t entry, size_t* bytes
 sox_status sox_sigma_bare(sox_plan* plan, const double* X, const double* V, const double* G,
                           double* Sigma, void* workspace, size_t workspace_bytes, void* stream);
 
+/* sox_sigma_bare without a caller workspace, for callers that cannot
+ * allocate device memory around the call: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  The call itself
+ * allocates nothing (no hipMalloc / hipFree, no graph, no profiling events;
+ * profiling records nothing for it).  Its workspace is a file-scope device
+ * array of 256 MiB that every GPU the library runs on holds from the first
+ * such call until the process ends.  Arguments, result and errors as
+ * sox_sigma_bare, plus:
+ *   - SOX_ERR_WORKSPACE when the plan's bare-entry workspace
+ *     (sox_workspace_size) exceeds 256 MiB; a plan created with
+ *     SOX_WS_BUDGET_MB=256 or less picks tau slabs that fit;
+ *   - SOX_ERR_INVALID_ARG when the current device is not the plan's.
+ * Every call on one GPU shares that GPU's array and leaves its contents
+ * behind (nothing in it must start at zero): calls that overlap in time on
+ * one GPU (several streams or host threads) race, so the caller serialises
+ * them. */
+sox_status sox_sigma_bare_noalloc(sox_plan* plan, const double* X, const double* V,
+                                  const double* G, double* Sigma, void* stream);
+
 /* Sigma = SOX(U1 = W0, U2 = V): the statically screened interaction W0 =
  * W(Omega = 0) (bare part included) on line 1 of eq:sox, the bare V on line
  * 2.  Shapes as sox_sigma_bare; W0 [N,N] symmetric. */

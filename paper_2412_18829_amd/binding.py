@@ -30,6 +30,7 @@ EXPORTED = (
     "sox_sigma_static", "sox_sigma_dynamic", "sox_sigma_vjp", "sox_build_g_tau",
     "sox_energy_gm", "sox_energy_gm_device", "sox_sync", "sox_last_error", "sox_abi_version", "sox_profile_enable",
     "sox_profile_read", "sox_profile_select", "sox_plan_set_graph", "sox_plan_describe",
+    "sox_sigma_bare_noalloc",
 )
 STAGES = ("gbuild", "utensor", "project", "astep", "fused", "back", "energy", "gg_ft", "wgemm",
           "ift", "split", "vjp", "kbc", "kd")
@@ -69,6 +70,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.sox_workspace_size.argtypes = [vp, i32, ctypes.POINTER(sz)]
     L.sox_sigma_bare.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_sigma_static.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.sox_sigma_bare_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
     L.sox_sigma_dynamic.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_sigma_vjp.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_build_g_tau.argtypes = [vp, vp, vp, dp, vp, vp]
@@ -232,6 +234,16 @@ def sox_sigma_bare(plan: Plan, X, V, G, Sigma, ws=None, stream=None):
     _check(load().sox_sigma_bare(plan.handle, t(X, (n, N), "X"), t(V, (N, N), "V"),
                                  t(G, (nt, n, n), "G"), t(Sigma, (nt, n, n), "Sigma"),
                                  w, wb, _stream(stream)), "sox_sigma_bare")
+    return Sigma
+
+
+def sox_sigma_bare_noalloc(plan: Plan, X, V, G, Sigma, stream=None):
+    """sox_sigma_bare on the library's static scratch array (no workspace)."""
+    n, N, nt = plan.n, plan.N, plan.n_tau
+    t = plan._t
+    _check(load().sox_sigma_bare_noalloc(plan.handle, t(X, (n, N), "X"), t(V, (N, N), "V"),
+                                         t(G, (nt, n, n), "G"), t(Sigma, (nt, n, n), "Sigma"),
+                                         _stream(stream)), "sox_sigma_bare_noalloc")
     return Sigma
 
 

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1689,6 +1690,41 @@ sox_status dispatch_static(sox_plan* plan, int entry, const double* X, const dou
 
 }  // namespace
 
+// -- the no-allocation entry point ---------------------------------------------
+// sox_sigma_bare_noalloc takes its workspace from this file-scope array
+// instead of a caller buffer.  Each GPU the library runs on holds its own copy
+// until the process ends.  Host code never uses the array's name as an
+// address: the device address is resolved per device with
+// hipGetSymbolAddress (with that device current) and kept in
+// g_scratch_dev[device].
+constexpr size_t kNoallocScratchBytes = size_t(256) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+namespace {
+constexpr int kNoallocMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kNoallocMaxDevices] = {};
+
+// The device address of `scratch` on the current device, resolved on the
+// first call from that device.
+sox_status noalloc_scratch(int device, void** out) {
+  if (device < 0 || device >= kNoallocMaxDevices)
+    return fail(SOX_ERR_UNSUPPORTED, "device %d: the no-allocation entry supports devices 0..%d",
+                device, kNoallocMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(SOX_ERR_HIP, "hipGetSymbolAddress of the static scratch array failed: %s",
+                  hipGetErrorString(e));
+    g_scratch_dev[device] = ptr;
+  }
+  *out = g_scratch_dev[device];
+  return SOX_OK;
+}
+}  // namespace
+
 // =============================================================================
 extern "C" {
 
@@ -1917,6 +1953,42 @@ sox_status sox_sigma_static(sox_plan* plan, const double* X, const double* W0, c
                             const double* G, double* Sigma, void* ws, size_t ws_bytes,
                             void* stream) {
   return dispatch_static(plan, SOX_ENTRY_STATIC, X, W0, V, G, Sigma, ws, ws_bytes, stream);
+}
+
+sox_status sox_sigma_bare_noalloc(sox_plan* plan, const double* X, const double* V,
+                                  const double* G, double* Sigma, void* stream) {
+  sox_status st = check_plan(plan);
+  if (st) return st;
+  if (!X || !V || !G || !Sigma) return fail(SOX_ERR_INVALID_ARG, "NULL tensor pointer");
+  const size_t need = workspace_bytes(*plan, SOX_ENTRY_BARE);
+  if (need > kNoallocScratchBytes)
+    return fail(SOX_ERR_WORKSPACE,
+                "the bare entry of this plan needs %zu workspace bytes, more than the %zu-byte "
+                "static scratch array (a plan made under SOX_WS_BUDGET_MB=%zu picks tau slabs "
+                "that fit)",
+                need, kNoallocScratchBytes, kNoallocScratchBytes >> 20);
+  int device = -1;
+  SOX_HIP(hipGetDevice(&device));
+  if (device != plan->device)
+    return fail(SOX_ERR_INVALID_ARG, "current device %d is not the plan's device %d", device,
+                plan->device);
+  void* ws = nullptr;
+  if ((st = noalloc_scratch(device, &ws))) return st;
+  // no graph capture and no profiling events: nothing in this call
+  // allocates (event pools grow with hipEventCreate)
+  const bool prof = plan->prof_on;
+  plan->prof_on = false;
+  const hipStream_t s = (hipStream_t)stream;
+  if (plan->nk > 1)
+    st = plan->precision == SOX_FP64
+             ? run_solid<double>(*plan, SOX_ENTRY_BARE, X, V, V, G, Sigma, ws, s)
+             : run_solid<float>(*plan, SOX_ENTRY_BARE, X, V, V, G, Sigma, ws, s);
+  else
+    st = plan->precision == SOX_FP64
+             ? run_static<double>(*plan, SOX_ENTRY_BARE, X, V, V, G, Sigma, ws, s)
+             : run_static<float>(*plan, SOX_ENTRY_BARE, X, V, V, G, Sigma, ws, s);
+  plan->prof_on = prof;
+  return st;
 }
 
 sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_tau,

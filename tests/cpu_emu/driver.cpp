@@ -184,8 +184,42 @@ int run_guards() {
   return bad;
 }
 
+// The no-allocation bare entry on the static scratch array: a plan whose
+// bare workspace exceeds the array is refused, then two calls in a row (the
+// second on a smaller problem) run inside the array's bounds.
+int run_noalloc(int prec) {
+  const int shapes[3][3] = {{64, 384, 64}, {13, 70, 5}, {6, 20, 3}};
+  int rc = 0;
+  for (int c = 0; c < 3; ++c) {
+    const int n = shapes[c][0], N = shapes[c][1], nt = shapes[c][2];
+    std::vector<double> tau(nt), w(nt, 1.0);
+    for (int k = 0; k < nt; ++k) tau[k] = 5.0 * (k + 0.5) / nt;
+    sox_problem pr{};
+    pr.n_orb = n; pr.n_thc = N; pr.n_tau = nt; pr.kmesh[0] = pr.kmesh[1] = pr.kmesh[2] = 1;
+    pr.beta = 5.0; pr.tau = tau.data(); pr.weights = w.data();
+    sox_plan* plan = nullptr;
+    if (sox_plan_create(&pr, prec, &plan)) { printf("create failed: %s\n", sox_last_error()); return 1; }
+    size_t wsb = 0;
+    sox_workspace_size(plan, SOX_ENTRY_BARE, &wsb);
+    double* X = dalloc((size_t)n * N);
+    double* V = dalloc((size_t)N * N);
+    double* G = dalloc((size_t)nt * n * n);
+    double* S = dalloc((size_t)nt * n * n);
+    const sox_status st = sox_sigma_bare_noalloc(plan, X, V, G, S, nullptr);
+    const sox_status want = wsb > kNoallocScratchBytes ? SOX_ERR_WORKSPACE : SOX_OK;
+    printf("noalloc n=%d N=%d nt=%d prec=%d ws=%zu -> status %d (want %d) %s\n", n, N, nt, prec,
+           wsb, st, want, st ? sox_last_error() : "");
+    if (st != want) rc = 1;
+    free(X); free(V); free(G); free(S);
+    sox_plan_destroy(plan);
+  }
+  printf("noalloc %s\n", rc ? "FAILED" : "ok");
+  return rc;
+}
+
 int main(int argc, char** argv) {
   if (argc == 2 && std::string(argv[1]) == "guards") return run_guards();
+  if (argc == 3 && std::string(argv[1]) == "noalloc") return run_noalloc(atoi(argv[2]));
   int n = atoi(argv[1]), N = atoi(argv[2]), nt = atoi(argv[3]), prec = atoi(argv[4]), entry = atoi(argv[5]), vjp = atoi(argv[6]);
   if (argc >= 10) {
     const int mesh[3] = {atoi(argv[7]), atoi(argv[8]), atoi(argv[9])};

@@ -166,3 +166,14 @@ def test_launchers_refuse_grids_past_32bit_work_items(emu):
                        env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"), timeout=120)
     out = r.stdout + r.stderr
     assert r.returncode == 0 and "guards: 0 launched" in out, out[-4000:]
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_noalloc_entry_in_bounds(emu, prec):
+    """sox_sigma_bare_noalloc on its static scratch array: an oversize plan is
+    refused with SOX_ERR_WORKSPACE, two later calls (the second smaller)
+    stay inside the array (AddressSanitizer guards the global)."""
+    r = subprocess.run([emu, "noalloc", str(prec)], capture_output=True, text=True,
+                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"), timeout=600)
+    out = r.stdout + r.stderr
+    assert r.returncode == 0 and "noalloc ok" in out and "AddressSanitizer" not in out, out[-4000:]
