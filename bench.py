@@ -7,17 +7,23 @@ step (or, for the dynamic interaction, GG -> FT -> W(Omega) GG(Omega) -> IFT),
 the B, C -> D contraction, the back-transform to orbitals (all tau nodes and
 momenta: one "sweep") and the Galitskii-Migdal energy (queued into device
 memory each step, read after the timed region).  Inputs are seeded and
-synthetic and resident in HBM before the timed region.  The default workload
-is the bare molecule n=64, N=384, 64 tau nodes, beta=50; --workload selects
-the others (3: static screening n=200 N=1200; 4: dynamic screening n=300
-N=1800; 5: 3x3x3 k-point solid n=52 N=400).
+synthetic and resident in HBM before the timed region.
 
-Prints ONE JSON line.  `value` is sweeps/s of the chosen precision path
-(float32 MFMA contractions by default); the float64 path is timed on the
-same inputs for the mixed-vs-FP64 comparison, the FP64 CPU oracle is timed
-on the host as a baseline where a bounded sample of it fits, and the
-dominant kernel's roofline fraction is measured with HIP events on the
-stream it runs on.
+The default workload (5) is the largest: the 3x3x3 k-point solid, n=52 and
+N=400 per k, 100 tau nodes, beta=100, with an 8-pole W^q(tau); its step is
+the bare plus dynamically screened SOX self-energy SOX(V,V) + SOX(W_d(tau),V)
+in one pass (sox_sigma_vertex, SOSEX_dyn), in bf16x3 by default.
+--workload selects the molecules (1, 2: bare n=8 / n=64; 3: static
+screening n=200 N=1200; 4: dynamic screening n=300 N=1800).
+
+Prints ONE JSON line.  `value` is sweeps/s of the chosen precision path; the
+float64 path is timed on the same inputs for the mixed-vs-FP64 comparison,
+max_rel_err is taken against the FP64 oracle (for the solid: a sweep of the
+same launch configuration on a column-supported collocation matrix, against
+the oracle values stored by tests/golden/make_c5_reference.py), the oracle
+is timed on the host as a baseline on a bounded sample, and the dominant
+kernel's roofline fraction is measured with HIP events on the stream it runs
+on.
 """
 from __future__ import annotations
 
@@ -40,11 +46,12 @@ WORKLOADS = {
     2: ("molecule bare SOX n=64 N=384 n_tau=64 beta=50", "bare"),
     3: ("molecule static SOX n=200 N=1200 n_tau=100 beta=100, W0 = V + V Pi V", "static"),
     4: ("molecule dynamic SOX n=300 N=1800 n_tau=120 beta=100, 8-pole W(tau)", "dynamic"),
-    5: ("solid bare + dynamic SOX 3x3x3 k-mesh n=52 N=400 n_tau=100 beta=100, 8-pole W^q(tau)",
-        "solid"),
+    5: ("solid SOX(V,V) + SOX(W_d(tau),V) 3x3x3 k-mesh n=52 N=400 n_tau=100 beta=100, "
+        "8-pole W^q(tau)", "solid"),
 }
 ENTRY = {"bare": "sox_sigma_bare", "static": "sox_sigma_static", "dynamic": "sox_sigma_dynamic",
-         "solid": "sox_sigma_bare + sox_sigma_dynamic"}
+         "solid": "sox_sigma_vertex (SOSEX_dyn, bare and dynamic terms in one pass)"}
+GOLDEN_C5 = os.path.join(ROOT, "tests", "golden", "c5_sosex_dyn_support8.npz")
 # dominant kernel per kind: (profiling stage, kernel name)
 # the fused kernel each molecular configuration launches (rocprofv3 names)
 FUSED_KERNEL = {0: "fused_bcd_kernel<float|double, 32, 32>", 3: "fused_bcd_kernel<float, 64, 64>",
@@ -62,22 +69,24 @@ def flops_per_sweep(n: int, N: int, nt: int, kind: str = "bare", n_omega: int = 
     is reported but excluded from the sweep total by the caller (it is set up
     once per X and U)."""
     if kind == "solid":
-        # bare and dynamic entries on the same mesh (one step runs both)
+        # SOX(V,V) + SOX(W_d,V) in one pass: the bare A step and its product
+        # with G(tau) join the dynamic chain's A(tau); B, C, D and the
+        # back-transform run once (complex multiply-adds: 8 real FLOPs)
         np2 = nk * nk
         nw = n_omega
         return {
             "gbuild": nk * nt * 8.0 * n ** 3,
-            "utensor": 2 * np2 * 8.0 * N * N * n * n,
-            "project": nt * nk * 5 * 8.0 * N * n * n,
-            "astep": nt * np2 * 8.0 * N * n ** 3,
+            "utensor": np2 * 8.0 * N * N * n * n,
+            "project": nt * nk * 3 * 8.0 * N * n * n,
+            "astep": nt * np2 * 2 * 8.0 * N * n ** 3,
             "gg_ft": 2 * 8.0 * nw * nt * nk * N * N + nt * np2 * N * n * n * 6.0
                      + 2 * 8.0 * nw * nt * np2 * N * n * n,
             "wgemm": 2 * nw * np2 * 8.0 * N * N * n * n,
             "ift": 8.0 * nt * 2 * nw * np2 * N * n * n,
-            "kbc": 2 * nt * np2 * 2 * 8.0 * N * N * n * n,
-            "kd": 2 * nt * nk ** 3 * 8.0 * N * N * n,
-            "back": 2 * nt * nk * 8.0 * (N * N * n + N * n * n),
-            "energy": 2 * nk * nt * 8.0 * n * n,
+            "kbc": nt * np2 * 2 * 8.0 * N * N * n * n,
+            "kd": nt * nk ** 3 * 8.0 * N * N * n,
+            "back": nt * nk * 8.0 * (N * N * n + N * n * n),
+            "energy": nk * nt * 8.0 * n * n,
         }
     f = {
         "gbuild": nt * 2.0 * n ** 3,
@@ -90,7 +99,8 @@ def flops_per_sweep(n: int, N: int, nt: int, kind: str = "bare", n_omega: int = 
     if kind == "dynamic":
         f["utensor"] = 2.0 * N * N * n * n
         f["gg_ft"] = nt * N * n * n + 4.0 * n_omega * nt * N * n * n
-        f["wgemm"] = n_omega * 8.0 * N * N * n * n
+        # a real W(Omega) times a complex GG(Omega): 4 N^2 n^2 per frequency
+        f["wgemm"] = n_omega * 4.0 * N * N * n * n
         f["ift"] = 4.0 * n_omega * nt * N * n * n
     else:
         f["astep"] = nt * 2.0 * N * n ** 3
@@ -122,6 +132,16 @@ def read_traffic(workload: int, precision: str):
         return float(kv["hbm_bytes_per_launch"])
     except (KeyError, ValueError):
         return None
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def blas_threads() -> int:
@@ -175,15 +195,51 @@ def cpu_oracle_baseline(wl: dict, kind: str, budget_s: float):
     return None, None
 
 
+def cpu_oracle_solid(wl: dict, poles: list, tp: dict, cols) -> dict:
+    """Oracle sample of the solid step SOX(V,V) + SOX(W_d,V).  At the full
+    THC rank one oracle node and orbital v already take minutes on the host,
+    so the sample is the same workload (mesh, n, tau grid, inputs) with the
+    collocation matrix restricted to the `cols` support: the eq:GG chain for
+    one orbital v (all nodes and momenta; the chain is a sum over v) and the
+    static chain for one mirror pair of nodes (independent per node),
+    scaled to one sweep of that reduced-rank problem."""
+    from oracle import sox_solid as osd
+    nt, n = wl["n_tau"], wl["n"]
+    tb = (wl["kvecs"], wl["kdiff"], wl["ksum"], wl["kneg"])
+    Xs = wl["X"][:, :, cols]
+    Vs = wl["V"][:, cols][:, :, cols]
+    Ws = sum(a * pole[None, :, None, None] * S[:, None][:, :, cols][:, :, :, cols]
+             for a, pole, S in poles)
+    c0 = time.perf_counter()
+    G = osd.g_tau_k(wl["eps"], wl["Q"], wl["mu"], wl["beta"], wl["tau"])
+    osd.sigma_solid_dynamic_thc(Xs, Ws, Vs, G, tp["T_fwd"], tp["T_bwd"], tb, v_subset=[0])
+    t_dyn = time.perf_counter() - c0
+    c1 = time.perf_counter()
+    osd.sigma_solid_thc(Xs, Vs, Vs, G[:, [0, nt - 1]], tb)
+    t_bare = time.perf_counter() - c1
+    sweep = n * t_dyn + (nt / 2) * t_bare
+    return {"value": 1.0 / sweep, "unit": "sweeps/s", "cores": blas_threads(),
+            "host_cpus": len(os.sched_getaffinity(0)), "cpu_model": cpu_model(),
+            "kind": "oracle", "extrapolated": True,
+            "sample": (f"numpy complex128 oracle on the same workload reduced to a "
+                       f"{len(cols)}-of-{wl['N']}-column THC support (reduced rank: the full-rank "
+                       f"oracle takes minutes per node and orbital): the eq:GG chain for 1 of {n} "
+                       f"orbitals v ({t_dyn:.1f} s, all {nt} nodes and {wl['nk']} momenta, "
+                       f"linear in v) and the static chain for 1 mirror pair of nodes "
+                       f"({t_bare:.1f} s, linear in the nodes), scaled to one sweep of that "
+                       f"reduced-rank problem")}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None,
-                    help="timed steps (default by workload: 100, 100, 5, 3, 2)")
+                    help="timed steps (default by workload: 100, 100, 5, 3, 5)")
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed steps first (default by workload: 10, 10, 1, 1, 1)")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16x3"])
-    ap.add_argument("--workload", type=int, default=2, choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default=None, choices=["fp32", "fp64", "bf16x3"],
+                    help="default: bf16x3 for the solid, fp32 for the molecules")
+    ap.add_argument("--workload", type=int, default=5, choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64-compare", action="store_true")
     ap.add_argument("--no-bf16x3-compare", action="store_true",
@@ -206,9 +262,11 @@ def main() -> int:
     # defaults keep each timed region under a minute; the small workloads run
     # long enough for the clocks to settle and the launch ramp to amortise
     if args.steps is None:
-        args.steps = {1: 100, 2: 100, 3: 5, 4: 3, 5: 2}[args.workload]
+        args.steps = {1: 100, 2: 100, 3: 5, 4: 3, 5: 5}[args.workload]
     if args.warmup is None:
         args.warmup = {1: 10, 2: 10}.get(args.workload, 1)
+    if args.precision is None:
+        args.precision = "bf16x3" if kind == "solid" else "fp32"
     import numpy as np
     import torch
 
@@ -225,11 +283,15 @@ def main() -> int:
     t = lambda a, dt=cdt: torch.as_tensor(np.ascontiguousarray(a), dtype=dt, device=dev)
     X, V, Q = t(wl["X"]), t(wl["V"]), t(wl["Q"])
     eps = t(wl["eps"], torch.float64)
+    poles = None
     if solid:
-        synth.add_dynamic_screening_solid(wl)
-    U1 = t(wl["W0"]) if kind == "static" else (t(wl["W_tau"]) if kind in ("dynamic", "solid") else V)
-    if solid:
-        wl.pop("W_tau")
+        # W^q(tau_j) = sum_k a_k pole_k(tau_j) S_k^q, assembled on the device
+        poles = synth.solid_screening_poles(wl)
+        U1 = torch.zeros((nk, nt, N, N), dtype=cdt, device=dev)
+        for a, pole, S_k in poles:
+            U1 += t(a * pole)[None, :, None, None] * t(S_k)[:, None]
+    else:
+        U1 = t(wl["W0"]) if kind == "static" else (t(wl["W_tau"]) if kind == "dynamic" else V)
     tp = None
     if kind in ("dynamic", "solid"):
         tp = synth.bosonic_transform_pair(wl["tau"], wl["beta"], omega_max=14.0, tol=1e-10)
@@ -244,7 +306,12 @@ def main() -> int:
         torch.cuda.synchronize()
         del a, b
 
-    def run(precision: str, steps: int, warmup: int, profile: bool):
+    def run(precision: str, steps: int, warmup: int, profile: bool, Xwarm=None):
+        """warmup untimed steps, then `steps` timed ones.  Xwarm: the first
+        warmup step runs on this collocation matrix instead (its Sigma is
+        returned as Sigma_warm), and with profile the last warmup step records
+        every stage (the per-stage breakdown), so neither costs extra steps."""
+        Xr = X
         extra = {}
         if tp is not None:
             extra = dict(t_fwd=tp["T_fwd"], t_bwd=tp["T_bwd"])
@@ -253,10 +320,7 @@ def main() -> int:
         G = torch.empty(gshape, dtype=cdt, device=dev)
         S = torch.empty_like(G)
         entry = "static" if kind == "static" else ("dynamic" if kind == "dynamic" else "bare")
-        ws = plan.workspace(entry)
-        if solid:  # one buffer serves both entries
-            ws = torch.empty(max(plan.workspace_size("bare"), plan.workspace_size("dynamic")) + 256,
-                             dtype=torch.uint8, device=dev)
+        ws = plan.workspace("vertex" if solid else entry)
         # the energy of every step is queued into device memory (no host
         # synchronisation per step) and read after the timed region
         E = torch.zeros((warmup + steps + 3, 2), dtype=torch.float64, device=dev)
@@ -266,19 +330,36 @@ def main() -> int:
             B.sox_build_g_tau(plan, Q, eps, wl["mu"], G)
             e = E[cur[0]]
             if kind == "static":
-                B.sox_sigma_static(plan, X, U1, V, G, S, ws=ws)
+                B.sox_sigma_static(plan, Xr, U1, V, G, S, ws=ws)
             elif kind == "dynamic":
-                B.sox_sigma_dynamic(plan, X, U1, V, G, S, ws=ws)
+                B.sox_sigma_dynamic(plan, Xr, U1, V, G, S, ws=ws)
             elif solid:
-                B.sox_sigma_bare(plan, X, V, G, S, ws=ws)
-                B.sox_energy_gm_device(plan, S, G, e[1])
-                B.sox_sigma_dynamic(plan, X, U1, V, G, S, ws=ws)
+                B.sox_sigma_vertex(plan, "sosex_dyn", Xr, V, U1, G, S, ws=ws)
             else:
-                B.sox_sigma_bare(plan, X, V, G, S, ws=ws)
+                B.sox_sigma_bare(plan, Xr, V, G, S, ws=ws)
             B.sox_energy_gm_device(plan, S, G, e[0])
             cur[0] += 1
 
-        for _ in range(warmup):
+        sig_warm = None
+        for w in range(warmup):
+            if w == 0 and Xwarm is not None:
+                Xr = Xwarm
+                step()
+                torch.cuda.synchronize()
+                sig_warm = S.cpu().numpy()
+                Xr = X
+                continue
+            if profile and w == warmup - 1 and warmup >= 2:
+                B.sox_profile_select(plan, None)
+                B.sox_profile_enable(plan, True)
+                B.sox_profile_read(plan, reset=True)
+                step()
+                torch.cuda.synchronize()
+                stages_warm = {k: round(v[0], 4) for k, v in
+                               B.sox_profile_read(plan, reset=True).items()
+                               if k != "dropped" and v[1] > 0}
+                B.sox_profile_enable(plan, False)
+                continue
             step()
         torch.cuda.synchronize()
         if profile:
@@ -295,23 +376,40 @@ def main() -> int:
         prof = stages = None
         if profile:
             prof = B.sox_profile_read(plan, reset=True)
-            # the per-stage breakdown from a short untimed pass with every
-            # stage recorded
-            B.sox_profile_select(plan, None)
-            kb = min(steps, 3)
-            for _ in range(kb):
-                step()
-            torch.cuda.synchronize()
-            stages = {k: round(v[0] / kb, 4) for k, v in B.sox_profile_read(plan, reset=True).items()
-                      if k != "dropped" and v[1] > 0}
+            if warmup >= 2:
+                stages = stages_warm
+            else:
+                # the per-stage breakdown from a short untimed pass with every
+                # stage recorded
+                B.sox_profile_select(plan, None)
+                kb = min(steps, 1 if solid else 3)
+                for _ in range(kb):
+                    step()
+                torch.cuda.synchronize()
+                stages = {k: round(v[0] / kb, 4) for k, v in
+                          B.sox_profile_read(plan, reset=True).items()
+                          if k != "dropped" and v[1] > 0}
             B.sox_profile_enable(plan, False)
         energies = E.cpu().numpy()[:cur[0]]
-        return dict(seconds=t1 - t0, Sigma=S.cpu().numpy(), prof=prof, stages=stages,
-                    energy=float(energies[warmup + steps - 1, 0]),
-                    energy_spread=float(np.ptp(energies[:, 0])),
-                    plan=B.sox_plan_describe(plan))
+        res = dict(seconds=t1 - t0, Sigma=S.cpu().numpy(), prof=prof, stages=stages,
+                   Sigma_warm=sig_warm,
+                   energy=float(energies[warmup + steps - 1, 0]),
+                   energy_spread=float(np.ptp(energies[:, 0])),
+                   plan=B.sox_plan_describe(plan))
+        # release this plan's workspace before the next leg builds its own
+        del plan, ws, G, S, E
+        torch.cuda.empty_cache()
+        return res
 
-    main_run = run(args.precision, args.steps, args.warmup, profile=True)
+    gold = Xc = None
+    if solid and os.path.exists(GOLDEN_C5):
+        # the error run: the first warmup step on a collocation matrix supported
+        # on the stored oracle reference's columns (same launch configuration)
+        gold = np.load(GOLDEN_C5)
+        Xc = torch.zeros_like(X)
+        Xc[:, :, gold["cols"]] = X[:, :, gold["cols"]]
+        args.warmup = max(args.warmup, 1)
+    main_run = run(args.precision, args.steps, args.warmup, profile=True, Xwarm=Xc)
     sec = main_run["seconds"]
     ms_per_step = 1e3 * sec / args.steps
     value = args.steps / sec
@@ -337,8 +435,18 @@ def main() -> int:
     out = {}
     r64 = rb = None
     if not args.no_fp64_compare and args.precision != "fp64":
-        k64 = max(1, args.steps // 2)
-        r64 = run("fp64", k64, 1, profile=False)
+        # the solid's float64 sweep takes tens of seconds: one sweep, no warmup
+        k64 = 1 if solid else max(1, args.steps // 2)
+        r64 = run("fp64", k64, 0 if solid else 1, profile=False)
+    solid_err = None
+    if gold is not None:
+        got = main_run["Sigma_warm"][gold["k"]][:, gold["nodes"]]
+        ref = gold["sigma"]
+        solid_err = {"max_rel_err": float(np.abs(got - ref).max() / np.abs(ref).max()),
+                     "against": ("FP64 oracle (tests/golden/c5_sosex_dyn_support8.npz) on the "
+                                 f"workload with X restricted to {len(gold['cols'])} of {N} THC "
+                                 f"columns, first warmup step; momenta {list(gold['k'])}, nodes "
+                                 f"{list(gold['nodes'])}")}
     if (args.precision == "fp32" and kind in ("bare", "static", "dynamic") and not solid
             and not args.no_bf16x3_compare):
         # the split-precision path on the same workload, same step
@@ -373,7 +481,10 @@ def main() -> int:
     # (bare molecules) is also the FP64 reference of max_rel_err
     cpu = ref = None
     if not args.no_cpu_baseline:
-        cpu, ref = cpu_oracle_baseline(wl, kind, args.cpu_seconds)
+        if solid:
+            cpu = cpu_oracle_solid(wl, poles, tp, synth.column_support(N, 1, 502))
+        else:
+            cpu, ref = cpu_oracle_baseline(wl, kind, args.cpu_seconds)
     out["cpu_baseline"] = cpu
     if cpu is None:
         out["cpu_baseline_note"] = ("not run: " + ("disabled by flag" if args.no_cpu_baseline else
@@ -385,6 +496,9 @@ def main() -> int:
         return float(np.abs(S - ref).max() / np.abs(ref).max())
 
     main_err = err_of(main_run["Sigma"])
+    if solid_err is not None:
+        main_err = solid_err["max_rel_err"]
+        out["max_rel_err_reference"] = solid_err["against"]
     if r64 is not None:
         s64 = r64["seconds"] / k64
         d = np.abs(main_run["Sigma"] - r64["Sigma"]).max() / np.abs(r64["Sigma"]).max()
@@ -421,13 +535,15 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": DTYPE_NAME[args.precision] if not solid else "c" + DTYPE_NAME[args.precision],
+        "dtype": (DTYPE_NAME[args.precision] if not solid
+                  else "c" + DTYPE_NAME[args.precision] if args.precision != "bf16x3"
+                  else "c64-bf16x3"),
         "data": "synthetic",
         "config": {"workload": desc, "entry": ENTRY[kind], "n_orb": n, "n_thc": N, "n_tau": nt,
                    "beta": wl["beta"], "kmesh": list(wl.get("mesh", (1, 1, 1))),
                    "n_omega": n_omega, "precision": args.precision,
-                   "step": ("G(tau) + Sigma(all tau" + (", all k; bare and dynamic" if solid else "")
-                            + ") + E_GM")},
+                   "step": ("G(tau) + Sigma(all tau" + (", all k; SOX(V,V) + SOX(W_d,V)" if solid
+                                                          else "") + ") + E_GM")},
         "tflops_alg": sweep_flops / (ms_per_step * 1e-3) / 1e12,
         "energy_gm": main_run["energy"],
         "energy_gm_spread_over_steps": main_run["energy_spread"],

@@ -107,8 +107,25 @@ typedef enum { SOX_FP64 = 0, SOX_FP32 = 1, SOX_BF16X3 = 2 } sox_precision;
 typedef enum {
   SOX_ENTRY_BARE = 0,    /* SOX(V, V)                                        */
   SOX_ENTRY_STATIC = 1,  /* SOX(W0, V), W0 = W(Omega = 0)                    */
-  SOX_ENTRY_DYNAMIC = 2  /* SOX(W_d(tau), V)                                 */
+  SOX_ENTRY_DYNAMIC = 2, /* SOX(W_d(tau), V)                                 */
+  SOX_ENTRY_VERTEX = 3   /* sox_sigma_vertex, every kind (workspace only)    */
 } sox_entry;
+
+/* Composite vertex self-energies of the paper's diagram family (fig:diag;
+ * the G3W2stat decomposition in "Total energies and self-energies"), W =
+ * V + W_d split into its bare and dynamic parts:
+ *   SOX_VERTEX_SOSEX_STAT   SOX(W0, V)                   statically screened SOSEX
+ *   SOX_VERTEX_2SOSEX_STAT  SOX(V,V) + SOX(V,Wd0) + SOX(Wd0,V), Wd0 = W0 - V
+ *   SOX_VERTEX_G3W2_STAT    SOX(W0, W0)                  both lines screened
+ *   SOX_VERTEX_SOSEX_DYN    SOX(V,V) + SOX(W_d(tau),V) = SOX(V + W_d, V)
+ *   SOX_VERTEX_2SOSEX_DYN   SOX(V,V) + SOX(V,W_d(tau)) + SOX(W_d(tau),V)       */
+typedef enum {
+  SOX_VERTEX_SOSEX_STAT = 0,
+  SOX_VERTEX_2SOSEX_STAT = 1,
+  SOX_VERTEX_G3W2_STAT = 2,
+  SOX_VERTEX_SOSEX_DYN = 3,
+  SOX_VERTEX_2SOSEX_DYN = 4
+} sox_vertex;
 
 typedef struct sox_plan sox_plan;
 
@@ -195,6 +212,28 @@ sox_status sox_sigma_static(sox_plan* plan, const double* X, const double* W0, c
 sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_tau, const double* V,
                              const double* G, double* Sigma, void* workspace,
                              size_t workspace_bytes, void* stream);
+
+/* Composite vertex self-energy `kind` (a sox_vertex), assembled on the
+ * device from the SOX terms above (the caller does no arithmetic):
+ *   W  the full screened interaction W0 = W(Omega = 0) [N,N] for the *_STAT
+ *      kinds; the dynamic part W_d(tau) [n_tau,N,N] for the *_DYN kinds
+ *      (plan with n_omega > 0).  Solids: complex128 with the leading n_k
+ *      axis, as for the other entries.
+ *   V  the bare interaction; X, G, Sigma as sox_sigma_bare.
+ * SOSEX_DYN on a k-point plan runs as one pass: both terms share line 2, so
+ * the bare term enters the dynamic chain's A(tau) and the B, C, D steps and
+ * the back-transform run once.  2SOSEX_DYN takes SOX(V, W_d) as the mirror
+ * image of SOX(W_d, V) (transpose for molecules, conjugate transpose per k
+ * and tau for solids), which holds when every G(tau) is symmetric
+ * (Hermitian per k), as for a G built by sox_build_g_tau; for a general G
+ * that term is not SOX(V, W_d).  2SOSEX_STAT is SOX(V, W0) + SOX(W0 - V, V)
+ * (bilinearity) and needs no such condition.  Workspace:
+ * sox_workspace_size(plan, SOX_ENTRY_VERTEX).  Errors as the other entries
+ * (SOX_ERR_INVALID_ARG for an unknown kind or a *_DYN kind without a
+ * transform pair). */
+sox_status sox_sigma_vertex(sox_plan* plan, int32_t kind, const double* X, const double* V,
+                            const double* W, const double* G, double* Sigma, void* workspace,
+                            size_t workspace_bytes, void* stream);
 
 /* Vector-Jacobian product of L = sum(Sigma * R) for the entry `entry`:
  *   R [n_tau,n,n] cotangent;  dG [n_tau,n,n], dX [n,N], dU1, dU2 outputs.

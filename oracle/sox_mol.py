@@ -205,6 +205,35 @@ def sigma_dynamic_thc(X: np.ndarray, W_tau: np.ndarray, V: np.ndarray, G: np.nda
     return out
 
 
+def sigma_dynamic_line2_eri(X: np.ndarray, V: np.ndarray, W_tau: np.ndarray, G: np.ndarray,
+                            Gb: np.ndarray, T_fwd: np.ndarray, T_bwd: np.ndarray) -> np.ndarray:
+    """eq:sox with U(1) = V instantaneous and U(2) = W_d(tau) time dependent:
+    SOX(V, W_d), the other one-dynamic-line term of 2SOSEX (fig:diag).
+
+    With the U(1) vertex pair at tau_r = 0, the U(2) end (t, u) at the
+    external time tau and its end (v, w) at tau', the lines are G_uq(tau),
+    G_wp(tau') and G_sv(-tau') (read as G(beta - tau'), as for line 1), and
+    the U(2) line carries W(tau - tau'):
+      Sigma_tr(tau) = - sum (pr|qs)_V G_uq(tau)
+                      int_0^beta (tu|vw)_W(tau - s) G_wp(s) G_sv(beta - s) ds,
+    the convolution now on the G_wp G_sv pair, evaluated with the same
+    transform pair as sigma_dynamic_eri.  Written independently of the
+    line-1 form; for a symmetric G it is that form's mirror image
+    (tests/test_oracle_vertex.py)."""
+    nt, n, _ = G.shape
+    E1 = eri(X, V)
+    E2w = np.stack([eri(X, W_tau[j]) for j in range(nt)])        # [nt, t, u, v, w]
+    f = np.einsum("jwp,jsv->jwpsv", G, Gb)                        # [nt, w, p, s, v]
+    E2m = matsubara(T_fwd, E2w)
+    fm = matsubara(T_fwd, f)
+    Km = np.einsum("mtuvw,mwpsv->mtups", E2m, fm)                 # product in frequency
+    K = imag_time(T_bwd, Km)                                      # [nt, t, u, p, s]
+    out = np.empty((nt, n, n))
+    for i in range(nt):
+        out[i] = -np.einsum("prqs,uq,tups->tr", E1, G[i], K[i], optimize=True)
+    return out
+
+
 # ---------------------------------------------------------------------------
 # Galitskii-Migdal energy of the SOX self-energy (eq:E2b on the tau grid)
 # ---------------------------------------------------------------------------

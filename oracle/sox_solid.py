@@ -171,6 +171,34 @@ def sigma_solid_dynamic_eri(X, W, V, G, T_fwd, T_bwd, tables) -> np.ndarray:
     return out / nk ** 2
 
 
+def sigma_solid_dynamic_line2_eri(X, V, W, G, T_fwd, T_bwd, tables) -> np.ndarray:
+    """4-index brute force of eq:sox with U(1) = V^q and U(2) = W^q(tau):
+    SOX(V, W_d) on a k-point mesh.  As for molecules (sox_mol's line-2 form)
+    the convolution sits on the G_wp G_sv pair and G_uq keeps the external
+    time:
+      Sigma^{k_t}_tr(tau) = -(1/N_k^2) sum_{k_p,k_q} (p k_p, r k_t | q k_q, s k_s)_V G^{k_q}_uq(tau)
+          int (t k_t, u k_q | v k_s, w k_p)_W(tau - s) G^{k_p}_wp(s) G^{k_s}_sv(beta - s) ds,
+    with the signed-frequency transforms of complex functions."""
+    ks_list, kdiff, ksum, kneg = tables
+    nk, nt, n, _ = G.shape
+    Gb = G[:, ::-1]
+    out = np.zeros((nk, nt, n, n), dtype=complex)
+    for kt in range(nk):
+        for kp in range(nk):
+            for kq in range(nk):
+                kss = kdiff[ksum[kp, kq], kt]
+                E1 = eri_k(X, V, kp, kt, kq, kss, kdiff)                     # (p kp, r kt | q kq, s ks)
+                E2w = np.stack([eri_k(X, W[:, j], kt, kq, kss, kp, kdiff) for j in range(nt)])
+                f = np.einsum("jwp,jsv->jwpsv", G[kp], Gb[kss])
+                Ep, Em = matsubara_pm(T_fwd, E2w)
+                fp, fm = matsubara_pm(T_fwd, f)
+                K = imag_time_pm(T_bwd, np.einsum("mtuvw,mwpsv->mtups", Ep, fp),
+                                 np.einsum("mtuvw,mwpsv->mtups", Em, fm))
+                for i in range(nt):
+                    out[kt, i] -= np.einsum("prqs,uq,tups->tr", E1, G[kq, i], K[i], optimize=True)
+    return out / nk ** 2
+
+
 def sigma_solid_dynamic_thc(X, W, V, G, T_fwd, T_bwd, tables, v_subset=None) -> np.ndarray:
     """The paper's momentum-resolved eq:GG chain with v outermost.
 

@@ -22,15 +22,17 @@ STATUS_NAMES = {
 }
 SOX_FP64, SOX_FP32, SOX_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": SOX_FP64, "fp32": SOX_FP32, "bf16x3": SOX_BF16X3}
-SOX_ENTRY_BARE, SOX_ENTRY_STATIC, SOX_ENTRY_DYNAMIC = 0, 1, 2
-ENTRIES = {"bare": SOX_ENTRY_BARE, "static": SOX_ENTRY_STATIC, "dynamic": SOX_ENTRY_DYNAMIC}
+SOX_ENTRY_BARE, SOX_ENTRY_STATIC, SOX_ENTRY_DYNAMIC, SOX_ENTRY_VERTEX = 0, 1, 2, 3
+ENTRIES = {"bare": SOX_ENTRY_BARE, "static": SOX_ENTRY_STATIC, "dynamic": SOX_ENTRY_DYNAMIC,
+           "vertex": SOX_ENTRY_VERTEX}
+VERTEX_KINDS = {"sosex_stat": 0, "2sosex_stat": 1, "g3w2_stat": 2, "sosex_dyn": 3, "2sosex_dyn": 4}
 
 EXPORTED = (
     "sox_plan_create", "sox_plan_destroy", "sox_workspace_size", "sox_sigma_bare",
     "sox_sigma_static", "sox_sigma_dynamic", "sox_sigma_vjp", "sox_build_g_tau",
     "sox_energy_gm", "sox_energy_gm_device", "sox_sync", "sox_last_error", "sox_abi_version", "sox_profile_enable",
     "sox_profile_read", "sox_profile_select", "sox_plan_set_graph", "sox_plan_describe",
-    "sox_sigma_bare_noalloc",
+    "sox_sigma_bare_noalloc", "sox_sigma_vertex",
 )
 STAGES = ("gbuild", "utensor", "project", "astep", "fused", "back", "energy", "gg_ft", "wgemm",
           "ift", "split", "vjp", "kbc", "kd")
@@ -71,6 +73,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.sox_sigma_bare.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_sigma_static.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_sigma_bare_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.sox_sigma_vertex.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_sigma_dynamic.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_sigma_vjp.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_build_g_tau.argtypes = [vp, vp, vp, dp, vp, vp]
@@ -244,6 +247,21 @@ def sox_sigma_bare_noalloc(plan: Plan, X, V, G, Sigma, stream=None):
     _check(load().sox_sigma_bare_noalloc(plan.handle, t(X, (n, N), "X"), t(V, (N, N), "V"),
                                          t(G, (nt, n, n), "G"), t(Sigma, (nt, n, n), "Sigma"),
                                          _stream(stream)), "sox_sigma_bare_noalloc")
+    return Sigma
+
+
+def sox_sigma_vertex(plan: Plan, kind, X, V, W, G, Sigma, ws=None, stream=None):
+    """Composite vertex self-energy; kind is a name of VERTEX_KINDS or its value.
+    W is W0 [N, N] for the *_stat kinds and W_d(tau) [n_tau, N, N] for *_dyn."""
+    n, N, nt = plan.n, plan.N, plan.n_tau
+    k = VERTEX_KINDS[kind] if isinstance(kind, str) else int(kind)
+    w, wb = _ws_args(plan, "vertex", ws)
+    t = plan._t
+    wshape = (nt, N, N) if k in (3, 4) else (N, N)
+    _check(load().sox_sigma_vertex(plan.handle, k, t(X, (n, N), "X"), t(V, (N, N), "V"),
+                                   t(W, wshape, "W"), t(G, (nt, n, n), "G"),
+                                   t(Sigma, (nt, n, n), "Sigma"), w, wb, _stream(stream)),
+           "sox_sigma_vertex")
     return Sigma
 
 

@@ -111,6 +111,7 @@ struct sox_plan {
   int vcs_bare = 0;  // bare entry (one U-tensor: wider slabs fit)
   int dyn_ps = 0;    // dynamic entry: momentum pairs per slab
   int dyn_ts = 0;    // dynamic entry: tau nodes per B, C, D slab
+  int dyn_ta = 0;    // bare + dynamic pass: tau nodes per slab of the bare A term
   int* d_ktab = nullptr;
   double* d_tfc = nullptr;  // [2 n_omega][n_tau] complex [T_fwd; conj(T_fwd)]
   double* d_tbc = nullptr;  // [n_tau][2 n_omega] complex [T_bwd / 2 | conj(T_bwd) / 2]
@@ -120,6 +121,8 @@ struct sox_plan {
   double* d_tau = nullptr;
   double* d_w = nullptr;
   double* d_scratch = nullptr;  // occupations / traces / energy: n_tau*(n+1)+1
+  double* d_wchk = nullptr;     // molecular dynamic plans: mirror-symmetry partial maxima
+  int last_w_real = -1;         // molecular dynamic entry: 1 if the last call ran the real W product
   int device = 0;
   // per-stage event timing (sox_profile_enable / sox_profile_read)
   struct Ev {
@@ -412,7 +415,10 @@ int pick_vjp_slab(const sox_plan& p, int entry) {
 
 size_t solid_workspace_bytes(const sox_plan& p, int entry);  // with the solid launch sequence
 
+size_t vertex_workspace_bytes(const sox_plan& p);  // with the composite entry
+
 size_t workspace_bytes(const sox_plan& p, int entry) {
+  if (entry == SOX_ENTRY_VERTEX) return vertex_workspace_bytes(p);
   if (p.nk > 1) return solid_workspace_bytes(p, entry);
   if (entry == SOX_ENTRY_DYNAMIC)
     return p.n_omega > 0 ? std::max(dyn_layout_for(p, p.vc, p.eslab).total, dyn_vjp_total(p, p.vc_vjp))
@@ -868,8 +874,83 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
 // (W2 [2NP][2NP], GG2 [vcn][2NP], AW [2NP][vcn]).  float32 on the LDS-staged
 // GEMM (C4: 1.28 s per sweep on the direct-load kernel), float64 on the
 // direct-load one.
+// Mirror symmetry of W_d(tau): per-block partial maxima of
+// |W(tau_j) - W(tau_{n_tau-1-j})| and of |W| over every node pair and entry.
+constexpr int kWchkBlocks = 256;
+__global__ __launch_bounds__(256) void mirror_asym_kernel(const double* W, int nt, long nn,
+                                                          double* part) {
+  __shared__ double sa[256], sm[256];
+  double a = 0.0, m = 0.0;
+  const long half = (long)((nt + 1) / 2) * nn;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < half; i += (long)gridDim.x * 256) {
+    const long j = i / nn, e = i - j * nn;
+    const double x = W[j * nn + e], y = W[(nt - 1 - j) * nn + e];
+    a = fmax(a, fabs(x - y));
+    m = fmax(m, fmax(fabs(x), fabs(y)));
+  }
+  sa[threadIdx.x] = a;
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      sa[threadIdx.x] = fmax(sa[threadIdx.x], sa[threadIdx.x + w]);
+      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = sa[0];
+    part[2 * blockIdx.x + 1] = sm[0];
+  }
+}
+
+// Whether the molecular dynamic entry may run the real W(Omega) product: a
+// float32 or bf16x3 plan and W_d(tau) mirror symmetric in tau to 1e-13 of
+// its largest entry.  A symmetric W(tau) has a real W(i Omega) in the
+// continuum; the plan's discrete transform pair leaves an imaginary part near
+// 1e-8 of the real one, which those plans' 1e-6 / 1e-4 bounds absorb (float64
+// plans keep the block product).  Synchronises `s` once to read the maxima.
+sox_status dynamic_w_is_real(sox_plan& p, const double* Wtau, hipStream_t s, bool* real_w) {
+  *real_w = false;
+  if (p.precision == SOX_FP64 || p.nk > 1 || !p.d_wchk) return SOX_OK;
+  const long nn = (long)p.N * p.N;
+  hipLaunchKernelGGL(mirror_asym_kernel, dim3(kWchkBlocks), dim3(256), 0, s, Wtau, p.n_tau, nn,
+                     p.d_wchk);
+  SOX_HIP(hipGetLastError());
+  double part[2 * kWchkBlocks];
+  SOX_HIP(hipMemcpyAsync(part, p.d_wchk, sizeof(part), hipMemcpyDeviceToHost, s));
+  SOX_HIP(hipStreamSynchronize(s));
+  double a = 0.0, m = 0.0;
+  for (int b = 0; b < kWchkBlocks; ++b) {
+    a = std::max(a, part[2 * b]);
+    m = std::max(m, part[2 * b + 1]);
+  }
+  *real_w = m > 0.0 && a <= 1e-13 * m;
+  return SOX_OK;
+}
+
+// W(Omega) GG(Omega) with the block operator W2 = [[Wr, -Wi], [Wi, Wr]] on
+// GG2 rows [GGr | GGi]: AW rows [0, NP) = Re, [NP, 2NP) = Im.  real_w: W(Omega)
+// is real (a mirror-symmetric W_d(tau)), so Re = Wr GGr and Im = Wr GGi, two
+// products of half the depth over half the rows: a quarter of the block
+// product's work each.
 template <typename T>
-sox_status launch_wgg(const T* W2, const T* GG2, T* AW, int NP, long vcn, int nw, hipStream_t s) {
+sox_status launch_wgg(const T* W2, const T* GG2, T* AW, int NP, long vcn, int nw, hipStream_t s,
+                      bool real_w = false) {
+  if (sizeof(T) == 4 && real_w) {
+    for (int c = 0; c < 2; ++c) {
+      DenseLdsArgs l{};
+      l.A = (const float*)W2;
+      l.B = (const float*)GG2 + (long)c * NP;
+      l.C = (float*)AW + (long)c * NP * vcn;
+      l.lda = 2L * NP; l.ldb = 2L * NP; l.ldc = vcn;
+      l.sA = 4L * NP * NP; l.sB = vcn * 2 * NP; l.sC = 2L * NP * vcn;
+      l.M = NP; l.N = (int)vcn; l.K = NP;
+      l.rgroup = l.M; l.rvalid = l.M;
+      SOX_HIP(launch_dense_lds_f32(l, nw, s));
+    }
+    return SOX_OK;
+  }
   if (sizeof(T) == 4) {
     DenseLdsArgs l{};
     l.A = (const float*)W2;
@@ -904,7 +985,7 @@ sox_status launch_transpose(const T* in, T* out, int rows, int cols, long batch,
 template <typename T>
 sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const double* V,
                        const double* G, double* Sigma, void* ws, hipStream_t s, int vcw = 0,
-                       T* W2T = nullptr) {
+                       T* W2T = nullptr, bool real_w = false) {
   if (vcw <= 0) vcw = p.vc;
   const DynLayout L = dyn_layout_for(p, vcw, p.eslab);
   char* base = (char*)ws;
@@ -1003,10 +1084,22 @@ sox_status run_dynamic(sox_plan& p, const double* X, const double* Wtau, const d
         l.lda = 2L * NP; l.ldb = 2L * NP; l.ldc = vcn;
         l.sA = 4L * NP * NP; l.sB = vcn * 2 * NP; l.sC = 2L * NP * vcn;
         l.M = 2 * NP; l.N = (int)vcn; l.K = 2 * NP;
-        // eight wavefronts of 64 x 32 (n=300 N=1800: 296 -> 274 ms per sweep
-        // against four of 64 x 64)
-        SOX_HIP(launch_dense_lds_bf16x3<2>(l, nw, s));
-      } else if ((st = launch_wgg<T>(W2, GG2, AW, NP, (long)vc * n, nw, s))) {
+        if (real_w) {
+          // Re = Wr GGr, Im = Wr GGi (the top-left block of the split W2 planes)
+          l.M = NP; l.K = NP;
+          for (int c = 0; c < 2; ++c) {
+            DenseLdsSplitArgs h = l;
+            h.Bh = l.Bh + (long)c * NP;
+            h.Bl = l.Bl + (long)c * NP;
+            h.C = l.C + (long)c * NP * vcn;
+            SOX_HIP(launch_dense_lds_bf16x3<2>(h, nw, s));
+          }
+        } else {
+          // eight wavefronts of 64 x 32 (n=300 N=1800: 296 -> 274 ms per sweep
+          // against four of 64 x 64)
+          SOX_HIP(launch_dense_lds_bf16x3<2>(l, nw, s));
+        }
+      } else if ((st = launch_wgg<T>(W2, GG2, AW, NP, (long)vc * n, nw, s, real_w))) {
         return st;
       }
     }
@@ -1688,6 +1781,144 @@ sox_status dispatch_static(sox_plan* plan, int entry, const double* X, const dou
   });
 }
 
+// -- composite vertex self-energies (fig:diag) ---------------------------------
+// The composites are sums of SOX terms with one interaction per line.  The
+// library runs the terms it needs and sums them on the device:
+//   SOSEX_STAT   SOX(W0, V)                       one static pass
+//   G3W2_STAT    SOX(W0, W0)                      one static pass
+//   2SOSEX_STAT  SOX(V,V) + SOX(V,Wd0) + SOX(Wd0,V)
+//                = SOX(V, W0) + SOX(W0 - V, V)    two static passes (bilinear)
+//   SOSEX_DYN    SOX(V,V) + SOX(W_d(tau),V)       solids: one pass with the bare
+//                term in the dynamic chain; molecules: bare + dynamic pass
+//   2SOSEX_DYN   SOX(V,V) + SOX(V,W_d) + SOX(W_d,V), with SOX(V, W_d) = SOX(W_d, V)^T
+//                (molecules) or ^dagger per (k, tau) (solids): the mirror image of the
+//                diagram for a symmetric (Hermitian) G(tau)
+// Workspace: the largest pass, then one Sigma-sized buffer and one
+// interaction-sized buffer (W0 - V).
+struct VertexLayout {
+  size_t pass, sig, wd0, total;
+};
+
+VertexLayout vertex_layout_for(const sox_plan& p) {
+  VertexLayout L{};
+  size_t pass = std::max(workspace_bytes(p, SOX_ENTRY_STATIC), workspace_bytes(p, SOX_ENTRY_BARE));
+  if (p.n_omega > 0) {
+    pass = std::max(pass, workspace_bytes(p, SOX_ENTRY_DYNAMIC));
+    if (p.nk > 1) pass = std::max(pass, solid_dyn_total(p, true));
+  }
+  const size_t cplx = p.nk > 1 ? 2 * (size_t)p.nk : 1;
+  Carver c;
+  L.pass = c.take(pass);
+  L.sig = c.take(cplx * p.n_tau * p.n * p.n * sizeof(double));
+  L.wd0 = c.take(cplx * p.N * p.N * sizeof(double));
+  L.total = c.off;
+  return L;
+}
+
+size_t vertex_workspace_bytes(const sox_plan& p) { return vertex_layout_for(p).total; }
+
+__global__ void vertex_axpby_kernel(double* out, const double* a, double alpha, const double* b,
+                                    double beta, long count) {
+  SOX_FOR_FLAT(i, count) out[i] = alpha * a[i] + beta * b[i];
+}
+
+// out[z][i][j] += a[z][j][i] (real) or conj(a[z][j][i]) (complex), z < batch
+__global__ void vertex_add_adjoint_kernel(double* out, const double* a, long batch, int n,
+                                          int cplx) {
+  const long per = (long)n * n;
+  SOX_FOR_FLAT(idx, batch * per) {
+    const long z = idx / per;
+    const int i = (int)((idx - z * per) / n), j = (int)(idx - z * per - (long)i * n);
+    const long src = z * per + (long)j * n + i;
+    if (cplx) {
+      out[2 * idx] += a[2 * src];
+      out[2 * idx + 1] -= a[2 * src + 1];
+    } else {
+      out[idx] += a[src];
+    }
+  }
+}
+
+sox_status vertex_pass_static(sox_plan& p, int entry, const double* X, const double* U1,
+                              const double* U2, const double* G, double* out, void* ws,
+                              hipStream_t s) {
+  if (p.nk > 1)
+    return p.precision == SOX_FP64 ? run_solid<double>(p, entry, X, U1, U2, G, out, ws, s)
+                                   : run_solid<float>(p, entry, X, U1, U2, G, out, ws, s);
+  return p.precision == SOX_FP64 ? run_static<double>(p, entry, X, U1, U2, G, out, ws, s)
+                                 : run_static<float>(p, entry, X, U1, U2, G, out, ws, s);
+}
+
+sox_status vertex_pass_dynamic(sox_plan& p, const double* X, const double* W, const double* V,
+                               const double* G, double* out, void* ws, hipStream_t s,
+                               bool with_bare, bool real_w) {
+  if (p.nk > 1)
+    return p.precision == SOX_FP64
+               ? run_solid_dynamic<double>(p, X, W, V, G, out, ws, s, with_bare)
+               : run_solid_dynamic<float>(p, X, W, V, G, out, ws, s, with_bare);
+  return p.precision == SOX_FP64
+             ? run_dynamic<double>(p, X, W, V, G, out, ws, s)
+             : run_dynamic<float>(p, X, W, V, G, out, ws, s, 0, nullptr, real_w);
+}
+
+sox_status run_vertex(sox_plan& p, int kind, const double* X, const double* V, const double* W,
+                      const double* G, double* Sigma, void* ws, hipStream_t s, bool real_w) {
+  const VertexLayout L = vertex_layout_for(p);
+  char* base = (char*)ws;
+  void* pw = base + L.pass;
+  double* tmp = (double*)(base + L.sig);
+  double* wd0 = (double*)(base + L.wd0);
+  const long cplx = p.nk > 1 ? 2L * p.nk : 1L;
+  const long nsig = cplx * p.n_tau * p.n * p.n;
+  const long nint = cplx * p.N * p.N;
+  const long batch = (long)(p.nk > 1 ? p.nk : 1) * p.n_tau;
+  sox_status st;
+  auto add = [&](double* out, const double* a) -> sox_status {
+    hipLaunchKernelGGL(vertex_axpby_kernel, grid1d(nsig), dim3(256), 0, s, out, out, 1.0, a, 1.0,
+                       nsig);
+    SOX_HIP(hipGetLastError());
+    return SOX_OK;
+  };
+  auto add_adjoint = [&](double* out, const double* a) -> sox_status {
+    hipLaunchKernelGGL(vertex_add_adjoint_kernel, grid1d(batch * p.n * p.n), dim3(256), 0, s, out,
+                       a, batch, p.n, p.nk > 1 ? 1 : 0);
+    SOX_HIP(hipGetLastError());
+    return SOX_OK;
+  };
+  switch (kind) {
+    case SOX_VERTEX_SOSEX_STAT:
+      return vertex_pass_static(p, SOX_ENTRY_STATIC, X, W, V, G, Sigma, pw, s);
+    case SOX_VERTEX_G3W2_STAT:
+      return vertex_pass_static(p, SOX_ENTRY_STATIC, X, W, W, G, Sigma, pw, s);
+    case SOX_VERTEX_2SOSEX_STAT: {
+      // SOX(V, W0) + SOX(W0 - V, V)
+      if ((st = vertex_pass_static(p, SOX_ENTRY_STATIC, X, V, W, G, Sigma, pw, s))) return st;
+      hipLaunchKernelGGL(vertex_axpby_kernel, grid1d(nint), dim3(256), 0, s, wd0, W, 1.0, V, -1.0,
+                         nint);
+      SOX_HIP(hipGetLastError());
+      if ((st = vertex_pass_static(p, SOX_ENTRY_STATIC, X, wd0, V, G, tmp, pw, s))) return st;
+      return add(Sigma, tmp);
+    }
+    case SOX_VERTEX_SOSEX_DYN:
+      if (p.nk > 1) return vertex_pass_dynamic(p, X, W, V, G, Sigma, pw, s, true, real_w);
+      if ((st = vertex_pass_static(p, SOX_ENTRY_BARE, X, V, V, G, Sigma, pw, s))) return st;
+      if ((st = vertex_pass_dynamic(p, X, W, V, G, tmp, pw, s, false, real_w))) return st;
+      return add(Sigma, tmp);
+    case SOX_VERTEX_2SOSEX_DYN:
+      // SOX(W_d, V) into tmp; SOX(V, V) + SOX(W_d, V) into Sigma; then the mirror term
+      if ((st = vertex_pass_dynamic(p, X, W, V, G, tmp, pw, s, false, real_w))) return st;
+      if (p.nk > 1) {
+        if ((st = vertex_pass_dynamic(p, X, W, V, G, Sigma, pw, s, true, real_w))) return st;
+      } else {
+        if ((st = vertex_pass_static(p, SOX_ENTRY_BARE, X, V, V, G, Sigma, pw, s))) return st;
+        if ((st = add(Sigma, tmp))) return st;
+      }
+      return add_adjoint(Sigma, tmp);
+    default:
+      return fail(SOX_ERR_INVALID_ARG, "unknown vertex kind %d", kind);
+  }
+}
+
 }  // namespace
 
 // -- the no-allocation entry point ---------------------------------------------
@@ -1869,6 +2100,8 @@ sox_status sox_plan_create(const sox_problem* pr, int32_t precision, sox_plan** 
                                  : (size_t)nt * (p->n + 1) + 1;
     e = hipMalloc(&p->d_scratch, sizeof(double) * nsc);
   }
+  if (e == hipSuccess && p->nk == 1 && p->n_omega > 0)
+    e = hipMalloc(&p->d_wchk, sizeof(double) * 2 * kWchkBlocks);
   if (e == hipSuccess && p->nk > 1 && p->n_omega > 0) {
     const int nw = p->n_omega;
     std::vector<double> tbc((size_t)nt * 4 * nw);
@@ -1928,6 +2161,7 @@ sox_status sox_plan_destroy(sox_plan* p) {
   if (p->d_tb2) (void)hipFree(p->d_tb2);
   if (p->d_w) (void)hipFree(p->d_w);
   if (p->d_scratch) (void)hipFree(p->d_scratch);
+  if (p->d_wchk) (void)hipFree(p->d_wchk);
   if (p->d_ktab) (void)hipFree(p->d_ktab);
   if (p->d_tfc) (void)hipFree(p->d_tfc);
   if (p->d_tbc) (void)hipFree(p->d_tbc);
@@ -1938,7 +2172,7 @@ sox_status sox_plan_destroy(sox_plan* p) {
 sox_status sox_workspace_size(const sox_plan* plan, int32_t entry, size_t* bytes) {
   if (!plan) return fail(SOX_ERR_INVALID_ARG, "plan is NULL");
   if (!bytes) return fail(SOX_ERR_INVALID_ARG, "bytes is NULL");
-  if (entry < SOX_ENTRY_BARE || entry > SOX_ENTRY_DYNAMIC)
+  if (entry < SOX_ENTRY_BARE || entry > SOX_ENTRY_VERTEX)
     return fail(SOX_ERR_INVALID_ARG, "unknown entry %d", entry);
   *bytes = workspace_bytes(*plan, entry);
   return SOX_OK;
@@ -1953,6 +2187,33 @@ sox_status sox_sigma_static(sox_plan* plan, const double* X, const double* W0, c
                             const double* G, double* Sigma, void* ws, size_t ws_bytes,
                             void* stream) {
   return dispatch_static(plan, SOX_ENTRY_STATIC, X, W0, V, G, Sigma, ws, ws_bytes, stream);
+}
+
+sox_status sox_sigma_vertex(sox_plan* plan, int32_t kind, const double* X, const double* V,
+                            const double* W, const double* G, double* Sigma, void* ws,
+                            size_t ws_bytes, void* stream) {
+  sox_status st = check_plan(plan);
+  if (st) return st;
+  if (kind < SOX_VERTEX_SOSEX_STAT || kind > SOX_VERTEX_2SOSEX_DYN)
+    return fail(SOX_ERR_INVALID_ARG, "unknown vertex kind %d", kind);
+  if (!X || !V || !W || !G || !Sigma) return fail(SOX_ERR_INVALID_ARG, "NULL tensor pointer");
+  const bool dyn = kind == SOX_VERTEX_SOSEX_DYN || kind == SOX_VERTEX_2SOSEX_DYN;
+  if (dyn && plan->n_omega <= 0)
+    return fail(SOX_ERR_INVALID_ARG, "plan has no transform pair (n_omega = 0)");
+  if (dyn && plan->nk == 1 && plan->precision == SOX_BF16X3 && plan->fused_cfg != 8)
+    return fail(SOX_ERR_UNSUPPORTED,
+                "the molecular dynamic entry in bf16x3 needs the LDS-staged fused kernel, whose "
+                "32-bit panel offsets overflow at this n_orb and n_thc");
+  st = check_ws(plan, SOX_ENTRY_VERTEX, ws, ws_bytes);
+  if (st) return st;
+  bool real_w = false;
+  if (dyn && (st = dynamic_w_is_real(*plan, W, (hipStream_t)stream, &real_w))) return st;
+  const uintptr_t key[9] = {(uintptr_t)SOX_ENTRY_VERTEX, (uintptr_t)X, (uintptr_t)V,
+                            (uintptr_t)W, (uintptr_t)G, (uintptr_t)Sigma, (uintptr_t)ws,
+                            (uintptr_t)ws_bytes, (uintptr_t)kind * 2 + (real_w ? 1 : 0)};
+  return run_maybe_graph(*plan, key, (hipStream_t)stream, [&](hipStream_t s) -> sox_status {
+    return run_vertex(*plan, kind, X, V, W, G, Sigma, ws, s, real_w);
+  });
 }
 
 sox_status sox_sigma_bare_noalloc(sox_plan* plan, const double* X, const double* V,
@@ -2005,9 +2266,12 @@ sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_ta
     return fail(SOX_ERR_UNSUPPORTED,
                 "the molecular dynamic entry in bf16x3 needs the LDS-staged fused kernel, whose "
                 "32-bit panel offsets overflow at this n_orb and n_thc");
+  bool real_w = false;
+  if ((st = dynamic_w_is_real(*plan, W_tau, (hipStream_t)stream, &real_w))) return st;
+  if (plan->nk == 1) plan->last_w_real = real_w ? 1 : 0;
   const uintptr_t key[9] = {(uintptr_t)SOX_ENTRY_DYNAMIC, (uintptr_t)X, (uintptr_t)W_tau,
                             (uintptr_t)V, (uintptr_t)G, (uintptr_t)Sigma, (uintptr_t)ws,
-                            (uintptr_t)ws_bytes, 0};
+                            (uintptr_t)ws_bytes, (uintptr_t)real_w};
   return run_maybe_graph(*plan, key, (hipStream_t)stream, [&](hipStream_t s) -> sox_status {
     if (plan->nk > 1) {
       if (plan->precision == SOX_FP64)
@@ -2017,7 +2281,8 @@ sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_ta
     switch (plan->precision) {
       case SOX_FP64: return run_dynamic<double>(*plan, X, W_tau, V, G, Sigma, ws, s);
       case SOX_FP32:
-      case SOX_BF16X3: return run_dynamic<float>(*plan, X, W_tau, V, G, Sigma, ws, s);
+      case SOX_BF16X3:
+        return run_dynamic<float>(*plan, X, W_tau, V, G, Sigma, ws, s, 0, nullptr, real_w);
       default:
         return fail(SOX_ERR_UNSUPPORTED, "unknown precision %d", plan->precision);
     }
@@ -2184,11 +2449,13 @@ sox_status sox_plan_describe(const sox_plan* plan, char* buf, size_t len) {
            "\"v_slab\":%d,\"vjp_v_slab\":%d,\"graph\":%d,\"fused_vsplit\":%d,\"n_cu\":%d,"
            "\"tune_ms_per_tau\":%s,"
            "\"tune_from_cache\":%d,\"kmesh\":[%d,%d,%d],\"n_k\":%d,\"solid_v_slab\":%d,"
-           "\"solid_v_slab_bare\":%d,\"solid_dyn_pair_slab\":%d,\"solid_dyn_tau_slab\":%d}",
+           "\"solid_v_slab_bare\":%d,\"solid_dyn_pair_slab\":%d,\"solid_dyn_tau_slab\":%d,"
+           "\"solid_bare_tau_slab\":%d,\"dynamic_real_w\":%d}",
            plan->n, plan->N, plan->n_tau, plan->nP, plan->NP, plan->precision, plan->fused_cfg,
            fc.wp, fc.wr, plan->slab, plan->vjp_slab, plan->vc, plan->vc_vjp, plan->graph_on ? 1 : 0,
            plan->fused_vsplit, plan->n_cu, tune.c_str(), plan->tune_from_cache ? 1 : 0, plan->kmesh[0], plan->kmesh[1],
-           plan->kmesh[2], plan->nk, plan->vcs, plan->vcs_bare, plan->dyn_ps, plan->dyn_ts);
+           plan->kmesh[2], plan->nk, plan->vcs, plan->vcs_bare, plan->dyn_ps, plan->dyn_ts,
+           plan->dyn_ta, plan->last_w_real);
   return SOX_OK;
 }
 

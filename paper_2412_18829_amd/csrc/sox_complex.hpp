@@ -895,6 +895,25 @@ __global__ __launch_bounds__(256) void ctranspose_kernel(const TI* in, TO* out, 
 }
 
 // occ_c[i] = (occ[i], 0): the occupation factors as complex values.
+// out[k][v][t][s] = G^k(tau_{n_tau-1-t})[s][v] in T (complex): for each
+// momentum k and orbital v, rows t of the mirrored node's column v, the A
+// operand of the bare term taken one v at a time over every node.
+template <typename T>
+__global__ void mirror_columns_kernel(const double* G, T* out, int nk, int nt, int n) {
+  const long count = (long)nk * n * nt * n;
+  SOX_FOR_FLAT(i, count) {
+    const int s = (int)(i % n);
+    const long r = i / n;
+    const int t = (int)(r % nt);
+    const long r2 = r / nt;
+    const int v = (int)(r2 % n);
+    const int k = (int)(r2 / n);
+    const long src = (((long)k * nt + (nt - 1 - t)) * n + s) * n + v;
+    out[2 * i] = T(G[2 * src]);
+    out[2 * i + 1] = T(G[2 * src + 1]);
+  }
+}
+
 __global__ void real_to_complex_kernel(const double* x, double* out, long count) {
   SOX_FOR_FLAT(i, count) {
     out[2 * i] = x[i];

@@ -58,7 +58,7 @@ SolidLayout solid_layout_for(const sox_plan& p, int entry, int vc) {
 
 int solid_vc(const sox_plan& p, int entry) { return entry == SOX_ENTRY_BARE ? p.vcs_bare : p.vcs; }
 
-size_t solid_dyn_total(const sox_plan& p);  // with the dynamic launch sequence
+size_t solid_dyn_total(const sox_plan& p, bool with_bare = false);  // with the dynamic launch sequence
 
 size_t solid_workspace_bytes(const sox_plan& p, int entry) {
   if (entry == SOX_ENTRY_DYNAMIC) return p.n_omega > 0 ? solid_dyn_total(p) : 0;
@@ -428,10 +428,14 @@ sox_status solid_energy(sox_plan& p, const double* Sigma, const double* G, doubl
 // projections, GG and both transforms run in float64, W GG, B, C and D in the
 // plan's precision; D and the back-transform in float64.
 struct SolidDynLayout {
-  size_t ut2, xtd, gtd, xtt, gwpd, grqtd, gwpt, wm, gg, ggw, aw, atau, bbuf, cbuf, dtau, ebuf, total;
+  size_t ut2, xtd, gtd, xtt, gwpd, grqtd, gwpt, wm, gg, ggw, aw, atau, bbuf, cbuf, dtau, ebuf;
+  size_t gtm, gct, abare;  // bare line-1 term (ta > 0 only)
+  size_t total;
 };
 
-SolidDynLayout solid_dyn_layout_for(const sox_plan& p, int ps, int ts) {
+// ta > 0: the layout of the pass that also carries the bare line-1 term in
+// tau slabs of ta nodes.
+SolidDynLayout solid_dyn_layout_for(const sox_plan& p, int ps, int ts, int ta = 0) {
   SolidDynLayout L{};
   const size_t es = 2 * elem_size(p.precision);
   const size_t n = p.n, N = p.N, nt = p.n_tau, nk = p.nk, np2 = nk * nk, nw = p.n_omega;
@@ -452,6 +456,11 @@ SolidDynLayout solid_dyn_layout_for(const sox_plan& p, int ps, int ts) {
   L.cbuf = c.take((size_t)ts * np2 * N * N * es);
   L.dtau = c.take(nt * nk * N * N * 16);
   L.ebuf = c.take(nt * nk * n * N * 16);
+  if (ta > 0) {
+    L.gtm = c.take(nk * n * nt * n * es);
+    L.gct = c.take(nk * nt * n * n * es);
+    L.abare = c.take((size_t)ta * np2 * N * n * es);
+  }
   L.total = c.off;
   return L;
 }
@@ -466,16 +475,30 @@ void pick_solid_dyn(sox_plan& p) {
   while (ts > 1 && solid_dyn_layout_for(p, nq * p.nk, ts).total > budget) ts = (ts + 1) / 2;
   p.dyn_ps = nq * p.nk;
   p.dyn_ts = ts;
+  // the bare term's tau slabs: at most 64 nodes (one row tile of its
+  // product), evened out over the slabs, halved while over the budget
+  int slabs = (p.n_tau + 63) / 64;
+  int ta = (p.n_tau + slabs - 1) / slabs;
+  while (ta > 1 && solid_dyn_layout_for(p, p.dyn_ps, ts, ta).total > budget) ta = (ta + 1) / 2;
+  p.dyn_ta = ta;
 }
 
-size_t solid_dyn_total(const sox_plan& p) { return solid_dyn_layout_for(p, p.dyn_ps, p.dyn_ts).total; }
+size_t solid_dyn_total(const sox_plan& p, bool with_bare) {
+  return solid_dyn_layout_for(p, p.dyn_ps, p.dyn_ts, with_bare ? p.dyn_ta : 0).total;
+}
 
+// with_bare: Sigma = SOX(V + W_d(tau), V) = SOX(V, V) + SOX(W_d(tau), V) in one
+// pass.  Both terms share line 2 (C), so by bilinearity they share the B, C
+// and D steps: with G_Rq = X^T G the bare chain's B^v = A^v G_Rq^T equals
+// (A^v G(tau)^T) X, so the bare A^v_Pq = sum_s Ut_Pqs G_sv(beta - tau)
+// enters the dynamic A(tau) as A_bare G(tau)^T before the B step.
 template <typename T>
 sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, const double* V,
-                             const double* G, double* Sigma, void* ws, hipStream_t s) {
+                             const double* G, double* Sigma, void* ws, hipStream_t s,
+                             bool with_bare = false) {
   const int n = p.n, N = p.N, nt = p.n_tau, nk = p.nk, np2 = nk * nk, nw = p.n_omega;
-  const int ps = p.dyn_ps, ts = p.dyn_ts;
-  const SolidDynLayout L = solid_dyn_layout_for(p, ps, ts);
+  const int ps = p.dyn_ps, ts = p.dyn_ts, ta = with_bare ? p.dyn_ta : 0;
+  const SolidDynLayout L = solid_dyn_layout_for(p, ps, ts, ta);
   char* base = (char*)ws;
   T* ut2 = (T*)(base + L.ut2);
   double* xtd = (double*)(base + L.xtd);
@@ -493,6 +516,9 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
   T* cbuf = (T*)(base + L.cbuf);
   double* dtau = (double*)(base + L.dtau);
   double* ebuf = (double*)(base + L.ebuf);
+  T* gtm = ta ? (T*)(base + L.gtm) : nullptr;
+  T* gct = ta ? (T*)(base + L.gct) : nullptr;
+  T* abare = ta ? (T*)(base + L.abare) : nullptr;
   const int* kOf = p.d_ktab;
   const int* qOf = p.d_ktab + np2;
   const int* kmqOf = p.d_ktab + 2 * np2;
@@ -539,6 +565,14 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
     b.nzi = nt;
     b.M = N; b.N = n; b.K = n;
     if ((st = cg_launch(b, nk * nt, 0, s))) return st;
+    if (ta) {
+      // the bare term's operands: G^k(beta - tau) by columns v, G^k(tau) in T
+      const long cg = (long)nk * n * nt * n;
+      hipLaunchKernelGGL((mirror_columns_kernel<T>), grid1d(cg), dim3(256), 0, s, G, gtm, nk, nt, n);
+      SOX_HIP(hipGetLastError());
+      hipLaunchKernelGGL((cast_kernel<T>), grid1d(2 * cg), dim3(256), 0, s, G, gct, 2 * cg);
+      SOX_HIP(hipGetLastError());
+    }
   }
   {
     // W^q(+-Omega)[P][Q] = sum_j [T_fwd; conj(T_fwd)][(+-, m)][j] W^q(tau_j)[P][Q]
@@ -591,6 +625,29 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
         a.M = nt; a.N = (int)(cp * nN); a.K = 2 * nw;
         if ((st = cg_launch(a, 1, nt <= 112 ? 5 : 3, s))) return st;
       }
+    }
+    for (int a0 = 0; a0 < nt && ta; a0 += ta) {
+      const int ca = std::min(ta, nt - a0);
+      ProfScope ps_(p, SOX_STAGE_ASTEP, s);
+      // A_bare[l][pair][P][q] = sum_s G^{k_v}(beta - tau_{a0+l})_sv Ut[pair][q][P][s]
+      // (rows: the slab's nodes; columns (P, q); Ut of V, the line-2 U-tensor)
+      CgArgs<T, T> a = cg_args<T, T>();
+      a.A = gtm + 2 * ((long)v * nt + a0) * n;
+      a.idxA = kOf; a.soA = (long)n * nt * n; a.ldA = n;
+      a.B = ut2; a.soB = (long)n * N * n; a.splitB = n; a.hiB = n; a.ldB = (long)N * n;
+      a.C = abare; a.soC = nN; a.ldc = (long)np2 * nN;
+      a.M = ca; a.N = N * n; a.K = n;
+      if ((st = cg_launch(a, np2, 1, s))) return st;
+      // A(tau)[pair][P][u] += sum_q A_bare[pair][P][q] G^{k_v - q1}(tau)[u][q]
+      CgArgs<T, T> b = cg_args<T, T>();
+      b.A = abare; b.soA = nN; b.siA = (long)np2 * nN; b.ldA = n;
+      b.B = gct + 2 * (long)a0 * n * n; b.idxB = kmqOf; b.soB = (long)nt * n * n;
+      b.siB = (long)n * n; b.ldB = n;
+      b.C = atau + 2 * (long)a0 * np2 * nN; b.soC = nN; b.siC = (long)np2 * nN; b.ldc = n;
+      b.accumulate = 1;
+      b.nzi = ca;
+      b.M = N; b.N = n; b.K = n;
+      if ((st = cg_launch(b, np2 * ca, 0, s))) return st;
     }
     for (int t0 = 0; t0 < nt; t0 += ts) {
       const int ct = std::min(ts, nt - t0);

@@ -343,6 +343,16 @@ def paired_hermitian(rng: np.random.Generator, kneg, N: int, scale: float) -> np
     return U
 
 
+def column_support(N: int, per_band: int, seed: int, band: int = 50) -> np.ndarray:
+    """Sorted THC column indices, per_band distinct ones drawn in each band of
+    `band` columns: the support of a collocation matrix that is zero
+    elsewhere (every 64- or 80-wide column tile holds some)."""
+    rng = np.random.default_rng(seed)
+    cols = [b0 + rng.choice(min(band, N - b0), size=min(per_band, N - b0), replace=False)
+            for b0 in range(0, N, band)]
+    return np.sort(np.concatenate(cols))
+
+
 # ---------------------------------------------------------------------------
 # the five workload recipes
 # ---------------------------------------------------------------------------

@@ -137,6 +137,30 @@ def test_dynamic_full_size_on_column_subset(B, precision):
     assert err <= TOL[precision]
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_real_w_product_and_asymmetric_w(B, precision):
+    """A W_d(tau) mirror symmetric in tau (the physical case) runs the real
+    W(Omega) product in the float32 and bf16x3 plans (the plan reports
+    dynamic_real_w = 1); a W(tau) with an added part odd about beta/2 keeps
+    the complex block product (dynamic_real_w = 0), as do float64 plans.  Both
+    against the oracle, which transforms W(tau) as it is."""
+    n, N, nt, beta = 21, 90, 20, 40.0
+    wl = synth.small_molecule(n, N, nt, beta, seed=79, dynamic=True)
+    tp = _pair(wl)
+    rng = np.random.default_rng(5)
+    G = om.g_tau(wl["eps"], wl["Q"], 0.0, beta, wl["tau"]) + 0.05 * rng.standard_normal((nt, n, n))
+    odd = (wl["tau"] - beta / 2) / beta
+    W_asym = wl["W_tau"] + 0.5 * odd[:, None, None] * wl["W_tau"][nt // 2][None]
+    for W, want in ((wl["W_tau"], precision != "fp64"), (W_asym, False)):
+        log(f"dynamic real-W check {precision}, mirror symmetric: {W is wl['W_tau']}")
+        got, plan = _run(B, wl, tp, precision, wl["X"], W, wl["V"], G)
+        assert B.sox_plan_describe(plan)["dynamic_real_w"] == (1 if want else 0)
+        ref = om.sigma_dynamic_thc(wl["X"], W, wl["V"], G, G[::-1], tp["T_fwd"], tp["T_bwd"])
+        err = rel_err(got, ref)
+        log(f"  rel err {err:.3e}")
+        assert err <= TOL[precision]
+
+
 def test_dynamic_requires_transform_pair(B):
     import torch
     wl = synth.small_molecule(4, 8, 6, 5.0, seed=1, dynamic=True)

@@ -47,11 +47,7 @@ def B():
 
 
 def _support(N, per_band, seed, band=50):
-    """per_band distinct columns drawn in each band of `band` columns."""
-    rng = np.random.default_rng(seed)
-    cols = [b0 + rng.choice(min(band, N - b0), size=per_band, replace=False)
-            for b0 in range(0, N, band)]
-    return np.sort(np.concatenate(cols))
+    return synth.column_support(N, per_band, seed, band)
 
 
 def cdev(a):
@@ -205,3 +201,29 @@ def test_dynamic_vjp_full_size_column_support(B):
     assert np.abs(got["dX"][:, off]).max() == 0.0
     assert np.abs(got["dV"][off]).max() == 0.0 and np.abs(got["dV"][:, off]).max() == 0.0
     assert np.abs(got["dW"][:, off]).max() == 0.0 and np.abs(got["dW"][:, :, off]).max() == 0.0
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_solid_sosex_dyn_full_size_column_support(B, solid_case, dyn_ref, precision):
+    """The benchmarked step: SOX(V,V) + SOX(W_d(tau),V) of the full 3x3x3
+    shape in one pass (sox_sigma_vertex, SOSEX_dyn), against the oracle's
+    dynamic chain plus its static chain at the sampled nodes, on the
+    dynamic test's column support."""
+    import torch
+    wl, G, tp = solid_case["wl"], solid_case["G"], solid_case["tp"]
+    cols, dref = dyn_ref
+    n, N, nt, nk = wl["n"], wl["N"], wl["n_tau"], wl["nk"]
+    Vs = wl["V"][:, cols][:, :, cols]
+    bare = osd.sigma_solid_thc(wl["X"][:, :, cols], Vs, Vs, G[:, list(BARE_NODES)], _tables(wl))
+    ref = bare + dref[:, list(BARE_NODES)]
+    log(f"solid sosex_dyn full size {precision}: support {len(cols)}")
+    plan = B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision=precision, kmesh=wl["mesh"],
+                  t_fwd=tp["T_fwd"], t_bwd=tp["T_bwd"])
+    W = _w_device(solid_case, nk, nt, N)
+    S = torch.empty((nk, nt, n, n), dtype=torch.complex128, device="cuda")
+    B.sox_sigma_vertex(plan, "sosex_dyn", cdev(_x_on(wl, cols)), cdev(wl["V"]), W, cdev(G), S)
+    torch.cuda.synchronize()
+    del W
+    err = rel_err(host(S)[:, list(BARE_NODES)], ref)
+    log(f"  rel err {err:.3e}")
+    assert err <= TOL[precision]

@@ -1,0 +1,153 @@
+"""GPU parity of the composite vertex self-energies (sox_sigma_vertex)
+against the oracle's term-by-term definitions (oracle/sox_vertex.py), through
+the C ABI, for molecules and k-point meshes, every kind and precision.
+
+The *_dyn kinds run on a G built from a symmetric (Hermitian per k) Fock
+matrix, the condition under which SOX(V, W_d) is the mirror image of
+SOX(W_d, V) (pinned in tests/test_oracle_vertex.py).  Tolerances (max |diff|
+/ max |oracle|): fp64 1e-12 static kinds and 1e-10 dynamic kinds (the
+transform pair's conditioning, as for the dynamic entry), fp32 1e-6,
+bf16x3 1e-4.
+"""
+import numpy as np
+import pytest
+
+from oracle import sox_mol as om
+from oracle import sox_solid as osd
+from oracle import sox_vertex as ovx
+from paper_2412_18829_amd import synth
+from tests.gpu_util import dev, have_gpu, host, log, rel_err
+
+pytestmark = pytest.mark.gpu
+
+KINDS = ("sosex_stat", "2sosex_stat", "g3w2_stat", "sosex_dyn", "2sosex_dyn")
+
+
+def _tol(precision, kind):
+    if precision == "fp64":
+        return 1e-10 if kind.endswith("dyn") else 1e-12
+    return {"fp32": 1e-6, "bf16x3": 1e-4}[precision]
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not have_gpu():
+        pytest.skip("no GPU")
+    from paper_2412_18829_amd import binding
+    binding.load()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def mol():
+    n, N, nt, beta = 11, 60, 18, 12.0
+    wl = synth.small_molecule(n, N, nt, beta, seed=811, static=True, dynamic=True)
+    tp = synth.bosonic_transform_pair(wl["tau"], beta, omega_max=10.0, tol=1e-10)
+    G = om.g_tau(wl["eps"], wl["Q"], 0.0, beta, wl["tau"])
+    refs = {}
+    for kind in KINDS:
+        W = wl["W_tau"] if kind.endswith("dyn") else wl["W0"]
+        refs[kind] = ovx.vertex_mol(kind, wl["X"], wl["V"], W, G, tp["T_fwd"], tp["T_bwd"])
+    return wl, tp, G, refs
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("kind", KINDS)
+def test_vertex_molecule_vs_oracle(B, mol, kind, precision):
+    import torch
+    wl, tp, G, refs = mol
+    n, N, nt = wl["n"], wl["N"], wl["n_tau"]
+    log(f"vertex molecule {kind} {precision}")
+    plan = B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision=precision,
+                  t_fwd=tp["T_fwd"], t_bwd=tp["T_bwd"])
+    W = wl["W_tau"] if kind.endswith("dyn") else wl["W0"]
+    S = torch.empty((nt, n, n), dtype=torch.float64, device="cuda")
+    B.sox_sigma_vertex(plan, kind, dev(wl["X"]), dev(wl["V"]), dev(W), dev(G), S)
+    torch.cuda.synchronize()
+    err = rel_err(host(S), refs[kind])
+    log(f"  rel err {err:.3e}")
+    assert err <= _tol(precision, kind)
+
+
+@pytest.fixture(scope="module")
+def solid():
+    wl = synth.add_dynamic_screening_solid(synth.solid((3, 1, 1), 7, 33, 10, 10.0, seed=812),
+                                           n_poles=3)
+    rng = np.random.default_rng(812)
+    W0 = wl["V"] + synth.paired_hermitian(rng, wl["kneg"], wl["N"], 0.3 / wl["N"])
+    tp = synth.bosonic_transform_pair(wl["tau"], wl["beta"], omega_max=10.0, tol=1e-10)
+    G = osd.g_tau_k(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    tb = (wl["kvecs"], wl["kdiff"], wl["ksum"], wl["kneg"])
+    dyn = osd.sigma_solid_dynamic_thc(wl["X"], wl["W_tau"], wl["V"], G, tp["T_fwd"], tp["T_bwd"], tb)
+    refs = {}
+    for kind in KINDS:
+        W = wl["W_tau"] if kind.endswith("dyn") else W0
+        refs[kind] = ovx.vertex_solid(kind, wl["X"], wl["V"], W, G, tb, tp["T_fwd"], tp["T_bwd"],
+                                      dyn=dyn)
+    return wl, W0, tp, G, refs
+
+
+def cdev(a):
+    import torch
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.complex128, device="cuda")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+@pytest.mark.parametrize("kind", KINDS)
+def test_vertex_solid_vs_oracle(B, solid, kind, precision):
+    import torch
+    wl, W0, tp, G, refs = solid
+    log(f"vertex solid 3x1x1 {kind} {precision}")
+    plan = B.Plan(wl["n"], wl["N"], wl["tau"], wl["weights"], wl["beta"], precision=precision,
+                  kmesh=wl["mesh"], t_fwd=tp["T_fwd"], t_bwd=tp["T_bwd"])
+    W = wl["W_tau"] if kind.endswith("dyn") else W0
+    S = torch.empty(G.shape, dtype=torch.complex128, device="cuda")
+    B.sox_sigma_vertex(plan, kind, cdev(wl["X"]), cdev(wl["V"]), cdev(W), cdev(G), S)
+    torch.cuda.synchronize()
+    err = rel_err(host(S), refs[kind])
+    log(f"  rel err {err:.3e}")
+    assert err <= _tol(precision, kind)
+
+
+@pytest.mark.parametrize("shape", [((2, 2, 1), 5, 26, 9), ((3, 3, 3), 3, 12, 6)],
+                         ids=lambda s: "x".join(map(str, s[0])))
+def test_sosex_dyn_one_pass_on_meshes(B, shape):
+    """The one-pass SOSEX_dyn of k-point plans (the bare term inside the
+    dynamic chain) on further meshes, against the oracle's two terms; with a
+    workspace budget that splits the bare term's tau slabs, the same."""
+    import os
+    import torch
+    mesh, n, N, nt = shape
+    wl = synth.add_dynamic_screening_solid(synth.solid(mesh, n, N, nt, 10.0, seed=813 + n),
+                                           n_poles=2)
+    tp = synth.bosonic_transform_pair(wl["tau"], wl["beta"], omega_max=10.0, tol=1e-10)
+    G = osd.g_tau_k(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    tb = (wl["kvecs"], wl["kdiff"], wl["ksum"], wl["kneg"])
+    log(f"sosex_dyn one pass {shape}")
+    ref = ovx.vertex_solid("sosex_dyn", wl["X"], wl["V"], wl["W_tau"], G, tb, tp["T_fwd"],
+                           tp["T_bwd"])
+    for precision in ("fp64", "fp32"):
+        plan = B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision=precision,
+                      kmesh=mesh, t_fwd=tp["T_fwd"], t_bwd=tp["T_bwd"])
+        S = torch.empty(G.shape, dtype=torch.complex128, device="cuda")
+        B.sox_sigma_vertex(plan, "sosex_dyn", cdev(wl["X"]), cdev(wl["V"]), cdev(wl["W_tau"]),
+                           cdev(G), S)
+        torch.cuda.synchronize()
+        err = rel_err(host(S), ref)
+        log(f"  {precision} rel err {err:.3e}")
+        assert err <= _tol(precision, "sosex_dyn")
+
+
+def test_vertex_rejects_bad_requests(B):
+    import torch
+    wl = synth.small_molecule(4, 8, 6, 5.0, seed=1, static=True)
+    plan = B.Plan(4, 8, wl["tau"], wl["weights"], wl["beta"], precision="fp32")
+    S = torch.empty((6, 4, 4), dtype=torch.float64, device="cuda")
+    args = (dev(wl["X"]), dev(wl["V"]))
+    G = dev(np.zeros((6, 4, 4)))
+    with pytest.raises(B.SoxError) as ei:   # a dynamic kind without a transform pair
+        B.sox_sigma_vertex(plan, "sosex_dyn", *args, dev(np.zeros((6, 8, 8))), G, S)
+    assert ei.value.status == 1
+    with pytest.raises(B.SoxError) as ei:   # an unknown kind
+        B.sox_sigma_vertex(plan, 9, *args, dev(wl["W0"]), G, S)
+    assert ei.value.status == 1
