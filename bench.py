@@ -249,6 +249,8 @@ def main() -> int:
                          "dynamic molecular run")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time of the oracle sample")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time eager launches instead of HIP graph replays")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="run one device copy of this size first (counter calibration)")
     args = ap.parse_args()
@@ -306,12 +308,17 @@ def main() -> int:
         torch.cuda.synchronize()
         del a, b
 
-    def run(precision: str, steps: int, warmup: int, profile: bool, Xwarm=None):
+    def run(precision: str, steps: int, warmup: int, profile: bool, Xwarm=None,
+            graph: bool = False):
         """warmup untimed steps, then `steps` timed ones.  Xwarm: the first
         warmup step runs on this collocation matrix instead (its Sigma is
-        returned as Sigma_warm), and with profile the last warmup step records
-        every stage (the per-stage breakdown), so neither costs extra steps."""
+        returned as Sigma_warm).  With profile, a later warmup step records
+        every stage (the per-stage breakdown and the dominant kernel's launch
+        times); with graphs, the last warmup step captures the sweep as a HIP
+        graph and the timed steps replay it.  None of this adds steps."""
         Xr = X
+        use_graph = graph and warmup >= (3 if profile else 2)
+        prof_step = warmup - 2 if use_graph else warmup - 1
         extra = {}
         if tp is not None:
             extra = dict(t_fwd=tp["T_fwd"], t_bwd=tp["T_bwd"])
@@ -349,32 +356,46 @@ def main() -> int:
                 sig_warm = S.cpu().numpy()
                 Xr = X
                 continue
-            if profile and w == warmup - 1 and warmup >= 2:
+            if use_graph and w == warmup - 1:
+                B.sox_plan_set_graph(plan, True)   # this step captures, later ones replay
+            if profile and w == prof_step and warmup >= 2:
                 B.sox_profile_select(plan, None)
                 B.sox_profile_enable(plan, True)
                 B.sox_profile_read(plan, reset=True)
                 step()
                 torch.cuda.synchronize()
-                stages_warm = {k: round(v[0], 4) for k, v in
-                               B.sox_profile_read(plan, reset=True).items()
+                prof_warm = B.sox_profile_read(plan, reset=True)
+                stages_warm = {k: round(v[0], 4) for k, v in prof_warm.items()
                                if k != "dropped" and v[1] > 0}
                 B.sox_profile_enable(plan, False)
                 continue
             step()
         torch.cuda.synchronize()
-        if profile:
+        if profile and not use_graph:
             # inside the timed region only the dominant stage is bracketed
-            # with events (on the stream its kernels run on)
+            # with events (on the stream its kernels run on); graph replays
+            # record none, so with graphs the profiled warmup step times it
             B.sox_profile_select(plan, [DOMINANT[kind][0]])
             B.sox_profile_enable(plan, True)
             B.sox_profile_read(plan, reset=True)
+        # per-step device times from events on the stream the steps run on
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(steps)]
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for i in range(steps):
+            evs[i][0].record()
             step()
+            evs[i][1].record()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        step_ms = sorted(a.elapsed_time(b) for a, b in evs)
         prof = stages = None
-        if profile:
+        prof_steps = steps
+        if profile and use_graph:
+            prof, prof_steps = prof_warm, 1
+            stages = stages_warm
+        elif profile:
             prof = B.sox_profile_read(plan, reset=True)
             if warmup >= 2:
                 stages = stages_warm
@@ -392,9 +413,13 @@ def main() -> int:
             B.sox_profile_enable(plan, False)
         energies = E.cpu().numpy()[:cur[0]]
         res = dict(seconds=t1 - t0, Sigma=S.cpu().numpy(), prof=prof, stages=stages,
-                   Sigma_warm=sig_warm,
+                   Sigma_warm=sig_warm, prof_steps=prof_steps, graph=use_graph,
+                   median_step_ms=step_ms[len(step_ms) // 2] if len(step_ms) % 2
+                   else 0.5 * (step_ms[len(step_ms) // 2 - 1] + step_ms[len(step_ms) // 2]),
                    energy=float(energies[warmup + steps - 1, 0]),
-                   energy_spread=float(np.ptp(energies[:, 0])),
+                   # over the steps on the workload's own inputs (the first
+                   # warmup step of the solid runs on the error input)
+                   energy_spread=float(np.ptp(energies[1 if Xwarm is not None else 0:, 0])),
                    plan=B.sox_plan_describe(plan))
         # release this plan's workspace before the next leg builds its own
         del plan, ws, G, S, E
@@ -409,7 +434,8 @@ def main() -> int:
         Xc = torch.zeros_like(X)
         Xc[:, :, gold["cols"]] = X[:, :, gold["cols"]]
         args.warmup = max(args.warmup, 1)
-    main_run = run(args.precision, args.steps, args.warmup, profile=True, Xwarm=Xc)
+    main_run = run(args.precision, args.steps, args.warmup, profile=True, Xwarm=Xc,
+                   graph=not args.no_graph)
     sec = main_run["seconds"]
     ms_per_step = 1e3 * sec / args.steps
     value = args.steps / sec
@@ -424,7 +450,7 @@ def main() -> int:
         kname = "cgemm_panel_bf16x3_kernel"
     dom_ms, dom_launches = prof[stage]
     dom_avg_ms = dom_ms / max(dom_launches, 1)
-    dom_flops_per_launch = fl[stage] * args.steps / max(dom_launches, 1)
+    dom_flops_per_launch = fl[stage] * main_run["prof_steps"] / max(dom_launches, 1)
     achieved = dom_flops_per_launch / (dom_avg_ms * 1e-3) / 1e12
     peak = PEAK_TFLOPS[args.precision]
     stage_ms = main_run["stages"]
@@ -445,12 +471,13 @@ def main() -> int:
         solid_err = {"max_rel_err": float(np.abs(got - ref).max() / np.abs(ref).max()),
                      "against": ("FP64 oracle (tests/golden/c5_sosex_dyn_support8.npz) on the "
                                  f"workload with X restricted to {len(gold['cols'])} of {N} THC "
-                                 f"columns, first warmup step; momenta {list(gold['k'])}, nodes "
-                                 f"{list(gold['nodes'])}")}
+                                 f"columns, first warmup step; momenta "
+                                 f"{[int(k) for k in gold['k']]}, nodes "
+                                 f"{[int(j) for j in gold['nodes']]}")}
     if (args.precision == "fp32" and kind in ("bare", "static", "dynamic") and not solid
             and not args.no_bf16x3_compare):
         # the split-precision path on the same workload, same step
-        rb = run("bf16x3", args.steps, args.warmup, profile=True)
+        rb = run("bf16x3", args.steps, args.warmup, profile=True, graph=not args.no_graph)
 
     vjp = None
     if kind == "dynamic" and not args.no_vjp and args.precision != "bf16x3":
@@ -511,7 +538,7 @@ def main() -> int:
     if rb is not None:
         sb = rb["seconds"] / args.steps
         fb_ms, fb_n = rb["prof"]["fused"]
-        fb_ach = fl["fused"] * args.steps / max(fb_n, 1) / (fb_ms / max(fb_n, 1) * 1e-3) / 1e12
+        fb_ach = fl["fused"] * rb["prof_steps"] / max(fb_n, 1) / (fb_ms / max(fb_n, 1) * 1e-3) / 1e12
         d = np.abs(rb["Sigma"] - main_run["Sigma"]).max() / np.abs(main_run["Sigma"]).max()
         out["bf16x3_path"] = {
             "sweeps_per_s": 1.0 / sb, "ms_per_step": 1e3 * sb,
@@ -545,6 +572,9 @@ def main() -> int:
                    "step": ("G(tau) + Sigma(all tau" + (", all k; SOX(V,V) + SOX(W_d,V)" if solid
                                                           else "") + ") + E_GM")},
         "tflops_alg": sweep_flops / (ms_per_step * 1e-3) / 1e12,
+        "median_step_ms": main_run["median_step_ms"],
+        "timed_as": ("HIP graph replays of the whole sweep (captured in the last warmup step)"
+                     if main_run["graph"] else "eager launches"),
         "energy_gm": main_run["energy"],
         "energy_gm_spread_over_steps": main_run["energy_spread"],
         "max_rel_err": main_err,

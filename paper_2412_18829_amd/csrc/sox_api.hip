@@ -874,47 +874,57 @@ sox_status run_static(sox_plan& p, int entry, const double* X, const double* U1,
 // (W2 [2NP][2NP], GG2 [vcn][2NP], AW [2NP][vcn]).  float32 on the LDS-staged
 // GEMM (C4: 1.28 s per sweep on the direct-load kernel), float64 on the
 // direct-load one.
-// Mirror symmetry of W_d(tau): per-block partial maxima of
-// |W(tau_j) - W(tau_{n_tau-1-j})| and of |W| over every node pair and entry.
+// Per-block partial maxima of |Im W(Omega)| and |Re W(Omega)| over the block
+// operator W2 = [[Wr, -Wi], [Wi, Wr]] of every Matsubara sample.
 constexpr int kWchkBlocks = 256;
-__global__ __launch_bounds__(256) void mirror_asym_kernel(const double* W, int nt, long nn,
-                                                          double* part) {
-  __shared__ double sa[256], sm[256];
+template <typename T>
+__global__ __launch_bounds__(256) void wimag_kernel(const T* W2, int nw, int NP, double* part) {
+  __shared__ double si[256], sr[256];
   double a = 0.0, m = 0.0;
-  const long half = (long)((nt + 1) / 2) * nn;
-  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < half; i += (long)gridDim.x * 256) {
-    const long j = i / nn, e = i - j * nn;
-    const double x = W[j * nn + e], y = W[(nt - 1 - j) * nn + e];
-    a = fmax(a, fabs(x - y));
-    m = fmax(m, fmax(fabs(x), fabs(y)));
+  const long ld = 2L * NP, per = (long)NP * NP;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < (long)nw * per;
+       i += (long)gridDim.x * 256) {
+    const long w = i / per, e = i - w * per;
+    const long P = e / NP, Q = e - P * NP;
+    const T* B = W2 + w * ld * ld;
+    a = fmax(a, fabs((double)B[(NP + P) * ld + Q]));
+    m = fmax(m, fabs((double)B[P * ld + Q]));
   }
-  sa[threadIdx.x] = a;
-  sm[threadIdx.x] = m;
+  si[threadIdx.x] = a;
+  sr[threadIdx.x] = m;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) {
-      sa[threadIdx.x] = fmax(sa[threadIdx.x], sa[threadIdx.x + w]);
-      sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + w]);
+      si[threadIdx.x] = fmax(si[threadIdx.x], si[threadIdx.x + w]);
+      sr[threadIdx.x] = fmax(sr[threadIdx.x], sr[threadIdx.x + w]);
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    part[2 * blockIdx.x] = sa[0];
-    part[2 * blockIdx.x + 1] = sm[0];
+    part[2 * blockIdx.x] = si[0];
+    part[2 * blockIdx.x + 1] = sr[0];
   }
 }
 
-// Whether the molecular dynamic entry may run the real W(Omega) product: a
-// float32 or bf16x3 plan and W_d(tau) mirror symmetric in tau to 1e-13 of
-// its largest entry.  A symmetric W(tau) has a real W(i Omega) in the
-// continuum; the plan's discrete transform pair leaves an imaginary part near
-// 1e-8 of the real one, which those plans' 1e-6 / 1e-4 bounds absorb (float64
-// plans keep the block product).  Synchronises `s` once to read the maxima.
-sox_status dynamic_w_is_real(sox_plan& p, const double* Wtau, hipStream_t s, bool* real_w) {
+// Whether the molecular dynamic entry of a float32 or bf16x3 plan may run
+// the real W(Omega) product: the plan's transform of W_d(tau) has an
+// imaginary part below float32 resolution of its real part (max |Im W| <=
+// 2^-24 max |Re W|), so its products lie below the rounding of the real
+// ones.  A W(tau) mirror symmetric in tau has a real W(i Omega) in the
+// continuum; on a fine grid the discrete pair keeps that (about 1e-8 on the
+// n=300, 120-node workload), on a coarse one it does not, and an asymmetric
+// W(tau) never does.  Builds W(Omega) into the dynamic workspace `dws` (the
+// pass rebuilds it) and synchronises `s` once to read the maxima.
+sox_status dynamic_w_is_real(sox_plan& p, const double* Wtau, void* dws, hipStream_t s,
+                             bool* real_w) {
   *real_w = false;
   if (p.precision == SOX_FP64 || p.nk > 1 || !p.d_wchk) return SOX_OK;
-  const long nn = (long)p.N * p.N;
-  hipLaunchKernelGGL(mirror_asym_kernel, dim3(kWchkBlocks), dim3(256), 0, s, Wtau, p.n_tau, nn,
+  const DynLayout L = dyn_layout_for(p, p.vc, p.eslab);
+  float* W2 = (float*)((char*)dws + L.w2);
+  const int nw = p.n_omega, nt = p.n_tau, N = p.N, NP = p.NP;
+  WOmegaProb<float> wp{p.d_tf2, Wtau, W2, nw, nt, N, NP, 2 * nw, NP * NP, nt, nullptr};
+  SOX_HIP((launch_gemm<WOmegaProb<float>, double, 2, 2, 2, 2>(wp, 1, s)));
+  hipLaunchKernelGGL(wimag_kernel<float>, dim3(kWchkBlocks), dim3(256), 0, s, W2, nw, NP,
                      p.d_wchk);
   SOX_HIP(hipGetLastError());
   double part[2 * kWchkBlocks];
@@ -925,7 +935,7 @@ sox_status dynamic_w_is_real(sox_plan& p, const double* Wtau, hipStream_t s, boo
     a = std::max(a, part[2 * b]);
     m = std::max(m, part[2 * b + 1]);
   }
-  *real_w = m > 0.0 && a <= 1e-13 * m;
+  *real_w = m > 0.0 && a <= std::ldexp(m, -24);
   return SOX_OK;
 }
 
@@ -1182,16 +1192,30 @@ sox_status launch_fill(T* ptr, long count, hipStream_t s) {
   return SOX_OK;
 }
 
+// A wavefront keeps all ny output columns in registers (at most 20 blocks of
+// 16); a wider y range runs as several launches over 320-column chunks of F
+// and Out, each recomputing the stage-1 tile it weights.
 template <typename T>
 sox_status launch_hc_cfg(const sox_plan& p, HcArgs<T, double> a, int nx, hipStream_t s) {
+  constexpr int kYChunk = 320;
+  if (a.ny > kYChunk) {
+    for (int y0 = 0; y0 < a.ny; y0 += kYChunk) {
+      HcArgs<T, double> b = a;
+      b.FT = a.FT + (long)y0 * a.f_ld;
+      b.Out = a.Out + y0;
+      b.ny = std::min(kYChunk, a.ny - y0);
+      sox_status st = launch_hc_cfg<T>(p, b, nx, s);
+      if (st) return st;
+    }
+    return SOX_OK;
+  }
   const int nyb = a.ny / 16;
   const bool wide = sizeof(T) == 4 && nx % 128 == 0;
 #define SOX_HC(XB, YB) SOX_HIP((launch_hc<T, double, XB, YB>(a, nx, s)))
   if (nyb <= 4) { if (wide) SOX_HC(2, 4); else SOX_HC(1, 4); }
   else if (nyb <= 8) { if (wide) SOX_HC(2, 8); else SOX_HC(1, 8); }
   else if (nyb <= 13) { if (wide) SOX_HC(2, 13); else SOX_HC(1, 13); }
-  else if (nyb <= 20) { if (wide) SOX_HC(2, 20); else SOX_HC(1, 20); }
-  else return fail(SOX_ERR_UNSUPPORTED, "adjoint kernels support n_orb <= 320");
+  else { if (wide) SOX_HC(2, 20); else SOX_HC(1, 20); }
 #undef SOX_HC
   (void)p;
   return SOX_OK;
@@ -2207,7 +2231,10 @@ sox_status sox_sigma_vertex(sox_plan* plan, int32_t kind, const double* X, const
   st = check_ws(plan, SOX_ENTRY_VERTEX, ws, ws_bytes);
   if (st) return st;
   bool real_w = false;
-  if (dyn && (st = dynamic_w_is_real(*plan, W, (hipStream_t)stream, &real_w))) return st;
+  if (dyn && (st = dynamic_w_is_real(*plan, W, (char*)ws + vertex_layout_for(*plan).pass,
+                                     (hipStream_t)stream, &real_w)))
+    return st;
+  if (dyn && plan->nk == 1) plan->last_w_real = real_w ? 1 : 0;
   const uintptr_t key[9] = {(uintptr_t)SOX_ENTRY_VERTEX, (uintptr_t)X, (uintptr_t)V,
                             (uintptr_t)W, (uintptr_t)G, (uintptr_t)Sigma, (uintptr_t)ws,
                             (uintptr_t)ws_bytes, (uintptr_t)kind * 2 + (real_w ? 1 : 0)};
@@ -2267,7 +2294,7 @@ sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_ta
                 "the molecular dynamic entry in bf16x3 needs the LDS-staged fused kernel, whose "
                 "32-bit panel offsets overflow at this n_orb and n_thc");
   bool real_w = false;
-  if ((st = dynamic_w_is_real(*plan, W_tau, (hipStream_t)stream, &real_w))) return st;
+  if ((st = dynamic_w_is_real(*plan, W_tau, ws, (hipStream_t)stream, &real_w))) return st;
   if (plan->nk == 1) plan->last_w_real = real_w ? 1 : 0;
   const uintptr_t key[9] = {(uintptr_t)SOX_ENTRY_DYNAMIC, (uintptr_t)X, (uintptr_t)W_tau,
                             (uintptr_t)V, (uintptr_t)G, (uintptr_t)Sigma, (uintptr_t)ws,

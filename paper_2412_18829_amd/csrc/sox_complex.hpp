@@ -914,6 +914,157 @@ __global__ void mirror_columns_kernel(const double* G, T* out, int nk, int nt, i
   }
 }
 
+// Real block form of the complex product A(Omega) = W(Omega) GG(Omega) on a
+// real NT GEMM: with A rows [Re W | -Im W] (K = 2 Nq) and, per complex
+// column c, the two B rows [Re GG | Im GG] and [Im GG | -Re GG], the real
+// product writes Re and Im of column c next to each other (interleaved
+// complex).  Both B rows of c are read from one [Re | Im | -Re] row of 3 Nq
+// (row 2c + s starts s Nq into it).  Each half is Nq wide (N rounded up to
+// 16) and zero past N.  Output float (f != null) or bf16 hi / lo planes.
+__device__ __forceinline__ void put_split(float x, long i, float* f, bf16_t* hi, bf16_t* lo) {
+  if (f) {
+    f[i] = x;
+  } else {
+    const bf16_t h = f32_to_bf16(x);
+    hi[i] = h;
+    lo[i] = f32_to_bf16(x - bf16_to_f32(h));
+  }
+}
+
+// wm [batch][N][N] complex -> [batch][N][2 Nq] = [Re W | -Im W]
+__global__ void wblock_kernel(const float* wm, long nbatch, int N, int Nq, float* f, bf16_t* hi,
+                              bf16_t* lo) {
+  const long row = 2L * Nq;
+  SOX_FOR_FLAT(i, nbatch * N * row) {
+    const long br = i / row;              // (batch, P)
+    const int k = (int)(i - br * row);
+    const int half = k >= Nq, Q = k - half * Nq;
+    float x = 0.f;
+    if (Q < N) {
+      const float* w = wm + 2 * (br * N + Q);
+      x = half ? -w[1] : w[0];
+    }
+    put_split(x, i, f, hi, lo);
+  }
+}
+
+// GG rows: ggw [r][ldr complex][...] with ncols columns of N per row r ->
+// [r][ncols][3 Nq] = [Re | Im | -Re] (row stride ncols * 3 Nq per r)
+__global__ void gblock_kernel(const float* ggw, long nr, long ldr, long ncols, int N, int Nq,
+                              float* f, bf16_t* hi, bf16_t* lo) {
+  const long row = 3L * Nq;
+  SOX_FOR_FLAT(i, nr * ncols * row) {
+    const long rc = i / row;
+    const int k = (int)(i - rc * row);
+    const long r = rc / ncols, c = rc - r * ncols;
+    const int part = k / Nq, Q = k - part * Nq;
+    float x = 0.f;
+    if (Q < N) {
+      const float* gv = ggw + 2 * (r * ldr + c * N + Q);
+      x = part == 0 ? gv[0] : part == 1 ? gv[1] : -gv[0];
+    }
+    put_split(x, i, f, hi, lo);
+  }
+}
+
+// The solid eq:GG chain's forward transform with GG formed in registers,
+// written straight in the block form above:
+//   GG(r)[l][u][Q] = sum_j Tc[r][j] G^{k_v - q1}_uQ(tau_j) G^{k_v}_Qv(beta - tau_j)
+// for the pairs l = p0 .. p0 + cp - 1 of a slab and one orbital v, with Tc
+// = [T_fwd; conj T_fwd] (M = 2 n_omega rows).  Tc stays in LDS for the whole
+// launch (one workgroup per CU); each wavefront owns 16 consecutive Q of one
+// (l, u) at a time and computes all M rows on float64 MFMAs (four real
+// products per complex one); rows [Re | Im | -Re] of 3 Nq per (r, l, u)
+// column, zero for Q >= N.
+constexpr int kFtsRows = 80, kFtsLd = 113;  // M <= 80 rows, n_tau <= 112 nodes
+struct FtSolidArgs {
+  const double* tfc;   // [M][nt] complex
+  const double* gwp;   // [nt][nk][n][N] complex, G_uQ(tau)
+  const double* grqt;  // [nt][nk][n][N] complex, G_vQ(tau), read at beta - tau
+  const int* k_of;     // per pair: k_v
+  const int* kmq_of;   // per pair: k_v - q1
+  float* f;            // float output, or
+  bf16_t* hi;          // bf16 hi and lo planes
+  bf16_t* lo;
+  long rstride;        // output elements between rows r: cp n 3 Nq
+  int M, nt, nk, n, N, Nq, p0, cp, v;
+};
+
+__global__ __launch_bounds__(512) void ft_solid_kernel(const FtSolidArgs a, long nblocks) {
+  __shared__ double tr[kFtsRows * kFtsLd], ti[kFtsRows * kFtsLd];
+  const int K = a.nt, Kp = (K + 3) & ~3;
+  for (int e = threadIdx.x; e < kFtsRows * Kp; e += blockDim.x) {
+    const int r = e / Kp, k = e - (e / Kp) * Kp;
+    const bool ok = r < a.M && k < K;
+    tr[r * kFtsLd + k] = ok ? a.tfc[2 * ((long)r * K + k)] : 0.0;
+    ti[r * kFtsLd + k] = ok ? a.tfc[2 * ((long)r * K + k) + 1] : 0.0;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int nqb = a.Nq / 16;
+  const int nrb = (a.M + 15) / 16;
+  const long per = (long)a.n * a.N;
+  for (long blk = (long)blockIdx.x * nwaves + wave; blk < nblocks;
+       blk += (long)gridDim.x * nwaves) {
+    const int qb = (int)(blk % nqb);
+    const long rest = blk / nqb;
+    const int u = (int)(rest % a.n);
+    const int l = (int)(rest / a.n);
+    const int pair = a.p0 + l;
+    const int kv = a.k_of[pair], kq = a.kmq_of[pair];
+    const int Q = 16 * qb + li;
+    const bool qok = Q < a.N;
+    const int Qc = qok ? Q : a.N - 1;
+    const double* gu = a.gwp + 2 * ((long)kq * per + (long)u * a.N + Qc);
+    const double* gv = a.grqt + 2 * ((long)kv * per + (long)a.v * a.N + Qc);
+    const long tstride = 2L * a.nk * per;
+    f64x4 cr[5], ci[5];
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      cr[b] = zero4<double>();
+      ci[b] = zero4<double>();
+    }
+    for (int k0 = 0; k0 < Kp; k0 += 4) {
+      const int k = k0 + g;
+      double xr = 0.0, xi = 0.0;
+      if (qok && k < K) {
+        const double* pu = gu + (long)k * tstride;
+        const double* pv = gv + (long)(K - 1 - k) * tstride;
+        const double ar = pu[0], ai = pu[1], br = pv[0], bi = pv[1];
+        xr = ar * br - ai * bi;
+        xi = ar * bi + ai * br;
+      }
+#pragma unroll
+      for (int b = 0; b < 5; ++b) {
+        if (b >= nrb) break;
+        const int o = (16 * b + li) * kFtsLd + k;
+        const double t_r = tr[o], t_i = ti[o];
+        cr[b] = mfma16x16x4(t_r, xr, cr[b]);
+        cr[b] = mfma16x16x4(-t_i, xi, cr[b]);
+        ci[b] = mfma16x16x4(t_r, xi, ci[b]);
+        ci[b] = mfma16x16x4(t_i, xr, ci[b]);
+      }
+    }
+    // lane (li, g) holds rows 16 b + g + 4 i of column Q
+    const long col = ((long)l * a.n + u) * 3 * a.Nq + Q;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+      if (b >= nrb) break;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int r = 16 * b + acc_row<double>(g, i);
+        if (r >= a.M) continue;
+        const long o = (long)r * a.rstride + col;
+        const float vr = qok ? (float)cr[b][i] : 0.f, vi = qok ? (float)ci[b][i] : 0.f;
+        put_split(vr, o, a.f, a.hi, a.lo);
+        put_split(vi, o + a.Nq, a.f, a.hi, a.lo);
+        put_split(-vr, o + 2 * a.Nq, a.f, a.hi, a.lo);
+      }
+    }
+  }
+}
+
 __global__ void real_to_complex_kernel(const double* x, double* out, long count) {
   SOX_FOR_FLAT(i, count) {
     out[2 * i] = x[i];

@@ -54,6 +54,12 @@ struct DenseLdsArgs {
   int vec;              // vector stores: 0 none, 1 four columns, 2 paired split planes (launcher)
   double* C64 = nullptr;  // float64 output instead of C (same offsets)
   int accumulate = 0;     // float64 output only: C64 += result
+  // split addressing (defaults: plain rows and columns): B row r sits at
+  // (r / bsplit) bhi + (r % bsplit) ldb, C column c at (c / csplit) chi + c % csplit
+  int bsplit = 1 << 30;
+  long bhi = 0;
+  int csplit = 1 << 30;
+  long chi = 0;
 };
 
 template <bool MULTI>
@@ -89,7 +95,8 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
       const int ra = M0 + row < p.M ? M0 + row : p.M - 1;
       const int rb = N0 + row < p.N ? N0 + row : p.N - 1;
       srca[h] = (const char*)(p.A + bat * p.sA + (long)ra * p.lda) + 16 * seg;
-      srcb[h] = (const char*)(p.B + bat * p.sB + (long)rb * p.ldb) + 16 * seg;
+      srcb[h] = (const char*)(p.B + bat * p.sB + (long)(rb / p.bsplit) * p.bhi +
+                              (long)(rb % p.bsplit) * p.ldb) + 16 * seg;
     }
   };
   set_src(wid);
@@ -155,11 +162,13 @@ __global__ __launch_bounds__(256) void dense_lds_f32_kernel(const DenseLdsArgs p
       const int row = Rw + 16 * i + li;
       const int grp = row / p.rgroup, rin = row - grp * p.rgroup;
       if (row >= p.M || rin >= p.rvalid) continue;
-      const long base = bat * p.sC + (long)grp * p.c_gstride + (long)rin * p.ldc;
+      const long base0 = bat * p.sC + (long)grp * p.c_gstride + (long)rin * p.ldc;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int col = Cw + 16 * j + 4 * g;
         if (col >= p.N) continue;
+        // four consecutive columns stay in one split group (csplit % 4 == 0)
+        const long base = base0 + (long)(col / p.csplit) * p.chi - col + col % p.csplit;
         const f32x4 x = acc[i][j];
         if (p.vec && col + 3 < p.N) {
           if (p.Chi) {
@@ -289,6 +298,12 @@ struct DenseLdsSplitArgs {
   float* C;
   int tiles_m, tiles_n;
   int vec;  // 16-byte stores allowed (set by the launcher)
+  double* C64 = nullptr;  // float64 output instead of C (same offsets)
+  // split addressing as for the float32 kernel
+  int bsplit = 1 << 30;
+  long bhi = 0;
+  int csplit = 1 << 30;
+  long chi = 0;
 };
 
 // PB = 4: four wavefronts of 64 x 64 of C; PB = 2: eight of 64 rows x 32
@@ -318,7 +333,8 @@ __global__ __launch_bounds__(1024 / PB) void dense_lds_bf16x3_kernel(const Dense
     const int seg = (lane & 3) ^ ((row >> 1) & 3);
     const long ra = M0 + row < p.M ? M0 + row : p.M - 1;
     const long rb = N0 + row < p.N ? N0 + row : p.N - 1;
-    const long oa = bat * p.sA + ra * p.lda, ob = bat * p.sB + rb * p.ldb;
+    const long oa = bat * p.sA + ra * p.lda,
+               ob = bat * p.sB + (rb / p.bsplit) * p.bhi + (rb % p.bsplit) * p.ldb;
     srca[0][h] = (const char*)(p.Ah + oa) + 16 * seg;
     srca[1][h] = (const char*)(p.Al + oa) + 16 * seg;
     srcb[0][h] = (const char*)(p.Bh + ob) + 16 * seg;
@@ -397,17 +413,31 @@ __global__ __launch_bounds__(1024 / PB) void dense_lds_bf16x3_kernel(const Dense
   for (int j = 0; j < 4; ++j) {
     const int row = Rw + 16 * j + li;
     if (row >= p.M) continue;
-    float* crow = p.C + bat * p.sC + (long)row * p.ldc;
+    const long rbase = bat * p.sC + (long)row * p.ldc;
 #pragma unroll
     for (int i = 0; i < PB; ++i) {
       const int col = Cw + 16 * i + 4 * g;
       if (col >= p.N) continue;
-      if (p.vec && col + 3 < p.N) {
-        *(f32x4*)(crow + col) = acc[i][j];
+      // four consecutive columns stay in one split group (csplit % 4 == 0)
+      const long o = rbase + (long)(col / p.csplit) * p.chi + col % p.csplit;
+      if (p.C64) {
+        if (p.vec && col + 3 < p.N) {
+          f64x2 lo, hi;
+          lo[0] = acc[i][j][0]; lo[1] = acc[i][j][1];
+          hi[0] = acc[i][j][2]; hi[1] = acc[i][j][3];
+          *(f64x2*)(p.C64 + o) = lo;
+          *(f64x2*)(p.C64 + o + 2) = hi;
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (col + r < p.N) p.C64[o + r] = acc[i][j][r];
+        }
+      } else if (p.vec && col + 3 < p.N) {
+        *(f32x4*)(p.C + o) = acc[i][j];
       } else {
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          if (col + r < p.N) crow[col + r] = acc[i][j][r];
+          if (col + r < p.N) p.C[o + r] = acc[i][j][r];
       }
     }
   }
@@ -416,11 +446,15 @@ __global__ __launch_bounds__(1024 / PB) void dense_lds_bf16x3_kernel(const Dense
 template <int PB = 4>
 inline hipError_t launch_dense_lds_bf16x3(DenseLdsSplitArgs a, int batch, hipStream_t s) {
   if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;
-  if (batch > 65535 || a.K % 32 != 0 || a.K <= 0 || !a.Ah || !a.Al || !a.Bh || !a.Bl || !a.C)
+  if (batch > 65535 || a.K % 32 != 0 || a.K <= 0 || !a.Ah || !a.Al || !a.Bh || !a.Bl ||
+      (!a.C && !a.C64) || a.bsplit <= 0 || a.csplit <= 0 ||
+      (a.csplit < (1 << 30) && a.csplit % 4))
     return hipErrorInvalidValue;
   // 16-byte panel rows: row strides and batch strides multiples of 8 bf16
-  if (a.lda % 8 || a.ldb % 8 || a.sA % 8 || a.sB % 8) return hipErrorInvalidValue;
-  a.vec = (a.ldc % 4 == 0 && a.sC % 4 == 0 && (uintptr_t)a.C % 16 == 0) ? 1 : 0;
+  if (a.lda % 8 || a.ldb % 8 || a.sA % 8 || a.sB % 8 || a.bhi % 8) return hipErrorInvalidValue;
+  const bool split_ok = a.csplit >= (1 << 30) || (a.csplit % 4 == 0 && a.chi % 4 == 0);
+  const uintptr_t out = a.C64 ? (uintptr_t)a.C64 : (uintptr_t)a.C;
+  a.vec = (a.ldc % 4 == 0 && a.sC % 4 == 0 && out % 16 == 0 && split_ok) ? 1 : 0;
   a.tiles_m = (a.M + kLdsTile - 1) / kLdsTile;
   a.tiles_n = (a.N + kLdsTile - 1) / kLdsTile;
   const long nb = (long)a.tiles_m * a.tiles_n;
@@ -435,7 +469,8 @@ inline hipError_t launch_dense_lds_f32(DenseLdsArgs a, int batch, hipStream_t s,
   if (a.M <= 0 || a.N <= 0 || batch <= 0) return hipSuccess;
   if (batch > 65535) return hipErrorInvalidValue;
   if (a.K % 16 != 0 || a.K <= 0 || a.rgroup <= 0 || (a.Chi && !a.Clo) ||
-      (!a.Chi && !a.C && !a.C64) || (a.accumulate && !a.C64))
+      (!a.Chi && !a.C && !a.C64) || (a.accumulate && !a.C64) || a.bsplit <= 0 ||
+      a.csplit <= 0 || (a.csplit < (1 << 30) && a.csplit % 4) || a.bhi % 4)
     return hipErrorInvalidValue;
   // vector stores of four consecutive columns: every row start a multiple of
   // four elements and the output 16-byte aligned
@@ -443,12 +478,14 @@ inline hipError_t launch_dense_lds_f32(DenseLdsArgs a, int batch, hipStream_t s,
     const uintptr_t out = a.Chi ? (uintptr_t)a.Chi | (uintptr_t)a.Clo
                                 : a.C64 ? (uintptr_t)a.C64 : (uintptr_t)a.C;
     const long esz = a.Chi ? 2 : a.C64 ? 8 : 4;
-    a.vec = (a.ldc % 4 == 0 && a.c_gstride % 4 == 0 && a.sC % 4 == 0 && out % (4 * esz < 16 ? 4 * esz : 16) == 0) ? 1 : 0;
+    const bool split_ok = a.csplit >= (1 << 30) || (a.csplit % 4 == 0 && a.chi % 4 == 0);
+    a.vec = (a.ldc % 4 == 0 && a.c_gstride % 4 == 0 && a.sC % 4 == 0 && split_ok &&
+             out % (4 * esz < 16 ? 4 * esz : 16) == 0) ? 1 : 0;
     // split planes: paired 16-byte stores of eight columns when every row
     // start is a multiple of eight, N too (partner lanes are then both in
     // or both out of range) and both planes 16-byte aligned
     if (a.Chi && a.vec && a.ldc % 8 == 0 && a.c_gstride % 8 == 0 && a.sC % 8 == 0 &&
-        a.N % 8 == 0 && out % 16 == 0)
+        a.N % 8 == 0 && out % 16 == 0 && a.csplit >= (1 << 30))
       a.vec = 2;
   }
   a.tiles_m = (a.M + kLdsTile - 1) / kLdsTile;

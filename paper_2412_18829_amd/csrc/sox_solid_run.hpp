@@ -430,8 +430,21 @@ sox_status solid_energy(sox_plan& p, const double* Sigma, const double* G, doubl
 struct SolidDynLayout {
   size_t ut2, xtd, gtd, xtt, gwpd, grqtd, gwpt, wm, gg, ggw, aw, atau, bbuf, cbuf, dtau, ebuf;
   size_t gtm, gct, abare;  // bare line-1 term (ta > 0 only)
+  size_t wblk, gblk;       // real block form of W(Omega) GG(Omega) (float plans, even n)
   size_t total;
 };
+
+// W(Omega) GG(Omega) as one real LDS-staged product per momentum transfer
+// (float32 and bf16 x 3 plans): A rows [Re W | -Im W], B rows [Re GG | Im GG]
+// and [Im GG | -Re GG] read from [Re | Im | -Re] rows, K = 2 Nq, interleaved
+// complex float64 output (the column split 2n needs n even).
+bool solid_wgg_block(const sox_plan& p) { return p.precision != SOX_FP64 && p.n % 2 == 0; }
+int solid_nq(const sox_plan& p) { return (int)round_up(p.N, 16); }
+// the forward transform with GG formed in registers, written in that block
+// form (ft_solid_kernel): the transform matrix must fit its LDS
+bool solid_ft_fused(const sox_plan& p) {
+  return solid_wgg_block(p) && 2 * p.n_omega <= kFtsRows && p.n_tau <= kFtsLd - 1;
+}
 
 // ta > 0: the layout of the pass that also carries the bare line-1 term in
 // tau slabs of ta nodes.
@@ -448,8 +461,9 @@ SolidDynLayout solid_dyn_layout_for(const sox_plan& p, int ps, int ts, int ta = 
   L.grqtd = c.take(nt * nk * n * N * 16);
   L.gwpt = c.take(nt * nk * N * n * es);
   L.wm = c.take(nk * 2 * nw * N * N * es);
-  L.gg = c.take(nt * (size_t)ps * n * N * 16);
-  L.ggw = c.take(2 * nw * (size_t)ps * n * N * es);
+  const bool fused_ft = solid_ft_fused(p);
+  L.gg = fused_ft ? c.off : c.take(nt * (size_t)ps * n * N * 16);
+  L.ggw = fused_ft ? c.off : c.take(2 * nw * (size_t)ps * n * N * es);
   L.aw = c.take(2 * nw * (size_t)ps * N * n * 16);
   L.atau = c.take(nt * np2 * N * n * es);
   L.bbuf = c.take((size_t)ts * np2 * N * N * es);
@@ -461,6 +475,12 @@ SolidDynLayout solid_dyn_layout_for(const sox_plan& p, int ps, int ts, int ta = 
     L.gct = c.take(nk * nt * n * n * es);
     L.abare = c.take((size_t)ta * np2 * N * n * es);
   }
+  if (solid_wgg_block(p)) {
+    // float, or bf16 hi and lo planes: 4 bytes per real value either way
+    const size_t nq = solid_nq(p);
+    L.wblk = c.take(nk * 2 * nw * N * 2 * nq * 4);
+    L.gblk = c.take(2 * nw * (size_t)ps * n * 3 * nq * 4);
+  }
   L.total = c.off;
   return L;
 }
@@ -470,16 +490,18 @@ SolidDynLayout solid_dyn_layout_for(const sox_plan& p, int ps, int ts, int ta = 
 // then the tau slab.
 void pick_solid_dyn(sox_plan& p) {
   const size_t budget = ws_budget();
+  // the bare term's tau slab first: it is the row count of that term's
+  // product, at most 64 nodes (one row tile), evened out over the slabs
+  // (3x3x3 mesh: 25 rows instead of 50 took its two products 2.1 -> 2.8 s)
+  const int slabs = (p.n_tau + 63) / 64;
+  int ta = (p.n_tau + slabs - 1) / slabs;
   int nq = p.nk, ts = std::min(p.n_tau, 8);
-  while (nq > 1 && solid_dyn_layout_for(p, nq * p.nk, ts).total > budget) nq = (nq + 1) / 2;
-  while (ts > 1 && solid_dyn_layout_for(p, nq * p.nk, ts).total > budget) ts = (ts + 1) / 2;
+  auto total = [&]() { return solid_dyn_layout_for(p, nq * p.nk, ts, ta).total; };
+  while (nq > 1 && total() > budget) nq = (nq + 1) / 2;
+  while (ts > 1 && total() > budget) ts = (ts + 1) / 2;
+  while (ta > 1 && total() > budget) ta = (ta + 1) / 2;
   p.dyn_ps = nq * p.nk;
   p.dyn_ts = ts;
-  // the bare term's tau slabs: at most 64 nodes (one row tile of its
-  // product), evened out over the slabs, halved while over the budget
-  int slabs = (p.n_tau + 63) / 64;
-  int ta = (p.n_tau + slabs - 1) / slabs;
-  while (ta > 1 && solid_dyn_layout_for(p, p.dyn_ps, ts, ta).total > budget) ta = (ta + 1) / 2;
   p.dyn_ta = ta;
 }
 
@@ -516,6 +538,9 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
   T* cbuf = (T*)(base + L.cbuf);
   double* dtau = (double*)(base + L.dtau);
   double* ebuf = (double*)(base + L.ebuf);
+  const bool blk = solid_wgg_block(p);
+  const int Nq = solid_nq(p);
+  const bool split = p.precision == SOX_BF16X3;
   T* gtm = ta ? (T*)(base + L.gtm) : nullptr;
   T* gct = ta ? (T*)(base + L.gct) : nullptr;
   T* abare = ta ? (T*)(base + L.abare) : nullptr;
@@ -583,11 +608,40 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
     a.C = wm; a.soC = 2L * nw * NN; a.ldc = NN;
     a.M = 2 * nw; a.N = (int)NN; a.K = nt;
     if ((st = cg_launch(a, nk, 4, s))) return st;
+    if (blk) {
+      // [Re W | -Im W] rows of every (q, +-Omega), float or bf16 hi / lo planes
+      const long nb = (long)nk * 2 * nw;
+      const long tot = nb * N * 2L * Nq;
+      float* f = split ? nullptr : (float*)(base + L.wblk);
+      bf16_t* hi = split ? (bf16_t*)(base + L.wblk) : nullptr;
+      hipLaunchKernelGGL(wblock_kernel, grid1d(tot), dim3(256), 0, s, (const float*)wm, nb, N, Nq,
+                         f, hi, hi ? hi + tot : nullptr);
+      SOX_HIP(hipGetLastError());
+    }
   }
   for (int v = 0; v < n; ++v) {
     for (int p0 = 0; p0 < np2; p0 += ps) {
       const int cp = std::min(ps, np2 - p0);
-      {
+      const bool fft = solid_ft_fused(p);
+      if (fft) {
+        // GG formed in registers, transformed, stored in the W GG block form
+        ProfScope ps_(p, SOX_STAGE_GG_FT, s);
+        FtSolidArgs f{};
+        f.tfc = p.d_tfc; f.gwp = gwpd; f.grqt = grqtd; f.k_of = kOf; f.kmq_of = kmqOf;
+        const long gplane = 2L * nw * ps * n * 3L * Nq;
+        if (split) {
+          f.hi = (bf16_t*)(base + L.gblk);
+          f.lo = f.hi + gplane;
+        } else {
+          f.f = (float*)(base + L.gblk);
+        }
+        f.rstride = (long)cp * n * 3 * Nq;
+        f.M = 2 * nw; f.nt = nt; f.nk = nk; f.n = n; f.N = N; f.Nq = Nq;
+        f.p0 = p0; f.cp = cp; f.v = v;
+        const long nblocks = (long)cp * n * (Nq / 16);
+        hipLaunchKernelGGL(ft_solid_kernel, dim3((unsigned)p.n_cu), dim3(512), 0, s, f, nblocks);
+        SOX_HIP(hipGetLastError());
+      } else {
         ProfScope ps_(p, SOX_STAGE_GG_FT, s);
         const long tot = (long)nt * cp * nN;
         hipLaunchKernelGGL(gg_solid_kernel, grid1d(tot), dim3(256), 0, s,
@@ -601,7 +655,53 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
         // 80 x 16 tiles (C5: 2.40 s -> 2.32 s against 80 x 32)
         if ((st = cg_launch(a, 1, 2, s))) return st;
       }
-      {
+      if (blk) {
+        // the same product in real block form on the LDS-staged GEMM: per
+        // transfer q1, batched over +-Omega; columns j = 2 (l u) + re/im
+        ProfScope ps_(p, SOX_STAGE_WGEMM, s);
+        float* gf = split ? nullptr : (float*)(base + L.gblk);
+        bf16_t* gh = split ? (bf16_t*)(base + L.gblk) : nullptr;
+        const long gplane = 2L * nw * ps * n * 3L * Nq;  // lo plane offset (allocated extent)
+        if (!fft) {
+          const long gtot = 2L * nw * cp * n * 3L * Nq;
+          hipLaunchKernelGGL(gblock_kernel, grid1d(gtot), dim3(256), 0, s, (const float*)ggw,
+                             (long)2 * nw, (long)ps * nN, (long)cp * n, N, Nq, gf, gh,
+                             gh ? gh + gplane : nullptr);
+          SOX_HIP(hipGetLastError());
+        }
+        // gblock writes [r][cp n][3 Nq]: r stride cp n 3 Nq
+        const long rstride = (long)cp * n * 3 * Nq;
+        const long wb = (long)N * 2 * Nq;
+        for (int t = 0; t < cp / nk; ++t) {
+          const int q1 = p0 / nk + t;
+          double* C64 = aw + 2 * (long)t * nk * nN;
+          if (split) {
+            const bf16_t* wh = (const bf16_t*)(base + L.wblk);
+            const bf16_t* wl = wh + (long)nk * 2 * nw * wb;
+            DenseLdsSplitArgs l{};
+            l.Ah = wh + (long)q1 * 2 * nw * wb; l.Al = wl + (long)q1 * 2 * nw * wb;
+            l.Bh = gh + (long)t * nk * n * 3 * Nq; l.Bl = gh + gplane + (long)t * nk * n * 3 * Nq;
+            l.C64 = C64;
+            l.lda = 2L * Nq; l.ldb = Nq; l.bsplit = 2; l.bhi = 3L * Nq;
+            l.ldc = 2L * n; l.csplit = 2 * n; l.chi = 2 * nN;
+            l.sA = wb; l.sB = rstride; l.sC = 2L * ps * nN;
+            l.M = N; l.N = 2 * nk * n; l.K = 2 * Nq;
+            SOX_HIP(launch_dense_lds_bf16x3<2>(l, 2 * nw, s));
+          } else {
+            const float* wf = (const float*)(base + L.wblk);
+            DenseLdsArgs l{};
+            l.A = wf + (long)q1 * 2 * nw * wb;
+            l.B = gf + (long)t * nk * n * 3 * Nq;
+            l.C64 = C64;
+            l.lda = 2L * Nq; l.ldb = Nq; l.bsplit = 2; l.bhi = 3L * Nq;
+            l.ldc = 2L * n; l.csplit = 2 * n; l.chi = 2 * nN;
+            l.c_gstride = 0; l.rgroup = N; l.rvalid = N;
+            l.sA = wb; l.sB = rstride; l.sC = 2L * ps * nN;
+            l.M = N; l.N = 2 * nk * n; l.K = 2 * Nq;
+            SOX_HIP(launch_dense_lds_f32(l, 2 * nw, s));
+          }
+        }
+      } else {
         // A(+-Omega)[l][P][u] = sum_Q W^{q1}(+-Omega)[P][Q] GG(+-Omega)[l][u][Q]: one
         // product per (+-Omega, q1) over the columns (k_v, u) of that transfer's n_k pairs
         ProfScope ps_(p, SOX_STAGE_WGEMM, s);

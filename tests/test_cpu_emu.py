@@ -51,6 +51,7 @@ CASES = [
     (13, 70, 5, 1, 2, 1, None),
     (16, 256, 3, 1, 2, 1, None),
     (21, 90, 6, 1, 2, 1, "4"),
+    (330, 20, 2, 1, 1, 1, None),   # adjoint past 320 orbitals: two y chunks of the hc kernel
     (13, 70, 5, 2, 1, 0, None),
     (6, 20, 8, 2, 0, 0, None),
     (16, 256, 3, 2, 0, 0, None),
@@ -75,6 +76,9 @@ SOLID_CASES = [
     (5, 80, 3, 1, 2, (2, 2, 1), "1"),     # dynamic entry, pair and tau slabs
     (5, 160, 1, 2, 0, (3, 1, 1), None),   # bf16 x 3 split B / C products
     (3, 10, 4, 2, 2, (3, 1, 1), None),    # bf16 x 3, dynamic entry
+    (4, 20, 4, 1, 2, (3, 1, 1), None),    # dynamic, even n: W(Omega) GG(Omega) in real block form
+    (6, 33, 3, 2, 2, (2, 2, 1), "1"),     # the same in bf16 x 3, pair and tau slabs
+    (4, 17, 3, 1, 2, (1, 3, 1), "1"),     # ragged N, several slabs
 ]
 
 

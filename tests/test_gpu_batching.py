@@ -53,6 +53,39 @@ def test_static_graph_replays_match_eager(B, precision):
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_solid_vertex_graph_replays_match_eager(B, precision):
+    """The benchmarked solid step (SOSEX_dyn in one pass, even n: the block
+    form of W(Omega) GG(Omega) and the register-GG forward transform) as
+    graph replays, one by one against eager runs, with new G values and
+    unrelated eager work between the replays."""
+    import torch
+    from oracle import sox_solid as osd
+    wl = synth.add_dynamic_screening_solid(synth.solid((3, 1, 1), 6, 40, 12, 10.0, seed=43),
+                                           n_poles=2)
+    tp = synth.bosonic_transform_pair(wl["tau"], wl["beta"], omega_max=10.0, tol=1e-10)
+    mk = lambda: B.Plan(wl["n"], wl["N"], wl["tau"], wl["weights"], wl["beta"],
+                        precision=precision, kmesh=wl["mesh"], t_fwd=tp["T_fwd"],
+                        t_bwd=tp["T_bwd"])
+    pg, pe = mk(), mk()
+    B.sox_plan_set_graph(pg, True)
+    c = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.complex128, device="cuda")
+    X, W, V = c(wl["X"]), c(wl["W_tau"]), c(wl["V"])
+    G0 = osd.g_tau_k(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    G = c(G0)
+    Sg, Se = torch.empty_like(G), torch.empty_like(G)
+    wsg, wse = pg.workspace("vertex"), pe.workspace("vertex")
+    for rep in range(3):
+        G.copy_(c(G0 * (1.0 + 0.02 * rep)))
+        junk = torch.randn(1 << 20, device="cuda") * 2.0
+        B.sox_sigma_vertex(pg, "sosex_dyn", X, V, W, G, Sg, ws=wsg)
+        B.sox_sigma_vertex(pe, "sosex_dyn", X, V, W, G, Se, ws=wse)
+        torch.cuda.synchronize()
+        assert torch.equal(Sg, Se), f"replay {rep}"
+        del junk
+    assert B.sox_plan_describe(pg)["graph"] == 1
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
 def test_dynamic_graph_replays_match_eager(B, precision):
     import torch
     wl = synth.small_molecule(13, 70, 24, 30.0, seed=42, dynamic=True)

@@ -139,20 +139,27 @@ def test_dynamic_full_size_on_column_subset(B, precision):
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
 def test_real_w_product_and_asymmetric_w(B, precision):
-    """A W_d(tau) mirror symmetric in tau (the physical case) runs the real
-    W(Omega) product in the float32 and bf16x3 plans (the plan reports
-    dynamic_real_w = 1); a W(tau) with an added part odd about beta/2 keeps
-    the complex block product (dynamic_real_w = 0), as do float64 plans.  Both
-    against the oracle, which transforms W(tau) as it is."""
-    n, N, nt, beta = 21, 90, 20, 40.0
-    wl = synth.small_molecule(n, N, nt, beta, seed=79, dynamic=True)
-    tp = _pair(wl)
-    rng = np.random.default_rng(5)
-    G = om.g_tau(wl["eps"], wl["Q"], 0.0, beta, wl["tau"]) + 0.05 * rng.standard_normal((nt, n, n))
-    odd = (wl["tau"] - beta / 2) / beta
-    W_asym = wl["W_tau"] + 0.5 * odd[:, None, None] * wl["W_tau"][nt // 2][None]
-    for W, want in ((wl["W_tau"], precision != "fp64"), (W_asym, False)):
-        log(f"dynamic real-W check {precision}, mirror symmetric: {W is wl['W_tau']}")
+    """The float32 and bf16x3 plans run the real W(Omega) product when the
+    plan's transform of W_d(tau) has an imaginary part below float32
+    resolution of its real part: a W(tau) mirror symmetric in tau on the
+    120-node, beta = 100 grid (dynamic_real_w = 1).  On a coarse 20-node grid
+    the same kind of W keeps an imaginary part, and a W with an added part odd
+    about beta/2 always does: those keep the complex block product, as do
+    float64 plans.  Every case against the oracle, which transforms W(tau) as
+    it is."""
+    cases = []
+    for nt, beta in ((120, 100.0), (20, 40.0)):
+        wl = synth.small_molecule(21, 90, nt, beta, seed=79, dynamic=True)
+        odd = (wl["tau"] - beta / 2) / beta
+        W_asym = wl["W_tau"] + 0.5 * odd[:, None, None] * wl["W_tau"][nt // 2][None]
+        fine = nt == 120
+        cases += [(wl, wl["W_tau"], fine and precision != "fp64"), (wl, W_asym, False)]
+    for wl, W, want in cases:
+        n, nt, beta = wl["n"], wl["n_tau"], wl["beta"]
+        tp = _pair(wl)
+        rng = np.random.default_rng(5)
+        G = om.g_tau(wl["eps"], wl["Q"], 0.0, beta, wl["tau"]) + 0.05 * rng.standard_normal((nt, n, n))
+        log(f"dynamic real-W check {precision}, n_tau={nt}, mirror symmetric: {W is wl['W_tau']}")
         got, plan = _run(B, wl, tp, precision, wl["X"], W, wl["V"], G)
         assert B.sox_plan_describe(plan)["dynamic_real_w"] == (1 if want else 0)
         ref = om.sigma_dynamic_thc(wl["X"], W, wl["V"], G, G[::-1], tp["T_fwd"], tp["T_bwd"])

@@ -61,6 +61,29 @@ def test_static_vjp_vs_reference(B, precision, entry, shape):
         assert v <= TOL[precision], k
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_static_vjp_past_320_orbitals(B, precision):
+    """n = 336 > 320: the adjoint's Hadamard-contract kernel runs its output
+    columns in two chunks (each recomputing its weighted tile); against the
+    reference VJP."""
+    import torch
+    from paper_2412_18829_amd import autograd as AG
+    n, N, nt = 336, 48, 4
+    log(f"vjp static n={n} {precision}")
+    wl, G, R = _inputs(n, N, nt, 6.0, 336)
+    plan = B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision=precision)
+    Xd, U1d, U2d, Gd = (dev(a).requires_grad_() for a in (wl["X"], wl["W0"], wl["V"], G))
+    S = AG.sox_sigma(plan, Xd, U1d, Gd, U2d)
+    S.backward(dev(R))
+    torch.cuda.synchronize()
+    dG, dX, d1, d2 = ov.vjp_static(wl["X"], wl["W0"], wl["V"], G, R)
+    errs = {"dG": rel_err(host(Gd.grad), dG), "dX": rel_err(host(Xd.grad), dX),
+            "dU1": rel_err(host(U1d.grad), d1), "dU2": rel_err(host(U2d.grad), d2)}
+    log("  " + " ".join(f"{k} {v:.2e}" for k, v in errs.items()))
+    for k, v in errs.items():
+        assert v <= TOL[precision], k
+
+
 def test_vjp_slabs_match_single_slab(B, monkeypatch):
     import torch
     n, N, nt = 10, 64, 7
