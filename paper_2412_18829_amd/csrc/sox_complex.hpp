@@ -969,97 +969,276 @@ __global__ void gblock_kernel(const float* ggw, long nr, long ldr, long ncols, i
 
 // The solid eq:GG chain's forward transform with GG formed in registers,
 // written straight in the block form above:
-//   GG(r)[l][u][Q] = sum_j Tc[r][j] G^{k_v - q1}_uQ(tau_j) G^{k_v}_Qv(beta - tau_j)
-// for the pairs l = p0 .. p0 + cp - 1 of a slab and one orbital v, with Tc
-// = [T_fwd; conj T_fwd] (M = 2 n_omega rows).  Tc stays in LDS for the whole
-// launch (one workgroup per CU); each wavefront owns 16 consecutive Q of one
-// (l, u) at a time and computes all M rows on float64 MFMAs (four real
-// products per complex one); rows [Re | Im | -Re] of 3 Nq per (r, l, u)
-// column, zero for Q >= N.
-constexpr int kFtsRows = 80, kFtsLd = 113;  // M <= 80 rows, n_tau <= 112 nodes
+//   GG(+-Omega_m)[l][u][Q] = sum_j T(+-)[m][j] G^{k_v - q1}_uQ(tau_j) G^{k_v}_Qv(beta - tau_j)
+// for the pairs l of a slab and one orbital v, with T(+) = T_fwd = a + i b
+// and T(-) = conj T_fwd.  For x = GG(tau) = xr + i xi both signs come from
+// the same four real products P1 = a xr, P2 = b xi, P3 = a xi, P4 = b xr:
+//   GG(+) = (P1 - P2) + i (P3 + P4),   GG(-) = (P1 + P2) + i (P3 - P4),
+// half the multiplies of one complex product per sign.  GG is formed from
+// float32 copies of the two projections and transformed on float32 MFMAs
+// (float plans only: the block form it feeds holds float32 or bf16 hi and lo
+// planes).  NRB row tiles of 16 frequencies.  T_fwd stays in LDS for
+// the launch.  A wavefront owns 16 consecutive Q of one (k_q = k_v - q1, u)
+// and one momentum transfer at a time, the transfers of the slab being the
+// fastest index: the G^{k_q}_uQ columns it reads are read by its neighbours
+// at the same time (once per slab from HBM instead of once per pair).  Rows
+// r < n_omega of the output are +Omega_r, rows n_omega + m are -Omega_m;
+// [Re | Im | -Re] of 3 Nq per (r, l, u) column, zero for Q >= N.
+constexpr int kFtsRows = 64, kFtsLd = 113;  // n_omega <= 64, n_tau <= 112 nodes
+constexpr int kFtsChunk = 4;                // k steps (of four nodes) per load chunk
 struct FtSolidArgs {
-  const double* tfc;   // [M][nt] complex
-  const double* gwp;   // [nt][nk][n][N] complex, G_uQ(tau)
-  const double* grqt;  // [nt][nk][n][N] complex, G_vQ(tau), read at beta - tau
-  const int* k_of;     // per pair: k_v
-  const int* kmq_of;   // per pair: k_v - q1
+  const double* tfc;   // [2 n_omega][nt] complex; rows < n_omega hold T_fwd
+  const float* gwp;    // [nt][nk][n][N] complex, G_uQ(tau)
+  const float* grqt;   // [nt][nk][n][N] complex, G_vQ(tau), read at beta - tau
+  const int* kdiff;    // [nk][nk]: index of k_a - k_b (index 0 is k = 0)
   float* f;            // float output, or
   bf16_t* hi;          // bf16 hi and lo planes
   bf16_t* lo;
   long rstride;        // output elements between rows r: cp n 3 Nq
-  int M, nt, nk, n, N, Nq, p0, cp, v;
+  int nw, nt, nk, n, N, Nq, p0, cp, v;
 };
 
-__global__ __launch_bounds__(512) void ft_solid_kernel(const FtSolidArgs a, long nblocks) {
-  __shared__ double tr[kFtsRows * kFtsLd], ti[kFtsRows * kFtsLd];
+// 16 NRB rows of T_fwd in LDS (43 KB for three row tiles): three workgroups
+// of four wavefronts per CU, at most 168 VGPRs
+template <int NRB>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+void ft_solid_kernel(const FtSolidArgs a, long nblocks) {
+  __shared__ float tr[16 * NRB * kFtsLd], ti[16 * NRB * kFtsLd];
   const int K = a.nt, Kp = (K + 3) & ~3;
-  for (int e = threadIdx.x; e < kFtsRows * Kp; e += blockDim.x) {
+  for (int e = threadIdx.x; e < 16 * NRB * Kp; e += blockDim.x) {
     const int r = e / Kp, k = e - (e / Kp) * Kp;
-    const bool ok = r < a.M && k < K;
-    tr[r * kFtsLd + k] = ok ? a.tfc[2 * ((long)r * K + k)] : 0.0;
-    ti[r * kFtsLd + k] = ok ? a.tfc[2 * ((long)r * K + k) + 1] : 0.0;
+    const bool ok = r < a.nw && k < K;
+    tr[r * kFtsLd + k] = ok ? (float)a.tfc[2 * ((long)r * K + k)] : 0.f;
+    ti[r * kFtsLd + k] = ok ? (float)a.tfc[2 * ((long)r * K + k) + 1] : 0.f;
   }
   __syncthreads();
   const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
-  const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nwaves = blockDim.x >> 6;
   const int nqb = a.Nq / 16;
-  const int nrb = (a.M + 15) / 16;
+  const int ntr = a.cp / a.nk;  // momentum transfers in the slab
   const long per = (long)a.n * a.N;
+  const long tsb = 8L * a.nk * per;  // bytes between nodes
   for (long blk = (long)blockIdx.x * nwaves + wave; blk < nblocks;
        blk += (long)gridDim.x * nwaves) {
-    const int qb = (int)(blk % nqb);
-    const long rest = blk / nqb;
+    const int t = (int)(blk % ntr);
+    long rest = blk / ntr;
+    const int qb = (int)(rest % nqb);
+    rest /= nqb;
     const int u = (int)(rest % a.n);
-    const int l = (int)(rest / a.n);
-    const int pair = a.p0 + l;
-    const int kv = a.k_of[pair], kq = a.kmq_of[pair];
+    const int kq = (int)(rest / a.n);
+    const int q1 = a.p0 / a.nk + t;
+    // k_q + q1 = k_q - (0 - q1), the same for the whole wavefront
+    const int kv = __builtin_amdgcn_readfirstlane(a.kdiff[kq * a.nk + a.kdiff[q1]]);
+    const int l = t * a.nk + kv;                     // pair - p0
     const int Q = 16 * qb + li;
     const bool qok = Q < a.N;
     const int Qc = qok ? Q : a.N - 1;
-    const double* gu = a.gwp + 2 * ((long)kq * per + (long)u * a.N + Qc);
-    const double* gv = a.grqt + 2 * ((long)kv * per + (long)a.v * a.N + Qc);
-    const long tstride = 2L * a.nk * per;
-    f64x4 cr[5], ci[5];
+    // wavefront-uniform bases (scalar registers) plus one 32-bit lane offset
+    // each: node g of a step of four and column Q (G(beta - tau) runs
+    // backwards: node K - 1 - k = (K - 4 - 4 step) + 3 - g)
+    const char* gu0 = (const char*)(a.gwp + 2 * ((long)kq * per + (long)u * a.N + 16 * qb));
+    const char* gv0 = (const char*)(a.grqt + 2 * ((long)kv * per + (long)a.v * a.N + 16 * qb));
+    const unsigned lu = (unsigned)(g * tsb + 8 * (Qc - 16 * qb));
+    const unsigned lv = (unsigned)((3 - g) * tsb + 8 * (Qc - 16 * qb));
+    f32x4 p1[NRB], p2[NRB], p3[NRB], p4[NRB];
 #pragma unroll
-    for (int b = 0; b < 5; ++b) {
-      cr[b] = zero4<double>();
-      ci[b] = zero4<double>();
+    for (int b = 0; b < NRB; ++b) {
+      p1[b] = zero4<float>();
+      p2[b] = zero4<float>();
+      p3[b] = zero4<float>();
+      p4[b] = zero4<float>();
     }
-    for (int k0 = 0; k0 < Kp; k0 += 4) {
-      const int k = k0 + g;
-      double xr = 0.0, xi = 0.0;
-      if (qok && k < K) {
-        const double* pu = gu + (long)k * tstride;
-        const double* pv = gv + (long)(K - 1 - k) * tstride;
-        const double ar = pu[0], ai = pu[1], br = pv[0], bi = pv[1];
-        xr = ar * br - ai * bi;
-        xi = ar * bi + ai * br;
-      }
+    // nodes in chunks of kFtsChunk steps of four; the next chunk's G values
+    // are loaded while the MFMAs of the current one run
+    const int nst = Kp / 4, nch = (nst + kFtsChunk - 1) / kFtsChunk;
+    f32x2 ru[kFtsChunk], rv[kFtsChunk];
+    auto load = [&](int kc) {
+      // (the chunk index through readfirstlane keeps the addresses a scalar
+      // base plus the lane offset instead of one 64-bit register pair per load)
+      kc = __builtin_amdgcn_readfirstlane(kc);
 #pragma unroll
-      for (int b = 0; b < 5; ++b) {
-        if (b >= nrb) break;
-        const int o = (16 * b + li) * kFtsLd + k;
-        const double t_r = tr[o], t_i = ti[o];
-        cr[b] = mfma16x16x4(t_r, xr, cr[b]);
-        cr[b] = mfma16x16x4(-t_i, xi, cr[b]);
-        ci[b] = mfma16x16x4(t_r, xi, ci[b]);
-        ci[b] = mfma16x16x4(t_i, xr, ci[b]);
+      for (int j = 0; j < kFtsChunk; ++j) {
+        const int st = kc * kFtsChunk + j;
+        const bool ok = qok && 4 * st + g < K;
+        ru[j] = ok ? *(const f32x2*)(gu0 + 4L * st * tsb + lu) : f32x2{0.f, 0.f};
+        rv[j] = ok ? *(const f32x2*)(gv0 + (long)(K - 4 - 4 * st) * tsb + lv) : f32x2{0.f, 0.f};
+      }
+    };
+    // the T_fwd values of step st + 1 are read from LDS while the MFMAs of
+    // step st run
+    auto rd = [&](int st, float (&x)[NRB], float (&y)[NRB]) {
+#pragma unroll
+      for (int b = 0; b < NRB; ++b) {
+        const int o = (16 * b + li) * kFtsLd + 4 * st + g;
+        x[b] = tr[o];
+        y[b] = ti[o];
+      }
+    };
+    float ta[NRB], tb[NRB];
+    rd(0, ta, tb);
+    load(0);
+    for (int kc = 0; kc < nch; ++kc) {
+      float xr[kFtsChunk], xi[kFtsChunk];
+#pragma unroll
+      for (int j = 0; j < kFtsChunk; ++j) {
+        xr[j] = ru[j].x * rv[j].x - ru[j].y * rv[j].y;
+        xi[j] = ru[j].x * rv[j].y + ru[j].y * rv[j].x;
+      }
+      if (kc + 1 < nch) load(kc + 1);
+#pragma unroll
+      for (int j = 0; j < kFtsChunk; ++j) {
+        const int st = kc * kFtsChunk + j;
+        if (st >= nst) break;
+        float na[NRB], nb[NRB];
+#pragma unroll
+        for (int b = 0; b < NRB; ++b) na[b] = nb[b] = 0.f;
+        if (st + 1 < nst) rd(st + 1, na, nb);
+#pragma unroll
+        for (int b = 0; b < NRB; ++b) {
+          p1[b] = mfma16x16x4(ta[b], xr[j], p1[b]);
+          p2[b] = mfma16x16x4(tb[b], xi[j], p2[b]);
+          p3[b] = mfma16x16x4(ta[b], xi[j], p3[b]);
+          p4[b] = mfma16x16x4(tb[b], xr[j], p4[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < NRB; ++b) {
+          ta[b] = na[b];
+          tb[b] = nb[b];
+        }
+        // one step in flight at a time (short live ranges, no spills)
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
-    // lane (li, g) holds rows 16 b + g + 4 i of column Q
+    // lane (li, g) holds frequencies m = 16 b + 4 g + i of column Q
     const long col = ((long)l * a.n + u) * 3 * a.Nq + Q;
 #pragma unroll
-    for (int b = 0; b < 5; ++b) {
-      if (b >= nrb) break;
+    for (int b = 0; b < NRB; ++b) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int r = 16 * b + acc_row<double>(g, i);
-        if (r >= a.M) continue;
-        const long o = (long)r * a.rstride + col;
-        const float vr = qok ? (float)cr[b][i] : 0.f, vi = qok ? (float)ci[b][i] : 0.f;
-        put_split(vr, o, a.f, a.hi, a.lo);
-        put_split(vi, o + a.Nq, a.f, a.hi, a.lo);
-        put_split(-vr, o + 2 * a.Nq, a.f, a.hi, a.lo);
+        const int m = 16 * b + acc_row<float>(g, i);
+        if (m >= a.nw) continue;
+        const float pr = qok ? p1[b][i] - p2[b][i] : 0.f, pi = qok ? p3[b][i] + p4[b][i] : 0.f;
+        const float mr = qok ? p1[b][i] + p2[b][i] : 0.f, mi = qok ? p3[b][i] - p4[b][i] : 0.f;
+        const long op = (long)m * a.rstride + col, om = (long)(a.nw + m) * a.rstride + col;
+        put_split(pr, op, a.f, a.hi, a.lo);
+        put_split(pi, op + a.Nq, a.f, a.hi, a.lo);
+        put_split(-pr, op + 2 * a.Nq, a.f, a.hi, a.lo);
+        put_split(mr, om, a.f, a.hi, a.lo);
+        put_split(mi, om + a.Nq, a.f, a.hi, a.lo);
+        put_split(-mr, om + 2 * a.Nq, a.f, a.hi, a.lo);
+      }
+    }
+  }
+}
+
+// The matching inverse transform (float plans).  With c = T_bwd / 2 = cr +
+// i ci the coefficient of A(+i Omega_m) and conj c that of A(-i Omega_m),
+// and A(+-i Omega_m) = a+- + i b+-:
+//   Re A(tau) = sum_m cr (a+ + a-) + ci (b- - b+)
+//   Im A(tau) = sum_m cr (b+ + b-) + ci (a+ - a-),
+// one real product over K = 2 n_omega with two output columns per complex
+// column: half the multiplies of the complex product over both signs.
+// Float32 MFMAs; [cr; ci] stays in LDS for the launch; a wavefront owns 16
+// consecutive complex columns and every node (up to eight row tiles of 16)
+// at a time, so each A(+-Omega) value is read once.
+constexpr int kIftRows = 128, kIftW = 40, kIftLd = 144;  // n_tau <= 128, n_omega <= 40
+struct IftSolidArgs {
+  const double* tbc;  // [nt][2 n_omega] complex; columns < n_omega hold T_bwd / 2
+  const float* aw;    // [2 n_omega][fstride] complex: +Omega rows, then -Omega rows
+  float* out;         // [nt][ldo] complex
+  long fstride, ldo, cols;
+  int nt, nw;
+};
+
+// three workgroups per CU (LDS), three wavefronts per SIMD
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+void ift_solid_kernel(const IftSolidArgs a) {
+  __shared__ float cr[kIftW * kIftLd], ci[kIftW * kIftLd];  // [m][tau]
+  for (int e = threadIdx.x; e < kIftW * kIftRows; e += blockDim.x) {
+    const int m = e / kIftRows, t = e - m * kIftRows;
+    const bool ok = m < a.nw && t < a.nt;
+    const double* c = a.tbc + 2 * ((long)t * 2 * a.nw + m);
+    cr[m * kIftLd + t] = ok ? (float)c[0] : 0.f;
+    ci[m * kIftLd + t] = ok ? (float)c[1] : 0.f;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nwaves = blockDim.x >> 6;
+  const int ns = (a.nw + 3) / 4;    // k steps of four frequencies
+  const int nrt = (a.nt + 15) / 16;  // row tiles of nodes
+  const long ntiles = (a.cols + 15) / 16;
+  constexpr int kS = kIftW / 4;
+  const long tstep = (long)gridDim.x * nwaves;
+  // lane (li, g) holds frequency m = 4 s + g of its column; the next tile's
+  // values are loaded while the MFMAs of the current one run
+  // a tile's values: a wavefront-uniform base per step (scalar registers)
+  // plus one 32-bit lane offset, frequency g of the step and column li
+  const long fsb = 8 * a.fstride;  // bytes between frequencies
+  const unsigned loff = (unsigned)(g * fsb + 8 * li);
+  const long soff = 8 * ((long)(4 * g) * a.ldo + li);  // output: node 4 g, column li
+  f32x2 np[kS], nm[kS];
+  auto load = [&](long tl) {
+    const bool ok = tl < ntiles && tl * 16 + li < a.cols;
+    const char* b0 = (const char*)a.aw + 128 * (tl < ntiles ? tl : 0);  // uniform
+#pragma unroll
+    for (int s = 0; s < kS; ++s) {
+      const bool mk = ok && s < ns && 4 * s + g < a.nw;
+      np[s] = mk ? *(const f32x2*)(b0 + 4L * s * fsb + loff) : f32x2{0.f, 0.f};
+      nm[s] = mk ? *(const f32x2*)(b0 + (a.nw + 4L * s) * fsb + loff) : f32x2{0.f, 0.f};
+    }
+  };
+  long tile = (long)blockIdx.x * nwaves + wave;
+  load(tile);
+  for (; tile < ntiles; tile += tstep) {
+    const long c = tile * 16 + li;
+    const bool cok = c < a.cols;
+    float sa[kS], db[kS], sb[kS], da[kS];
+#pragma unroll
+    for (int s = 0; s < kS; ++s) {
+      sa[s] = np[s].x + nm[s].x;
+      db[s] = nm[s].y - np[s].y;
+      sb[s] = np[s].y + nm[s].y;
+      da[s] = np[s].x - nm[s].x;
+    }
+    load(tile + tstep);
+    // the nodes in two groups of four row tiles (32 accumulator registers)
+#pragma unroll
+    for (int h = 0; h < kIftRows / 64; ++h) {
+      if (4 * h >= nrt) break;
+      f32x4 ar[4], ai[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        ar[i] = zero4<float>();
+        ai[i] = zero4<float>();
+      }
+#pragma unroll
+      for (int s = 0; s < kS; ++s) {
+        if (s >= ns) break;
+        const int m = 4 * s + g;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if (4 * h + i >= nrt) break;
+          const int o = m * kIftLd + 16 * (4 * h + i) + li;
+          const float tR = cr[o], tI = ci[o];
+          ar[i] = mfma16x16x4(tR, sa[s], ar[i]);
+          ar[i] = mfma16x16x4(tI, db[s], ar[i]);
+          ai[i] = mfma16x16x4(tR, sb[s], ai[i]);
+          ai[i] = mfma16x16x4(tI, da[s], ai[i]);
+        }
+        // one step's LDS reads at a time (short live ranges, no spills)
+        __builtin_amdgcn_sched_barrier(0);
+      }
+      if (!cok) continue;
+      // lane (li, g) holds nodes 16 rt + 4 g + r of column c: a uniform base
+      // per (rt, r) plus the lane's offset
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int t = 16 * (4 * h + i) + acc_row<float>(g, r);
+          char* ob = (char*)a.out + 8 * ((long)(16 * (4 * h + i) + r) * a.ldo + 16 * tile);
+          if (t < a.nt) *(f32x2*)(ob + soff) = f32x2{ar[i][r], ai[i][r]};
+        }
       }
     }
   }

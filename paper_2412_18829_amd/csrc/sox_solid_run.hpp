@@ -442,8 +442,30 @@ bool solid_wgg_block(const sox_plan& p) { return p.precision != SOX_FP64 && p.n 
 int solid_nq(const sox_plan& p) { return (int)round_up(p.N, 16); }
 // the forward transform with GG formed in registers, written in that block
 // form (ft_solid_kernel): the transform matrix must fit its LDS
+// The two transform kernels address their loads as a wavefront-uniform base
+// plus a 32-bit lane offset: three frequency rows of a pair slab (inverse)
+// or three nodes of the projections (forward) must stay below 2^32 bytes.
+// Both need one momentum transfer's n_k n N columns within this bound, and
+// the pair slab is capped to it.
+constexpr long kTransformSlabCols = 1L << 26;
 bool solid_ft_fused(const sox_plan& p) {
-  return solid_wgg_block(p) && 2 * p.n_omega <= kFtsRows && p.n_tau <= kFtsLd - 1;
+  return solid_wgg_block(p) && p.n_omega <= kFtsRows && p.n_tau <= kFtsLd - 1 &&
+         (long)p.nk * p.n * p.N <= kTransformSlabCols;
+}
+// the inverse transform in real form on float32 MFMAs (ift_solid_kernel):
+// W(Omega) GG(Omega) then writes its products in float32
+bool solid_ift_real(const sox_plan& p) {
+  return solid_wgg_block(p) && p.n_tau <= kIftRows && p.n_omega <= kIftW &&
+         (long)p.nk * p.n * p.N <= kTransformSlabCols;
+}
+
+// workgroups of a persistent launch: as many as are resident at once
+template <typename K>
+unsigned resident_grid(const sox_plan& p, K kernel, int threads) {
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1)
+    nb = 1;
+  return (unsigned)(nb * p.n_cu);
 }
 
 // ta > 0: the layout of the pass that also carries the bare line-1 term in
@@ -464,7 +486,7 @@ SolidDynLayout solid_dyn_layout_for(const sox_plan& p, int ps, int ts, int ta = 
   const bool fused_ft = solid_ft_fused(p);
   L.gg = fused_ft ? c.off : c.take(nt * (size_t)ps * n * N * 16);
   L.ggw = fused_ft ? c.off : c.take(2 * nw * (size_t)ps * n * N * es);
-  L.aw = c.take(2 * nw * (size_t)ps * N * n * 16);
+  L.aw = c.take(2 * nw * (size_t)ps * N * n * (solid_ift_real(p) ? 8 : 16));
   L.atau = c.take(nt * np2 * N * n * es);
   L.bbuf = c.take((size_t)ts * np2 * N * N * es);
   L.cbuf = c.take((size_t)ts * np2 * N * N * es);
@@ -498,6 +520,7 @@ void pick_solid_dyn(sox_plan& p) {
   int nq = p.nk, ts = std::min(p.n_tau, 8);
   auto total = [&]() { return solid_dyn_layout_for(p, nq * p.nk, ts, ta).total; };
   while (nq > 1 && total() > budget) nq = (nq + 1) / 2;
+  while (nq > 1 && (long)nq * p.nk * p.n * p.N > kTransformSlabCols) nq = (nq + 1) / 2;
   while (ts > 1 && total() > budget) ts = (ts + 1) / 2;
   while (ta > 1 && total() > budget) ta = (ta + 1) / 2;
   p.dyn_ps = nq * p.nk;
@@ -566,22 +589,31 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
     hipLaunchKernelGGL((cast_kernel<T>), grid1d(cx), dim3(256), 0, s, xtd,
                        xtt, cx);
     SOX_HIP(hipGetLastError());
-    // GwP^k(tau)[w][P] = sum_p G^k_wp conj(X^k_pP)        (float64, for GG)
-    CgArgs<double, double> a = cg_args<double, double>();
-    a.A = G; a.soA = (long)nt * n * n; a.siA = (long)n * n; a.ldA = n;
-    a.B = xtd; a.soB = nN; a.ldB = n; a.conjB = 1;
-    a.C = gwpd; a.soC = nN; a.siC = (long)nk * nN; a.ldc = N;
-    a.nzi = nt;
-    a.M = n; a.N = N; a.K = n;
-    if ((st = cg_launch(a, nk * nt, 0, s))) return st;
-    // GRqT^k(tau)[v][Q] = sum_s G^k_sv X^k_sQ                (float64, for GG)
-    a = cg_args<double, double>();
-    a.A = gtd; a.soA = (long)nt * n * n; a.siA = (long)n * n; a.ldA = n;
-    a.B = xtd; a.soB = nN; a.ldB = n;
-    a.C = grqtd; a.soC = nN; a.siC = (long)nk * nN; a.ldc = N;
-    a.nzi = nt;
-    a.M = n; a.N = N; a.K = n;
-    if ((st = cg_launch(a, nk * nt, 0, s))) return st;
+    // GwP^k(tau)[w][P] = sum_p G^k_wp conj(X^k_pP) and GRqT^k(tau)[v][Q] =
+    // sum_s G^k_sv X^k_sQ, the operands of GG: float64 products, stored in
+    // float64, or in float32 for the forward transform that forms GG on
+    // float32 MFMAs
+    auto gg_operands = [&](auto* gw, auto* gr) -> sox_status {
+      using TO = std::remove_pointer_t<decltype(gw)>;
+      CgArgs<double, TO> a = cg_args<double, TO>();
+      a.A = G; a.soA = (long)nt * n * n; a.siA = (long)n * n; a.ldA = n;
+      a.B = xtd; a.soB = nN; a.ldB = n; a.conjB = 1;
+      a.C = gw; a.soC = nN; a.siC = (long)nk * nN; a.ldc = N;
+      a.nzi = nt;
+      a.M = n; a.N = N; a.K = n;
+      sox_status r;
+      if ((r = cg_launch(a, nk * nt, 0, s))) return r;
+      a = cg_args<double, TO>();
+      a.A = gtd; a.soA = (long)nt * n * n; a.siA = (long)n * n; a.ldA = n;
+      a.B = xtd; a.soB = nN; a.ldB = n;
+      a.C = gr; a.soC = nN; a.siC = (long)nk * nN; a.ldc = N;
+      a.nzi = nt;
+      a.M = n; a.N = N; a.K = n;
+      return cg_launch(a, nk * nt, 0, s);
+    };
+    if ((st = solid_ft_fused(p) ? gg_operands((float*)gwpd, (float*)grqtd)
+                                : gg_operands(gwpd, grqtd)))
+      return st;
     // GwPt^k(tau)[P][w] in the plan's precision (the C step)
     CgArgs<double, T> b = cg_args<double, T>();
     b.A = xtd; b.soA = nN; b.ldA = n; b.conjA = 1;
@@ -627,7 +659,8 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
         // GG formed in registers, transformed, stored in the W GG block form
         ProfScope ps_(p, SOX_STAGE_GG_FT, s);
         FtSolidArgs f{};
-        f.tfc = p.d_tfc; f.gwp = gwpd; f.grqt = grqtd; f.k_of = kOf; f.kmq_of = kmqOf;
+        f.tfc = p.d_tfc; f.gwp = (const float*)gwpd; f.grqt = (const float*)grqtd;
+        f.kdiff = p.d_ktab + 3 * np2;
         const long gplane = 2L * nw * ps * n * 3L * Nq;
         if (split) {
           f.hi = (bf16_t*)(base + L.gblk);
@@ -636,10 +669,22 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
           f.f = (float*)(base + L.gblk);
         }
         f.rstride = (long)cp * n * 3 * Nq;
-        f.M = 2 * nw; f.nt = nt; f.nk = nk; f.n = n; f.N = N; f.Nq = Nq;
+        f.nw = nw; f.nt = nt; f.nk = nk; f.n = n; f.N = N; f.Nq = Nq;
         f.p0 = p0; f.cp = cp; f.v = v;
         const long nblocks = (long)cp * n * (Nq / 16);
-        hipLaunchKernelGGL(ft_solid_kernel, dim3((unsigned)p.n_cu), dim3(512), 0, s, f, nblocks);
+        switch ((nw + 15) / 16) {
+#define SOX_FTS(R_)                                                                          \
+  case R_:                                                                                   \
+    hipLaunchKernelGGL(ft_solid_kernel<R_>, dim3(resident_grid(p, &ft_solid_kernel<R_>, 256)), \
+                       dim3(256), 0, s, f, nblocks);                                         \
+    break;
+          SOX_FTS(1)
+          SOX_FTS(2)
+          SOX_FTS(3)
+          SOX_FTS(4)
+#undef SOX_FTS
+          default: return fail(SOX_ERR_SHAPE, "internal: forward transform rows");
+        }
         SOX_HIP(hipGetLastError());
       } else {
         ProfScope ps_(p, SOX_STAGE_GG_FT, s);
@@ -672,16 +717,18 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
         // gblock writes [r][cp n][3 Nq]: r stride cp n 3 Nq
         const long rstride = (long)cp * n * 3 * Nq;
         const long wb = (long)N * 2 * Nq;
+        const bool f32out = solid_ift_real(p);
         for (int t = 0; t < cp / nk; ++t) {
           const int q1 = p0 / nk + t;
-          double* C64 = aw + 2 * (long)t * nk * nN;
+          double* C64 = f32out ? nullptr : aw + 2 * (long)t * nk * nN;
+          float* C32 = f32out ? (float*)aw + 2 * (long)t * nk * nN : nullptr;
           if (split) {
             const bf16_t* wh = (const bf16_t*)(base + L.wblk);
             const bf16_t* wl = wh + (long)nk * 2 * nw * wb;
             DenseLdsSplitArgs l{};
             l.Ah = wh + (long)q1 * 2 * nw * wb; l.Al = wl + (long)q1 * 2 * nw * wb;
             l.Bh = gh + (long)t * nk * n * 3 * Nq; l.Bl = gh + gplane + (long)t * nk * n * 3 * Nq;
-            l.C64 = C64;
+            l.C64 = C64; l.C = C32;
             l.lda = 2L * Nq; l.ldb = Nq; l.bsplit = 2; l.bhi = 3L * Nq;
             l.ldc = 2L * n; l.csplit = 2 * n; l.chi = 2 * nN;
             l.sA = wb; l.sB = rstride; l.sC = 2L * ps * nN;
@@ -692,7 +739,7 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
             DenseLdsArgs l{};
             l.A = wf + (long)q1 * 2 * nw * wb;
             l.B = gf + (long)t * nk * n * 3 * Nq;
-            l.C64 = C64;
+            l.C64 = C64; l.C = C32;
             l.lda = 2L * Nq; l.ldb = Nq; l.bsplit = 2; l.bhi = 3L * Nq;
             l.ldc = 2L * n; l.csplit = 2 * n; l.chi = 2 * nN;
             l.c_gstride = 0; l.rgroup = N; l.rvalid = N;
@@ -715,7 +762,17 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
         // 64 x 64 tiles of four wavefronts (C5: 3.82 s -> 3.44 s against 80 x 64)
         if ((st = cg_launch(a, (cp / nk) * 2 * nw, 0, s))) return st;
       }
-      {
+      if (solid_ift_real(p)) {
+        // A(tau)[pair][P][u] from the float32 A(+-Omega_m)[l][P][u], real form
+        ProfScope ps_(p, SOX_STAGE_IFT, s);
+        IftSolidArgs f{};
+        f.tbc = p.d_tbc; f.aw = (const float*)aw; f.out = (float*)(atau + 2 * (long)p0 * nN);
+        f.fstride = (long)ps * nN; f.ldo = (long)np2 * nN; f.cols = (long)cp * nN;
+        f.nt = nt; f.nw = nw;
+        hipLaunchKernelGGL(ift_solid_kernel, dim3(resident_grid(p, &ift_solid_kernel, 256)),
+                           dim3(256), 0, s, f);
+        SOX_HIP(hipGetLastError());
+      } else {
         // A(tau)[pair][P][u] = sum_{+-m} Tb[tau][+-m] A(+-Omega_m)[l][P][u]
         ProfScope ps_(p, SOX_STAGE_IFT, s);
         CgArgs<double, T> a = cg_args<double, T>();

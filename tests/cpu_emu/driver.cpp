@@ -80,7 +80,8 @@ int run_case(int n, int N, int nt, int prec, int entry, bool vjp, bool dyn) {
 }
 
 // k-point plans: complex128 buffers of their exact sizes; G is built on the
-// mesh, then the bare or static entry and the energy run.
+// mesh, then the bare, static or dynamic entry (0, 1, 2) or the vertex entry
+// with kind entry - 3 (3 .. 7), and the energy run.
 int run_solid_case(int n, int N, int nt, int prec, int entry, const int mesh[3]) {
   const int nk = mesh[0] * mesh[1] * mesh[2];
   std::vector<double> tau(nt), w(nt, 1.0);
@@ -91,16 +92,17 @@ int run_solid_case(int n, int N, int nt, int prec, int entry, const int mesh[3])
   for (int i = 0; i < 3; ++i) pr.kmesh[i] = mesh[i];
   pr.beta = beta; pr.tau = tau.data(); pr.weights = w.data();
   const int nw = 3;
+  const bool dyn = entry == 2 || entry >= 3 + SOX_VERTEX_SOSEX_DYN;
   std::vector<double> tf(2 * nw * nt, 0.01), tb(2 * nw * nt, 0.01);
-  if (entry == 2) { pr.n_omega = nw; pr.t_fwd = tf.data(); pr.t_bwd = tb.data(); }
+  if (dyn) { pr.n_omega = nw; pr.t_fwd = tf.data(); pr.t_bwd = tb.data(); }
   sox_plan* plan = nullptr;
   if (sox_plan_create(&pr, prec, &plan)) { printf("create failed: %s\n", sox_last_error()); return 1; }
   size_t wsb = 0;
-  sox_workspace_size(plan, entry, &wsb);
+  sox_workspace_size(plan, entry >= 3 ? SOX_ENTRY_VERTEX : entry, &wsb);
   g_ws_size = wsb + 4096;
   g_ws_base = (char*)aligned_alloc(256, (g_ws_size + 255) & ~size_t(255));
   double* X = dalloc(2 * (size_t)nk * n * N);
-  double* U1 = dalloc(2 * (size_t)nk * N * N * (entry == 2 ? nt : 1));
+  double* U1 = dalloc(2 * (size_t)nk * N * N * (dyn ? nt : 1));
   double* U2 = dalloc(2 * (size_t)nk * N * N);
   double* Q = dalloc(2 * (size_t)nk * n * n);
   double* eps = dalloc((size_t)nk * n, 3.0);
@@ -110,7 +112,8 @@ int run_solid_case(int n, int N, int nt, int prec, int entry, const int mesh[3])
   if (!st) {
     if (entry == 0) st = sox_sigma_bare(plan, X, U1, G, S, g_ws_base, wsb, nullptr);
     else if (entry == 1) st = sox_sigma_static(plan, X, U1, U2, G, S, g_ws_base, wsb, nullptr);
-    else st = sox_sigma_dynamic(plan, X, U1, U2, G, S, g_ws_base, wsb, nullptr);
+    else if (entry == 2) st = sox_sigma_dynamic(plan, X, U1, U2, G, S, g_ws_base, wsb, nullptr);
+    else st = sox_sigma_vertex(plan, entry - 3, X, U2, U1, G, S, g_ws_base, wsb, nullptr);
   }
   double E = 0.0;
   if (!st) st = sox_energy_gm(plan, S, G, &E, nullptr);

@@ -18,6 +18,8 @@ extern thread_local uint3e threadIdx, blockIdx, blockDim, gridDim;
 #define __host__
 #define __forceinline__ inline
 #define __launch_bounds__(x)
+// occupancy hints apply to GPU kernels only
+#define amdgpu_waves_per_eu(...) unused
 #define __shared__ static
 #define __align__(x) __attribute__((aligned(x)))
 inline void __syncthreads() {}

@@ -79,6 +79,12 @@ SOLID_CASES = [
     (4, 20, 4, 1, 2, (3, 1, 1), None),    # dynamic, even n: W(Omega) GG(Omega) in real block form
     (6, 33, 3, 2, 2, (2, 2, 1), "1"),     # the same in bf16 x 3, pair and tau slabs
     (4, 17, 3, 1, 2, (1, 3, 1), "1"),     # ragged N, several slabs
+    # vertex entry, kind = entry - 3: SOSEX_dyn (bare and dynamic terms in one
+    # pass) with the real-form transforms, 2SOSEX_dyn, G3W2_stat
+    (4, 20, 4, 1, 6, (3, 1, 1), None),
+    (6, 33, 3, 2, 6, (2, 2, 1), "1"),
+    (5, 17, 3, 1, 7, (1, 3, 1), None),
+    (4, 20, 2, 2, 5, (2, 1, 1), None),
 ]
 
 
