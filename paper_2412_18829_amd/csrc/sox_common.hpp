@@ -48,6 +48,11 @@ __device__ __forceinline__ void global_to_lds16(const void* src, void* lds) {
 }
 // s_waitcnt vmcnt(0) (expcnt and lgkmcnt left at their maxima)
 __device__ __forceinline__ void wait_vm_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+// s_waitcnt vmcnt(N) with the other counters at their maxima
+template <int N> __device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt holds six bits");
+  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
+}
 
 // Workgroup barrier without a memory fence.  __syncthreads() fences, and a
 // fence makes every wavefront wait for all of its global-to-LDS copies

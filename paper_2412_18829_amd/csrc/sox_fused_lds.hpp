@@ -89,12 +89,6 @@ constexpr int kLdsPieces = kLdsTile * 4;  // 16-byte pieces per panel plane
 constexpr int kLdsBufs = 5;               // ring of half-stage buffers
 constexpr int kLdsAhead = kLdsBufs - 1;   // halves copied ahead of the MFMAs
 
-// s_waitcnt vmcnt(N) with the other counters at their maxima
-template <int N> __device__ __forceinline__ void wait_vm() {
-  static_assert(N >= 0 && N < 64, "vmcnt holds six bits");
-  __builtin_amdgcn_s_waitcnt((N & 15) | ((N >> 4) << 14) | 0x0F70);
-}
-
 template <int MODE, int NPL, int PB = 4>
 __device__ __forceinline__ void lds_frags(const u32x4 (*buf)[kLdsPieces], const int* sa,
                                           const int* sy, LdsFrags<MODE, PB>& f) {
