@@ -39,6 +39,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2516.6}
+HBM_PEAK_GBS = 8000.0
 DTYPE_NAME = {"fp64": "f64", "fp32": "f32", "bf16x3": "bf16x3"}
 METRIC = "SOX Sigma(all tau) sweeps/sec + TFLOP/s vs MFMA peak; mixed vs FP64 path at stated err"
 WORKLOADS = {
@@ -107,18 +108,47 @@ def flops_per_sweep(n: int, N: int, nt: int, kind: str = "bare", n_omega: int = 
     return f
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(kind: str = "bare") -> str:
+    """Hash of the dominant kernel's source: the fused kernels' files for
+    molecules; for solids the split panel kernel and its launcher (the text
+    between their markers in sox_complex.hpp) and the shared helpers."""
+    csrc = os.path.join(ROOT, "paper_2412_18829_amd", "csrc")
     h = hashlib.sha256()
+    if kind == "solid":
+        src = open(os.path.join(csrc, "sox_complex.hpp")).read()
+        a = src.index("template <bool FIXA, int NW, bool DMA>")
+        b = src.index("#undef SOX_PANEL3", a)
+        h.update(src[a:b].encode())
+        with open(os.path.join(csrc, "sox_common.hpp"), "rb") as fh:
+            h.update(fh.read())
+        return h.hexdigest()[:16]
     for f in ("sox_fused.hpp", "sox_fused_lds.hpp", "sox_common.hpp"):
-        with open(os.path.join(ROOT, "paper_2412_18829_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def read_traffic(workload: int, precision: str):
-    """HBM bytes per fused launch from the committed rocprofv3 counter summary,
-    or None when absent or taken on a different kernel source."""
-    path = os.path.join(ROOT, "profiles", f"fused_bcd_w{workload}_{precision}_traffic.txt")
+def solid_bc_bytes(n: int, N: int, nt: int, nk: int, ts: int) -> float:
+    """Algorithmic HBM bytes of one sweep's B and C products (complex64, the
+    dynamic chain's tau slabs of ts nodes per orbital v): every output
+    written once, every distinct operand read once per launch.
+      B[l][pair] = A(tau_l)[pair] X^{k_v - q1}^T: A read once, the n_k X panels
+      C[l][pair] = GwPt^{k_w}(tau_l) Ut2[pair][v]^T: the n_k GwPt panels of each
+      node, the Ut2 rows of v"""
+    np2, e = nk * nk, 8.0
+    slabs = (nt + ts - 1) // ts
+    writes = 2 * nt * np2 * N * N * e
+    reads_b = nt * np2 * N * n * e + slabs * nk * N * n * e
+    reads_c = nt * nk * N * n * e + slabs * np2 * N * n * e
+    return n * (writes + reads_b + reads_c)
+
+
+def read_traffic(workload: int, precision: str, kind: str = "bare"):
+    """HBM bytes per launch of the dominant kernel from the committed
+    rocprofv3 counter summary, or None when absent or taken on a different
+    kernel source."""
+    stem = "cgemm_panel_bf16x3" if kind == "solid" else "fused_bcd"
+    path = os.path.join(ROOT, "profiles", f"{stem}_w{workload}_{precision}_traffic.txt")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -126,7 +156,7 @@ def read_traffic(workload: int, precision: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_hash") != kernel_source_hash():
+    if kv.get("kernel_source_hash") != kernel_source_hash(kind):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -451,8 +481,26 @@ def main() -> int:
     dom_ms, dom_launches = prof[stage]
     dom_avg_ms = dom_ms / max(dom_launches, 1)
     dom_flops_per_launch = fl[stage] * main_run["prof_steps"] / max(dom_launches, 1)
-    achieved = dom_flops_per_launch / (dom_avg_ms * 1e-3) / 1e12
-    peak = PEAK_TFLOPS[args.precision]
+    mfma_tflops = dom_flops_per_launch / (dom_avg_ms * 1e-3) / 1e12
+    peak_tflops = PEAK_TFLOPS[args.precision]
+    if solid:
+        # the B and C products write N x N outputs per K = n inputs: HBM-bound
+        dom_bytes_per_launch = (solid_bc_bytes(n, N, nt, nk, main_run["plan"]["solid_dyn_tau_slab"])
+                                * main_run["prof_steps"] / max(dom_launches, 1))
+        roofline = {"kernel": kname, "bound": "hbm",
+                    "achieved": dom_bytes_per_launch / (dom_avg_ms * 1e-3) / 1e9,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        roofline["frac"] = roofline["achieved"] / HBM_PEAK_GBS
+        roofline["traffic"] = read_traffic(args.workload, args.precision, kind)
+        roofline.update({"avg_launch_ms": dom_avg_ms, "bytes_per_launch": dom_bytes_per_launch,
+                         "flops_per_launch": dom_flops_per_launch,
+                         "mfma_tflops_fp32_equivalent": mfma_tflops,
+                         "mfma_peak_tflops": peak_tflops})
+    else:
+        roofline = {"kernel": kname, "bound": "mfma", "achieved": mfma_tflops,
+                    "peak": peak_tflops, "unit": "TFLOP/s", "frac": mfma_tflops / peak_tflops,
+                    "traffic": read_traffic(args.workload, args.precision, kind),
+                    "avg_launch_ms": dom_avg_ms, "flops_per_launch": dom_flops_per_launch}
     stage_ms = main_run["stages"]
 
     # every GPU run first (host-side numpy work between them would perturb
@@ -578,12 +626,7 @@ def main() -> int:
         "energy_gm": main_run["energy"],
         "energy_gm_spread_over_steps": main_run["energy_spread"],
         "max_rel_err": main_err,
-        "roofline": {
-            "kernel": kname, "bound": "mfma", "achieved": achieved, "peak": peak,
-            "unit": "TFLOP/s", "frac": achieved / peak,
-            "traffic": read_traffic(args.workload, args.precision),
-            "avg_launch_ms": dom_avg_ms, "flops_per_launch": dom_flops_per_launch,
-        },
+        "roofline": roofline,
         "stage_ms_per_step": stage_ms,
         "plan": main_run["plan"],
     }
