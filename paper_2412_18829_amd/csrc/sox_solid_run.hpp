@@ -786,18 +786,25 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
     for (int a0 = 0; a0 < nt && ta; a0 += ta) {
       const int ca = std::min(ta, nt - a0);
       ProfScope ps_(p, SOX_STAGE_ASTEP, s);
-      // A_bare[l][pair][P][q] = sum_s G^{k_v}(beta - tau_{a0+l})_sv Ut[pair][q][P][s]
-      // (rows: the slab's nodes; columns (P, q); Ut of V, the line-2 U-tensor)
+      // A_bare[l][pair][q][P] = sum_s G^{k_v}(beta - tau_{a0+l})_sv Ut[pair][q][P][s]
+      // (rows: the slab's nodes; columns (q, P), so that the U-tensor rows of
+      // a column block are one contiguous block; Ut of V, the line-2 U-tensor).
+      // On the panel kernels the nodes' rows are the staged panel (ca <= 64
+      // rows) and the columns are streamed in nvb blocks per workgroup.
+      int nvb = 8;
+      while (nvb > 1 && nN % nvb) --nvb;
       CgArgs<T, T> a = cg_args<T, T>();
       a.A = gtm + 2 * ((long)v * nt + a0) * n;
       a.idxA = kOf; a.soA = (long)n * nt * n; a.ldA = n;
-      a.B = ut2; a.soB = (long)n * N * n; a.splitB = n; a.hiB = n; a.ldB = (long)N * n;
-      a.C = abare; a.soC = nN; a.ldc = (long)np2 * nN;
-      a.M = ca; a.N = N * n; a.K = n;
-      if ((st = cg_launch(a, np2, 1, s))) return st;
-      // A(tau)[pair][P][u] += sum_q A_bare[pair][P][q] G^{k_v - q1}(tau)[u][q]
+      a.B = ut2; a.soB = (long)n * N * n; a.ldB = n; a.vsB = nN / nvb * n;
+      a.C = abare; a.soC = nN; a.ldc = (long)np2 * nN; a.vsC = nN / nvb;
+      a.nv = nvb;
+      a.M = ca; a.N = (int)(nN / nvb); a.K = n;
+      if ((st = bc_launch(a, np2, true, 1, s, split))) return st;
+      // A(tau)[pair][P][u] += sum_q A_bare[pair][q][P] G^{k_v - q1}(tau)[u][q]
+      // (A rows P consecutive, k = q N apart)
       CgArgs<T, T> b = cg_args<T, T>();
-      b.A = abare; b.soA = nN; b.siA = (long)np2 * nN; b.ldA = n;
+      b.A = abare; b.soA = nN; b.siA = (long)np2 * nN; b.ldA = 1; b.ksA = N;
       b.B = gct + 2 * (long)a0 * n * n; b.idxB = kmqOf; b.soB = (long)nt * n * n;
       b.siB = (long)n * n; b.ldB = n;
       b.C = atau + 2 * (long)a0 * np2 * nN; b.soC = nN; b.siC = (long)np2 * nN; b.ldc = n;
