@@ -108,6 +108,28 @@ __device__ __forceinline__ void lds_frags(const u32x4 (*buf)[kLdsPieces], const 
   }
 }
 
+// the same from separate plane sets: P rows from pp[0 .. NPL), R rows from
+// rp[0 .. NPL)
+template <int MODE, int NPL, int PB = 4>
+__device__ __forceinline__ void lds_frags2(const u32x4 (*pp)[kLdsPieces],
+                                           const u32x4 (*rp)[kLdsPieces], const int* sa,
+                                           const int* sy, LdsFrags<MODE, PB>& f) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if constexpr (MODE == kLdsBf16x3) {
+      if (i < PB) {
+        f.ah[i] = __builtin_bit_cast(bf16x8, pp[0][sa[i]]);
+        f.al[i] = __builtin_bit_cast(bf16x8, pp[1][sa[i]]);
+      }
+      f.bh[i] = __builtin_bit_cast(bf16x8, rp[0][sy[i]]);
+      f.bl[i] = __builtin_bit_cast(bf16x8, rp[1][sy[i]]);
+    } else {
+      if (i < PB) f.a[i] = __builtin_bit_cast(f32x4, pp[0][sa[i]]);
+      f.b[i] = __builtin_bit_cast(f32x4, rp[0][sy[i]]);
+    }
+  }
+}
+
 // acc (+)= one 64-byte k chunk of the product; FIRST starts from zero
 template <int MODE, bool FIRST, int PB = 4>
 __device__ __forceinline__ void lds_half_mfma(const LdsFrags<MODE, PB>& f, f32x4 (*acc)[4]) {
@@ -134,16 +156,30 @@ __device__ __forceinline__ void lds_half_mfma(const LdsFrags<MODE, PB>& f, f32x4
 
 // PB = 4: four wavefronts of 64 x 64; PB = 2: eight wavefronts of 32 x 64
 // (the P rows of the workgroup tile split four ways), two per SIMD.
-template <int MODE, int PB = 4>
+//
+// RES: the two v-independent panels (Y for the B half, G_wP^T for the C
+// half) are copied into LDS once, for every k chunk, when the workgroup
+// starts, and stay resident for the whole v sum; the ring then carries only
+// the v-dependent panels (A^v, U2^v), half the copies and LDS writes per
+// half.  For K up to lds_res_chunks 64-byte chunks (nP <= 64: 144 KB of
+// LDS in bf16 x 3).
+template <int MODE> constexpr int lds_res_chunks() { return MODE == kLdsBf16x3 ? 2 : 1; }
+
+template <int MODE, int PB = 4, bool RES = false>
 __global__ __launch_bounds__(1024 / PB) void fused_bcd_lds_kernel(const LdsFusedArgs p) {
   static_assert(PB == 2 || PB == 4, "32 or 64 P rows per wavefront");
   constexpr int NPL = LdsMode<MODE>::kPlanes;
   constexpr int ES = LdsMode<MODE>::kEsize;
   constexpr int NW = 16 / PB;           // wavefronts
   constexpr int CP = PB / 2;            // copies per wavefront, panel and plane
-  constexpr int kCopies = 2 * NPL * CP;  // copies per wavefront and half
-  // [buffer][plane: P rows (hi, lo), then R rows (hi, lo)][row * 4 + swizzled segment]
-  __shared__ u32x4 lds[kLdsBufs][2 * NPL][kLdsPieces];
+  constexpr int RPL = RES ? NPL : 2 * NPL;  // ring planes per half
+  constexpr int kCopies = RPL * CP;        // copies per wavefront and half
+  constexpr int RC = RES ? lds_res_chunks<MODE>() : 1;
+  // ring: [buffer][plane: P rows (hi, lo), then R rows (hi, lo); RES: the
+  // half's v-dependent panel only][row * 4 + swizzled segment]
+  __shared__ u32x4 lds[kLdsBufs][RPL][kLdsPieces];
+  // RES: [k chunk][plane: Y rows (hi, lo), then G_wP^T rows (hi, lo)][...]
+  __shared__ u32x4 res[RC][RES ? 2 * NPL : 1][RES ? kLdsPieces : 1];
   const int bid = xcd_remap(blockIdx.x, gridDim.x);
   const int rt = bid % p.tiles_r;
   int rest = bid / p.tiles_r;
@@ -211,13 +247,29 @@ __global__ __launch_bounds__(1024 / PB) void fused_bcd_lds_kernel(const LdsFused
         global_to_lds16(srcr[q] + offr + orr[h], &buf[NPL + q][ch]);
       }
   };
+  // one panel's planes (RES)
+  auto copy_one = [&](u32x4 (*buf)[kLdsPieces], const char* const* src, long off,
+                      const unsigned* orr) {
+#pragma unroll
+    for (int q = 0; q < NPL; ++q)
+#pragma unroll
+      for (int h = 0; h < CP; ++h)
+        global_to_lds16(src[q] + off + orr[h], &buf[q][64 * (wave + NW * h)]);
+  };
   auto copy_b = [&](int b) {
     const long ko = (long)ckc * 64;
-    copy_panels(lds[b], p.bp, ot_a + (long)cv * p.a_vstride * ES + ko, p.br, ot_y + ko, orow_r);
+    if constexpr (RES)
+      copy_one(lds[b], p.bp, ot_a + (long)cv * p.a_vstride * ES + ko, orow_p);
+    else
+      copy_panels(lds[b], p.bp, ot_a + (long)cv * p.a_vstride * ES + ko, p.br, ot_y + ko,
+                  orow_r);
   };
   auto copy_c = [&](int b) {
     const long ko = (long)ckc * 64;
-    copy_panels(lds[b], p.cp, ot_p + ko, p.cr, (long)cv * p.u_vstride * ES + ko, orow_u);
+    if constexpr (RES)
+      copy_one(lds[b], p.cr, (long)cv * p.u_vstride * ES + ko, orow_u);
+    else
+      copy_panels(lds[b], p.cp, ot_p + ko, p.cr, (long)cv * p.u_vstride * ES + ko, orow_u);
     const int adv = cs + 1 < nst ? 1 : 0;  // selects, no branch: one block per half
     cs += adv;
     ckc += adv;
@@ -226,8 +278,26 @@ __global__ __launch_bounds__(1024 / PB) void fused_bcd_lds_kernel(const LdsFused
     cv += wrap;
   };
 
+  // fragments of the B half of stage (v, kc) in buffer b, and of its C half
+  auto frags_b = [&](int b, int kc, LdsFrags<MODE, PB>& f) {
+    if constexpr (RES) lds_frags2<MODE, NPL, PB>(lds[b], res[kc], sa, sy, f);
+    else lds_frags<MODE, NPL, PB>(lds[b], sa, sy, f);
+  };
+  auto frags_c = [&](int b, int kc, LdsFrags<MODE, PB>& f) {
+    if constexpr (RES) lds_frags2<MODE, NPL, PB>(res[kc] + NPL, lds[b], sa, sy, f);
+    else lds_frags<MODE, NPL, PB>(lds[b], sa, sy, f);
+  };
+
   if (nst > 0) {
     LdsFrags<MODE, PB> f0, f1;
+    if constexpr (RES) {
+      // the resident panels of every k chunk first (they complete before
+      // any ring copy, so the ring's counted waits cover them)
+      for (int kc = 0; kc < KC; ++kc) {
+        copy_one(res[kc], p.br, ot_y + (long)kc * 64, orow_r);
+        copy_one(res[kc] + NPL, p.cp, ot_p + (long)kc * 64, orow_p);
+      }
+    }
     // halves 0..3 (stages 0 and 1) in flight, then halves 0 and 1 landed
     copy_b(0);
     copy_c(1);
@@ -235,7 +305,7 @@ __global__ __launch_bounds__(1024 / PB) void fused_bcd_lds_kernel(const LdsFused
     copy_c(3);
     wait_vm<kCopies * (kLdsAhead - 2)>();
     barrier_nofence();
-    lds_frags<MODE, NPL, PB>(lds[0], sa, sy, f0);
+    frags_b(0, 0, f0);
     int b1 = 1;  // buffer of half 2 s + 1
     // B half of stage s: copy half 2 s + 4 into the buffer of half 2 s - 1,
     // read the C-half fragments, MFMAs from f0.  C half: copy half 2 s + 5
@@ -243,10 +313,10 @@ __global__ __launch_bounds__(1024 / PB) void fused_bcd_lds_kernel(const LdsFused
     // from f1.  Each half is one basic block (no branch between its copies,
     // fragment reads and MFMAs), which leaves the compiler free to overlap
     // them.
-    auto half_b = [&](auto first, int bcopy) {
+    auto half_b = [&](auto first, int bcopy, int kc) {
       constexpr bool F = decltype(first)::value;
       copy_b(bcopy);
-      lds_frags<MODE, NPL, PB>(lds[b1], sa, sy, f1);
+      frags_c(b1, kc, f1);
       if constexpr (F) {
 #pragma unroll
         for (int i = 0; i < PB; ++i)
@@ -257,10 +327,10 @@ __global__ __launch_bounds__(1024 / PB) void fused_bcd_lds_kernel(const LdsFused
       wait_vm<kCopies * (kLdsAhead - 2)>();
       barrier_nofence();
     };
-    auto half_c = [&](auto first, int bcopy, int bread) {
+    auto half_c = [&](auto first, int bcopy, int bread, int kcn) {
       constexpr bool F = decltype(first)::value;
       copy_c(bcopy);
-      lds_frags<MODE, NPL, PB>(lds[bread], sa, sy, f0);
+      frags_b(bread, kcn, f0);
       lds_half_mfma<MODE, F, PB>(f1, accC);
       wait_vm<kCopies * (kLdsAhead - 2)>();
       barrier_nofence();
@@ -271,12 +341,13 @@ __global__ __launch_bounds__(1024 / PB) void fused_bcd_lds_kernel(const LdsFused
         const int b2 = b1 + 1 == kLdsBufs ? 0 : b1 + 1;  // half 2 s + 2
         const int b3 = b2 + 1 == kLdsBufs ? 0 : b2 + 1;  // half 2 s + 3
         const int b4 = b3 + 1 == kLdsBufs ? 0 : b3 + 1;  // half 2 s + 4
+        const int kcn = kc + 1 == KC ? 0 : kc + 1;  // k chunk of the next stage
         if (kc == 0) {
-          half_b(std::true_type{}, b4);
-          half_c(std::true_type{}, b0, b2);
+          half_b(std::true_type{}, b4, kc);
+          half_c(std::true_type{}, b0, b2, kcn);
         } else {
-          half_b(std::false_type{}, b4);
-          half_c(std::false_type{}, b0, b2);
+          half_b(std::false_type{}, b4, kc);
+          half_c(std::false_type{}, b0, b2, kcn);
         }
         b1 = b3;
       }
@@ -301,6 +372,14 @@ __global__ __launch_bounds__(1024 / PB) void fused_bcd_lds_kernel(const LdsFused
       }
 }
 
+// the resident-panel form applies: split precision (in float32 it measured
+// slower, 1.16 -> 1.24 ms per fused launch at n = 64, N = 384, 64 nodes:
+// its single-plane ring halves are already small) and every k chunk's Y and
+// G_wP^T panels fit (bf16 x 3 at n = 64, N = 384: 0.496 -> 0.472 ms)
+template <int MODE> inline bool fused_lds_resident(int nP) {
+  return MODE == kLdsBf16x3 && nP * LdsMode<MODE>::kEsize / 64 <= lds_res_chunks<MODE>();
+}
+
 // Grid: (R tile, P tile, tau, v split), R tiles fastest; 1024 / PB threads.
 template <int MODE, int PB = 4>
 inline hipError_t launch_fused_lds(const LdsFusedArgs& a, hipStream_t s) {
@@ -314,8 +393,12 @@ inline hipError_t launch_fused_lds(const LdsFusedArgs& a, hipStream_t s) {
   const long nb = (long)a.tiles_p * a.tiles_r * a.n_tau * a.vsplit;
   if (nb <= 0) return hipSuccess;
   if (!grid_fits(nb, 1024 / PB)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((fused_bcd_lds_kernel<MODE, PB>), dim3((unsigned)nb), dim3(1024 / PB), 0, s,
-                     a);
+  if (fused_lds_resident<MODE>(a.nP))
+    hipLaunchKernelGGL((fused_bcd_lds_kernel<MODE, PB, true>), dim3((unsigned)nb), dim3(1024 / PB),
+                       0, s, a);
+  else
+    hipLaunchKernelGGL((fused_bcd_lds_kernel<MODE, PB, false>), dim3((unsigned)nb),
+                       dim3(1024 / PB), 0, s, a);
   return hipGetLastError();
 }
 
