@@ -62,6 +62,20 @@ DOMINANT = {"bare": ("fused", "fused_bcd_kernel"), "static": ("fused", "fused_bc
             "dynamic": ("fused", "fused_bcd_kernel"), "solid": ("kbc", "cgemm_panel_kernel")}
 
 
+_T_START = time.perf_counter()
+_last_note = [0.0]
+
+
+def note(msg: str, every: float = 0.0) -> None:
+    """Progress line on stderr (stdout carries only the JSON line); with
+    `every`, at most one such line per that many seconds."""
+    now = time.perf_counter()
+    if every and now - _last_note[0] < every:
+        return
+    _last_note[0] = now
+    print(f"[bench {now - _T_START:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
+
 def flops_per_sweep(n: int, N: int, nt: int, kind: str = "bare", n_omega: int = 0,
                     nk: int = 1) -> dict:
     """Algorithmic FLOPs of one sweep, by stage (the paper's step costs).
@@ -279,6 +293,8 @@ def main() -> int:
                          "dynamic molecular run")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time of the oracle sample")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the plan's own launch choices (no sox_autotune before the warmup)")
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager launches instead of HIP graph replays")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -339,13 +355,16 @@ def main() -> int:
         del a, b
 
     def run(precision: str, steps: int, warmup: int, profile: bool, Xwarm=None,
-            graph: bool = False):
+            graph: bool = False, tune: bool = False):
         """warmup untimed steps, then `steps` timed ones.  Xwarm: the first
         warmup step runs on this collocation matrix instead (its Sigma is
         returned as Sigma_warm).  With profile, a later warmup step records
         every stage (the per-stage breakdown and the dominant kernel's launch
         times); with graphs, the last warmup step captures the sweep as a HIP
-        graph and the timed steps replay it.  None of this adds steps."""
+        graph and the timed steps replay it.  With tune, the plan's launch
+        choices are first autotuned on the workload's own operands
+        (sox_autotune, one call per candidate, before the warmup steps).
+        None of this adds steps."""
         Xr = X
         use_graph = graph and warmup >= (3 if profile else 2)
         prof_step = warmup - 2 if use_graph else warmup - 1
@@ -357,7 +376,17 @@ def main() -> int:
         G = torch.empty(gshape, dtype=cdt, device=dev)
         S = torch.empty_like(G)
         entry = "static" if kind == "static" else ("dynamic" if kind == "dynamic" else "bare")
-        ws = plan.workspace("vertex" if solid else entry)
+        went = "vertex" if solid else entry
+        vkind = "sosex_dyn" if solid else 0
+        ws = plan.workspace(went, plan.autotune_workspace_size(went, vkind) if tune else None)
+        if tune:
+            B.sox_build_g_tau(plan, Q, eps, wl["mu"], G)
+            u1, u2 = ((V, U1) if solid else (U1, V) if kind in ("static", "dynamic")
+                      else (V, None))
+            note(f"{precision}: autotuning the plan's launch choices")
+            B.sox_autotune(plan, went, X, u1, u2, G, S, kind=vkind, ws=ws)
+            torch.cuda.synchronize()
+            note(f"{precision}: autotuned {len(B.sox_plan_describe(plan)['autotune'])} candidates")
         # the energy of every step is queued into device memory (no host
         # synchronisation per step) and read after the timed region
         E = torch.zeros((warmup + steps + 3, 2), dtype=torch.float64, device=dev)
@@ -379,6 +408,9 @@ def main() -> int:
 
         sig_warm = None
         for w in range(warmup):
+            note(f"{precision}: warmup step {w + 1} of {warmup}", every=20.0)
+            if solid:
+                torch.cuda.synchronize()
             if w == 0 and Xwarm is not None:
                 Xr = Xwarm
                 step()
@@ -413,12 +445,19 @@ def main() -> int:
                for _ in range(steps)]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        note(f"{precision}: {steps} timed steps")
         for i in range(steps):
             evs[i][0].record()
             step()
             evs[i][1].record()
+            if solid:
+                # seconds per step: wait for each step (a few microseconds of
+                # launch gap against seconds of work) to print progress now and then
+                evs[i][1].synchronize()
+                note(f"{precision}: timed step {i + 1} of {steps} done", every=30.0)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        note(f"{precision}: timed steps done")
         step_ms = sorted(a.elapsed_time(b) for a, b in evs)
         prof = stages = None
         prof_steps = steps
@@ -465,7 +504,7 @@ def main() -> int:
         Xc[:, :, gold["cols"]] = X[:, :, gold["cols"]]
         args.warmup = max(args.warmup, 1)
     main_run = run(args.precision, args.steps, args.warmup, profile=True, Xwarm=Xc,
-                   graph=not args.no_graph)
+                   graph=not args.no_graph, tune=not args.no_autotune)
     sec = main_run["seconds"]
     ms_per_step = 1e3 * sec / args.steps
     value = args.steps / sec

@@ -324,9 +324,44 @@ sox_status sox_profile_read(sox_plan* plan, double* ms, int64_t* launches, int64
  * timing (sox_profile_*) records nothing for replayed sweeps. */
 sox_status sox_plan_set_graph(sox_plan* plan, int32_t enable);
 
+/* Autotuner on the caller's operands (the batching of all tau nodes and,
+ * for k-point plans, all momentum pairs into few launches whose shapes are
+ * the plan's choices; see the THC section's step lists for the steps).
+ * Times one call of `entry` (several when a call takes under 20 ms) for
+ * every candidate setting of the plan's launch choices and keeps the
+ * fastest:
+ *   molecules        the fused B, C -> D kernel's configuration (wave tile,
+ *                    direct-load or LDS-staged, of the plan's precision)
+ *                    and the split of its v sum over workgroups;
+ *   k-point, dynamic the tau slab of the B, C and D steps (4, 8, 16 nodes)
+ *                    and the momentum-pair slab of the transforms (the
+ *                    plan's and half of it);
+ *   k-point, static / bare  the v slab of the B, C and D steps (the plan's
+ *                    and half of it).
+ * Candidates whose workspace exceeds SOX_WS_BUDGET_MB or workspace_bytes
+ * are skipped; sox_autotune_workspace_size gives the size that admits every
+ * candidate.  Operands as the entry takes them: BARE U1 = V, U2 = NULL;
+ * STATIC U1 = W0, U2 = V; DYNAMIC U1 = W_tau, U2 = V; VERTEX U1 = V,
+ * U2 = W with vertex kind `kind` (ignored otherwise).  Sigma receives the
+ * result of the last candidate timed (every candidate computes the same
+ * Sigma).  With SOX_TUNE_CACHE=<file> the choice is appended to the file,
+ * keyed by entry, kind, precision and shape, and a later call with the same
+ * key takes it from there without timing.  The plan's graphs are dropped
+ * (its launch sequence may change); the plan's graph mode is kept.  Results
+ * appear under "autotune" in sox_plan_describe.  Errors: those of the entry
+ * (the first failing candidate's status is returned). */
+sox_status sox_autotune(sox_plan* plan, int32_t entry, int32_t kind, const double* X,
+                        const double* U1, const double* U2, const double* G, double* Sigma,
+                        void* workspace, size_t workspace_bytes, void* stream);
+
+/* Workspace bytes that admit every sox_autotune candidate of `entry`
+ * (`kind` as for sox_autotune). */
+sox_status sox_autotune_workspace_size(const sox_plan* plan, int32_t entry, int32_t kind,
+                                       size_t* bytes);
+
 /* A one-line JSON description of the plan's decisions: padded extents, the
- * fused kernel's wave tile, tau-slab and v-slab widths, and the autotuner's
- * timings when it ran.  Writes at most `len` bytes including the NUL. */
+ * fused kernel's wave tile, tau-slab and v-slab widths, and the autotuners'
+ * timings when they ran.  Writes at most `len` bytes including the NUL. */
 sox_status sox_plan_describe(const sox_plan* plan, char* buf, size_t len);
 
 /* Synchronise `stream` and report any pending device error. */

@@ -32,7 +32,7 @@ EXPORTED = (
     "sox_sigma_static", "sox_sigma_dynamic", "sox_sigma_vjp", "sox_build_g_tau",
     "sox_energy_gm", "sox_energy_gm_device", "sox_sync", "sox_last_error", "sox_abi_version", "sox_profile_enable",
     "sox_profile_read", "sox_profile_select", "sox_plan_set_graph", "sox_plan_describe",
-    "sox_sigma_bare_noalloc", "sox_sigma_vertex",
+    "sox_sigma_bare_noalloc", "sox_sigma_vertex", "sox_autotune", "sox_autotune_workspace_size",
 )
 STAGES = ("gbuild", "utensor", "project", "astep", "fused", "back", "energy", "gg_ft", "wgemm",
           "ift", "split", "vjp", "kbc", "kd")
@@ -74,6 +74,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.sox_sigma_static.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_sigma_bare_noalloc.argtypes = [vp, vp, vp, vp, vp, vp]
     L.sox_sigma_vertex.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.sox_autotune.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.sox_autotune_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
     L.sox_sigma_dynamic.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_sigma_vjp.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_build_g_tau.argtypes = [vp, vp, vp, dp, vp, vp]
@@ -198,14 +200,26 @@ class Plan:
         _check(load().sox_workspace_size(self.handle, e, ctypes.byref(out)), "sox_workspace_size")
         return int(out.value)
 
-    def workspace(self, entry: str | int):
-        """A cached device workspace (torch uint8 tensor) for `entry`."""
+    def autotune_workspace_size(self, entry: str | int, kind=0) -> int:
+        e = ENTRIES[entry] if isinstance(entry, str) else int(entry)
+        k = VERTEX_KINDS[kind] if isinstance(kind, str) else int(kind)
+        out = ctypes.c_size_t()
+        _check(load().sox_autotune_workspace_size(self.handle, e, k, ctypes.byref(out)),
+               "sox_autotune_workspace_size")
+        return int(out.value)
+
+    def workspace(self, entry: str | int, nbytes: int | None = None):
+        """A cached device workspace (torch uint8 tensor) for `entry`, of at
+        least nbytes (default: the entry's size for the plan's choices)."""
         import torch
-        nbytes = self.workspace_size(entry)
-        ws = self._ws.get(entry)
-        if ws is None or ws.numel() < nbytes:
+        e = ENTRIES[entry] if isinstance(entry, str) else int(entry)
+        if nbytes is None:
+            nbytes = self.workspace_size(e)
+        ws = self._ws.get(e)
+        if ws is None or ws.numel() < nbytes + 256:
+            self._ws.pop(e, None)
             ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
-            self._ws[entry] = ws
+            self._ws[e] = ws
         return ws
 
     def close(self):
@@ -262,6 +276,28 @@ def sox_sigma_vertex(plan: Plan, kind, X, V, W, G, Sigma, ws=None, stream=None):
                                    t(W, wshape, "W"), t(G, (nt, n, n), "G"),
                                    t(Sigma, (nt, n, n), "Sigma"), w, wb, _stream(stream)),
            "sox_sigma_vertex")
+    return Sigma
+
+
+def sox_autotune(plan: Plan, entry, X, U1, U2, G, Sigma, kind=0, ws=None, stream=None):
+    """Time the plan's launch-choice candidates on these operands (one call of
+    `entry` each) and keep the fastest.  U1, U2 as the entry takes them: bare
+    V, None; static W0, V; dynamic W_tau, V; vertex V, W (kind as for
+    sox_sigma_vertex).  Sigma receives the last candidate's result.  The
+    default workspace is sized for every candidate."""
+    n, N, nt = plan.n, plan.N, plan.n_tau
+    e = ENTRIES[entry] if isinstance(entry, str) else int(entry)
+    k = VERTEX_KINDS[kind] if isinstance(kind, str) else int(kind)
+    if ws is None:
+        ws = plan.workspace(e, plan.autotune_workspace_size(e, k))
+    w, wb = _ws_args(plan, e, ws)
+    t = plan._t
+    s1 = (nt, N, N) if e == SOX_ENTRY_DYNAMIC else (N, N)
+    s2 = (nt, N, N) if (e == SOX_ENTRY_VERTEX and k in (3, 4)) else (N, N)
+    _check(load().sox_autotune(plan.handle, e, k, t(X, (n, N), "X"), t(U1, s1, "U1"),
+                               t(U2, s2, "U2") if U2 is not None else None,
+                               t(G, (nt, n, n), "G"), t(Sigma, (nt, n, n), "Sigma"), w, wb,
+                               _stream(stream)), "sox_autotune")
     return Sigma
 
 
@@ -371,6 +407,6 @@ def sox_plan_set_graph(plan: Plan, enable: bool = True):
 
 def sox_plan_describe(plan: Plan) -> dict:
     import json
-    buf = ctypes.create_string_buffer(4096)
+    buf = ctypes.create_string_buffer(16384)
     _check(load().sox_plan_describe(plan.handle, buf, len(buf)), "sox_plan_describe")
     return json.loads(buf.value.decode())

@@ -142,6 +142,13 @@ struct sox_plan {
   // fused-tile autotuner results: (config, ms per tau)
   std::vector<std::pair<int, double>> tune_ms;
   bool tune_from_cache = false;
+  // sox_autotune: every candidate's launch choices and its ms per call
+  struct TuneResult {
+    int fused_cfg, fused_vsplit, dyn_ts, dyn_ps, vcs, vcs_bare;
+    double ms;
+  };
+  std::vector<TuneResult> autotune;
+  int autotune_cached = 0;  // 1: the choices came from the tune cache
   bool prof_on = false;
   uint32_t prof_mask = 0xFFFFFFFFu;  // stages recorded while profiling is on
   std::vector<Ev> ev_pool;
@@ -2451,6 +2458,267 @@ sox_status sox_profile_read(sox_plan* plan, double* ms, int64_t* launches, int64
   return SOX_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Autotuner on the caller's operands.  A candidate is one setting of the
+// plan's launch choices: molecules the fused kernel config and the split of
+// its v sum; k-point meshes the tau slab of the B, C and D steps and the
+// pair slab of the transforms (dynamic terms) or the v slab (static and
+// bare terms).  Every candidate whose workspace fits the budget and the
+// caller's buffer is timed on one call of the entry (several for calls
+// under 20 ms), the fastest is kept, and the choice is cached per
+// (entry, kind, precision, shape) in the file SOX_TUNE_CACHE names.
+typedef sox_plan::TuneResult TuneKnobs;
+
+TuneKnobs get_knobs(const sox_plan& p) {
+  return TuneKnobs{p.fused_cfg, p.fused_vsplit, p.dyn_ts, p.dyn_ps, p.vcs, p.vcs_bare, 0.0};
+}
+
+// the plan's own picks for its current fused config (as at plan creation)
+void refresh_choices(sox_plan& p) {
+  if (p.nk > 1) {
+    p.vcs = pick_solid_vc(p, SOX_ENTRY_STATIC);
+    p.vcs_bare = pick_solid_vc(p, SOX_ENTRY_BARE);
+    if (p.n_omega > 0) pick_solid_dyn(p);
+  } else {
+    p.slab = pick_slab(p, SOX_ENTRY_STATIC);
+    p.vjp_slab = pick_vjp_slab(p, SOX_ENTRY_STATIC);
+    if (p.n_omega > 0) pick_dyn(p);
+    pick_vsplit(p);
+  }
+}
+
+void set_knobs(sox_plan& p, const TuneKnobs& k) {
+  if (k.fused_cfg != p.fused_cfg) {
+    set_fused_cfg(p, k.fused_cfg);
+    refresh_choices(p);
+  }
+  p.fused_vsplit = k.fused_vsplit;
+  p.dyn_ts = k.dyn_ts;
+  p.dyn_ps = k.dyn_ps;
+  p.vcs = k.vcs;
+  p.vcs_bare = k.vcs_bare;
+}
+
+bool entry_is_dynamic(int entry, int kind) {
+  return entry == SOX_ENTRY_DYNAMIC ||
+         (entry == SOX_ENTRY_VERTEX &&
+          (kind == SOX_VERTEX_SOSEX_DYN || kind == SOX_VERTEX_2SOSEX_DYN));
+}
+
+// candidates within the workspace budget, the plan's own choice first
+std::vector<TuneKnobs> tune_candidates(const sox_plan& p0, int entry, int kind) {
+  std::vector<TuneKnobs> out;
+  const size_t budget = ws_budget();
+  sox_plan p = p0;  // a copy for the layout arithmetic (no resources are freed)
+  auto add = [&](const TuneKnobs& k) {
+    set_knobs(p, k);
+    if (workspace_bytes(p, entry) > budget) return;
+    for (auto& o : out)
+      if (o.fused_cfg == k.fused_cfg && o.fused_vsplit == k.fused_vsplit && o.dyn_ts == k.dyn_ts &&
+          o.dyn_ps == k.dyn_ps && o.vcs == k.vcs && o.vcs_bare == k.vcs_bare)
+        return;
+    out.push_back(k);
+  };
+  const TuneKnobs base = get_knobs(p0);
+  add(base);
+  const bool dyn = entry_is_dynamic(entry, kind);
+  if (p0.nk == 1) {
+    for (int c = 0; c < kNumFusedCfgs; ++c) {
+      if (!cfg_usable(p0, c)) continue;
+      // the split-precision dynamic entry runs on the LDS-staged kernel only
+      if (dyn && p0.precision == SOX_BF16X3 && c != 8) continue;
+      set_knobs(p, base);
+      TuneKnobs k = base;
+      k.fused_cfg = c;
+      set_knobs(p, k);
+      const TuneKnobs own = get_knobs(p);  // that config's own v split
+      add(own);
+      // the v split applies to the static entries' LDS-staged and direct-load
+      // float kernels; the split-precision direct-load kernels sum all v
+      if (p0.precision != SOX_BF16X3 || c == 8)
+        for (int s : {1, 2, 4})
+          if (s != own.fused_vsplit && (p0.n + s - 1) / s >= 8) {
+            TuneKnobs ks = own;
+            ks.fused_vsplit = s;
+            add(ks);
+          }
+    }
+  } else if (dyn) {
+    for (int ts : {4, 8, 16})
+      for (int half = 0; half < 2; ++half) {
+        TuneKnobs k = base;
+        k.dyn_ts = std::min(ts, p0.n_tau);
+        if (half) {
+          const int nq = base.dyn_ps / p0.nk;  // whole momentum transfers per slab
+          if (nq < 2) continue;
+          k.dyn_ps = (nq + 1) / 2 * p0.nk;
+        }
+        add(k);
+      }
+  } else {
+    for (int h : {1, 2}) {
+      TuneKnobs k = base;
+      k.vcs = std::max(1, (base.vcs + h - 1) / h);
+      k.vcs_bare = std::max(1, (base.vcs_bare + h - 1) / h);
+      add(k);
+    }
+  }
+  return out;
+}
+
+std::string autotune_key(const sox_plan& p, int entry, int kind) {
+  char k[160];
+  snprintf(k, sizeof(k), "auto-%d-%d %d %d %d %d %d %d %d %d", entry, kind, p.precision, p.n,
+           p.N, p.n_tau, p.kmesh[0], p.kmesh[1], p.kmesh[2], p.n_omega);
+  return k;
+}
+
+}  // namespace
+
+extern "C" {
+
+sox_status sox_autotune_workspace_size(const sox_plan* plan, int32_t entry, int32_t kind,
+                                       size_t* bytes) {
+  if (!plan) return fail(SOX_ERR_INVALID_ARG, "plan is NULL");
+  if (!bytes) return fail(SOX_ERR_INVALID_ARG, "bytes is NULL");
+  if (entry < SOX_ENTRY_BARE || entry > SOX_ENTRY_VERTEX)
+    return fail(SOX_ERR_INVALID_ARG, "unknown entry %d", entry);
+  sox_plan p = *plan;
+  size_t need = workspace_bytes(p, entry);
+  for (const TuneKnobs& k : tune_candidates(*plan, entry, kind)) {
+    set_knobs(p, k);
+    need = std::max(need, workspace_bytes(p, entry));
+  }
+  *bytes = need;
+  return SOX_OK;
+}
+
+sox_status sox_autotune(sox_plan* plan, int32_t entry, int32_t kind, const double* X,
+                        const double* U1, const double* U2, const double* G, double* Sigma,
+                        void* ws, size_t ws_bytes, void* stream) {
+  sox_status st = check_plan(plan);
+  if (st) return st;
+  if (entry < SOX_ENTRY_BARE || entry > SOX_ENTRY_VERTEX)
+    return fail(SOX_ERR_INVALID_ARG, "unknown entry %d", entry);
+  if (!X || !U1 || !G || !Sigma || (entry != SOX_ENTRY_BARE && !U2))
+    return fail(SOX_ERR_INVALID_ARG, "NULL tensor pointer");
+  if (!ws) return fail(SOX_ERR_WORKSPACE, "workspace is NULL");
+  sox_plan& p = *plan;
+  const hipStream_t s = (hipStream_t)stream;
+  auto call = [&]() -> sox_status {
+    switch (entry) {
+      case SOX_ENTRY_BARE: return sox_sigma_bare(plan, X, U1, G, Sigma, ws, ws_bytes, stream);
+      case SOX_ENTRY_STATIC:
+        return sox_sigma_static(plan, X, U1, U2, G, Sigma, ws, ws_bytes, stream);
+      case SOX_ENTRY_DYNAMIC:
+        return sox_sigma_dynamic(plan, X, U1, U2, G, Sigma, ws, ws_bytes, stream);
+      default: return sox_sigma_vertex(plan, kind, X, U1, U2, G, Sigma, ws, ws_bytes, stream);
+    }
+  };
+  std::vector<TuneKnobs> cand = tune_candidates(p, entry, kind);
+  const TuneKnobs own = get_knobs(p);
+  // a cached choice (validated like any candidate) replaces the timing
+  const std::string key = autotune_key(p, entry, kind);
+  if (const char* cache = getenv("SOX_TUNE_CACHE")) {
+    if (FILE* f = fopen(cache, "r")) {
+      char line[256];
+      bool found = false;
+      TuneKnobs best{};
+      while (fgets(line, sizeof(line), f)) {
+        char k[32];
+        int e, pr, n, N, nt, m0, m1, m2, nw;
+        TuneKnobs t{};
+        if (sscanf(line, "%31s %d %d %d %d %d %d %d %d | %d %d %d %d %d %d", k, &pr, &n, &N, &nt,
+                   &m0, &m1, &m2, &nw, &t.fused_cfg, &t.fused_vsplit, &t.dyn_ts, &t.dyn_ps,
+                   &t.vcs, &t.vcs_bare) != 15)
+          continue;
+        (void)e;
+        char full[160];
+        snprintf(full, sizeof(full), "%s %d %d %d %d %d %d %d %d", k, pr, n, N, nt, m0, m1, m2, nw);
+        if (key != full) continue;
+        for (const TuneKnobs& c : cand)
+          if (c.fused_cfg == t.fused_cfg && c.fused_vsplit == t.fused_vsplit &&
+              c.dyn_ts == t.dyn_ts && c.dyn_ps == t.dyn_ps && c.vcs == t.vcs &&
+              c.vcs_bare == t.vcs_bare) {
+            best = c;
+            found = true;
+          }
+      }
+      fclose(f);
+      if (found) {
+        sox_plan q = p;
+        set_knobs(q, best);
+        if (workspace_bytes(q, entry) <= ws_bytes) {
+          drop_graphs(p);
+          set_knobs(p, best);
+          p.autotune.clear();
+          p.autotune_cached = 1;
+          return SOX_OK;
+        }
+      }
+    }
+  }
+  const bool graph = p.graph_on, prof = p.prof_on;
+  p.graph_on = false;  // eager launches: the launch sequence changes between candidates
+  p.prof_on = false;
+  drop_graphs(p);
+  hipEvent_t a = nullptr, b = nullptr;
+  auto finish = [&](sox_status r) {
+    if (a) (void)hipEventDestroy(a);
+    if (b) (void)hipEventDestroy(b);
+    p.graph_on = graph;
+    p.prof_on = prof;
+    return r;
+  };
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+    return finish(fail(SOX_ERR_HIP, "autotune events"));
+  p.autotune.clear();
+  p.autotune_cached = 0;
+  double best_ms = 1e300;
+  TuneKnobs best = own;
+  bool warm = false;
+  for (const TuneKnobs& c : cand) {
+    sox_plan q = p;
+    set_knobs(q, c);
+    if (workspace_bytes(q, entry) > ws_bytes) continue;
+    set_knobs(p, c);
+    if (!warm) {  // first touch of the operands and the code
+      if ((st = call())) return finish(st);
+      warm = true;
+    }
+    int reps = 0;
+    float ms = 0.f;
+    SOX_HIP(hipEventRecord(a, s));
+    do {
+      if ((st = call())) return finish(st);
+      ++reps;
+      SOX_HIP(hipEventRecord(b, s));
+      SOX_HIP(hipEventSynchronize(b));
+      SOX_HIP(hipEventElapsedTime(&ms, a, b));
+    } while (ms < 20.f && reps < 50);
+    TuneKnobs r = c;
+    r.ms = ms / reps;
+    p.autotune.push_back(r);
+    if (r.ms < best_ms) {
+      best_ms = r.ms;
+      best = c;
+    }
+  }
+  set_knobs(p, best);
+  if (const char* cache = getenv("SOX_TUNE_CACHE")) {
+    if (FILE* f = fopen(cache, "a")) {
+      fprintf(f, "%s | %d %d %d %d %d %d\n", key.c_str(), best.fused_cfg, best.fused_vsplit,
+              best.dyn_ts, best.dyn_ps, best.vcs, best.vcs_bare);
+      fclose(f);
+    }
+  }
+  return finish(SOX_OK);
+}
+
 sox_status sox_plan_set_graph(sox_plan* plan, int32_t enable) {
   sox_status st = check_plan(plan);
   if (st) return st;
@@ -2470,6 +2738,17 @@ sox_status sox_plan_describe(const sox_plan* plan, char* buf, size_t len) {
     tune += t;
   }
   tune += "]";
+  std::string at = "[";
+  for (size_t i = 0; i < plan->autotune.size(); ++i) {
+    const auto& r = plan->autotune[i];
+    char t[160];
+    snprintf(t, sizeof(t),
+             "%s{\"fused_cfg\":%d,\"fused_vsplit\":%d,\"tau_slab\":%d,\"pair_slab\":%d,"
+             "\"v_slab\":%d,\"v_slab_bare\":%d,\"ms\":%.6g}",
+             i ? "," : "", r.fused_cfg, r.fused_vsplit, r.dyn_ts, r.dyn_ps, r.vcs, r.vcs_bare, r.ms);
+    at += t;
+  }
+  at += "]";
   const FusedCfg& fc = kFusedCfgs[plan->fused_cfg];
   snprintf(buf, len,
            "{\"n\":%d,\"N\":%d,\"n_tau\":%d,\"nP\":%d,\"NP\":%d,\"precision\":%d,"
@@ -2478,12 +2757,13 @@ sox_status sox_plan_describe(const sox_plan* plan, char* buf, size_t len) {
            "\"tune_ms_per_tau\":%s,"
            "\"tune_from_cache\":%d,\"kmesh\":[%d,%d,%d],\"n_k\":%d,\"solid_v_slab\":%d,"
            "\"solid_v_slab_bare\":%d,\"solid_dyn_pair_slab\":%d,\"solid_dyn_tau_slab\":%d,"
-           "\"solid_bare_tau_slab\":%d,\"dynamic_real_w\":%d}",
+           "\"solid_bare_tau_slab\":%d,\"dynamic_real_w\":%d,\"autotune\":%s,"
+           "\"autotune_cached\":%d}",
            plan->n, plan->N, plan->n_tau, plan->nP, plan->NP, plan->precision, plan->fused_cfg,
            fc.wp, fc.wr, plan->slab, plan->vjp_slab, plan->vc, plan->vc_vjp, plan->graph_on ? 1 : 0,
            plan->fused_vsplit, plan->n_cu, tune.c_str(), plan->tune_from_cache ? 1 : 0, plan->kmesh[0], plan->kmesh[1],
            plan->kmesh[2], plan->nk, plan->vcs, plan->vcs_bare, plan->dyn_ps, plan->dyn_ts,
-           plan->dyn_ta, plan->last_w_real);
+           plan->dyn_ta, plan->last_w_real, at.c_str(), plan->autotune_cached);
   return SOX_OK;
 }
 

@@ -50,7 +50,9 @@ int run_case(int n, int N, int nt, int prec, int entry, bool vjp, bool dyn) {
     printf("plan %s\n", desc);
   }
   size_t wsb = 0;
-  sox_workspace_size(plan, entry, &wsb);
+  const bool tune = getenv("EMU_AUTOTUNE") != nullptr && !vjp;
+  if (tune) sox_autotune_workspace_size(plan, entry, 0, &wsb);
+  else sox_workspace_size(plan, entry, &wsb);
   g_ws_size = wsb + 4096;
   g_ws_base = (char*)aligned_alloc(256, (g_ws_size + 255) & ~size_t(255));
   double* X = dalloc((size_t)n * N);
@@ -64,6 +66,13 @@ int run_case(int n, int N, int nt, int prec, int entry, bool vjp, bool dyn) {
   double* dU1 = dalloc((size_t)N * N * (entry == 2 ? nt : 1));
   double* dU2 = dalloc((size_t)N * N);
   sox_status st;
+  if (tune) {
+    st = sox_autotune(plan, entry, 0, X, U1, entry == 0 ? nullptr : U2, G, S, g_ws_base, wsb, nullptr);
+    char desc[8192];
+    sox_plan_describe(plan, desc, sizeof(desc));
+    printf("tuned %s (status %d %s)\n", desc, st, st ? sox_last_error() : "");
+    if (st) return st;
+  }
   if (!vjp) {
     if (entry == 0) st = sox_sigma_bare(plan, X, U1, G, S, g_ws_base, wsb, nullptr);
     else if (entry == 1) st = sox_sigma_static(plan, X, U1, U2, G, S, g_ws_base, wsb, nullptr);
@@ -98,7 +107,10 @@ int run_solid_case(int n, int N, int nt, int prec, int entry, const int mesh[3])
   sox_plan* plan = nullptr;
   if (sox_plan_create(&pr, prec, &plan)) { printf("create failed: %s\n", sox_last_error()); return 1; }
   size_t wsb = 0;
-  sox_workspace_size(plan, entry >= 3 ? SOX_ENTRY_VERTEX : entry, &wsb);
+  const bool tune = getenv("EMU_AUTOTUNE") != nullptr;
+  const int ent = entry >= 3 ? SOX_ENTRY_VERTEX : entry, kind = entry >= 3 ? entry - 3 : 0;
+  if (tune) sox_autotune_workspace_size(plan, ent, kind, &wsb);
+  else sox_workspace_size(plan, ent, &wsb);
   g_ws_size = wsb + 4096;
   g_ws_base = (char*)aligned_alloc(256, (g_ws_size + 255) & ~size_t(255));
   double* X = dalloc(2 * (size_t)nk * n * N);
@@ -109,6 +121,14 @@ int run_solid_case(int n, int N, int nt, int prec, int entry, const int mesh[3])
   double* G = dalloc(2 * (size_t)nk * nt * n * n);
   double* S = dalloc(2 * (size_t)nk * nt * n * n);
   sox_status st = sox_build_g_tau(plan, Q, eps, 0.0, G, nullptr);
+  if (!st && tune) {
+    const double* u1 = ent == SOX_ENTRY_VERTEX ? U2 : U1;
+    const double* u2 = ent == SOX_ENTRY_VERTEX ? U1 : (entry == 0 ? nullptr : U2);
+    st = sox_autotune(plan, ent, kind, X, u1, u2, G, S, g_ws_base, wsb, nullptr);
+    char desc[8192];
+    sox_plan_describe(plan, desc, sizeof(desc));
+    printf("tuned %s (status %d %s)\n", desc, st, st ? sox_last_error() : "");
+  }
   if (!st) {
     if (entry == 0) st = sox_sigma_bare(plan, X, U1, G, S, g_ws_base, wsb, nullptr);
     else if (entry == 1) st = sox_sigma_static(plan, X, U1, U2, G, S, g_ws_base, wsb, nullptr);

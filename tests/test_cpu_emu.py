@@ -187,3 +187,31 @@ def test_noalloc_entry_in_bounds(emu, prec):
                        env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"), timeout=600)
     out = r.stdout + r.stderr
     assert r.returncode == 0 and "noalloc ok" in out and "AddressSanitizer" not in out, out[-4000:]
+
+
+# the operand-based autotuner: every candidate's launch sequence on the
+# caller's buffers, then the entry with the chosen settings (molecules:
+# fused configs and v splits, float32 and bf16 x 3; k-point: tau and pair
+# slabs of the dynamic chain, v slabs of the static one)
+TUNE_CASES = [
+    ("mol", (13, 70, 5, 2, 1, 0, None)),
+    ("mol", (16, 256, 2, 1, 0, 0, None)),
+    ("solid", (4, 20, 4, 1, 6, (3, 1, 1), None)),
+    ("solid", (5, 17, 2, 0, 1, (4, 1, 1), None)),
+]
+
+
+@pytest.mark.parametrize("case", TUNE_CASES, ids=lambda c: c[0] + "-" + "-".join(str(x) for x in c[1]))
+def test_autotune_in_bounds(emu, case):
+    kind, c = case
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", EMU_AUTOTUNE="1")
+    if kind == "mol":
+        n, N, nt, prec, entry, vjp, budget = c
+        args = [emu, str(n), str(N), str(nt), str(prec), str(entry), "0"]
+    else:
+        n, N, nt, prec, entry, mesh, budget = c
+        args = [emu, str(n), str(N), str(nt), str(prec), str(entry), "0", *[str(m) for m in mesh]]
+    r = subprocess.run(args, capture_output=True, text=True, env=env, timeout=900)
+    out = r.stdout + r.stderr
+    assert r.returncode == 0 and "status 0" in out and "AddressSanitizer" not in out, out[-4000:]
+    assert '"autotune":[{' in out, out[-4000:]

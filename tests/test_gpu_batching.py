@@ -170,3 +170,81 @@ def test_solid_graph_replays_match_eager(B, entry):
         torch.cuda.synchronize()
         assert torch.equal(Sg, Se), f"replay {rep}"
         del junk
+
+
+def _check_autotune(desc):
+    """Every candidate timed, the plan left on the fastest one."""
+    at = desc["autotune"]
+    assert len(at) >= 2 and desc["autotune_cached"] == 0, desc
+    assert all(r["ms"] > 0 for r in at)
+    best = min(at, key=lambda r: r["ms"])
+    return best
+
+
+def test_autotuned_bf16x3_molecule_vs_oracle(B, tmp_path, monkeypatch):
+    """sox_autotune on the caller's operands (split precision: the LDS-staged
+    and direct-load fused configurations, v splits), then the tuned plan
+    against the oracle at the split-precision bound; a second plan of the
+    same shape takes the cached choice without timing."""
+    import torch
+    cache = tmp_path / "auto.txt"
+    monkeypatch.setenv("SOX_TUNE_CACHE", str(cache))
+    n, N, nt = 40, 200, 4
+    wl = synth.small_molecule(n, N, nt, 7.0, seed=240, static=True)
+    Gr = om.g_tau(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    mk = lambda: B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision="bf16x3")
+    X, W0, V, G = dev(wl["X"]), dev(wl["W0"]), dev(wl["V"]), dev(Gr)
+    S = torch.empty((nt, n, n), dtype=torch.float64, device="cuda")
+    p1 = mk()
+    B.sox_autotune(p1, "static", X, W0, V, G, S)
+    d1 = B.sox_plan_describe(p1)
+    log(f"autotuned bf16x3 molecule: {d1['autotune']}")
+    best = _check_autotune(d1)
+    assert (d1["fused_cfg"], d1["fused_vsplit"]) == (best["fused_cfg"], best["fused_vsplit"])
+    assert {r["fused_cfg"] for r in d1["autotune"]} >= {8}
+    ref = om.sigma_static_thc(wl["X"], wl["W0"], wl["V"], Gr, Gr[::-1])
+    err_tune = rel_err(host(S), ref)      # the last candidate's Sigma
+    B.sox_sigma_static(p1, X, W0, V, G, S)
+    torch.cuda.synchronize()
+    err = rel_err(host(S), ref)
+    log(f"  rel err {err:.3e} (last candidate {err_tune:.3e})")
+    assert err <= 1e-4 and err_tune <= 1e-4
+    p2 = mk()
+    B.sox_autotune(p2, "static", X, W0, V, G, S)
+    d2 = B.sox_plan_describe(p2)
+    assert d2["autotune_cached"] == 1 and d2["autotune"] == []
+    assert (d2["fused_cfg"], d2["fused_vsplit"]) == (d1["fused_cfg"], d1["fused_vsplit"])
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_autotuned_solid_dynamic_vs_oracle(B, precision, tmp_path, monkeypatch):
+    """k-point plan (3x1x1 mesh, even n: the register-GG transforms and the
+    block-form W(Omega) GG(Omega)): sox_autotune over the tau slab of the
+    B, C, D steps and the pair slab of the transforms, then the tuned plan
+    against the oracle's eq:GG chain."""
+    import torch
+    from oracle import sox_solid as osd
+    monkeypatch.setenv("SOX_TUNE_CACHE", str(tmp_path / "auto.txt"))
+    wl = synth.add_dynamic_screening_solid(synth.solid((3, 1, 1), 6, 40, 12, 10.0, seed=47),
+                                           n_poles=2)
+    tp = synth.bosonic_transform_pair(wl["tau"], wl["beta"], omega_max=10.0, tol=1e-10)
+    plan = B.Plan(wl["n"], wl["N"], wl["tau"], wl["weights"], wl["beta"], precision=precision,
+                  kmesh=wl["mesh"], t_fwd=tp["T_fwd"], t_bwd=tp["T_bwd"])
+    c = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.complex128, device="cuda")
+    G0 = osd.g_tau_k(wl["eps"], wl["Q"], 0.0, wl["beta"], wl["tau"])
+    X, W, V, G = c(wl["X"]), c(wl["W_tau"]), c(wl["V"]), c(G0)
+    S = torch.empty_like(G)
+    B.sox_autotune(plan, "dynamic", X, W, V, G, S)
+    d = B.sox_plan_describe(plan)
+    log(f"autotuned solid dynamic {precision}: {d['autotune']}")
+    best = _check_autotune(d)
+    assert (d["solid_dyn_tau_slab"], d["solid_dyn_pair_slab"]) == (best["tau_slab"], best["pair_slab"])
+    assert len({(r["tau_slab"], r["pair_slab"]) for r in d["autotune"]}) >= 2
+    B.sox_sigma_dynamic(plan, X, W, V, G, S)
+    torch.cuda.synchronize()
+    tables = (wl["kvecs"], wl["kdiff"], wl["ksum"], wl["kneg"])
+    ref = osd.sigma_solid_dynamic_thc(wl["X"], wl["W_tau"], wl["V"], G0, tp["T_fwd"], tp["T_bwd"],
+                                      tables)
+    err = rel_err(host(S), ref)
+    log(f"  rel err {err:.3e}")
+    assert err <= (1e-6 if precision == "fp32" else 1e-4)
