@@ -293,7 +293,7 @@ struct DenseLdsSplitArgs {
   const bf16_t* Bh;
   const bf16_t* Bl;
   long lda, ldb, ldc;  // row strides (elements)
-  long sA, sB, sC;     // batch strides (elements; blockIdx.y is the batch)
+  long sA, sB, sC;     // batch strides (elements; the batch is the grid's slowest index)
   int M, N, K;
   float* C;
   int tiles_m, tiles_n;
@@ -316,14 +316,20 @@ __global__ __launch_bounds__(1024 / PB) void dense_lds_bf16x3_kernel(const Dense
   constexpr int NBG = 8 / PB;    // wavefront groups over the B rows (C columns)
   // [buffer][plane: B rows hi, lo (first MFMA operand), A rows hi, lo][row * 4 + swizzled segment]
   __shared__ u32x4 lds[kLdsBufs][4][kLdsPieces];
-  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  // one-dimensional grid over (batch, tile), batch-major, remapped so that
+  // each XCD takes a contiguous range: the tiles of a batch share its A and B
+  // operands in one L2 (with the batch on a second grid axis every XCD took
+  // a share of every batch and read its A panel again)
+  const int lg = xcd_remap(blockIdx.x, gridDim.x);
+  const int ntl = p.tiles_m * p.tiles_n;
+  const long bat = lg / ntl;
+  const int bid = lg - (int)bat * ntl;
   const int M0 = (bid % p.tiles_m) * kLdsTile;  // row blocks fastest: they share B
   const int N0 = (bid / p.tiles_m) * kLdsTile;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15;
   const int g = lane >> 4;
-  const long bat = blockIdx.y;
   const char* srcb[2][CP];  // [plane][copy]
   const char* srca[2][CP];
 #pragma unroll
@@ -457,10 +463,9 @@ inline hipError_t launch_dense_lds_bf16x3(DenseLdsSplitArgs a, int batch, hipStr
   a.vec = (a.ldc % 4 == 0 && a.sC % 4 == 0 && out % 16 == 0 && split_ok) ? 1 : 0;
   a.tiles_m = (a.M + kLdsTile - 1) / kLdsTile;
   a.tiles_n = (a.N + kLdsTile - 1) / kLdsTile;
-  const long nb = (long)a.tiles_m * a.tiles_n;
-  if (!grid_fits(nb, 1024 / PB, batch)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL((dense_lds_bf16x3_kernel<PB>), dim3((unsigned)nb, (unsigned)batch),
-                     dim3(1024 / PB), 0, s, a);
+  const long nb = (long)a.tiles_m * a.tiles_n * batch;
+  if (nb >= (1L << 31) || !grid_fits(nb, 1024 / PB)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL((dense_lds_bf16x3_kernel<PB>), dim3((unsigned)nb), dim3(1024 / PB), 0, s, a);
   return hipGetLastError();
 }
 
