@@ -36,6 +36,8 @@ Modules:
   sox_solid  k-point solids: brute force and the THC step chain.
   sox_vjp    reference vector-Jacobian products (torch CPU float64 autograd
              of the THC chain).
+  sox_gw     the THC-GW direct term Sigma^GW = -G W_d of fig:diag (molecules
+             and k-point meshes): 4-index brute force and THC chain.
   sox_vertex the composite vertex self-energies (SOSEX, 2SOSEX, G3W2stat of
              fig:diag) as sums of SOX terms; SOX(V, W_d) with the dynamic
              interaction on line 2 has its own brute force in sox_mol /
