@@ -239,6 +239,50 @@ def cpu_oracle_baseline(wl: dict, kind: str, budget_s: float):
     return None, None
 
 
+GW_CALLS = 5
+
+
+def gw_flops(n: int, N: int, nt: int, nk: int = 1) -> float:
+    """Flops of one sox_sigma_gw call: per node and momentum the projections
+    X^T G (n^2 N), (X^T G) X (N^2 n), X M (n N^2) and (X M) X^T (n^2 N)
+    multiply-adds, 2 flops each (8 for complex); the mesh's momentum
+    convolution as its direct n_k^2 N^2 complex multiply-adds per node."""
+    macs = 2.0 * n * n * N + 2.0 * N * N * n
+    if nk == 1:
+        return 2.0 * nt * macs
+    return 8.0 * nk * nt * macs + 8.0 * nk * nk * nt * N * N
+
+
+def cpu_oracle_gw(wl: dict, poles):
+    """Oracle sample of the THC-GW direct term: G(tau) synthesis and the
+    THC chain for two tau nodes at full rank (the term is local in tau),
+    timed and scaled to one call over every node; also the error reference
+    of the GPU call at those nodes."""
+    from oracle import sox_gw as ogw
+    from oracle import sox_mol as om
+    from oracle import sox_solid as osd
+    nt = wl["n_tau"]
+    nodes = [0, nt // 2]
+    tn = wl["tau"][nodes]
+    c0 = time.perf_counter()
+    if poles is not None:
+        G = osd.g_tau_k(wl["eps"], wl["Q"], wl["mu"], wl["beta"], tn)
+        Wn = sum(a * pole[None, nodes, None, None] * S[:, None] for a, pole, S in poles)
+        tb = (wl["kvecs"], wl["kdiff"], wl["ksum"], wl["kneg"])
+        ref = ogw.sigma_gw_solid_thc(wl["X"], Wn, G, tb)
+    else:
+        G = om.g_tau(wl["eps"], wl["Q"], wl["mu"], wl["beta"], tn)
+        ref = ogw.sigma_gw_thc(wl["X"], wl["W_tau"][nodes], G)
+    sec = time.perf_counter() - c0
+    rec = {"value": len(nodes) / nt / sec, "unit": "calls/s", "cores": blas_threads(),
+           "host_cpus": len(os.sched_getaffinity(0)), "cpu_model": cpu_model(),
+           "kind": "oracle", "extrapolated": True,
+           "sample": (f"numpy float64 oracle (THC chain, full rank) for {len(nodes)} of {nt} "
+                      f"tau nodes ({sec:.2f} s, G(tau) and W_d(tau) at those nodes formed inside), "
+                      "scaled to one call over every node")}
+    return rec, ref, nodes
+
+
 def cpu_oracle_solid(wl: dict, poles: list, tp: dict, cols) -> dict:
     """Oracle sample of the solid step SOX(V,V) + SOX(W_d,V).  At the full
     THC rank one oracle node and orbital v already take minutes on the host,
@@ -293,6 +337,8 @@ def main() -> int:
                          "dynamic molecular run")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="minimum CPU time of the oracle sample")
+    ap.add_argument("--no-gw", action="store_true",
+                    help="skip the THC-GW direct term (sox_sigma_gw) timed after a dynamic run")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the plan's own launch choices (no sox_autotune before the warmup)")
     ap.add_argument("--no-graph", action="store_true",
@@ -591,6 +637,39 @@ def main() -> int:
                "note": "one call after the timed forward steps, no warmup"}
         del plan, G, Rr, grads
 
+    gw = None
+    if kind in ("dynamic", "solid") and not args.no_gw:
+        # the THC-GW direct term on the same W_d(tau), G(tau) and X: one warm
+        # call, then GW_CALLS timed calls (float64 whatever the precision)
+        note("gw: THC-GW direct term")
+        plan = B.Plan(n, N, wl["tau"], wl["weights"], wl["beta"], precision="fp64",
+                      kmesh=wl.get("mesh", (1, 1, 1)))
+        G = torch.empty(gshape, dtype=cdt, device=dev)
+        Sg = torch.empty_like(G)
+        B.sox_build_g_tau(plan, Q, eps, wl["mu"], G)
+        wsg = plan.workspace("gw")
+        B.sox_sigma_gw(plan, X, U1, G, Sg, ws=wsg)
+        torch.cuda.synchronize()
+        ev = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        ev[0].record()
+        for _ in range(GW_CALLS):
+            B.sox_sigma_gw(plan, X, U1, G, Sg, ws=wsg)
+        ev[1].record()
+        torch.cuda.synchronize()
+        gms = ev[0].elapsed_time(ev[1]) / GW_CALLS
+        gfl = gw_flops(n, N, nt, nk)
+        gw = {"entry": "sox_sigma_gw", "ms_per_call": gms, "calls_timed": GW_CALLS,
+              "dtype": "c128" if solid else "f64", "flops_per_call": gfl,
+              "roofline": {"scope": "whole call (float64 MFMA products and, for the mesh, the "
+                                    "momentum convolution)",
+                           "bound": "mfma", "achieved": gfl / (gms * 1e-3) / 1e12,
+                           "peak": PEAK_TFLOPS["fp64"], "unit": "TFLOP/s",
+                           "frac": gfl / (gms * 1e-3) / 1e12 / PEAK_TFLOPS["fp64"]},
+              "workspace_bytes": plan.workspace_size("gw")}
+        gw_sigma = Sg.cpu().numpy()
+        del plan, G, Sg, wsg
+        torch.cuda.empty_cache()
+
     # the oracle runs only in the CPU baseline leg; the last sweep it timed
     # (bare molecules) is also the FP64 reference of max_rel_err
     cpu = ref = None
@@ -600,6 +679,15 @@ def main() -> int:
         else:
             cpu, ref = cpu_oracle_baseline(wl, kind, args.cpu_seconds)
     out["cpu_baseline"] = cpu
+    if gw is not None and not args.no_cpu_baseline:
+        gcpu, gref, gnodes = cpu_oracle_gw(wl, poles)
+        gw["cpu_baseline"] = gcpu
+        gw["max_rel_err"] = float(np.abs(gw_sigma[..., gnodes, :, :] - gref).max()
+                                  / np.abs(gref).max())
+        gw["max_rel_err_reference"] = (f"FP64 oracle (full rank, its own G(tau)) at tau "
+                                       f"nodes {gnodes}")
+    if gw is not None:
+        out["gw"] = gw
     if cpu is None:
         out["cpu_baseline_note"] = ("not run: " + ("disabled by flag" if args.no_cpu_baseline else
                                     "no bounded oracle sample fits this workload on the host"))

@@ -108,7 +108,8 @@ typedef enum {
   SOX_ENTRY_BARE = 0,    /* SOX(V, V)                                        */
   SOX_ENTRY_STATIC = 1,  /* SOX(W0, V), W0 = W(Omega = 0)                    */
   SOX_ENTRY_DYNAMIC = 2, /* SOX(W_d(tau), V)                                 */
-  SOX_ENTRY_VERTEX = 3   /* sox_sigma_vertex, every kind (workspace only)    */
+  SOX_ENTRY_VERTEX = 3,  /* sox_sigma_vertex, every kind (workspace only)    */
+  SOX_ENTRY_GW = 4       /* sox_sigma_gw (workspace only)                    */
 } sox_entry;
 
 /* Composite vertex self-energies of the paper's diagram family (fig:diag;
@@ -235,6 +236,27 @@ sox_status sox_sigma_vertex(sox_plan* plan, int32_t kind, const double* X, const
                             const double* W, const double* G, double* Sigma, void* workspace,
                             size_t workspace_bytes, void* stream);
 
+/* The THC-GW direct term: the GW self-energy of fig:diag (the dynamic
+ * part: the propagator and the screened line W_d join the same two points),
+ *   Sigma_ij(tau) = - sum_kl (ik|lj)_{W_d(tau)} G_kl(tau)
+ *                 = - sum_PQ X_iP [Gt_PQ(tau) W_PQ(tau)] X_jQ,
+ *   Gt_PQ(tau) = sum_kl X_kP G_kl(tau) X_lQ,
+ * with the interaction in the THC form of section "THC-SOX and THC-SOSEX"
+ * (Gt starts from the SOX chain's half projection G_Rq).  Local in tau: no
+ * transform pair is needed, and W_tau is sampled on the plan's tau grid.
+ * Molecules: X [n,N], W_tau [n_tau,N,N], G, Sigma [n_tau,n,n], float64.
+ * Solids (complex128, leading n_k axis; W_tau indexed by the transfer q):
+ *   Sigma^k_ij(tau) = -(1/N_k) sum_k' sum_PQ conj(X^k_iP) W^{k-k'}_PQ(tau)
+ *                     Gt^{k'}_PQ(tau) X^k_jQ,
+ *   Gt^{k'}_PQ = sum_ls X^{k'}_lP G^{k'}_ls conj(X^{k'}_sQ).
+ * Every step runs in float64 whatever the plan's precision (the term costs
+ * O(n_tau N^2 n) per momentum pair, a factor n below the SOX chain).
+ * Workspace: sox_workspace_size(plan, SOX_ENTRY_GW).  Errors: NULL pointers
+ * (SOX_ERR_INVALID_ARG), workspace (SOX_ERR_WORKSPACE), launch failures
+ * (SOX_ERR_HIP). */
+sox_status sox_sigma_gw(sox_plan* plan, const double* X, const double* W_tau, const double* G,
+                        double* Sigma, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Vector-Jacobian product of L = sum(Sigma * R) for the entry `entry`:
  *   R [n_tau,n,n] cotangent;  dG [n_tau,n,n], dX [n,N], dU1, dU2 outputs.
  * For SOX_ENTRY_BARE, U1 = U2 = V is passed as U1 (U2 ignored) and dU1
@@ -298,7 +320,8 @@ typedef enum {
   SOX_STAGE_VJP = 11,     /* adjoint kernels                                */
   SOX_STAGE_KBC = 12,     /* solids: B and C products of every momentum pair */
   SOX_STAGE_KD = 13,      /* solids: the n_k^3 D step                        */
-  SOX_N_STAGES = 14
+  SOX_STAGE_GW = 14,      /* sox_sigma_gw, the whole chain                   */
+  SOX_N_STAGES = 15
 } sox_stage;
 
 sox_status sox_profile_enable(sox_plan* plan, int32_t on);

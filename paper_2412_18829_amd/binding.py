@@ -22,9 +22,9 @@ STATUS_NAMES = {
 }
 SOX_FP64, SOX_FP32, SOX_BF16X3 = 0, 1, 2
 PRECISIONS = {"fp64": SOX_FP64, "fp32": SOX_FP32, "bf16x3": SOX_BF16X3}
-SOX_ENTRY_BARE, SOX_ENTRY_STATIC, SOX_ENTRY_DYNAMIC, SOX_ENTRY_VERTEX = 0, 1, 2, 3
+SOX_ENTRY_BARE, SOX_ENTRY_STATIC, SOX_ENTRY_DYNAMIC, SOX_ENTRY_VERTEX, SOX_ENTRY_GW = 0, 1, 2, 3, 4
 ENTRIES = {"bare": SOX_ENTRY_BARE, "static": SOX_ENTRY_STATIC, "dynamic": SOX_ENTRY_DYNAMIC,
-           "vertex": SOX_ENTRY_VERTEX}
+           "vertex": SOX_ENTRY_VERTEX, "gw": SOX_ENTRY_GW}
 VERTEX_KINDS = {"sosex_stat": 0, "2sosex_stat": 1, "g3w2_stat": 2, "sosex_dyn": 3, "2sosex_dyn": 4}
 
 EXPORTED = (
@@ -33,9 +33,10 @@ EXPORTED = (
     "sox_energy_gm", "sox_energy_gm_device", "sox_sync", "sox_last_error", "sox_abi_version", "sox_profile_enable",
     "sox_profile_read", "sox_profile_select", "sox_plan_set_graph", "sox_plan_describe",
     "sox_sigma_bare_noalloc", "sox_sigma_vertex", "sox_autotune", "sox_autotune_workspace_size",
+    "sox_sigma_gw",
 )
 STAGES = ("gbuild", "utensor", "project", "astep", "fused", "back", "energy", "gg_ft", "wgemm",
-          "ift", "split", "vjp", "kbc", "kd")
+          "ift", "split", "vjp", "kbc", "kd", "gw")
 
 
 class SoxError(RuntimeError):
@@ -77,6 +78,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.sox_autotune.argtypes = [vp, i32, i32, vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_autotune_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
     L.sox_sigma_dynamic.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    L.sox_sigma_gw.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_sigma_vjp.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_build_g_tau.argtypes = [vp, vp, vp, dp, vp, vp]
     L.sox_energy_gm.argtypes = [vp, vp, vp, ctypes.POINTER(dp), vp]
@@ -276,6 +278,17 @@ def sox_sigma_vertex(plan: Plan, kind, X, V, W, G, Sigma, ws=None, stream=None):
                                    t(W, wshape, "W"), t(G, (nt, n, n), "G"),
                                    t(Sigma, (nt, n, n), "Sigma"), w, wb, _stream(stream)),
            "sox_sigma_vertex")
+    return Sigma
+
+
+def sox_sigma_gw(plan: Plan, X, W_tau, G, Sigma, ws=None, stream=None):
+    """THC-GW direct term Sigma = -G W_d (float64 whatever the plan's precision)."""
+    n, N, nt = plan.n, plan.N, plan.n_tau
+    w, wb = _ws_args(plan, "gw", ws)
+    t = plan._t
+    _check(load().sox_sigma_gw(plan.handle, t(X, (n, N), "X"), t(W_tau, (nt, N, N), "W_tau"),
+                               t(G, (nt, n, n), "G"), t(Sigma, (nt, n, n), "Sigma"), w, wb,
+                               _stream(stream)), "sox_sigma_gw")
     return Sigma
 
 

@@ -27,6 +27,7 @@
 #include "sox_dense_lds.hpp"
 #include "sox_vjp_steps.hpp"
 #include "sox_complex.hpp"
+#include "sox_gw.hpp"
 
 using namespace sox;
 
@@ -425,8 +426,11 @@ size_t solid_workspace_bytes(const sox_plan& p, int entry);  // with the solid l
 
 size_t vertex_workspace_bytes(const sox_plan& p);  // with the composite entry
 
+size_t gw_workspace_bytes(const sox_plan& p);  // with the GW entry
+
 size_t workspace_bytes(const sox_plan& p, int entry) {
   if (entry == SOX_ENTRY_VERTEX) return vertex_workspace_bytes(p);
+  if (entry == SOX_ENTRY_GW) return gw_workspace_bytes(p);
   if (p.nk > 1) return solid_workspace_bytes(p, entry);
   if (entry == SOX_ENTRY_DYNAMIC)
     return p.n_omega > 0 ? std::max(dyn_layout_for(p, p.vc, p.eslab).total, dyn_vjp_total(p, p.vc_vjp))
@@ -1951,6 +1955,128 @@ sox_status run_vertex(sox_plan& p, int kind, const double* X, const double* V, c
   }
 }
 
+// -- THC-GW direct term (sox_gw.hpp) ---------------------------------------------
+// Float64 buffers of one tau slab of c nodes (complex for meshes, every
+// momentum): the half projection G_Rl, the second projection Gt (meshes
+// only: molecules fold the elementwise product into it), M and Y = X M.
+struct GwLayout {
+  size_t p1, gt, m, y, total;
+};
+
+GwLayout gw_layout_for(const sox_plan& p, int c) {
+  GwLayout L{};
+  const size_t es = p.nk > 1 ? 16 : 8;
+  const size_t nk = p.nk, n = p.n, N = p.N, cc = c;
+  Carver k;
+  L.p1 = k.take(nk * cc * N * n * es);
+  L.gt = p.nk > 1 ? k.take(nk * cc * N * N * es) : 0;
+  L.m = k.take(nk * cc * N * N * es);
+  L.y = k.take(nk * cc * n * N * es);
+  L.total = k.off;
+  return L;
+}
+
+// tau nodes per slab: all of them if the buffers fit the workspace budget,
+// else halved until they do (at least one)
+int gw_slab(const sox_plan& p) {
+  const size_t budget = ws_budget();
+  int c = p.n_tau;
+  while (c > 1 && gw_layout_for(p, c).total > budget) c = (c + 1) / 2;
+  return c;
+}
+
+size_t gw_workspace_bytes(const sox_plan& p) { return gw_layout_for(p, gw_slab(p)).total; }
+
+sox_status run_gw(sox_plan& p, const double* X, const double* W, const double* G, double* Sigma,
+                  void* ws, hipStream_t s) {
+  const int c = gw_slab(p);
+  const GwLayout L = gw_layout_for(p, c);
+  char* base = (char*)ws;
+  double* p1 = (double*)(base + L.p1);
+  double* gt = (double*)(base + L.gt);
+  double* m = (double*)(base + L.m);
+  double* y = (double*)(base + L.y);
+  const int n = p.n, N = p.N, nt = p.n_tau, nk = p.nk;
+  ProfScope ps(p, SOX_STAGE_GW, s);
+  for (int t0 = 0; t0 < nt; t0 += c) {
+    const int cnt = std::min(c, nt - t0);
+    if (nk == 1) {
+      ProjP1Prob<double> pr1{X, G, p1, n, N, n, N, t0, N, n, n};
+      SOX_HIP((launch_gemm<ProjP1Prob<double>, double, 2, 2, 2, 2>(pr1, cnt, s)));
+      GwHadProb had{p1, X, W, m, n, N, t0, N, N, n};
+      SOX_HIP((launch_gemm<GwHadProb, double, 2, 2, 2, 2>(had, cnt, s)));
+      GwLeftProb left{X, m, y, n, N, n, N, N};
+      SOX_HIP((launch_gemm<GwLeftProb, double, 2, 2, 2, 2>(left, cnt, s)));
+      GwRightProb right{y, X, Sigma, n, N, t0, n, n, N};
+      SOX_HIP((launch_gemm<GwRightProb, double, 2, 2, 2, 2>(right, cnt, s)));
+      continue;
+    }
+    const int nz = nk * cnt;
+    const long cN = (long)c * N;
+    // G_Rl^k = sum_j X^k_jR G^k_jl
+    CgArgs<double, double> a = cg_args<double, double>();
+    a.A = X, a.ldA = 1, a.ksA = N, a.soA = (long)n * N;
+    a.B = G + 2 * (long)t0 * n * n, a.ldB = 1, a.ksB = n, a.soB = (long)nt * n * n,
+    a.siB = (long)n * n;
+    a.C = p1, a.ldc = n, a.soC = cN * n, a.siC = (long)N * n;
+    a.M = N, a.N = n, a.K = n, a.nzi = cnt;
+    sox_status st = cg_launch(a, nz, 0, s);
+    if (st) return st;
+    // Gt^k[R][Q] = sum_l G_Rl^k conj(X^k_lQ)
+    a = cg_args<double, double>();
+    a.A = p1, a.ldA = n, a.soA = cN * n, a.siA = (long)N * n;
+    a.B = X, a.ldB = 1, a.ksB = N, a.soB = (long)n * N, a.conjB = 1;
+    a.C = gt, a.ldc = N, a.soC = cN * N, a.siC = (long)N * N;
+    a.M = N, a.N = N, a.K = n, a.nzi = cnt;
+    if ((st = cg_launch(a, nz, 0, s))) return st;
+    // M^k = -(1/N_k) sum_k' W^{k-k'} Gt^{k'}: registers for the meshes of the
+    // templated D step, the LDS kernel for any other
+    const long NN = (long)N * N;
+    bool done = false;
+    const int* mc = p.mesh_canon;
+#define SOX_GWCONV(A_, B_, C_)                                                               \
+    if (!done && mc[0] == A_ && mc[1] == B_ && mc[2] == C_) {                                \
+      hipLaunchKernelGGL((gw_conv_mesh_kernel<A_, B_, C_>), grid1d(NN * cnt), dim3(256), 0, s, \
+                         W, gt, m, NN, c, t0, nt, -1.0 / nk, NN * cnt);                     \
+      SOX_HIP(hipGetLastError());                                                          \
+      done = true;                                                                         \
+    }
+    SOX_GWCONV(2, 1, 1)
+    SOX_GWCONV(3, 1, 1)
+    SOX_GWCONV(2, 2, 1)
+    SOX_GWCONV(2, 3, 1)
+    SOX_GWCONV(3, 2, 1)
+    SOX_GWCONV(3, 3, 1)
+    SOX_GWCONV(2, 2, 2)
+    SOX_GWCONV(3, 3, 3)
+#undef SOX_GWCONV
+    if (!done) {
+      const int E = gw_conv_width(nk);
+      const long nblk = (NN + E - 1) / E;
+      if (!grid_fits(nblk * cnt, 256))
+        return fail(SOX_ERR_SHAPE, "GW convolution grid too large");
+      hipLaunchKernelGGL(gw_conv_kernel, dim3((unsigned)(nblk * cnt)), dim3(256), 0, s, W, gt, m,
+                         p.d_ktab + 3 * (size_t)nk * nk, nk, E, NN, c, t0, nt, -1.0 / nk, nblk);
+      SOX_HIP(hipGetLastError());
+    }
+    // Y^k[i][Q] = sum_R conj(X^k_iR) M^k[R][Q]
+    a = cg_args<double, double>();
+    a.A = X, a.ldA = N, a.soA = (long)n * N, a.conjA = 1;
+    a.B = m, a.ldB = 1, a.ksB = N, a.soB = cN * N, a.siB = (long)N * N;
+    a.C = y, a.ldc = N, a.soC = cN * n, a.siC = (long)n * N;
+    a.M = n, a.N = N, a.K = N, a.nzi = cnt;
+    if ((st = cg_launch(a, nz, 0, s))) return st;
+    // Sigma^k[i][j] = sum_Q Y^k[i][Q] X^k_jQ
+    a = cg_args<double, double>();
+    a.A = y, a.ldA = N, a.soA = cN * n, a.siA = (long)n * N;
+    a.B = X, a.ldB = N, a.soB = (long)n * N;
+    a.C = Sigma + 2 * (long)t0 * n * n, a.ldc = n, a.soC = (long)nt * n * n, a.siC = (long)n * n;
+    a.M = n, a.N = n, a.K = N, a.nzi = cnt;
+    if ((st = cg_launch(a, nz, 0, s))) return st;
+  }
+  return SOX_OK;
+}
+
 }  // namespace
 
 // -- the no-allocation entry point ---------------------------------------------
@@ -2204,7 +2330,7 @@ sox_status sox_plan_destroy(sox_plan* p) {
 sox_status sox_workspace_size(const sox_plan* plan, int32_t entry, size_t* bytes) {
   if (!plan) return fail(SOX_ERR_INVALID_ARG, "plan is NULL");
   if (!bytes) return fail(SOX_ERR_INVALID_ARG, "bytes is NULL");
-  if (entry < SOX_ENTRY_BARE || entry > SOX_ENTRY_VERTEX)
+  if (entry < SOX_ENTRY_BARE || entry > SOX_ENTRY_GW)
     return fail(SOX_ERR_INVALID_ARG, "unknown entry %d", entry);
   *bytes = workspace_bytes(*plan, entry);
   return SOX_OK;
@@ -2321,6 +2447,20 @@ sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_ta
       default:
         return fail(SOX_ERR_UNSUPPORTED, "unknown precision %d", plan->precision);
     }
+  });
+}
+
+sox_status sox_sigma_gw(sox_plan* plan, const double* X, const double* W_tau, const double* G,
+                        double* Sigma, void* ws, size_t ws_bytes, void* stream) {
+  sox_status st = check_plan(plan);
+  if (st) return st;
+  if (!X || !W_tau || !G || !Sigma) return fail(SOX_ERR_INVALID_ARG, "NULL tensor pointer");
+  if ((st = check_ws(plan, SOX_ENTRY_GW, ws, ws_bytes))) return st;
+  const uintptr_t key[9] = {(uintptr_t)SOX_ENTRY_GW, (uintptr_t)X, (uintptr_t)W_tau,
+                            (uintptr_t)G, (uintptr_t)Sigma, (uintptr_t)ws, (uintptr_t)ws_bytes,
+                            0, 0};
+  return run_maybe_graph(*plan, key, (hipStream_t)stream, [&](hipStream_t s) -> sox_status {
+    return run_gw(*plan, X, W_tau, G, Sigma, ws, s);
   });
 }
 

@@ -56,7 +56,7 @@ int run_case(int n, int N, int nt, int prec, int entry, bool vjp, bool dyn) {
   g_ws_size = wsb + 4096;
   g_ws_base = (char*)aligned_alloc(256, (g_ws_size + 255) & ~size_t(255));
   double* X = dalloc((size_t)n * N);
-  double* U1 = dalloc((size_t)N * N * (entry == 2 ? nt : 1));
+  double* U1 = dalloc((size_t)N * N * (entry == 2 || entry == 4 ? nt : 1));
   double* U2 = dalloc((size_t)N * N);
   double* G = dalloc((size_t)nt * n * n);
   double* S = dalloc((size_t)nt * n * n);
@@ -76,6 +76,7 @@ int run_case(int n, int N, int nt, int prec, int entry, bool vjp, bool dyn) {
   if (!vjp) {
     if (entry == 0) st = sox_sigma_bare(plan, X, U1, G, S, g_ws_base, wsb, nullptr);
     else if (entry == 1) st = sox_sigma_static(plan, X, U1, U2, G, S, g_ws_base, wsb, nullptr);
+    else if (entry == 4) st = sox_sigma_gw(plan, X, U1, G, S, g_ws_base, wsb, nullptr);
     else st = sox_sigma_dynamic(plan, X, U1, U2, G, S, g_ws_base, wsb, nullptr);
   } else {
     st = sox_sigma_vjp(plan, entry, X, U1, entry == 0 ? nullptr : U2, G, R, dG, dX, dU1,
@@ -89,8 +90,8 @@ int run_case(int n, int N, int nt, int prec, int entry, bool vjp, bool dyn) {
 }
 
 // k-point plans: complex128 buffers of their exact sizes; G is built on the
-// mesh, then the bare, static or dynamic entry (0, 1, 2) or the vertex entry
-// with kind entry - 3 (3 .. 7), and the energy run.
+// mesh, then the bare, static or dynamic entry (0, 1, 2), the vertex entry
+// with kind entry - 3 (3 .. 7) or the GW entry (8), and the energy run.
 int run_solid_case(int n, int N, int nt, int prec, int entry, const int mesh[3]) {
   const int nk = mesh[0] * mesh[1] * mesh[2];
   std::vector<double> tau(nt), w(nt, 1.0);
@@ -108,7 +109,9 @@ int run_solid_case(int n, int N, int nt, int prec, int entry, const int mesh[3])
   if (sox_plan_create(&pr, prec, &plan)) { printf("create failed: %s\n", sox_last_error()); return 1; }
   size_t wsb = 0;
   const bool tune = getenv("EMU_AUTOTUNE") != nullptr;
-  const int ent = entry >= 3 ? SOX_ENTRY_VERTEX : entry, kind = entry >= 3 ? entry - 3 : 0;
+  const bool gw = entry == 8;
+  const int ent = gw ? SOX_ENTRY_GW : entry >= 3 ? SOX_ENTRY_VERTEX : entry;
+  const int kind = !gw && entry >= 3 ? entry - 3 : 0;
   if (tune) sox_autotune_workspace_size(plan, ent, kind, &wsb);
   else sox_workspace_size(plan, ent, &wsb);
   g_ws_size = wsb + 4096;
@@ -133,6 +136,7 @@ int run_solid_case(int n, int N, int nt, int prec, int entry, const int mesh[3])
     if (entry == 0) st = sox_sigma_bare(plan, X, U1, G, S, g_ws_base, wsb, nullptr);
     else if (entry == 1) st = sox_sigma_static(plan, X, U1, U2, G, S, g_ws_base, wsb, nullptr);
     else if (entry == 2) st = sox_sigma_dynamic(plan, X, U1, U2, G, S, g_ws_base, wsb, nullptr);
+    else if (gw) st = sox_sigma_gw(plan, X, U1, G, S, g_ws_base, wsb, nullptr);
     else st = sox_sigma_vertex(plan, entry - 3, X, U2, U1, G, S, g_ws_base, wsb, nullptr);
   }
   double E = 0.0;

@@ -31,7 +31,8 @@ def emu(tmp_path_factory):
 
 
 CASES = [
-    # n, N, n_tau, precision(0 fp64 / 1 fp32 / 2 bf16x3), entry(0 bare, 1 static, 2 dynamic), vjp, env budget
+    # n, N, n_tau, precision(0 fp64 / 1 fp32 / 2 bf16x3), entry(0 bare, 1 static, 2 dynamic,
+    # 4 GW), vjp, env budget
     (6, 20, 8, 0, 0, 0, None),
     (13, 70, 5, 1, 1, 0, None),
     (3, 7, 1, 1, 1, 0, None),
@@ -56,6 +57,9 @@ CASES = [
     (6, 20, 8, 2, 0, 0, None),
     (16, 256, 3, 2, 0, 0, None),
     (10, 40, 6, 2, 0, 0, "1"),
+    # GW entry (4): one slab, and two tau slabs under a 1 MB budget
+    (7, 23, 5, 1, 4, 0, None),
+    (20, 150, 8, 2, 4, 0, "1"),
 ]
 
 
@@ -85,6 +89,12 @@ SOLID_CASES = [
     (6, 33, 3, 2, 6, (2, 2, 1), "1"),
     (5, 17, 3, 1, 7, (1, 3, 1), None),
     (4, 20, 2, 2, 5, (2, 1, 1), None),
+    # GW entry (8): LDS element blocks of 64 (3 momenta), 32 (64 momenta) and
+    # 16 (75 momenta), and tau slabs under a 1 MB budget
+    (5, 20, 3, 1, 8, (3, 1, 1), None),
+    (3, 9, 2, 0, 8, (4, 4, 4), None),
+    (2, 5, 1, 1, 8, (5, 5, 3), None),
+    (8, 60, 4, 1, 8, (3, 1, 1), "1"),
 ]
 
 
