@@ -240,6 +240,9 @@ def cpu_oracle_baseline(wl: dict, kind: str, budget_s: float):
 
 
 GW_CALLS = 5
+# the IR grid leg: Lambda = beta * omega_max of the workloads' transform pair
+IR_OMEGA_MAX = 14.0
+IR_EPS = 1e-10
 
 
 def gw_flops(n: int, N: int, nt: int, nk: int = 1) -> float:
@@ -339,6 +342,8 @@ def main() -> int:
                     help="minimum CPU time of the oracle sample")
     ap.add_argument("--no-gw", action="store_true",
                     help="skip the THC-GW direct term (sox_sigma_gw) timed after a dynamic run")
+    ap.add_argument("--no-ir", action="store_true",
+                    help="skip the sweep on the library's IR grid after a dynamic run")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the plan's own launch choices (no sox_autotune before the warmup)")
     ap.add_argument("--no-graph", action="store_true",
@@ -670,6 +675,67 @@ def main() -> int:
         del plan, G, Sg, wsg
         torch.cuda.empty_cache()
 
+    irr = None
+    if kind in ("dynamic", "solid") and not args.no_ir:
+        # the same step on the library's IR grid (sox_ir_grid) for the
+        # workload's beta and omega_max: one warmup and one timed sweep
+        lam = wl["beta"] * IR_OMEGA_MAX
+        note(f"ir: IR grid beta={wl['beta']:g} Lambda={lam:g} eps={IR_EPS:g}")
+        c0 = time.perf_counter()
+        g = B.sox_ir_grid(wl["beta"], lam, IR_EPS)
+        build_s = time.perf_counter() - c0
+        nti = len(g["tau"])
+        wir = synth.workload(args.workload)      # same draws, sampled on the IR nodes
+        wir["tau"] = g["tau"]
+        if solid:
+            Wir = torch.zeros((nk, nti, N, N), dtype=cdt, device=dev)
+            for a, pole, S_k in synth.solid_screening_poles(wir):
+                Wir += t(a * pole)[None, :, None, None] * t(S_k)[:, None]
+        else:
+            Wir = t(sum(a * synth.periodic_bosonic_pole(g["tau"], wl["beta"], w)[:, None, None] * S
+                        for w, a, S in zip(wl["pole_w"], wl["pole_a"], wl["pole_S"])))
+        plan = B.Plan(n, N, g["tau"], g["weights"], wl["beta"], precision=args.precision,
+                      kmesh=wl.get("mesh", (1, 1, 1)), t_fwd=g["T_fwd"], t_bwd=g["T_bwd"])
+        Gi = torch.empty((nk, nti, n, n) if solid else (nti, n, n), dtype=cdt, device=dev)
+        Si = torch.empty_like(Gi)
+        went = "vertex" if solid else "dynamic"
+        wsi = plan.workspace(went)
+        Ei = torch.zeros(2, dtype=torch.float64, device=dev)
+
+        def ir_step():
+            B.sox_build_g_tau(plan, Q, eps, wl["mu"], Gi)
+            if solid:
+                B.sox_sigma_vertex(plan, "sosex_dyn", X, V, Wir, Gi, Si, ws=wsi)
+            else:
+                B.sox_sigma_dynamic(plan, X, Wir, V, Gi, Si, ws=wsi)
+            B.sox_energy_gm_device(plan, Si, Gi, Ei[0])
+
+        ir_step()
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        ir_step()
+        torch.cuda.synchronize()
+        sweep_s = time.perf_counter() - c0
+        # the per-stage breakdown from one more sweep with every stage recorded
+        B.sox_profile_select(plan, None)
+        B.sox_profile_enable(plan, True)
+        B.sox_profile_read(plan, reset=True)
+        ir_step()
+        torch.cuda.synchronize()
+        ir_stages = {k: round(v[0], 2) for k, v in B.sox_profile_read(plan, reset=True).items()
+                     if k != "dropped" and v[1] > 0}
+        B.sox_profile_enable(plan, False)
+        irr = {"beta": wl["beta"], "lambda": lam, "eps": IR_EPS, "n_tau": nti,
+               "n_omega": int(len(g["m"])), "build_s": build_s,
+               "sweep_s": sweep_s, "sweeps_per_s": 1.0 / sweep_s,
+               "vs_main_grid": {"n_tau": nt, "n_omega": n_omega, "sweep_s": sec / args.steps},
+               "energy_gm": float(Ei[0].item()), "stage_ms": ir_stages,
+               "note": ("the timed step of this workload (same inputs, precision and entry) on "
+                        "the IR grid sox_ir_grid builds in host code for the workload's beta "
+                        "and the transform pair's omega_max; untuned plan, one timed sweep")}
+        del plan, Gi, Si, wsi, Wir
+        torch.cuda.empty_cache()
+
     # the oracle runs only in the CPU baseline leg; the last sweep it timed
     # (bare molecules) is also the FP64 reference of max_rel_err
     cpu = ref = None
@@ -688,6 +754,19 @@ def main() -> int:
                                        f"nodes {gnodes}")
     if gw is not None:
         out["gw"] = gw
+    if irr is not None:
+        if not args.no_cpu_baseline:
+            from oracle import ir_grid as oir
+            c0 = time.perf_counter()
+            og = oir.ir_grid(irr["beta"], irr["lambda"], irr["eps"])
+            osec = time.perf_counter() - c0
+            irr["cpu_baseline"] = {"value": 1.0 / osec, "unit": "grids/s", "cores": blas_threads(),
+                                   "kind": "oracle",
+                                   "sample": "one full IR grid construction by the numpy oracle "
+                                             "(same beta, Lambda, eps)"}
+            irr["grid_matches_oracle"] = bool(len(og["tau"]) == irr["n_tau"]
+                                              and len(og["m"]) == irr["n_omega"])
+        out["ir_grid"] = irr
     if cpu is None:
         out["cpu_baseline_note"] = ("not run: " + ("disabled by flag" if args.no_cpu_baseline else
                                     "no bounded oracle sample fits this workload on the host"))

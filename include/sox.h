@@ -257,6 +257,35 @@ sox_status sox_sigma_vertex(sox_plan* plan, int32_t kind, const double* X, const
 sox_status sox_sigma_gw(sox_plan* plan, const double* X, const double* W_tau, const double* G,
                         double* Sigma, void* workspace, size_t workspace_bytes, void* stream);
 
+/* An IR (intermediate representation) imaginary-time grid built in-house,
+ * the sparse grid of the paper's computational details (beta, Lambda = beta
+ * omega_max): the singular value expansion of the logistic kernel
+ * K(x, y) = exp(-Lambda y (x + 1) / 2) / (1 + exp(-Lambda y)) (x = 2 tau /
+ * beta - 1, y = beta omega / Lambda), truncated at s_l >= eps s_0 (L basis
+ * functions); tau nodes at the L roots of the first function left out
+ * (ascending, mirror symmetric: usable as sox_problem.tau); quadrature
+ * weights of int_0^beta for sox_problem.weights; bosonic Matsubara samples
+ * Omega_m = 2 pi m / beta (m = omega_index[q] >= 0: m = 0 and the sign
+ * changes of the first even and odd functions left out); and the transform
+ * pair in the layout of sox_problem.t_fwd / t_bwd: f(i Omega_m) =
+ * sum_j t_fwd[q,j] f(tau_j), f(tau_i) = Re sum_q t_bwd[i,q] f(i Omega_q) for
+ * a function real in imaginary time.  Host code, no device work; float64.
+ *   beta > 0; 1 <= lambda <= 1e8; 1e-12 <= eps <= 1e-2 (float64 resolves
+ *   the basis there);
+ *   capacity: the length the caller's arrays allow: tau, weights,
+ *   singular_values (s_l / s_0) hold L values, omega_index n_omega, t_fwd
+ *   2 n_omega L doubles (complex interleaved [n_omega][L]) and t_bwd
+ *   2 L n_omega ([L][n_omega]): allocate capacity, capacity, capacity and
+ *   2 capacity^2 doubles.
+ * *n_tau = L and *n_omega are written on success and when capacity is too
+ * small (SOX_ERR_SHAPE, nothing else written: call again with a larger
+ * capacity).  SOX_ERR_INVALID_ARG for parameters out of range or NULL
+ * arrays; SOX_ERR_UNSUPPORTED when the root count of the first omitted
+ * function shows the basis unresolved. */
+sox_status sox_ir_grid(double beta, double lambda, double eps, int32_t capacity, int32_t* n_tau,
+                       int32_t* n_omega, double* tau, double* weights, int64_t* omega_index,
+                       double* t_fwd, double* t_bwd, double* singular_values);
+
 /* Vector-Jacobian product of L = sum(Sigma * R) for the entry `entry`:
  *   R [n_tau,n,n] cotangent;  dG [n_tau,n,n], dX [n,N], dU1, dU2 outputs.
  * For SOX_ENTRY_BARE, U1 = U2 = V is passed as U1 (U2 ignored) and dU1

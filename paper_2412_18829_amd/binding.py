@@ -33,7 +33,7 @@ EXPORTED = (
     "sox_energy_gm", "sox_energy_gm_device", "sox_sync", "sox_last_error", "sox_abi_version", "sox_profile_enable",
     "sox_profile_read", "sox_profile_select", "sox_plan_set_graph", "sox_plan_describe",
     "sox_sigma_bare_noalloc", "sox_sigma_vertex", "sox_autotune", "sox_autotune_workspace_size",
-    "sox_sigma_gw",
+    "sox_sigma_gw", "sox_ir_grid",
 )
 STAGES = ("gbuild", "utensor", "project", "astep", "fused", "back", "energy", "gg_ft", "wgemm",
           "ift", "split", "vjp", "kbc", "kd", "gw")
@@ -79,6 +79,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.sox_autotune_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
     L.sox_sigma_dynamic.argtypes = [vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_sigma_gw.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
+    L.sox_ir_grid.argtypes = [dp, dp, dp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, vp,
+                              vp, vp, vp, vp]
     L.sox_sigma_vjp.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_build_g_tau.argtypes = [vp, vp, vp, dp, vp, vp]
     L.sox_energy_gm.argtypes = [vp, vp, vp, ctypes.POINTER(dp), vp]
@@ -290,6 +292,27 @@ def sox_sigma_gw(plan: Plan, X, W_tau, G, Sigma, ws=None, stream=None):
                                t(G, (nt, n, n), "G"), t(Sigma, (nt, n, n), "Sigma"), w, wb,
                                _stream(stream)), "sox_sigma_gw")
     return Sigma
+
+
+def sox_ir_grid(beta: float, lam: float, eps: float, capacity: int = 512) -> dict:
+    """The library's IR grid: tau nodes, weights, Matsubara indices m, the
+    transform pair T_fwd [n_omega, n_tau], T_bwd [n_tau, n_omega] (complex)
+    and the singular values s_l / s_0 (host arrays)."""
+    nt, nw = ctypes.c_int32(), ctypes.c_int32()
+    tau = np.zeros(capacity)
+    w = np.zeros(capacity)
+    m = np.zeros(capacity, dtype=np.int64)
+    tf = np.zeros(2 * capacity * capacity)
+    tb = np.zeros(2 * capacity * capacity)
+    sv = np.zeros(capacity)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _check(load().sox_ir_grid(float(beta), float(lam), float(eps), int(capacity), ctypes.byref(nt),
+                              ctypes.byref(nw), p(tau), p(w), p(m), p(tf), p(tb), p(sv)),
+           "sox_ir_grid")
+    L, n = nt.value, nw.value
+    return dict(tau=tau[:L].copy(), weights=w[:L].copy(), m=m[:n].copy(),
+                T_fwd=tf[:2 * n * L].view(np.complex128).reshape(n, L).copy(),
+                T_bwd=tb[:2 * L * n].view(np.complex128).reshape(L, n).copy(), s=sv[:L].copy())
 
 
 def sox_autotune(plan: Plan, entry, X, U1, U2, G, Sigma, kind=0, ws=None, stream=None):

@@ -28,6 +28,7 @@
 #include "sox_vjp_steps.hpp"
 #include "sox_complex.hpp"
 #include "sox_gw.hpp"
+#include "sox_ir.hpp"
 
 using namespace sox;
 
@@ -2448,6 +2449,46 @@ sox_status sox_sigma_dynamic(sox_plan* plan, const double* X, const double* W_ta
         return fail(SOX_ERR_UNSUPPORTED, "unknown precision %d", plan->precision);
     }
   });
+}
+
+sox_status sox_ir_grid(double beta, double lambda, double eps, int32_t capacity, int32_t* n_tau,
+                       int32_t* n_omega, double* tau, double* weights, int64_t* omega_index,
+                       double* t_fwd, double* t_bwd, double* singular_values) {
+  if (!n_tau || !n_omega) return fail(SOX_ERR_INVALID_ARG, "n_tau or n_omega is NULL");
+  *n_tau = 0;
+  *n_omega = 0;
+  if (!(beta > 0.0) || !std::isfinite(beta))
+    return fail(SOX_ERR_INVALID_ARG, "beta must be positive and finite");
+  if (!(lambda >= 1.0) || !(lambda <= 1e8))
+    return fail(SOX_ERR_INVALID_ARG, "lambda %g outside [1, 1e8]", lambda);
+  if (!(eps >= 1e-12) || !(eps <= 1e-2))
+    return fail(SOX_ERR_INVALID_ARG, "eps %g outside [1e-12, 1e-2]", eps);
+  if (capacity < 0) return fail(SOX_ERR_INVALID_ARG, "negative capacity");
+  sox_ir::Grid g = sox_ir::build(beta, lambda, eps);
+  if (!g.error.empty()) return fail(SOX_ERR_UNSUPPORTED, "IR grid: %s", g.error.c_str());
+  const int L = g.L, nm = (int)g.m.size();
+  *n_tau = L;
+  *n_omega = nm;
+  if (capacity < std::max(L, nm))
+    return fail(SOX_ERR_SHAPE, "capacity %d below the grid's %d tau nodes and %d frequencies",
+                capacity, L, nm);
+  if (!tau || !weights || !omega_index || !t_fwd || !t_bwd || !singular_values)
+    return fail(SOX_ERR_INVALID_ARG, "NULL output array");
+  for (int i = 0; i < L; ++i) {
+    tau[i] = g.tau[i];
+    weights[i] = g.weights[i];
+    singular_values[i] = g.sv[i];
+  }
+  for (int q = 0; q < nm; ++q) omega_index[q] = g.m[q];
+  for (size_t i = 0; i < g.t_fwd.size(); ++i) {
+    t_fwd[2 * i] = g.t_fwd[i].real();
+    t_fwd[2 * i + 1] = g.t_fwd[i].imag();
+  }
+  for (size_t i = 0; i < g.t_bwd.size(); ++i) {
+    t_bwd[2 * i] = g.t_bwd[i].real();
+    t_bwd[2 * i + 1] = g.t_bwd[i].imag();
+  }
+  return SOX_OK;
 }
 
 sox_status sox_sigma_gw(sox_plan* plan, const double* X, const double* W_tau, const double* G,

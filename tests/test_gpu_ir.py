@@ -1,0 +1,73 @@
+"""The dynamic SOX entry on the library's IR grid (sox_ir_grid) against the
+oracle on the oracle's own IR grid (oracle/ir_grid.py).
+
+Molecule n = 12, N = 60, beta = 50, Lambda = 500 (omega_max = 10), eps = 1e-8:
+38 tau nodes and 30 bosonic frequencies.  The GPU plan takes the library's
+grid (tau, weights, transform pair); G(tau) is built on it by the library
+and W_d(tau) is the eight-pole workload interaction sampled on its nodes.
+The oracle evaluates the eq:GG chain on its own grid with its own G and the
+same poles.  The two grids agree to about 1e-14 / eps = 1e-6 relative at
+most (measured 6e-9: tests/test_ir_grid.py), so the FP64 bound is 1e-7; FP32
+1e-6; BF16x3 1e-4 (the stated split-precision bound).  The GM energies of
+both agree to the same bound.
+"""
+import numpy as np
+import pytest
+
+from oracle import ir_grid as ir
+from oracle import sox_mol as om
+from paper_2412_18829_amd import synth
+from tests.gpu_util import dev, have_gpu, host, log, rel_err
+
+pytestmark = pytest.mark.gpu
+
+BETA, LAM, EPS = 50.0, 500.0, 1e-8
+TOL = {"fp64": 1e-7, "fp32": 1e-6, "bf16x3": 1e-4}
+
+
+@pytest.fixture(scope="module")
+def B():
+    if not have_gpu():
+        pytest.skip("no GPU")
+    from paper_2412_18829_amd import binding
+    binding.load()
+    return binding
+
+
+def _w_on(wl, tau):
+    return sum(a * synth.periodic_bosonic_pole(tau, BETA, w)[:, None, None] * S[None]
+               for w, a, S in zip(wl["pole_w"], wl["pole_a"], wl["pole_S"]))
+
+
+@pytest.fixture(scope="module")
+def case():
+    og = ir.ir_grid(BETA, LAM, EPS)
+    wl = synth.small_molecule(12, 60, len(og["tau"]), BETA, seed=951)
+    wl["tau"] = og["tau"]
+    synth.add_dynamic_screening(wl)     # draws the poles; W on the oracle grid
+    G = om.g_tau(wl["eps"], wl["Q"], wl["mu"], BETA, og["tau"])
+    ref = om.sigma_dynamic_thc(wl["X"], wl["W_tau"], wl["V"], G, G[::-1], og["T_fwd"],
+                               og["T_bwd"])
+    e_ref = om.energy_gm(ref, G[::-1], og["weights"])
+    return wl, ref, e_ref
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16x3"])
+def test_dynamic_entry_on_ir_grid(B, case, precision):
+    import torch
+    wl, ref, e_ref = case
+    g = B.sox_ir_grid(BETA, LAM, EPS)
+    n, N, nt = wl["n"], wl["N"], len(g["tau"])
+    log(f"dynamic SOX on the IR grid (L={nt}, n_omega={len(g['m'])}) {precision}")
+    plan = B.Plan(n, N, g["tau"], g["weights"], BETA, precision, t_fwd=g["T_fwd"],
+                  t_bwd=g["T_bwd"])
+    G = torch.empty((nt, n, n), dtype=torch.float64, device="cuda")
+    B.sox_build_g_tau(plan, dev(wl["Q"]), dev(wl["eps"]), wl["mu"], G)
+    S = torch.empty_like(G)
+    B.sox_sigma_dynamic(plan, dev(wl["X"]), dev(_w_on(wl, g["tau"])), dev(wl["V"]), G, S)
+    e = B.sox_energy_gm(plan, S, G)
+    torch.cuda.synchronize()
+    err = rel_err(host(S), ref)
+    log(f"  rel err {err:.2e}, energy {e:.12e} vs {e_ref:.12e}")
+    assert err <= TOL[precision]
+    assert abs(e - e_ref) <= TOL[precision] * abs(e_ref)
