@@ -39,8 +39,10 @@ Modules:
   sox_gw     the THC-GW direct term Sigma^GW = -G W_d of fig:diag (molecules
              and k-point meshes): 4-index brute force and THC chain.
   ir_grid    an in-house IR grid (singular value expansion of the logistic
-             kernel): tau sampling points, quadrature weights and the
-             bosonic transform pair.
+             kernel): tau sampling points, quadrature weights, the bosonic
+             and the fermionic transform pairs.
+  scf        a minimal self-consistent Dyson loop (Sigma^HF + Sigma^GW with a
+             fixed W_d, optionally SOX(V,V); mu search; E_inf, E_dyn).
   sox_vertex the composite vertex self-energies (SOSEX, 2SOSEX, G3W2stat of
              fig:diag) as sums of SOX terms; SOX(V, W_d) with the dynamic
              interaction on line 2 has its own brute force in sox_mol /

@@ -36,6 +36,12 @@ builds it from that definition with numpy's SVD as the one library step:
    (f(-i Omega) = conj f(i Omega)): f(tau_i) = Re sum_m T_bwd[i][m] f(i Omega_m).
 9. Quadrature weights on the sampling times: w = U_s^{-T} I, I_l =
    int_0^beta U_l(tau) dtau.
+10. Fermionic pair (ir_fermion): the same basis and sampling times, odd
+   frequencies nu_n = (2n + 1) pi / beta (m = n + 1/2 in step 6), n = 0 and
+   the sign changes of Im U^ (first omitted even function: a function even
+   about beta / 2 has an imaginary fermionic transform) and of Re U^ (first
+   omitted odd function); T_fwd, T_bwd as in step 8, and the row t_beta with
+   f(beta^-) = sum_i t_beta[i] f(tau_i) (the basis evaluated at x = 1).
 
 Readings (also in the design notes): the paper gives beta, Lambda and the
 number of tau points but not eps, the discretisation or the Matsubara
@@ -203,3 +209,34 @@ def ir_grid(beta: float, lam: float, eps: float) -> dict:
     weights = np.linalg.solve(Us.T, I)
     return dict(tau=tau, weights=weights, m=sel, T_fwd=T_fwd, T_bwd=T_bwd,
                 s=s[:L] / s[0], L=L, Us=Us, Uhat=Uh)
+
+
+def ir_fermion(beta: float, lam: float, eps: float) -> dict:
+    """Fermionic transform pair on the IR sampling times: n (nu_n = (2n+1)
+    pi / beta), T_fwd [n_nu, n_tau], T_bwd [n_tau, n_nu] (f(tau_i) = Re
+    sum_n T_bwd[i][n] f(i nu_n) for a function real in imaginary time) and
+    t_beta [n_tau] (f(beta^-) = t_beta . f(tau))."""
+    fs, bx, x, wx = sve(lam)
+    s = np.array([f[0] for f in fs])
+    L = int(np.sum(s >= eps * s[0]))
+    cs = [legendre_coeffs(f[2]) for f in fs[:L]]
+    pars = [f[1] for f in fs[:L]]
+    xr = roots(legendre_coeffs(fs[L][2]), fs[L][1], bx)
+    if len(xr) != L:
+        raise RuntimeError(f"u_L has {len(xr)} roots, expected {L}")
+    tau = beta * (xr + 1) / 2
+    Us = np.stack([evaluate(cs[l], pars[l], bx, xr) for l in range(L)], axis=1) * np.sqrt(2 / beta)
+    le = next(l for l in range(L, len(fs)) if fs[l][1] > 0)
+    lo = next(l for l in range(L, len(fs)) if fs[l][1] < 0)
+    ns = np.arange(0, int(4 * lam) + 1)
+    ge = matsubara(legendre_coeffs(fs[le][2]), 1, bx, beta, ns + 0.5).imag
+    go = matsubara(legendre_coeffs(fs[lo][2]), -1, bx, beta, ns + 0.5).real
+    sel = np.unique(np.concatenate([[0], _sign_changes(ge), _sign_changes(go)]))
+    Uh = np.stack([matsubara(cs[l], pars[l], bx, beta, sel + 0.5) for l in range(L)], axis=1)
+    Uinv = np.linalg.inv(Us)
+    T_fwd = Uh @ Uinv
+    A = Us @ np.linalg.pinv(np.concatenate([Uh.real, Uh.imag], axis=0))
+    nm = len(sel)
+    T_bwd = A[:, :nm] - 1j * A[:, nm:]
+    ub = np.array([evaluate(cs[l], pars[l], bx, 1.0)[0] for l in range(L)]) * np.sqrt(2 / beta)
+    return dict(tau=tau, n=sel, T_fwd=T_fwd, T_bwd=T_bwd, t_beta=ub @ Uinv, L=L)
