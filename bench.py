@@ -243,6 +243,8 @@ GW_CALLS = 5
 # the IR grid leg: Lambda = beta * omega_max of the workloads' transform pair
 IR_OMEGA_MAX = 14.0
 IR_EPS = 1e-10
+# the self-consistent loop leg: one spin channel of a synthetic molecule
+SCF_N, SCF_NTHC, SCF_BETA, SCF_LAMBDA, SCF_SEED, SCF_TOL = 64, 384, 50.0, 500.0, 7, 1e-8
 
 
 def gw_flops(n: int, N: int, nt: int, nk: int = 1) -> float:
@@ -344,6 +346,8 @@ def main() -> int:
                     help="skip the THC-GW direct term (sox_sigma_gw) timed after a dynamic run")
     ap.add_argument("--no-ir", action="store_true",
                     help="skip the sweep on the library's IR grid after a dynamic run")
+    ap.add_argument("--no-scf", action="store_true",
+                    help="skip the self-consistent loop (sox_scf) on its own molecular system")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the plan's own launch choices (no sox_autotune before the warmup)")
     ap.add_argument("--no-graph", action="store_true",
@@ -736,6 +740,37 @@ def main() -> int:
         del plan, Gi, Si, wsi, Wir
         torch.cuda.empty_cache()
 
+    scf = None
+    if not args.no_scf:
+        # the minimal self-consistent loop on its own system (every workload):
+        # one spin channel, n = 64, N = 384, GW with a fixed 8-pole W_d, IR grid
+        note("scf: self-consistent loop")
+        fg = B.sox_ir_grid_fermion(SCF_BETA, SCF_LAMBDA, IR_EPS)
+        bg = B.sox_ir_grid(SCF_BETA, SCF_LAMBDA, IR_EPS)
+        swl = synth.small_molecule(SCF_N, SCF_NTHC, len(fg["tau"]), SCF_BETA, seed=SCF_SEED)
+        swl["tau"] = fg["tau"]
+        synth.add_dynamic_screening(swl)
+        hs = swl["Q"] @ np.diag(swl["eps"]) @ swl["Q"].T
+        f64 = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+        plan = B.Plan(SCF_N, SCF_NTHC, fg["tau"], bg["weights"], SCF_BETA, precision="fp64")
+        Gs = torch.empty((len(fg["tau"]), SCF_N, SCF_N), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        c0 = time.perf_counter()
+        so = B.sox_scf(plan, fg, f64(swl["X"]), f64(swl["V"]), f64(swl["W_tau"]), f64(hs),
+                       SCF_N / 2, Gs, terms=("gw",), tol=SCF_TOL, max_iter=100)
+        torch.cuda.synchronize()
+        scf_s = time.perf_counter() - c0
+        scf = {"entry": "sox_scf (terms: GW with a fixed W_d)", "n_orb": SCF_N, "n_thc": SCF_NTHC,
+               "beta": SCF_BETA, "lambda": SCF_LAMBDA, "eps": IR_EPS, "n_tau": len(fg["tau"]),
+               "n_nu": int(len(fg["n"])), "n_elec": SCF_N / 2, "tol": SCF_TOL,
+               "seconds": scf_s, "iterations": so["iterations"],
+               "ms_per_iteration": 1e3 * scf_s / max(so["iterations"], 1), "mu": so["mu"],
+               "e_inf": so["e_inf"], "e_dyn": so["e_dyn"], "delta": so["delta"],
+               "data": "synthetic one-spin-channel molecule, seed %d" % SCF_SEED}
+        scf_G = Gs.cpu().numpy()
+        del plan, Gs
+        torch.cuda.empty_cache()
+
     # the oracle runs only in the CPU baseline leg; the last sweep it timed
     # (bare molecules) is also the FP64 reference of max_rel_err
     cpu = ref = None
@@ -754,6 +789,24 @@ def main() -> int:
                                        f"nodes {gnodes}")
     if gw is not None:
         out["gw"] = gw
+    if scf is not None:
+        if not args.no_cpu_baseline:
+            from oracle import ir_grid as oir
+            from oracle import scf as oscf
+            c0 = time.perf_counter()
+            ofg, obg = oir.ir_fermion(SCF_BETA, SCF_LAMBDA, IR_EPS), oir.ir_grid(SCF_BETA, SCF_LAMBDA, IR_EPS)
+            ref = oscf.scf(swl["X"], swl["V"], swl["W_tau"], hs, SCF_N / 2, SCF_BETA, ofg,
+                           obg["weights"], terms=("gw",), tol=SCF_TOL, max_iter=100)
+            osec = time.perf_counter() - c0
+            scf["cpu_baseline"] = {"value": 1.0 / osec, "unit": "loops/s", "cores": blas_threads(),
+                                   "kind": "oracle",
+                                   "sample": (f"the whole loop by the numpy oracle on its own IR "
+                                              f"grid ({ref['iterations']} iterations, {osec:.1f} s)")}
+            scf["max_abs_dG_vs_oracle"] = float(np.abs(scf_G - ref["G"]).max())
+            scf["e_inf_rel_err"] = abs(scf["e_inf"] - ref["e_inf"]) / abs(ref["e_inf"])
+            scf["e_dyn_rel_err"] = abs(scf["e_dyn"] - ref["e_dyn"]) / abs(ref["e_dyn"])
+            scf["mu_abs_err"] = abs(scf["mu"] - ref["mu"])
+        out["scf"] = scf
     if irr is not None:
         if not args.no_cpu_baseline:
             from oracle import ir_grid as oir

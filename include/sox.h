@@ -286,6 +286,66 @@ sox_status sox_ir_grid(double beta, double lambda, double eps, int32_t capacity,
                        int32_t* n_omega, double* tau, double* weights, int64_t* omega_index,
                        double* t_fwd, double* t_bwd, double* singular_values);
 
+/* The fermionic counterpart of sox_ir_grid on the same basis and tau nodes:
+ * odd Matsubara samples nu_n = (2n + 1) pi / beta (n = nu_index[q] >= 0: n = 0
+ * and the sign changes of the first omitted even function's Im U^ and odd
+ * function's Re U^), the pair f(i nu_n) = sum_j t_fwd[q,j] f(tau_j),
+ * f(tau_i) = Re sum_q t_bwd[i,q] f(i nu_q) (complex interleaved, layouts as
+ * sox_ir_grid) and t_beta [n_tau] with f(beta^-) = sum_i t_beta[i] f(tau_i).
+ * Arguments, capacity protocol and errors as sox_ir_grid.  Host code. */
+sox_status sox_ir_grid_fermion(double beta, double lambda, double eps, int32_t capacity,
+                               int32_t* n_tau, int32_t* n_nu, double* tau, int64_t* nu_index,
+                               double* t_fwd, double* t_bwd, double* t_beta);
+
+/* A minimal self-consistent Dyson loop (section "Definitions": eq:Dyson,
+ * eq:G0 with an orthonormal basis S = I, the chemical potential updated
+ * every iteration for the target electron count, energies eq:E1b and
+ * eq:E2b) for one spin channel of a molecule, float64:
+ *   Sigma[G] = Sigma^HF[gamma] + Sigma^dyn[G](tau),
+ *   Sigma^HF_ij = sum_kl [(ij|kl) gamma_lk - (ik|lj) gamma_kl] with V,
+ *   Sigma^dyn = the THC-GW direct term with the fixed W_tau (terms bit 0; a
+ *   stand-in for the screened interaction, not rebuilt from G) plus SOX(V,
+ *   V) (bit 1, in the plan's precision);
+ *   gamma_pq = -G_qp(beta^-); each iteration transforms Sigma^dyn to the
+ *   fermionic samples, solves G(i nu) = [(i nu + mu) I - h - Sigma^HF -
+ *   Sigma^dyn(i nu)]^-1 for the mu that holds n_elec (100 bisection
+ *   halvings of N(mu) = -Tr G(beta^-)), returns to tau, and mixes
+ *   G <- (1 - mix) G + mix G_new until max |G_new - G| <= tol or max_iter.
+ *   E_inf = sum_pq (h + Sigma^HF / 2)_pq gamma_pq; E_dyn = -1/2 sum_j w_j
+ *   Tr[Sigma^dyn(tau_j) G(beta - tau_j)] (the plan's weights).
+ * The plan: a molecular plan on the IR tau grid of sox_ir_grid_fermion
+ * (with its sox_ir_grid weights), n_orb <= 1024.  Device inputs X [n,N], V
+ * [N,N], W_tau [n_tau,N,N] (may be NULL without bit 0), h [n,n] (the one-body
+ * H0 of eq:G0), h_start [n,n] or NULL (the H0 of the starting G0; default
+ * h); output G [n_tau,n,n] device.  The host arrays of the fermionic pair
+ * are copied at the call.  Workspace: sox_scf_workspace_size.  Errors:
+ * SOX_ERR_UNSUPPORTED for k-point plans or n_orb > 1024, SOX_ERR_INVALID_ARG
+ * for parameters out of range.  The call synchronises the stream (the loop
+ * control runs on the host). */
+typedef struct {
+  double n_elec;        /* target electrons of the channel, 0 < n_elec < n_orb */
+  double mix;           /* 0 < mix <= 1 */
+  double tol;           /* > 0: stop at max |G_new - G| <= tol */
+  int32_t max_iter;     /* >= 1 */
+  int32_t terms;        /* bit 0: GW with W_tau; bit 1: SOX(V, V)          */
+  int32_t n_nu;         /* fermionic samples of the pair                  */
+  const double* nu;     /* HOST [n_nu] nu_n = (2n + 1) pi / beta           */
+  const double* t_fwd;  /* HOST complex [n_nu][n_tau]                      */
+  const double* t_bwd;  /* HOST complex [n_tau][n_nu]                      */
+  const double* t_beta; /* HOST [n_tau]                                    */
+} sox_scf_params;
+
+typedef struct {
+  double mu, e_inf, e_dyn, delta;  /* converged mu, eq:E1b, eq:E2b, last max |dG| */
+  int32_t iterations;
+} sox_scf_result;
+
+sox_status sox_scf_workspace_size(const sox_plan* plan, int32_t n_nu, int32_t terms,
+                                  size_t* bytes);
+sox_status sox_scf(sox_plan* plan, const sox_scf_params* params, const double* X, const double* V,
+                   const double* W_tau, const double* h, const double* h_start, double* G,
+                   sox_scf_result* result, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Vector-Jacobian product of L = sum(Sigma * R) for the entry `entry`:
  *   R [n_tau,n,n] cotangent;  dG [n_tau,n,n], dX [n,N], dU1, dU2 outputs.
  * For SOX_ENTRY_BARE, U1 = U2 = V is passed as U1 (U2 ignored) and dU1

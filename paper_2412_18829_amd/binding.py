@@ -33,7 +33,7 @@ EXPORTED = (
     "sox_energy_gm", "sox_energy_gm_device", "sox_sync", "sox_last_error", "sox_abi_version", "sox_profile_enable",
     "sox_profile_read", "sox_profile_select", "sox_plan_set_graph", "sox_plan_describe",
     "sox_sigma_bare_noalloc", "sox_sigma_vertex", "sox_autotune", "sox_autotune_workspace_size",
-    "sox_sigma_gw", "sox_ir_grid",
+    "sox_sigma_gw", "sox_ir_grid", "sox_ir_grid_fermion", "sox_scf_workspace_size", "sox_scf",
 )
 STAGES = ("gbuild", "utensor", "project", "astep", "fused", "back", "energy", "gg_ft", "wgemm",
           "ift", "split", "vjp", "kbc", "kd", "gw")
@@ -53,6 +53,20 @@ class sox_problem(ctypes.Structure):
         ("n_omega", ctypes.c_int32),
         ("t_fwd", ctypes.POINTER(ctypes.c_double)), ("t_bwd", ctypes.POINTER(ctypes.c_double)),
     ]
+
+
+class sox_scf_params(ctypes.Structure):
+    _fields_ = [
+        ("n_elec", ctypes.c_double), ("mix", ctypes.c_double), ("tol", ctypes.c_double),
+        ("max_iter", ctypes.c_int32), ("terms", ctypes.c_int32), ("n_nu", ctypes.c_int32),
+        ("nu", ctypes.POINTER(ctypes.c_double)), ("t_fwd", ctypes.POINTER(ctypes.c_double)),
+        ("t_bwd", ctypes.POINTER(ctypes.c_double)), ("t_beta", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class sox_scf_result(ctypes.Structure):
+    _fields_ = [("mu", ctypes.c_double), ("e_inf", ctypes.c_double), ("e_dyn", ctypes.c_double),
+                ("delta", ctypes.c_double), ("iterations", ctypes.c_int32)]
 
 
 _lib = None
@@ -81,6 +95,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     L.sox_sigma_gw.argtypes = [vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_ir_grid.argtypes = [dp, dp, dp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32), vp, vp,
                               vp, vp, vp, vp]
+    L.sox_ir_grid_fermion.argtypes = [dp, dp, dp, i32, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                      vp, vp, vp, vp, vp]
+    L.sox_scf_workspace_size.argtypes = [vp, i32, i32, ctypes.POINTER(sz)]
+    L.sox_scf.argtypes = [vp, ctypes.POINTER(sox_scf_params), vp, vp, vp, vp, vp, vp,
+                          ctypes.POINTER(sox_scf_result), vp, sz, vp]
     L.sox_sigma_vjp.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
     L.sox_build_g_tau.argtypes = [vp, vp, vp, dp, vp, vp]
     L.sox_energy_gm.argtypes = [vp, vp, vp, ctypes.POINTER(dp), vp]
@@ -313,6 +332,61 @@ def sox_ir_grid(beta: float, lam: float, eps: float, capacity: int = 512) -> dic
     return dict(tau=tau[:L].copy(), weights=w[:L].copy(), m=m[:n].copy(),
                 T_fwd=tf[:2 * n * L].view(np.complex128).reshape(n, L).copy(),
                 T_bwd=tb[:2 * L * n].view(np.complex128).reshape(L, n).copy(), s=sv[:L].copy())
+
+
+def sox_ir_grid_fermion(beta: float, lam: float, eps: float, capacity: int = 512) -> dict:
+    """The fermionic pair on the library's IR grid: tau, n (nu_n = (2n+1) pi /
+    beta), T_fwd [n_nu, n_tau], T_bwd [n_tau, n_nu], t_beta [n_tau]."""
+    nt, nw = ctypes.c_int32(), ctypes.c_int32()
+    tau = np.zeros(capacity)
+    m = np.zeros(capacity, dtype=np.int64)
+    tf = np.zeros(2 * capacity * capacity)
+    tb = np.zeros(2 * capacity * capacity)
+    tbeta = np.zeros(capacity)
+    p = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+    _check(load().sox_ir_grid_fermion(float(beta), float(lam), float(eps), int(capacity),
+                                      ctypes.byref(nt), ctypes.byref(nw), p(tau), p(m), p(tf), p(tb),
+                                      p(tbeta)), "sox_ir_grid_fermion")
+    L, n = nt.value, nw.value
+    return dict(tau=tau[:L].copy(), n=m[:n].copy(),
+                T_fwd=tf[:2 * n * L].view(np.complex128).reshape(n, L).copy(),
+                T_bwd=tb[:2 * L * n].view(np.complex128).reshape(L, n).copy(),
+                t_beta=tbeta[:L].copy())
+
+
+SCF_TERMS = {"gw": 1, "sox": 2}
+
+
+def sox_scf(plan: Plan, fgrid: dict, X, V, W_tau, h, n_elec: float, G, terms=("gw",),
+            mix: float = 0.5, tol: float = 1e-8, max_iter: int = 100, h_start=None, stream=None):
+    """The minimal self-consistent loop on `plan` (its tau grid must be
+    fgrid's).  G [n_tau, n, n] receives the converged G(tau); returns mu,
+    e_inf, e_dyn, delta and iterations."""
+    import torch
+    n, N, nt = plan.n, plan.N, plan.n_tau
+    bits = sum(SCF_TERMS[t] for t in terms)
+    nu = np.ascontiguousarray((2 * fgrid["n"] + 1) * np.pi / plan.beta, dtype=np.float64)
+    tf = np.ascontiguousarray(fgrid["T_fwd"], dtype=np.complex128)
+    tb = np.ascontiguousarray(fgrid["T_bwd"], dtype=np.complex128)
+    tbeta = np.ascontiguousarray(fgrid["t_beta"], dtype=np.float64)
+    dptr = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    prm = sox_scf_params(float(n_elec), float(mix), float(tol), int(max_iter), int(bits),
+                         int(len(nu)), dptr(nu), dptr(tf), dptr(tb), dptr(tbeta))
+    nbytes = ctypes.c_size_t()
+    _check(load().sox_scf_workspace_size(plan.handle, len(nu), bits, ctypes.byref(nbytes)),
+           "sox_scf_workspace_size")
+    ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device="cuda")
+    wp = (ws.data_ptr() + 255) & ~255
+    res = sox_scf_result()
+    _check(load().sox_scf(plan.handle, ctypes.byref(prm), _f64(X, (n, N), "X"),
+                          _f64(V, (N, N), "V"),
+                          _f64(W_tau, (nt, N, N), "W_tau") if W_tau is not None else None,
+                          _f64(h, (n, n), "h"),
+                          _f64(h_start, (n, n), "h_start") if h_start is not None else None,
+                          _f64(G, (nt, n, n), "G"), ctypes.byref(res), wp,
+                          ws.numel() - (wp - ws.data_ptr()), _stream(stream)), "sox_scf")
+    return dict(mu=res.mu, e_inf=res.e_inf, e_dyn=res.e_dyn, delta=res.delta,
+                iterations=res.iterations)
 
 
 def sox_autotune(plan: Plan, entry, X, U1, U2, G, Sigma, kind=0, ws=None, stream=None):

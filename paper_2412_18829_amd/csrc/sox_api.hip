@@ -29,6 +29,7 @@
 #include "sox_complex.hpp"
 #include "sox_gw.hpp"
 #include "sox_ir.hpp"
+#include "sox_scf.hpp"
 
 using namespace sox;
 
@@ -1988,6 +1989,22 @@ int gw_slab(const sox_plan& p) {
 
 size_t gw_workspace_bytes(const sox_plan& p) { return gw_layout_for(p, gw_slab(p)).total; }
 
+// the molecular chain for nodes t0 .. t0 + cnt - 1 of G and W (one slab)
+sox_status gw_mol_slab(const sox_plan& p, const double* X, const double* W, const double* G,
+                       double* Sigma, int t0, int cnt, double* p1, double* m, double* y,
+                       hipStream_t s) {
+  const int n = p.n, N = p.N;
+  ProjP1Prob<double> pr1{X, G, p1, n, N, n, N, t0, N, n, n};
+  SOX_HIP((launch_gemm<ProjP1Prob<double>, double, 2, 2, 2, 2>(pr1, cnt, s)));
+  GwHadProb had{p1, X, W, m, n, N, t0, N, N, n};
+  SOX_HIP((launch_gemm<GwHadProb, double, 2, 2, 2, 2>(had, cnt, s)));
+  GwLeftProb left{X, m, y, n, N, n, N, N};
+  SOX_HIP((launch_gemm<GwLeftProb, double, 2, 2, 2, 2>(left, cnt, s)));
+  GwRightProb right{y, X, Sigma, n, N, t0, n, n, N};
+  SOX_HIP((launch_gemm<GwRightProb, double, 2, 2, 2, 2>(right, cnt, s)));
+  return SOX_OK;
+}
+
 sox_status run_gw(sox_plan& p, const double* X, const double* W, const double* G, double* Sigma,
                   void* ws, hipStream_t s) {
   const int c = gw_slab(p);
@@ -2002,14 +2019,8 @@ sox_status run_gw(sox_plan& p, const double* X, const double* W, const double* G
   for (int t0 = 0; t0 < nt; t0 += c) {
     const int cnt = std::min(c, nt - t0);
     if (nk == 1) {
-      ProjP1Prob<double> pr1{X, G, p1, n, N, n, N, t0, N, n, n};
-      SOX_HIP((launch_gemm<ProjP1Prob<double>, double, 2, 2, 2, 2>(pr1, cnt, s)));
-      GwHadProb had{p1, X, W, m, n, N, t0, N, N, n};
-      SOX_HIP((launch_gemm<GwHadProb, double, 2, 2, 2, 2>(had, cnt, s)));
-      GwLeftProb left{X, m, y, n, N, n, N, N};
-      SOX_HIP((launch_gemm<GwLeftProb, double, 2, 2, 2, 2>(left, cnt, s)));
-      GwRightProb right{y, X, Sigma, n, N, t0, n, n, N};
-      SOX_HIP((launch_gemm<GwRightProb, double, 2, 2, 2, 2>(right, cnt, s)));
+      sox_status st = gw_mol_slab(p, X, W, G, Sigma, t0, cnt, p1, m, y, s);
+      if (st) return st;
       continue;
     }
     const int nz = nk * cnt;
@@ -2075,6 +2086,212 @@ sox_status run_gw(sox_plan& p, const double* X, const double* W, const double* G
     a.M = n, a.N = n, a.K = N, a.nzi = cnt;
     if ((st = cg_launch(a, nz, 0, s))) return st;
   }
+  return SOX_OK;
+}
+
+// -- minimal self-consistent loop (sox_scf.hpp) -------------------------------------
+sox_status queue_energy(sox_plan& p, const double* Sigma, const double* G, double* e,
+                        double** slot, hipStream_t s);  // with the energy entry points
+
+struct ScfLayout {
+  size_t g, gn, sd, sd2, snu, gin, aw, gam, shf, heff, exch, rho, v, tf, tb, tbeta, nu, bmax,
+      scal, hf_p1, hf_m, hf_y, sub, total;
+};
+constexpr int kScfBlocks = 1024;  // blocks of the mixing reduction
+
+size_t scf_sub_bytes(const sox_plan& p, int terms) {
+  size_t b = 0;
+  if (terms & 1) b = std::max(b, gw_workspace_bytes(p));
+  if (terms & 2) b = std::max(b, workspace_bytes(p, SOX_ENTRY_BARE));
+  return b;
+}
+
+ScfLayout scf_layout_for(const sox_plan& p, int n_nu, int terms) {
+  ScfLayout L{};
+  const size_t n = p.n, N = p.N, nt = p.n_tau, nn = n * n, nm = n_nu;
+  Carver c;
+  L.g = c.take(nt * nn * 8);
+  L.gn = c.take(nt * nn * 8);
+  L.sd = c.take(nt * nn * 8);
+  L.sd2 = c.take(nt * nn * 8);
+  L.snu = c.take(2 * nm * nn * 8);
+  L.gin = c.take(2 * nm * nn * 8);
+  L.aw = c.take(2 * nm * nn * 8);
+  L.gam = c.take(nn * 8);
+  L.shf = c.take(nn * 8);
+  L.heff = c.take(nn * 8);
+  L.exch = c.take(nn * 8);
+  L.rho = c.take(N * 8);
+  L.v = c.take(N * 8);
+  L.tf = c.take(2 * nm * nt * 8);
+  L.tb = c.take(2 * nt * nm * 8);
+  L.tbeta = c.take(nt * 8);
+  L.nu = c.take(nm * 8);
+  L.bmax = c.take(kScfBlocks * 8);
+  L.scal = c.take(8 * 8);
+  L.hf_p1 = c.take(N * n * 8);
+  L.hf_m = c.take(N * N * 8);
+  L.hf_y = c.take(n * N * 8);
+  L.sub = c.take(scf_sub_bytes(p, terms));
+  L.total = c.off;
+  return L;
+}
+
+sox_status run_scf(sox_plan& p, const sox_scf_params& prm, const double* X, const double* V,
+                   const double* W, const double* h, const double* h_start, double* Gout,
+                   sox_scf_result* res, void* ws, hipStream_t s) {
+  const ScfLayout L = scf_layout_for(p, prm.n_nu, prm.terms);
+  char* base = (char*)ws;
+  auto P = [&](size_t off) { return (double*)(base + off); };
+  double *g = P(L.g), *gn = P(L.gn), *sd = P(L.sd), *sd2 = P(L.sd2), *snu = P(L.snu);
+  double *gin = P(L.gin), *aw = P(L.aw), *gam = P(L.gam), *shf = P(L.shf), *heff = P(L.heff);
+  double *exch = P(L.exch), *rho = P(L.rho), *v = P(L.v), *tf = P(L.tf), *tb = P(L.tb);
+  double *tbeta = P(L.tbeta), *nu = P(L.nu), *bmax = P(L.bmax), *scal = P(L.scal);
+  const int n = p.n, N = p.N, nt = p.n_tau, nm = prm.n_nu;
+  const long nn = (long)n * n;
+  SOX_HIP(hipMemcpyAsync(tf, prm.t_fwd, sizeof(double) * 2 * nm * nt, hipMemcpyHostToDevice, s));
+  SOX_HIP(hipMemcpyAsync(tb, prm.t_bwd, sizeof(double) * 2 * nt * nm, hipMemcpyHostToDevice, s));
+  SOX_HIP(hipMemcpyAsync(tbeta, prm.t_beta, sizeof(double) * nt, hipMemcpyHostToDevice, s));
+  SOX_HIP(hipMemcpyAsync(nu, prm.nu, sizeof(double) * nm, hipMemcpyHostToDevice, s));
+  SOX_HIP(hipStreamSynchronize(s));
+  double hmax = 0.0;  // host bound on |h| for the mu bracket: read h once
+  {
+    std::vector<double> hh(nn);
+    SOX_HIP(hipMemcpy(hh.data(), h_start ? h_start : h, sizeof(double) * nn, hipMemcpyDeviceToHost));
+    for (int i = 0; i < n; ++i) {
+      double row = 0.0;
+      for (int j = 0; j < n; ++j) row += std::fabs(hh[(size_t)i * n + j]);
+      hmax = std::max(hmax, row);
+    }
+  }
+  const double span = hmax + 50.0;
+  // N(mu) for the current heff and snu, G(tau) into out
+  auto dyson = [&](double mu, double* out, double* count) -> sox_status {
+    hipLaunchKernelGGL(scf_dyson_kernel, dim3(nm), dim3(kScfThreads), 0, s, heff, snu, nu, mu, n,
+                       aw, gin);
+    SOX_HIP(hipGetLastError());
+    hipLaunchKernelGGL(scf_ift_kernel, grid1d((long)nt * nn), dim3(256), 0, s, tb, gin, nt, nm, nn,
+                       out);
+    SOX_HIP(hipGetLastError());
+    if (count) {
+      hipLaunchKernelGGL(scf_count_kernel, dim3(1), dim3(256), 0, s, out, tbeta, n, nt, scal);
+      SOX_HIP(hipGetLastError());
+      SOX_HIP(hipMemcpyAsync(count, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+      SOX_HIP(hipStreamSynchronize(s));
+    }
+    return SOX_OK;
+  };
+  // root of f(mu) = N(mu) - n_elec (increasing) in [lo, hi]: Illinois
+  // regula falsi, a bisection step every fourth evaluation, until the
+  // bracket is below 1e-12 (1 + |mu|) or f vanishes; G at the final mu
+  auto solve_mu = [&](double lo, double hi, double* out, double* mu_out) -> sox_status {
+    double flo = 0.0, fhi = 0.0;
+    sox_status q;
+    if ((q = dyson(lo, out, &flo))) return q;
+    if ((q = dyson(hi, out, &fhi))) return q;
+    flo -= prm.n_elec;
+    fhi -= prm.n_elec;
+    double mu = 0.5 * (lo + hi);
+    int side = 0;
+    for (int it = 0; it < 200 && flo < 0.0 && fhi > 0.0; ++it) {
+      if (hi - lo <= 1e-12 * (1.0 + std::fabs(mu))) break;
+      mu = (it % 4 == 3) ? 0.5 * (lo + hi) : (lo * fhi - hi * flo) / (fhi - flo);
+      if (!(mu > lo && mu < hi)) mu = 0.5 * (lo + hi);
+      double f = 0.0;
+      if ((q = dyson(mu, out, &f))) return q;
+      f -= prm.n_elec;
+      if (f == 0.0) {
+        lo = hi = mu;
+        break;
+      }
+      if (f < 0.0) {
+        lo = mu;
+        flo = f;
+        if (side < 0) fhi *= 0.5;
+        side = -1;
+      } else {
+        hi = mu;
+        fhi = f;
+        if (side > 0) flo *= 0.5;
+        side = 1;
+      }
+    }
+    *mu_out = 0.5 * (lo + hi);
+    return dyson(*mu_out, out, nullptr);
+  };
+  // start: G0 of h_start (or h), no self-energy
+  SOX_HIP(hipMemcpyAsync(heff, h_start ? h_start : h, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
+  sox_status st = launch_fill<double>(snu, 2L * nm * nn, s);
+  if (st) return st;
+  double mu = 0.0;
+  if ((st = solve_mu(-span, span, g, &mu))) return st;
+  const long cnt = (long)nt * nn;
+  const int nb = (int)std::min<long>(kScfBlocks, (cnt + 255) / 256);
+  void* sub = base + L.sub;
+  auto self_energy = [&]() -> sox_status {
+    // gamma, Sigma^HF (exchange by the GW chain with W = V, G = gamma), heff
+    hipLaunchKernelGGL(scf_density_kernel, grid1d(nn), dim3(256), 0, s, g, tbeta, n, nt, gam);
+    SOX_HIP(hipGetLastError());
+    sox_status q = gw_mol_slab(p, X, V, gam, exch, 0, 1, P(L.hf_p1), P(L.hf_m), P(L.hf_y), s);
+    if (q) return q;
+    hipLaunchKernelGGL(scf_rho_kernel, grid1d(N), dim3(256), 0, s, X, gam, n, N, rho);
+    SOX_HIP(hipGetLastError());
+    hipLaunchKernelGGL(scf_matvec_kernel, grid1d(N), dim3(256), 0, s, V, rho, N, v);
+    SOX_HIP(hipGetLastError());
+    hipLaunchKernelGGL(scf_hartree_kernel, grid1d(nn), dim3(256), 0, s, X, v, exch, h, n, N, shf,
+                       heff);
+    SOX_HIP(hipGetLastError());
+    // Sigma^dyn(tau)
+    if ((q = launch_fill<double>(sd, cnt, s))) return q;
+    if (prm.terms & 1) {
+      if ((q = run_gw(p, X, W, g, sd, sub, s))) return q;
+    }
+    if (prm.terms & 2) {
+      q = p.precision == SOX_FP64 ? run_static<double>(p, SOX_ENTRY_BARE, X, V, V, g, sd2, sub, s)
+                                  : run_static<float>(p, SOX_ENTRY_BARE, X, V, V, g, sd2, sub, s);
+      if (q) return q;
+      hipLaunchKernelGGL(scf_add_kernel, grid1d(cnt), dim3(256), 0, s, sd, sd2, cnt);
+      SOX_HIP(hipGetLastError());
+    }
+    return SOX_OK;
+  };
+  double delta = INFINITY;
+  int it = 0;
+  for (it = 1; it <= prm.max_iter; ++it) {
+    if ((st = self_energy())) return st;
+    hipLaunchKernelGGL(scf_ft_kernel, grid1d((long)nm * nn), dim3(256), 0, s, tf, sd, nt, nm, nn,
+                       snu);
+    SOX_HIP(hipGetLastError());
+    if ((st = solve_mu(mu - span, mu + span, gn, &mu))) return st;
+    hipLaunchKernelGGL(scf_mix_kernel, dim3(nb), dim3(256), 0, s, g, gn, prm.mix, cnt, bmax);
+    SOX_HIP(hipGetLastError());
+    hipLaunchKernelGGL(scf_reduce_kernel, dim3(1), dim3(256), 0, s, bmax, nb, h, shf, gam, nn, scal);
+    SOX_HIP(hipGetLastError());
+    SOX_HIP(hipMemcpyAsync(&delta, scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    SOX_HIP(hipStreamSynchronize(s));
+    if (delta <= prm.tol) break;
+  }
+  if (it > prm.max_iter) it = prm.max_iter;
+  // energies at the final G: E_inf (eq:E1b) and E_dyn (eq:E2b, tau form)
+  if ((st = self_energy())) return st;
+  hipLaunchKernelGGL(scf_reduce_kernel, dim3(1), dim3(256), 0, s, bmax, 0, h, shf, gam, nn, scal);
+  SOX_HIP(hipGetLastError());
+  double e_dyn = 0.0;
+  if (prm.terms) {
+    if ((st = queue_energy(p, sd, g, scal + 2, nullptr, s))) return st;
+  } else if ((st = launch_fill<double>(scal + 2, 1, s))) {
+    return st;
+  }
+  double host[3];
+  SOX_HIP(hipMemcpyAsync(host, scal, sizeof(host), hipMemcpyDeviceToHost, s));
+  SOX_HIP(hipMemcpyAsync(Gout, g, sizeof(double) * cnt, hipMemcpyDeviceToDevice, s));
+  SOX_HIP(hipStreamSynchronize(s));
+  e_dyn = host[2];
+  res->mu = mu;
+  res->e_inf = host[1];
+  res->e_dyn = e_dyn;
+  res->delta = delta;
+  res->iterations = it;
   return SOX_OK;
 }
 
@@ -2489,6 +2706,83 @@ sox_status sox_ir_grid(double beta, double lambda, double eps, int32_t capacity,
     t_bwd[2 * i + 1] = g.t_bwd[i].imag();
   }
   return SOX_OK;
+}
+
+sox_status sox_ir_grid_fermion(double beta, double lambda, double eps, int32_t capacity,
+                               int32_t* n_tau, int32_t* n_nu, double* tau, int64_t* nu_index,
+                               double* t_fwd, double* t_bwd, double* t_beta) {
+  if (!n_tau || !n_nu) return fail(SOX_ERR_INVALID_ARG, "n_tau or n_nu is NULL");
+  *n_tau = 0;
+  *n_nu = 0;
+  if (!(beta > 0.0) || !std::isfinite(beta))
+    return fail(SOX_ERR_INVALID_ARG, "beta must be positive and finite");
+  if (!(lambda >= 1.0) || !(lambda <= 1e8))
+    return fail(SOX_ERR_INVALID_ARG, "lambda %g outside [1, 1e8]", lambda);
+  if (!(eps >= 1e-12) || !(eps <= 1e-2))
+    return fail(SOX_ERR_INVALID_ARG, "eps %g outside [1e-12, 1e-2]", eps);
+  if (capacity < 0) return fail(SOX_ERR_INVALID_ARG, "negative capacity");
+  sox_ir::Grid g = sox_ir::build(beta, lambda, eps, true);
+  if (!g.error.empty()) return fail(SOX_ERR_UNSUPPORTED, "IR grid: %s", g.error.c_str());
+  const int L = g.L, nm = (int)g.m.size();
+  *n_tau = L;
+  *n_nu = nm;
+  if (capacity < std::max(L, nm))
+    return fail(SOX_ERR_SHAPE, "capacity %d below the grid's %d tau nodes and %d frequencies",
+                capacity, L, nm);
+  if (!tau || !nu_index || !t_fwd || !t_bwd || !t_beta)
+    return fail(SOX_ERR_INVALID_ARG, "NULL output array");
+  for (int i = 0; i < L; ++i) {
+    tau[i] = g.tau[i];
+    t_beta[i] = g.t_beta[i];
+  }
+  for (int q = 0; q < nm; ++q) nu_index[q] = g.m[q];
+  for (size_t i = 0; i < g.t_fwd.size(); ++i) {
+    t_fwd[2 * i] = g.t_fwd[i].real();
+    t_fwd[2 * i + 1] = g.t_fwd[i].imag();
+  }
+  for (size_t i = 0; i < g.t_bwd.size(); ++i) {
+    t_bwd[2 * i] = g.t_bwd[i].real();
+    t_bwd[2 * i + 1] = g.t_bwd[i].imag();
+  }
+  return SOX_OK;
+}
+
+sox_status sox_scf_workspace_size(const sox_plan* plan, int32_t n_nu, int32_t terms,
+                                  size_t* bytes) {
+  if (!plan || !bytes) return fail(SOX_ERR_INVALID_ARG, "plan or bytes is NULL");
+  if (n_nu < 1) return fail(SOX_ERR_INVALID_ARG, "n_nu must be positive");
+  if (terms < 0 || terms > 3) return fail(SOX_ERR_INVALID_ARG, "unknown terms %d", terms);
+  *bytes = scf_layout_for(*plan, n_nu, terms).total;
+  return SOX_OK;
+}
+
+sox_status sox_scf(sox_plan* plan, const sox_scf_params* prm, const double* X, const double* V,
+                   const double* W_tau, const double* h, const double* h_start, double* G,
+                   sox_scf_result* result, void* ws, size_t ws_bytes, void* stream) {
+  sox_status st = check_plan(plan);
+  if (st) return st;
+  if (!prm || !result) return fail(SOX_ERR_INVALID_ARG, "params or result is NULL");
+  if (plan->nk != 1)
+    return fail(SOX_ERR_UNSUPPORTED, "the self-consistent loop runs on molecular plans only");
+  if (plan->n > kScfMaxN)
+    return fail(SOX_ERR_UNSUPPORTED, "the Dyson kernel takes at most %d orbitals", kScfMaxN);
+  if (prm->terms < 0 || prm->terms > 3)
+    return fail(SOX_ERR_INVALID_ARG, "unknown terms %d", prm->terms);
+  if (prm->n_nu < 1 || !prm->nu || !prm->t_fwd || !prm->t_bwd || !prm->t_beta)
+    return fail(SOX_ERR_INVALID_ARG, "fermionic transform pair missing");
+  if (!(prm->mix > 0.0 && prm->mix <= 1.0)) return fail(SOX_ERR_INVALID_ARG, "mix outside (0, 1]");
+  if (!(prm->tol > 0.0) || prm->max_iter < 1)
+    return fail(SOX_ERR_INVALID_ARG, "tol must be positive and max_iter at least 1");
+  if (!(prm->n_elec > 0.0 && prm->n_elec < plan->n))
+    return fail(SOX_ERR_INVALID_ARG, "n_elec outside (0, n_orb)");
+  if (!X || !V || !h || !G || ((prm->terms & 1) && !W_tau))
+    return fail(SOX_ERR_INVALID_ARG, "NULL tensor pointer");
+  const size_t need = scf_layout_for(*plan, prm->n_nu, prm->terms).total;
+  if (!ws) return fail(SOX_ERR_WORKSPACE, "workspace is NULL (need %zu bytes)", need);
+  if (((uintptr_t)ws & 255) != 0) return fail(SOX_ERR_WORKSPACE, "workspace not 256-byte aligned");
+  if (ws_bytes < need)
+    return fail(SOX_ERR_WORKSPACE, "workspace too small: %zu < %zu bytes", ws_bytes, need);
+  return run_scf(*plan, *prm, X, V, W_tau, h, h_start, G, result, ws, (hipStream_t)stream);
 }
 
 sox_status sox_sigma_gw(sox_plan* plan, const double* X, const double* W_tau, const double* G,

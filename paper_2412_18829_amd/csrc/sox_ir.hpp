@@ -30,6 +30,9 @@
 //    (even) or Im U^ (odd) for m <= 4 Lambda, found on every integer up to
 //    1024 and on steps of m / 32 beyond (the sign changes there are at least
 //    0.15 m apart for eps >= 1e-12), each bracket closed by bisection;
+//  * fermionic pair: the odd frequencies and the sign changes of Im U^ (even)
+//    and Re U^ (odd) instead, plus the row t_beta that evaluates the fitted
+//    expansion at tau = beta^-;
 //  * transform pair for functions real in imaginary time: T_fwd = U^ U_s^-1,
 //    T_bwd from the least-squares inverse of [Re U^; Im U^] (Householder QR),
 //    f(tau_i) = Re sum_m T_bwd[i][m] f(i Omega_m); weights w = U_s^-T I with
@@ -315,23 +318,24 @@ inline std::vector<double> roots(const Sve& sv, const Func& fn) {
   return out;
 }
 
-// U^(i Omega_m) = sqrt(beta / 2) int_{-1}^{1} e^{i pi m (x + 1)} u(x) dx
-inline cplx matsubara(const Sve& sv, const Func& fn, double beta, long m) {
+// U^(i Omega) = sqrt(beta / 2) int_{-1}^{1} e^{i pi m (x + 1)} u(x) dx with
+// Omega = 2 pi m / beta: m integer for bosons, m = n + 1/2 for fermions
+inline cplx matsubara(const Sve& sv, const Func& fn, double beta, double m) {
   cplx acc(0.0, 0.0);
   double jb[kIrP];
   const cplx ipow[4] = {cplx(1, 0), cplx(0, 1), cplx(-1, 0), cplx(0, -1)};
   for (size_t sg = 0; sg + 1 < sv.bx.size(); ++sg) {
     const double a = sv.bx[sg], b = sv.bx[sg + 1];
     const double cc = (a + b) / 2.0, h = (b - a) / 2.0;
-    sph_bessel_all(M_PI * (double)m * h, kIrP, jb);
+    sph_bessel_all(M_PI * m * h, kIrP, jb);
     cplx plus(0.0, 0.0), minus(0.0, 0.0);
     for (int k = 0; k < kIrP; ++k) {
       const double cj = fn.coef[sg * kIrP + k] * jb[k];
       plus += ipow[k & 3] * cj;
       minus += ipow[(4 - (k & 3)) & 3] * cj;
     }
-    const cplx e1 = std::polar(1.0, M_PI * (double)m * (cc + 1.0));
-    const cplx e2 = std::polar(1.0, M_PI * (double)m * (1.0 - cc));
+    const cplx e1 = std::polar(1.0, M_PI * m * (cc + 1.0));
+    const cplx e2 = std::polar(1.0, M_PI * m * (1.0 - cc));
     acc += 2.0 * h * (e1 * plus + (double)fn.par * e2 * minus);
   }
   return std::sqrt(beta / 2.0) * acc;
@@ -438,13 +442,18 @@ inline bool lsq_inverse(std::vector<double> B, int rows, int cols, std::vector<d
 struct Grid {
   int L = 0;
   std::vector<double> tau, weights, sv;  // sv: s_l / s_0
+  std::vector<double> t_beta;            // f(beta^-) = sum_i t_beta[i] f(tau_i)
   std::vector<long> m;
   std::vector<cplx> t_fwd;  // [n_omega][L]
   std::vector<cplx> t_bwd;  // [L][n_omega]
   std::string error;
 };
 
-inline Grid build(double beta, double lam, double eps) {
+// fermion: the odd frequencies nu_n = (2n + 1) pi / beta (m = n + 1/2), the
+// sign changes of Im U^ of the first omitted even function and Re U^ of the
+// first omitted odd one (a function even about beta / 2 has an imaginary
+// fermionic transform); bosons: the even frequencies, Re and Im swapped.
+inline Grid build(double beta, double lam, double eps, bool fermion = false) {
   Grid g;
   Sve sv = compute_sve(lam);
   const double s0 = sv.f[0].s;
@@ -476,8 +485,19 @@ inline Grid build(double beta, double lam, double eps) {
   // bosonic frequencies
   const long mmax = (long)(4.0 * lam);
   std::vector<long> sc{0};
-  sign_changes([&](long m) { return matsubara(sv, sv.f[le], beta, m).real(); }, mmax, sc);
-  sign_changes([&](long m) { return matsubara(sv, sv.f[lo], beta, m).imag(); }, mmax, sc);
+  const double sh = fermion ? 0.5 : 0.0;
+  sign_changes(
+      [&](long m) {
+        const cplx v = matsubara(sv, sv.f[le], beta, (double)m + sh);
+        return fermion ? v.imag() : v.real();
+      },
+      mmax, sc);
+  sign_changes(
+      [&](long m) {
+        const cplx v = matsubara(sv, sv.f[lo], beta, (double)m + sh);
+        return fermion ? v.real() : v.imag();
+      },
+      mmax, sc);
   std::sort(sc.begin(), sc.end());
   sc.erase(std::unique(sc.begin(), sc.end()), sc.end());
   g.m = sc;
@@ -489,7 +509,7 @@ inline Grid build(double beta, double lam, double eps) {
   }
   std::vector<cplx> Uh((size_t)nm * L);
   for (int q = 0; q < nm; ++q)
-    for (int l = 0; l < L; ++l) Uh[(size_t)q * L + l] = matsubara(sv, sv.f[l], beta, sc[q]);
+    for (int l = 0; l < L; ++l) Uh[(size_t)q * L + l] = matsubara(sv, sv.f[l], beta, (double)sc[q] + sh);
   // inverse of U_s: solve U_s X = I
   std::vector<double> Inv((size_t)L * L, 0.0);
   for (int i = 0; i < L; ++i) Inv[(size_t)i * L + i] = 1.0;
@@ -528,6 +548,12 @@ inline Grid build(double beta, double lam, double eps) {
       }
       g.t_bwd[(size_t)i * nm + q] = cplx(re, -im);
     }
+  // t_beta[i] = sum_l U_l(beta) Inv[l][i]
+  g.t_beta.assign(L, 0.0);
+  for (int l = 0; l < L; ++l) {
+    const double ub = std::sqrt(2.0 / beta) * evaluate(sv, sv.f[l], 1.0);
+    for (int i = 0; i < L; ++i) g.t_beta[i] += ub * Inv[(size_t)l * L + i];
+  }
   // weights: w_i = sum_l Inv[l][i] I_l
   std::vector<double> I(L, 0.0);
   for (int l = 0; l < L; ++l) {

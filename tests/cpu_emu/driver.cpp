@@ -244,7 +244,50 @@ int run_noalloc(int prec) {
   return rc;
 }
 
+// The self-consistent loop (sox_scf) on a small molecule: two iterations
+// with every kernel of the loop, the GW chain (bit 0) and the bare SOX
+// entry (bit 1); transform values are arbitrary (only accesses matter).
+int run_scf_case(int n, int N, int nt, int nnu, int terms, int prec) {
+  std::vector<double> tau(nt), w(nt, 1.0);
+  const double beta = 5.0;
+  for (int k = 0; k < nt; ++k) tau[k] = beta * (k + 0.5) / nt;
+  sox_problem pr{};
+  pr.n_orb = n; pr.n_thc = N; pr.n_tau = nt; pr.kmesh[0] = pr.kmesh[1] = pr.kmesh[2] = 1;
+  pr.beta = beta; pr.tau = tau.data(); pr.weights = w.data();
+  sox_plan* plan = nullptr;
+  if (sox_plan_create(&pr, prec, &plan)) { printf("create failed: %s\n", sox_last_error()); return 1; }
+  std::vector<double> nu(nnu), tf(2 * (size_t)nnu * nt, 0.01), tb(2 * (size_t)nt * nnu, 0.01),
+      tbeta(nt, -0.1);
+  for (int q = 0; q < nnu; ++q) nu[q] = (2 * q + 1) * M_PI / beta;
+  sox_scf_params prm{};
+  prm.n_elec = 0.5 * n; prm.mix = 0.5; prm.tol = 1e-30; prm.max_iter = 2; prm.terms = terms;
+  prm.n_nu = nnu; prm.nu = nu.data(); prm.t_fwd = tf.data(); prm.t_bwd = tb.data();
+  prm.t_beta = tbeta.data();
+  size_t wsb = 0;
+  sox_scf_workspace_size(plan, nnu, terms, &wsb);
+  g_ws_size = wsb + 4096;
+  g_ws_base = (char*)aligned_alloc(256, (g_ws_size + 255) & ~size_t(255));
+  double* X = dalloc((size_t)n * N);
+  double* V = dalloc((size_t)N * N);
+  double* W = dalloc((size_t)nt * N * N);
+  double* h = dalloc((size_t)n * n, 3.0);
+  double* G = dalloc((size_t)nt * n * n);
+  sox_scf_result res{};
+  const sox_status st = sox_scf(plan, &prm, X, V, (terms & 1) ? W : nullptr, h, nullptr, G, &res,
+                                g_ws_base, wsb, nullptr);
+  printf("scf n=%d N=%d nt=%d nnu=%d terms=%d -> status %d %s\n", n, N, nt, nnu, terms, st,
+         st ? sox_last_error() : "");
+  ASAN_UNPOISON_MEMORY_REGION(g_ws_base, g_ws_size);
+  g_ws_base = nullptr;
+  free(X); free(V); free(W); free(h); free(G);
+  sox_plan_destroy(plan);
+  return st;
+}
+
 int main(int argc, char** argv) {
+  if (argc == 8 && std::string(argv[1]) == "scf")
+    return run_scf_case(atoi(argv[2]), atoi(argv[3]), atoi(argv[4]), atoi(argv[5]), atoi(argv[6]),
+                        atoi(argv[7]));
   if (argc == 2 && std::string(argv[1]) == "guards") return run_guards();
   if (argc == 3 && std::string(argv[1]) == "noalloc") return run_noalloc(atoi(argv[2]));
   int n = atoi(argv[1]), N = atoi(argv[2]), nt = atoi(argv[3]), prec = atoi(argv[4]), entry = atoi(argv[5]), vjp = atoi(argv[6]);

@@ -225,3 +225,18 @@ def test_autotune_in_bounds(emu, case):
     out = r.stdout + r.stderr
     assert r.returncode == 0 and "status 0" in out and "AddressSanitizer" not in out, out[-4000:]
     assert '"autotune":[{' in out, out[-4000:]
+
+
+# the self-consistent loop: HF only, GW (bit 0), GW + bare SOX (bits 0, 1),
+# a ragged N over several tiles, and 300 frequencies (one Dyson workgroup each)
+SCF_CASES = [(5, 9, 4, 3, 0, 0), (6, 70, 6, 5, 1, 0), (7, 20, 4, 3, 3, 1), (4, 11, 2, 300, 1, 0)]
+
+
+@pytest.mark.parametrize("case", SCF_CASES, ids=lambda c: "-".join(str(x) for x in c))
+def test_scf_in_bounds(emu, case):
+    n, N, nt, nnu, terms, prec = case
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    r = subprocess.run([emu, "scf", str(n), str(N), str(nt), str(nnu), str(terms), str(prec)],
+                       capture_output=True, text=True, env=env, timeout=900)
+    out = r.stdout + r.stderr
+    assert r.returncode == 0 and "status 0" in out and "AddressSanitizer" not in out, out[-4000:]
