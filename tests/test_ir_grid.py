@@ -90,3 +90,29 @@ def test_argument_checks_and_capacity(B):
     assert e.value.status == 2
     g = B.sox_ir_grid(100.0, 1000.0, 1e-8, capacity=64)
     assert len(g["tau"]) <= 64 and len(g["m"]) <= 64
+
+
+@pytest.mark.parametrize("beta,lam,eps", [(20.0, 300.0, 1e-10), (100.0, 1400.0, 1e-10)])
+def test_library_fermionic_pair(B, beta, lam, eps):
+    """The fermionic pair: closed-form fermionic poles (f(i nu) = 1 / (i nu - e),
+    f(beta^-) = -1 / (1 + e^{beta e})) and parity with the oracle's pair."""
+    g = B.sox_ir_grid_fermion(beta, lam, eps)
+    o = ir.ir_fermion(beta, lam, eps)
+    assert np.array_equal(g["n"], o["n"])
+    tol = 1e-14 / eps
+    assert np.abs(g["tau"] - o["tau"]).max() <= tol * beta
+    for key in ("T_fwd", "T_bwd", "t_beta"):
+        err = np.abs(g[key] - o[key]).max() / np.abs(o[key]).max()
+        assert err <= tol, (key, err)
+    tau, nu = g["tau"], (2 * g["n"] + 1) * np.pi / beta
+    for e in (lam / beta) * np.array([-1.0, -0.2, 0.01, 0.5, 1.0]):
+        if e > 0:
+            ft = -np.exp(-e * tau) / (1 + np.exp(-beta * e))
+            fb = -np.exp(-e * beta) / (1 + np.exp(-beta * e))
+        else:
+            ft = -np.exp(-e * (tau - beta)) / (np.exp(beta * e) + 1)
+            fb = -1.0 / (np.exp(beta * e) + 1)
+        fh = 1.0 / (1j * nu - e)
+        assert np.abs(g["T_fwd"] @ ft - fh).max() <= 1e2 * eps * np.abs(fh).max()
+        assert np.abs((g["T_bwd"] @ fh).real - ft).max() <= 1e2 * eps * np.abs(ft).max()
+        assert abs(g["t_beta"] @ ft - fb) <= 1e2 * eps
