@@ -795,17 +795,17 @@ def main() -> int:
             from oracle import scf as oscf
             c0 = time.perf_counter()
             ofg, obg = oir.ir_fermion(SCF_BETA, SCF_LAMBDA, IR_EPS), oir.ir_grid(SCF_BETA, SCF_LAMBDA, IR_EPS)
-            ref = oscf.scf(swl["X"], swl["V"], swl["W_tau"], hs, SCF_N / 2, SCF_BETA, ofg,
+            sref = oscf.scf(swl["X"], swl["V"], swl["W_tau"], hs, SCF_N / 2, SCF_BETA, ofg,
                            obg["weights"], terms=("gw",), tol=SCF_TOL, max_iter=100)
             osec = time.perf_counter() - c0
             scf["cpu_baseline"] = {"value": 1.0 / osec, "unit": "loops/s", "cores": blas_threads(),
                                    "kind": "oracle",
                                    "sample": (f"the whole loop by the numpy oracle on its own IR "
-                                              f"grid ({ref['iterations']} iterations, {osec:.1f} s)")}
-            scf["max_abs_dG_vs_oracle"] = float(np.abs(scf_G - ref["G"]).max())
-            scf["e_inf_rel_err"] = abs(scf["e_inf"] - ref["e_inf"]) / abs(ref["e_inf"])
-            scf["e_dyn_rel_err"] = abs(scf["e_dyn"] - ref["e_dyn"]) / abs(ref["e_dyn"])
-            scf["mu_abs_err"] = abs(scf["mu"] - ref["mu"])
+                                              f"grid ({sref['iterations']} iterations, {osec:.1f} s)")}
+            scf["max_abs_dG_vs_oracle"] = float(np.abs(scf_G - sref["G"]).max())
+            scf["e_inf_rel_err"] = abs(scf["e_inf"] - sref["e_inf"]) / abs(sref["e_inf"])
+            scf["e_dyn_rel_err"] = abs(scf["e_dyn"] - sref["e_dyn"]) / abs(sref["e_dyn"])
+            scf["mu_abs_err"] = abs(scf["mu"] - sref["mu"])
         out["scf"] = scf
     if irr is not None:
         if not args.no_cpu_baseline:
