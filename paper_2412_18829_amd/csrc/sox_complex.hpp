@@ -1236,7 +1236,9 @@ void ft_solid_kernel(const FtSolidArgs a, long nblocks) {
 // Float32 MFMAs; [cr; ci] stays in LDS for the launch; a wavefront owns 16
 // consecutive complex columns and every node (up to eight row tiles of 16)
 // at a time, so each A(+-Omega) value is read once.
-constexpr int kIftRows = 128, kIftW = 40, kIftLd = 144;  // n_tau <= 128, n_omega <= 40
+// n_tau <= 128; n_omega <= W, the kernel's template width: 40 (three
+// workgroups per CU) or 64 (the wider grids, e.g. IR grids: two per CU)
+constexpr int kIftRows = 128, kIftW = 40, kIftWMax = 64, kIftLd = 144;
 struct IftSolidArgs {
   const double* tbc;  // [nt][2 n_omega] complex; columns < n_omega hold T_bwd / 2
   const float* aw;    // [2 n_omega][fstride] complex: +Omega rows, then -Omega rows
@@ -1245,11 +1247,12 @@ struct IftSolidArgs {
   int nt, nw;
 };
 
-// three workgroups per CU (LDS), three wavefronts per SIMD
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+// W = 40: three workgroups per CU (LDS), three wavefronts per SIMD
+template <int W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(W <= 40 ? 3 : 2)))
 void ift_solid_kernel(const IftSolidArgs a) {
-  __shared__ float cr[kIftW * kIftLd], ci[kIftW * kIftLd];  // [m][tau]
-  for (int e = threadIdx.x; e < kIftW * kIftRows; e += blockDim.x) {
+  __shared__ float cr[W * kIftLd], ci[W * kIftLd];  // [m][tau]
+  for (int e = threadIdx.x; e < W * kIftRows; e += blockDim.x) {
     const int m = e / kIftRows, t = e - m * kIftRows;
     const bool ok = m < a.nw && t < a.nt;
     const double* c = a.tbc + 2 * ((long)t * 2 * a.nw + m);
@@ -1262,7 +1265,7 @@ void ift_solid_kernel(const IftSolidArgs a) {
   const int ns = (a.nw + 3) / 4;    // k steps of four frequencies
   const int nrt = (a.nt + 15) / 16;  // row tiles of nodes
   const long ntiles = (a.cols + 15) / 16;
-  constexpr int kS = kIftW / 4;
+  constexpr int kS = W / 4;
   const long tstep = (long)gridDim.x * nwaves;
   // lane (li, g) holds frequency m = 4 s + g of its column; the next tile's
   // values are loaded while the MFMAs of the current one run

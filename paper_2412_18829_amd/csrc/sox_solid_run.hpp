@@ -455,7 +455,7 @@ bool solid_ft_fused(const sox_plan& p) {
 // the inverse transform in real form on float32 MFMAs (ift_solid_kernel):
 // W(Omega) GG(Omega) then writes its products in float32
 bool solid_ift_real(const sox_plan& p) {
-  return solid_wgg_block(p) && p.n_tau <= kIftRows && p.n_omega <= kIftW &&
+  return solid_wgg_block(p) && p.n_tau <= kIftRows && p.n_omega <= kIftWMax &&
          (long)p.nk * p.n * p.N <= kTransformSlabCols;
 }
 
@@ -769,8 +769,14 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
         f.tbc = p.d_tbc; f.aw = (const float*)aw; f.out = (float*)(atau + 2 * (long)p0 * nN);
         f.fstride = (long)ps * nN; f.ldo = (long)np2 * nN; f.cols = (long)cp * nN;
         f.nt = nt; f.nw = nw;
-        hipLaunchKernelGGL(ift_solid_kernel, dim3(resident_grid(p, &ift_solid_kernel, 256)),
-                           dim3(256), 0, s, f);
+        if (nw <= kIftW)
+          hipLaunchKernelGGL(ift_solid_kernel<kIftW>,
+                             dim3(resident_grid(p, &ift_solid_kernel<kIftW>, 256)), dim3(256), 0,
+                             s, f);
+        else
+          hipLaunchKernelGGL(ift_solid_kernel<kIftWMax>,
+                             dim3(resident_grid(p, &ift_solid_kernel<kIftWMax>, 256)), dim3(256),
+                             0, s, f);
         SOX_HIP(hipGetLastError());
       } else {
         // A(tau)[pair][P][u] = sum_{+-m} Tb[tau][+-m] A(+-Omega_m)[l][P][u]

@@ -101,7 +101,7 @@ int run_solid_case(int n, int N, int nt, int prec, int entry, const int mesh[3])
   pr.n_orb = n; pr.n_thc = N; pr.n_tau = nt;
   for (int i = 0; i < 3; ++i) pr.kmesh[i] = mesh[i];
   pr.beta = beta; pr.tau = tau.data(); pr.weights = w.data();
-  const int nw = 3;
+  const int nw = getenv("EMU_NW") ? atoi(getenv("EMU_NW")) : 3;
   const bool dyn = entry == 2 || entry >= 3 + SOX_VERTEX_SOSEX_DYN;
   std::vector<double> tf(2 * nw * nt, 0.01), tb(2 * nw * nt, 0.01);
   if (dyn) { pr.n_omega = nw; pr.t_fwd = tf.data(); pr.t_bwd = tb.data(); }

@@ -111,6 +111,22 @@ def test_solid_entry_in_bounds(emu, case):
     assert r.returncode == 0 and "status 0" in out and "AddressSanitizer" not in out, out[-4000:]
 
 
+# more than 40 bosonic samples (IR grids): the inverse transform's 64-wide
+# instantiation, in float32 and bf16 x 3, plain dynamic and SOSEX_dyn
+WIDE_CASES = [(4, 20, 6, 1, 2, (2, 1, 1)), (4, 20, 5, 2, 6, (3, 1, 1))]
+
+
+@pytest.mark.parametrize("case", WIDE_CASES, ids=lambda c: "-".join(str(x) for x in c))
+def test_solid_wide_frequency_in_bounds(emu, case):
+    n, N, nt, prec, entry, mesh = case
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", EMU_NW="48")
+    r = subprocess.run([emu, str(n), str(N), str(nt), str(prec), str(entry), "0",
+                        *[str(m) for m in mesh]],
+                       capture_output=True, text=True, env=env, timeout=900)
+    out = r.stdout + r.stderr
+    assert r.returncode == 0 and "status 0" in out and "AddressSanitizer" not in out, out[-4000:]
+
+
 # the LDS-staged fused kernel, split precision (config 8) and float32
 # (config 9): one, two and three k stages per v, padded tiles, several tau
 # slabs, the dynamic entry's v slabs

@@ -10,6 +10,11 @@ same poles.  The two grids agree to about 1e-14 / eps = 1e-6 relative at
 most (measured 6e-9: tests/test_ir_grid.py), so the FP64 bound is 1e-7; FP32
 1e-6; BF16x3 1e-4 (the stated split-precision bound).  The GM energies of
 both agree to the same bound.
+
+A 2x1x1 mesh (n = 4, N = 20) on the beta = 100, Lambda = 1400 grid (55 nodes,
+46 bosonic samples: the inverse transform's 64-wide real-form kernel) against
+the oracle's momentum-resolved eq:GG chain on its own grid: FP32 1e-6,
+BF16x3 1e-4 (the grids' transforms agree to 8e-7 there).
 """
 import numpy as np
 import pytest
@@ -71,3 +76,51 @@ def test_dynamic_entry_on_ir_grid(B, case, precision):
     log(f"  rel err {err:.2e}, energy {e:.12e} vs {e_ref:.12e}")
     assert err <= TOL[precision]
     assert abs(e - e_ref) <= TOL[precision] * abs(e_ref)
+
+
+# ---------------------------------------------------------------------------
+# a k-point mesh on an IR grid with more than 40 bosonic samples (the
+# inverse transform's 64-wide real-form instantiation)
+SBETA, SLAM, SEPS = 100.0, 1400.0, 1e-10
+SMESH = (2, 1, 1)
+STOL = {"fp32": 1e-6, "bf16x3": 1e-4}
+
+
+def _solid_on(tau, seed=961):
+    wl = synth.solid(SMESH, 4, 20, len(tau), SBETA, seed=seed)
+    wl["tau"] = tau
+    return wl, synth.solid_screening_poles(wl)
+
+
+@pytest.fixture(scope="module")
+def solid_case():
+    from oracle import sox_solid as osd
+    og = ir.ir_grid(SBETA, SLAM, SEPS)
+    wl, poles = _solid_on(og["tau"])
+    W = sum(a * pole[None, :, None, None] * S[:, None] for a, pole, S in poles)
+    G = osd.g_tau_k(wl["eps"], wl["Q"], wl["mu"], SBETA, og["tau"])
+    tb = (wl["kvecs"], wl["kdiff"], wl["ksum"], wl["kneg"])
+    ref = osd.sigma_solid_dynamic_thc(wl["X"], W, wl["V"], G, og["T_fwd"], og["T_bwd"], tb)
+    return ref
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+def test_solid_dynamic_on_ir_grid(B, solid_case, precision):
+    import torch
+    g = B.sox_ir_grid(SBETA, SLAM, SEPS)
+    assert len(g["m"]) > 40
+    wl, poles = _solid_on(g["tau"])
+    nk, n, N, nt = wl["nk"], wl["n"], wl["N"], len(g["tau"])
+    log(f"solid dynamic SOX on the IR grid (L={nt}, n_omega={len(g['m'])}) {precision}")
+    c = lambda a: torch.as_tensor(np.ascontiguousarray(a), dtype=torch.complex128, device="cuda")
+    W = sum(a * pole[None, :, None, None] * S[:, None] for a, pole, S in poles)
+    plan = B.Plan(n, N, g["tau"], g["weights"], SBETA, precision, kmesh=SMESH, t_fwd=g["T_fwd"],
+                  t_bwd=g["T_bwd"])
+    G = torch.empty((nk, nt, n, n), dtype=torch.complex128, device="cuda")
+    B.sox_build_g_tau(plan, c(wl["Q"]), dev(wl["eps"]), wl["mu"], G)
+    S = torch.empty_like(G)
+    B.sox_sigma_dynamic(plan, c(wl["X"]), c(W), c(wl["V"]), G, S)
+    torch.cuda.synchronize()
+    err = rel_err(host(S), solid_case)
+    log(f"  rel err {err:.2e}")
+    assert err <= STOL[precision]
