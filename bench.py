@@ -439,7 +439,11 @@ def main() -> int:
             u1, u2 = ((V, U1) if solid else (U1, V) if kind in ("static", "dynamic")
                       else (V, None))
             note(f"{precision}: autotuning the plan's launch choices")
+            if use_graph:
+                # candidates timed as graph replays, the mode the timed steps use
+                B.sox_plan_set_graph(plan, True)
             B.sox_autotune(plan, went, X, u1, u2, G, S, kind=vkind, ws=ws)
+            B.sox_plan_set_graph(plan, False)
             torch.cuda.synchronize()
             note(f"{precision}: autotuned {len(B.sox_plan_describe(plan)['autotune'])} candidates")
         # the energy of every step is queued into device memory (no host
@@ -706,6 +710,17 @@ def main() -> int:
         wsi = plan.workspace(went)
         Ei = torch.zeros(2, dtype=torch.float64, device=dev)
 
+        if not args.no_autotune:
+            # the same launch-choice tuning as the main run, on this grid's operands
+            B.sox_build_g_tau(plan, Q, eps, wl["mu"], Gi)
+            wsi = plan.workspace(went, plan.autotune_workspace_size(went, "sosex_dyn" if solid
+                                                                    else 0))
+            u1, u2 = (V, Wir) if solid else (Wir, V)
+            note("ir: autotuning the plan's launch choices")
+            B.sox_autotune(plan, went, X, u1, u2, Gi, Si, kind="sosex_dyn" if solid else 0,
+                           ws=wsi)
+            torch.cuda.synchronize()
+
         def ir_step():
             B.sox_build_g_tau(plan, Q, eps, wl["mu"], Gi)
             if solid:
@@ -736,7 +751,8 @@ def main() -> int:
                "energy_gm": float(Ei[0].item()), "stage_ms": ir_stages,
                "note": ("the timed step of this workload (same inputs, precision and entry) on "
                         "the IR grid sox_ir_grid builds in host code for the workload's beta "
-                        "and the transform pair's omega_max; untuned plan, one timed sweep")}
+                        "and the transform pair's omega_max; plan tuned as the main run's, one "
+                        "timed sweep")}
         del plan, Gi, Si, wsi, Wir
         torch.cuda.empty_cache()
 

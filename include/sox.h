@@ -439,9 +439,18 @@ sox_status sox_plan_set_graph(sox_plan* plan, int32_t enable);
 /* Autotuner on the caller's operands (the batching of all tau nodes and,
  * for k-point plans, all momentum pairs into few launches whose shapes are
  * the plan's choices; see the THC section's step lists for the steps).
- * Times one call of `entry` (several when a call takes under 20 ms) for
- * every candidate setting of the plan's launch choices and keeps the
- * fastest:
+ * Times `entry` for every candidate setting of the plan's launch choices
+ * and keeps the fastest: one synchronised call sizes the measurement and,
+ * when it is shorter than 20 ms, calls filling about 20 ms (up to 100) run
+ * back to back with a single synchronisation, so the time is the device's
+ * per call as in a caller's loop, not the launch overhead of an idle
+ * stream.  With the plan's graph mode on (sox_plan_set_graph) and calls
+ * shorter than 20 ms, each candidate is captured once and timed as graph
+ * replays, the mode such a caller runs in.  For such short calls the three
+ * fastest candidates are then timed again, interleaved over three rounds of
+ * about 40 ms each, and keep their fastest time (the sweep's fixed order
+ * would otherwise favour candidates timed after the clocks have settled).
+ * The choices:
  *   molecules        the fused B, C -> D kernel's configuration (wave tile,
  *                    direct-load or LDS-staged, of the plan's precision)
  *                    and the split of its v sum over workgroups;
@@ -459,7 +468,8 @@ sox_status sox_plan_set_graph(sox_plan* plan, int32_t enable);
  * Sigma).  With SOX_TUNE_CACHE=<file> the choice is appended to the file,
  * keyed by entry, kind, precision and shape, and a later call with the same
  * key takes it from there without timing.  The plan's graphs are dropped
- * (its launch sequence may change); the plan's graph mode is kept.  Results
+ * (its launch sequence may change; the next call captures the chosen one);
+ * the plan's graph mode is kept.  Results
  * appear under "autotune" in sox_plan_describe.  Errors: those of the entry
  * (the first failing candidate's status is returned). */
 sox_status sox_autotune(sox_plan* plan, int32_t entry, int32_t kind, const double* X,
