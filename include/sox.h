@@ -308,8 +308,12 @@ sox_status sox_ir_grid_fermion(double beta, double lambda, double eps, int32_t c
  *   V) (bit 1, in the plan's precision);
  *   gamma_pq = -G_qp(beta^-); each iteration transforms Sigma^dyn to the
  *   fermionic samples, solves G(i nu) = [(i nu + mu) I - h - Sigma^HF -
- *   Sigma^dyn(i nu)]^-1 for the mu that holds n_elec (100 bisection
- *   halvings of N(mu) = -Tr G(beta^-)), returns to tau, and mixes
+ *   Sigma^dyn(i nu)]^-1 (batched in-place Gauss-Jordan inversions with
+ *   partial pivoting, in LDS for n_orb <= 96 unless
+ *   SOX_SCF_DYSON_IN_MEMORY=1) for the mu that holds n_elec (the root of N(mu) =
+ *   -Tr G(beta^-) by Illinois regula falsi, to 1e-12 (1 + |mu|), inside a
+ *   bracket about the previous mu of twice its last change, widened
+ *   fourfold until it holds the root), returns to tau, and mixes
  *   G <- (1 - mix) G + mix G_new until max |G_new - G| <= tol or max_iter.
  *   E_inf = sum_pq (h + Sigma^HF / 2)_pq gamma_pq; E_dyn = -1/2 sum_j w_j
  *   Tr[Sigma^dyn(tau_j) G(beta - tau_j)] (the plan's weights).

@@ -2094,7 +2094,7 @@ sox_status queue_energy(sox_plan& p, const double* Sigma, const double* G, doubl
                         double** slot, hipStream_t s);  // with the energy entry points
 
 struct ScfLayout {
-  size_t g, gn, sd, sd2, snu, gin, aw, gam, shf, heff, exch, rho, v, tf, tb, tbeta, nu, bmax,
+  size_t g, gn, sd, sd2, snu, gin, gam, shf, heff, exch, rho, v, tf, tb, tbeta, nu, bmax,
       scal, hf_p1, hf_m, hf_y, sub, total;
 };
 constexpr int kScfBlocks = 1024;  // blocks of the mixing reduction
@@ -2116,7 +2116,6 @@ ScfLayout scf_layout_for(const sox_plan& p, int n_nu, int terms) {
   L.sd2 = c.take(nt * nn * 8);
   L.snu = c.take(2 * nm * nn * 8);
   L.gin = c.take(2 * nm * nn * 8);
-  L.aw = c.take(2 * nm * nn * 8);
   L.gam = c.take(nn * 8);
   L.shf = c.take(nn * 8);
   L.heff = c.take(nn * 8);
@@ -2144,7 +2143,7 @@ sox_status run_scf(sox_plan& p, const sox_scf_params& prm, const double* X, cons
   char* base = (char*)ws;
   auto P = [&](size_t off) { return (double*)(base + off); };
   double *g = P(L.g), *gn = P(L.gn), *sd = P(L.sd), *sd2 = P(L.sd2), *snu = P(L.snu);
-  double *gin = P(L.gin), *aw = P(L.aw), *gam = P(L.gam), *shf = P(L.shf), *heff = P(L.heff);
+  double *gin = P(L.gin), *gam = P(L.gam), *shf = P(L.shf), *heff = P(L.heff);
   double *exch = P(L.exch), *rho = P(L.rho), *v = P(L.v), *tf = P(L.tf), *tb = P(L.tb);
   double *tbeta = P(L.tbeta), *nu = P(L.nu), *bmax = P(L.bmax), *scal = P(L.scal);
   const int n = p.n, N = p.N, nt = p.n_tau, nm = prm.n_nu;
@@ -2165,10 +2164,18 @@ sox_status run_scf(sox_plan& p, const sox_scf_params& prm, const double* X, cons
     }
   }
   const double span = hmax + 50.0;
+  // the Dyson matrices in LDS when they fit (SOX_SCF_DYSON_IN_MEMORY=1: in
+  // device memory at any size, the form larger n takes)
+  const char* dmem = getenv("SOX_SCF_DYSON_IN_MEMORY");
+  const bool dyson_lds = n <= kScfLdsN && !(dmem && atoi(dmem) == 1);
   // N(mu) for the current heff and snu, G(tau) into out
   auto dyson = [&](double mu, double* out, double* count) -> sox_status {
-    hipLaunchKernelGGL(scf_dyson_kernel, dim3(nm), dim3(kScfThreads), 0, s, heff, snu, nu, mu, n,
-                       aw, gin);
+    if (dyson_lds)
+      hipLaunchKernelGGL(scf_dyson_kernel<true>, dim3(nm), dim3(kScfThreads), 0, s, heff, snu, nu,
+                         mu, n, gin);
+    else
+      hipLaunchKernelGGL(scf_dyson_kernel<false>, dim3(nm), dim3(kScfThreads), 0, s, heff, snu, nu,
+                         mu, n, gin);
     SOX_HIP(hipGetLastError());
     hipLaunchKernelGGL(scf_ift_kernel, grid1d((long)nt * nn), dim3(256), 0, s, tb, gin, nt, nm, nn,
                        out);
@@ -2181,16 +2188,15 @@ sox_status run_scf(sox_plan& p, const sox_scf_params& prm, const double* X, cons
     }
     return SOX_OK;
   };
-  // root of f(mu) = N(mu) - n_elec (increasing) in [lo, hi]: Illinois
-  // regula falsi, a bisection step every fourth evaluation, until the
-  // bracket is below 1e-12 (1 + |mu|) or f vanishes; G at the final mu
-  auto solve_mu = [&](double lo, double hi, double* out, double* mu_out) -> sox_status {
-    double flo = 0.0, fhi = 0.0;
+  // root of f(mu) = N(mu) - n_elec (increasing) in [lo, hi] with f(lo) <= 0
+  // <= f(hi): Illinois regula falsi, a bisection step every fourth
+  // evaluation, until the bracket is below 1e-12 (1 + |mu|) or f vanishes;
+  // G at the final mu
+  auto illinois = [&](double lo, double hi, double flo, double fhi, double* out,
+                      double* mu_out) -> sox_status {
     sox_status q;
-    if ((q = dyson(lo, out, &flo))) return q;
-    if ((q = dyson(hi, out, &fhi))) return q;
-    flo -= prm.n_elec;
-    fhi -= prm.n_elec;
+    if (flo == 0.0) hi = lo;
+    if (fhi == 0.0) lo = hi;
     double mu = 0.5 * (lo + hi);
     int side = 0;
     for (int it = 0; it < 200 && flo < 0.0 && fhi > 0.0; ++it) {
@@ -2219,12 +2225,41 @@ sox_status run_scf(sox_plan& p, const sox_scf_params& prm, const double* X, cons
     *mu_out = 0.5 * (lo + hi);
     return dyson(*mu_out, out, nullptr);
   };
+  // the root within span of mu0: f at mu0 -/+ d, the side that does not
+  // bracket moved out fourfold (the other end taking its place) until the
+  // signs differ or span is reached, then the search above
+  auto solve_mu = [&](double mu0, double d, double* out, double* mu_out) -> sox_status {
+    sox_status q;
+    d = std::min(d, span);
+    double lo = mu0 - d, hi = mu0 + d, flo = 0.0, fhi = 0.0;
+    if ((q = dyson(lo, out, &flo))) return q;
+    flo -= prm.n_elec;
+    if ((q = dyson(hi, out, &fhi))) return q;
+    fhi -= prm.n_elec;
+    while (flo > 0.0 && lo > mu0 - span) {
+      hi = lo;
+      fhi = flo;
+      d = std::min(4.0 * d, span);
+      lo = mu0 - d;
+      if ((q = dyson(lo, out, &flo))) return q;
+      flo -= prm.n_elec;
+    }
+    while (fhi < 0.0 && hi < mu0 + span) {
+      lo = hi;
+      flo = fhi;
+      d = std::min(4.0 * d, span);
+      hi = mu0 + d;
+      if ((q = dyson(hi, out, &fhi))) return q;
+      fhi -= prm.n_elec;
+    }
+    return illinois(lo, hi, flo, fhi, out, mu_out);
+  };
   // start: G0 of h_start (or h), no self-energy
   SOX_HIP(hipMemcpyAsync(heff, h_start ? h_start : h, sizeof(double) * nn, hipMemcpyDeviceToDevice, s));
   sox_status st = launch_fill<double>(snu, 2L * nm * nn, s);
   if (st) return st;
   double mu = 0.0;
-  if ((st = solve_mu(-span, span, g, &mu))) return st;
+  if ((st = solve_mu(0.0, span, g, &mu))) return st;
   const long cnt = (long)nt * nn;
   const int nb = (int)std::min<long>(kScfBlocks, (cnt + 255) / 256);
   void* sub = base + L.sub;
@@ -2234,9 +2269,10 @@ sox_status run_scf(sox_plan& p, const sox_scf_params& prm, const double* X, cons
     SOX_HIP(hipGetLastError());
     sox_status q = gw_mol_slab(p, X, V, gam, exch, 0, 1, P(L.hf_p1), P(L.hf_m), P(L.hf_y), s);
     if (q) return q;
-    hipLaunchKernelGGL(scf_rho_kernel, grid1d(N), dim3(256), 0, s, X, gam, n, N, rho);
+    hipLaunchKernelGGL(scf_rho_kernel, dim3((N + 63) / 64), dim3(kScfThreads), 0, s, X, gam, n, N,
+                       rho);
     SOX_HIP(hipGetLastError());
-    hipLaunchKernelGGL(scf_matvec_kernel, grid1d(N), dim3(256), 0, s, V, rho, N, v);
+    hipLaunchKernelGGL(scf_matvec_kernel, dim3((N + 3) / 4), dim3(256), 0, s, V, rho, N, v);
     SOX_HIP(hipGetLastError());
     hipLaunchKernelGGL(scf_hartree_kernel, grid1d(nn), dim3(256), 0, s, X, v, exch, h, n, N, shf,
                        heff);
@@ -2255,14 +2291,18 @@ sox_status run_scf(sox_plan& p, const sox_scf_params& prm, const double* X, cons
     }
     return SOX_OK;
   };
-  double delta = INFINITY;
+  double delta = INFINITY, dmu = 1.0;
   int it = 0;
   for (it = 1; it <= prm.max_iter; ++it) {
     if ((st = self_energy())) return st;
     hipLaunchKernelGGL(scf_ft_kernel, grid1d((long)nm * nn), dim3(256), 0, s, tf, sd, nt, nm, nn,
                        snu);
     SOX_HIP(hipGetLastError());
-    if ((st = solve_mu(mu - span, mu + span, gn, &mu))) return st;
+    // bracket half-width: twice the last change of mu (at least 1e-6 (1 + |mu|));
+    // the first iteration, where Sigma^HF enters, starts from 1
+    const double mu_prev = mu;
+    if ((st = solve_mu(mu, std::max(dmu, 1e-6 * (1.0 + std::fabs(mu))), gn, &mu))) return st;
+    dmu = 2.0 * std::fabs(mu - mu_prev);
     hipLaunchKernelGGL(scf_mix_kernel, dim3(nb), dim3(256), 0, s, g, gn, prm.mix, cnt, bmax);
     SOX_HIP(hipGetLastError());
     hipLaunchKernelGGL(scf_reduce_kernel, dim3(1), dim3(256), 0, s, bmax, nb, h, shf, gam, nn, scal);

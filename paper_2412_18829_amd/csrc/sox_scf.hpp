@@ -12,15 +12,16 @@
 //   G <- (1 - a) G + a G_new,  delta = max |G_new - G|
 //   E_inf = sum_pq (h + Sigma^HF / 2)_pq gamma_pq
 //
-// The Dyson inversions are batched Gauss-Jordan eliminations with partial
-// pivoting, one workgroup per frequency, on the matrices in device memory.
+// The Dyson inversions are batched Gauss-Jordan inversions in place with
+// partial pivoting, one workgroup per frequency, the matrix in LDS when it
+// fits.
 #pragma once
 
 #include "sox_common.hpp"
 
 namespace sox {
 
-constexpr int kScfMaxN = 1024;    // orbitals at most (LDS column of the Dyson kernel)
+constexpr int kScfMaxN = 1024;    // orbitals at most (LDS row and column of the Dyson kernel)
 constexpr int kScfThreads = 1024;  // threads of a Dyson workgroup (one frequency each)
 
 // gamma[p][q] = -sum_i tb[i] G[i][q][p]
@@ -34,26 +35,41 @@ __global__ void scf_density_kernel(const double* G, const double* tb, int n, int
   }
 }
 
-// rho[Q] = sum_kl X[k][Q] gamma[l][k] X[l][Q]
-__global__ void scf_rho_kernel(const double* X, const double* gam, int n, int N, double* rho) {
-  SOX_FOR_FLAT(Q, N) {
-    double acc = 0.0;
-    for (int k = 0; k < n; ++k) {
+// rho[Q] = sum_kl X[k][Q] gamma[l][k] X[l][Q]: one workgroup of kScfThreads
+// per 64 columns Q (one per lane), the k sum split over the wavefronts
+__global__ __launch_bounds__(kScfThreads) void scf_rho_kernel(const double* X, const double* gam,
+                                                              int n, int N, double* rho) {
+  constexpr int NW = kScfThreads / 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int Q = blockIdx.x * 64 + lane;
+  double acc = 0.0;
+  if (Q < N)
+    for (int k = wave; k < n; k += NW) {
       double t = 0.0;
       for (int l = 0; l < n; ++l) t += gam[(long)l * n + k] * X[(long)l * N + Q];
       acc += X[(long)k * N + Q] * t;
     }
-    rho[Q] = acc;
+  __shared__ double part[NW][64];
+  part[wave][lane] = acc;
+  __syncthreads();
+  if (wave == 0 && Q < N) {
+    double r = 0.0;
+    for (int w = 0; w < NW; ++w) r += part[w][lane];
+    rho[Q] = r;
   }
 }
 
-// v[P] = sum_Q V[P][Q] rho[Q]
-__global__ void scf_matvec_kernel(const double* V, const double* rho, int N, double* v) {
-  SOX_FOR_FLAT(P, N) {
-    double acc = 0.0;
-    for (int Q = 0; Q < N; ++Q) acc += V[(long)P * N + Q] * rho[Q];
-    v[P] = acc;
-  }
+// v[P] = sum_Q V[P][Q] rho[Q]: one wavefront per row P (256 threads)
+__global__ __launch_bounds__(256) void scf_matvec_kernel(const double* V, const double* rho, int N,
+                                                         double* v) {
+  const int lane = threadIdx.x & 63;
+  const int P = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (P >= N) return;
+  double acc = 0.0;
+  for (int Q = lane; Q < N; Q += 64) acc += V[(long)P * N + Q] * rho[Q];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+  if (lane == 0) v[P] = acc;
 }
 
 // shf = exch + J, J[i][j] = sum_P X[i][P] X[j][P] v[P]; heff = h + shf
@@ -86,117 +102,158 @@ __global__ void scf_ft_kernel(const double* Tf, const double* S, int nt, int nm,
 }
 
 // Ginv[m] = [(i nu_m + mu) I - heff - Snu[m]]^-1, one workgroup of
-// kScfThreads per m (the widest workgroup: each elimination step is one pass
-// over the matrix in memory, so more waves keep more of it in flight)
+// kScfThreads per m: Gauss-Jordan inversion in place with partial pivoting.
+// Step k: the pivot row r >= k of largest |A[r][k]| (a wavefront max
+// reduction, then one over the wavefronts), rows k and r exchanged, row k
+// scaled by 1 / p with its own column-k entry taken as 1 (so A[k][k] becomes
+// 1 / p), then every other row i loses f_i times row k with its column-k
+// entry taken as 0 (f_i = A[i][k] before the step), which leaves -f_i / p
+// there.  After the last step the inverse of the row-exchanged matrix is in
+// place; exchanging columns k and r_k for k = n - 1 down to 0 undoes the
+// row exchanges.  Three barriers per step.  LDS: the matrix is held in
+// LDS (n <= kScfLdsN) and written out at the end; otherwise it is
+// eliminated in place in Gi (2 n^2 doubles per frequency, read through the
+// cache).
+constexpr int kScfLdsN = 96;  // largest n held in LDS (147 KB)
+
+struct __attribute__((aligned(16))) ScfC {  // one complex double (16-byte loads)
+  double x, y;
+  __host__ __device__ ScfC() = default;
+  __host__ __device__ constexpr ScfC(double a, double b) : x(a), y(b) {}
+};
+
+template <bool LDS>
 __global__ __launch_bounds__(kScfThreads) void scf_dyson_kernel(const double* heff,
                                                                 const double* Snu,
                                                                 const double* nu, double mu,
-                                                                int n, double* Aw, double* Gi) {
+                                                                int n, double* Gi) {
+  constexpr int NW = kScfThreads / 64;
+  constexpr int NR = LDS ? kScfLdsN : kScfMaxN;
   const int m = blockIdx.x;
   const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
   const long nn = (long)n * n;
-  double* A = Aw + 2 * (long)m * nn;
-  double* R = Gi + 2 * (long)m * nn;
-  const double* S = Snu + 2 * (long)m * nn;
+  ScfC* R = reinterpret_cast<ScfC*>(Gi) + (long)m * nn;
+  const ScfC* S = reinterpret_cast<const ScfC*>(Snu) + (long)m * nn;
+  __shared__ ScfC lmat[LDS ? kScfLdsN * kScfLdsN : 1];
+  __shared__ ScfC row[NR], col[NR];
+  __shared__ int perm[NR];
+  __shared__ unsigned long long wkey[NW];
+  __shared__ ScfC wval[NW];
+  ScfC* A = LDS ? lmat : R;
+  // the elements e = tid + kScfThreads t as (row, column): stepped without
+  // divisions (the stride in columns is below n)
+  const int nn32 = n * n;
+  const int di = kScfThreads / n, dj = kScfThreads - di * n;
+  const int i0 = tid / n, j0 = tid - i0 * n;
   const double w = nu[m];
-  for (long e = tid; e < nn; e += kScfThreads) {
-    const int i = (int)(e / n), j = (int)(e - (long)i * n);
-    double re = -heff[e] - S[2 * e], im = -S[2 * e + 1];
+  for (int e = tid, i = i0, j = j0; e < nn32; e += kScfThreads) {
+    const ScfC sv = S[e];
+    ScfC a = ScfC(-heff[e] - sv.x, -sv.y);
     if (i == j) {
-      re += mu;
-      im += w;
+      a.x += mu;
+      a.y += w;
     }
-    A[2 * e] = re;
-    A[2 * e + 1] = im;
-    R[2 * e] = i == j ? 1.0 : 0.0;
-    R[2 * e + 1] = 0.0;
+    A[e] = a;
+    i += di;
+    j += dj;
+    if (j >= n) {
+      j -= n;
+      ++i;
+    }
   }
-  __shared__ double fr[kScfMaxN], fi[kScfMaxN];
-  __shared__ double pv[kScfThreads];
-  __shared__ int pix[kScfThreads];
-  __shared__ double inv_r, inv_i;
   __syncthreads();
   for (int k = 0; k < n; ++k) {
-    // pivot: the largest |A[i][k]|, i >= k
-    double best = -1.0;
-    int bi = k;
-    for (int i = k + tid; i < n; i += kScfThreads) {
-      const double ar = A[2 * ((long)i * n + k)], ai = A[2 * ((long)i * n + k) + 1];
-      const double a = ar * ar + ai * ai;
-      if (a > best) {
-        best = a;
-        bi = i;
-      }
-    }
-    pv[tid] = best;
-    pix[tid] = bi;
-    __syncthreads();
-    for (int s = kScfThreads / 2; s > 0; s >>= 1) {
-      if (tid < s && pv[tid + s] > pv[tid]) {
-        pv[tid] = pv[tid + s];
-        pix[tid] = pix[tid + s];
-      }
-      __syncthreads();
-    }
-    int r = pix[0];
-    r = r < k ? k : (r > n - 1 ? n - 1 : r);
-    if (r != k) {
-      for (int j = tid; j < n; j += kScfThreads) {
-        for (int c = 0; c < 2; ++c) {
-          double* a1 = A + 2 * ((long)k * n + j) + c;
-          double* a2 = A + 2 * ((long)r * n + j) + c;
-          const double t = *a1;
-          *a1 = *a2;
-          *a2 = t;
-          double* b1 = R + 2 * ((long)k * n + j) + c;
-          double* b2 = R + 2 * ((long)r * n + j) + c;
-          const double u = *b1;
-          *b1 = *b2;
-          *b2 = u;
+    // pivot: the largest |A[i][k]| over i >= k, as the largest key
+    // bits(|A[i][k]|^2) with its low 10 bits replaced by 1023 - i (non-negative
+    // doubles order as their bit patterns; among values equal to 2^-42
+    // relative the smaller i wins); 0: no row.  n <= 128: wavefront 0 alone,
+    // else every wavefront and then a pass over their winners.
+    const bool one = n <= 128;
+    if (!one || wave == 0) {
+      unsigned long long key = 0;
+      ScfC bv = ScfC(0.0, 0.0);
+      const int i_begin = k + (one ? lane : tid), i_step = one ? 64 : kScfThreads;
+      for (int i = i_begin; i < n; i += i_step) {
+        const ScfC a = A[(long)i * n + k];
+        const double q = a.x * a.x + a.y * a.y;
+        const unsigned long long kk =
+            (__builtin_bit_cast(unsigned long long, q) & ~1023ull) | (unsigned)(1023 - i);
+        if (kk > key) {
+          key = kk;
+          bv = a;
         }
       }
-    }
-    __syncthreads();
-    if (tid == 0) {
-      const double pr = A[2 * ((long)k * n + k)], pi = A[2 * ((long)k * n + k) + 1];
-      const double d = pr * pr + pi * pi;
-      inv_r = pr / d;
-      inv_i = -pi / d;
-    }
-    __syncthreads();
-    const double ir = inv_r, ii = inv_i;
-    for (int j = tid; j < n; j += kScfThreads) {
-      double* a = A + 2 * ((long)k * n + j);
-      double* b = R + 2 * ((long)k * n + j);
-      const double ar = a[0], ai = a[1], br = b[0], bi2 = b[1];
-      a[0] = ar * ir - ai * ii;
-      a[1] = ar * ii + ai * ir;
-      b[0] = br * ir - bi2 * ii;
-      b[1] = br * ii + bi2 * ir;
-    }
-    __syncthreads();
-    for (int i = tid; i < n; i += kScfThreads) {
-      fr[i] = A[2 * ((long)i * n + k)];
-      fi[i] = A[2 * ((long)i * n + k) + 1];
-    }
-    __syncthreads();
-    for (long e = tid; e < nn; e += kScfThreads) {
-      const int i = (int)(e / n);
-      if (i == k) continue;
-      const int j = (int)(e - (long)i * n);
-      const double f_r = fr[i], f_i = fi[i];
-      if (j > k) {  // columns <= k of A are not read again
-        const double* ak = A + 2 * ((long)k * n + j);
-        double* a = A + 2 * e;
-        a[0] -= f_r * ak[0] - f_i * ak[1];
-        a[1] -= f_r * ak[1] + f_i * ak[0];
+      unsigned long long wmax = key;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long ok = __shfl_xor(wmax, o);
+        wmax = ok > wmax ? ok : wmax;
       }
-      const double* bk = R + 2 * ((long)k * n + j);
-      double* b = R + 2 * e;
-      b[0] -= f_r * bk[0] - f_i * bk[1];
-      b[1] -= f_r * bk[1] + f_i * bk[0];
+      if (key == wmax && wmax != 0) wval[wave] = bv;  // the row is unique
+      if (lane == 0) wkey[wave] = wmax;
     }
     __syncthreads();
+    int wbest = 0;
+    if (!one)
+      for (int q = 1; q < NW; ++q)
+        if (wkey[q] > wkey[wbest]) wbest = q;
+    const unsigned long long kbest = wkey[wbest];
+    int r = 1023 - (int)(kbest & 1023ull);
+    const ScfC p = kbest != 0 ? wval[wbest] : ScfC(0.0, 0.0);
+    r = kbest == 0 || r < k ? k : (r > n - 1 ? n - 1 : r);
+    const double d = p.x * p.x + p.y * p.y;
+    const double ir = p.x / d, ii = -p.y / d;
+    // exchange rows k and r, scale row k (each column j by one thread); the
+    // column of multipliers (rows k and r by the owner of column k)
+    for (int j = tid; j < n; j += kScfThreads) {
+      const ScfC ak = A[(long)k * n + j];
+      const ScfC ar = r != k ? A[(long)r * n + j] : ak;
+      if (r != k) A[(long)r * n + j] = ak;
+      const ScfC x = j == k ? ScfC(1.0, 0.0) : ar;
+      const ScfC y = ScfC(x.x * ir - x.y * ii, x.x * ii + x.y * ir);
+      A[(long)k * n + j] = y;
+      row[j] = y;
+      if (j == k) {
+        col[k] = ScfC(0.0, 0.0);
+        if (r != k) col[r] = ak;
+      }
+    }
+    for (int i = tid; i < n; i += kScfThreads)
+      if (i != k && i != r) col[i] = A[(long)i * n + k];
+    if (tid == 0) perm[k] = r;
+    __syncthreads();
+    for (int e = tid, i = i0, j = j0; e < nn32; e += kScfThreads) {
+      if (i != k) {
+        const ScfC f = col[i], y = row[j];
+        ScfC a = j == k ? ScfC(0.0, 0.0) : A[e];
+        a.x -= f.x * y.x - f.y * y.y;
+        a.y -= f.x * y.y + f.y * y.x;
+        A[e] = a;
+      }
+      i += di;
+      j += dj;
+      if (j >= n) {
+        j -= n;
+        ++i;
+      }
+    }
+    __syncthreads();
+  }
+  // undo the row exchanges: column exchanges in reverse order, each row by
+  // one thread
+  for (int i = tid; i < n; i += kScfThreads)
+    for (int k = n - 1; k >= 0; --k) {
+      const int r = perm[k];
+      if (r != k) {
+        const ScfC t = A[(long)i * n + k];
+        A[(long)i * n + k] = A[(long)i * n + r];
+        A[(long)i * n + r] = t;
+      }
+    }
+  if constexpr (LDS) {
+    __syncthreads();
+    for (int e = tid; e < nn32; e += kScfThreads) R[e] = A[e];
   }
 }
 

@@ -244,8 +244,10 @@ def test_autotune_in_bounds(emu, case):
 
 
 # the self-consistent loop: HF only, GW (bit 0), GW + bare SOX (bits 0, 1),
-# a ragged N over several tiles, and 300 frequencies (one Dyson workgroup each)
-SCF_CASES = [(5, 9, 4, 3, 0, 0), (6, 70, 6, 5, 1, 0), (7, 20, 4, 3, 3, 1), (4, 11, 2, 300, 1, 0)]
+# a ragged N over several tiles, 300 frequencies (one Dyson workgroup each)
+# and n = 100 (the Dyson matrix past the LDS size, inverted in device memory)
+SCF_CASES = [(5, 9, 4, 3, 0, 0), (6, 70, 6, 5, 1, 0), (7, 20, 4, 3, 3, 1), (4, 11, 2, 300, 1, 0),
+             (100, 110, 2, 2, 1, 0)]
 
 
 @pytest.mark.parametrize("case", SCF_CASES, ids=lambda c: "-".join(str(x) for x in c))

@@ -10,6 +10,12 @@ molecule (n = 6, N = 14, beta = 20, Lambda = 300, eps = 1e-10: 40 tau nodes,
   and the two grids differ by about 1e-6 of T_fwd), E_inf and E_dyn (1e-7
   relative), the chemical potential (1e-5: in a gap N(mu) is flat, so mu is
   determined only to about that), Tr gamma = N through the library's G.
+* The Dyson inversions past the LDS size (n = 100, held in device memory):
+  three iterations of the GW loop against the oracle's three (G 1e-7).
+* The LDS and device-memory forms of the Dyson inversion on the same
+  n = 64 loop (SOX_SCF_DYSON_IN_MEMORY=1 forces the latter): the same
+  iteration count, G and mu to 1e-10 (pivots and rounding order agree; the
+  bracketing search may land on a different mu in its last step).
 """
 import numpy as np
 import pytest
@@ -77,3 +83,51 @@ def test_scf_vs_oracle(B, system, terms):
         assert abs(out["e_dyn"] - ref["e_dyn"]) <= 1e-7 * abs(ref["e_dyn"])
     gam = -np.einsum("i,iqp->pq", lf["t_beta"], Gh)
     assert abs(np.trace(gam) - N_ELEC) <= 1e-8
+
+
+def _loop(B, wl, h, n_elec, terms, tol, max_iter):
+    import torch
+    lf = B.sox_ir_grid_fermion(BETA, LAM, EPS)
+    lb = B.sox_ir_grid(BETA, LAM, EPS)
+    n, N, nt = wl["n"], wl["N"], len(lf["tau"])
+    plan = B.Plan(n, N, lf["tau"], lb["weights"], BETA, "fp64")
+    G = torch.empty((nt, n, n), dtype=torch.float64, device="cuda")
+    out = B.sox_scf(plan, lf, dev(wl["X"]), dev(wl["V"]), dev(_w_on(wl, lf["tau"])), dev(h),
+                    n_elec, G, terms=terms, tol=tol, max_iter=max_iter)
+    torch.cuda.synchronize()
+    return out, host(G)
+
+
+def _molecule(n, N, seed):
+    of = ir.ir_fermion(BETA, LAM, EPS)
+    wl = synth.small_molecule(n, N, len(of["tau"]), BETA, seed=seed)
+    wl["tau"] = of["tau"]
+    synth.add_dynamic_screening(wl)
+    h = wl["Q"] @ np.diag(wl["eps"]) @ wl["Q"].T
+    return wl, h, of
+
+
+def test_scf_dyson_in_device_memory_vs_oracle(B):
+    wl, h, of = _molecule(100, 120, 17)
+    ob = ir.ir_grid(BETA, LAM, EPS)
+    ref = osc.scf(wl["X"], wl["V"], wl["W_tau"], h, 50.0, BETA, of, ob["weights"], terms=("gw",),
+                  tol=1e-300, max_iter=3)
+    log(f"scf gw n=100 N=120: three iterations; oracle mu {ref['mu']:.10f}")
+    out, Gh = _loop(B, wl, h, 50.0, ("gw",), 1e-300, 3)
+    err = np.abs(Gh - ref["G"]).max()
+    log(f"  library {out['iterations']} iterations, mu {out['mu']:.10f}, max |dG| {err:.1e}")
+    assert out["iterations"] == 3
+    assert err <= 1e-7
+    assert abs(out["mu"] - ref["mu"]) <= 1e-5
+
+
+def test_scf_dyson_lds_and_device_memory_agree(B, monkeypatch):
+    wl, h, _ = _molecule(64, 96, 19)
+    a, Ga = _loop(B, wl, h, 32.0, ("gw",), 1e-8, 100)
+    monkeypatch.setenv("SOX_SCF_DYSON_IN_MEMORY", "1")
+    b, Gb = _loop(B, wl, h, 32.0, ("gw",), 1e-8, 100)
+    log(f"scf gw n=64: LDS {a['iterations']} iterations mu {a['mu']:.12f}; device memory "
+        f"{b['iterations']} iterations mu {b['mu']:.12f}; max |dG| {np.abs(Ga - Gb).max():.1e}")
+    assert a["iterations"] == b["iterations"]
+    assert np.abs(Ga - Gb).max() <= 1e-10
+    assert abs(a["mu"] - b["mu"]) <= 1e-10
