@@ -638,9 +638,11 @@ __global__ __launch_bounds__(64 * NW) void cgemm_panel_bf16x3_kernel(const CgArg
   }
   for (int v = 0; v < p.nv; ++v) {
     if (DMA) {
-      // v's copy has landed once at most the stores issued after it (the
-      // twenty of v - 2, for a full wavefront past its second v) are in flight
-      if (full && v > 1) wait_vm<20>(); else wait_vm<0>();
+      // v's copy has landed: every vector memory operation of the wavefront
+      // has completed (the stores of v - 2 were issued after the copy, and
+      // loads and stores do not complete in issue order, so a count that
+      // leaves those stores in flight does not cover the copy)
+      wait_vm<0>();
       asm volatile("" ::: "memory");
       fetch();
       split();
