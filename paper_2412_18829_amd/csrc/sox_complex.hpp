@@ -750,6 +750,103 @@ inline hipError_t launch_cgemm_panel_bf16x3(CgArgs<float, float> a, int nz, bool
 }
 
 // ---------------------------------------------------------------------------
+// The merge product of the one-pass SOSEX_dyn on a k mesh (float plans):
+// A(tau_l)[pair][P][u] += sum_q A_bare[l][pair][q][P] G^{k}(tau_l)[u][q],
+// k = gidx[pair].  One workgroup per (pair, node): G^k(tau_l) (n x n,
+// n <= 64) is staged in LDS once, and each wavefront takes 16-row P blocks
+// of A_bare in turn.  Complex values interleaved; each complex multiply-add
+// is four real 16x16x4 float32 MFMAs, lane group g holding k = 4 s + g in
+// step s.  The accumulators start from the A(tau) values, so A(tau) is read
+// and written once per element and A_bare read once.
+struct MergeArgs {
+  const float* ab;    // complex A_bare: (P, q) at pair ab_so + node ab_si + q N + P
+  const float* g;     // complex G: (u, q) at gidx[pair] g_so + node g_si + u n + q
+  const int* gidx;
+  float* a;           // complex A(tau): (P, u) at pair a_so + node a_si + P n + u
+  long ab_so, ab_si, g_so, g_si, a_so, a_si;
+  int nodes, n, N;
+};
+constexpr int kMergeLd = 65;  // LDS row stride of G (complex), n <= 64
+
+template <int SM>
+__global__ __launch_bounds__(256) void merge_bare_kernel(const MergeArgs p) {
+  __shared__ f32x2 gl[64 * kMergeLd];
+  const int pair = blockIdx.x / p.nodes, node = blockIdx.x - pair * p.nodes;
+  const int n = p.n, N = p.N;
+  const f32x2* G = (const f32x2*)p.g + (long)p.gidx[pair] * p.g_so + (long)node * p.g_si;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int u = e / n, q = e - u * n;
+    gl[u * kMergeLd + q] = G[e];
+  }
+  __syncthreads();
+  const f32x2* Ab = (const f32x2*)p.ab + (long)pair * p.ab_so + (long)node * p.ab_si;
+  f32x2* Ac = (f32x2*)p.a + (long)pair * p.a_so + (long)node * p.a_si;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, g = lane >> 4;
+  const int nrb = (N + 15) / 16;
+  for (int rb = wave; rb < nrb; rb += 4) {
+    const int P0 = 16 * rb;
+    const bool prow = P0 + li < N;
+    f32x2 av[SM];  // A_bare (P0 + li, 4 s + g)
+#pragma unroll
+    for (int s = 0; s < SM; ++s) {
+      const int q = 4 * s + g;
+      av[s] = (prow && q < n) ? Ab[(long)q * N + P0 + li] : f32x2{0.f, 0.f};
+    }
+    f32x4 re[4], im[4];  // element r of column block c: (P0 + 4 g + r, 16 c + li)
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int P = P0 + acc_row<float>(g, r), u = 16 * c + li;
+        const f32x2 x = (P < N && u < n) ? Ac[(long)P * n + u] : f32x2{0.f, 0.f};
+        re[c][r] = x.x;
+        im[c][r] = x.y;
+      }
+#pragma unroll
+    for (int s = 0; s < SM; ++s) {
+      const int q = 4 * s + g;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int u = 16 * c + li;
+        const f32x2 b = (u < n && q < n) ? gl[u * kMergeLd + q] : f32x2{0.f, 0.f};
+        re[c] = mfma16x16x4(av[s].x, b.x, re[c]);
+        re[c] = mfma16x16x4(-av[s].y, b.y, re[c]);
+        im[c] = mfma16x16x4(av[s].x, b.y, im[c]);
+        im[c] = mfma16x16x4(av[s].y, b.x, im[c]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int P = P0 + acc_row<float>(g, r), u = 16 * c + li;
+        if (P < N && u < n) Ac[(long)P * n + u] = f32x2{re[c][r], im[c][r]};
+      }
+  }
+}
+
+// hipErrorNotSupported for n > 64 (the caller takes the generic product)
+inline hipError_t launch_merge_bare(const MergeArgs& a, int np2, hipStream_t s) {
+  if (a.n < 1 || a.n > 64 || a.N < 1 || a.nodes < 1) return hipErrorNotSupported;
+  const long nb = (long)np2 * a.nodes;
+  if (nb <= 0) return hipSuccess;
+  if (!grid_fits(nb, 256)) return hipErrorInvalidValue;
+  const int S = (a.n + 3) / 4;
+#define SOX_MERGE(SM_)                                                                    \
+  if (S <= SM_) {                                                                         \
+    hipLaunchKernelGGL((merge_bare_kernel<SM_>), dim3((unsigned)nb), dim3(256), 0, s, a);  \
+    return hipGetLastError();                                                             \
+  }
+  SOX_MERGE(4)
+  SOX_MERGE(8)
+  SOX_MERGE(13)
+  SOX_MERGE(16)
+#undef SOX_MERGE
+  return hipErrorNotSupported;
+}
+
+// ---------------------------------------------------------------------------
 template <int M1, int M2, int M3>
 __host__ __device__ constexpr int kdiff_of(int a, int b) {
   return ((((a / (M2 * M3)) - (b / (M2 * M3)) + M1) % M1) * M2 +

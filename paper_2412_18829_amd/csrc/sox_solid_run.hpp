@@ -809,6 +809,18 @@ sox_status run_solid_dynamic(sox_plan& p, const double* X, const double* W, cons
       if ((st = bc_launch(a, np2, true, 1, s, split))) return st;
       // A(tau)[pair][P][u] += sum_q A_bare[pair][q][P] G^{k_v - q1}(tau)[u][q]
       // (A rows P consecutive, k = q N apart)
+      if constexpr (sizeof(T) == 4) {
+        MergeArgs m{};
+        m.ab = abare; m.ab_so = nN; m.ab_si = (long)np2 * nN;
+        m.g = gct + 2 * (long)a0 * n * n; m.gidx = kmqOf; m.g_so = (long)nt * n * n;
+        m.g_si = (long)n * n;
+        m.a = atau + 2 * (long)a0 * np2 * nN; m.a_so = nN; m.a_si = (long)np2 * nN;
+        m.nodes = ca; m.n = n; m.N = N;
+        const hipError_t e = launch_merge_bare(m, np2, s);
+        if (e == hipSuccess) continue;
+        if (e != hipErrorNotSupported)
+          return fail(SOX_ERR_HIP, "merge kernel launch failed: %s", hipGetErrorString(e));
+      }
       CgArgs<T, T> b = cg_args<T, T>();
       b.A = abare; b.soA = nN; b.siA = (long)np2 * nN; b.ldA = 1; b.ksA = N;
       b.B = gct + 2 * (long)a0 * n * n; b.idxB = kmqOf; b.soB = (long)nt * n * n;
