@@ -6,10 +6,16 @@ and threads sequentially, caller buffers have their exact sizes and every
 buffer carved from the workspace is followed by a poisoned guard gap.  Any
 out-of-bounds read or write of any kernel aborts the case.  The shapes cover
 ragged n and N, one tau node, multiple tau / v slabs and both fused tiles.
+
+The cases run as concurrent processes (up to eight at once, one fixture per
+module that starts every selected case), each test then checks its own
+case's output: the cases are independent processes, and the suite's wall
+time is that of the longest few instead of their sum.
 """
 import os
 import shutil
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 import pytest
 
@@ -27,6 +33,94 @@ def emu(tmp_path_factory):
            "-I", EMU, "-x", "c++", os.path.join(EMU, "driver.cpp"), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     assert r.returncode == 0, r.stderr[-4000:]
+    return out
+
+
+def _env(**extra):
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
+    env.update({k: v for k, v in extra.items() if v is not None})
+    return env
+
+
+def _mol(c, env_extra=None):  # (n, N, nt, prec, entry, vjp, budget)
+    n, N, nt, prec, entry, vjp, budget = c[:7]
+    return ([str(n), str(N), str(nt), str(prec), str(entry), str(vjp)],
+            _env(SOX_WS_BUDGET_MB=budget, **(env_extra or {})))
+
+
+def _solid(c, env_extra=None):  # (n, N, nt, prec, entry, mesh[, budget])
+    n, N, nt, prec, entry, mesh = c[:6]
+    budget = c[6] if len(c) > 6 else None
+    return ([str(n), str(N), str(nt), str(prec), str(entry), "0", *[str(m) for m in mesh]],
+            _env(SOX_WS_BUDGET_MB=budget, **(env_extra or {})))
+
+
+def _tune(c):
+    kind, case = c
+    if kind == "mol":
+        args, env = _mol(case[:6] + (None,), {"EMU_AUTOTUNE": "1"})
+        args[-1] = "0"
+        return args, env
+    return _solid(case[:6] + (None,), {"EMU_AUTOTUNE": "1"})
+
+
+# test name -> (case -> (arguments, environment), time limit in seconds)
+JOBS = {
+    "test_entry_point_in_bounds": (lambda c: _mol(c), 600),
+    "test_solid_entry_in_bounds": (lambda c: _solid(c), 600),
+    "test_solid_wide_frequency_in_bounds": (lambda c: _solid(c, {"EMU_NW": "48"}), 900),
+    "test_lds_fused_kernel_in_bounds": (lambda c: _mol(c, {"SOX_FUSED_CFG": str(c[7])}), 900),
+    "test_dense_multi_tile_in_bounds": (lambda c: _mol(c, {"SOX_DENSE_WG": str(c[7])}), 900),
+    "test_noalloc_entry_in_bounds": (lambda c: (["noalloc", str(c)], _env()), 600),
+    "test_autotune_in_bounds": (_tune, 900),
+    "test_scf_in_bounds": (lambda c: (["scf", *[str(x) for x in c]], _env()), 900),
+}
+WORKERS = max(1, min(8, os.cpu_count() or 1))
+
+
+def _run(emu, args, env, limit):
+    try:
+        r = subprocess.run([emu, *args], capture_output=True, text=True, env=env, timeout=limit)
+        return r.returncode, r.stdout + r.stderr
+    except subprocess.TimeoutExpired as e:
+        return -1, f"time limit of {limit} s: {e}"
+
+
+class _Runs:
+    """(return code, output) per test id: every selected case run up front in
+    a pool of processes, or (under pytest-xdist, whose workers each collect
+    every test but run only their share) each case when its test asks."""
+
+    def __init__(self, emu, jobs, eager):
+        self.emu, self.jobs, self.done = emu, jobs, {}
+        if eager:
+            with ThreadPoolExecutor(max_workers=WORKERS) as pool:
+                fut = {k: pool.submit(_run, emu, *v) for k, v in jobs.items()}
+                self.done = {k: f.result() for k, f in fut.items()}
+
+    def __getitem__(self, key):
+        if key not in self.done:
+            self.done[key] = _run(self.emu, *self.jobs[key])
+        return self.done[key]
+
+
+@pytest.fixture(scope="module")
+def runs(emu, request):
+    jobs = {}
+    for item in request.session.items:
+        if item.module.__name__ != __name__ or item.originalname not in JOBS:
+            continue
+        params = item.callspec.params
+        case = params["case"] if "case" in params else params["prec"]
+        build, limit = JOBS[item.originalname]
+        args, env = build(case)
+        jobs[item.nodeid] = (args, env, limit)
+    return _Runs(emu, jobs, eager="PYTEST_XDIST_WORKER" not in os.environ)
+
+
+def _ok(runs, request, marker="status 0"):
+    rc, out = runs[request.node.nodeid]
+    assert rc == 0 and marker in out and "AddressSanitizer" not in out, out[-4000:]
     return out
 
 
@@ -89,6 +183,10 @@ SOLID_CASES = [
     (6, 33, 3, 2, 6, (2, 2, 1), "1"),
     (5, 17, 3, 1, 7, (1, 3, 1), None),
     (4, 20, 2, 2, 5, (2, 1, 1), None),
+    # SOSEX_dyn with n = 20 and n = 54: the bare-term merge kernel's 8- and
+    # 16-step K loops
+    (20, 44, 2, 1, 6, (2, 1, 1), None),
+    (54, 56, 2, 2, 6, (2, 1, 1), None),
     # GW entry (8): LDS element blocks of 64 (3 momenta), 32 (64 momenta) and
     # 16 (75 momenta), and tau slabs under a 1 MB budget
     (5, 20, 3, 1, 8, (3, 1, 1), None),
@@ -99,16 +197,8 @@ SOLID_CASES = [
 
 
 @pytest.mark.parametrize("case", SOLID_CASES, ids=lambda c: "-".join(str(x) for x in c))
-def test_solid_entry_in_bounds(emu, case):
-    n, N, nt, prec, entry, mesh, budget = case
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
-    if budget:
-        env["SOX_WS_BUDGET_MB"] = budget
-    r = subprocess.run([emu, str(n), str(N), str(nt), str(prec), str(entry), "0",
-                        *[str(m) for m in mesh]],
-                       capture_output=True, text=True, env=env, timeout=600)
-    out = r.stdout + r.stderr
-    assert r.returncode == 0 and "status 0" in out and "AddressSanitizer" not in out, out[-4000:]
+def test_solid_entry_in_bounds(runs, request, case):
+    _ok(runs, request)
 
 
 # more than 40 bosonic samples (IR grids): the inverse transform's 64-wide
@@ -117,14 +207,8 @@ WIDE_CASES = [(4, 20, 6, 1, 2, (2, 1, 1)), (4, 20, 5, 2, 6, (3, 1, 1))]
 
 
 @pytest.mark.parametrize("case", WIDE_CASES, ids=lambda c: "-".join(str(x) for x in c))
-def test_solid_wide_frequency_in_bounds(emu, case):
-    n, N, nt, prec, entry, mesh = case
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", EMU_NW="48")
-    r = subprocess.run([emu, str(n), str(N), str(nt), str(prec), str(entry), "0",
-                        *[str(m) for m in mesh]],
-                       capture_output=True, text=True, env=env, timeout=900)
-    out = r.stdout + r.stderr
-    assert r.returncode == 0 and "status 0" in out and "AddressSanitizer" not in out, out[-4000:]
+def test_solid_wide_frequency_in_bounds(runs, request, case):
+    _ok(runs, request)
 
 
 # the LDS-staged fused kernel, split precision (config 8) and float32
@@ -145,16 +229,9 @@ LDS_CASES = [
 
 
 @pytest.mark.parametrize("case", LDS_CASES, ids=lambda c: "-".join(str(x) for x in c))
-def test_lds_fused_kernel_in_bounds(emu, case):
-    n, N, nt, prec, entry, vjp, budget, cfg = case
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", SOX_FUSED_CFG=str(cfg))
-    if budget:
-        env["SOX_WS_BUDGET_MB"] = budget
-    r = subprocess.run([emu, str(n), str(N), str(nt), str(prec), str(entry), str(vjp)],
-                       capture_output=True, text=True, env=env, timeout=900)
-    out = r.stdout + r.stderr
-    assert r.returncode == 0 and "status 0" in out and "AddressSanitizer" not in out, out[-4000:]
-    assert f'"fused_cfg":{cfg}' in out, out[-2000:]
+def test_lds_fused_kernel_in_bounds(runs, request, case):
+    out = _ok(runs, request)
+    assert f'"fused_cfg":{case[7]}' in out, out[-2000:]
 
 
 # the LDS-staged GEMM with several output tiles per workgroup (A step and
@@ -170,27 +247,13 @@ DENSE_WG_CASES = [
 
 
 @pytest.mark.parametrize("case", DENSE_WG_CASES, ids=lambda c: "-".join(str(x) for x in c))
-def test_dense_multi_tile_in_bounds(emu, case):
-    n, N, nt, prec, entry, vjp, budget, wg = case
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", SOX_DENSE_WG=str(wg))
-    if budget:
-        env["SOX_WS_BUDGET_MB"] = budget
-    r = subprocess.run([emu, str(n), str(N), str(nt), str(prec), str(entry), str(vjp)],
-                       capture_output=True, text=True, env=env, timeout=900)
-    out = r.stdout + r.stderr
-    assert r.returncode == 0 and "status 0" in out and "AddressSanitizer" not in out, out[-4000:]
+def test_dense_multi_tile_in_bounds(runs, request, case):
+    _ok(runs, request)
 
 
 @pytest.mark.parametrize("case", CASES, ids=lambda c: "-".join(str(x) for x in c))
-def test_entry_point_in_bounds(emu, case):
-    n, N, nt, prec, entry, vjp, budget = case
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
-    if budget:
-        env["SOX_WS_BUDGET_MB"] = budget
-    r = subprocess.run([emu, str(n), str(N), str(nt), str(prec), str(entry), str(vjp)],
-                       capture_output=True, text=True, env=env, timeout=600)
-    out = r.stdout + r.stderr
-    assert r.returncode == 0 and "status 0" in out and "AddressSanitizer" not in out, out[-4000:]
+def test_entry_point_in_bounds(runs, request, case):
+    _ok(runs, request)
 
 
 def test_launchers_refuse_grids_past_32bit_work_items(emu):
@@ -205,14 +268,11 @@ def test_launchers_refuse_grids_past_32bit_work_items(emu):
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2])
-def test_noalloc_entry_in_bounds(emu, prec):
+def test_noalloc_entry_in_bounds(runs, request, prec):
     """sox_sigma_bare_noalloc on its static scratch array: an oversize plan is
     refused with SOX_ERR_WORKSPACE, two later calls (the second smaller)
     stay inside the array (AddressSanitizer guards the global)."""
-    r = subprocess.run([emu, "noalloc", str(prec)], capture_output=True, text=True,
-                       env=dict(os.environ, ASAN_OPTIONS="detect_leaks=0"), timeout=600)
-    out = r.stdout + r.stderr
-    assert r.returncode == 0 and "noalloc ok" in out and "AddressSanitizer" not in out, out[-4000:]
+    _ok(runs, request, "noalloc ok")
 
 
 # the operand-based autotuner: every candidate's launch sequence on the
@@ -228,18 +288,8 @@ TUNE_CASES = [
 
 
 @pytest.mark.parametrize("case", TUNE_CASES, ids=lambda c: c[0] + "-" + "-".join(str(x) for x in c[1]))
-def test_autotune_in_bounds(emu, case):
-    kind, c = case
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0", EMU_AUTOTUNE="1")
-    if kind == "mol":
-        n, N, nt, prec, entry, vjp, budget = c
-        args = [emu, str(n), str(N), str(nt), str(prec), str(entry), "0"]
-    else:
-        n, N, nt, prec, entry, mesh, budget = c
-        args = [emu, str(n), str(N), str(nt), str(prec), str(entry), "0", *[str(m) for m in mesh]]
-    r = subprocess.run(args, capture_output=True, text=True, env=env, timeout=900)
-    out = r.stdout + r.stderr
-    assert r.returncode == 0 and "status 0" in out and "AddressSanitizer" not in out, out[-4000:]
+def test_autotune_in_bounds(runs, request, case):
+    out = _ok(runs, request)
     assert '"autotune":[{' in out, out[-4000:]
 
 
@@ -251,10 +301,5 @@ SCF_CASES = [(5, 9, 4, 3, 0, 0), (6, 70, 6, 5, 1, 0), (7, 20, 4, 3, 3, 1), (4, 1
 
 
 @pytest.mark.parametrize("case", SCF_CASES, ids=lambda c: "-".join(str(x) for x in c))
-def test_scf_in_bounds(emu, case):
-    n, N, nt, nnu, terms, prec = case
-    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0")
-    r = subprocess.run([emu, "scf", str(n), str(N), str(nt), str(nnu), str(terms), str(prec)],
-                       capture_output=True, text=True, env=env, timeout=900)
-    out = r.stdout + r.stderr
-    assert r.returncode == 0 and "status 0" in out and "AddressSanitizer" not in out, out[-4000:]
+def test_scf_in_bounds(runs, request, case):
+    _ok(runs, request)

@@ -109,12 +109,15 @@ def test_vertex_solid_vs_oracle(B, solid, kind, precision):
     assert err <= _tol(precision, kind)
 
 
-@pytest.mark.parametrize("shape", [((2, 2, 1), 5, 26, 9), ((3, 3, 3), 3, 12, 6)],
-                         ids=lambda s: "x".join(map(str, s[0])))
+@pytest.mark.parametrize("shape", [((2, 2, 1), 5, 26, 9), ((3, 3, 3), 3, 12, 6),
+                                   ((2, 1, 1), 20, 44, 6), ((2, 1, 1), 54, 56, 4)],
+                         ids=lambda s: "x".join(map(str, s[0])) + f"-n{s[1]}")
 def test_sosex_dyn_one_pass_on_meshes(B, shape):
     """The one-pass SOSEX_dyn of k-point plans (the bare term inside the
-    dynamic chain) on further meshes, against the oracle's two terms; with a
-    workspace budget that splits the bare term's tau slabs, the same."""
+    dynamic chain) on further meshes, against the oracle's two terms.  The
+    float plans merge the bare term into A(tau) on merge_bare_kernel, whose
+    K = n loop has 4, 8, 13 or 16 steps: n = 5 and 3 take the first, n = 20
+    the second, n = 54 the last (n = 52 at full size the third)."""
     import os
     import torch
     mesh, n, N, nt = shape
