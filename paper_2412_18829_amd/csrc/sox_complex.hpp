@@ -907,7 +907,8 @@ __device__ __forceinline__ void mesh_dft(R (&xr)[M1 * M2 * M3], R (&xi)[M1 * M2 
 // The inner sum is a cyclic cross-correlation over the momentum group, so
 // with F[f](xi) = sum_k f[k] w^(xi.k) it is F^-1[ F[c] * F~[b] ] where F~
 // uses the conjugate phases.  One thread per element: for each (k_v, v) it
-// loads the n_k values of b and of c, transforms both in registers (one
+// loads the n_k values of b and of c (non-temporal loads: each is read
+// once), transforms both in registers (one
 // butterfly pass per mesh axis), and accumulates the n_k products of the
 // transforms in float64; the inverse transform runs once at the end.  This
 // is the same sum as the direct n_k^2 products, in n_k log n_k work.  The
@@ -943,14 +944,14 @@ __global__ __launch_bounds__(256) void dstep_mesh_kernel(const T* __restrict__ B
       T br[NK], bi[NK], cr[NK], ci[NK];
 #pragma unroll
       for (int q1 = 0; q1 < NK; ++q1) {
-        const V2 x = Bp[(long)(q1 * NK + kv) * sp + ov];
+        const V2 x = __builtin_nontemporal_load(&Bp[(long)(q1 * NK + kv) * sp + ov]);
         br[q1] = x.x;
         bi[q1] = x.y;
       }
 #pragma unroll
       for (int kw = 0; kw < NK; ++kw) {
         const int q2 = kdiff_of<M1, M2, M3>(kw, kv);
-        const V2 x = Cp[(long)(q2 * NK + kw) * sp + ov];
+        const V2 x = __builtin_nontemporal_load(&Cp[(long)(q2 * NK + kw) * sp + ov]);
         cr[kw] = x.x;
         ci[kw] = x.y;
       }
