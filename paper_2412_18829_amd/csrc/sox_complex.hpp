@@ -908,9 +908,9 @@ __device__ __forceinline__ void mesh_dft(R (&xr)[M1 * M2 * M3], R (&xi)[M1 * M2 
 // with F[f](xi) = sum_k f[k] w^(xi.k) it is F^-1[ F[c] * F~[b] ] where F~
 // uses the conjugate phases.  One thread per element: for each (k_v, v) it
 // loads the n_k values of b and of c (non-temporal loads: each is read
-// once), transforms both in registers (one
-// butterfly pass per mesh axis), and accumulates the n_k products of the
-// transforms in float64; the inverse transform runs once at the end.  This
+// once), transforms both in registers (one butterfly pass per mesh axis),
+// and accumulates the n_k products of the transforms in float64; the
+// inverse transform runs once at the end.  This
 // is the same sum as the direct n_k^2 products, in n_k log n_k work.  The
 // mesh is a template parameter (every index a compile-time register).
 // Pairs are sp elements apart, v slices NN apart; nv slices are summed.  The
