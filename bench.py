@@ -246,6 +246,28 @@ IR_EPS = 1e-10
 # the self-consistent loop leg: one spin channel of a synthetic molecule
 SCF_N, SCF_NTHC, SCF_BETA, SCF_LAMBDA, SCF_SEED, SCF_TOL = 64, 384, 50.0, 500.0, 7, 1e-8
 
+# workspace budget of the timed k-mesh plans (the main run and the IR-grid
+# leg): 192 GiB of the GPU's 288 GB, against the library's default cap of
+# 64 GiB, so that the tuner can take 16-node tau slabs; a budget set by the
+# caller (SOX_WS_BUDGET_MB) is kept.  The float64 comparison sweep keeps the
+# library default.
+SOLID_WS_BUDGET_MB = 196608
+
+
+class ws_budget:
+    def __init__(self, active: bool):
+        self.active = active and "SOX_WS_BUDGET_MB" not in os.environ
+
+    def __enter__(self):
+        if self.active:
+            os.environ["SOX_WS_BUDGET_MB"] = str(SOLID_WS_BUDGET_MB)
+        return self
+
+    def __exit__(self, *exc):
+        if self.active:
+            del os.environ["SOX_WS_BUDGET_MB"]
+        return False
+
 
 def gw_flops(n: int, N: int, nt: int, nk: int = 1) -> float:
     """Flops of one sox_sigma_gw call: per node and momentum the projections
@@ -562,8 +584,9 @@ def main() -> int:
         Xc = torch.zeros_like(X)
         Xc[:, :, gold["cols"]] = X[:, :, gold["cols"]]
         args.warmup = max(args.warmup, 1)
-    main_run = run(args.precision, args.steps, args.warmup, profile=True, Xwarm=Xc,
-                   graph=not args.no_graph, tune=not args.no_autotune)
+    with ws_budget(solid):
+        main_run = run(args.precision, args.steps, args.warmup, profile=True, Xwarm=Xc,
+                       graph=not args.no_graph, tune=not args.no_autotune)
     sec = main_run["seconds"]
     ms_per_step = 1e3 * sec / args.steps
     value = args.steps / sec
@@ -689,6 +712,7 @@ def main() -> int:
         # workload's beta and omega_max: one warmup and one timed sweep
         lam = wl["beta"] * IR_OMEGA_MAX
         note(f"ir: IR grid beta={wl['beta']:g} Lambda={lam:g} eps={IR_EPS:g}")
+        ir_budget = ws_budget(solid).__enter__()
         c0 = time.perf_counter()
         g = B.sox_ir_grid(wl["beta"], lam, IR_EPS)
         build_s = time.perf_counter() - c0
@@ -755,6 +779,7 @@ def main() -> int:
                         "timed sweep")}
         del plan, Gi, Si, wsi, Wir
         torch.cuda.empty_cache()
+        ir_budget.__exit__()
 
     scf = None
     if not args.no_scf:
@@ -904,6 +929,9 @@ def main() -> int:
         "roofline": roofline,
         "stage_ms_per_step": stage_ms,
         "plan": main_run["plan"],
+        "workspace_budget_mb": int(os.environ.get("SOX_WS_BUDGET_MB", 0)) or
+                               (SOLID_WS_BUDGET_MB if solid else 65536),
+        "peak_device_memory_gib": round(torch.cuda.max_memory_allocated() / 2 ** 30, 2),
     }
     if vjp is not None:
         out["vjp"] = vjp
