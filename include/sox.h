@@ -81,10 +81,15 @@ typedef enum {
 
 /* Arithmetic of the contraction kernels (the A step and the fused B.C -> D
  * step).  G(tau) synthesis, the half projections, the back-transform to
- * orbitals, the Matsubara transforms and the energy are always float64.
- * The U-contraction (eq:U_contraction) runs in float64 for SOX_FP64 plans
- * and for every k-point plan; molecular SOX_FP32 and SOX_BF16X3 plans run it
- * in float32 (its result is stored in float32 for the A step either way).
+ * orbitals and the energy are always float64.  The Matsubara transforms are
+ * float64 for molecules and for SOX_FP64 plans; k-point SOX_FP32 and
+ * SOX_BF16X3 plans with even n run them on float32 MFMAs in real form (the
+ * other k-point float plans in float64).  The U-contraction
+ * (eq:U_contraction) runs in float64 for SOX_FP64 plans and for every
+ * k-point plan; molecular SOX_FP32 and SOX_BF16X3 plans run it in float32
+ * (its result is stored in float32 for the A step either way).  The k-point
+ * D step transforms B and C over the mesh in float32 (float64 for SOX_FP64
+ * plans) and accumulates in float64.
  *   SOX_FP64    float64 MFMA (v_mfma_f64_16x16x4f64)
  *   SOX_FP32    float32 MFMA (v_mfma_f32_16x16x4f32), float32 accumulation
  *   SOX_BF16X3  each float32 operand split as hi + lo bfloat16; the products
